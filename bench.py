@@ -1,0 +1,185 @@
+"""Throughput of the APC hot path on one MI355X.
+
+One step = one frame of the whole path on the largest single-GPU workload:
+stage one (boundary-face binning + tet walk + power moments) for all 72
+subdomains, the canonical-order moment sum, and stage two (the same walk with
+the FP64 moment bound) with the final renormalised image.  Inputs (mesh,
+transfer function, camera) are resident in HBM before timing starts.
+
+Prints ONE JSON line.  `value` is ray samples per second (pieces generated
+per frame / frame time); frames/s, per-kernel times, the roofline figure of
+the dominant kernel, sampled parity against the FP64 oracle, and the oracle's
+own throughput on a bounded pixel sample of the same frame are reported beside
+it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ray samples/s + frames/s at 2560², m=8; p50/p99 frame latency (served)"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+# algorithmic work per unit (measurement section)
+FP64_FLOPS_PER_PIECE_M8 = 250.0   # per-sample moment bound at m = 8
+TET_BYTES = 32.0                  # vertex ids + neighbour codes of one tet
+VERT_BYTES = 16.0                 # x, y, z, scalar
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="large", choices=["large", "medium", "tiny"])
+    ap.add_argument("--size", type=int, default=None, help="override the image size (square)")
+    ap.add_argument("--grid", type=int, default=None, help="override cubes per axis (large workload)")
+    ap.add_argument("--cpu-pixels", type=int, default=4096, help="oracle sample size (0 = skip)")
+    ap.add_argument("--profile-steps", action="store_true", help="no oracle leg (for profiler runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: the multi-GPU path (subdomains sharded over GPUs with an "
+              "all-reduce of the moment image) is not part of this build; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2501_12581_amd as apc
+    import synth
+
+    t0 = time.time()
+    if args.workload == "large":
+        kw = {}
+        if args.size:
+            kw["size"] = args.size
+        if args.grid:
+            kw["n"] = args.grid
+        sc = synth.scene_large(**kw)
+    elif args.workload == "medium":
+        sc = synth.scene_medium(**({"size": args.size} if args.size else {}))
+    else:
+        sc = synth.scene_tiny()
+    mesh = sc.mesh
+    log("generated %s: %d tets, %d vertices, %d subdomains in %.1fs" % (
+        sc.name, mesh.n_tets, mesh.n_vertices, mesh.n_sub, time.time() - t0))
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ctx = apc.Context(0)
+    t0 = time.time()
+    r = apc.Renderer(ctx, sc, device=dev)
+    torch.cuda.synchronize()
+    info = r.mesh.info()
+    log("mesh resident in %.1fs: %d boundary faces, %.2f GB" % (
+        time.time() - t0, info["n_boundary_faces"], info["device_bytes"] / 1e9))
+
+    for _ in range(args.warmup):
+        r.frame()
+    torch.cuda.synchronize()
+    log("warmup done")
+    ctx.counters(reset=True)
+    kern = {"bin_ms": 0.0, "moments_ms": 0.0, "sum_ms": 0.0, "resolve_ms": 0.0}
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    frame_ms = []
+    for k in range(args.steps):
+        f0 = time.perf_counter()
+        r.frame()
+        # the library records HIP events around each kernel on this stream; reading them waits for the frame
+        tk = ctx.timings()
+        stream.synchronize()
+        frame_ms.append((time.perf_counter() - f0) * 1e3)
+        for key in kern:
+            kern[key] += tk[key]
+        log("step %d: %.1f ms (moments %.1f, resolve %.1f)" % (k, frame_ms[-1], tk["moments_ms"],
+                                                              tk["resolve_ms"]))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_per_step = elapsed * 1e3 / args.steps
+    cnt = ctx.counters()
+    pieces_per_frame = cnt["pieces"] / (2.0 * args.steps)   # both passes count their pieces
+    steps_per_frame = cnt["tet_steps"] / (2.0 * args.steps)
+    for key in kern:
+        kern[key] /= args.steps
+    samples_per_s = pieces_per_frame / (ms_per_step / 1e3)
+
+    # ---- roofline of the dominant kernel
+    H, W, m = r.view.height, r.view.width, sc.m
+    S = mesh.n_sub
+    mesh_bytes = mesh.n_tets * TET_BYTES + mesh.n_vertices * VERT_BYTES
+    mom_bytes = S * (m + 1) * H * W * 4.0
+    rooflines = {
+        "k_moments": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+                      "achieved": (mesh_bytes + mom_bytes) / (kern["moments_ms"] / 1e3) / 1e9,
+                      "per_launch": "mesh %.3g B + dense per-subdomain moments %.3g B" % (mesh_bytes, mom_bytes)},
+        "k_resolve": {"bound": "alu", "unit": "TFLOP/s", "peak": FP64_PEAK_TFLOPS,
+                      "achieved": FP64_FLOPS_PER_PIECE_M8 * pieces_per_frame / (kern["resolve_ms"] / 1e3) / 1e12,
+                      "per_launch": "%d FP64 flops x %.4g pieces" % (FP64_FLOPS_PER_PIECE_M8, pieces_per_frame)},
+    }
+    dom = "k_resolve" if kern["resolve_ms"] >= kern["moments_ms"] else "k_moments"
+    rf = rooflines[dom]
+    roofline = {"kernel": dom, "bound": rf["bound"], "achieved": round(rf["achieved"], 4), "peak": rf["peak"],
+                "unit": rf["unit"], "frac": round(rf["achieved"] / rf["peak"], 5), "traffic": None,
+                "work_per_launch": rf["per_launch"],
+                "other": {k: {"bound": v["bound"], "achieved": round(v["achieved"], 4), "unit": v["unit"],
+                              "frac": round(v["achieved"] / v["peak"], 5)} for k, v in rooflines.items()
+                          if k != dom}}
+
+    # ---- sampled parity + CPU baseline (FP64 oracle on a bounded pixel sample)
+    cpu = None
+    parity = None
+    if args.cpu_pixels > 0 and not args.profile_steps:
+        import oracle
+        pix = np.sort(np.random.default_rng(11).choice(H * W, min(args.cpu_pixels, H * W), replace=False))
+        threads = os.cpu_count() or 1
+        log("oracle on %d sampled pixels with %d threads" % (len(pix), threads))
+        t0 = time.perf_counter()
+        ref = oracle.render(sc, pixels=pix, threads=threads)
+        cpu_s = time.perf_counter() - t0
+        cpu = {"value": round(ref["n_pieces"] / cpu_s, 1), "unit": "samples/s", "cores": threads, "kind": "oracle",
+               "sample": "%d seeded pixels of the same %dx%d frame (%d samples, both passes, %.1f s)" % (
+                   len(pix), W, H, ref["n_pieces"], cpu_s)}
+        mom = r.moments.reshape(m + 1, -1)[:, torch.as_tensor(pix, device=dev)].double().cpu().numpy()
+        rgba = r.rgba.reshape(-1, 4)[torch.as_tensor(pix, device=dev)].double().cpu().numpy()
+        b0 = ref["moments"][0]
+        cov = b0 > 0
+        den = np.maximum(b0[cov], 1e-3)
+        d = rgba - ref["rgba"]
+        parity = {"pixels": int(len(pix)), "covered": int(cov.sum()),
+                  "moments_rel_max": float(np.max(np.abs(mom[:, cov] - ref["moments"][:, cov]) / den)),
+                  "background_exact": bool(np.all(mom[:, ~cov] == 0)),
+                  "rgba_max_abs": float(np.abs(d).max()), "rgba_rmse": float(math.sqrt(np.mean(d ** 2)))}
+        log("parity %s" % parity)
+
+    out = {
+        "metric": METRIC, "value": round(samples_per_s, 1), "unit": "samples/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "%s: %d tets (jittered Kuhn grid), %d Morton subdomains, %dx%d %s view, m=%d" % (
+            sc.name, mesh.n_tets, S, W, H, "perspective" if sc.view["projection"] else "orthographic", m),
+            "global_batch": 1, "seq_len": None, "parallelism": "single GPU, all subdomains on device"},
+        "frames_per_s": round(1e3 / ms_per_step, 4),
+        "samples_per_frame": int(pieces_per_frame), "tet_steps_per_frame": int(steps_per_frame),
+        "kernels_ms": {k: round(v, 3) for k, v in kern.items()},
+        "frame_ms_each": [round(x, 2) for x in frame_ms],
+        "counters": cnt, "roofline": roofline, "cpu_baseline": cpu, "parity": parity,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,251 @@
+/*
+ * apc.h -- C ABI of the MI355X (gfx950) library for the data-parallel hot path
+ * of Approximate Puzzlepiece Compositing (APC).
+ *
+ * The method (paper Sections 3 and 4): every subdomain of a distributed tet
+ * mesh is rendered twice.  Stage one (Section 4.1) traces rays through the
+ * subdomain's own cells and sums, per pixel, power moments of optical depth
+ * over log-warped depth (Alg. 2); the per-subdomain moment images are added
+ * into one global moment image, which is order independent because addition
+ * commutes.  Stage two (Section 4.2) traces the same rays again and weights
+ * each sample by the transmittance that the global moments imply at the
+ * sample's depth (Alg. 3: normalise and bias the moments, Cholesky-factor the
+ * Hankel matrix, find the roots of the kernel polynomial, weight the nodes
+ * and read off the absorbance in front); the per-subdomain colour images are
+ * then simply added (Alg. 1) and renormalised by the total opacity
+ * (Section 4.3).
+ *
+ * Here every subdomain that the paper places on its own MPI rank lives on one
+ * GPU; the two MPI reductions of the paper become device sums in canonical
+ * subdomain order.
+ *
+ * Conventions
+ *  - Every call returns apc_status; nothing aborts or throws across the ABI.
+ *    On failure the reason is available from apc_last_error() on the calling
+ *    thread.  All argument validation happens before any device work, so a
+ *    call that fails validation writes nothing.
+ *  - "device" pointers are HIP device memory owned by the caller (for example
+ *    torch tensors on cuda:0); "host" pointers are ordinary host memory read
+ *    during the call only.  `stream` is a hipStream_t (NULL = default
+ *    stream); work is stream ordered like the HIP APIs, and outputs are ready
+ *    when that stream reaches the end of the call's work.  The library never
+ *    keeps a caller pointer after a call returns.
+ *  - A device-side failure (launch error, fault) reported by HIP is returned
+ *    as APC_E_DEVICE by the call that observes it.
+ *  - Image layout: pixel (row i, column j) of a W x H image has index
+ *    i*W + j.  Moment images are planar: element (j, pixel) of an [m+1][H][W]
+ *    image is at j*H*W + pixel.
+ */
+#ifndef APC_H
+#define APC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum apc_status {
+  APC_OK = 0,
+  APC_E_ARG = 1,         /* invalid argument (null pointer, size, id, unsupported m) */
+  APC_E_MESH = 2,        /* invalid mesh: index out of range, non-positive volume, non-manifold face */
+  APC_E_NOMEM = 3,       /* device or host allocation failed */
+  APC_E_DEVICE = 4,      /* HIP runtime error */
+  APC_E_NUMERIC = 5,     /* numeric failure in strict mode (walk step limit hit) */
+  APC_E_UNSUPPORTED = 6  /* valid request the library does not implement */
+} apc_status;
+
+typedef struct apc_ctx_s* apc_ctx;   /* one per device: workspace and diagnostic counters */
+typedef struct apc_mesh_s* apc_mesh; /* device-resident mesh of all subdomains, owned by the library */
+
+/* ------------------------------------------------------------------ context */
+
+/* Create a context on HIP device `device`.  The context owns growable device
+ * workspace; calls on one context must not overlap in time (one host thread
+ * at a time, one stream at a time). */
+apc_status apc_create(int device, apc_ctx* out);
+apc_status apc_destroy(apc_ctx ctx);
+
+/* Message describing the last failed call on this thread (never NULL). */
+const char* apc_last_error(apc_ctx ctx);
+
+/* Library version string. */
+const char* apc_version(void);
+
+/* ------------------------------------------------------------------ mesh */
+
+/* A tetrahedral mesh split into disjoint subdomains (Section 4: each rank
+ * holds one subdomain; subdomains may be non-convex and their bounding boxes
+ * may overlap, but no cell belongs to two subdomains -- Section 6 notes that
+ * overlapping volumes are not supported). */
+typedef struct apc_mesh_desc {
+  int64_t n_vertices;           /* V >= 4 */
+  int64_t n_tets;               /* 1 <= T < 2^29 */
+  int32_t n_subdomains;         /* S >= 1 */
+  int32_t flags;                /* reserved, must be 0 (all pointers are host memory) */
+  const float* xyz;             /* host [V][3] vertex positions */
+  const float* scalar;          /* host [V] vertex scalars, linearly interpolated inside each tet */
+  const int32_t* tet_vertices;  /* host [T][4] vertex ids; every tet must have positive signed volume
+                                   det(v1-v0, v2-v0, v3-v0) > 0 */
+  const int32_t* tet_subdomain; /* host [T] subdomain id in [0, S) */
+} apc_mesh_desc;
+
+/* Copy a mesh to the device and build its residency structures: face
+ * adjacency (each face is shared by at most two tets), tets grouped by
+ * subdomain (the input order is kept inside each subdomain, so pass tets in a
+ * spatially coherent order such as Morton order), and per subdomain the list
+ * of boundary faces -- faces on the mesh hull or shared with another
+ * subdomain -- through which rays enter it.
+ * Errors: APC_E_ARG (null pointers, sizes), APC_E_MESH (vertex id out of
+ * range, repeated vertex in a tet, non-positive volume, subdomain id out of
+ * range, a face shared by more than two tets), APC_E_NOMEM, APC_E_DEVICE.
+ * Synchronous: the caller may free its arrays when the call returns. */
+apc_status apc_load_mesh(apc_ctx ctx, const apc_mesh_desc* desc, apc_mesh* out, void* stream);
+apc_status apc_free_mesh(apc_ctx ctx, apc_mesh mesh);
+
+typedef struct apc_mesh_info {
+  int64_t n_vertices, n_tets, n_boundary_faces;
+  int32_t n_subdomains, pad;
+  double bbox_lo[3], bbox_hi[3];     /* global bounding box of all vertices */
+  int64_t device_bytes;              /* resident device memory held by the mesh */
+} apc_mesh_info;
+apc_status apc_mesh_get_info(apc_mesh mesh, apc_mesh_info* out);
+/* Number of tets and boundary faces of one subdomain. */
+apc_status apc_mesh_subdomain_info(apc_mesh mesh, int32_t subdomain, int64_t* n_tets, int64_t* n_boundary_faces);
+
+/* ------------------------------------------------------------------ frame parameters */
+
+#define APC_ORTHOGRAPHIC 0
+#define APC_PERSPECTIVE 1
+
+/* Camera.  Pixel (row i, column j), a = j + 1/2, b = i + 1/2:
+ *   orthographic: origin = eye + a*right + b*down, direction = dir/|dir|
+ *   perspective:  origin = eye, direction = normalise(dir + (a - W/2)*right + (b - H/2)*down)
+ * Ray depth t is the distance along the unit direction.  The log-depth warp
+ * of Alg. 2/3 maps [t_near, t_far] to [-1, 1]; the sampling lattice is
+ * t_near + k*step.  If t_near <= 0 and t_far <= 0 both are derived from the
+ * bounding sphere of the whole mesh (centre c, radius R of its bounding box):
+ * t_near = dist - R, t_far = dist + R with dist = |c - eye| (perspective) or
+ * (c - eye).dir/|dir| (orthographic).  The same range must be used by every
+ * subdomain and by both passes.  t_near must come out positive. */
+typedef struct apc_view {
+  int32_t width, height;
+  int32_t projection;   /* APC_ORTHOGRAPHIC or APC_PERSPECTIVE */
+  int32_t pad;
+  double eye[3], dir[3], right[3], down[3];
+  double t_near, t_far; /* <= 0: derive from the mesh */
+  double step;          /* world-space lattice spacing, > 0 */
+} apc_view;
+
+/* Transfer function: a table of n_entries RGBA values over [s_min, s_max],
+ * linearly interpolated and clamped.  Extinction per unit length is
+ * kappa * A; a sample of length l has optical depth
+ * min(kappa * A * l, absorbance_max) (Alg. 2 caps the absorbance). */
+typedef struct apc_tf {
+  int32_t n_entries;    /* 2..1024 */
+  int32_t pad;
+  const float* rgba;    /* device [n_entries][4] */
+  float s_min, s_max, kappa, absorbance_max;
+} apc_tf;
+
+/* Moment-bound parameters (Alg. 3 and Section 4.3).  The moments are
+ * normalised by b0 and mixed with a bias vector: beta' = (1-alpha)*b/b0 +
+ * alpha*bias; the node at the sample's own depth is weighted by eta
+ * ("overestimation"). */
+typedef struct apc_mboit {
+  int32_t m;            /* number of power moments: 4, 6 or 8 */
+  int32_t renormalize;  /* finalised output: 1 = rgb * (1 - exp(-b0)) / sum(T*a), 0 = literal Alg. 1 sums */
+  double alpha;         /* bias mixing strength, 0 <= alpha < 1 */
+  double bias[8];       /* b*_1..b*_m */
+  double eta;           /* overestimation weight, 0..1 */
+} apc_mboit;
+
+/* ------------------------------------------------------------------ the hot path */
+
+/* Stage one for a list of subdomains (Section 4.1, Alg. 2).  For each listed
+ * subdomain s (slot k = position in `subdomains`), every pixel ray is walked
+ * through the tets of s from each boundary face where it enters s; the chord
+ * in each tet is cut at the lattice t_near + k*step into pieces, and each
+ * piece of optical depth a at warped depth z adds a*z^j to moment j.
+ *   subdomains      host [n_sub] distinct subdomain ids
+ *   moments_per_sub device [n_sub][m+1][H][W] FP32, fully written (zero where
+ *                   subdomain k is not hit)
+ * m is 4, 6 or 8.  flags: reserved, 0. */
+apc_status apc_moments_pass(apc_ctx ctx, apc_mesh mesh, const apc_view* view, const apc_tf* tf, int32_t m,
+                            const int32_t* subdomains, int32_t n_sub, float* moments_per_sub, uint32_t flags,
+                            void* stream);
+
+/* Global moments = sum of the per-subdomain moment images (Section 4.1; the
+ * paper's MPI_Allreduce).  The sum runs in FP64 over the slots in ascending
+ * subdomain-id order, whatever their order in the buffer, so the result is
+ * bitwise independent of the order in which subdomains were rendered.
+ *   moments_per_sub device [n_sub][m+1][H][W] FP32
+ *   subdomains      host [n_sub] ids of the slots (NULL: slot order is canonical)
+ *   moments_global  device [m+1][H][W] FP32 */
+apc_status apc_sum_moments(apc_ctx ctx, const float* moments_per_sub, int32_t n_sub, int32_t m, int32_t height,
+                           int32_t width, const int32_t* subdomains, float* moments_global, void* stream);
+
+#define APC_FINALIZE 1u
+
+/* Stage two for a list of subdomains (Section 4.2, Alg. 1 second loop and
+ * Alg. 3).  The same pieces as stage one are generated again; each piece of
+ * opacity alpha_p = 1 - exp(-a) and colour c (transfer-function RGB) adds
+ * T * alpha_p * (c, 1), where T = clamp(exp(-b0 * F)) and F is the moment
+ * bound at the piece's warped depth computed from `moments_global`.
+ *   moments_global  device [m+1][H][W] FP32 (from apc_sum_moments)
+ *   rgba_out        device [H][W][4] FP32.  Without APC_FINALIZE: the additive
+ *                   partial image (sum T*a*rgb, sum T*a) of the listed
+ *                   subdomains, summed in the listed order.  With
+ *                   APC_FINALIZE: the final image of those subdomains
+ *                   (renormalised when mboit->renormalize, see apc_mboit).
+ * The per-pixel Hankel/Cholesky set-up and the per-piece solve run in FP64
+ * when m = 8 and in FP32 when m = 4 or 6; everything else runs in FP32. */
+apc_status apc_resolve_pass(apc_ctx ctx, apc_mesh mesh, const apc_view* view, const apc_tf* tf,
+                            const apc_mboit* mboit, const float* moments_global, const int32_t* subdomains,
+                            int32_t n_sub, float* rgba_out, uint32_t flags, void* stream);
+
+/* Final image = sum of partial images (Section 4.2; the paper's
+ * MPI_Reduce), in ascending subdomain-id order, then finalised like
+ * apc_resolve_pass with APC_FINALIZE.
+ *   partials        device [n_sub][H][W][4] additive partial images
+ *   subdomains      host [n_sub] ids of the partial images (NULL: canonical)
+ *   moments_global  device [m+1][H][W] (b0 plane used for the opacity)
+ *   rgba_out        device [H][W][4] */
+apc_status apc_sum_images(apc_ctx ctx, const float* partials, int32_t n_sub, int32_t height, int32_t width,
+                          const int32_t* subdomains, const float* moments_global, const apc_mboit* mboit,
+                          float* rgba_out, void* stream);
+
+/* ------------------------------------------------------------------ diagnostics */
+
+typedef struct apc_counters {
+  int64_t pieces;           /* samples (pieces) generated, both passes */
+  int64_t tet_steps;        /* tets walked, both passes */
+  int64_t entries;          /* (ray, boundary face) entries walked, both passes */
+  int64_t bin_records;      /* (face, tile) records binned */
+  int64_t walk_step_limit;  /* walks cut off by the step limit (should be 0) */
+  int64_t exit_fallback;    /* exit faces chosen by the tie fallback (should be ~0) */
+  int64_t entry_overflow;   /* per-ray entry lists flushed early (results stay correct) */
+  int64_t nonpd_pivots;     /* Cholesky pivots floored in the resolve pass */
+} apc_counters;
+
+/* Read (and with reset != 0, clear) the counters accumulated by this context.
+ * Synchronises the device. */
+apc_status apc_get_counters(apc_ctx ctx, apc_counters* out, int32_t reset);
+
+/* Durations in milliseconds of the kernels of the most recent calls on this
+ * context, measured with HIP events recorded on the caller's stream around
+ * each launch.  Waits for those events.  A kernel that has not run yet
+ * reports 0. */
+typedef struct apc_timings {
+  double bin_ms;       /* binning of the most recent pass (count + scan + fill) */
+  double moments_ms;   /* stage-one walk kernel of the last apc_moments_pass */
+  double sum_ms;       /* last apc_sum_moments */
+  double resolve_ms;   /* stage-two walk kernel of the last apc_resolve_pass */
+} apc_timings;
+apc_status apc_get_timings(apc_ctx ctx, apc_timings* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* APC_H */

@@ -1,0 +1,307 @@
+"""Python binding of libapc.so, the MI355X (gfx950) library for the data-parallel
+hot path of Approximate Puzzlepiece Compositing (see include/apc.h).
+
+This module only marshals arguments: every step of the path (binning, tet
+walk, moments, sums, moment-bound resolve) runs in the library's HIP kernels.
+PyTorch supplies device memory and streams.  There is no CPU fallback: if
+libapc.so is missing or cannot be loaded the import of any entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libapc.so")
+
+APC_ORTHOGRAPHIC = 0
+APC_PERSPECTIVE = 1
+APC_FINALIZE = 1
+STATUS = {0: "APC_OK", 1: "APC_E_ARG", 2: "APC_E_MESH", 3: "APC_E_NOMEM", 4: "APC_E_DEVICE",
+          5: "APC_E_NUMERIC", 6: "APC_E_UNSUPPORTED"}
+EXPORTS = ["apc_create", "apc_destroy", "apc_last_error", "apc_version", "apc_load_mesh", "apc_free_mesh",
+           "apc_mesh_get_info", "apc_mesh_subdomain_info", "apc_moments_pass", "apc_sum_moments",
+           "apc_resolve_pass", "apc_sum_images", "apc_get_counters", "apc_get_timings"]
+
+
+class ApcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("n_vertices", C.c_int64), ("n_tets", C.c_int64), ("n_subdomains", C.c_int32),
+                ("flags", C.c_int32), ("xyz", C.c_void_p), ("scalar", C.c_void_p),
+                ("tet_vertices", C.c_void_p), ("tet_subdomain", C.c_void_p)]
+
+
+class MeshInfo(C.Structure):
+    _fields_ = [("n_vertices", C.c_int64), ("n_tets", C.c_int64), ("n_boundary_faces", C.c_int64),
+                ("n_subdomains", C.c_int32), ("pad", C.c_int32), ("bbox_lo", C.c_double * 3),
+                ("bbox_hi", C.c_double * 3), ("device_bytes", C.c_int64)]
+
+
+class View(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("projection", C.c_int32), ("pad", C.c_int32),
+                ("eye", C.c_double * 3), ("dir", C.c_double * 3), ("right", C.c_double * 3),
+                ("down", C.c_double * 3), ("t_near", C.c_double), ("t_far", C.c_double), ("step", C.c_double)]
+
+
+class TF(C.Structure):
+    _fields_ = [("n_entries", C.c_int32), ("pad", C.c_int32), ("rgba", C.c_void_p), ("s_min", C.c_float),
+                ("s_max", C.c_float), ("kappa", C.c_float), ("absorbance_max", C.c_float)]
+
+
+class Mboit(C.Structure):
+    _fields_ = [("m", C.c_int32), ("renormalize", C.c_int32), ("alpha", C.c_double), ("bias", C.c_double * 8),
+                ("eta", C.c_double)]
+
+
+class Timings(C.Structure):
+    _fields_ = [("bin_ms", C.c_double), ("moments_ms", C.c_double), ("sum_ms", C.c_double),
+                ("resolve_ms", C.c_double)]
+
+
+class Counters(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("pieces", "tet_steps", "entries", "bin_records", "walk_step_limit",
+                                         "exit_fallback", "entry_overflow", "nonpd_pivots")]
+
+
+_lib = None
+
+
+def lib():
+    """Load libapc.so (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libapc.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        L = C.CDLL(LIB_PATH)
+        st = C.c_int
+        vp = C.c_void_p
+        L.apc_version.restype = C.c_char_p
+        L.apc_last_error.restype = C.c_char_p
+        L.apc_last_error.argtypes = [vp]
+        L.apc_create.restype = st
+        L.apc_create.argtypes = [C.c_int, C.POINTER(vp)]
+        L.apc_destroy.restype = st
+        L.apc_destroy.argtypes = [vp]
+        L.apc_load_mesh.restype = st
+        L.apc_load_mesh.argtypes = [vp, C.POINTER(MeshDesc), C.POINTER(vp), vp]
+        L.apc_free_mesh.restype = st
+        L.apc_free_mesh.argtypes = [vp, vp]
+        L.apc_mesh_get_info.restype = st
+        L.apc_mesh_get_info.argtypes = [vp, C.POINTER(MeshInfo)]
+        L.apc_mesh_subdomain_info.restype = st
+        L.apc_mesh_subdomain_info.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.apc_moments_pass.restype = st
+        L.apc_moments_pass.argtypes = [vp, vp, C.POINTER(View), C.POINTER(TF), C.c_int32, vp, C.c_int32, vp,
+                                       C.c_uint32, vp]
+        L.apc_sum_moments.restype = st
+        L.apc_sum_moments.argtypes = [vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp, vp, vp]
+        L.apc_resolve_pass.restype = st
+        L.apc_resolve_pass.argtypes = [vp, vp, C.POINTER(View), C.POINTER(TF), C.POINTER(Mboit), vp, vp,
+                                       C.c_int32, vp, C.c_uint32, vp]
+        L.apc_sum_images.restype = st
+        L.apc_sum_images.argtypes = [vp, vp, C.c_int32, C.c_int32, C.c_int32, vp, vp, C.POINTER(Mboit), vp, vp]
+        L.apc_get_counters.restype = st
+        L.apc_get_counters.argtypes = [vp, C.POINTER(Counters), C.c_int32]
+        L.apc_get_timings.restype = st
+        L.apc_get_timings.argtypes = [vp, C.POINTER(Timings)]
+        _lib = L
+    return _lib
+
+
+def _check(status, ctx=None):
+    if status != 0:
+        raise ApcError(status, lib().apc_last_error(ctx).decode())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return C.c_void_p(stream)
+
+
+def _dev_ptr(t, dtype, shape=None, name="tensor"):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype or not t.is_contiguous():
+        raise ValueError("%s must be contiguous %s" % (name, dtype))
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s has shape %s, expected %s" % (name, tuple(t.shape), tuple(shape)))
+    return C.c_void_p(t.data_ptr())
+
+
+def _ids(subdomains):
+    a = np.ascontiguousarray(np.asarray(subdomains, dtype=np.int32).ravel())
+    return a, C.c_void_p(a.ctypes.data)
+
+
+def make_view(view: dict, step: float, t_near: float = 0.0, t_far: float = 0.0) -> View:
+    """apc_view from a camera dict with width, height, projection, eye, dir, right, down."""
+    return View(width=int(view["width"]), height=int(view["height"]), projection=int(view["projection"]), pad=0,
+                eye=(C.c_double * 3)(*map(float, view["eye"])), dir=(C.c_double * 3)(*map(float, view["dir"])),
+                right=(C.c_double * 3)(*map(float, view["right"])), down=(C.c_double * 3)(*map(float, view["down"])),
+                t_near=float(t_near), t_far=float(t_far), step=float(step))
+
+
+def make_tf(rgba_dev, s_min, s_max, kappa, absorbance_max) -> TF:
+    import torch
+    ptr = _dev_ptr(rgba_dev, torch.float32, name="tf table")
+    return TF(n_entries=int(rgba_dev.shape[0]), pad=0, rgba=ptr, s_min=float(s_min), s_max=float(s_max),
+              kappa=float(kappa), absorbance_max=float(absorbance_max))
+
+
+def make_mboit(m, alpha, bias, eta, renormalize=1) -> Mboit:
+    b = np.zeros(8)
+    b[:m] = np.asarray(bias, dtype=np.float64)[:m]
+    return Mboit(m=int(m), renormalize=int(renormalize), alpha=float(alpha), bias=(C.c_double * 8)(*b),
+                 eta=float(eta))
+
+
+class Mesh:
+    def __init__(self, ctx, handle):
+        self.ctx = ctx
+        self.handle = handle
+
+    def info(self) -> dict:
+        mi = MeshInfo()
+        _check(lib().apc_mesh_get_info(self.handle, C.byref(mi)))
+        return dict(n_vertices=mi.n_vertices, n_tets=mi.n_tets, n_boundary_faces=mi.n_boundary_faces,
+                    n_subdomains=mi.n_subdomains, bbox_lo=tuple(mi.bbox_lo), bbox_hi=tuple(mi.bbox_hi),
+                    device_bytes=mi.device_bytes)
+
+    def subdomain_info(self, sub) -> tuple:
+        nt, nf = C.c_int64(0), C.c_int64(0)
+        _check(lib().apc_mesh_subdomain_info(self.handle, int(sub), C.byref(nt), C.byref(nf)))
+        return nt.value, nf.value
+
+    def free(self):
+        if self.handle:
+            lib().apc_free_mesh(self.ctx.handle, self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Context:
+    """One library context on a HIP device (apc_create)."""
+
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        _check(lib().apc_create(int(device), C.byref(h)))
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            lib().apc_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _ck(self, st):
+        _check(st, self.handle)
+
+    def load_mesh(self, xyz, scalar, tets, tet_sub, n_sub, stream=None) -> Mesh:
+        xyz = np.ascontiguousarray(xyz, dtype=np.float32)
+        scalar = np.ascontiguousarray(scalar, dtype=np.float32)
+        tets = np.ascontiguousarray(tets, dtype=np.int32)
+        tet_sub = np.ascontiguousarray(tet_sub, dtype=np.int32)
+        d = MeshDesc(n_vertices=xyz.shape[0], n_tets=tets.shape[0], n_subdomains=int(n_sub), flags=0,
+                     xyz=xyz.ctypes.data, scalar=scalar.ctypes.data, tet_vertices=tets.ctypes.data,
+                     tet_subdomain=tet_sub.ctypes.data)
+        h = C.c_void_p()
+        self._ck(lib().apc_load_mesh(self.handle, C.byref(d), C.byref(h), _stream(stream)))
+        return Mesh(self, h)
+
+    def moments_pass(self, mesh, view: View, tf: TF, m, subdomains, out, stream=None):
+        import torch
+        ids, ptr = _ids(subdomains)
+        shape = (len(ids), m + 1, view.height, view.width)
+        self._ck(lib().apc_moments_pass(self.handle, mesh.handle, C.byref(view), C.byref(tf), int(m), ptr,
+                                        len(ids), _dev_ptr(out, torch.float32, shape, "moments_per_sub"), 0,
+                                        _stream(stream)))
+
+    def sum_moments(self, per_sub, m, subdomains, out, stream=None):
+        import torch
+        n, m1, H, W = per_sub.shape
+        ids, ptr = (None, None) if subdomains is None else _ids(subdomains)
+        self._ck(lib().apc_sum_moments(self.handle, _dev_ptr(per_sub, torch.float32, name="moments_per_sub"), n,
+                                       int(m), H, W, ptr, _dev_ptr(out, torch.float32, (m1, H, W), "moments"),
+                                       _stream(stream)))
+
+    def resolve_pass(self, mesh, view: View, tf: TF, mboit: Mboit, moments, subdomains, out, finalize=True,
+                     stream=None):
+        import torch
+        ids, ptr = _ids(subdomains)
+        self._ck(lib().apc_resolve_pass(self.handle, mesh.handle, C.byref(view), C.byref(tf), C.byref(mboit),
+                                        _dev_ptr(moments, torch.float32, (mboit.m + 1, view.height, view.width),
+                                                 "moments"), ptr, len(ids),
+                                        _dev_ptr(out, torch.float32, (view.height, view.width, 4), "rgba"),
+                                        APC_FINALIZE if finalize else 0, _stream(stream)))
+
+    def sum_images(self, partials, subdomains, moments, mboit: Mboit, out, stream=None):
+        import torch
+        n, H, W, _ = partials.shape
+        ids, ptr = (None, None) if subdomains is None else _ids(subdomains)
+        self._ck(lib().apc_sum_images(self.handle, _dev_ptr(partials, torch.float32, name="partials"), n, H, W,
+                                      ptr, _dev_ptr(moments, torch.float32, name="moments"), C.byref(mboit),
+                                      _dev_ptr(out, torch.float32, (H, W, 4), "rgba"), _stream(stream)))
+
+    def timings(self) -> dict:
+        t = Timings()
+        self._ck(lib().apc_get_timings(self.handle, C.byref(t)))
+        return {n: getattr(t, n) for n, _ in Timings._fields_}
+
+    def counters(self, reset=False) -> dict:
+        c = Counters()
+        self._ck(lib().apc_get_counters(self.handle, C.byref(c), int(bool(reset))))
+        return {n: getattr(c, n) for n, _ in Counters._fields_}
+
+
+class Renderer:
+    """A resident mesh plus the per-scene device buffers of one workload.
+
+    `frame()` runs the whole hot path once: stage one for all subdomains, the
+    canonical moment sum, stage two with the final renormalised image.
+    """
+
+    def __init__(self, ctx: Context, scene, device="cuda"):
+        import torch
+        self.ctx = ctx
+        self.scene = scene
+        mesh = scene.mesh
+        self.mesh = ctx.load_mesh(mesh.xyz, mesh.scalar, mesh.tets, mesh.tet_sub, mesh.n_sub)
+        self.tf_dev = torch.as_tensor(np.ascontiguousarray(scene.tf, dtype=np.float32), device=device)
+        self.view = make_view(scene.view, scene.step)
+        self.tf = make_tf(self.tf_dev, scene.s_min, scene.s_max, scene.kappa, scene.absorbance_max)
+        self.mboit = make_mboit(scene.m, scene.alpha, scene.bias, scene.eta, scene.renormalize)
+        self.subs = np.arange(mesh.n_sub, dtype=np.int32)
+        H, W, m = self.view.height, self.view.width, scene.m
+        self.per_sub = torch.empty((mesh.n_sub, m + 1, H, W), dtype=torch.float32, device=device)
+        self.moments = torch.empty((m + 1, H, W), dtype=torch.float32, device=device)
+        self.rgba = torch.empty((H, W, 4), dtype=torch.float32, device=device)
+
+    def frame(self, subdomains=None, finalize=True, stream=None):
+        subs = self.subs if subdomains is None else np.asarray(subdomains, np.int32)
+        per_sub = self.per_sub if len(subs) == len(self.subs) else self.per_sub[:len(subs)]
+        self.ctx.moments_pass(self.mesh, self.view, self.tf, self.scene.m, subs, per_sub, stream)
+        self.ctx.sum_moments(per_sub, self.scene.m, subs, self.moments, stream)
+        self.ctx.resolve_pass(self.mesh, self.view, self.tf, self.mboit, self.moments, subs, self.rgba,
+                              finalize=finalize, stream=stream)
+        return self.rgba

@@ -1,0 +1,738 @@
+// Host side of the C ABI declared in include/apc.h: argument validation,
+// mesh residency (validation, grouping by subdomain, face adjacency on the
+// device, per-subdomain boundary faces), per-call frame constants and the
+// launch sequence of the two passes.
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/apc.h"
+#include "apc_internal.h"
+
+using apc::FrameDev;
+using apc::MeshDev;
+using apc::SlotDev;
+
+namespace {
+
+thread_local std::string g_error = "no error";
+
+apc_status fail(apc_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_error = buf;
+  return st;
+}
+
+#define HIPCHK(x)                                                                                \
+  do {                                                                                           \
+    hipError_t e_ = (x);                                                                         \
+    if (e_ != hipSuccess) return fail(APC_E_DEVICE, "%s failed: %s", #x, hipGetErrorString(e_)); \
+  } while (0)
+
+template <class Fn>
+void parallel_for(int64_t n, Fn fn) {
+  unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  if (n < 100000) nt = 1;
+  std::vector<std::thread> th;
+  for (unsigned k = 0; k < nt; ++k) {
+    int64_t lo = n * k / nt, hi = n * (k + 1) / nt;
+    th.emplace_back([=] { fn(lo, hi, int(k)); });
+  }
+  for (auto& t : th) t.join();
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipError_t ensure(size_t need) {
+    if (need <= bytes) return hipSuccess;
+    if (p) {
+      hipError_t e = hipFree(p);
+      if (e != hipSuccess) return e;
+      p = nullptr;
+      bytes = 0;
+    }
+    size_t nb = std::max<size_t>(need + need / 4, 4096);
+    hipError_t e = hipMalloc(&p, nb);
+    if (e != hipSuccess) return e;
+    bytes = nb;
+    return hipSuccess;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+}  // namespace
+
+struct apc_ctx_s {
+  int device = 0;
+  DevBuf counts, offsets, cursors, records, scan_tmp, slots, order, counters;
+  void* staging = nullptr;  // pinned host memory for small uploads
+  size_t staging_bytes = 0;
+  hipEvent_t staging_done = nullptr;
+  int64_t bin_records = 0;  // (face, tile) records binned, counted on the host
+  // event pairs around the launches: 0 binning, 1 moments, 2 sum, 3 resolve
+  hipEvent_t ev[4][2] = {};
+  bool ev_used[4] = {};
+};
+
+namespace {
+enum { EV_BIN = 0, EV_MOM, EV_SUM, EV_RES };
+hipError_t ev_mark(apc_ctx ctx, int k, int which, hipStream_t s) {
+  if (which == 1) ctx->ev_used[k] = true;
+  return hipEventRecord(ctx->ev[k][which], s);
+}
+}  // namespace
+
+struct apc_mesh_s {
+  apc_ctx ctx = nullptr;
+  int64_t V = 0, T = 0, NB = 0;
+  int32_t S = 0;
+  float4* vert = nullptr;
+  int4* tet = nullptr;
+  int* bface = nullptr;
+  std::vector<int> sub_begin, face_begin;  // [S+1] each
+  double lo[3], hi[3];
+  int64_t device_bytes = 0;
+};
+
+namespace {
+
+// Copy `bytes` from host to device through the context's pinned staging
+// buffer, ordered on `s`.  Waits for the previous staged copy first, so the
+// staging buffer is never overwritten while a copy still reads it.
+apc_status stage_upload(apc_ctx ctx, void* dst, const void* src, size_t bytes, hipStream_t s) {
+  if (ctx->staging_done) HIPCHK(hipEventSynchronize(ctx->staging_done));
+  if (bytes > ctx->staging_bytes) {
+    if (ctx->staging) HIPCHK(hipHostFree(ctx->staging));
+    ctx->staging = nullptr;
+    size_t nb = std::max<size_t>(bytes, 64 << 10);
+    HIPCHK(hipHostMalloc(&ctx->staging, nb, hipHostMallocDefault));
+    ctx->staging_bytes = nb;
+  }
+  std::memcpy(ctx->staging, src, bytes);
+  HIPCHK(hipMemcpyAsync(dst, ctx->staging, bytes, hipMemcpyHostToDevice, s));
+  HIPCHK(hipEventRecord(ctx->staging_done, s));
+  return APC_OK;
+}
+
+bool finite3(const double* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+// inverse of the 3x3 matrix with columns a, b, c; false when singular
+bool inverse3(const double* a, const double* b, const double* c, double* inv) {
+  double m[3][3] = {{a[0], b[0], c[0]}, {a[1], b[1], c[1]}, {a[2], b[2], c[2]}};
+  double det = m[0][0] * (m[1][1] * m[2][2] - m[1][2] * m[2][1]) - m[0][1] * (m[1][0] * m[2][2] - m[1][2] * m[2][0]) +
+               m[0][2] * (m[1][0] * m[2][1] - m[1][1] * m[2][0]);
+  double scale = std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]) *
+                 std::sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]) *
+                 std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+  if (!(std::fabs(det) > 1e-12 * scale)) return false;
+  double id = 1.0 / det;
+  inv[0] = (m[1][1] * m[2][2] - m[1][2] * m[2][1]) * id;
+  inv[1] = (m[0][2] * m[2][1] - m[0][1] * m[2][2]) * id;
+  inv[2] = (m[0][1] * m[1][2] - m[0][2] * m[1][1]) * id;
+  inv[3] = (m[1][2] * m[2][0] - m[1][0] * m[2][2]) * id;
+  inv[4] = (m[0][0] * m[2][2] - m[0][2] * m[2][0]) * id;
+  inv[5] = (m[0][2] * m[1][0] - m[0][0] * m[1][2]) * id;
+  inv[6] = (m[1][0] * m[2][1] - m[1][1] * m[2][0]) * id;
+  inv[7] = (m[0][1] * m[2][0] - m[0][0] * m[2][1]) * id;
+  inv[8] = (m[0][0] * m[1][1] - m[0][1] * m[1][0]) * id;
+  return true;
+}
+
+apc_status check_view_tf(const apc_view* v, const apc_tf* tf) {
+  if (!v) return fail(APC_E_ARG, "view is NULL");
+  if (v->width <= 0 || v->height <= 0 || int64_t(v->width) * v->height > (int64_t(1) << 30))
+    return fail(APC_E_ARG, "image size %d x %d out of range", v->width, v->height);
+  if (v->projection != APC_ORTHOGRAPHIC && v->projection != APC_PERSPECTIVE)
+    return fail(APC_E_ARG, "unknown projection %d", v->projection);
+  if (!finite3(v->eye) || !finite3(v->dir) || !finite3(v->right) || !finite3(v->down))
+    return fail(APC_E_ARG, "camera vectors must be finite");
+  if (!(v->step > 0.0) || !std::isfinite(v->step)) return fail(APC_E_ARG, "step must be positive");
+  if (!tf) return fail(APC_E_ARG, "transfer function is NULL");
+  if (tf->n_entries < 2 || tf->n_entries > apc::MAX_TF)
+    return fail(APC_E_ARG, "transfer function needs 2..%d entries", apc::MAX_TF);
+  if (!tf->rgba) return fail(APC_E_ARG, "transfer function table is NULL");
+  if (!(tf->s_max > tf->s_min)) return fail(APC_E_ARG, "transfer function domain is empty");
+  if (!(tf->kappa >= 0.0f) || !(tf->absorbance_max > 0.0f)) return fail(APC_E_ARG, "kappa/absorbance_max invalid");
+  return APC_OK;
+}
+
+// Frame constants shared by both passes.
+apc_status make_frame(const apc_mesh_s* m, const apc_view* v, const apc_tf* tf, int n_slots, int max_sub_tets,
+                      FrameDev& f) {
+  std::memset(&f, 0, sizeof(f));
+  f.W = v->width;
+  f.H = v->height;
+  f.proj = v->projection;
+  f.tiles_x = (v->width + apc::TILE - 1) / apc::TILE;
+  f.tiles_y = (v->height + apc::TILE - 1) / apc::TILE;
+  int64_t nt = int64_t(f.tiles_x) * f.tiles_y;
+  if (nt * n_slots > (int64_t(1) << 31) - 1) return fail(APC_E_ARG, "too many tiles x subdomains");
+  f.n_tiles = int(nt);
+  f.n_slots = n_slots;
+  f.n_tf = tf->n_entries;
+  double dn = std::sqrt(v->dir[0] * v->dir[0] + v->dir[1] * v->dir[1] + v->dir[2] * v->dir[2]);
+  if (!(dn > 0.0)) return fail(APC_E_ARG, "view direction is zero");
+  double dir[3] = {v->dir[0], v->dir[1], v->dir[2]};
+  if (v->projection == APC_ORTHOGRAPHIC)
+    for (int k = 0; k < 3; ++k) dir[k] /= dn;
+  f.ex = float(v->eye[0]);
+  f.ey = float(v->eye[1]);
+  f.ez = float(v->eye[2]);
+  f.dx = float(dir[0]);
+  f.dy = float(dir[1]);
+  f.dz = float(dir[2]);
+  f.rx = float(v->right[0]);
+  f.ry = float(v->right[1]);
+  f.rz = float(v->right[2]);
+  f.wx = float(v->down[0]);
+  f.wy = float(v->down[1]);
+  f.wz = float(v->down[2]);
+  f.half_w = 0.5f * float(v->width);
+  f.half_h = 0.5f * float(v->height);
+  double minv[9];
+  if (!inverse3(dir, v->right, v->down, minv)) return fail(APC_E_ARG, "dir, right and down are not independent");
+  for (int k = 0; k < 9; ++k) f.minv[k] = float(minv[k]);
+  // one depth range for every subdomain and both passes
+  double tn = v->t_near, tfar = v->t_far;
+  if (tn <= 0.0 && tfar <= 0.0) {
+    double c[3], ext2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      c[k] = 0.5 * (m->lo[k] + m->hi[k]);
+      ext2 += (m->hi[k] - m->lo[k]) * (m->hi[k] - m->lo[k]);
+    }
+    double R = 0.5 * std::sqrt(ext2), dist;
+    if (v->projection == APC_PERSPECTIVE) {
+      double e2 = 0.0;
+      for (int k = 0; k < 3; ++k) e2 += (c[k] - v->eye[k]) * (c[k] - v->eye[k]);
+      dist = std::sqrt(e2);
+    } else {
+      dist = 0.0;
+      for (int k = 0; k < 3; ++k) dist += (c[k] - v->eye[k]) * dir[k];
+    }
+    tn = dist - R;
+    tfar = dist + R;
+  }
+  if (!(tn > 0.0) || !(tfar > tn)) return fail(APC_E_ARG, "depth range [%g, %g] invalid (camera inside the mesh?)", tn, tfar);
+  if ((tfar - tn) / v->step > double(1 << 22)) return fail(APC_E_ARG, "step too small for the depth range");
+  const double tmid = 0.5 * (tn + tfar);
+  f.t_mid = float(tmid);
+  f.t_near = float(tn - double(f.t_mid));
+  f.step = float(v->step);
+  f.inv_step = float(1.0 / v->step);
+  double lg0 = std::log2(tn), lg1 = std::log2(tfar);
+  f.lg_near = float(lg0);
+  f.warp_scale = float(2.0 / (lg1 - lg0));
+  f.s_min = tf->s_min;
+  f.tf_scale = float(double(tf->n_entries - 1) / (double(tf->s_max) - double(tf->s_min)));
+  f.kappa = tf->kappa;
+  f.amax = tf->absorbance_max;
+  f.max_steps = std::min(max_sub_tets + 16, 1 << 22);
+  return APC_OK;
+}
+
+apc_status check_subdomains(const apc_mesh_s* m, const int32_t* subs, int32_t n_sub) {
+  if (!subs) return fail(APC_E_ARG, "subdomain list is NULL");
+  if (n_sub < 1 || n_sub > m->S) return fail(APC_E_ARG, "n_sub %d out of range [1, %d]", n_sub, m->S);
+  std::vector<char> seen(m->S, 0);
+  for (int k = 0; k < n_sub; ++k) {
+    if (subs[k] < 0 || subs[k] >= m->S) return fail(APC_E_ARG, "subdomain id %d out of range", subs[k]);
+    if (seen[subs[k]]) return fail(APC_E_ARG, "subdomain id %d listed twice", subs[k]);
+    seen[subs[k]] = 1;
+  }
+  return APC_OK;
+}
+
+// Bin the boundary faces of the listed subdomains into (tile, slot) bins.
+apc_status build_bins(apc_ctx ctx, const apc_mesh_s* m, const FrameDev& f, const int32_t* subs, int32_t n_sub,
+                      hipStream_t s, MeshDev& md) {
+  std::vector<SlotDev> sl(n_sub);
+  int max_faces = 0;
+  for (int k = 0; k < n_sub; ++k) {
+    int id = subs[k];
+    sl[k].tet_begin = m->sub_begin[id];
+    sl[k].tet_end = m->sub_begin[id + 1];
+    sl[k].face_begin = m->face_begin[id];
+    sl[k].face_end = m->face_begin[id + 1];
+    max_faces = std::max(max_faces, sl[k].face_end - sl[k].face_begin);
+  }
+  HIPCHK(ctx->slots.ensure(sizeof(SlotDev) * n_sub));
+  apc_status st = stage_upload(ctx, ctx->slots.p, sl.data(), sizeof(SlotDev) * n_sub, s);
+  if (st != APC_OK) return st;
+  const int64_t nb = int64_t(f.n_tiles) * n_sub;
+  HIPCHK(ctx->counts.ensure(sizeof(int) * nb));
+  HIPCHK(ctx->offsets.ensure(sizeof(int) * (nb + 1)));
+  HIPCHK(ctx->cursors.ensure(sizeof(int) * nb));
+  HIPCHK(ctx->scan_tmp.ensure(sizeof(int) * apc::scan_tmp_elems(nb)));
+  md.vert = m->vert;
+  md.tet = m->tet;
+  md.n_vertices = m->V;
+  md.n_tets = m->T;
+  HIPCHK(ev_mark(ctx, EV_BIN, 0, s));
+  HIPCHK(apc::launch_fill_i32(ctx->counts.as<int>(), 0, nb, s));
+  HIPCHK(apc::launch_bin_count(md, f, ctx->slots.as<SlotDev>(), max_faces, m->bface, ctx->counts.as<int>(), s));
+  HIPCHK(apc::launch_exclusive_scan(ctx->counts.as<int>(), ctx->offsets.as<int>(), nb, ctx->scan_tmp.as<int>(), s));
+  int tail[2];
+  HIPCHK(hipMemcpyAsync(&tail[0], ctx->offsets.as<int>() + nb - 1, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&tail[1], ctx->counts.as<int>() + nb - 1, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const int64_t total = int64_t(tail[0]) + tail[1];
+  if (total < 0 || total > (int64_t(1) << 31) - 1) return fail(APC_E_NUMERIC, "bin records overflow (%lld)", (long long)total);
+  HIPCHK(ctx->records.ensure(sizeof(int) * std::max<int64_t>(total, 1)));
+  HIPCHK(apc::launch_fill_i32(ctx->cursors.as<int>(), 0, nb, s));
+  HIPCHK(apc::launch_bin_fill(md, f, ctx->slots.as<SlotDev>(), max_faces, m->bface, ctx->offsets.as<int>(),
+                              ctx->cursors.as<int>(), ctx->records.as<int>(), s));
+  HIPCHK(ev_mark(ctx, EV_BIN, 1, s));
+  ctx->bin_records += total;
+  return APC_OK;
+}
+
+int max_tets_of(const apc_mesh_s* m, const int32_t* subs, int32_t n_sub) {
+  int mx = 0;
+  for (int k = 0; k < n_sub; ++k) mx = std::max(mx, m->sub_begin[subs[k] + 1] - m->sub_begin[subs[k]]);
+  return mx;
+}
+
+apc_status check_ctx(apc_ctx ctx) {
+  if (!ctx) return fail(APC_E_ARG, "context is NULL");
+  HIPCHK(hipSetDevice(ctx->device));
+  return APC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* apc_version(void) { return "apc-mi355x 0.1 (gfx950)"; }
+
+const char* apc_last_error(apc_ctx) { return g_error.c_str(); }
+
+apc_status apc_create(int device, apc_ctx* out) {
+  if (!out) return fail(APC_E_ARG, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  HIPCHK(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) return fail(APC_E_ARG, "device %d not present (%d devices)", device, n);
+  HIPCHK(hipSetDevice(device));
+  apc_ctx c = new (std::nothrow) apc_ctx_s();
+  if (!c) return fail(APC_E_NOMEM, "host allocation failed");
+  c->device = device;
+  hipError_t e = c->counters.ensure(sizeof(unsigned long long) * apc::C_COUNT);
+  if (e == hipSuccess) e = hipMemset(c->counters.p, 0, c->counters.bytes);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->staging_done, hipEventDisableTiming);
+  for (int k = 0; k < 4 && e == hipSuccess; ++k)
+    for (int w = 0; w < 2 && e == hipSuccess; ++w) e = hipEventCreate(&c->ev[k][w]);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(APC_E_DEVICE, "context set-up failed: %s", hipGetErrorString(e));
+  }
+  *out = c;
+  return APC_OK;
+}
+
+apc_status apc_destroy(apc_ctx ctx) {
+  if (!ctx) return APC_OK;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  for (DevBuf* b : {&ctx->counts, &ctx->offsets, &ctx->cursors, &ctx->records, &ctx->scan_tmp, &ctx->slots,
+                    &ctx->order, &ctx->counters})
+    b->release();
+  if (ctx->staging) (void)hipHostFree(ctx->staging);
+  if (ctx->staging_done) (void)hipEventDestroy(ctx->staging_done);
+  for (int k = 0; k < 4; ++k)
+    for (int w = 0; w < 2; ++w)
+      if (ctx->ev[k][w]) (void)hipEventDestroy(ctx->ev[k][w]);
+  delete ctx;
+  return APC_OK;
+}
+
+apc_status apc_load_mesh(apc_ctx ctx, const apc_mesh_desc* d, apc_mesh* out, void* stream) {
+  apc_status st = check_ctx(ctx);
+  if (st != APC_OK) return st;
+  if (!d || !out) return fail(APC_E_ARG, "desc/out is NULL");
+  *out = nullptr;
+  if (d->flags != 0) return fail(APC_E_UNSUPPORTED, "mesh flags must be 0 (host pointers)");
+  if (!d->xyz || !d->scalar || !d->tet_vertices || !d->tet_subdomain) return fail(APC_E_ARG, "mesh array is NULL");
+  const int64_t V = d->n_vertices, T = d->n_tets;
+  const int S = d->n_subdomains;
+  if (V < 4 || V > (int64_t(1) << 31) - 1) return fail(APC_E_ARG, "n_vertices %lld out of range", (long long)V);
+  if (T < 1 || T >= (int64_t(1) << 29)) return fail(APC_E_ARG, "n_tets %lld out of range", (long long)T);
+  if (S < 1) return fail(APC_E_ARG, "n_subdomains must be >= 1");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int32_t* tv = d->tet_vertices;
+  const int32_t* ts = d->tet_subdomain;
+  const float* xyz = d->xyz;
+  // ---- validation (indices first: nothing touches memory through an unchecked id)
+  std::vector<int64_t> bad(16, -1);
+  std::vector<int> why(16, 0);
+  parallel_for(T, [&](int64_t lo, int64_t hi, int k) {
+    for (int64_t t = lo; t < hi; ++t) {
+      int reason = 0;
+      const int32_t* v = tv + 4 * t;
+      for (int q = 0; q < 4 && !reason; ++q)
+        if (v[q] < 0 || v[q] >= V) reason = 1;
+      if (!reason && (v[0] == v[1] || v[0] == v[2] || v[0] == v[3] || v[1] == v[2] || v[1] == v[3] || v[2] == v[3]))
+        reason = 2;
+      if (!reason && (ts[t] < 0 || ts[t] >= S)) reason = 3;
+      if (!reason) {
+        double p[4][3];
+        for (int q = 0; q < 4; ++q)
+          for (int c = 0; c < 3; ++c) p[q][c] = xyz[3 * int64_t(v[q]) + c];
+        double a[3], b[3], c3[3];
+        for (int c = 0; c < 3; ++c) {
+          a[c] = p[1][c] - p[0][c];
+          b[c] = p[2][c] - p[0][c];
+          c3[c] = p[3][c] - p[0][c];
+        }
+        double vol = a[0] * (b[1] * c3[2] - b[2] * c3[1]) - a[1] * (b[0] * c3[2] - b[2] * c3[0]) +
+                     a[2] * (b[0] * c3[1] - b[1] * c3[0]);
+        if (!(vol > 0.0)) reason = 4;
+      }
+      if (reason) {
+        bad[k] = t;
+        why[k] = reason;
+        return;
+      }
+    }
+  });
+  for (int k = 0; k < 16; ++k)
+    if (bad[k] >= 0) {
+      static const char* msg[] = {"", "vertex id out of range", "repeated vertex", "subdomain id out of range",
+                                  "non-positive signed volume"};
+      return fail(APC_E_MESH, "tet %lld: %s", (long long)bad[k], msg[why[k]]);
+    }
+  for (int64_t q = 0; q < 3 * V; ++q)
+    if (!std::isfinite(xyz[q])) return fail(APC_E_MESH, "vertex coordinate %lld is not finite", (long long)(q / 3));
+  // ---- group tets by subdomain, keeping input order inside each (stable counting sort)
+  apc_mesh_s* m = new (std::nothrow) apc_mesh_s();
+  if (!m) return fail(APC_E_NOMEM, "host allocation failed");
+  m->ctx = ctx;
+  m->V = V;
+  m->T = T;
+  m->S = S;
+  m->sub_begin.assign(S + 1, 0);
+  for (int64_t t = 0; t < T; ++t) ++m->sub_begin[ts[t] + 1];
+  for (int k = 0; k < S; ++k) m->sub_begin[k + 1] += m->sub_begin[k];
+  std::vector<int4> tv_sorted(T);
+  {
+    std::vector<int> cur(m->sub_begin.begin(), m->sub_begin.end() - 1);
+    for (int64_t t = 0; t < T; ++t) {
+      const int32_t* v = tv + 4 * t;
+      tv_sorted[cur[ts[t]]++] = make_int4(v[0], v[1], v[2], v[3]);
+    }
+  }
+  for (int c = 0; c < 3; ++c) {
+    m->lo[c] = 1e300;
+    m->hi[c] = -1e300;
+  }
+  for (int64_t v = 0; v < V; ++v)
+    for (int c = 0; c < 3; ++c) {
+      m->lo[c] = std::min(m->lo[c], double(xyz[3 * v + c]));
+      m->hi[c] = std::max(m->hi[c], double(xyz[3 * v + c]));
+    }
+  std::vector<float4> vert(V);
+  for (int64_t v = 0; v < V; ++v) vert[v] = make_float4(xyz[3 * v], xyz[3 * v + 1], xyz[3 * v + 2], d->scalar[v]);
+  // ---- face adjacency on the device through vertex -> tet incidence lists
+  DevBuf d_tv, d_cnt, d_off, d_cur, d_inc, d_nbr, d_err, d_tmp;
+  auto cleanup = [&]() {
+    for (DevBuf* b : {&d_tv, &d_cnt, &d_off, &d_cur, &d_inc, &d_nbr, &d_err, &d_tmp}) b->release();
+  };
+  auto dev_fail = [&](hipError_t e, const char* what) {
+    cleanup();
+    if (m->vert) (void)hipFree(m->vert);
+    if (m->tet) (void)hipFree(m->tet);
+    if (m->bface) (void)hipFree(m->bface);
+    delete m;
+    return fail(e == hipErrorOutOfMemory ? APC_E_NOMEM : APC_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+  };
+  hipError_t e;
+  std::vector<int> nbr(4 * T);
+  {
+    if ((e = d_tv.ensure(sizeof(int4) * T)) != hipSuccess) return dev_fail(e, "alloc");
+    if ((e = d_cnt.ensure(sizeof(int) * (V + 1))) != hipSuccess) return dev_fail(e, "alloc");
+    if ((e = d_off.ensure(sizeof(int) * (V + 1))) != hipSuccess) return dev_fail(e, "alloc");
+    if ((e = d_cur.ensure(sizeof(int) * V)) != hipSuccess) return dev_fail(e, "alloc");
+    if ((e = d_inc.ensure(sizeof(int) * 4 * T)) != hipSuccess) return dev_fail(e, "alloc");
+    if ((e = d_nbr.ensure(sizeof(int) * 4 * T)) != hipSuccess) return dev_fail(e, "alloc");
+    if ((e = d_err.ensure(sizeof(int))) != hipSuccess) return dev_fail(e, "alloc");
+    if ((e = d_tmp.ensure(sizeof(int) * apc::scan_tmp_elems(V + 1))) != hipSuccess) return dev_fail(e, "alloc");
+    if ((e = hipMemcpyAsync(d_tv.p, tv_sorted.data(), sizeof(int4) * T, hipMemcpyHostToDevice, s)) != hipSuccess)
+      return dev_fail(e, "upload");
+    if ((e = apc::launch_fill_i32(d_cnt.as<int>(), 0, V + 1, s)) != hipSuccess) return dev_fail(e, "fill");
+    if ((e = apc::launch_fill_i32(d_cur.as<int>(), 0, V, s)) != hipSuccess) return dev_fail(e, "fill");
+    if ((e = apc::launch_fill_i32(d_err.as<int>(), 0, 1, s)) != hipSuccess) return dev_fail(e, "fill");
+    if ((e = apc::launch_incidence_count(d_tv.as<int4>(), T, d_cnt.as<int>(), s)) != hipSuccess)
+      return dev_fail(e, "incidence");
+    if ((e = apc::launch_exclusive_scan(d_cnt.as<int>(), d_off.as<int>(), V + 1, d_tmp.as<int>(), s)) != hipSuccess)
+      return dev_fail(e, "scan");
+    if ((e = apc::launch_incidence_fill(d_tv.as<int4>(), T, d_off.as<int>(), d_cur.as<int>(), d_inc.as<int>(), s)) !=
+        hipSuccess)
+      return dev_fail(e, "incidence");
+    if ((e = apc::launch_adjacency(d_tv.as<int4>(), T, d_off.as<int>(), d_inc.as<int>(), d_nbr.as<int>(),
+                                   d_err.as<int>(), s)) != hipSuccess)
+      return dev_fail(e, "adjacency");
+    int err = 0;
+    if ((e = hipMemcpyAsync(nbr.data(), d_nbr.p, sizeof(int) * 4 * T, hipMemcpyDeviceToHost, s)) != hipSuccess)
+      return dev_fail(e, "download");
+    if ((e = hipMemcpyAsync(&err, d_err.p, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess)
+      return dev_fail(e, "download");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return dev_fail(e, "adjacency");
+    cleanup();
+    if (err) {
+      delete m;
+      return fail(APC_E_MESH, "a face is shared by more than two tets (non-manifold mesh)");
+    }
+  }
+  // ---- boundary faces of each subdomain: hull faces and faces shared with another subdomain
+  std::vector<std::vector<int>> bf(S);
+  {
+    std::vector<std::thread> th;
+    unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    for (unsigned w = 0; w < nt; ++w)
+      th.emplace_back([&, w] {
+        for (int k = int(w); k < S; k += int(nt)) {
+          const int b0 = m->sub_begin[k], b1 = m->sub_begin[k + 1];
+          for (int t = b0; t < b1; ++t)
+            for (int fc = 0; fc < 4; ++fc) {
+              const int nb = nbr[4 * int64_t(t) + fc];
+              if (nb < 0 || (nb >> 2) < b0 || (nb >> 2) >= b1) bf[k].push_back((t << 2) | fc);
+            }
+        }
+      });
+    for (auto& t : th) t.join();
+  }
+  m->face_begin.assign(S + 1, 0);
+  for (int k = 0; k < S; ++k) m->face_begin[k + 1] = m->face_begin[k] + int(bf[k].size());
+  m->NB = m->face_begin[S];
+  std::vector<int> bface(std::max<int64_t>(m->NB, 1));
+  for (int k = 0; k < S; ++k) std::copy(bf[k].begin(), bf[k].end(), bface.begin() + m->face_begin[k]);
+  std::vector<int4> rec(2 * T);
+  parallel_for(T, [&](int64_t lo, int64_t hi, int) {
+    for (int64_t t = lo; t < hi; ++t) {
+      rec[2 * t] = tv_sorted[t];
+      rec[2 * t + 1] = make_int4(nbr[4 * t], nbr[4 * t + 1], nbr[4 * t + 2], nbr[4 * t + 3]);
+    }
+  });
+  // ---- resident upload
+  if ((e = hipMalloc(&m->vert, sizeof(float4) * V)) != hipSuccess) return dev_fail(e, "alloc");
+  if ((e = hipMalloc(&m->tet, sizeof(int4) * 2 * T)) != hipSuccess) return dev_fail(e, "alloc");
+  if ((e = hipMalloc(&m->bface, sizeof(int) * bface.size())) != hipSuccess) return dev_fail(e, "alloc");
+  if ((e = hipMemcpyAsync(m->vert, vert.data(), sizeof(float4) * V, hipMemcpyHostToDevice, s)) != hipSuccess)
+    return dev_fail(e, "upload");
+  if ((e = hipMemcpyAsync(m->tet, rec.data(), sizeof(int4) * 2 * T, hipMemcpyHostToDevice, s)) != hipSuccess)
+    return dev_fail(e, "upload");
+  if ((e = hipMemcpyAsync(m->bface, bface.data(), sizeof(int) * bface.size(), hipMemcpyHostToDevice, s)) !=
+      hipSuccess)
+    return dev_fail(e, "upload");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return dev_fail(e, "upload");
+  m->device_bytes = int64_t(sizeof(float4) * V + sizeof(int4) * 2 * T + sizeof(int) * bface.size());
+  *out = m;
+  return APC_OK;
+}
+
+apc_status apc_free_mesh(apc_ctx ctx, apc_mesh m) {
+  if (!m) return APC_OK;
+  if (ctx) (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  if (m->vert) (void)hipFree(m->vert);
+  if (m->tet) (void)hipFree(m->tet);
+  if (m->bface) (void)hipFree(m->bface);
+  delete m;
+  return APC_OK;
+}
+
+apc_status apc_mesh_get_info(apc_mesh m, apc_mesh_info* out) {
+  if (!m || !out) return fail(APC_E_ARG, "mesh/out is NULL");
+  std::memset(out, 0, sizeof(*out));
+  out->n_vertices = m->V;
+  out->n_tets = m->T;
+  out->n_boundary_faces = m->NB;
+  out->n_subdomains = m->S;
+  for (int c = 0; c < 3; ++c) {
+    out->bbox_lo[c] = m->lo[c];
+    out->bbox_hi[c] = m->hi[c];
+  }
+  out->device_bytes = m->device_bytes;
+  return APC_OK;
+}
+
+apc_status apc_mesh_subdomain_info(apc_mesh m, int32_t sub, int64_t* n_tets, int64_t* n_faces) {
+  if (!m) return fail(APC_E_ARG, "mesh is NULL");
+  if (sub < 0 || sub >= m->S) return fail(APC_E_ARG, "subdomain %d out of range", sub);
+  if (n_tets) *n_tets = m->sub_begin[sub + 1] - m->sub_begin[sub];
+  if (n_faces) *n_faces = m->face_begin[sub + 1] - m->face_begin[sub];
+  return APC_OK;
+}
+
+apc_status apc_moments_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const apc_tf* tf, int32_t mm,
+                            const int32_t* subs, int32_t n_sub, float* out, uint32_t flags, void* stream) {
+  apc_status st = check_ctx(ctx);
+  if (st != APC_OK) return st;
+  if (!m) return fail(APC_E_ARG, "mesh is NULL");
+  if ((st = check_view_tf(view, tf)) != APC_OK) return st;
+  if (mm != 4 && mm != 6 && mm != 8) return fail(APC_E_ARG, "m = %d unsupported (4, 6 or 8)", mm);
+  if ((st = check_subdomains(m, subs, n_sub)) != APC_OK) return st;
+  if (!out) return fail(APC_E_ARG, "output is NULL");
+  if (flags != 0) return fail(APC_E_ARG, "unknown flags 0x%x", flags);
+  FrameDev f;
+  if ((st = make_frame(m, view, tf, n_sub, max_tets_of(m, subs, n_sub), f)) != APC_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  MeshDev md;
+  if ((st = build_bins(ctx, m, f, subs, n_sub, s, md)) != APC_OK) return st;
+  HIPCHK(ev_mark(ctx, EV_MOM, 0, s));
+  HIPCHK(apc::launch_moments(mm, md, f, ctx->slots.as<SlotDev>(), ctx->offsets.as<int>(), ctx->counts.as<int>(),
+                             ctx->records.as<int>(), tf->rgba, out, ctx->counters.as<unsigned long long>(), s));
+  HIPCHK(ev_mark(ctx, EV_MOM, 1, s));
+  return APC_OK;
+}
+
+apc_status apc_sum_moments(apc_ctx ctx, const float* in, int32_t n_sub, int32_t mm, int32_t H, int32_t W,
+                           const int32_t* subs, float* outg, void* stream) {
+  apc_status st = check_ctx(ctx);
+  if (st != APC_OK) return st;
+  if (!in || !outg) return fail(APC_E_ARG, "buffer is NULL");
+  if (mm != 4 && mm != 6 && mm != 8) return fail(APC_E_ARG, "m = %d unsupported", mm);
+  if (n_sub < 1 || H <= 0 || W <= 0) return fail(APC_E_ARG, "sizes out of range");
+  std::vector<int> order(n_sub);
+  for (int k = 0; k < n_sub; ++k) order[k] = k;
+  if (subs) {
+    for (int k = 0; k < n_sub; ++k)
+      for (int q = 0; q < k; ++q)
+        if (subs[q] == subs[k]) return fail(APC_E_ARG, "subdomain id %d listed twice", subs[k]);
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return subs[a] < subs[b]; });
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIPCHK(ctx->order.ensure(sizeof(int) * n_sub));
+  if ((st = stage_upload(ctx, ctx->order.p, order.data(), sizeof(int) * n_sub, s)) != APC_OK) return st;
+  HIPCHK(ev_mark(ctx, EV_SUM, 0, s));
+  HIPCHK(apc::launch_sum_moments(in, n_sub, ctx->order.as<int>(), int64_t(mm + 1) * H * W, outg, s));
+  HIPCHK(ev_mark(ctx, EV_SUM, 1, s));
+  return APC_OK;
+}
+
+static apc_status bound_params(const apc_mboit* mb, apc::BoundParams& bp, int finalize) {
+  if (!mb) return fail(APC_E_ARG, "mboit is NULL");
+  if (mb->m != 4 && mb->m != 6 && mb->m != 8) return fail(APC_E_ARG, "m = %d unsupported", mb->m);
+  if (!(mb->alpha >= 0.0 && mb->alpha < 1.0)) return fail(APC_E_ARG, "alpha must be in [0, 1)");
+  if (!(mb->eta >= 0.0 && mb->eta <= 1.0)) return fail(APC_E_ARG, "eta must be in [0, 1]");
+  std::memset(&bp, 0, sizeof(bp));
+  bp.alpha = mb->alpha;
+  bp.eta = mb->eta;
+  for (int j = 0; j < 8; ++j) bp.bias[j] = j < mb->m ? mb->bias[j] : 0.0;
+  bp.renormalize = mb->renormalize ? 1 : 0;
+  bp.finalize = finalize;
+  return APC_OK;
+}
+
+apc_status apc_resolve_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const apc_tf* tf, const apc_mboit* mb,
+                            const float* moments, const int32_t* subs, int32_t n_sub, float* rgba, uint32_t flags,
+                            void* stream) {
+  apc_status st = check_ctx(ctx);
+  if (st != APC_OK) return st;
+  if (!m) return fail(APC_E_ARG, "mesh is NULL");
+  if ((st = check_view_tf(view, tf)) != APC_OK) return st;
+  apc::BoundParams bp;
+  if ((st = bound_params(mb, bp, (flags & APC_FINALIZE) ? 1 : 0)) != APC_OK) return st;
+  if ((st = check_subdomains(m, subs, n_sub)) != APC_OK) return st;
+  if (!moments || !rgba) return fail(APC_E_ARG, "buffer is NULL");
+  if (reinterpret_cast<uintptr_t>(rgba) & 15) return fail(APC_E_ARG, "rgba_out must be 16-byte aligned");
+  if (flags & ~APC_FINALIZE) return fail(APC_E_ARG, "unknown flags 0x%x", flags);
+  FrameDev f;
+  if ((st = make_frame(m, view, tf, n_sub, max_tets_of(m, subs, n_sub), f)) != APC_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  MeshDev md;
+  if ((st = build_bins(ctx, m, f, subs, n_sub, s, md)) != APC_OK) return st;
+  HIPCHK(ev_mark(ctx, EV_RES, 0, s));
+  HIPCHK(apc::launch_resolve(mb->m, md, f, ctx->slots.as<SlotDev>(), ctx->offsets.as<int>(), ctx->counts.as<int>(),
+                             ctx->records.as<int>(), tf->rgba, moments, bp, rgba,
+                             ctx->counters.as<unsigned long long>(), s));
+  HIPCHK(ev_mark(ctx, EV_RES, 1, s));
+  return APC_OK;
+}
+
+apc_status apc_sum_images(apc_ctx ctx, const float* partials, int32_t n_sub, int32_t H, int32_t W,
+                          const int32_t* subs, const float* moments, const apc_mboit* mb, float* rgba,
+                          void* stream) {
+  apc_status st = check_ctx(ctx);
+  if (st != APC_OK) return st;
+  if (!partials || !moments || !rgba) return fail(APC_E_ARG, "buffer is NULL");
+  if (n_sub < 1 || H <= 0 || W <= 0) return fail(APC_E_ARG, "sizes out of range");
+  if ((reinterpret_cast<uintptr_t>(rgba) | reinterpret_cast<uintptr_t>(partials)) & 15)
+    return fail(APC_E_ARG, "image buffers must be 16-byte aligned");
+  apc::BoundParams bp;
+  if ((st = bound_params(mb, bp, 1)) != APC_OK) return st;
+  std::vector<int> order(n_sub);
+  for (int k = 0; k < n_sub; ++k) order[k] = k;
+  if (subs) {
+    for (int k = 0; k < n_sub; ++k)
+      for (int q = 0; q < k; ++q)
+        if (subs[q] == subs[k]) return fail(APC_E_ARG, "subdomain id %d listed twice", subs[k]);
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return subs[a] < subs[b]; });
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIPCHK(ctx->order.ensure(sizeof(int) * n_sub));
+  if ((st = stage_upload(ctx, ctx->order.p, order.data(), sizeof(int) * n_sub, s)) != APC_OK) return st;
+  HIPCHK(apc::launch_sum_images(partials, n_sub, ctx->order.as<int>(), int64_t(H) * W, moments, bp, rgba, s));
+  return APC_OK;
+}
+
+apc_status apc_get_counters(apc_ctx ctx, apc_counters* out, int32_t reset) {
+  apc_status st = check_ctx(ctx);
+  if (st != APC_OK) return st;
+  if (!out) return fail(APC_E_ARG, "out is NULL");
+  HIPCHK(hipDeviceSynchronize());
+  unsigned long long c[apc::C_COUNT];
+  HIPCHK(hipMemcpy(c, ctx->counters.p, sizeof(c), hipMemcpyDeviceToHost));
+  out->pieces = int64_t(c[apc::C_PIECES]);
+  out->tet_steps = int64_t(c[apc::C_STEPS]);
+  out->entries = int64_t(c[apc::C_ENTRIES]);
+  out->bin_records = ctx->bin_records;
+  out->walk_step_limit = int64_t(c[apc::C_STEPLIMIT]);
+  out->exit_fallback = int64_t(c[apc::C_FALLBACK]);
+  out->entry_overflow = int64_t(c[apc::C_OVERFLOW]);
+  out->nonpd_pivots = int64_t(c[apc::C_NONPD]);
+  if (reset) {
+    HIPCHK(hipMemset(ctx->counters.p, 0, sizeof(c)));
+    ctx->bin_records = 0;
+  }
+  return APC_OK;
+}
+
+apc_status apc_get_timings(apc_ctx ctx, apc_timings* out) {
+  apc_status st = check_ctx(ctx);
+  if (st != APC_OK) return st;
+  if (!out) return fail(APC_E_ARG, "out is NULL");
+  double ms[4] = {0, 0, 0, 0};
+  for (int k = 0; k < 4; ++k) {
+    if (!ctx->ev_used[k]) continue;
+    HIPCHK(hipEventSynchronize(ctx->ev[k][1]));
+    float v = 0.0f;
+    HIPCHK(hipEventElapsedTime(&v, ctx->ev[k][0], ctx->ev[k][1]));
+    ms[k] = v;
+  }
+  out->bin_ms = ms[EV_BIN];
+  out->moments_ms = ms[EV_MOM];
+  out->sum_ms = ms[EV_SUM];
+  out->resolve_ms = ms[EV_RES];
+  return APC_OK;
+}
+
+}  // extern "C"

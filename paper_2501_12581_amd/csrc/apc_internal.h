@@ -1,0 +1,88 @@
+// Declarations shared by the host side of the C ABI (apc_api.cpp) and the
+// HIP kernels (apc_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace apc {
+
+// Device-resident mesh.  Tets are grouped by subdomain; tet record t is two
+// int4 at tet[2t] (vertex ids, positively oriented) and tet[2t+1] (neighbour
+// code per face: face f is opposite vertex f; code = (nbr_tet << 2) | face
+// index of the shared face in nbr_tet, or -1 on the mesh hull).
+struct MeshDev {
+  const float4* vert;  // [V]: x, y, z, scalar
+  const int4* tet;     // [2T]
+  int64_t n_vertices;
+  int64_t n_tets;
+};
+
+// One subdomain taking part in a call.
+struct SlotDev {
+  int tet_begin, tet_end;    // tet range of the subdomain
+  int face_begin, face_end;  // range in the boundary-face array
+};
+
+// Per-call constants, FP32 copies of the camera, lattice, warp and transfer
+// function parameters.
+struct FrameDev {
+  int W, H, proj, tiles_x, tiles_y, n_tiles, n_slots, n_tf;
+  float ex, ey, ez;     // eye (perspective origin / orthographic image-plane origin)
+  float dx, dy, dz;     // forward direction (unit for orthographic)
+  float rx, ry, rz;     // right
+  float wx, wy, wz;     // down
+  float half_w, half_h; // W/2, H/2
+  // Depths inside the kernels are measured from a ray origin moved forward by
+  // t_mid = (t_near + t_far) / 2, so |t| <= (t_far - t_near) / 2 and FP32
+  // depths resolve ~4x finer than absolute distances would.  t_near below is
+  // the lattice origin in those shifted units (t_near - t_mid).
+  float t_mid, t_near, step, inv_step;
+  float lg_near, warp_scale;  // log2(t_near), 2 / (log2 t_far - log2 t_near), absolute units
+  float s_min, tf_scale;      // table coordinate = (s - s_min) * tf_scale
+  float kappa, amax;
+  int max_steps;
+  float minv[9];  // inverse of the 3x3 matrix with columns dir, right, down (screen projection)
+};
+
+// Moment-bound parameters in the precision of the resolve pass.
+struct BoundParams {
+  double alpha, eta;
+  double bias[8];
+  int renormalize, finalize;
+};
+
+// Diagnostic counters (device memory, int64 each), in apc_counters order.
+enum { C_PIECES = 0, C_STEPS, C_ENTRIES, C_BINREC, C_STEPLIMIT, C_FALLBACK, C_OVERFLOW, C_NONPD, C_COUNT };
+
+constexpr int TILE = 8;   // 8x8 pixels per tile, one wavefront
+constexpr int MAX_TF = 1024;
+
+// ---- frame kernels (apc_kernels.hip)
+hipError_t launch_bin_count(const MeshDev& m, const FrameDev& f, const SlotDev* slots, int max_faces,
+                            const int* bface, int* counts, hipStream_t s);
+hipError_t launch_bin_fill(const MeshDev& m, const FrameDev& f, const SlotDev* slots, int max_faces,
+                           const int* bface, const int* offsets, int* cursors, int* records, hipStream_t s);
+hipError_t launch_moments(int mm, const MeshDev& m, const FrameDev& f, const SlotDev* slots, const int* offsets,
+                          const int* counts, const int* records, const float* tf_rgba, float* out,
+                          unsigned long long* counters, hipStream_t s);
+hipError_t launch_resolve(int mm, const MeshDev& m, const FrameDev& f, const SlotDev* slots, const int* offsets,
+                          const int* counts, const int* records, const float* tf_rgba, const float* moments,
+                          const BoundParams& bp, float* rgba, unsigned long long* counters, hipStream_t s);
+hipError_t launch_sum_moments(const float* in, int n_slots, const int* order, int64_t elems, float* out,
+                              hipStream_t s);
+hipError_t launch_sum_images(const float* in, int n_slots, const int* order, int64_t pixels, const float* b0,
+                             const BoundParams& bp, float* out, hipStream_t s);
+// exclusive scan of n int32 values; tmp must hold scan_tmp_elems(n) ints
+int64_t scan_tmp_elems(int64_t n);
+hipError_t launch_exclusive_scan(const int* in, int* out, int64_t n, int* tmp, hipStream_t s);
+hipError_t launch_fill_i32(int* p, int value, int64_t n, hipStream_t s);
+
+// ---- mesh residency kernels
+hipError_t launch_incidence_count(const int4* tv, int64_t n_tets, int* counts, hipStream_t s);
+hipError_t launch_incidence_fill(const int4* tv, int64_t n_tets, const int* offsets, int* cursors, int* inc,
+                                 hipStream_t s);
+hipError_t launch_adjacency(const int4* tv, int64_t n_tets, const int* offsets, const int* inc, int* nbr,
+                            int* err, hipStream_t s);
+
+}  // namespace apc

@@ -1,0 +1,931 @@
+// HIP kernels (gfx950) for the APC hot path.
+//
+// One frame = for the listed subdomains:
+//   k_bin        boundary faces of each subdomain -> (tile, subdomain) bins
+//                (count pass, exclusive scan, fill pass)
+//   k_moments    one 64-lane wavefront per 8x8 pixel tile: per subdomain,
+//                collect the boundary faces where each pixel ray enters the
+//                subdomain, walk the ray tet by tet from each entry to where
+//                it leaves the subdomain, cut every chord at the global
+//                sampling lattice and add a*z^j per piece (paper Alg. 2)
+//   k_sum_moments  canonical-order FP64 sum of the per-subdomain images
+//                (the paper's moment Allreduce, Section 4.1)
+//   k_resolve    the same walk again; per pixel the global moments give the
+//                moment bound (Alg. 3), per piece T = exp(-b0 F) weights the
+//                piece's colour (Alg. 1 second loop, Section 4.2)
+//   k_sum_images canonical-order sum of partial images + renormalisation
+//
+// Geometry.  A ray crosses a face iff its Plücker side products with the
+// face's three edges share one sign.  Every edge product is computed from the
+// edge's lower-id vertex towards its higher-id vertex, with one formula, and
+// an exact zero counts as positive; the entry test of one subdomain and the
+// exit test of the walk in its neighbour therefore see identical signs for
+// the face they share, so every ray crosses each subdomain interface exactly
+// once (no gaps, no double counting).  The barycentric coordinates of the
+// crossing point are the three edge products of the face, which give the
+// depth t and the scalar at the crossing.  Functions whose results must agree
+// bit for bit between the two passes or between the entry test and the walk
+// are compiled without floating-point contraction.
+#include <float.h>
+
+#include "apc_internal.h"
+#include "apc_mboit.h"
+
+namespace apc {
+namespace {
+
+constexpr int WAVE = 64;
+constexpr int E_MAX = 16;    // entries per ray held at once (more are handled in further rounds)
+constexpr int CHUNK = 64;    // boundary faces staged in LDS at a time
+
+// outward vertex order of the face opposite vertex f of a positively oriented tet
+__device__ __constant__ int kFaceOut[4][3] = {{1, 2, 3}, {0, 3, 2}, {0, 1, 3}, {0, 2, 1}};
+
+__device__ __forceinline__ int sel4(const int4& v, int i) {
+  return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs; give every XCD a
+// contiguous run of tiles so that neighbouring tiles (which read the same
+// tets) share that XCD's L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  int q = nb >> 3, r = nb & 7;
+  int x = b & 7, i = b >> 3;
+  return x * q + (x < r ? x : r) + i;
+}
+
+struct Ray {
+  float ox, oy, oz, dx, dy, dz;
+};
+
+__device__ __forceinline__ Ray pixel_ray(const FrameDev& f, int i, int j) {
+#pragma clang fp contract(off)
+  float a = float(j) + 0.5f, b = float(i) + 0.5f;
+  Ray r;
+  float dx, dy, dz;
+  if (f.proj == 0) {
+    r.ox = f.ex + a * f.rx + b * f.wx;
+    r.oy = f.ey + a * f.ry + b * f.wy;
+    r.oz = f.ez + a * f.rz + b * f.wz;
+    dx = f.dx;
+    dy = f.dy;
+    dz = f.dz;
+  } else {
+    r.ox = f.ex;
+    r.oy = f.ey;
+    r.oz = f.ez;
+    float aa = a - f.half_w, bb = b - f.half_h;
+    dx = f.dx + aa * f.rx + bb * f.wx;
+    dy = f.dy + aa * f.ry + bb * f.wy;
+    dz = f.dz + aa * f.rz + bb * f.wz;
+  }
+  float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+  r.dx = dx * inv;
+  r.dy = dy * inv;
+  r.dz = dz * inv;
+  // depth 0 at the middle of the depth range
+  r.ox = r.ox + f.t_mid * r.dx;
+  r.oy = r.oy + f.t_mid * r.dy;
+  r.oz = r.oz + f.t_mid * r.dz;
+  return r;
+}
+
+// A vertex as seen from one ray: id, position, scalar, depth t = d.(P-o) and
+// w = d x (P-o).
+struct VS {
+  int id;
+  float x, y, z, s, t, wx, wy, wz;
+};
+
+__device__ __forceinline__ VS vstate(const Ray& r, int id, float4 p) {
+#pragma clang fp contract(off)
+  VS v;
+  v.id = id;
+  v.x = p.x;
+  v.y = p.y;
+  v.z = p.z;
+  v.s = p.w;
+  float px = p.x - r.ox, py = p.y - r.oy, pz = p.z - r.oz;
+  v.t = r.dx * px + r.dy * py + r.dz * pz;
+  v.wx = r.dy * pz - r.dz * py;
+  v.wy = r.dz * px - r.dx * pz;
+  v.wz = r.dx * py - r.dy * px;
+  return v;
+}
+
+// Plücker side product d.((lo-o) x (hi-o)) = (d x (lo-o)).(hi-lo) of the ray
+// with the edge lo -> hi, lo.id < hi.id.  Exact zero counts as positive.
+__device__ __forceinline__ float side_canon(const VS& lo, const VS& hi) {
+#pragma clang fp contract(off)
+  float p = lo.wx * (hi.x - lo.x) + lo.wy * (hi.y - lo.y) + lo.wz * (hi.z - lo.z);
+  return p == 0.0f ? FLT_MIN : p;
+}
+
+// oriented side product of a -> b
+__device__ __forceinline__ float side(const VS& a, const VS& b) {
+  return a.id < b.id ? side_canon(a, b) : -side_canon(b, a);
+}
+
+// Crossing point of the ray with the face (A, B, C) whose oriented products
+// pAB, pBC, pCA are all positive: barycentric weights (pBC, pCA, pAB).  The
+// sums start at the vertex with the smallest id, so the walk that leaves a
+// tet through a face and the entry test of the tet behind it (which list the
+// face's vertices in different rotations) get the same depth bit for bit.
+__device__ __forceinline__ void face_point(const VS& A, const VS& B, const VS& C, float pAB, float pBC, float pCA,
+                                           float& t, float& s) {
+#pragma clang fp contract(off)
+  float uA = fmaxf(pBC, 0.0f), uB = fmaxf(pCA, 0.0f), uC = fmaxf(pAB, 0.0f);
+  const bool bmin = B.id < A.id && B.id < C.id, cmin = C.id < A.id && C.id < B.id;
+  const float u0 = bmin ? uB : (cmin ? uC : uA), u1 = bmin ? uC : (cmin ? uA : uB), u2 = bmin ? uA : (cmin ? uB : uC);
+  const float t0 = bmin ? B.t : (cmin ? C.t : A.t), t1 = bmin ? C.t : (cmin ? A.t : B.t),
+              t2 = bmin ? A.t : (cmin ? B.t : C.t);
+  const float s0 = bmin ? B.s : (cmin ? C.s : A.s), s1 = bmin ? C.s : (cmin ? A.s : B.s),
+              s2 = bmin ? A.s : (cmin ? B.s : C.s);
+  float sum = u0 + u1 + u2;
+  if (!(sum > 0.0f)) {
+    t = t0;
+    s = s0;
+    return;
+  }
+  float inv = 1.0f / sum;
+  t = (u0 * t0 + u1 * t1 + u2 * t2) * inv;
+  s = (u0 * s0 + u1 * s1 + u2 * s2) * inv;
+}
+
+// A boundary face staged in LDS, vertices in outward order of its tet.
+struct FaceL {
+  int code;  // (tet << 2) | face
+  int id0, id1, id2;
+  float4 p0, p1, p2;
+};
+
+// Does the ray enter the face's tet through it?  On success returns the
+// entry state: the face in inward order (A, B, C) with its positive
+// products, and the entry depth/scalar.
+struct Entry {
+  VS A, B, C;
+  float pAB, pBC, pCA, t, s;
+};
+
+__device__ __forceinline__ bool enter_face(const Ray& r, int id0, int id1, int id2, float4 p0, float4 p1,
+                                           float4 p2, Entry& e) {
+  VS a = vstate(r, id0, p0), b = vstate(r, id1, p1), c = vstate(r, id2, p2);
+  float sab = side(a, b), sbc = side(b, c), sca = side(c, a);
+  if (!(sab < 0.0f && sbc < 0.0f && sca < 0.0f)) return false;
+  // inward order (a, c, b): pi(a->c) = -sca, pi(c->b) = -sbc, pi(b->a) = -sab
+  e.A = a;
+  e.B = c;
+  e.C = b;
+  e.pAB = -sca;
+  e.pBC = -sbc;
+  e.pCA = -sab;
+  face_point(e.A, e.B, e.C, e.pAB, e.pBC, e.pCA, e.t, e.s);
+  return true;
+}
+
+struct LaneCount {
+  unsigned pieces, steps, entries, steplimit, fallback, overflow, nonpd;
+};
+
+// Cut the chord [t0, t1] (scalar s0 -> s1) at the lattice t_near + k*step and
+// hand each piece (mid depth, length, scalar at the mid point) to fn.
+template <class Fn>
+__device__ __forceinline__ void cut_chord(const FrameDev& f, float t0, float t1, float s0, float s1, Fn&& fn) {
+#pragma clang fp contract(off)
+  float len = t1 - t0;
+  if (!(len > 0.0f)) return;
+  float slope = (s1 - s0) / len;
+  float kf = floorf((t0 - f.t_near) * f.inv_step) + 1.0f;
+  float u = t0;
+  for (int guard = 0; u < t1 && guard < (1 << 22); ++guard) {
+    float nxt = f.t_near + kf * f.step;
+    kf += 1.0f;
+    if (nxt <= u) continue;
+    float v = fminf(nxt, t1);
+    float tm = 0.5f * (u + v);
+    float s = s0 + slope * (tm - t0);
+    fn(tm, v - u, s);
+    u = v;
+  }
+}
+
+// Transfer-function table coordinate of scalar s: entry i0 and fraction fr.
+__device__ __forceinline__ void tf_coord(const FrameDev& f, float s, int& i0, float& fr) {
+#pragma clang fp contract(off)
+  float u = (s - f.s_min) * f.tf_scale;
+  u = fminf(fmaxf(u, 0.0f), float(f.n_tf - 1));
+  i0 = min(int(u), f.n_tf - 2);
+  fr = u - float(i0);
+}
+
+// Optical depth of a piece and its warped depth (Alg. 2: absorbance capped,
+// log depth rescaled to [-1, 1]).
+__device__ __forceinline__ void piece_az(const FrameDev& f, float tm, float len, float A, float& a, float& z) {
+#pragma clang fp contract(off)
+  a = fminf(f.kappa * A * len, f.amax);
+  z = (__log2f(tm + f.t_mid) - f.lg_near) * f.warp_scale - 1.0f;
+  z = fminf(fmaxf(z, -1.0f), 1.0f);
+}
+
+__device__ __forceinline__ float lerp_nc(float a, float b, float fr) {
+#pragma clang fp contract(off)
+  return a * (1.0f - fr) + b * fr;
+}
+
+// Walk the ray from an entry through the tets of one subdomain (tet range
+// [t_lo, t_hi)) until it leaves the subdomain, handing every chord to sink.
+// `apex` is the local index of the vertex opposite the entry face.
+template <class Sink>
+__device__ void walk(const MeshDev& M, const FrameDev& f, const Ray& r, int tet, int apex, Entry e, int t_lo,
+                     int t_hi, Sink& sink, LaneCount& cnt) {
+  VS A = e.A, B = e.B, C = e.C;
+  float pAB = e.pAB, pBC = e.pBC, pCA = e.pCA, tin = e.t, sin_ = e.s;
+  for (int step = 0;; ++step) {
+    if (step >= f.max_steps) {
+      ++cnt.steplimit;
+      return;
+    }
+    const int4 tv = M.tet[2 * tet];
+    const int4 tn = M.tet[2 * tet + 1];
+    int did = sel4(tv, apex);
+    VS D = vstate(r, did, M.vert[did]);
+    float qA = side(D, A), qB = side(D, B), qC = side(D, C);
+    // exit through the face opposite X where q(next of X) > 0 > q(previous of X)
+    int x;
+    if (qB > 0.0f && qC < 0.0f)
+      x = 0;
+    else if (qC > 0.0f && qA < 0.0f)
+      x = 1;
+    else if (qA > 0.0f && qB < 0.0f)
+      x = 2;
+    else {  // sign pattern no line can have (rounding near a vertex): least-violated face
+      float m0 = fminf(qB, -qC), m1 = fminf(qC, -qA), m2 = fminf(qA, -qB);
+      x = (m0 >= m1 && m0 >= m2) ? 0 : (m1 >= m2 ? 1 : 2);
+      ++cnt.fallback;
+    }
+    VS Y = x == 0 ? B : (x == 1 ? C : A);
+    VS Z = x == 0 ? C : (x == 1 ? A : B);
+    float pYZ = x == 0 ? pBC : (x == 1 ? pCA : pAB);
+    float qY = x == 0 ? qB : (x == 1 ? qC : qA);
+    float qZ = x == 0 ? qC : (x == 1 ? qA : qB);
+    int xid = x == 0 ? A.id : (x == 1 ? B.id : C.id);
+    float tout, sout;
+    face_point(Y, Z, D, pYZ, -qZ, qY, tout, sout);
+    if (!(tout >= tin)) tout = tin;
+    ++cnt.steps;
+    sink.chord(tin, tout, sin_, sout);
+    int xl = tv.x == xid ? 0 : (tv.y == xid ? 1 : (tv.z == xid ? 2 : 3));
+    int nb = sel4(tn, xl);
+    if (nb < 0) return;
+    int t2 = nb >> 2;
+    if (t2 < t_lo || t2 >= t_hi) return;
+    tet = t2;
+    apex = nb & 3;
+    A = Y;
+    B = Z;
+    C = D;
+    pAB = pYZ;
+    pBC = -qZ;
+    pCA = qY;
+    tin = tout;
+    sin_ = sout;
+  }
+}
+
+// Per-lane list of entries (depth, face code) in LDS, kept sorted by
+// (depth, code); lane-minor layout so the 64 lanes hit distinct banks.
+struct EntryList {
+  float* t;  // [E_MAX][WAVE]
+  int* c;
+  int lane;
+  __device__ float& T(int e) { return t[e * WAVE + lane]; }
+  __device__ int& Cd(int e) { return c[e * WAVE + lane]; }
+};
+
+__device__ __forceinline__ bool key_less(float ta, int ca, float tb, int cb) {
+  return ta < tb || (ta == tb && ca < cb);
+}
+
+// Stage a chunk of boundary-face records of one bin into LDS.
+__device__ __forceinline__ void stage_faces(const MeshDev& M, const int* rec, int n, FaceL* faces, int lane) {
+  if (lane < n) {
+    int code = rec[lane];
+    int t = code >> 2, fc = code & 3;
+    int4 tv = M.tet[2 * t];
+    FaceL F;
+    F.code = code;
+    F.id0 = sel4(tv, kFaceOut[fc][0]);
+    F.id1 = sel4(tv, kFaceOut[fc][1]);
+    F.id2 = sel4(tv, kFaceOut[fc][2]);
+    F.p0 = M.vert[F.id0];
+    F.p1 = M.vert[F.id1];
+    F.p2 = M.vert[F.id2];
+    faces[lane] = F;
+  }
+}
+
+// All entries of this lane's ray into one subdomain, walked in (depth, code)
+// order.  Handles more than E_MAX entries by repeated rounds that pick the
+// next E_MAX entries after the last one walked.  Must be called by the whole
+// wavefront (it stages faces cooperatively).
+template <class Sink>
+__device__ void walk_subdomain(const MeshDev& M, const FrameDev& f, const Ray& r, bool valid, const int* rec,
+                               int n_rec, const SlotDev& sl, FaceL* faces, EntryList& L, Sink& sink,
+                               LaneCount& cnt) {
+  float last_t = -FLT_MAX;
+  int last_c = -1;
+  bool more = true;
+  while (true) {
+    bool want = valid && more;
+    if (!__any(want)) break;
+    int n = 0;
+    more = false;
+    for (int c0 = 0; c0 < n_rec; c0 += CHUNK) {
+      int nc = min(CHUNK, n_rec - c0);
+      __syncthreads();
+      stage_faces(M, rec + c0, nc, faces, threadIdx.x);
+      __syncthreads();
+      if (!want) continue;
+      for (int k = 0; k < nc; ++k) {
+        const FaceL& F = faces[k];
+        Entry e;
+        if (!enter_face(r, F.id0, F.id1, F.id2, F.p0, F.p1, F.p2, e)) continue;
+        if (!key_less(last_t, last_c, e.t, F.code)) continue;  // walked in an earlier round
+        if (n == E_MAX) {
+          more = true;
+          if (!key_less(e.t, F.code, L.T(n - 1), L.Cd(n - 1))) continue;
+          --n;  // evict the largest
+        }
+        int pos = n;
+        while (pos > 0 && key_less(e.t, F.code, L.T(pos - 1), L.Cd(pos - 1))) {
+          L.T(pos) = L.T(pos - 1);
+          L.Cd(pos) = L.Cd(pos - 1);
+          --pos;
+        }
+        L.T(pos) = e.t;
+        L.Cd(pos) = F.code;
+        ++n;
+      }
+    }
+    if (more) ++cnt.overflow;
+    for (int k = 0; k < n; ++k) {
+      int code = L.Cd(k);
+      int t = code >> 2, fc = code & 3;
+      int4 tv = M.tet[2 * t];
+      int i0 = sel4(tv, kFaceOut[fc][0]), i1 = sel4(tv, kFaceOut[fc][1]), i2 = sel4(tv, kFaceOut[fc][2]);
+      Entry e;
+      if (!enter_face(r, i0, i1, i2, M.vert[i0], M.vert[i1], M.vert[i2], e)) continue;  // cannot happen
+      ++cnt.entries;
+      walk(M, f, r, t, fc, e, sl.tet_begin, sl.tet_end, sink, cnt);
+    }
+    if (n > 0) {
+      last_t = L.T(n - 1);
+      last_c = L.Cd(n - 1);
+    }
+  }
+}
+
+__device__ __forceinline__ unsigned wave_sum(unsigned v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  return v;
+}
+
+__device__ __forceinline__ void flush_counts(const LaneCount& c, unsigned long long* ctr) {
+  unsigned v[7] = {c.pieces, c.steps, c.entries, c.steplimit, c.fallback, c.overflow, c.nonpd};
+  int idx[7] = {C_PIECES, C_STEPS, C_ENTRIES, C_STEPLIMIT, C_FALLBACK, C_OVERFLOW, C_NONPD};
+  for (int k = 0; k < 7; ++k) {
+    unsigned s = wave_sum(v[k]);
+    if (threadIdx.x == 0 && s) atomicAdd(ctr + idx[k], (unsigned long long)s);
+  }
+}
+
+// ------------------------------------------------------------------ stage one
+
+// Compensated (Kahan) accumulation: a ray crosses hundreds of pieces per
+// subdomain at the largest workloads, and plain FP32 sums would drift by
+// ~1e-5 of b0.
+__device__ __forceinline__ void kahan_add(float& sum, float& comp, float x) {
+#pragma clang fp contract(off)
+  float y = x - comp;
+  float tt = sum + y;
+  comp = (tt - sum) - y;
+  sum = tt;
+}
+
+template <int M1>
+struct MomentSink {
+  const FrameDev* f;
+  const float* tfa;  // LDS alpha column of the table
+  float b[M1];
+  float comp[M1];    // Kahan compensation terms
+  unsigned pieces;
+  __device__ void chord(float t0, float t1, float s0, float s1) {
+    cut_chord(*f, t0, t1, s0, s1, [&](float tm, float len, float s) {
+      int i0;
+      float fr, a, z;
+      tf_coord(*f, s, i0, fr);
+      float A = lerp_nc(tfa[i0], tfa[i0 + 1], fr);
+      piece_az(*f, tm, len, A, a, z);
+      float term = a;
+#pragma unroll
+      for (int j = 0; j < M1; ++j) {  // Alg. 2: moment j gains absorbance * depth^j
+        kahan_add(b[j], comp[j], term);
+        term *= z;
+      }
+      ++pieces;
+    });
+  }
+};
+
+template <int M1>
+__global__ __launch_bounds__(WAVE) void k_moments(MeshDev M, FrameDev f, const SlotDev* __restrict__ slots,
+                                                  const int* __restrict__ offsets, const int* __restrict__ counts,
+                                                  const int* __restrict__ records, const float* __restrict__ tf_rgba,
+                                                  float* __restrict__ out, unsigned long long* ctr) {
+  extern __shared__ float4 dyn_lds[];
+  float* tfa = reinterpret_cast<float*>(dyn_lds);  // [n_tf] alpha column
+  __shared__ FaceL faces[CHUNK];
+  __shared__ float ent_t[E_MAX * WAVE];
+  __shared__ int ent_c[E_MAX * WAVE];
+  const int lane = threadIdx.x;
+  for (int i = lane; i < f.n_tf; i += WAVE) tfa[i] = tf_rgba[4 * i + 3];
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int tx = tile % f.tiles_x, ty = tile / f.tiles_x;
+  const int px = tx * TILE + (lane & (TILE - 1)), py = ty * TILE + (lane / TILE);
+  const bool valid = px < f.W && py < f.H;
+  const Ray r = pixel_ray(f, valid ? py : 0, valid ? px : 0);
+  const size_t HW = size_t(f.W) * f.H, pix = size_t(py) * f.W + px;
+  EntryList L{ent_t, ent_c, lane};
+  LaneCount cnt = {};
+  __syncthreads();
+  for (int k = 0; k < f.n_slots; ++k) {
+    const int bin = tile * f.n_slots + k;
+    const int n_rec = counts[bin];
+    MomentSink<M1> sink;
+    sink.f = &f;
+    sink.tfa = tfa;
+    sink.pieces = 0;
+#pragma unroll
+    for (int j = 0; j < M1; ++j) sink.b[j] = sink.comp[j] = 0.0f;
+    if (n_rec > 0) {
+      const SlotDev sl = slots[k];
+      walk_subdomain(M, f, r, valid, records + offsets[bin], n_rec, sl, faces, L, sink, cnt);
+    }
+    cnt.pieces += sink.pieces;
+    if (valid) {
+      float* o = out + size_t(k) * M1 * HW + pix;
+#pragma unroll
+      for (int j = 0; j < M1; ++j) o[size_t(j) * HW] = sink.b[j];
+    }
+  }
+  flush_counts(cnt, ctr);
+}
+
+// ------------------------------------------------------------------ stage two
+
+template <int N, class R>
+struct ColorSink {
+  const FrameDev* f;
+  const float4* tf;  // LDS table
+  const apcm::Bound<N, R>* bound;
+  R eta;
+  bool active;
+  float acc[4];
+  unsigned pieces;
+  __device__ void chord(float t0, float t1, float s0, float s1) {
+    cut_chord(*f, t0, t1, s0, s1, [&](float tm, float len, float s) {
+      int i0;
+      float fr, a, z;
+      tf_coord(*f, s, i0, fr);
+      const float4 c0 = tf[i0], c1 = tf[i0 + 1];
+      float A = lerp_nc(c0.w, c1.w, fr);
+      piece_az(*f, tm, len, A, a, z);
+      ++pieces;
+      if (!active) return;
+      R F = bound->frac_before(R(z), eta);
+      float T = __expf(-float(bound->b0 * F));
+      T = fminf(fmaxf(T, 0.0f), 1.0f);
+      float w = T * (-expm1f(-a));
+      acc[0] += w * lerp_nc(c0.x, c1.x, fr);
+      acc[1] += w * lerp_nc(c0.y, c1.y, fr);
+      acc[2] += w * lerp_nc(c0.z, c1.z, fr);
+      acc[3] += w;
+    });
+  }
+};
+
+__device__ __forceinline__ float4 finalize_px(float4 acc, float b0, int finalize, int renormalize) {
+  if (!finalize) return acc;
+  if (!renormalize) return acc;
+  float A = -expm1f(-b0);
+  float sc = acc.w > 1e-30f ? A / acc.w : 0.0f;
+  return make_float4(acc.x * sc, acc.y * sc, acc.z * sc, A);
+}
+
+template <int N, class R>
+__global__ __launch_bounds__(WAVE) void k_resolve(MeshDev M, FrameDev f, const SlotDev* __restrict__ slots,
+                                                  const int* __restrict__ offsets, const int* __restrict__ counts,
+                                                  const int* __restrict__ records, const float* __restrict__ tf_rgba,
+                                                  const float* __restrict__ moments, BoundParams bp,
+                                                  float* __restrict__ rgba, unsigned long long* ctr) {
+  extern __shared__ float4 dyn_lds[];
+  float4* tf = dyn_lds;  // [n_tf] RGBA
+  __shared__ FaceL faces[CHUNK];
+  __shared__ float ent_t[E_MAX * WAVE];
+  __shared__ int ent_c[E_MAX * WAVE];
+  constexpr int M1 = 2 * N + 1;
+  const int lane = threadIdx.x;
+  for (int i = lane; i < f.n_tf; i += WAVE)
+    tf[i] = make_float4(tf_rgba[4 * i], tf_rgba[4 * i + 1], tf_rgba[4 * i + 2], tf_rgba[4 * i + 3]);
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int tx = tile % f.tiles_x, ty = tile / f.tiles_x;
+  const int px = tx * TILE + (lane & (TILE - 1)), py = ty * TILE + (lane / TILE);
+  const bool valid = px < f.W && py < f.H;
+  const Ray r = pixel_ray(f, valid ? py : 0, valid ? px : 0);
+  const size_t HW = size_t(f.W) * f.H, pix = size_t(py) * f.W + px;
+  LaneCount cnt = {};
+  // per-pixel part of Alg. 3, once per pixel instead of once per sample
+  apcm::Bound<N, R> bound;
+  float b0f = 0.0f;
+  {
+    R b[M1], bias[2 * N];
+#pragma unroll
+    for (int j = 0; j < M1; ++j) b[j] = valid ? R(moments[size_t(j) * HW + pix]) : R(0);
+#pragma unroll
+    for (int j = 0; j < 2 * N; ++j) bias[j] = R(bp.bias[j]);
+    b0f = valid ? moments[pix] : 0.0f;
+    cnt.nonpd += bound.setup(b, R(bp.alpha), bias);
+  }
+  EntryList L{ent_t, ent_c, lane};
+  ColorSink<N, R> sink;
+  sink.f = &f;
+  sink.tf = tf;
+  sink.bound = &bound;
+  sink.eta = R(bp.eta);
+  sink.active = valid && bound.mode != 0;
+  sink.acc[0] = sink.acc[1] = sink.acc[2] = sink.acc[3] = 0.0f;
+  sink.pieces = 0;
+  __syncthreads();
+  for (int k = 0; k < f.n_slots; ++k) {
+    const int bin = tile * f.n_slots + k;
+    const int n_rec = counts[bin];
+    if (n_rec == 0) continue;
+    const SlotDev sl = slots[k];
+    walk_subdomain(M, f, r, valid, records + offsets[bin], n_rec, sl, faces, L, sink, cnt);
+  }
+  cnt.pieces += sink.pieces;
+  if (valid) {
+    float4 acc = make_float4(sink.acc[0], sink.acc[1], sink.acc[2], sink.acc[3]);
+    reinterpret_cast<float4*>(rgba)[pix] = finalize_px(acc, b0f, bp.finalize, bp.renormalize);
+  }
+  flush_counts(cnt, ctr);
+}
+
+// ------------------------------------------------------------------ binning
+
+__device__ __forceinline__ void project_px(const FrameDev& f, float4 p, float& col, float& row, bool& ok) {
+  const float* Minv = f.minv;
+  // solve [dir right down] (l, la, lb)^T = p - eye
+  float yx = p.x - f.ex, yy = p.y - f.ey, yz = p.z - f.ez;
+  float l = Minv[0] * yx + Minv[1] * yy + Minv[2] * yz;
+  float la = Minv[3] * yx + Minv[4] * yy + Minv[5] * yz;
+  float lb = Minv[6] * yx + Minv[7] * yy + Minv[8] * yz;
+  if (f.proj == 0) {
+    col = la - 0.5f;
+    row = lb - 0.5f;
+    ok = true;
+  } else {
+    ok = l > 1e-6f;
+    float il = 1.0f / l;
+    col = la * il + f.half_w - 0.5f;
+    row = lb * il + f.half_h - 0.5f;
+  }
+}
+
+__global__ void k_bin(MeshDev M, FrameDev f, const SlotDev* __restrict__ slots,
+                      const int* __restrict__ bface, int* __restrict__ counts, const int* __restrict__ offsets,
+                      int* __restrict__ cursors, int* __restrict__ records, int fill) {
+  const int k = blockIdx.y;
+  const SlotDev sl = slots[k];
+  const int i = sl.face_begin + blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= sl.face_end) return;
+  const int code = bface[i];
+  const int t = code >> 2, fc = code & 3;
+  const int4 tv = M.tet[2 * t];
+  const float4 a = M.vert[sel4(tv, kFaceOut[fc][0])];
+  const float4 b = M.vert[sel4(tv, kFaceOut[fc][1])];
+  const float4 c = M.vert[sel4(tv, kFaceOut[fc][2])];
+  // conservative back-face cull: drop faces every ray crosses outwards
+  {
+    float ux = b.x - a.x, uy = b.y - a.y, uz = b.z - a.z, vx = c.x - a.x, vy = c.y - a.y, vz = c.z - a.z;
+    float nx = uy * vz - uz * vy, ny = uz * vx - ux * vz, nz = ux * vy - uy * vx;
+    float nn = sqrtf(nx * nx + ny * ny + nz * nz);
+    float gx, gy, gz;
+    if (f.proj == 0) {
+      gx = f.dx;
+      gy = f.dy;
+      gz = f.dz;
+    } else {
+      gx = a.x - f.ex;
+      gy = a.y - f.ey;
+      gz = a.z - f.ez;
+    }
+    float gn = sqrtf(gx * gx + gy * gy + gz * gz);
+    if (gx * nx + gy * ny + gz * nz > 1e-4f * gn * nn) return;
+  }
+  float cmin = FLT_MAX, cmax = -FLT_MAX, rmin = FLT_MAX, rmax = -FLT_MAX;
+  bool all_ok = true;
+  const float4 pts[3] = {a, b, c};
+  for (int q = 0; q < 3; ++q) {
+    float col, row;
+    bool ok;
+    project_px(f, pts[q], col, row, ok);
+    all_ok = all_ok && ok;
+    cmin = fminf(cmin, col);
+    cmax = fmaxf(cmax, col);
+    rmin = fminf(rmin, row);
+    rmax = fmaxf(rmax, row);
+  }
+  int c0, c1, r0, r1;
+  if (!all_ok || !(cmax - cmin < 1e7f) || !(rmax - rmin < 1e7f)) {
+    c0 = 0;
+    r0 = 0;
+    c1 = f.W - 1;
+    r1 = f.H - 1;
+  } else {
+    if (cmax < -2.0f || rmax < -2.0f || cmin > float(f.W) + 1.0f || rmin > float(f.H) + 1.0f) return;
+    c0 = max(0, int(floorf(cmin)) - 1);
+    r0 = max(0, int(floorf(rmin)) - 1);
+    c1 = min(f.W - 1, int(ceilf(cmax)) + 1);
+    r1 = min(f.H - 1, int(ceilf(rmax)) + 1);
+    if (c0 > c1 || r0 > r1) return;
+  }
+  for (int ty = r0 / TILE; ty <= r1 / TILE; ++ty)
+    for (int tx = c0 / TILE; tx <= c1 / TILE; ++tx) {
+      const int bin = (ty * f.tiles_x + tx) * f.n_slots + k;
+      if (!fill) {
+        atomicAdd(counts + bin, 1);
+      } else {
+        const int pos = offsets[bin] + atomicAdd(cursors + bin, 1);
+        records[pos] = code;
+      }
+    }
+}
+
+// ------------------------------------------------------------------ sums
+
+__global__ void k_sum_moments(const float* __restrict__ in, int n_slots, const int* __restrict__ order,
+                              int64_t elems, float* __restrict__ out) {
+  int64_t i = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) * 4;
+  if (i >= elems) return;
+  if (i + 4 <= elems && (elems & 3) == 0) {
+    double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    for (int k = 0; k < n_slots; ++k) {
+      const float4 v = *reinterpret_cast<const float4*>(in + int64_t(order[k]) * elems + i);
+      s0 += v.x;
+      s1 += v.y;
+      s2 += v.z;
+      s3 += v.w;
+    }
+    *reinterpret_cast<float4*>(out + i) = make_float4(float(s0), float(s1), float(s2), float(s3));
+  } else {
+    for (int64_t e = i; e < elems && e < i + 4; ++e) {
+      double s = 0;
+      for (int k = 0; k < n_slots; ++k) s += in[int64_t(order[k]) * elems + e];
+      out[e] = float(s);
+    }
+  }
+}
+
+__global__ void k_sum_images(const float4* __restrict__ in, int n_slots, const int* __restrict__ order,
+                             int64_t pixels, const float* __restrict__ b0, BoundParams bp,
+                             float4* __restrict__ out) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= pixels) return;
+  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  for (int k = 0; k < n_slots; ++k) {
+    const float4 v = in[int64_t(order[k]) * pixels + i];
+    s0 += v.x;
+    s1 += v.y;
+    s2 += v.z;
+    s3 += v.w;
+  }
+  out[i] = finalize_px(make_float4(float(s0), float(s1), float(s2), float(s3)), b0[i], 1, bp.renormalize);
+}
+
+// ------------------------------------------------------------------ scan / fill
+
+constexpr int SCAN_THREADS = 256, SCAN_ITEMS = 8, SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_local(const int* __restrict__ in, int* __restrict__ out,
+                                                             int64_t n, int* __restrict__ sums) {
+  __shared__ int part[SCAN_THREADS];
+  const int64_t base = int64_t(blockIdx.x) * SCAN_TILE + int64_t(threadIdx.x) * SCAN_ITEMS;
+  int v[SCAN_ITEMS];
+  int tot = 0;
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    v[k] = base + k < n ? in[base + k] : 0;
+    tot += v[k];
+  }
+  part[threadIdx.x] = tot;
+  __syncthreads();
+  for (int o = 1; o < SCAN_THREADS; o <<= 1) {  // Hillis-Steele inclusive scan
+    int add = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
+    __syncthreads();
+    part[threadIdx.x] += add;
+    __syncthreads();
+  }
+  int run = part[threadIdx.x] - tot;
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    if (base + k < n) out[base + k] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == SCAN_THREADS - 1) sums[blockIdx.x] = part[threadIdx.x];
+}
+
+__global__ void k_scan_add(int* __restrict__ out, int64_t n, const int* __restrict__ sums) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) out[i] += sums[i / SCAN_TILE];
+}
+
+__global__ void k_fill(int* p, int v, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// ------------------------------------------------------------------ mesh residency
+
+__global__ void k_inc_count(const int4* __restrict__ tv, int64_t n_tets, int* __restrict__ counts) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n_tets) return;
+  const int4 v = tv[t];
+  atomicAdd(counts + v.x, 1);
+  atomicAdd(counts + v.y, 1);
+  atomicAdd(counts + v.z, 1);
+  atomicAdd(counts + v.w, 1);
+}
+
+__global__ void k_inc_fill(const int4* __restrict__ tv, int64_t n_tets, const int* __restrict__ offsets,
+                           int* __restrict__ cursors, int* __restrict__ inc) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n_tets) return;
+  const int4 v = tv[t];
+  inc[offsets[v.x] + atomicAdd(cursors + v.x, 1)] = int(t);
+  inc[offsets[v.y] + atomicAdd(cursors + v.y, 1)] = int(t);
+  inc[offsets[v.z] + atomicAdd(cursors + v.z, 1)] = int(t);
+  inc[offsets[v.w] + atomicAdd(cursors + v.w, 1)] = int(t);
+}
+
+// neighbour of every (tet, face): the other tet holding the face's 3 vertices
+__global__ void k_adjacency(const int4* __restrict__ tv, int64_t n_tets, const int* __restrict__ offsets,
+                            const int* __restrict__ inc, int* __restrict__ nbr, int* __restrict__ err) {
+  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= 4 * n_tets) return;
+  const int t = int(g >> 2), fc = int(g & 3);
+  const int4 v = tv[t];
+  int f3[3], q = 0;
+  for (int k = 0; k < 4; ++k)
+    if (k != fc) f3[q++] = sel4(v, k);
+  int a = min(f3[0], min(f3[1], f3[2]));
+  int found = -1, n_found = 0;
+  for (int p = offsets[a]; p < offsets[a + 1]; ++p) {
+    const int t2 = inc[p];
+    if (t2 == t) continue;
+    const int4 w = tv[t2];
+    int hit = 0, miss = -1;
+    for (int k = 0; k < 4; ++k) {
+      const int x = sel4(w, k);
+      if (x == f3[0] || x == f3[1] || x == f3[2])
+        ++hit;
+      else
+        miss = k;
+    }
+    if (hit == 3) {
+      found = (t2 << 2) | miss;
+      ++n_found;
+    }
+  }
+  if (n_found > 1) atomicOr(err, 1);
+  nbr[g] = n_found == 1 ? found : -1;
+}
+
+inline unsigned grid1(int64_t n, int b) { return unsigned((n + b - 1) / b); }
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+
+hipError_t launch_bin_count(const MeshDev& m, const FrameDev& f, const SlotDev* slots, int max_faces,
+                            const int* bface, int* counts, hipStream_t s) {
+  if (max_faces <= 0 || f.n_slots <= 0) return hipSuccess;
+  dim3 grid(grid1(max_faces, 256), f.n_slots);
+  hipLaunchKernelGGL(k_bin, grid, dim3(256), 0, s, m, f, slots, bface, counts, (const int*)nullptr, (int*)nullptr,
+                     (int*)nullptr, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_fill(const MeshDev& m, const FrameDev& f, const SlotDev* slots, int max_faces,
+                           const int* bface, const int* offsets, int* cursors, int* records, hipStream_t s) {
+  if (max_faces <= 0 || f.n_slots <= 0) return hipSuccess;
+  dim3 grid(grid1(max_faces, 256), f.n_slots);
+  hipLaunchKernelGGL(k_bin, grid, dim3(256), 0, s, m, f, slots, bface, (int*)nullptr, offsets, cursors, records,
+                     1);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments(int mm, const MeshDev& m, const FrameDev& f, const SlotDev* slots, const int* offsets,
+                          const int* counts, const int* records, const float* tf_rgba, float* out,
+                          unsigned long long* counters, hipStream_t s) {
+  const size_t lds = size_t(f.n_tf) * sizeof(float);
+  const dim3 grid(f.n_tiles), block(WAVE);
+  if (mm == 4)
+    hipLaunchKernelGGL(k_moments<5>, grid, block, lds, s, m, f, slots, offsets, counts, records, tf_rgba, out,
+                       counters);
+  else if (mm == 6)
+    hipLaunchKernelGGL(k_moments<7>, grid, block, lds, s, m, f, slots, offsets, counts, records, tf_rgba, out,
+                       counters);
+  else
+    hipLaunchKernelGGL(k_moments<9>, grid, block, lds, s, m, f, slots, offsets, counts, records, tf_rgba, out,
+                       counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_resolve(int mm, const MeshDev& m, const FrameDev& f, const SlotDev* slots, const int* offsets,
+                          const int* counts, const int* records, const float* tf_rgba, const float* moments,
+                          const BoundParams& bp, float* rgba, unsigned long long* counters, hipStream_t s) {
+  const size_t lds = size_t(f.n_tf) * sizeof(float4);
+  const dim3 grid(f.n_tiles), block(WAVE);
+  if (mm == 4)
+    hipLaunchKernelGGL((k_resolve<2, float>), grid, block, lds, s, m, f, slots, offsets, counts, records, tf_rgba,
+                       moments, bp, rgba, counters);
+  else if (mm == 6)
+    hipLaunchKernelGGL((k_resolve<3, double>), grid, block, lds, s, m, f, slots, offsets, counts, records,
+                       tf_rgba, moments, bp, rgba, counters);
+  else
+    hipLaunchKernelGGL((k_resolve<4, double>), grid, block, lds, s, m, f, slots, offsets, counts, records,
+                       tf_rgba, moments, bp, rgba, counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_moments(const float* in, int n_slots, const int* order, int64_t elems, float* out,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_moments, dim3(grid1((elems + 3) / 4, 256)), dim3(256), 0, s, in, n_slots, order, elems,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_images(const float* in, int n_slots, const int* order, int64_t pixels, const float* b0,
+                             const BoundParams& bp, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_images, dim3(grid1(pixels, 256)), dim3(256), 0, s, reinterpret_cast<const float4*>(in),
+                     n_slots, order, pixels, b0, bp, reinterpret_cast<float4*>(out));
+  return hipGetLastError();
+}
+
+int64_t scan_tmp_elems(int64_t n) {
+  int64_t total = 0;
+  while (n > 1) {
+    n = (n + SCAN_TILE - 1) / SCAN_TILE;
+    total += 2 * n + 1;
+  }
+  return total + 1;
+}
+
+hipError_t launch_exclusive_scan(const int* in, int* out, int64_t n, int* tmp, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+  int* sums = tmp;
+  int* sums_scan = tmp + nb;
+  hipLaunchKernelGGL(k_scan_local, dim3(unsigned(nb)), dim3(SCAN_THREADS), 0, s, in, out, n, sums);
+  if (nb > 1) {
+    hipError_t e = launch_exclusive_scan(sums, sums_scan, nb, tmp + 2 * nb + 1, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scan_add, dim3(grid1(n, 256)), dim3(256), 0, s, out, n, (const int*)sums_scan);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int* p, int value, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3(grid1(n, 256)), dim3(256), 0, s, p, value, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_incidence_count(const int4* tv, int64_t n_tets, int* counts, hipStream_t s) {
+  hipLaunchKernelGGL(k_inc_count, dim3(grid1(n_tets, 256)), dim3(256), 0, s, tv, n_tets, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_incidence_fill(const int4* tv, int64_t n_tets, const int* offsets, int* cursors, int* inc,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(k_inc_fill, dim3(grid1(n_tets, 256)), dim3(256), 0, s, tv, n_tets, offsets, cursors, inc);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjacency(const int4* tv, int64_t n_tets, const int* offsets, const int* inc, int* nbr,
+                            int* err, hipStream_t s) {
+  hipLaunchKernelGGL(k_adjacency, dim3(grid1(4 * n_tets, 256)), dim3(256), 0, s, tv, n_tets, offsets, inc, nbr,
+                     err);
+  return hipGetLastError();
+}
+
+}  // namespace apc

@@ -1,0 +1,313 @@
+// Moment-bound reconstruction of transmittance (paper Alg. 3), for the GPU.
+//
+// Per pixel (hoisted out of the per-sample loop of Alg. 3, same result):
+//   beta'_j = (1 - alpha) * b_j / b0 + alpha * bias_j,  beta'_0 = 1
+//   B = Hankel(beta'_0..beta'_2n) of size (n+1)^2,  B = L L^T,  Li = L^-1
+// Per sample at warped depth z:
+//   P = Li * (1, z, ..., z^n)       values of the orthonormal polynomials at z
+//   q = Li^T * P                    coefficients of the kernel polynomial
+//                                   K(x, z) = (1, x, ..., x^n) B^-1 (1, z, ..., z^n)^T
+//   x_1..x_n = roots of K(., z)     (real and simple when B is positive definite)
+//   the nodes {z, x_1..x_n} carry the weights 1 / K(x_i, x_i) (Christoffel
+//   numbers: the nodes are pairwise K-orthogonal, so a degree-2n quadrature on
+//   them reproduces all moments exactly)
+//   F = eta / K(z, z) + sum_{x_i < z} 1 / K(x_i, x_i)
+// F is the fraction of the pixel's absorbance in front of z; the caller forms
+// T = clamp(exp(-b0 * F), 0, 1).  This is the same quantity as evaluating the
+// 0/1/eta interpolant through the nodes against the biased moments (Alg. 3,
+// the polynomial solve and dot product), reached through the Christoffel
+// numbers instead of a Lagrange or Newton interpolant.
+//
+// Roots: closed forms (quadratic; trigonometric cubic; Ferrari quartic whose
+// resolvent's largest root comes from the trigonometric cubic), each root
+// polished by one Newton step on the kernel polynomial.  A vanishing leading
+// coefficient means one node has gone to infinity with zero weight; the
+// degree is lowered instead of dividing by it.
+//
+// Precision R is float or double; n = m/2 is 2, 3 or 4.
+//
+// The functions are host+device so that host-side tests can exercise exactly
+// the code the kernels run.
+#pragma once
+
+#include <math.h>
+
+#if defined(__HIPCC__)
+#define APC_HD __host__ __device__ inline
+#else
+#define APC_HD inline
+#endif
+
+namespace apcm {
+
+template <class R>
+struct Num;
+template <>
+struct Num<float> {
+  static constexpr float rank1_tol = 1e-6f;    // variance below which all absorbance sits at one depth
+  static constexpr float pivot_floor = 1e-9f;  // smallest admitted Cholesky pivot
+  static constexpr float deg_tol = 1e-6f;      // relative size of a negligible leading coefficient
+  static constexpr float far = 1e8f;           // nodes beyond this carry no weight
+  static constexpr float same_depth = 1e-5f;   // single-depth branch: "at the sample's depth"
+};
+template <>
+struct Num<double> {
+  static constexpr double rank1_tol = 1e-12;
+  static constexpr double pivot_floor = 1e-12;
+  static constexpr double deg_tol = 1e-13;
+  static constexpr double far = 1e30;
+  static constexpr double same_depth = 1e-5;
+};
+
+APC_HD float m_sqrt(float x) { return sqrtf(x); }
+APC_HD double m_sqrt(double x) { return sqrt(x); }
+APC_HD float m_acos(float x) { return acosf(x); }
+APC_HD double m_acos(double x) { return acos(x); }
+APC_HD float m_cos(float x) { return cosf(x); }
+APC_HD double m_cos(double x) { return cos(x); }
+APC_HD float m_cbrt(float x) { return cbrtf(x); }
+APC_HD double m_cbrt(double x) { return cbrt(x); }
+APC_HD float m_abs(float x) { return fabsf(x); }
+APC_HD double m_abs(double x) { return fabs(x); }
+
+template <class R>
+APC_HD R m_max(R a, R b) {
+  return a > b ? a : b;
+}
+template <class R>
+APC_HD R m_clamp(R x, R lo, R hi) {
+  return x < lo ? lo : (x > hi ? hi : x);
+}
+template <class R>
+APC_HD bool m_finite(R x) {
+  return x - x == R(0);
+}
+
+// Real roots of c0 + c1 x + c2 x^2 (numerically stable form).  Returns count.
+template <class R>
+APC_HD int roots2(R c0, R c1, R c2, R* x) {
+  if (c2 == R(0)) {
+    if (c1 == R(0)) return 0;
+    x[0] = -c0 / c1;
+    return 1;
+  }
+  R disc = m_max(c1 * c1 - R(4) * c2 * c0, R(0));
+  R s = m_sqrt(disc);
+  R t = R(-0.5) * (c1 + (c1 < R(0) ? -s : s));
+  if (t == R(0)) {  // c1 = 0 and c0 = 0: double root at 0
+    x[0] = x[1] = R(0);
+    return 2;
+  }
+  x[0] = t / c2;
+  x[1] = c0 / t;
+  return 2;
+}
+
+// Roots of the depressed cubic y^3 + p y + q, real parts when two are complex.
+template <class R>
+APC_HD void depressed3(R p, R q, R* y) {
+  const R two_pi_3 = R(2.0943951023931954923);
+  if (p < R(0)) {
+    R mm = m_sqrt(-p / R(3));
+    R arg = m_clamp(-q / (R(2) * mm * mm * mm), R(-1), R(1));
+    R th = m_acos(arg) / R(3);
+    y[0] = R(2) * mm * m_cos(th);  // largest
+    y[1] = R(2) * mm * m_cos(th - two_pi_3);
+    y[2] = R(2) * mm * m_cos(th + two_pi_3);
+  } else {
+    R sd = m_sqrt(m_max(q * q / R(4) + p * p * p / R(27), R(0)));
+    R u = m_cbrt(-q / R(2) + sd), w = m_cbrt(-q / R(2) - sd);
+    y[0] = u + w;
+    y[1] = y[2] = R(-0.5) * (u + w);
+  }
+}
+
+// Roots of c0 + c1 x + c2 x^2 + c3 x^3 (c3 != 0); x[0] is the largest when all are real.
+template <class R>
+APC_HD int roots3(const R* c, R* x) {
+  R inv = R(1) / c[3];
+  R a = c[2] * inv, b = c[1] * inv, cc = c[0] * inv;
+  R a3 = a / R(3);
+  R p = b - a * a3;
+  R q = cc + a3 * (R(2) * a3 * a3 - b);
+  R y[3];
+  depressed3(p, q, y);
+  for (int i = 0; i < 3; ++i) x[i] = y[i] - a3;
+  return 3;
+}
+
+// Roots of c0 + ... + c4 x^4 (c4 != 0) by Ferrari's resolvent.
+template <class R>
+APC_HD int roots4(const R* c, R* x) {
+  R inv = R(1) / c[4];
+  R a = c[3] * inv, b = c[2] * inv, cc = c[1] * inv, d = c[0] * inv;
+  R a4 = a / R(4), a4s = a4 * a4;
+  R p = b - R(6) * a4s;
+  R q = cc - R(2) * b * a4 + R(8) * a4s * a4;
+  R r = d - cc * a4 + b * a4s - R(3) * a4s * a4s;
+  // resolvent m^3 + p m^2 + (p^2/4 - r) m - q^2/8 = 0: its largest root is >= 0
+  R rc[4] = {-q * q / R(8), p * p / R(4) - r, p, R(1)};
+  R mr[3];
+  roots3(rc, mr);
+  R m0 = mr[0];
+  for (int it = 0; it < 2; ++it) {  // Newton polish of the resolvent root
+    R f = ((m0 + rc[2]) * m0 + rc[1]) * m0 + rc[0];
+    R df = (R(3) * m0 + R(2) * rc[2]) * m0 + rc[1];
+    if (df != R(0)) {
+      R mn = m0 - f / df;
+      if (m_finite(mn)) m0 = mn;
+    }
+  }
+  R y[4];
+  if (!(m0 > R(0))) {  // biquadratic y^4 + p y^2 + r
+    R w[2];
+    roots2(r, p, R(1), w);
+    R s0 = m_sqrt(m_max(w[0], R(0))), s1 = m_sqrt(m_max(w[1], R(0)));
+    y[0] = s0;
+    y[1] = -s0;
+    y[2] = s1;
+    y[3] = -s1;
+  } else {
+    R s = m_sqrt(R(2) * m0);
+    R h = q / (R(2) * s);
+    R base = p / R(2) + m0;
+    roots2(base + h, -s, R(1), y);
+    roots2(base - h, s, R(1), y + 2);
+  }
+  for (int i = 0; i < 4; ++i) x[i] = y[i] - a4;
+  return 4;
+}
+
+// Roots of the kernel polynomial q[0..N]; returns how many finite ones.
+template <int N, class R>
+APC_HD int kernel_roots(const R* q, R* x) {
+  R cmax = R(0);
+  for (int j = 0; j <= N; ++j) cmax = m_max(cmax, m_abs(q[j]));
+  int deg = N;
+  while (deg > 0 && m_abs(q[deg]) <= Num<R>::deg_tol * cmax) --deg;
+  int nr = 0;
+  if (deg == 1) {
+    x[0] = -q[0] / q[1];
+    nr = 1;
+  } else if (deg == 2) {
+    nr = roots2(q[0], q[1], q[2], x);
+  } else if (deg == 3) {
+    nr = roots3(q, x);
+  } else if (deg == 4) {
+    nr = roots4(q, x);
+  }
+  for (int i = 0; i < nr; ++i) {  // one Newton step on the full polynomial
+    R xi = x[i];
+    R p = q[N], dp = R(0);
+    for (int j = N - 1; j >= 0; --j) {
+      dp = dp * xi + p;
+      p = p * xi + q[j];
+    }
+    if (dp != R(0)) {
+      R xn = xi - p / dp;
+      if (m_finite(xn)) x[i] = xn;
+    }
+  }
+  return nr;
+}
+
+// Per-pixel state of the bound.
+template <int N, class R>
+struct Bound {
+  static constexpr int NL = (N + 1) * (N + 2) / 2;
+  R b0;
+  R z1;
+  R Li[NL];  // L^-1, packed lower triangle: row k starts at k(k+1)/2
+  int mode;  // 0: no absorbance, 1: all absorbance at depth z1, 2: regular
+
+  // b[0..2N] raw moments; bias[0..2N-1] = b*_1..b*_2N.  Returns the number of
+  // Cholesky pivots that had to be floored.
+  APC_HD int setup(const R* b, R alpha, const R* bias) {
+    mode = 0;
+    b0 = b[0];
+    z1 = R(0);
+    if (!(b0 > R(0))) return 0;
+    R bp[2 * N + 1];
+    bp[0] = R(1);
+    R inv0 = R(1) / b0;
+    for (int j = 1; j <= 2 * N; ++j) bp[j] = (R(1) - alpha) * (b[j] * inv0) + alpha * bias[j - 1];
+    if (bp[2] - bp[1] * bp[1] <= Num<R>::rank1_tol) {
+      mode = 1;
+      z1 = bp[1];
+      return 0;
+    }
+    mode = 2;
+    R L[N + 1][N + 1];
+    int floored = 0;
+    for (int j = 0; j <= N; ++j) {
+      for (int k = 0; k < j; ++k) {
+        R s = bp[j + k];
+        for (int l = 0; l < k; ++l) s -= L[j][l] * L[k][l];
+        L[j][k] = s / L[k][k];
+      }
+      R dd = bp[2 * j];
+      for (int l = 0; l < j; ++l) dd -= L[j][l] * L[j][l];
+      if (!(dd > Num<R>::pivot_floor)) {
+        dd = Num<R>::pivot_floor;
+        ++floored;
+      }
+      L[j][j] = m_sqrt(dd);
+    }
+    for (int j = 0; j <= N; ++j) {
+      R dj = R(1) / L[j][j];
+      Li[j * (j + 1) / 2 + j] = dj;
+      for (int k = 0; k < j; ++k) {
+        R s = R(0);
+        for (int l = k; l < j; ++l) s += L[j][l] * Li[l * (l + 1) / 2 + k];
+        Li[j * (j + 1) / 2 + k] = -s * dj;
+      }
+    }
+    return floored;
+  }
+
+  // K(x, x) = |Li (1, x, ..., x^N)|^2
+  APC_HD R kernel_diag(R x) const {
+    R P[N + 1];
+    for (int k = 0; k <= N; ++k) P[k] = R(0);
+    R v = R(1);
+    for (int j = 0; j <= N; ++j) {
+      for (int k = j; k <= N; ++k) P[k] += Li[k * (k + 1) / 2 + j] * v;
+      v *= x;
+    }
+    R K = R(0);
+    for (int k = 0; k <= N; ++k) K += P[k] * P[k];
+    return K;
+  }
+
+  // Fraction of the absorbance in front of warped depth z.
+  APC_HD R frac_before(R z, R eta) const {
+    if (mode == 1) {
+      if (m_abs(z1 - z) <= Num<R>::same_depth) return eta;
+      return z1 < z ? R(1) : R(0);
+    }
+    R P[N + 1];
+    for (int k = 0; k <= N; ++k) P[k] = R(0);
+    R v = R(1);
+    for (int j = 0; j <= N; ++j) {
+      for (int k = j; k <= N; ++k) P[k] += Li[k * (k + 1) / 2 + j] * v;
+      v *= z;
+    }
+    R K0 = R(0);
+    for (int k = 0; k <= N; ++k) K0 += P[k] * P[k];
+    R q[N + 1];
+    for (int j = 0; j <= N; ++j) {
+      R s = R(0);
+      for (int k = j; k <= N; ++k) s += Li[k * (k + 1) / 2 + j] * P[k];
+      q[j] = s;
+    }
+    R x[N];
+    int nr = kernel_roots<N, R>(q, x);
+    R F = eta / K0;
+    for (int i = 0; i < nr; ++i) {
+      if (x[i] < z && m_abs(x[i]) < Num<R>::far) F += R(1) / kernel_diag(x[i]);
+    }
+    return F;
+  }
+};
+
+}  // namespace apcm

@@ -1,0 +1,45 @@
+// Host build of the library's moment-bound header, for CPU tests that compare
+// it with the FP64 oracle.  Test infrastructure only.
+#include "../paper_2501_12581_amd/csrc/apc_mboit.h"
+
+template <int N, class R>
+static double run(const double* b, double alpha, const double* bias, double eta, double zf, int* floored) {
+  R bb[2 * N + 1], bs[2 * N];
+  for (int j = 0; j <= 2 * N; ++j) bb[j] = R(b[j]);
+  for (int j = 0; j < 2 * N; ++j) bs[j] = R(bias[j]);
+  apcm::Bound<N, R> B;
+  *floored = B.setup(bb, R(alpha), bs);
+  if (B.mode == 0) return 0.0;
+  return double(B.frac_before(R(zf), R(eta)));
+}
+
+extern "C" double shim_bound(const double* b, int m, double alpha, const double* bias, double eta, double zf,
+                             int fp64, int* floored) {
+  if (fp64) {
+    if (m == 4) return run<2, double>(b, alpha, bias, eta, zf, floored);
+    if (m == 6) return run<3, double>(b, alpha, bias, eta, zf, floored);
+    return run<4, double>(b, alpha, bias, eta, zf, floored);
+  }
+  if (m == 4) return run<2, float>(b, alpha, bias, eta, zf, floored);
+  if (m == 6) return run<3, float>(b, alpha, bias, eta, zf, floored);
+  return run<4, float>(b, alpha, bias, eta, zf, floored);
+}
+
+extern "C" int shim_roots(const double* q, int n, int fp64, double* out) {
+  int k = 0;
+  if (fp64) {
+    double x[4];
+    if (n == 2) k = apcm::kernel_roots<2, double>(q, x);
+    if (n == 3) k = apcm::kernel_roots<3, double>(q, x);
+    if (n == 4) k = apcm::kernel_roots<4, double>(q, x);
+    for (int i = 0; i < k; ++i) out[i] = x[i];
+  } else {
+    float qq[5], x[4];
+    for (int j = 0; j <= n; ++j) qq[j] = float(q[j]);
+    if (n == 2) k = apcm::kernel_roots<2, float>(qq, x);
+    if (n == 3) k = apcm::kernel_roots<3, float>(qq, x);
+    if (n == 4) k = apcm::kernel_roots<4, float>(qq, x);
+    for (int i = 0; i < k; ++i) out[i] = x[i];
+  }
+  return k;
+}
