@@ -49,6 +49,8 @@ def main():
     ap.add_argument("--grid", type=int, default=None, help="override cubes per axis (large workload)")
     ap.add_argument("--cpu-pixels", type=int, default=4096, help="oracle sample size (0 = skip)")
     ap.add_argument("--profile-steps", action="store_true", help="no oracle leg (for profiler runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (scales the HBM byte counters of a profiler run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the multi-GPU path (subdomains sharded over GPUs with an "
@@ -56,6 +58,17 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.copy_calibration:
+        n = 256 << 20
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "copies": 3}), flush=True)
+        return
 
     import paper_2501_12581_amd as apc
     import synth
