@@ -33,6 +33,7 @@ FP64_PEAK_TFLOPS = 78.6
 FP64_FLOPS_PER_PIECE_M8 = 250.0   # per-sample moment bound at m = 8
 TET_BYTES = 32.0                  # vertex ids + neighbour codes of one tet
 VERT_BYTES = 16.0                 # x, y, z, scalar
+STAGE_BYTES = 12.0                # one staged piece of stage two: z, a, s
 
 
 def log(msg):
@@ -47,7 +48,7 @@ def main():
     ap.add_argument("--workload", default="large", choices=["large", "medium", "tiny"])
     ap.add_argument("--size", type=int, default=None, help="override the image size (square)")
     ap.add_argument("--grid", type=int, default=None, help="override cubes per axis (large workload)")
-    ap.add_argument("--cpu-pixels", type=int, default=4096, help="oracle sample size (0 = skip)")
+    ap.add_argument("--cpu-pixels", type=int, default=16384, help="oracle sample size (0 = skip)")
     ap.add_argument("--profile-steps", action="store_true", help="no oracle leg (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (scales the HBM byte counters of a profiler run)")
@@ -103,7 +104,7 @@ def main():
     torch.cuda.synchronize()
     log("warmup done")
     ctx.counters(reset=True)
-    kern = {"bin_ms": 0.0, "moments_ms": 0.0, "sum_ms": 0.0, "resolve_ms": 0.0}
+    kern = {"bin_ms": 0.0, "moments_ms": 0.0, "sum_ms": 0.0, "resolve_ms": 0.0, "stage_ms": 0.0, "eval_ms": 0.0}
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
     t_start = time.perf_counter()
@@ -117,8 +118,8 @@ def main():
         frame_ms.append((time.perf_counter() - f0) * 1e3)
         for key in kern:
             kern[key] += tk[key]
-        log("step %d: %.1f ms (moments %.1f, resolve %.1f)" % (k, frame_ms[-1], tk["moments_ms"],
-                                                              tk["resolve_ms"]))
+        log("step %d: %.1f ms (moments %.1f, resolve %.1f = re-walk %.1f + evaluation %.1f)" % (
+            k, frame_ms[-1], tk["moments_ms"], tk["resolve_ms"], tk["stage_ms"], tk["eval_ms"]))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     ms_per_step = elapsed * 1e3 / args.steps
@@ -138,13 +139,17 @@ def main():
         "k_moments": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
                       "achieved": (mesh_bytes + mom_bytes) / (kern["moments_ms"] / 1e3) / 1e9,
                       "per_launch": "mesh %.3g B + dense per-subdomain moments %.3g B" % (mesh_bytes, mom_bytes)},
-        "k_resolve": {"bound": "alu", "unit": "TFLOP/s", "peak": FP64_PEAK_TFLOPS,
-                      "achieved": FP64_FLOPS_PER_PIECE_M8 * pieces_per_frame / (kern["resolve_ms"] / 1e3) / 1e12,
-                      "per_launch": "%d FP64 flops x %.4g pieces" % (FP64_FLOPS_PER_PIECE_M8, pieces_per_frame)},
+        "k_stage": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+                    "achieved": (mesh_bytes + pieces_per_frame * STAGE_BYTES) / (kern["stage_ms"] / 1e3) / 1e9,
+                    "per_launch": "mesh %.3g B + staged pieces %.3g B" % (mesh_bytes, pieces_per_frame * STAGE_BYTES)},
+        "k_eval": {"bound": "alu", "unit": "TFLOP/s", "peak": FP64_PEAK_TFLOPS,
+                   "achieved": FP64_FLOPS_PER_PIECE_M8 * pieces_per_frame / (kern["eval_ms"] / 1e3) / 1e12,
+                   "per_launch": "%d FP64 flops x %.4g pieces" % (FP64_FLOPS_PER_PIECE_M8, pieces_per_frame)},
     }
-    dom = "k_resolve" if kern["resolve_ms"] >= kern["moments_ms"] else "k_moments"
+    timed = {"k_moments": kern["moments_ms"], "k_stage": kern["stage_ms"], "k_eval": kern["eval_ms"]}
+    dom = max(timed, key=timed.get)
     rf = rooflines[dom]
-    roofline = {"kernel": dom, "bound": rf["bound"], "achieved": round(rf["achieved"], 4), "peak": rf["peak"],
+    roofline = {"kernel": dom, "kernel_ms": round(timed[dom], 3), "bound": rf["bound"], "achieved": round(rf["achieved"], 4), "peak": rf["peak"],
                 "unit": rf["unit"], "frac": round(rf["achieved"] / rf["peak"], 5), "traffic": None,
                 "work_per_launch": rf["per_launch"],
                 "other": {k: {"bound": v["bound"], "achieved": round(v["achieved"], 4), "unit": v["unit"],
@@ -157,7 +162,7 @@ def main():
     if args.cpu_pixels > 0 and not args.profile_steps:
         import oracle
         pix = np.sort(np.random.default_rng(11).choice(H * W, min(args.cpu_pixels, H * W), replace=False))
-        threads = os.cpu_count() or 1
+        threads = min(16, os.cpu_count() or 1)  # the host share of one GPU
         log("oracle on %d sampled pixels with %d threads" % (len(pix), threads))
         t0 = time.perf_counter()
         ref = oracle.render(sc, pixels=pix, threads=threads)

@@ -188,7 +188,9 @@ apc_status apc_sum_moments(apc_ctx ctx, const float* moments_per_sub, int32_t n_
 #define APC_FINALIZE 1u
 
 /* Stage two for a list of subdomains (Section 4.2, Alg. 1 second loop and
- * Alg. 3).  The same pieces as stage one are generated again; each piece of
+ * Alg. 3).  The same pieces as stage one are generated again (a second walk),
+ * staged in context-owned device memory (12 bytes per piece; the frame is
+ * processed in chunks of tiles when the pieces do not fit), and each piece of
  * opacity alpha_p = 1 - exp(-a) and colour c (transfer-function RGB) adds
  * T * alpha_p * (c, 1), where T = clamp(exp(-b0 * F)) and F is the moment
  * bound at the piece's warped depth computed from `moments_global`.
@@ -224,7 +226,8 @@ typedef struct apc_counters {
   int64_t bin_records;      /* (face, tile) records binned */
   int64_t walk_step_limit;  /* walks cut off by the step limit (should be 0) */
   int64_t exit_fallback;    /* exit faces chosen by the tie fallback (should be ~0) */
-  int64_t entry_overflow;   /* per-ray entry lists flushed early (results stay correct) */
+  int64_t entry_overflow;   /* per-ray entry lists refilled in extra rounds (results stay correct), plus
+                               stage-two re-walks whose piece count differed from the count (never expected) */
   int64_t nonpd_pivots;     /* Cholesky pivots floored in the resolve pass */
 } apc_counters;
 
@@ -240,7 +243,9 @@ typedef struct apc_timings {
   double bin_ms;       /* binning of the most recent pass (count + scan + fill) */
   double moments_ms;   /* stage-one walk kernel of the last apc_moments_pass */
   double sum_ms;       /* last apc_sum_moments */
-  double resolve_ms;   /* stage-two walk kernel of the last apc_resolve_pass */
+  double resolve_ms;   /* everything after binning in the last apc_resolve_pass */
+  double stage_ms;     /* its re-walk kernel (first chunk of tiles) */
+  double eval_ms;      /* its moment-bound evaluation kernel (first chunk of tiles) */
 } apc_timings;
 apc_status apc_get_timings(apc_ctx ctx, apc_timings* out);
 

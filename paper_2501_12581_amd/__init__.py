@@ -62,7 +62,7 @@ class Mboit(C.Structure):
 
 class Timings(C.Structure):
     _fields_ = [("bin_ms", C.c_double), ("moments_ms", C.c_double), ("sum_ms", C.c_double),
-                ("resolve_ms", C.c_double)]
+                ("resolve_ms", C.c_double), ("stage_ms", C.c_double), ("eval_ms", C.c_double)]
 
 
 class Counters(C.Structure):

@@ -88,13 +88,20 @@ struct apc_ctx_s {
   size_t staging_bytes = 0;
   hipEvent_t staging_done = nullptr;
   int64_t bin_records = 0;  // (face, tile) records binned, counted on the host
-  // event pairs around the launches: 0 binning, 1 moments, 2 sum, 3 resolve
-  hipEvent_t ev[4][2] = {};
-  bool ev_used[4] = {};
+  // event pairs around the launches: binning, moments, sum, resolve, re-walk, evaluation
+  hipEvent_t ev[6][2] = {};
+  bool ev_used[6] = {};
+  // stage two: pieces per pixel (tile-major), 64-bit piece offsets, staged pieces
+  DevBuf pcount, tile_tot, tile_off, poff, stage;
+  // the pieces per pixel in `pcount` belong to this (mesh, view, subdomain list)
+  const void* pc_mesh = nullptr;
+  apc_view pc_view;
+  std::vector<int> pc_subs;
+  bool pc_valid = false;
 };
 
 namespace {
-enum { EV_BIN = 0, EV_MOM, EV_SUM, EV_RES };
+enum { EV_BIN = 0, EV_MOM, EV_SUM, EV_RES, EV_STG, EV_EVL, EV_COUNT };
 hipError_t ev_mark(apc_ctx ctx, int k, int which, hipStream_t s) {
   if (which == 1) ctx->ev_used[k] = true;
   return hipEventRecord(ctx->ev[k][which], s);
@@ -305,6 +312,20 @@ apc_status build_bins(apc_ctx ctx, const apc_mesh_s* m, const FrameDev& f, const
   return APC_OK;
 }
 
+void set_piece_key(apc_ctx ctx, const apc_mesh_s* m, const apc_view* v, const int32_t* subs, int32_t n_sub) {
+  ctx->pc_mesh = m;
+  ctx->pc_view = *v;
+  ctx->pc_subs.assign(subs, subs + n_sub);
+  ctx->pc_valid = true;
+}
+
+// Do the pieces per pixel in the context belong to this mesh, camera, lattice
+// and subdomain list?  (They do not depend on the transfer function or m.)
+bool piece_key_matches(apc_ctx ctx, const apc_mesh_s* m, const apc_view* v, const int32_t* subs, int32_t n_sub) {
+  return ctx->pc_valid && ctx->pc_mesh == m && std::memcmp(&ctx->pc_view, v, sizeof(apc_view)) == 0 &&
+         ctx->pc_subs.size() == size_t(n_sub) && std::equal(ctx->pc_subs.begin(), ctx->pc_subs.end(), subs);
+}
+
 int max_tets_of(const apc_mesh_s* m, const int32_t* subs, int32_t n_sub) {
   int mx = 0;
   for (int k = 0; k < n_sub; ++k) mx = std::max(mx, m->sub_begin[subs[k] + 1] - m->sub_begin[subs[k]]);
@@ -338,7 +359,7 @@ apc_status apc_create(int device, apc_ctx* out) {
   hipError_t e = c->counters.ensure(sizeof(unsigned long long) * apc::C_COUNT);
   if (e == hipSuccess) e = hipMemset(c->counters.p, 0, c->counters.bytes);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->staging_done, hipEventDisableTiming);
-  for (int k = 0; k < 4 && e == hipSuccess; ++k)
+  for (int k = 0; k < EV_COUNT && e == hipSuccess; ++k)
     for (int w = 0; w < 2 && e == hipSuccess; ++w) e = hipEventCreate(&c->ev[k][w]);
   if (e != hipSuccess) {
     delete c;
@@ -353,11 +374,12 @@ apc_status apc_destroy(apc_ctx ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   for (DevBuf* b : {&ctx->counts, &ctx->offsets, &ctx->cursors, &ctx->records, &ctx->scan_tmp, &ctx->slots,
-                    &ctx->order, &ctx->counters})
+                    &ctx->order, &ctx->counters, &ctx->pcount, &ctx->tile_tot, &ctx->tile_off, &ctx->poff,
+                    &ctx->stage})
     b->release();
   if (ctx->staging) (void)hipHostFree(ctx->staging);
   if (ctx->staging_done) (void)hipEventDestroy(ctx->staging_done);
-  for (int k = 0; k < 4; ++k)
+  for (int k = 0; k < EV_COUNT; ++k)
     for (int w = 0; w < 2; ++w)
       if (ctx->ev[k][w]) (void)hipEventDestroy(ctx->ev[k][w]);
   delete ctx;
@@ -597,10 +619,13 @@ apc_status apc_moments_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const
   hipStream_t s = static_cast<hipStream_t>(stream);
   MeshDev md;
   if ((st = build_bins(ctx, m, f, subs, n_sub, s, md)) != APC_OK) return st;
+  HIPCHK(ctx->pcount.ensure(sizeof(int) * size_t(f.n_tiles) * 64));
   HIPCHK(ev_mark(ctx, EV_MOM, 0, s));
   HIPCHK(apc::launch_moments(mm, md, f, ctx->slots.as<SlotDev>(), ctx->offsets.as<int>(), ctx->counts.as<int>(),
-                             ctx->records.as<int>(), tf->rgba, out, ctx->counters.as<unsigned long long>(), s));
+                             ctx->records.as<int>(), tf->rgba, out, ctx->pcount.as<int>(),
+                             ctx->counters.as<unsigned long long>(), s));
   HIPCHK(ev_mark(ctx, EV_MOM, 1, s));
+  set_piece_key(ctx, m, view, subs, n_sub);
   return APC_OK;
 }
 
@@ -660,10 +685,68 @@ apc_status apc_resolve_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const
   hipStream_t s = static_cast<hipStream_t>(stream);
   MeshDev md;
   if ((st = build_bins(ctx, m, f, subs, n_sub, s, md)) != APC_OK) return st;
+  const int nt = f.n_tiles;
+  unsigned long long* ctr = ctx->counters.as<unsigned long long>();
   HIPCHK(ev_mark(ctx, EV_RES, 0, s));
-  HIPCHK(apc::launch_resolve(mb->m, md, f, ctx->slots.as<SlotDev>(), ctx->offsets.as<int>(), ctx->counts.as<int>(),
-                             ctx->records.as<int>(), tf->rgba, moments, bp, rgba,
-                             ctx->counters.as<unsigned long long>(), s));
+  // pieces per pixel: from stage one when it ran on the same geometry, else counted by a walk
+  if (!piece_key_matches(ctx, m, view, subs, n_sub)) {
+    ctx->pc_valid = false;
+    HIPCHK(ctx->pcount.ensure(sizeof(int) * size_t(nt) * 64));
+    HIPCHK(apc::launch_stage(0, md, f, ctx->slots.as<SlotDev>(), ctx->offsets.as<int>(), ctx->counts.as<int>(),
+                             ctx->records.as<int>(), tf->rgba, 0, nt, ctx->pcount.as<int>(), nullptr, 0, nullptr,
+                             ctr, s));
+    set_piece_key(ctx, m, view, subs, n_sub);
+  }
+  HIPCHK(ctx->tile_tot.ensure(sizeof(long long) * nt));
+  HIPCHK(ctx->tile_off.ensure(sizeof(long long) * nt));
+  HIPCHK(ctx->poff.ensure(sizeof(long long) * (size_t(nt) * 64 + 1)));
+  HIPCHK(apc::launch_tile_sums(ctx->pcount.as<int>(), nt, ctx->tile_tot.as<long long>(), s));
+  std::vector<long long> tot(nt), toff(nt);
+  HIPCHK(hipMemcpyAsync(tot.data(), ctx->tile_tot.p, sizeof(long long) * nt, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  long long total = 0, biggest = 0;
+  for (int t = 0; t < nt; ++t) {
+    toff[t] = total;
+    total += tot[t];
+    biggest = std::max(biggest, tot[t]);
+  }
+  if ((st = stage_upload(ctx, ctx->tile_off.p, toff.data(), sizeof(long long) * nt, s)) != APC_OK) return st;
+  HIPCHK(apc::launch_piece_offsets(ctx->pcount.as<int>(), ctx->tile_off.as<long long>(), nt,
+                                   ctx->poff.as<long long>(), s));
+  // staging capacity: all pieces if they fit in 60% of the free device memory, else chunks of tiles
+  const size_t rec_bytes = 3 * sizeof(float);
+  size_t want = size_t(std::max<long long>(total, 1)) * rec_bytes;
+  if (want > ctx->stage.bytes) {
+    size_t free_b = 0, total_b = 0;
+    HIPCHK(hipMemGetInfo(&free_b, &total_b));
+    size_t cap = size_t(0.6 * double(free_b + ctx->stage.bytes));
+    size_t need = std::min(want, cap);
+    if (need < size_t(biggest) * rec_bytes) return fail(APC_E_NOMEM, "one tile's pieces do not fit in device memory");
+    ctx->stage.release();
+    hipError_t e = ctx->stage.ensure(need);
+    if (e != hipSuccess) return fail(APC_E_NOMEM, "staging %zu bytes: %s", need, hipGetErrorString(e));
+  }
+  const long long cap_pieces = (long long)(ctx->stage.bytes / rec_bytes);
+  bool first = true;
+  for (int t0 = 0; t0 < nt;) {
+    int t1 = t0;
+    long long used = 0;
+    while (t1 < nt && used + tot[t1] <= cap_pieces) used += tot[t1++];
+    if (t1 == t0) return fail(APC_E_NOMEM, "tile %d does not fit in the staging buffer", t0);
+    if (first) HIPCHK(ev_mark(ctx, EV_STG, 0, s));
+    HIPCHK(apc::launch_stage(1, md, f, ctx->slots.as<SlotDev>(), ctx->offsets.as<int>(), ctx->counts.as<int>(),
+                             ctx->records.as<int>(), tf->rgba, t0, t1, nullptr, ctx->poff.as<long long>(), toff[t0],
+                             ctx->stage.as<float>(), ctr, s));
+    if (first) {
+      HIPCHK(ev_mark(ctx, EV_STG, 1, s));
+      HIPCHK(ev_mark(ctx, EV_EVL, 0, s));
+    }
+    HIPCHK(apc::launch_eval(mb->m, f, t0, t1, ctx->poff.as<long long>(), toff[t0], ctx->stage.as<float>(), tf->rgba,
+                            moments, bp, rgba, ctr, s));
+    if (first) HIPCHK(ev_mark(ctx, EV_EVL, 1, s));
+    first = false;
+    t0 = t1;
+  }
   HIPCHK(ev_mark(ctx, EV_RES, 1, s));
   return APC_OK;
 }
@@ -720,8 +803,8 @@ apc_status apc_get_timings(apc_ctx ctx, apc_timings* out) {
   apc_status st = check_ctx(ctx);
   if (st != APC_OK) return st;
   if (!out) return fail(APC_E_ARG, "out is NULL");
-  double ms[4] = {0, 0, 0, 0};
-  for (int k = 0; k < 4; ++k) {
+  double ms[EV_COUNT] = {};
+  for (int k = 0; k < EV_COUNT; ++k) {
     if (!ctx->ev_used[k]) continue;
     HIPCHK(hipEventSynchronize(ctx->ev[k][1]));
     float v = 0.0f;
@@ -732,6 +815,8 @@ apc_status apc_get_timings(apc_ctx ctx, apc_timings* out) {
   out->moments_ms = ms[EV_MOM];
   out->sum_ms = ms[EV_SUM];
   out->resolve_ms = ms[EV_RES];
+  out->stage_ms = ms[EV_STG];
+  out->eval_ms = ms[EV_EVL];
   return APC_OK;
 }
 

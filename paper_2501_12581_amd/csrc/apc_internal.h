@@ -63,12 +63,23 @@ hipError_t launch_bin_count(const MeshDev& m, const FrameDev& f, const SlotDev* 
                             const int* bface, int* counts, hipStream_t s);
 hipError_t launch_bin_fill(const MeshDev& m, const FrameDev& f, const SlotDev* slots, int max_faces,
                            const int* bface, const int* offsets, int* cursors, int* records, hipStream_t s);
+// stage one; pcount (tile-major [n_tiles * 64], may be null) receives the pieces per pixel
 hipError_t launch_moments(int mm, const MeshDev& m, const FrameDev& f, const SlotDev* slots, const int* offsets,
-                          const int* counts, const int* records, const float* tf_rgba, float* out,
+                          const int* counts, const int* records, const float* tf_rgba, float* out, int* pcount,
                           unsigned long long* counters, hipStream_t s);
-hipError_t launch_resolve(int mm, const MeshDev& m, const FrameDev& f, const SlotDev* slots, const int* offsets,
-                          const int* counts, const int* records, const float* tf_rgba, const float* moments,
-                          const BoundParams& bp, float* rgba, unsigned long long* counters, hipStream_t s);
+// stage two, walk part: mode 0 counts pieces per pixel into pcount; mode 1 writes the
+// pieces of tiles [tile_lo, tile_hi) as (z, a, s) at rec + 3 * (poff[pixel] - base)
+hipError_t launch_stage(int mode, const MeshDev& m, const FrameDev& f, const SlotDev* slots, const int* offsets,
+                        const int* counts, const int* records, const float* tf_rgba, int tile_lo, int tile_hi,
+                        int* pcount, const long long* poff, long long base, float* rec,
+                        unsigned long long* counters, hipStream_t s);
+// stage two, evaluation part for tiles [tile_lo, tile_hi)
+hipError_t launch_eval(int mm, const FrameDev& f, int tile_lo, int tile_hi, const long long* poff, long long base,
+                       const float* rec, const float* tf_rgba, const float* moments, const BoundParams& bp,
+                       float* rgba, unsigned long long* counters, hipStream_t s);
+hipError_t launch_tile_sums(const int* pcount, int n_tiles, long long* tile_tot, hipStream_t s);
+hipError_t launch_piece_offsets(const int* pcount, const long long* tile_off, int n_tiles, long long* poff,
+                                hipStream_t s);
 hipError_t launch_sum_moments(const float* in, int n_slots, const int* order, int64_t elems, float* out,
                               hipStream_t s);
 hipError_t launch_sum_images(const float* in, int n_slots, const int* order, int64_t pixels, const float* b0,

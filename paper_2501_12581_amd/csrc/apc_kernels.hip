@@ -10,9 +10,10 @@
 //                sampling lattice and add a*z^j per piece (paper Alg. 2)
 //   k_sum_moments  canonical-order FP64 sum of the per-subdomain images
 //                (the paper's moment Allreduce, Section 4.1)
-//   k_resolve    the same walk again; per pixel the global moments give the
-//                moment bound (Alg. 3), per piece T = exp(-b0 F) weights the
-//                piece's colour (Alg. 1 second loop, Section 4.2)
+//   k_stage      the same walk again, staging every piece (z, a, s) in HBM
+//   k_eval       per pixel the global moments give the moment bound (Alg. 3);
+//                64 staged pieces at a time get T = exp(-b0 F), which weights
+//                the piece's colour (Alg. 1 second loop, Section 4.2)
 //   k_sum_images canonical-order sum of partial images + renormalisation
 //
 // Geometry.  A ray crosses a face iff its Plücker side products with the
@@ -124,6 +125,23 @@ __device__ __forceinline__ float side_canon(const VS& lo, const VS& hi) {
 // oriented side product of a -> b
 __device__ __forceinline__ float side(const VS& a, const VS& b) {
   return a.id < b.id ? side_canon(a, b) : -side_canon(b, a);
+}
+
+// Field-by-field selection among three vertex records (a conditional on the
+// whole struct would be lowered to an indexed scratch array).
+__device__ __forceinline__ float fsel3(int x, float a, float b, float c) { return x == 0 ? a : (x == 1 ? b : c); }
+__device__ __forceinline__ VS vsel3(int x, const VS& a, const VS& b, const VS& c) {
+  VS r;
+  r.id = x == 0 ? a.id : (x == 1 ? b.id : c.id);
+  r.x = fsel3(x, a.x, b.x, c.x);
+  r.y = fsel3(x, a.y, b.y, c.y);
+  r.z = fsel3(x, a.z, b.z, c.z);
+  r.s = fsel3(x, a.s, b.s, c.s);
+  r.t = fsel3(x, a.t, b.t, c.t);
+  r.wx = fsel3(x, a.wx, b.wx, c.wx);
+  r.wy = fsel3(x, a.wy, b.wy, c.wy);
+  r.wz = fsel3(x, a.wz, b.wz, c.wz);
+  return r;
 }
 
 // Crossing point of the ray with the face (A, B, C) whose oriented products
@@ -263,12 +281,12 @@ __device__ void walk(const MeshDev& M, const FrameDev& f, const Ray& r, int tet,
       x = (m0 >= m1 && m0 >= m2) ? 0 : (m1 >= m2 ? 1 : 2);
       ++cnt.fallback;
     }
-    VS Y = x == 0 ? B : (x == 1 ? C : A);
-    VS Z = x == 0 ? C : (x == 1 ? A : B);
-    float pYZ = x == 0 ? pBC : (x == 1 ? pCA : pAB);
-    float qY = x == 0 ? qB : (x == 1 ? qC : qA);
-    float qZ = x == 0 ? qC : (x == 1 ? qA : qB);
-    int xid = x == 0 ? A.id : (x == 1 ? B.id : C.id);
+    const VS Y = vsel3(x, B, C, A);
+    const VS Z = vsel3(x, C, A, B);
+    const float pYZ = fsel3(x, pBC, pCA, pAB);
+    const float qY = fsel3(x, qB, qC, qA);
+    const float qZ = fsel3(x, qC, qA, qB);
+    const int xid = x == 0 ? A.id : (x == 1 ? B.id : C.id);
     float tout, sout;
     face_point(Y, Z, D, pYZ, -qZ, qY, tout, sout);
     if (!(tout >= tin)) tout = tin;
@@ -390,13 +408,19 @@ __device__ __forceinline__ unsigned wave_sum(unsigned v) {
   return v;
 }
 
+__device__ __forceinline__ void flush_one(unsigned v, unsigned long long* slot) {
+  unsigned s = wave_sum(v);
+  if (threadIdx.x == 0 && s) atomicAdd(slot, (unsigned long long)s);
+}
+
 __device__ __forceinline__ void flush_counts(const LaneCount& c, unsigned long long* ctr) {
-  unsigned v[7] = {c.pieces, c.steps, c.entries, c.steplimit, c.fallback, c.overflow, c.nonpd};
-  int idx[7] = {C_PIECES, C_STEPS, C_ENTRIES, C_STEPLIMIT, C_FALLBACK, C_OVERFLOW, C_NONPD};
-  for (int k = 0; k < 7; ++k) {
-    unsigned s = wave_sum(v[k]);
-    if (threadIdx.x == 0 && s) atomicAdd(ctr + idx[k], (unsigned long long)s);
-  }
+  flush_one(c.pieces, ctr + C_PIECES);
+  flush_one(c.steps, ctr + C_STEPS);
+  flush_one(c.entries, ctr + C_ENTRIES);
+  flush_one(c.steplimit, ctr + C_STEPLIMIT);
+  flush_one(c.fallback, ctr + C_FALLBACK);
+  flush_one(c.overflow, ctr + C_OVERFLOW);
+  flush_one(c.nonpd, ctr + C_NONPD);
 }
 
 // ------------------------------------------------------------------ stage one
@@ -441,7 +465,8 @@ template <int M1>
 __global__ __launch_bounds__(WAVE) void k_moments(MeshDev M, FrameDev f, const SlotDev* __restrict__ slots,
                                                   const int* __restrict__ offsets, const int* __restrict__ counts,
                                                   const int* __restrict__ records, const float* __restrict__ tf_rgba,
-                                                  float* __restrict__ out, unsigned long long* ctr) {
+                                                  float* __restrict__ out, int* __restrict__ pcount,
+                                                  unsigned long long* ctr) {
   extern __shared__ float4 dyn_lds[];
   float* tfa = reinterpret_cast<float*>(dyn_lds);  // [n_tf] alpha column
   __shared__ FaceL faces[CHUNK];
@@ -478,41 +503,108 @@ __global__ __launch_bounds__(WAVE) void k_moments(MeshDev M, FrameDev f, const S
       for (int j = 0; j < M1; ++j) o[size_t(j) * HW] = sink.b[j];
     }
   }
+  if (pcount) pcount[size_t(tile) * WAVE + lane] = int(cnt.pieces);
   flush_counts(cnt, ctr);
 }
 
 // ------------------------------------------------------------------ stage two
+//
+// Stage two is split in two kernels so that the per-sample FP64 moment bound
+// never runs inside the divergent tet walk:
+//   k_stage  walks the rays again exactly like stage one and writes every
+//            piece (warped depth z, optical depth a, scalar s) in walk order
+//            to a pixel-ordered buffer in HBM (per-pixel offsets come from the
+//            piece counts of stage one);
+//   k_eval   one wavefront per tile: the 64 lanes evaluate 64 consecutive
+//            pieces of the tile together (whatever pixel they belong to) with
+//            that pixel's Cholesky factor from LDS, then every pixel adds its
+//            own contributions in walk order, so the sum is deterministic.
 
-template <int N, class R>
-struct ColorSink {
+// counts the pieces each pixel ray generates (same walk, no output)
+struct CountSink {
   const FrameDev* f;
-  const float4* tf;  // LDS table
-  const apcm::Bound<N, R>* bound;
-  R eta;
-  bool active;
-  float acc[4];
   unsigned pieces;
+  __device__ void chord(float t0, float t1, float s0, float s1) {
+    cut_chord(*f, t0, t1, s0, s1, [&](float, float, float) { ++pieces; });
+  }
+};
+
+// writes (z, a, s) of every piece of one pixel ray, in walk order; the walk
+// is the bit-identical repeat of the counting walk, and `cap` (the counted
+// pieces) bounds the writes regardless
+struct StageSink {
+  const FrameDev* f;
+  const float* tfa;  // LDS alpha column
+  float* out;        // this pixel's records: 3 floats each
+  unsigned pieces;
+  unsigned cap;
   __device__ void chord(float t0, float t1, float s0, float s1) {
     cut_chord(*f, t0, t1, s0, s1, [&](float tm, float len, float s) {
       int i0;
       float fr, a, z;
       tf_coord(*f, s, i0, fr);
-      const float4 c0 = tf[i0], c1 = tf[i0 + 1];
-      float A = lerp_nc(c0.w, c1.w, fr);
+      float A = lerp_nc(tfa[i0], tfa[i0 + 1], fr);
       piece_az(*f, tm, len, A, a, z);
+      if (pieces < cap) {
+        float* o = out + 3 * size_t(pieces);
+        o[0] = z;
+        o[1] = a;
+        o[2] = s;
+      }
       ++pieces;
-      if (!active) return;
-      R F = bound->frac_before(R(z), eta);
-      float T = __expf(-float(bound->b0 * F));
-      T = fminf(fmaxf(T, 0.0f), 1.0f);
-      float w = T * (-expm1f(-a));
-      acc[0] += w * lerp_nc(c0.x, c1.x, fr);
-      acc[1] += w * lerp_nc(c0.y, c1.y, fr);
-      acc[2] += w * lerp_nc(c0.z, c1.z, fr);
-      acc[3] += w;
     });
   }
 };
+
+// Walk every pixel ray of a tile through the listed subdomains.  mode 0:
+// count pieces into pcount (tile-major); mode 1: write piece records at
+// poff[pixel] - base into rec.
+__global__ __launch_bounds__(WAVE) void k_stage(MeshDev M, FrameDev f, const SlotDev* __restrict__ slots,
+                                                const int* __restrict__ offsets, const int* __restrict__ counts,
+                                                const int* __restrict__ records, const float* __restrict__ tf_rgba,
+                                                int tile_lo, int mode, int* __restrict__ pcount,
+                                                const long long* __restrict__ poff, long long base,
+                                                float* __restrict__ rec, unsigned long long* ctr) {
+  extern __shared__ float4 dyn_lds[];
+  float* tfa = reinterpret_cast<float*>(dyn_lds);
+  __shared__ FaceL faces[CHUNK];
+  __shared__ float ent_t[E_MAX * WAVE];
+  __shared__ int ent_c[E_MAX * WAVE];
+  const int lane = threadIdx.x;
+  for (int i = lane; i < f.n_tf; i += WAVE) tfa[i] = tf_rgba[4 * i + 3];
+  const int tile = tile_lo + xcd_tile(blockIdx.x, gridDim.x);
+  const int tx = tile % f.tiles_x, ty = tile / f.tiles_x;
+  const int px = tx * TILE + (lane & (TILE - 1)), py = ty * TILE + (lane / TILE);
+  const bool valid = px < f.W && py < f.H;
+  const Ray r = pixel_ray(f, valid ? py : 0, valid ? px : 0);
+  EntryList L{ent_t, ent_c, lane};
+  LaneCount cnt = {};
+  const size_t slot = size_t(tile) * WAVE + lane;
+  __syncthreads();
+  if (mode == 0) {
+    CountSink sink{&f, 0u};
+    for (int k = 0; k < f.n_slots; ++k) {
+      const int bin = tile * f.n_slots + k;
+      const int n_rec = counts[bin];
+      if (n_rec > 0) walk_subdomain(M, f, r, valid, records + offsets[bin], n_rec, slots[k], faces, L, sink, cnt);
+    }
+    pcount[slot] = int(sink.pieces);
+  } else {
+    const unsigned cap = unsigned(poff[slot + 1] - poff[slot]);
+    StageSink sink{&f, tfa, rec + 3 * (poff[slot] - base), 0u, cap};
+    for (int k = 0; k < f.n_slots; ++k) {
+      const int bin = tile * f.n_slots + k;
+      const int n_rec = counts[bin];
+      if (n_rec > 0) walk_subdomain(M, f, r, valid, records + offsets[bin], n_rec, slots[k], faces, L, sink, cnt);
+    }
+    cnt.pieces += sink.pieces;
+    if (sink.pieces != cap) ++cnt.overflow;  // a re-walk that disagrees with the count (never expected)
+  }
+  flush_counts(cnt, ctr);
+}
+
+template <int N, class R>
+using LdsBound = apcm::Bound<N, R, apcm::StridedStore<(N + 1) * (N + 2) / 2, R, WAVE>>;
 
 __device__ __forceinline__ float4 finalize_px(float4 acc, float b0, int finalize, int renormalize) {
   if (!finalize) return acc;
@@ -522,32 +614,49 @@ __device__ __forceinline__ float4 finalize_px(float4 acc, float b0, int finalize
   return make_float4(acc.x * sc, acc.y * sc, acc.z * sc, A);
 }
 
+__device__ __forceinline__ float wave_sum_f(float v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  return v;
+}
+
+// Moment bound for every staged piece of a tile and the per-pixel colour
+// sums (Alg. 1 second loop, Alg. 3).  The tile's pixels are taken one at a
+// time: the 64 lanes evaluate that pixel's consecutive pieces (so they share
+// the pixel's factor and, with nearby depths, mostly the same branches), each
+// lane keeps a partial sum, and a fixed butterfly adds the partials, so the
+// result does not depend on scheduling.
 template <int N, class R>
-__global__ __launch_bounds__(WAVE) void k_resolve(MeshDev M, FrameDev f, const SlotDev* __restrict__ slots,
-                                                  const int* __restrict__ offsets, const int* __restrict__ counts,
-                                                  const int* __restrict__ records, const float* __restrict__ tf_rgba,
-                                                  const float* __restrict__ moments, BoundParams bp,
-                                                  float* __restrict__ rgba, unsigned long long* ctr) {
+__global__ __launch_bounds__(WAVE) void k_eval(FrameDev f, int tile_lo, const long long* __restrict__ poff,
+                                               long long base, const float* __restrict__ rec,
+                                               const float* __restrict__ tf_rgba, const float* __restrict__ moments,
+                                               BoundParams bp, float* __restrict__ rgba,
+                                               unsigned long long* ctr) {
   extern __shared__ float4 dyn_lds[];
   float4* tf = dyn_lds;  // [n_tf] RGBA
-  __shared__ FaceL faces[CHUNK];
-  __shared__ float ent_t[E_MAX * WAVE];
-  __shared__ int ent_c[E_MAX * WAVE];
   constexpr int M1 = 2 * N + 1;
+  constexpr int NL = (N + 1) * (N + 2) / 2;
+  __shared__ R li_lds[NL * WAVE];  // per-pixel inverse Cholesky factors, lane-minor
+  __shared__ R b0_lds[WAVE], z1_lds[WAVE], xlo_lds[WAVE], xhi_lds[WAVE];
+  __shared__ int mode_lds[WAVE];
+  __shared__ int off_lds[WAVE + 1];  // piece offsets of the tile's pixels, relative to the tile
   const int lane = threadIdx.x;
   for (int i = lane; i < f.n_tf; i += WAVE)
     tf[i] = make_float4(tf_rgba[4 * i], tf_rgba[4 * i + 1], tf_rgba[4 * i + 2], tf_rgba[4 * i + 3]);
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int tile = tile_lo + xcd_tile(blockIdx.x, gridDim.x);
   const int tx = tile % f.tiles_x, ty = tile / f.tiles_x;
   const int px = tx * TILE + (lane & (TILE - 1)), py = ty * TILE + (lane / TILE);
   const bool valid = px < f.W && py < f.H;
-  const Ray r = pixel_ray(f, valid ? py : 0, valid ? px : 0);
   const size_t HW = size_t(f.W) * f.H, pix = size_t(py) * f.W + px;
+  const size_t slot0 = size_t(tile) * WAVE;
+  const long long tile_base = poff[slot0];
+  off_lds[lane] = int(poff[slot0 + lane] - tile_base);
+  if (lane == 0) off_lds[WAVE] = int(poff[slot0 + WAVE] - tile_base);
   LaneCount cnt = {};
   // per-pixel part of Alg. 3, once per pixel instead of once per sample
-  apcm::Bound<N, R> bound;
   float b0f = 0.0f;
   {
+    LdsBound<N, R> bound;
+    bound.Li.base = li_lds + lane;
     R b[M1], bias[2 * N];
 #pragma unroll
     for (int j = 0; j < M1; ++j) b[j] = valid ? R(moments[size_t(j) * HW + pix]) : R(0);
@@ -555,30 +664,79 @@ __global__ __launch_bounds__(WAVE) void k_resolve(MeshDev M, FrameDev f, const S
     for (int j = 0; j < 2 * N; ++j) bias[j] = R(bp.bias[j]);
     b0f = valid ? moments[pix] : 0.0f;
     cnt.nonpd += bound.setup(b, R(bp.alpha), bias);
+    b0_lds[lane] = bound.b0;
+    z1_lds[lane] = bound.z1;
+    xlo_lds[lane] = bound.xlo;
+    xhi_lds[lane] = bound.xhi;
+    mode_lds[lane] = valid ? bound.mode : 0;
   }
-  EntryList L{ent_t, ent_c, lane};
-  ColorSink<N, R> sink;
-  sink.f = &f;
-  sink.tf = tf;
-  sink.bound = &bound;
-  sink.eta = R(bp.eta);
-  sink.active = valid && bound.mode != 0;
-  sink.acc[0] = sink.acc[1] = sink.acc[2] = sink.acc[3] = 0.0f;
-  sink.pieces = 0;
   __syncthreads();
-  for (int k = 0; k < f.n_slots; ++k) {
-    const int bin = tile * f.n_slots + k;
-    const int n_rec = counts[bin];
-    if (n_rec == 0) continue;
-    const SlotDev sl = slots[k];
-    walk_subdomain(M, f, r, valid, records + offsets[bin], n_rec, sl, faces, L, sink, cnt);
+  const float* trec = rec + 3 * (tile_base - base);
+  const R eta = R(bp.eta);
+  float4 mine = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  for (int p = 0; p < WAVE; ++p) {  // uniform loop over the tile's pixels
+    const int lo = off_lds[p], hi = off_lds[p + 1];
+    const int md = mode_lds[p];
+    if (lo == hi || md == 0) continue;
+    LdsBound<N, R> bound;
+    bound.Li.base = li_lds + p;
+    bound.b0 = b0_lds[p];
+    bound.z1 = z1_lds[p];
+    bound.xlo = xlo_lds[p];
+    bound.xhi = xhi_lds[p];
+    bound.mode = md;
+    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+    for (int i = lo + lane; i < hi; i += WAVE) {
+      const float z = trec[3 * i], a = trec[3 * i + 1], s = trec[3 * i + 2];
+      const R F = bound.frac_before(R(z), eta);
+      float T = __expf(-float(bound.b0 * F));
+      T = fminf(fmaxf(T, 0.0f), 1.0f);
+      int i0;
+      float fr;
+      tf_coord(f, s, i0, fr);
+      const float4 t0 = tf[i0], t1 = tf[i0 + 1];
+      const float w = T * (-expm1f(-a));
+      a0 += w * lerp_nc(t0.x, t1.x, fr);
+      a1 += w * lerp_nc(t0.y, t1.y, fr);
+      a2 += w * lerp_nc(t0.z, t1.z, fr);
+      a3 += w;
+    }
+    a0 = wave_sum_f(a0);
+    a1 = wave_sum_f(a1);
+    a2 = wave_sum_f(a2);
+    a3 = wave_sum_f(a3);
+    if (lane == p) mine = make_float4(a0, a1, a2, a3);
   }
-  cnt.pieces += sink.pieces;
-  if (valid) {
-    float4 acc = make_float4(sink.acc[0], sink.acc[1], sink.acc[2], sink.acc[3]);
-    reinterpret_cast<float4*>(rgba)[pix] = finalize_px(acc, b0f, bp.finalize, bp.renormalize);
-  }
+  if (valid) reinterpret_cast<float4*>(rgba)[pix] = finalize_px(mine, b0f, bp.finalize, bp.renormalize);
   flush_counts(cnt, ctr);
+}
+
+// per-tile totals of the per-pixel piece counts (tile-major)
+__global__ void k_tile_sums(const int* __restrict__ pcount, int n_tiles, long long* __restrict__ tot) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_tiles) return;
+  long long s = 0;
+  for (int l = 0; l < WAVE; ++l) s += pcount[size_t(t) * WAVE + l];
+  tot[t] = s;
+}
+
+// exclusive prefix of the tile-major piece counts in 64-bit (one block per
+// tile: lane-level scan inside, tile bases from the scanned tile totals)
+__global__ void k_piece_offsets(const int* __restrict__ pcount, const long long* __restrict__ tile_off,
+                                int n_tiles, long long* __restrict__ poff) {
+  __shared__ long long part[WAVE];
+  const int t = blockIdx.x, lane = threadIdx.x;
+  const long long v = pcount[size_t(t) * WAVE + lane];
+  part[lane] = v;
+  __syncthreads();
+  for (int o = 1; o < WAVE; o <<= 1) {
+    long long add = lane >= o ? part[lane - o] : 0;
+    __syncthreads();
+    part[lane] += add;
+    __syncthreads();
+  }
+  poff[size_t(t) * WAVE + lane] = tile_off[t] + part[lane] - v;
+  if (t == n_tiles - 1 && lane == WAVE - 1) poff[size_t(n_tiles) * WAVE] = tile_off[t] + part[lane];
 }
 
 // ------------------------------------------------------------------ binning
@@ -834,36 +992,59 @@ hipError_t launch_bin_fill(const MeshDev& m, const FrameDev& f, const SlotDev* s
 }
 
 hipError_t launch_moments(int mm, const MeshDev& m, const FrameDev& f, const SlotDev* slots, const int* offsets,
-                          const int* counts, const int* records, const float* tf_rgba, float* out,
+                          const int* counts, const int* records, const float* tf_rgba, float* out, int* pcount,
                           unsigned long long* counters, hipStream_t s) {
   const size_t lds = size_t(f.n_tf) * sizeof(float);
   const dim3 grid(f.n_tiles), block(WAVE);
   if (mm == 4)
     hipLaunchKernelGGL(k_moments<5>, grid, block, lds, s, m, f, slots, offsets, counts, records, tf_rgba, out,
-                       counters);
+                       pcount, counters);
   else if (mm == 6)
     hipLaunchKernelGGL(k_moments<7>, grid, block, lds, s, m, f, slots, offsets, counts, records, tf_rgba, out,
-                       counters);
+                       pcount, counters);
   else
     hipLaunchKernelGGL(k_moments<9>, grid, block, lds, s, m, f, slots, offsets, counts, records, tf_rgba, out,
-                       counters);
+                       pcount, counters);
   return hipGetLastError();
 }
 
-hipError_t launch_resolve(int mm, const MeshDev& m, const FrameDev& f, const SlotDev* slots, const int* offsets,
-                          const int* counts, const int* records, const float* tf_rgba, const float* moments,
-                          const BoundParams& bp, float* rgba, unsigned long long* counters, hipStream_t s) {
+hipError_t launch_stage(int mode, const MeshDev& m, const FrameDev& f, const SlotDev* slots, const int* offsets,
+                        const int* counts, const int* records, const float* tf_rgba, int tile_lo, int tile_hi,
+                        int* pcount, const long long* poff, long long base, float* rec,
+                        unsigned long long* counters, hipStream_t s) {
+  if (tile_hi <= tile_lo) return hipSuccess;
+  const size_t lds = size_t(f.n_tf) * sizeof(float);
+  hipLaunchKernelGGL(k_stage, dim3(tile_hi - tile_lo), dim3(WAVE), lds, s, m, f, slots, offsets, counts, records,
+                     tf_rgba, tile_lo, mode, pcount, poff, base, rec, counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval(int mm, const FrameDev& f, int tile_lo, int tile_hi, const long long* poff, long long base,
+                       const float* rec, const float* tf_rgba, const float* moments, const BoundParams& bp,
+                       float* rgba, unsigned long long* counters, hipStream_t s) {
+  if (tile_hi <= tile_lo) return hipSuccess;
   const size_t lds = size_t(f.n_tf) * sizeof(float4);
-  const dim3 grid(f.n_tiles), block(WAVE);
+  const dim3 grid(tile_hi - tile_lo), block(WAVE);
   if (mm == 4)
-    hipLaunchKernelGGL((k_resolve<2, float>), grid, block, lds, s, m, f, slots, offsets, counts, records, tf_rgba,
-                       moments, bp, rgba, counters);
+    hipLaunchKernelGGL((k_eval<2, float>), grid, block, lds, s, f, tile_lo, poff, base, rec, tf_rgba, moments, bp,
+                       rgba, counters);
   else if (mm == 6)
-    hipLaunchKernelGGL((k_resolve<3, double>), grid, block, lds, s, m, f, slots, offsets, counts, records,
-                       tf_rgba, moments, bp, rgba, counters);
+    hipLaunchKernelGGL((k_eval<3, double>), grid, block, lds, s, f, tile_lo, poff, base, rec, tf_rgba, moments, bp,
+                       rgba, counters);
   else
-    hipLaunchKernelGGL((k_resolve<4, double>), grid, block, lds, s, m, f, slots, offsets, counts, records,
-                       tf_rgba, moments, bp, rgba, counters);
+    hipLaunchKernelGGL((k_eval<4, double>), grid, block, lds, s, f, tile_lo, poff, base, rec, tf_rgba, moments, bp,
+                       rgba, counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_sums(const int* pcount, int n_tiles, long long* tile_tot, hipStream_t s) {
+  hipLaunchKernelGGL(k_tile_sums, dim3(grid1(n_tiles, 256)), dim3(256), 0, s, pcount, n_tiles, tile_tot);
+  return hipGetLastError();
+}
+
+hipError_t launch_piece_offsets(const int* pcount, const long long* tile_off, int n_tiles, long long* poff,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_piece_offsets, dim3(n_tiles), dim3(WAVE), 0, s, pcount, tile_off, n_tiles, poff);
   return hipGetLastError();
 }
 

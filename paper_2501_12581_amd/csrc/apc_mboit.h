@@ -3,6 +3,8 @@
 // Per pixel (hoisted out of the per-sample loop of Alg. 3, same result):
 //   beta'_j = (1 - alpha) * b_j / b0 + alpha * bias_j,  beta'_0 = 1
 //   B = Hankel(beta'_0..beta'_2n) of size (n+1)^2,  B = L L^T,  Li = L^-1
+//   xlo, xhi = smallest and largest zero of the orthonormal polynomial of
+//              degree n (row n of Li)
 // Per sample at warped depth z:
 //   P = Li * (1, z, ..., z^n)       values of the orthonormal polynomials at z
 //   q = Li^T * P                    coefficients of the kernel polynomial
@@ -10,7 +12,7 @@
 //   x_1..x_n = roots of K(., z)     (real and simple when B is positive definite)
 //   the nodes {z, x_1..x_n} carry the weights 1 / K(x_i, x_i) (Christoffel
 //   numbers: the nodes are pairwise K-orthogonal, so a degree-2n quadrature on
-//   them reproduces all moments exactly)
+//   them reproduces all moments exactly; the weights sum to 1)
 //   F = eta / K(z, z) + sum_{x_i < z} 1 / K(x_i, x_i)
 // F is the fraction of the pixel's absorbance in front of z; the caller forms
 // T = clamp(exp(-b0 * F), 0, 1).  This is the same quantity as evaluating the
@@ -18,16 +20,25 @@
 // the polynomial solve and dot product), reached through the Christoffel
 // numbers instead of a Lagrange or Newton interpolant.
 //
+// The nodes other than z interlace with the zeros of the degree-n orthonormal
+// polynomial: each gap between consecutive zeros, and each of the two
+// unbounded ends, holds exactly one node except the gap that holds z.  So for
+// z below the smallest zero no node lies in front (F = eta / K(z, z)), for z
+// above the largest all do (F = 1 - (1 - eta) / K(z, z)), and only in between
+// are the roots needed; the weights are summed over whichever side of z has
+// fewer nodes.
+//
 // Roots: closed forms (quadratic; trigonometric cubic; Ferrari quartic whose
 // resolvent's largest root comes from the trigonometric cubic), each root
 // polished by one Newton step on the kernel polynomial.  A vanishing leading
 // coefficient means one node has gone to infinity with zero weight; the
-// degree is lowered instead of dividing by it.
+// degree is lowered instead of dividing by it.  Reciprocals use the hardware
+// estimate (plus two Newton-Raphson steps in FP64) on the device.
 //
 // Precision R is float or double; n = m/2 is 2, 3 or 4.
 //
-// The functions are host+device so that host-side tests can exercise exactly
-// the code the kernels run.
+// The functions are host+device so that host-side tests can exercise the code
+// the kernels run (on the host, reciprocals are IEEE divisions).
 #pragma once
 
 #include <math.h>
@@ -70,9 +81,33 @@ APC_HD double m_cbrt(double x) { return cbrt(x); }
 APC_HD float m_abs(float x) { return fabsf(x); }
 APC_HD double m_abs(double x) { return fabs(x); }
 
+// 1/b for finite b != 0: hardware reciprocal estimate (refined by
+// Newton-Raphson in FP64) on the device, a plain division on the host.
+APC_HD float m_rcp(float b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rcpf(b);
+#else
+  return 1.0f / b;
+#endif
+}
+APC_HD double m_rcp(double b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r = __builtin_amdgcn_rcp(b);
+  r = fma(fma(-b, r, 1.0), r, r);
+  r = fma(fma(-b, r, 1.0), r, r);
+  return r;
+#else
+  return 1.0 / b;
+#endif
+}
+
 template <class R>
 APC_HD R m_max(R a, R b) {
   return a > b ? a : b;
+}
+template <class R>
+APC_HD R m_min(R a, R b) {
+  return a < b ? a : b;
 }
 template <class R>
 APC_HD R m_clamp(R x, R lo, R hi) {
@@ -88,7 +123,7 @@ template <class R>
 APC_HD int roots2(R c0, R c1, R c2, R* x) {
   if (c2 == R(0)) {
     if (c1 == R(0)) return 0;
-    x[0] = -c0 / c1;
+    x[0] = -c0 * m_rcp(c1);
     return 1;
   }
   R disc = m_max(c1 * c1 - R(4) * c2 * c0, R(0));
@@ -98,25 +133,26 @@ APC_HD int roots2(R c0, R c1, R c2, R* x) {
     x[0] = x[1] = R(0);
     return 2;
   }
-  x[0] = t / c2;
-  x[1] = c0 / t;
+  x[0] = t * m_rcp(c2);
+  x[1] = c0 * m_rcp(t);
   return 2;
 }
 
-// Roots of the depressed cubic y^3 + p y + q, real parts when two are complex.
+// Roots of the depressed cubic y^3 + p y + q, real parts when two are complex;
+// y[0] is the largest when all three are real.
 template <class R>
 APC_HD void depressed3(R p, R q, R* y) {
   const R two_pi_3 = R(2.0943951023931954923);
   if (p < R(0)) {
-    R mm = m_sqrt(-p / R(3));
-    R arg = m_clamp(-q / (R(2) * mm * mm * mm), R(-1), R(1));
-    R th = m_acos(arg) / R(3);
-    y[0] = R(2) * mm * m_cos(th);  // largest
+    R mm = m_sqrt(-p * R(1.0 / 3.0));
+    R arg = m_clamp(-q * m_rcp(R(2) * mm * mm * mm), R(-1), R(1));
+    R th = m_acos(arg) * R(1.0 / 3.0);
+    y[0] = R(2) * mm * m_cos(th);
     y[1] = R(2) * mm * m_cos(th - two_pi_3);
     y[2] = R(2) * mm * m_cos(th + two_pi_3);
   } else {
-    R sd = m_sqrt(m_max(q * q / R(4) + p * p * p / R(27), R(0)));
-    R u = m_cbrt(-q / R(2) + sd), w = m_cbrt(-q / R(2) - sd);
+    R sd = m_sqrt(m_max(q * q * R(0.25) + p * p * p * R(1.0 / 27.0), R(0)));
+    R u = m_cbrt(-q * R(0.5) + sd), w = m_cbrt(-q * R(0.5) - sd);
     y[0] = u + w;
     y[1] = y[2] = R(-0.5) * (u + w);
   }
@@ -125,39 +161,57 @@ APC_HD void depressed3(R p, R q, R* y) {
 // Roots of c0 + c1 x + c2 x^2 + c3 x^3 (c3 != 0); x[0] is the largest when all are real.
 template <class R>
 APC_HD int roots3(const R* c, R* x) {
-  R inv = R(1) / c[3];
+  R inv = m_rcp(c[3]);
   R a = c[2] * inv, b = c[1] * inv, cc = c[0] * inv;
-  R a3 = a / R(3);
+  R a3 = a * R(1.0 / 3.0);
   R p = b - a * a3;
   R q = cc + a3 * (R(2) * a3 * a3 - b);
   R y[3];
   depressed3(p, q, y);
+#pragma unroll
   for (int i = 0; i < 3; ++i) x[i] = y[i] - a3;
   return 3;
+}
+
+// Largest real root of m^3 + p m^2 + s m + t (only that root is needed, so
+// one cosine instead of three), polished by two Newton steps.
+template <class R>
+APC_HD R largest_root3(R p, R s, R t) {
+  const R a3 = p * R(1.0 / 3.0);
+  const R pp = s - p * a3;
+  const R qq = t + a3 * (R(2) * a3 * a3 - s);
+  R m0;
+  if (pp < R(0)) {
+    const R mm = m_sqrt(-pp * R(1.0 / 3.0));
+    const R arg = m_clamp(-qq * m_rcp(R(2) * mm * mm * mm), R(-1), R(1));
+    m0 = R(2) * mm * m_cos(m_acos(arg) * R(1.0 / 3.0)) - a3;
+  } else {
+    const R sd = m_sqrt(m_max(qq * qq * R(0.25) + pp * pp * pp * R(1.0 / 27.0), R(0)));
+    m0 = m_cbrt(-qq * R(0.5) + sd) + m_cbrt(-qq * R(0.5) - sd) - a3;
+  }
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const R f = ((m0 + p) * m0 + s) * m0 + t;
+    const R df = (R(3) * m0 + R(2) * p) * m0 + s;
+    if (df != R(0)) {
+      const R mn = m0 - f * m_rcp(df);
+      if (m_finite(mn)) m0 = mn;
+    }
+  }
+  return m0;
 }
 
 // Roots of c0 + ... + c4 x^4 (c4 != 0) by Ferrari's resolvent.
 template <class R>
 APC_HD int roots4(const R* c, R* x) {
-  R inv = R(1) / c[4];
+  R inv = m_rcp(c[4]);
   R a = c[3] * inv, b = c[2] * inv, cc = c[1] * inv, d = c[0] * inv;
-  R a4 = a / R(4), a4s = a4 * a4;
+  R a4 = a * R(0.25), a4s = a4 * a4;
   R p = b - R(6) * a4s;
   R q = cc - R(2) * b * a4 + R(8) * a4s * a4;
   R r = d - cc * a4 + b * a4s - R(3) * a4s * a4s;
   // resolvent m^3 + p m^2 + (p^2/4 - r) m - q^2/8 = 0: its largest root is >= 0
-  R rc[4] = {-q * q / R(8), p * p / R(4) - r, p, R(1)};
-  R mr[3];
-  roots3(rc, mr);
-  R m0 = mr[0];
-  for (int it = 0; it < 2; ++it) {  // Newton polish of the resolvent root
-    R f = ((m0 + rc[2]) * m0 + rc[1]) * m0 + rc[0];
-    R df = (R(3) * m0 + R(2) * rc[2]) * m0 + rc[1];
-    if (df != R(0)) {
-      R mn = m0 - f / df;
-      if (m_finite(mn)) m0 = mn;
-    }
-  }
+  R m0 = largest_root3(p, p * p * R(0.25) - r, -q * q * R(0.125));
   R y[4];
   if (!(m0 > R(0))) {  // biquadratic y^4 + p y^2 + r
     R w[2];
@@ -169,56 +223,90 @@ APC_HD int roots4(const R* c, R* x) {
     y[3] = -s1;
   } else {
     R s = m_sqrt(R(2) * m0);
-    R h = q / (R(2) * s);
-    R base = p / R(2) + m0;
+    R h = q * m_rcp(R(2) * s);
+    R base = p * R(0.5) + m0;
     roots2(base + h, -s, R(1), y);
     roots2(base - h, s, R(1), y + 2);
   }
+#pragma unroll
   for (int i = 0; i < 4; ++i) x[i] = y[i] - a4;
   return 4;
 }
 
-// Roots of the kernel polynomial q[0..N]; returns how many finite ones.
+// Roots of the polynomial q[0..N]; returns how many finite ones (x[0..nr)).
 template <int N, class R>
-APC_HD int kernel_roots(const R* q, R* x) {
+APC_HD int poly_roots(const R* q, R* x) {
   R cmax = R(0);
+#pragma unroll
   for (int j = 0; j <= N; ++j) cmax = m_max(cmax, m_abs(q[j]));
-  int deg = N;
-  while (deg > 0 && m_abs(q[deg]) <= Num<R>::deg_tol * cmax) --deg;
+  // degree after dropping negligible leading coefficients (unrolled: no indexed arrays)
+  int deg = 0;
+  bool top = true;
+#pragma unroll
+  for (int j = N; j >= 1; --j) {
+    if (top && m_abs(q[j]) > Num<R>::deg_tol * cmax) {
+      deg = j;
+      top = false;
+    }
+  }
   int nr = 0;
   if (deg == 1) {
-    x[0] = -q[0] / q[1];
+    x[0] = -q[0] * m_rcp(q[1]);
     nr = 1;
   } else if (deg == 2) {
     nr = roots2(q[0], q[1], q[2], x);
-  } else if (deg == 3) {
+  } else if (N >= 3 && deg == 3) {
     nr = roots3(q, x);
-  } else if (deg == 4) {
+  } else if (N >= 4 && deg == 4) {
     nr = roots4(q, x);
   }
-  for (int i = 0; i < nr; ++i) {  // one Newton step on the full polynomial
+#pragma unroll
+  for (int i = 0; i < N; ++i) {  // one Newton step on the full polynomial (fixed trip count: no indexed arrays)
+    if (i >= nr) continue;
     R xi = x[i];
     R p = q[N], dp = R(0);
+#pragma unroll
     for (int j = N - 1; j >= 0; --j) {
       dp = dp * xi + p;
       p = p * xi + q[j];
     }
     if (dp != R(0)) {
-      R xn = xi - p / dp;
+      R xn = xi - p * m_rcp(dp);
       if (m_finite(xn)) x[i] = xn;
     }
   }
   return nr;
 }
 
-// Per-pixel state of the bound.
+// the name the host tests use
 template <int N, class R>
+APC_HD int kernel_roots(const R* q, R* x) {
+  return poly_roots<N, R>(q, x);
+}
+
+// Storage of the packed inverse factor: a plain array (host tests), or a
+// lane-strided slice of LDS shared by a wavefront (kernels).
+template <int NL, class R>
+struct ArrayStore {
+  R v[NL];
+  APC_HD R& operator[](int k) { return v[k]; }
+  APC_HD const R& operator[](int k) const { return v[k]; }
+};
+template <int NL, class R, int STRIDE>
+struct StridedStore {
+  R* base;  // element k at base[k * STRIDE]
+  APC_HD R& operator[](int k) const { return base[k * STRIDE]; }
+};
+
+// Per-pixel state of the bound.
+template <int N, class R, class Store = ArrayStore<(N + 1) * (N + 2) / 2, R>>
 struct Bound {
   static constexpr int NL = (N + 1) * (N + 2) / 2;
   R b0;
-  R z1;
-  R Li[NL];  // L^-1, packed lower triangle: row k starts at k(k+1)/2
-  int mode;  // 0: no absorbance, 1: all absorbance at depth z1, 2: regular
+  R z1;        // single-depth branch: the depth
+  R xlo, xhi;  // smallest / largest zero of the degree-N orthonormal polynomial
+  Store Li;    // L^-1, packed lower triangle: row k starts at k(k+1)/2
+  int mode;    // 0: no absorbance, 1: all absorbance at depth z1, 2: regular
 
   // b[0..2N] raw moments; bias[0..2N-1] = b*_1..b*_2N.  Returns the number of
   // Cholesky pivots that had to be floored.
@@ -226,10 +314,13 @@ struct Bound {
     mode = 0;
     b0 = b[0];
     z1 = R(0);
+    xlo = R(1);
+    xhi = R(-1);
     if (!(b0 > R(0))) return 0;
     R bp[2 * N + 1];
     bp[0] = R(1);
     R inv0 = R(1) / b0;
+#pragma unroll
     for (int j = 1; j <= 2 * N; ++j) bp[j] = (R(1) - alpha) * (b[j] * inv0) + alpha * bias[j - 1];
     if (bp[2] - bp[1] * bp[1] <= Num<R>::rank1_tol) {
       mode = 1;
@@ -239,13 +330,17 @@ struct Bound {
     mode = 2;
     R L[N + 1][N + 1];
     int floored = 0;
+#pragma unroll
     for (int j = 0; j <= N; ++j) {
+#pragma unroll
       for (int k = 0; k < j; ++k) {
         R s = bp[j + k];
+#pragma unroll
         for (int l = 0; l < k; ++l) s -= L[j][l] * L[k][l];
         L[j][k] = s / L[k][k];
       }
       R dd = bp[2 * j];
+#pragma unroll
       for (int l = 0; l < j; ++l) dd -= L[j][l] * L[j][l];
       if (!(dd > Num<R>::pivot_floor)) {
         dd = Num<R>::pivot_floor;
@@ -253,14 +348,36 @@ struct Bound {
       }
       L[j][j] = m_sqrt(dd);
     }
+    R row[N + 1];  // row N of Li: coefficients of the orthonormal polynomial of degree N
+#pragma unroll
     for (int j = 0; j <= N; ++j) {
       R dj = R(1) / L[j][j];
       Li[j * (j + 1) / 2 + j] = dj;
+      if (j == N) row[N] = dj;
+#pragma unroll
       for (int k = 0; k < j; ++k) {
         R s = R(0);
+#pragma unroll
         for (int l = k; l < j; ++l) s += L[j][l] * Li[l * (l + 1) / 2 + k];
         Li[j * (j + 1) / 2 + k] = -s * dj;
+        if (j == N) row[k] = -s * dj;
       }
+    }
+    // its zeros lie inside (-1, 1); only the extreme two are kept
+    R xi[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) xi[i] = R(0);
+    const int nz = poly_roots<N, R>(row, xi);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      if (i < nz) {
+        xlo = m_min(xlo, xi[i]);
+        xhi = m_max(xhi, xi[i]);
+      }
+    }
+    if (nz < N) {  // cannot happen for a positive definite factor; disable the shortcut
+      xlo = R(1);
+      xhi = R(-1);
     }
     return floored;
   }
@@ -268,13 +385,17 @@ struct Bound {
   // K(x, x) = |Li (1, x, ..., x^N)|^2
   APC_HD R kernel_diag(R x) const {
     R P[N + 1];
+#pragma unroll
     for (int k = 0; k <= N; ++k) P[k] = R(0);
     R v = R(1);
+#pragma unroll
     for (int j = 0; j <= N; ++j) {
+#pragma unroll
       for (int k = j; k <= N; ++k) P[k] += Li[k * (k + 1) / 2 + j] * v;
       v *= x;
     }
     R K = R(0);
+#pragma unroll
     for (int k = 0; k <= N; ++k) K += P[k] * P[k];
     return K;
   }
@@ -286,27 +407,44 @@ struct Bound {
       return z1 < z ? R(1) : R(0);
     }
     R P[N + 1];
+#pragma unroll
     for (int k = 0; k <= N; ++k) P[k] = R(0);
     R v = R(1);
+#pragma unroll
     for (int j = 0; j <= N; ++j) {
+#pragma unroll
       for (int k = j; k <= N; ++k) P[k] += Li[k * (k + 1) / 2 + j] * v;
       v *= z;
     }
     R K0 = R(0);
+#pragma unroll
     for (int k = 0; k <= N; ++k) K0 += P[k] * P[k];
+    const R lam0 = m_rcp(K0);
+    if (z < xlo) return eta * lam0;                  // no node in front of z
+    if (z > xhi) return R(1) - (R(1) - eta) * lam0;  // every other node in front of z
     R q[N + 1];
+#pragma unroll
     for (int j = 0; j <= N; ++j) {
       R s = R(0);
+#pragma unroll
       for (int k = j; k <= N; ++k) s += Li[k * (k + 1) / 2 + j] * P[k];
       q[j] = s;
     }
     R x[N];
-    int nr = kernel_roots<N, R>(q, x);
-    R F = eta / K0;
-    for (int i = 0; i < nr; ++i) {
-      if (x[i] < z && m_abs(x[i]) < Num<R>::far) F += R(1) / kernel_diag(x[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] = R(0);
+    const int nr = poly_roots<N, R>(q, x);
+    int below = 0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) below += (i < nr && x[i] < z) ? 1 : 0;
+    const bool use_below = 2 * below <= nr;  // sum over the side with fewer nodes
+    R S = R(0);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      if (i < nr && ((x[i] < z) == use_below) && m_abs(x[i]) < Num<R>::far) S += m_rcp(kernel_diag(x[i]));
     }
-    return F;
+    // a node at infinity (nr < N) carries no weight, so the finite weights still sum to 1
+    return use_below ? eta * lam0 + S : R(1) - (R(1) - eta) * lam0 - S;
   }
 };
 
