@@ -127,23 +127,6 @@ __device__ __forceinline__ float side(const VS& a, const VS& b) {
   return a.id < b.id ? side_canon(a, b) : -side_canon(b, a);
 }
 
-// Field-by-field selection among three vertex records (a conditional on the
-// whole struct would be lowered to an indexed scratch array).
-__device__ __forceinline__ float fsel3(int x, float a, float b, float c) { return x == 0 ? a : (x == 1 ? b : c); }
-__device__ __forceinline__ VS vsel3(int x, const VS& a, const VS& b, const VS& c) {
-  VS r;
-  r.id = x == 0 ? a.id : (x == 1 ? b.id : c.id);
-  r.x = fsel3(x, a.x, b.x, c.x);
-  r.y = fsel3(x, a.y, b.y, c.y);
-  r.z = fsel3(x, a.z, b.z, c.z);
-  r.s = fsel3(x, a.s, b.s, c.s);
-  r.t = fsel3(x, a.t, b.t, c.t);
-  r.wx = fsel3(x, a.wx, b.wx, c.wx);
-  r.wy = fsel3(x, a.wy, b.wy, c.wy);
-  r.wz = fsel3(x, a.wz, b.wz, c.wz);
-  return r;
-}
-
 // Crossing point of the ray with the face (A, B, C) whose oriented products
 // pAB, pBC, pCA are all positive: barycentric weights (pBC, pCA, pAB).  The
 // sums start at the vertex with the smallest id, so the walk that leaves a
@@ -281,14 +264,21 @@ __device__ void walk(const MeshDev& M, const FrameDev& f, const Ray& r, int tet,
       x = (m0 >= m1 && m0 >= m2) ? 0 : (m1 >= m2 ? 1 : 2);
       ++cnt.fallback;
     }
-    const VS Y = vsel3(x, B, C, A);
-    const VS Z = vsel3(x, C, A, B);
-    const float pYZ = fsel3(x, pBC, pCA, pAB);
-    const float qY = fsel3(x, qB, qC, qA);
-    const float qZ = fsel3(x, qC, qA, qB);
     const int xid = x == 0 ? A.id : (x == 1 ? B.id : C.id);
+    // The exit face replaces X by D in place: (D, B, C), (A, D, C) and
+    // (A, B, D) are rotations of the exit faces (B, C, D), (C, A, D) and
+    // (A, B, D), so the cyclic order with positive products is kept.
+    const float nAB = x == 0 ? qB : (x == 1 ? -qA : pAB);
+    const float nBC = x == 0 ? pBC : (x == 1 ? qC : -qB);
+    const float nCA = x == 0 ? -qC : (x == 1 ? pCA : qA);
+    if (x == 0) A = D;
+    if (x == 1) B = D;
+    if (x == 2) C = D;
+    pAB = nAB;
+    pBC = nBC;
+    pCA = nCA;
     float tout, sout;
-    face_point(Y, Z, D, pYZ, -qZ, qY, tout, sout);
+    face_point(A, B, C, pAB, pBC, pCA, tout, sout);
     if (!(tout >= tin)) tout = tin;
     ++cnt.steps;
     sink.chord(tin, tout, sin_, sout);
@@ -299,12 +289,6 @@ __device__ void walk(const MeshDev& M, const FrameDev& f, const Ray& r, int tet,
     if (t2 < t_lo || t2 >= t_hi) return;
     tet = t2;
     apex = nb & 3;
-    A = Y;
-    B = Z;
-    C = D;
-    pAB = pYZ;
-    pBC = -qZ;
-    pCA = qY;
     tin = tout;
     sin_ = sout;
   }
@@ -425,23 +409,15 @@ __device__ __forceinline__ void flush_counts(const LaneCount& c, unsigned long l
 
 // ------------------------------------------------------------------ stage one
 
-// Compensated (Kahan) accumulation: a ray crosses hundreds of pieces per
-// subdomain at the largest workloads, and plain FP32 sums would drift by
-// ~1e-5 of b0.
-__device__ __forceinline__ void kahan_add(float& sum, float& comp, float x) {
-#pragma clang fp contract(off)
-  float y = x - comp;
-  float tt = sum + y;
-  comp = (tt - sum) - y;
-  sum = tt;
-}
-
+// The moments accumulate in FP64: a ray crosses hundreds of pieces per
+// subdomain at the largest workloads, where FP32 sums would drift by ~1e-5 of
+// b0; FP64 adds cost the same issue slot as FP32 ones here and need no
+// compensation terms.
 template <int M1>
 struct MomentSink {
   const FrameDev* f;
   const float* tfa;  // LDS alpha column of the table
-  float b[M1];
-  float comp[M1];    // Kahan compensation terms
+  double b[M1];
   unsigned pieces;
   __device__ void chord(float t0, float t1, float s0, float s1) {
     cut_chord(*f, t0, t1, s0, s1, [&](float tm, float len, float s) {
@@ -453,7 +429,7 @@ struct MomentSink {
       float term = a;
 #pragma unroll
       for (int j = 0; j < M1; ++j) {  // Alg. 2: moment j gains absorbance * depth^j
-        kahan_add(b[j], comp[j], term);
+        b[j] += double(term);
         term *= z;
       }
       ++pieces;
@@ -461,8 +437,13 @@ struct MomentSink {
   }
 };
 
+// Waves per SIMD the walk kernels are compiled for (register budget 512 / n).
+#ifndef APC_WALK_WAVES
+#define APC_WALK_WAVES 3
+#endif
+
 template <int M1>
-__global__ __launch_bounds__(WAVE) void k_moments(MeshDev M, FrameDev f, const SlotDev* __restrict__ slots,
+__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_WALK_WAVES, 8))) void k_moments(MeshDev M, FrameDev f, const SlotDev* __restrict__ slots,
                                                   const int* __restrict__ offsets, const int* __restrict__ counts,
                                                   const int* __restrict__ records, const float* __restrict__ tf_rgba,
                                                   float* __restrict__ out, int* __restrict__ pcount,
@@ -491,7 +472,7 @@ __global__ __launch_bounds__(WAVE) void k_moments(MeshDev M, FrameDev f, const S
     sink.tfa = tfa;
     sink.pieces = 0;
 #pragma unroll
-    for (int j = 0; j < M1; ++j) sink.b[j] = sink.comp[j] = 0.0f;
+    for (int j = 0; j < M1; ++j) sink.b[j] = 0.0;
     if (n_rec > 0) {
       const SlotDev sl = slots[k];
       walk_subdomain(M, f, r, valid, records + offsets[bin], n_rec, sl, faces, L, sink, cnt);
@@ -500,7 +481,7 @@ __global__ __launch_bounds__(WAVE) void k_moments(MeshDev M, FrameDev f, const S
     if (valid) {
       float* o = out + size_t(k) * M1 * HW + pix;
 #pragma unroll
-      for (int j = 0; j < M1; ++j) o[size_t(j) * HW] = sink.b[j];
+      for (int j = 0; j < M1; ++j) o[size_t(j) * HW] = float(sink.b[j]);
     }
   }
   if (pcount) pcount[size_t(tile) * WAVE + lane] = int(cnt.pieces);
@@ -559,7 +540,8 @@ struct StageSink {
 // Walk every pixel ray of a tile through the listed subdomains.  mode 0:
 // count pieces into pcount (tile-major); mode 1: write piece records at
 // poff[pixel] - base into rec.
-__global__ __launch_bounds__(WAVE) void k_stage(MeshDev M, FrameDev f, const SlotDev* __restrict__ slots,
+__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_WALK_WAVES, 8))) void k_stage(
+    MeshDev M, FrameDev f, const SlotDev* __restrict__ slots,
                                                 const int* __restrict__ offsets, const int* __restrict__ counts,
                                                 const int* __restrict__ records, const float* __restrict__ tf_rgba,
                                                 int tile_lo, int mode, int* __restrict__ pcount,
@@ -625,8 +607,14 @@ __device__ __forceinline__ float wave_sum_f(float v) {
 // the pixel's factor and, with nearby depths, mostly the same branches), each
 // lane keeps a partial sum, and a fixed butterfly adds the partials, so the
 // result does not depend on scheduling.
+// Waves per SIMD the FP64 evaluation is compiled for (register budget 512 / n).
+#ifndef APC_EVAL_WAVES
+#define APC_EVAL_WAVES 3
+#endif
+
 template <int N, class R>
-__global__ __launch_bounds__(WAVE) void k_eval(FrameDev f, int tile_lo, const long long* __restrict__ poff,
+__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_EVAL_WAVES, 8))) void k_eval(
+    FrameDev f, int tile_lo, const long long* __restrict__ poff,
                                                long long base, const float* __restrict__ rec,
                                                const float* __restrict__ tf_rgba, const float* __restrict__ moments,
                                                BoundParams bp, float* __restrict__ rgba,
