@@ -492,3 +492,45 @@ def test_apc_vs_exact_compositing_report():
     print("APC vs exact (tiny): max abs %.3g rmse %.3g psnr %.2f dB" % (np.abs(d).max(), math.sqrt(mse), psnr))
     assert psnr > 30.0
     assert np.all(np.abs(d[:, 3]) <= 1e-14)  # opacity is 1 - exp(-b0) in both
+
+
+def test_depth_range_perspective_touches_the_bounding_sphere():
+    # the near/far depths are where the ray through the sphere centre meets the sphere
+    sc = synth.scene_medium(size=8)
+    lo = sc.mesh.xyz.min(axis=0).astype(np.float64)
+    hi = sc.mesh.xyz.max(axis=0).astype(np.float64)
+    c, R = 0.5 * (lo + hi), 0.5 * np.linalg.norm(hi - lo)
+    for seed in range(5):
+        eye = synth.sphere_eye(100 + seed, radius=2.0 + seed)
+        sc.view = synth.perspective_view(eye, (0.5, 0.5, 0.5), 8, 8)
+        tn, tf = oracle.depth_range(sc)
+        u = (c - eye) / np.linalg.norm(c - eye)
+        for t in (tn, tf):
+            assert abs(np.linalg.norm(eye + t * u - c) - R) <= 1e-12
+        assert 0 < tn < tf
+
+
+def test_exact_compositing_of_two_constant_fragments():
+    # two disjoint tets with constant scalars; each ray chord is one piece of known optical depth
+    xyz = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1],
+                    [0, 0, 2], [1, 0, 2], [0, 1, 2], [0, 0, 3]], dtype=np.float32)
+    tets = np.array([[0, 1, 2, 3], [4, 5, 6, 7]], np.int32)
+    scal = np.array([0.25] * 4 + [0.75] * 4, np.float32)
+    mesh = synth.Mesh(xyz=xyz, scalar=scal, tets=tets, tet_sub=np.array([0, 1], np.int32), n_sub=2)
+    o, d = (0.2, 0.25, -1.0), (0.0, 0.0, 1.0)
+    tf = synth.make_tf(8)
+    sc = _scene_from(mesh, _one_ray_view(o, d), m=4, step=100.0, tf=tf, s_min=0.0, s_max=1.0, renormalize=0)
+    r = oracle.render(sc, exact=True)
+    # chord lengths along +z at (0.2, 0.25): both tets are x + y + z' <= 1 slices, length 1 - 0.45
+    ln = 1.0 - 0.45
+    rgba = []
+    for s in (0.25, 0.75):
+        u = s * 255.0
+        i0 = int(math.floor(u))
+        fr = u - i0
+        rgba.append([(1 - fr) * float(tf[i0, c]) + fr * float(tf[i0 + 1, c]) for c in range(4)])
+    a = [sc.kappa * rgba[k][3] * ln for k in range(2)]
+    al = [-math.expm1(-x) for x in a]
+    expect = [al[0] * rgba[0][c] + math.exp(-a[0]) * al[1] * rgba[1][c] for c in range(3)]
+    assert np.allclose(r["exact"][0, :3], expect, atol=1e-14)
+    assert abs(r["exact"][0, 3] - (-math.expm1(-(a[0] + a[1])))) <= 1e-14
