@@ -45,10 +45,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="large", choices=["large", "medium", "tiny"])
+    ap.add_argument("--workload", default="large", choices=["large", "medium", "tiny", "slabs"])
+    ap.add_argument("--ranks", type=int, default=16, help="slabs workload: subdomains (4 slabs each)")
+    ap.add_argument("--m", type=int, default=None, help="override the number of moments (4, 6, 8)")
     ap.add_argument("--size", type=int, default=None, help="override the image size (square)")
     ap.add_argument("--grid", type=int, default=None, help="override cubes per axis (large workload)")
-    ap.add_argument("--cpu-pixels", type=int, default=16384, help="oracle sample size (0 = skip)")
+    ap.add_argument("--cpu-pixels", type=int, default=65536, help="oracle sample size (0 = skip)")
     ap.add_argument("--profile-steps", action="store_true", help="no oracle leg (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (scales the HBM byte counters of a profiler run)")
@@ -84,8 +86,13 @@ def main():
         sc = synth.scene_large(**kw)
     elif args.workload == "medium":
         sc = synth.scene_medium(**({"size": args.size} if args.size else {}))
+    elif args.workload == "slabs":
+        sc = synth.scene_slabs(n_ranks=args.ranks, size=args.size or 2560)
     else:
         sc = synth.scene_tiny()
+    if args.m:
+        sc.m = args.m
+        sc.bias = synth.default_bias(args.m)
     mesh = sc.mesh
     log("generated %s: %d tets, %d vertices, %d subdomains in %.1fs" % (
         sc.name, mesh.n_tets, mesh.n_vertices, mesh.n_sub, time.time() - t0))
@@ -130,6 +137,18 @@ def main():
         kern[key] /= args.steps
     samples_per_s = pieces_per_frame / (ms_per_step / 1e3)
 
+    # ---- segments per pixel (what a sort-last compositor would exchange) vs APC's fixed exchange
+    segs = ctx.segment_counts(r.view.height, r.view.width).reshape(2, -1)
+    met = segs[1]
+    cov = met > 0
+    n_cov = int(cov.sum().item())
+    seg_stats = {"covered_pixels": n_cov,
+                 "segments_mean": round(segs[0][cov].double().mean().item(), 4) if n_cov else 0.0,
+                 "segments_max": int(segs[0].max().item()),
+                 "subdomains_met_mean": round(met[cov].double().mean().item(), 4) if n_cov else 0.0,
+                 "apc_exchanged_per_pixel_mean": round(2.0 * met[cov].double().mean().item(), 4) if n_cov else 0.0,
+                 "apc_exchanged_upper_bound": 2 * mesh.n_sub}
+
     # ---- roofline of the dominant kernel
     H, W, m = r.view.height, r.view.width, sc.m
     S = mesh.n_sub
@@ -159,6 +178,7 @@ def main():
     # ---- sampled parity + CPU baseline (FP64 oracle on a bounded pixel sample)
     cpu = None
     parity = None
+    variants = None
     if args.cpu_pixels > 0 and not args.profile_steps:
         import oracle
         pix = np.sort(np.random.default_rng(11).choice(H * W, min(args.cpu_pixels, H * W), replace=False))
@@ -172,29 +192,38 @@ def main():
                    len(pix), W, H, ref["n_pieces"], cpu_s)}
         mom = r.moments.reshape(m + 1, -1)[:, torch.as_tensor(pix, device=dev)].double().cpu().numpy()
         rgba = r.rgba.reshape(-1, 4)[torch.as_tensor(pix, device=dev)].double().cpu().numpy()
-        b0 = ref["moments"][0]
-        cov = b0 > 0
-        den = np.maximum(b0[cov], 1e-3)
+        from oracle.parity import moment_parity
+        mp = moment_parity(sc, pix, mom, ref, tol=1e-5, floor=1e-3, threads=threads)
         d = rgba - ref["rgba"]
-        parity = {"pixels": int(len(pix)), "covered": int(cov.sum()),
-                  "moments_rel_max": float(np.max(np.abs(mom[:, cov] - ref["moments"][:, cov]) / den)),
-                  "background_exact": bool(np.all(mom[:, ~cov] == 0)),
+        parity = {"pixels": int(len(pix)), "covered": mp["covered"], "background_exact": mp["background_exact"],
+                  "moments_rel_max_forward": mp["forward_max"],
+                  "moments_backward_bar_pixels": mp["backward_bar_pixels"],
+                  "moments_outside_backward_band": mp["outside_backward_band"],
                   "rgba_max_abs": float(np.abs(d).max()), "rgba_rmse": float(math.sqrt(np.mean(d ** 2)))}
         log("parity %s" % parity)
+        # FP16 moment-image variant (ln b0, b_j / b0), run after the timed frames on the same sample
+        r.frame(moments_f16=True)
+        rgba16 = r.rgba.reshape(-1, 4)[torch.as_tensor(pix, device=dev)].double().cpu().numpy()
+        d16 = rgba16 - ref["rgba"]
+        variants = {"fp16_moments": {
+            "rgba_max_abs": float(np.abs(d16).max()), "rgba_rmse": float(math.sqrt(np.mean(d16 ** 2))),
+            "moment_image_bytes": int(r.moments_h.numel() * 2), "fp32_moment_image_bytes": int(r.moments.numel() * 4)}}
+        log("variants %s" % variants)
 
     out = {
         "metric": METRIC, "value": round(samples_per_s, 1), "unit": "samples/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "%s: %d tets (jittered Kuhn grid), %d Morton subdomains, %dx%d %s view, m=%d" % (
-            sc.name, mesh.n_tets, S, W, H, "perspective" if sc.view["projection"] else "orthographic", m),
+        "config": {"workload": "%s: %d tets (jittered Kuhn grid), %d %s subdomains, %dx%d %s view, m=%d" % (
+            sc.name, mesh.n_tets, S, "interleaved-slab (4 slabs each)" if args.workload == "slabs" else "Morton",
+            W, H, "perspective" if sc.view["projection"] else "orthographic", m),
             "global_batch": 1, "seq_len": None, "parallelism": "single GPU, all subdomains on device"},
         "frames_per_s": round(1e3 / ms_per_step, 4),
         "samples_per_frame": int(pieces_per_frame), "tet_steps_per_frame": int(steps_per_frame),
         "kernels_ms": {k: round(v, 3) for k, v in kern.items()},
         "frame_ms_each": [round(x, 2) for x in frame_ms],
-        "counters": cnt, "roofline": roofline, "cpu_baseline": cpu, "parity": parity,
+        "segments": seg_stats, "counters": cnt, "roofline": roofline, "cpu_baseline": cpu, "parity": parity, "variants": variants,
     }
     print(json.dumps(out), flush=True)
 

@@ -186,6 +186,19 @@ apc_status apc_sum_moments(apc_ctx ctx, const float* moments_per_sub, int32_t n_
                            int32_t width, const int32_t* subdomains, float* moments_global, void* stream);
 
 #define APC_FINALIZE 1u
+#define APC_MOMENTS_F16 2u
+
+/* Pack a global moment image for FP16 storage: plane 0 holds ln(b0) (-inf
+ * where b0 <= 0), planes j = 1..m hold b_j / b0 (in [-1, 1] since the warped
+ * depth is; 0 where b0 <= 0), each rounded to the nearest FP16 value.  Half
+ * the bytes of the FP32 image; apc_resolve_pass reads it with
+ * APC_MOMENTS_F16.  The rounding perturbs the moments by up to 2^-11
+ * relative, far beyond the FP32 bar: the resulting image error is a property
+ * of the variant, not a parity result.
+ *   moments_global  device [m+1][H][W] FP32 (from apc_sum_moments)
+ *   packed          device [m+1][H][W] FP16 (2-byte aligned), written */
+apc_status apc_pack_moments_f16(apc_ctx ctx, const float* moments_global, int32_t m, int32_t height, int32_t width,
+                                void* packed, void* stream);
 
 /* Stage two for a list of subdomains (Section 4.2, Alg. 1 second loop and
  * Alg. 3).  The same pieces as stage one are generated again (a second walk),
@@ -194,16 +207,18 @@ apc_status apc_sum_moments(apc_ctx ctx, const float* moments_per_sub, int32_t n_
  * opacity alpha_p = 1 - exp(-a) and colour c (transfer-function RGB) adds
  * T * alpha_p * (c, 1), where T = clamp(exp(-b0 * F)) and F is the moment
  * bound at the piece's warped depth computed from `moments_global`.
- *   moments_global  device [m+1][H][W] FP32 (from apc_sum_moments)
+ *   moments_global  device [m+1][H][W] FP32 (from apc_sum_moments), or with
+ *                   APC_MOMENTS_F16 the FP16 image of apc_pack_moments_f16
  *   rgba_out        device [H][W][4] FP32.  Without APC_FINALIZE: the additive
  *                   partial image (sum T*a*rgb, sum T*a) of the listed
  *                   subdomains, summed in the listed order.  With
  *                   APC_FINALIZE: the final image of those subdomains
  *                   (renormalised when mboit->renormalize, see apc_mboit).
  * The per-pixel Hankel/Cholesky set-up and the per-piece solve run in FP64
- * when m = 8 and in FP32 when m = 4 or 6; everything else runs in FP32. */
+ * when m = 6 or 8 and in FP32 when m = 4; everything else runs in FP32.
+ * flags: APC_FINALIZE, APC_MOMENTS_F16. */
 apc_status apc_resolve_pass(apc_ctx ctx, apc_mesh mesh, const apc_view* view, const apc_tf* tf,
-                            const apc_mboit* mboit, const float* moments_global, const int32_t* subdomains,
+                            const apc_mboit* mboit, const void* moments_global, const int32_t* subdomains,
                             int32_t n_sub, float* rgba_out, uint32_t flags, void* stream);
 
 /* Final image = sum of partial images (Section 4.2; the paper's
@@ -219,6 +234,17 @@ apc_status apc_sum_images(apc_ctx ctx, const float* partials, int32_t n_sub, int
 
 /* ------------------------------------------------------------------ diagnostics */
 
+/* Per-pixel segment statistics of the last apc_moments_pass on this context
+ * (its subdomains only).  A segment is a maximal interval of a pixel ray
+ * inside one subdomain that holds at least one piece: the number of colour
+ * fragments a sort-last compositor would have to exchange and order for that
+ * pixel (Section 6, segment counts), while APC exchanges one moment vector
+ * and one colour per subdomain that the ray meets.
+ *   out  device [2][H][W] int32: plane 0 segments, plane 1 subdomains with at
+ *        least one piece on the ray
+ * Errors: APC_E_ARG when no stage one has run or H, W differ from its view. */
+apc_status apc_segment_counts(apc_ctx ctx, int32_t* out, int32_t height, int32_t width, void* stream);
+
 typedef struct apc_counters {
   int64_t pieces;           /* samples (pieces) generated, both passes */
   int64_t tet_steps;        /* tets walked, both passes */
@@ -229,6 +255,9 @@ typedef struct apc_counters {
   int64_t entry_overflow;   /* per-ray entry lists refilled in extra rounds (results stay correct), plus
                                stage-two re-walks whose piece count differed from the count (never expected) */
   int64_t nonpd_pivots;     /* Cholesky pivots floored in the resolve pass */
+  int64_t table_samples;    /* samples whose moment-bound roots came from their pixel's gap table (m >= 6) */
+  int64_t table_fallback;   /* of those, samples that went back to the closed-form roots (~1e-4 expected) */
+  int64_t segments;         /* stage one: maximal ray intervals inside one subdomain with at least one piece */
 } apc_counters;
 
 /* Read (and with reset != 0, clear) the counters accumulated by this context.

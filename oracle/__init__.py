@@ -54,7 +54,7 @@ class OOut(C.Structure):
                 ("color", C.c_void_p), ("rgba", C.c_void_p), ("exact", C.c_void_p),
                 ("pieces_sub", C.c_void_p), ("n_pieces", C.c_int64), ("n_chords", C.c_int64),
                 ("n_nonpd", C.c_int64), ("n_rank1", C.c_int64), ("t_near", C.c_double),
-                ("t_far", C.c_double)]
+                ("t_far", C.c_double), ("segments", C.c_void_p)]
 
 
 def lib():
@@ -157,13 +157,14 @@ def depth_range(sc):
     return float(out[0]), float(out[1])
 
 
-def render(sc, pixels=None, pass2=True, exact=False, per_sub=False, threads=None) -> dict:
+def render(sc, pixels=None, pass2=True, exact=False, per_sub=False, threads=None, segments=False) -> dict:
     """Render a scene (see synth.Scene) in FP64.
 
     pixels: optional int64 array of pixel ids (row*W + col); default all pixels.
     Returns a dict with 'moments' [m+1, P], 'color' [P, 4] (additive sums),
     'rgba' [P, 4], optionally 'moments_sub' [S, m+1, P], 'color_sub' [S, P, 4],
-    'exact' [P, 4], plus counters.  P is the number of rendered pixels.
+    'exact' [P, 4], 'segments' [2, P] (segments per pixel ray, subdomains it
+    meets), plus counters.  P is the number of rendered pixels.
     """
     keep = []
     s = _scene_struct(sc, keep)
@@ -178,6 +179,8 @@ def render(sc, pixels=None, pass2=True, exact=False, per_sub=False, threads=None
     res = {"moments": np.zeros((M1, P)), "pieces_sub": np.zeros(S, dtype=np.int64)}
     if per_sub:
         res["moments_sub"] = np.zeros((S, M1, P))
+    if segments:
+        res["segments"] = np.zeros((2, P), dtype=np.int32)
     if pass2:
         res["color"] = np.zeros((P, 4))
         res["rgba"] = np.zeros((P, 4))
@@ -189,7 +192,8 @@ def render(sc, pixels=None, pass2=True, exact=False, per_sub=False, threads=None
     out = OOut(pixels=_ptr(pix), n_pixels=P, do_pass2=int(pass2), do_exact=int(exact), n_threads=threads,
                pad=0, moments_sub=_ptr(res.get("moments_sub")), moments=_ptr(res["moments"]),
                color_sub=_ptr(res.get("color_sub")), color=_ptr(res.get("color")), rgba=_ptr(res.get("rgba")),
-               exact=_ptr(res.get("exact")), pieces_sub=_ptr(res["pieces_sub"]))
+               exact=_ptr(res.get("exact")), pieces_sub=_ptr(res["pieces_sub"]),
+               segments=_ptr(res.get("segments")))
     rc = lib().oracle_render(C.byref(s), C.byref(out))
     if rc != 0:
         raise RuntimeError("oracle_render failed with code %d" % rc)

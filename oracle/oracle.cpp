@@ -76,6 +76,7 @@ struct OOut {
   int64_t* pieces_sub;     // [S] piece counts or null
   int64_t n_pieces, n_chords, n_nonpd, n_rank1;
   double t_near, t_far;
+  int32_t* segments;       // [2][P]: segments per pixel, subdomains met per pixel; or null
 };
 
 }  // extern "C"
@@ -545,6 +546,7 @@ int oracle_render(const OScene* sp, OOut* out) {
     std::vector<int64_t> my_pieces(S, 0);
     std::vector<double> local;
     std::vector<int64_t> tile_pix;
+    std::vector<std::vector<std::pair<double, double>>> ivl;  // chords per (local pixel, subdomain)
 #pragma omp for schedule(dynamic, 1)
     for (int64_t ai = 0; ai < int64_t(active.size()); ++ai) {
       int64_t tile = active[ai];
@@ -560,11 +562,13 @@ int oracle_render(const OScene* sp, OOut* out) {
         int64_t i = pid / W - ty * TILE, j = pid % W - tx * TILE;
         return (i * TILE + j) * S * M1;
       };
+      if (out->segments) ivl.assign(size_t(TILE * TILE) * S, {});
       for_each_chord(tile, [&](int64_t q, int64_t t, const V3* p, const double* sv, V3 o, V3 d, double t0,
                                double t1) {
         ++n_chords;
         int sub = s.tet_sub[t];
         double* bl = &local[lidx(q) + size_t(sub) * M1];
+        if (out->segments) ivl[lidx(q) / M1 + sub].push_back({t0, t1});
         pieces_of_chord(s, p, sv, o, d, t0, t1, t_near, [&](const Piece& pc) {
           double z = warp(pc.tm, t_near, t_far);
           double zp = 1.0;
@@ -575,6 +579,23 @@ int oracle_render(const OScene* sp, OOut* out) {
           ++my_pieces[sub];
         });
       });
+      // segments: a pixel ray's chords in one subdomain, sorted along the ray, form one segment per run of
+      // chords that meet end to start (neighbouring tets share the face); a gap starts a new segment
+      if (out->segments)
+        for (int64_t q : tile_pix) {
+          int32_t segs = 0, met = 0;
+          for (int sub = 0; sub < S; ++sub) {
+            auto& c = ivl[lidx(q) / M1 + sub];
+            if (c.empty()) continue;
+            std::sort(c.begin(), c.end());
+            ++met;
+            ++segs;
+            for (size_t k = 1; k < c.size(); ++k)
+              if (c[k].first > c[k - 1].second + 1e-9 * (1.0 + std::fabs(c[k - 1].second))) ++segs;
+          }
+          out->segments[q] = segs;
+          out->segments[P + q] = met;
+        }
       for (int64_t q : tile_pix) {
         const double* bl = &local[lidx(q)];
         for (int j = 0; j <= m; ++j) {

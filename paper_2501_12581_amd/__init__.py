@@ -19,11 +19,13 @@ LIB_PATH = os.path.join(_HERE, "libapc.so")
 APC_ORTHOGRAPHIC = 0
 APC_PERSPECTIVE = 1
 APC_FINALIZE = 1
+APC_MOMENTS_F16 = 2
 STATUS = {0: "APC_OK", 1: "APC_E_ARG", 2: "APC_E_MESH", 3: "APC_E_NOMEM", 4: "APC_E_DEVICE",
           5: "APC_E_NUMERIC", 6: "APC_E_UNSUPPORTED"}
 EXPORTS = ["apc_create", "apc_destroy", "apc_last_error", "apc_version", "apc_load_mesh", "apc_free_mesh",
            "apc_mesh_get_info", "apc_mesh_subdomain_info", "apc_moments_pass", "apc_sum_moments",
-           "apc_resolve_pass", "apc_sum_images", "apc_get_counters", "apc_get_timings"]
+           "apc_resolve_pass", "apc_sum_images", "apc_pack_moments_f16", "apc_segment_counts", "apc_get_counters",
+           "apc_get_timings"]
 
 
 class ApcError(RuntimeError):
@@ -67,7 +69,8 @@ class Timings(C.Structure):
 
 class Counters(C.Structure):
     _fields_ = [(n, C.c_int64) for n in ("pieces", "tet_steps", "entries", "bin_records", "walk_step_limit",
-                                         "exit_fallback", "entry_overflow", "nonpd_pivots")]
+                                         "exit_fallback", "entry_overflow", "nonpd_pivots",
+                                         "table_samples", "table_fallback", "segments")]
 
 
 _lib = None
@@ -105,6 +108,10 @@ def lib():
         L.apc_resolve_pass.restype = st
         L.apc_resolve_pass.argtypes = [vp, vp, C.POINTER(View), C.POINTER(TF), C.POINTER(Mboit), vp, vp,
                                        C.c_int32, vp, C.c_uint32, vp]
+        L.apc_pack_moments_f16.restype = st
+        L.apc_pack_moments_f16.argtypes = [vp, vp, C.c_int32, C.c_int32, C.c_int32, vp, vp]
+        L.apc_segment_counts.restype = st
+        L.apc_segment_counts.argtypes = [vp, vp, C.c_int32, C.c_int32, vp]
         L.apc_sum_images.restype = st
         L.apc_sum_images.argtypes = [vp, vp, C.c_int32, C.c_int32, C.c_int32, vp, vp, C.POINTER(Mboit), vp, vp]
         L.apc_get_counters.restype = st
@@ -247,13 +254,32 @@ class Context:
 
     def resolve_pass(self, mesh, view: View, tf: TF, mboit: Mboit, moments, subdomains, out, finalize=True,
                      stream=None):
+        """`moments`: the FP32 global image, or (torch.float16) the packed image of pack_moments_f16."""
         import torch
         ids, ptr = _ids(subdomains)
+        f16 = moments.dtype == torch.float16
+        flags = (APC_FINALIZE if finalize else 0) | (APC_MOMENTS_F16 if f16 else 0)
         self._ck(lib().apc_resolve_pass(self.handle, mesh.handle, C.byref(view), C.byref(tf), C.byref(mboit),
-                                        _dev_ptr(moments, torch.float32, (mboit.m + 1, view.height, view.width),
-                                                 "moments"), ptr, len(ids),
+                                        _dev_ptr(moments, torch.float16 if f16 else torch.float32,
+                                                 (mboit.m + 1, view.height, view.width), "moments"), ptr, len(ids),
                                         _dev_ptr(out, torch.float32, (view.height, view.width, 4), "rgba"),
-                                        APC_FINALIZE if finalize else 0, _stream(stream)))
+                                        flags, _stream(stream)))
+
+    def segment_counts(self, height, width, stream=None):
+        """[2][H][W] int32 of the last stage one: segments per pixel, subdomains met per pixel."""
+        import torch
+        out = torch.empty((2, height, width), dtype=torch.int32, device="cuda:%d" % self.device)
+        self._ck(lib().apc_segment_counts(self.handle, _dev_ptr(out, torch.int32, name="segments"), height, width,
+                                          _stream(stream)))
+        return out
+
+    def pack_moments_f16(self, moments, m, out, stream=None):
+        """FP16 form of a global moment image: ln b0 and b_j / b0 (include/apc.h)."""
+        import torch
+        m1, H, W = moments.shape
+        self._ck(lib().apc_pack_moments_f16(self.handle, _dev_ptr(moments, torch.float32, (m1, H, W), "moments"),
+                                            int(m), H, W, _dev_ptr(out, torch.float16, (m1, H, W), "packed"),
+                                            _stream(stream)))
 
     def sum_images(self, partials, subdomains, moments, mboit: Mboit, out, stream=None):
         import torch
@@ -297,11 +323,19 @@ class Renderer:
         self.moments = torch.empty((m + 1, H, W), dtype=torch.float32, device=device)
         self.rgba = torch.empty((H, W, 4), dtype=torch.float32, device=device)
 
-    def frame(self, subdomains=None, finalize=True, stream=None):
+    def frame(self, subdomains=None, finalize=True, stream=None, moments_f16=False):
+        """One frame; with moments_f16 the resolve reads the FP16-packed moment image (self.moments_h)."""
         subs = self.subs if subdomains is None else np.asarray(subdomains, np.int32)
         per_sub = self.per_sub if len(subs) == len(self.subs) else self.per_sub[:len(subs)]
         self.ctx.moments_pass(self.mesh, self.view, self.tf, self.scene.m, subs, per_sub, stream)
         self.ctx.sum_moments(per_sub, self.scene.m, subs, self.moments, stream)
-        self.ctx.resolve_pass(self.mesh, self.view, self.tf, self.mboit, self.moments, subs, self.rgba,
+        mom = self.moments
+        if moments_f16:
+            import torch
+            if getattr(self, "moments_h", None) is None:
+                self.moments_h = torch.empty(self.moments.shape, dtype=torch.float16, device=self.moments.device)
+            self.ctx.pack_moments_f16(self.moments, self.scene.m, self.moments_h, stream)
+            mom = self.moments_h
+        self.ctx.resolve_pass(self.mesh, self.view, self.tf, self.mboit, mom, subs, self.rgba,
                               finalize=finalize, stream=stream)
         return self.rgba

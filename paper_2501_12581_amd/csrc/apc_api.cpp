@@ -93,6 +93,9 @@ struct apc_ctx_s {
   bool ev_used[6] = {};
   // stage two: pieces per pixel (tile-major), 64-bit piece offsets, staged pieces
   DevBuf pcount, tile_tot, tile_off, poff, stage;
+  // per-pixel segment statistics of the last stage one: [2][seg_h][seg_w]
+  DevBuf segs;
+  int seg_h = 0, seg_w = 0;
   // the pieces per pixel in `pcount` belong to this (mesh, view, subdomain list)
   const void* pc_mesh = nullptr;
   apc_view pc_view;
@@ -375,7 +378,7 @@ apc_status apc_destroy(apc_ctx ctx) {
   (void)hipDeviceSynchronize();
   for (DevBuf* b : {&ctx->counts, &ctx->offsets, &ctx->cursors, &ctx->records, &ctx->scan_tmp, &ctx->slots,
                     &ctx->order, &ctx->counters, &ctx->pcount, &ctx->tile_tot, &ctx->tile_off, &ctx->poff,
-                    &ctx->stage})
+                    &ctx->stage, &ctx->segs})
     b->release();
   if (ctx->staging) (void)hipHostFree(ctx->staging);
   if (ctx->staging_done) (void)hipEventDestroy(ctx->staging_done);
@@ -620,9 +623,12 @@ apc_status apc_moments_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const
   MeshDev md;
   if ((st = build_bins(ctx, m, f, subs, n_sub, s, md)) != APC_OK) return st;
   HIPCHK(ctx->pcount.ensure(sizeof(int) * size_t(f.n_tiles) * 64));
+  HIPCHK(ctx->segs.ensure(sizeof(int) * 2 * size_t(view->width) * view->height));
+  ctx->seg_h = view->height;
+  ctx->seg_w = view->width;
   HIPCHK(ev_mark(ctx, EV_MOM, 0, s));
   HIPCHK(apc::launch_moments(mm, md, f, ctx->slots.as<SlotDev>(), ctx->offsets.as<int>(), ctx->counts.as<int>(),
-                             ctx->records.as<int>(), tf->rgba, out, ctx->pcount.as<int>(),
+                             ctx->records.as<int>(), tf->rgba, out, ctx->pcount.as<int>(), ctx->segs.as<int>(),
                              ctx->counters.as<unsigned long long>(), s));
   HIPCHK(ev_mark(ctx, EV_MOM, 1, s));
   set_piece_key(ctx, m, view, subs, n_sub);
@@ -668,7 +674,7 @@ static apc_status bound_params(const apc_mboit* mb, apc::BoundParams& bp, int fi
 }
 
 apc_status apc_resolve_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const apc_tf* tf, const apc_mboit* mb,
-                            const float* moments, const int32_t* subs, int32_t n_sub, float* rgba, uint32_t flags,
+                            const void* moments, const int32_t* subs, int32_t n_sub, float* rgba, uint32_t flags,
                             void* stream) {
   apc_status st = check_ctx(ctx);
   if (st != APC_OK) return st;
@@ -679,7 +685,10 @@ apc_status apc_resolve_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const
   if ((st = check_subdomains(m, subs, n_sub)) != APC_OK) return st;
   if (!moments || !rgba) return fail(APC_E_ARG, "buffer is NULL");
   if (reinterpret_cast<uintptr_t>(rgba) & 15) return fail(APC_E_ARG, "rgba_out must be 16-byte aligned");
-  if (flags & ~APC_FINALIZE) return fail(APC_E_ARG, "unknown flags 0x%x", flags);
+  if (flags & ~(APC_FINALIZE | APC_MOMENTS_F16)) return fail(APC_E_ARG, "unknown flags 0x%x", flags);
+  bp.moments_f16 = (flags & APC_MOMENTS_F16) ? 1 : 0;
+  if (bp.moments_f16 && (reinterpret_cast<uintptr_t>(moments) & 1))
+    return fail(APC_E_ARG, "packed FP16 moments must be 2-byte aligned");
   FrameDev f;
   if ((st = make_frame(m, view, tf, n_sub, max_tets_of(m, subs, n_sub), f)) != APC_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -751,6 +760,31 @@ apc_status apc_resolve_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const
   return APC_OK;
 }
 
+apc_status apc_segment_counts(apc_ctx ctx, int32_t* out, int32_t H, int32_t W, void* stream) {
+  apc_status st = check_ctx(ctx);
+  if (st != APC_OK) return st;
+  if (!out) return fail(APC_E_ARG, "out is NULL");
+  if (ctx->seg_h == 0) return fail(APC_E_ARG, "no stage one has run on this context");
+  if (H != ctx->seg_h || W != ctx->seg_w)
+    return fail(APC_E_ARG, "image is %dx%d, the last stage one was %dx%d", W, H, ctx->seg_w, ctx->seg_h);
+  HIPCHK(hipMemcpyAsync(out, ctx->segs.p, sizeof(int) * 2 * size_t(H) * W, hipMemcpyDeviceToDevice,
+                        static_cast<hipStream_t>(stream)));
+  return APC_OK;
+}
+
+apc_status apc_pack_moments_f16(apc_ctx ctx, const float* moments, int32_t mm, int32_t H, int32_t W, void* packed,
+                                void* stream) {
+  apc_status st = check_ctx(ctx);
+  if (st != APC_OK) return st;
+  if (!moments || !packed) return fail(APC_E_ARG, "buffer is NULL");
+  if (mm != 4 && mm != 6 && mm != 8) return fail(APC_E_ARG, "m = %d unsupported", mm);
+  if (H <= 0 || W <= 0) return fail(APC_E_ARG, "sizes out of range");
+  if (reinterpret_cast<uintptr_t>(packed) & 1) return fail(APC_E_ARG, "packed must be 2-byte aligned");
+  HIPCHK(apc::launch_pack_f16(moments, mm + 1, int64_t(H) * W, static_cast<_Float16*>(packed),
+                              static_cast<hipStream_t>(stream)));
+  return APC_OK;
+}
+
 apc_status apc_sum_images(apc_ctx ctx, const float* partials, int32_t n_sub, int32_t H, int32_t W,
                           const int32_t* subs, const float* moments, const apc_mboit* mb, float* rgba,
                           void* stream) {
@@ -792,6 +826,9 @@ apc_status apc_get_counters(apc_ctx ctx, apc_counters* out, int32_t reset) {
   out->exit_fallback = int64_t(c[apc::C_FALLBACK]);
   out->entry_overflow = int64_t(c[apc::C_OVERFLOW]);
   out->nonpd_pivots = int64_t(c[apc::C_NONPD]);
+  out->table_samples = int64_t(c[apc::C_TABLED]);
+  out->table_fallback = int64_t(c[apc::C_TABFB]);
+  out->segments = int64_t(c[apc::C_SEGMENTS]);
   if (reset) {
     HIPCHK(hipMemset(ctx->counters.p, 0, sizeof(c)));
     ctx->bin_records = 0;

@@ -50,10 +50,12 @@ struct BoundParams {
   double alpha, eta;
   double bias[8];
   int renormalize, finalize;
+  int moments_f16;  // the moment image is the packed FP16 form (ln b0, b_j / b0)
 };
 
 // Diagnostic counters (device memory, int64 each), in apc_counters order.
-enum { C_PIECES = 0, C_STEPS, C_ENTRIES, C_BINREC, C_STEPLIMIT, C_FALLBACK, C_OVERFLOW, C_NONPD, C_COUNT };
+enum { C_PIECES = 0, C_STEPS, C_ENTRIES, C_BINREC, C_STEPLIMIT, C_FALLBACK, C_OVERFLOW, C_NONPD, C_TABLED,
+       C_TABFB, C_SEGMENTS, C_COUNT };
 
 constexpr int TILE = 8;   // 8x8 pixels per tile, one wavefront
 constexpr int MAX_TF = 1024;
@@ -63,10 +65,11 @@ hipError_t launch_bin_count(const MeshDev& m, const FrameDev& f, const SlotDev* 
                             const int* bface, int* counts, hipStream_t s);
 hipError_t launch_bin_fill(const MeshDev& m, const FrameDev& f, const SlotDev* slots, int max_faces,
                            const int* bface, const int* offsets, int* cursors, int* records, hipStream_t s);
-// stage one; pcount (tile-major [n_tiles * 64], may be null) receives the pieces per pixel
+// stage one; pcount (tile-major [n_tiles * 64], may be null) receives the pieces per pixel, segs
+// ([2][H][W], may be null) the segments per pixel and the subdomains with pieces on each ray
 hipError_t launch_moments(int mm, const MeshDev& m, const FrameDev& f, const SlotDev* slots, const int* offsets,
                           const int* counts, const int* records, const float* tf_rgba, float* out, int* pcount,
-                          unsigned long long* counters, hipStream_t s);
+                          int* segs, unsigned long long* counters, hipStream_t s);
 // stage two, walk part: mode 0 counts pieces per pixel into pcount; mode 1 writes the
 // pieces of tiles [tile_lo, tile_hi) as (z, a, s) at rec + 3 * (poff[pixel] - base)
 hipError_t launch_stage(int mode, const MeshDev& m, const FrameDev& f, const SlotDev* slots, const int* offsets,
@@ -75,8 +78,10 @@ hipError_t launch_stage(int mode, const MeshDev& m, const FrameDev& f, const Slo
                         unsigned long long* counters, hipStream_t s);
 // stage two, evaluation part for tiles [tile_lo, tile_hi)
 hipError_t launch_eval(int mm, const FrameDev& f, int tile_lo, int tile_hi, const long long* poff, long long base,
-                       const float* rec, const float* tf_rgba, const float* moments, const BoundParams& bp,
+                       const float* rec, const float* tf_rgba, const void* moments, const BoundParams& bp,
                        float* rgba, unsigned long long* counters, hipStream_t s);
+// FP16 packing of a global moment image
+hipError_t launch_pack_f16(const float* in, int m1, int64_t pixels, _Float16* out, hipStream_t s);
 hipError_t launch_tile_sums(const int* pcount, int n_tiles, long long* tile_tot, hipStream_t s);
 hipError_t launch_piece_offsets(const int* pcount, const long long* tile_off, int n_tiles, long long* poff,
                                 hipStream_t s);

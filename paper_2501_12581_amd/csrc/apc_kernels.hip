@@ -185,7 +185,7 @@ __device__ __forceinline__ bool enter_face(const Ray& r, int id0, int id1, int i
 }
 
 struct LaneCount {
-  unsigned pieces, steps, entries, steplimit, fallback, overflow, nonpd;
+  unsigned pieces, steps, entries, steplimit, fallback, overflow, nonpd, tabled, tab_fallback, segments;
 };
 
 // Cut the chord [t0, t1] (scalar s0 -> s1) at the lattice t_near + k*step and
@@ -378,7 +378,9 @@ __device__ void walk_subdomain(const MeshDev& M, const FrameDev& f, const Ray& r
       Entry e;
       if (!enter_face(r, i0, i1, i2, M.vert[i0], M.vert[i1], M.vert[i2], e)) continue;  // cannot happen
       ++cnt.entries;
+      const unsigned before = sink.pieces;
       walk(M, f, r, t, fc, e, sl.tet_begin, sl.tet_end, sink, cnt);
+      cnt.segments += sink.pieces > before ? 1u : 0u;  // a maximal ray interval inside the subdomain
     }
     if (n > 0) {
       last_t = L.T(n - 1);
@@ -394,7 +396,7 @@ __device__ __forceinline__ unsigned wave_sum(unsigned v) {
 
 __device__ __forceinline__ void flush_one(unsigned v, unsigned long long* slot) {
   unsigned s = wave_sum(v);
-  if (threadIdx.x == 0 && s) atomicAdd(slot, (unsigned long long)s);
+  if ((threadIdx.x & (WAVE - 1)) == 0 && s) atomicAdd(slot, (unsigned long long)s);
 }
 
 __device__ __forceinline__ void flush_counts(const LaneCount& c, unsigned long long* ctr) {
@@ -405,6 +407,9 @@ __device__ __forceinline__ void flush_counts(const LaneCount& c, unsigned long l
   flush_one(c.fallback, ctr + C_FALLBACK);
   flush_one(c.overflow, ctr + C_OVERFLOW);
   flush_one(c.nonpd, ctr + C_NONPD);
+  flush_one(c.tabled, ctr + C_TABLED);
+  flush_one(c.tab_fallback, ctr + C_TABFB);
+  flush_one(c.segments, ctr + C_SEGMENTS);
 }
 
 // ------------------------------------------------------------------ stage one
@@ -447,7 +452,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_WALK_W
                                                   const int* __restrict__ offsets, const int* __restrict__ counts,
                                                   const int* __restrict__ records, const float* __restrict__ tf_rgba,
                                                   float* __restrict__ out, int* __restrict__ pcount,
-                                                  unsigned long long* ctr) {
+                                                  int* __restrict__ segs, unsigned long long* ctr) {
   extern __shared__ float4 dyn_lds[];
   float* tfa = reinterpret_cast<float*>(dyn_lds);  // [n_tf] alpha column
   __shared__ FaceL faces[CHUNK];
@@ -463,6 +468,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_WALK_W
   const size_t HW = size_t(f.W) * f.H, pix = size_t(py) * f.W + px;
   EntryList L{ent_t, ent_c, lane};
   LaneCount cnt = {};
+  int covering = 0;  // subdomains with at least one piece on this ray
   __syncthreads();
   for (int k = 0; k < f.n_slots; ++k) {
     const int bin = tile * f.n_slots + k;
@@ -478,6 +484,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_WALK_W
       walk_subdomain(M, f, r, valid, records + offsets[bin], n_rec, sl, faces, L, sink, cnt);
     }
     cnt.pieces += sink.pieces;
+    covering += sink.pieces > 0 ? 1 : 0;
     if (valid) {
       float* o = out + size_t(k) * M1 * HW + pix;
 #pragma unroll
@@ -485,6 +492,10 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_WALK_W
     }
   }
   if (pcount) pcount[size_t(tile) * WAVE + lane] = int(cnt.pieces);
+  if (segs && valid) {  // [2][H][W]: segments, covering subdomains
+    segs[pix] = int(cnt.segments);
+    segs[HW + pix] = covering;
+  }
   flush_counts(cnt, ctr);
 }
 
@@ -512,13 +523,32 @@ struct CountSink {
 
 // writes (z, a, s) of every piece of one pixel ray, in walk order; the walk
 // is the bit-identical repeat of the counting walk, and `cap` (the counted
-// pieces) bounds the writes regardless
+// pieces) bounds the writes regardless.  Pieces are gathered SB at a time in
+// registers and written as one contiguous burst: single 12-byte stores from
+// 64 lanes into 64 separate streams leave cache lines partly written long
+// enough to be written back several times.
+constexpr int SB = 8;
 struct StageSink {
   const FrameDev* f;
   const float* tfa;  // LDS alpha column
   float* out;        // this pixel's records: 3 floats each
-  unsigned pieces;
+  unsigned pieces;   // pieces generated so far
   unsigned cap;
+  unsigned flushed;  // pieces already written
+  float bz[SB], ba[SB], bs[SB];
+  __device__ void flush() {
+    const unsigned n = pieces - flushed;  // 0..SB
+    float* o = out + 3 * size_t(flushed);
+#pragma unroll
+    for (int i = 0; i < SB; ++i) {
+      if (unsigned(i) < n && flushed + i < cap) {
+        o[3 * i] = bz[i];
+        o[3 * i + 1] = ba[i];
+        o[3 * i + 2] = bs[i];
+      }
+    }
+    flushed = pieces;
+  }
   __device__ void chord(float t0, float t1, float s0, float s1) {
     cut_chord(*f, t0, t1, s0, s1, [&](float tm, float len, float s) {
       int i0;
@@ -526,13 +556,16 @@ struct StageSink {
       tf_coord(*f, s, i0, fr);
       float A = lerp_nc(tfa[i0], tfa[i0 + 1], fr);
       piece_az(*f, tm, len, A, a, z);
-      if (pieces < cap) {
-        float* o = out + 3 * size_t(pieces);
-        o[0] = z;
-        o[1] = a;
-        o[2] = s;
+      const unsigned slot = pieces - flushed;  // < SB
+#pragma unroll
+      for (int i = 0; i < SB; ++i) {  // register slot by select (no indexed arrays)
+        const bool here = unsigned(i) == slot;
+        bz[i] = here ? z : bz[i];
+        ba[i] = here ? a : ba[i];
+        bs[i] = here ? s : bs[i];
       }
       ++pieces;
+      if (pieces - flushed == SB) flush();
     });
   }
 };
@@ -573,16 +606,27 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_WALK_W
     pcount[slot] = int(sink.pieces);
   } else {
     const unsigned cap = unsigned(poff[slot + 1] - poff[slot]);
-    StageSink sink{&f, tfa, rec + 3 * (poff[slot] - base), 0u, cap};
+    StageSink sink{&f, tfa, rec + 3 * (poff[slot] - base), 0u, cap, 0u, {}, {}, {}};
     for (int k = 0; k < f.n_slots; ++k) {
       const int bin = tile * f.n_slots + k;
       const int n_rec = counts[bin];
       if (n_rec > 0) walk_subdomain(M, f, r, valid, records + offsets[bin], n_rec, slots[k], faces, L, sink, cnt);
     }
+    sink.flush();
     cnt.pieces += sink.pieces;
     if (sink.pieces != cap) ++cnt.overflow;  // a re-walk that disagrees with the count (never expected)
   }
   flush_counts(cnt, ctr);
+}
+
+__device__ __forceinline__ float wave_uniform(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double wave_uniform(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane(int(b & 0xffffffffll));
+  const int hi = __builtin_amdgcn_readfirstlane(int(b >> 32));
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
 }
 
 template <int N, class R>
@@ -606,31 +650,64 @@ __device__ __forceinline__ float wave_sum_f(float v) {
 // time: the 64 lanes evaluate that pixel's consecutive pieces (so they share
 // the pixel's factor and, with nearby depths, mostly the same branches), each
 // lane keeps a partial sum, and a fixed butterfly adds the partials, so the
-// result does not depend on scheduling.
-// Waves per SIMD the FP64 evaluation is compiled for (register budget 512 / n).
+// result does not depend on scheduling.  For n >= 3 a pixel with at least
+// TABLE_MIN_PIECES pieces first fills its gap table (one node per lane) and
+// its pieces take their roots from it.
+// Waves per SIMD the FP64 evaluation is compiled for (register budget 512 / n):
+// the closed-form root solver is out of line, which keeps n = 4 within 168.
 #ifndef APC_EVAL_WAVES
 #define APC_EVAL_WAVES 3
 #endif
+#ifndef APC_EVAL_WAVES_N4
+#define APC_EVAL_WAVES_N4 3
+#endif
+#ifndef APC_TABLE_MIN_PIECES
+#define APC_TABLE_MIN_PIECES 128
+#endif
+
+// Wavefronts per workgroup of the evaluation: they share one copy of the
+// transfer-function table in LDS (the per-pixel state is per wavefront).
+constexpr int EVAL_WPB = 4;
+
+// LDS writes of a wavefront visible to all its lanes (no workgroup barrier)
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 template <int N, class R>
-__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_EVAL_WAVES, 8))) void k_eval(
-    FrameDev f, int tile_lo, const long long* __restrict__ poff,
+__global__ __launch_bounds__(WAVE * EVAL_WPB) __attribute__((amdgpu_waves_per_eu(N >= 4 ? APC_EVAL_WAVES_N4 : APC_EVAL_WAVES, 8))) void k_eval(
+    FrameDev f, int tile_lo, int tile_hi, const long long* __restrict__ poff,
                                                long long base, const float* __restrict__ rec,
-                                               const float* __restrict__ tf_rgba, const float* __restrict__ moments,
+                                               const float* __restrict__ tf_rgba, const void* __restrict__ moments,
                                                BoundParams bp, float* __restrict__ rgba,
                                                unsigned long long* ctr) {
   extern __shared__ float4 dyn_lds[];
   float4* tf = dyn_lds;  // [n_tf] RGBA
   constexpr int M1 = 2 * N + 1;
   constexpr int NL = (N + 1) * (N + 2) / 2;
-  __shared__ R li_lds[NL * WAVE];  // per-pixel inverse Cholesky factors, lane-minor
-  __shared__ R b0_lds[WAVE], z1_lds[WAVE], xlo_lds[WAVE], xhi_lds[WAVE];
-  __shared__ int mode_lds[WAVE];
-  __shared__ int off_lds[WAVE + 1];  // piece offsets of the tile's pixels, relative to the tile
-  const int lane = threadIdx.x;
-  for (int i = lane; i < f.n_tf; i += WAVE)
+  constexpr bool TABLES = N >= 3;
+  constexpr int TAB_ENTRIES = TABLES ? apcm::Gaps<N>::NODES * apcm::Gaps<N>::NC : 1;
+  __shared__ R li_all[EVAL_WPB][NL * WAVE];  // per-pixel inverse Cholesky factors, lane-minor
+  __shared__ R zs_all[EVAL_WPB][N * WAVE];   // per-pixel sorted zeros of the degree-N orthonormal polynomial
+  __shared__ R b0_all[EVAL_WPB][WAVE], z1_all[EVAL_WPB][WAVE];
+  __shared__ R tab_all[EVAL_WPB][TAB_ENTRIES];  // gap table of the pixel being evaluated
+  __shared__ int mode_all[EVAL_WPB][WAVE];
+  __shared__ int off_all[EVAL_WPB][WAVE + 1];  // piece offsets of the tile's pixels, relative to the tile
+  for (int i = threadIdx.x; i < f.n_tf; i += WAVE * EVAL_WPB)
     tf[i] = make_float4(tf_rgba[4 * i], tf_rgba[4 * i + 1], tf_rgba[4 * i + 2], tf_rgba[4 * i + 3]);
-  const int tile = tile_lo + xcd_tile(blockIdx.x, gridDim.x);
+  __syncthreads();  // the only workgroup barrier: every later wait is within a wavefront
+  const int wv = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  const int tile = tile_lo + xcd_tile(blockIdx.x, gridDim.x) * EVAL_WPB + wv;
+  if (tile >= tile_hi) return;
+  R* li_lds = li_all[wv];
+  R* zs_lds = zs_all[wv];
+  R* b0_lds = b0_all[wv];
+  R* z1_lds = z1_all[wv];
+  R* tab_lds = tab_all[wv];
+  int* mode_lds = mode_all[wv];
+  int* off_lds = off_all[wv];
   const int tx = tile % f.tiles_x, ty = tile / f.tiles_x;
   const int px = tx * TILE + (lane & (TILE - 1)), py = ty * TILE + (lane / TILE);
   const bool valid = px < f.W && py < f.H;
@@ -645,20 +722,30 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_EVAL_W
   {
     LdsBound<N, R> bound;
     bound.Li.base = li_lds + lane;
-    R b[M1], bias[2 * N];
+    R b[M1], bias[2 * N], zs[N];
+    if (bp.moments_f16) {  // ln b0 and b_j / b0 in FP16
+      const _Float16* hm = static_cast<const _Float16*>(moments);
+      const float lb0 = valid ? float(hm[pix]) : -HUGE_VALF;
+      b0f = expf(lb0);  // exp(-inf) = 0: background
+      b[0] = R(b0f);
 #pragma unroll
-    for (int j = 0; j < M1; ++j) b[j] = valid ? R(moments[size_t(j) * HW + pix]) : R(0);
+      for (int j = 1; j < M1; ++j) b[j] = valid ? R(float(hm[size_t(j) * HW + pix])) * b[0] : R(0);
+    } else {
+      const float* fm = static_cast<const float*>(moments);
+#pragma unroll
+      for (int j = 0; j < M1; ++j) b[j] = valid ? R(fm[size_t(j) * HW + pix]) : R(0);
+      b0f = valid ? fm[pix] : 0.0f;
+    }
 #pragma unroll
     for (int j = 0; j < 2 * N; ++j) bias[j] = R(bp.bias[j]);
-    b0f = valid ? moments[pix] : 0.0f;
-    cnt.nonpd += bound.setup(b, R(bp.alpha), bias);
+    cnt.nonpd += bound.setup(b, R(bp.alpha), bias, zs);
     b0_lds[lane] = bound.b0;
     z1_lds[lane] = bound.z1;
-    xlo_lds[lane] = bound.xlo;
-    xhi_lds[lane] = bound.xhi;
+#pragma unroll
+    for (int i = 0; i < N; ++i) zs_lds[i * WAVE + lane] = zs[i];
     mode_lds[lane] = valid ? bound.mode : 0;
   }
-  __syncthreads();
+  wave_sync();
   const float* trec = rec + 3 * (tile_base - base);
   const R eta = R(bp.eta);
   float4 mine = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -666,17 +753,43 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_EVAL_W
     const int lo = off_lds[p], hi = off_lds[p + 1];
     const int md = mode_lds[p];
     if (lo == hi || md == 0) continue;
-    LdsBound<N, R> bound;
-    bound.Li.base = li_lds + p;
+    // the pixel's factor, uniform over the wavefront: held in scalar registers
+    apcm::Bound<N, R> bound;
+#pragma unroll
+    for (int k = 0; k < NL; ++k) bound.Li[k] = wave_uniform(li_lds[k * WAVE + p]);
     bound.b0 = b0_lds[p];
     bound.z1 = z1_lds[p];
-    bound.xlo = xlo_lds[p];
-    bound.xhi = xhi_lds[p];
     bound.mode = md;
+    const apcm::StridedStore<N, R, WAVE> zs{zs_lds + p};
+    bound.xlo = md == 2 ? zs[0] : R(1);
+    bound.xhi = md == 2 ? zs[N - 1] : R(-1);
+    // no zeros found (never expected for a positive definite factor): no shortcut, no table
+    if (md == 2 && !(zs[0] < zs[N - 1])) {
+      bound.xlo = R(1);
+      bound.xhi = R(-1);
+    }
+    bool use_table = false;
+    if constexpr (TABLES) {
+      use_table = md == 2 && bound.xlo < bound.xhi && hi - lo >= APC_TABLE_MIN_PIECES;
+      if (use_table) {
+        apcm::TablePtr<N, R> tab{tab_lds};
+        if (lane < apcm::Gaps<N>::NODES) bound.gap_node(zs, lane, tab);
+        wave_sync();
+      }
+    }
     float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
     for (int i = lo + lane; i < hi; i += WAVE) {
       const float z = trec[3 * i], a = trec[3 * i + 1], s = trec[3 * i + 2];
-      const R F = bound.frac_before(R(z), eta);
+      R F = R(0);
+      bool closed = true;
+      if constexpr (TABLES) {
+        if (use_table) {
+          closed = !bound.frac_before_tab(R(z), eta, zs, apcm::TablePtr<N, R>{tab_lds}, F);
+          ++cnt.tabled;
+          cnt.tab_fallback += closed ? 1u : 0u;
+        }
+      }
+      if (closed) F = bound.frac_before(R(z), eta);  // the one inlined copy of the closed forms
       float T = __expf(-float(bound.b0 * F));
       T = fminf(fmaxf(T, 0.0f), 1.0f);
       int i0;
@@ -689,6 +802,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_EVAL_W
       a2 += w * lerp_nc(t0.z, t1.z, fr);
       a3 += w;
     }
+    if (use_table) wave_sync();  // the next pixel's table overwrites this one
     a0 = wave_sum_f(a0);
     a1 = wave_sum_f(a1);
     a2 = wave_sum_f(a2);
@@ -843,6 +957,17 @@ __global__ void k_sum_moments(const float* __restrict__ in, int n_slots, const i
   }
 }
 
+// FP16 form of a global moment image: ln b0 (-inf on background) and b_j / b0
+__global__ void k_pack_f16(const float* __restrict__ in, int m1, int64_t pixels, _Float16* __restrict__ out) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= pixels) return;
+  const float b0 = in[i];
+  const bool bg = !(b0 > 0.0f);
+  out[i] = bg ? _Float16(-HUGE_VALF) : _Float16(logf(b0));
+  const float inv = bg ? 0.0f : 1.0f / b0;
+  for (int j = 1; j < m1; ++j) out[int64_t(j) * pixels + i] = _Float16(in[int64_t(j) * pixels + i] * inv);
+}
+
 __global__ void k_sum_images(const float4* __restrict__ in, int n_slots, const int* __restrict__ order,
                              int64_t pixels, const float* __restrict__ b0, BoundParams bp,
                              float4* __restrict__ out) {
@@ -981,18 +1106,18 @@ hipError_t launch_bin_fill(const MeshDev& m, const FrameDev& f, const SlotDev* s
 
 hipError_t launch_moments(int mm, const MeshDev& m, const FrameDev& f, const SlotDev* slots, const int* offsets,
                           const int* counts, const int* records, const float* tf_rgba, float* out, int* pcount,
-                          unsigned long long* counters, hipStream_t s) {
+                          int* segs, unsigned long long* counters, hipStream_t s) {
   const size_t lds = size_t(f.n_tf) * sizeof(float);
   const dim3 grid(f.n_tiles), block(WAVE);
   if (mm == 4)
     hipLaunchKernelGGL(k_moments<5>, grid, block, lds, s, m, f, slots, offsets, counts, records, tf_rgba, out,
-                       pcount, counters);
+                       pcount, segs, counters);
   else if (mm == 6)
     hipLaunchKernelGGL(k_moments<7>, grid, block, lds, s, m, f, slots, offsets, counts, records, tf_rgba, out,
-                       pcount, counters);
+                       pcount, segs, counters);
   else
     hipLaunchKernelGGL(k_moments<9>, grid, block, lds, s, m, f, slots, offsets, counts, records, tf_rgba, out,
-                       pcount, counters);
+                       pcount, segs, counters);
   return hipGetLastError();
 }
 
@@ -1008,20 +1133,26 @@ hipError_t launch_stage(int mode, const MeshDev& m, const FrameDev& f, const Slo
 }
 
 hipError_t launch_eval(int mm, const FrameDev& f, int tile_lo, int tile_hi, const long long* poff, long long base,
-                       const float* rec, const float* tf_rgba, const float* moments, const BoundParams& bp,
+                       const float* rec, const float* tf_rgba, const void* moments, const BoundParams& bp,
                        float* rgba, unsigned long long* counters, hipStream_t s) {
   if (tile_hi <= tile_lo) return hipSuccess;
   const size_t lds = size_t(f.n_tf) * sizeof(float4);
-  const dim3 grid(tile_hi - tile_lo), block(WAVE);
+  const dim3 grid((tile_hi - tile_lo + EVAL_WPB - 1) / EVAL_WPB), block(WAVE * EVAL_WPB);
   if (mm == 4)
-    hipLaunchKernelGGL((k_eval<2, float>), grid, block, lds, s, f, tile_lo, poff, base, rec, tf_rgba, moments, bp,
-                       rgba, counters);
+    hipLaunchKernelGGL((k_eval<2, float>), grid, block, lds, s, f, tile_lo, tile_hi, poff, base, rec, tf_rgba,
+                       moments, bp, rgba, counters);
   else if (mm == 6)
-    hipLaunchKernelGGL((k_eval<3, double>), grid, block, lds, s, f, tile_lo, poff, base, rec, tf_rgba, moments, bp,
-                       rgba, counters);
+    hipLaunchKernelGGL((k_eval<3, double>), grid, block, lds, s, f, tile_lo, tile_hi, poff, base, rec, tf_rgba,
+                       moments, bp, rgba, counters);
   else
-    hipLaunchKernelGGL((k_eval<4, double>), grid, block, lds, s, f, tile_lo, poff, base, rec, tf_rgba, moments, bp,
-                       rgba, counters);
+    hipLaunchKernelGGL((k_eval<4, double>), grid, block, lds, s, f, tile_lo, tile_hi, poff, base, rec, tf_rgba,
+                       moments, bp, rgba, counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_f16(const float* in, int m1, int64_t pixels, _Float16* out, hipStream_t s) {
+  if (pixels <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pack_f16, dim3(grid1(pixels, 256)), dim3(256), 0, s, in, m1, pixels, out);
   return hipGetLastError();
 }
 

@@ -35,6 +35,18 @@
 // degree is lowered instead of dividing by it.  Reciprocals use the hardware
 // estimate (plus two Newton-Raphson steps in FP64) on the device.
 //
+// Gap tables (n >= 3, FP64).  Written t for the zeros of the degree-n
+// orthonormal polynomial, the node sets vary smoothly with z inside each gap
+// (t_k-1, t_k), and at the gap's ends they become the other zeros plus one node
+// at infinity.  A pixel with many samples therefore solves the closed forms
+// only at 64 depths spread over its gaps (one per lane), stores a regularised
+// position of each root a sample in that gap will need, and gives each sample
+// its roots by quadratic interpolation in that table followed by four Newton
+// steps on the kernel polynomial.  A root that does not land in its gap, or
+// whose last Newton step is not small enough for the weight to be exact to
+// about 1e-12, sends the sample back to the closed forms, so the table changes
+// the cost of a sample but not its result beyond rounding.
+//
 // Precision R is float or double; n = m/2 is 2, 3 or 4.
 //
 // The functions are host+device so that host-side tests can exercise the code
@@ -45,8 +57,12 @@
 
 #if defined(__HIPCC__)
 #define APC_HD __host__ __device__ inline
+// out of line on the device: called once per pixel or for rare samples, and
+// inlined it would set the register budget of the loops around it
+#define APC_HD_COLD __host__ __device__ __attribute__((noinline))
 #else
 #define APC_HD inline
+#define APC_HD_COLD inline
 #endif
 
 namespace apcm {
@@ -101,6 +117,16 @@ APC_HD double m_rcp(double b) {
 #endif
 }
 
+// 1/b to about half precision (hardware estimate on the device): enough for
+// the steps of an iteration whose final step is checked
+APC_HD double m_rcp_est(double b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rcp(b);
+#else
+  return 1.0 / b;
+#endif
+}
+
 template <class R>
 APC_HD R m_max(R a, R b) {
   return a > b ? a : b;
@@ -121,41 +147,50 @@ APC_HD bool m_finite(R x) {
 // Real roots of c0 + c1 x + c2 x^2 (numerically stable form).  Returns count.
 template <class R>
 APC_HD int roots2(R c0, R c1, R c2, R* x) {
+  R x0 = R(0), x1 = R(0);
+  int nr = 2;
   if (c2 == R(0)) {
-    if (c1 == R(0)) return 0;
-    x[0] = -c0 * m_rcp(c1);
-    return 1;
+    nr = c1 == R(0) ? 0 : 1;
+    x0 = nr ? -c0 * m_rcp(c1) : R(0);
+  } else {
+    R disc = m_max(c1 * c1 - R(4) * c2 * c0, R(0));
+    R s = m_sqrt(disc);
+    R t = R(-0.5) * (c1 + (c1 < R(0) ? -s : s));
+    if (t != R(0)) {  // t = 0 only for c1 = c0 = 0: double root at 0
+      x0 = t * m_rcp(c2);
+      x1 = c0 * m_rcp(t);
+    }
   }
-  R disc = m_max(c1 * c1 - R(4) * c2 * c0, R(0));
-  R s = m_sqrt(disc);
-  R t = R(-0.5) * (c1 + (c1 < R(0) ? -s : s));
-  if (t == R(0)) {  // c1 = 0 and c0 = 0: double root at 0
-    x[0] = x[1] = R(0);
-    return 2;
-  }
-  x[0] = t * m_rcp(c2);
-  x[1] = c0 * m_rcp(t);
-  return 2;
+  x[0] = x0;
+  x[1] = x1;
+  return nr;
 }
 
 // Roots of the depressed cubic y^3 + p y + q, real parts when two are complex;
 // y[0] is the largest when all three are real.
 template <class R>
 APC_HD void depressed3(R p, R q, R* y) {
+  // both branches end in one store per element (stores sunk out of the
+  // branches would otherwise be merged into one with a run-time address)
   const R two_pi_3 = R(2.0943951023931954923);
+  R y0, y1, y2;
   if (p < R(0)) {
     R mm = m_sqrt(-p * R(1.0 / 3.0));
     R arg = m_clamp(-q * m_rcp(R(2) * mm * mm * mm), R(-1), R(1));
     R th = m_acos(arg) * R(1.0 / 3.0);
-    y[0] = R(2) * mm * m_cos(th);
-    y[1] = R(2) * mm * m_cos(th - two_pi_3);
-    y[2] = R(2) * mm * m_cos(th + two_pi_3);
+    y0 = R(2) * mm * m_cos(th);
+    y1 = R(2) * mm * m_cos(th - two_pi_3);
+    y2 = R(2) * mm * m_cos(th + two_pi_3);
   } else {
     R sd = m_sqrt(m_max(q * q * R(0.25) + p * p * p * R(1.0 / 27.0), R(0)));
     R u = m_cbrt(-q * R(0.5) + sd), w = m_cbrt(-q * R(0.5) - sd);
-    y[0] = u + w;
-    y[1] = y[2] = R(-0.5) * (u + w);
+    y0 = u + w;
+    y1 = R(-0.5) * (u + w);
+    y2 = y1;
   }
+  y[0] = y0;
+  y[1] = y1;
+  y[2] = y2;
 }
 
 // Roots of c0 + c1 x + c2 x^2 + c3 x^3 (c3 != 0); x[0] is the largest when all are real.
@@ -235,7 +270,7 @@ APC_HD int roots4(const R* c, R* x) {
 
 // Roots of the polynomial q[0..N]; returns how many finite ones (x[0..nr)).
 template <int N, class R>
-APC_HD int poly_roots(const R* q, R* x) {
+APC_HD_COLD int poly_roots(const R* q, R* x) {
   R cmax = R(0);
 #pragma unroll
   for (int j = 0; j <= N; ++j) cmax = m_max(cmax, m_abs(q[j]));
@@ -298,6 +333,45 @@ struct StridedStore {
   APC_HD R& operator[](int k) const { return base[k * STRIDE]; }
 };
 
+// Gap-table shape for n = N: NI nodes per gap, N - 1 gaps, at most NC roots
+// per sample (the side of z with fewer nodes).
+template <int N>
+struct Gaps {
+  static constexpr int NI = N >= 3 ? 64 / (N - 1) : 2;
+  static constexpr int NC = N / 2;
+  static constexpr int NODES = (N - 1) * NI;
+};
+
+// Storage of one pixel's gap table: a plain array (host tests) or a slice of
+// LDS shared by the wavefront (kernels).  Entry (node, c) at node * NC + c.
+template <int N, class R>
+struct TableArray {
+  R v[Gaps<N>::NODES * Gaps<N>::NC];
+  APC_HD R& at(int node, int c) { return v[node * Gaps<N>::NC + c]; }
+  APC_HD const R& at(int node, int c) const { return v[node * Gaps<N>::NC + c]; }
+};
+template <int N, class R>
+struct TablePtr {
+  R* base;
+  APC_HD R& at(int node, int c) const { return base[node * Gaps<N>::NC + c]; }
+};
+
+// a[i] for a run-time i: plain indexing for memory-backed accessors (the
+// zeros live in LDS on the device) ...
+template <int K, class A>
+APC_HD auto pick(const A& a, int i) -> decltype(a[0] + 0) {
+  return a[i];
+}
+// ... and, for a register array, a sum of masked terms, which the compiler
+// cannot turn back into an indexed (scratch) access; a[] must be finite.
+template <int K, class R>
+APC_HD R pick_reg(const R* a, int i) {
+  R r = R(0);
+#pragma unroll
+  for (int t = 0; t < K; ++t) r += R(i == t ? 1 : 0) * a[t];
+  return r;
+}
+
 // Per-pixel state of the bound.
 template <int N, class R, class Store = ArrayStore<(N + 1) * (N + 2) / 2, R>>
 struct Bound {
@@ -309,13 +383,19 @@ struct Bound {
   int mode;    // 0: no absorbance, 1: all absorbance at depth z1, 2: regular
 
   // b[0..2N] raw moments; bias[0..2N-1] = b*_1..b*_2N.  Returns the number of
-  // Cholesky pivots that had to be floored.
-  APC_HD int setup(const R* b, R alpha, const R* bias) {
+  // Cholesky pivots that had to be floored.  With zeros != null, the N zeros
+  // of the degree-N orthonormal polynomial are written there in ascending
+  // order (all equal to 0 when they could not be found; xlo > xhi then).
+  APC_HD int setup(const R* b, R alpha, const R* bias, R* zeros = nullptr) {
     mode = 0;
     b0 = b[0];
     z1 = R(0);
     xlo = R(1);
     xhi = R(-1);
+    if (zeros) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) zeros[i] = R(0);
+    }
     if (!(b0 > R(0))) return 0;
     R bp[2 * N + 1];
     bp[0] = R(1);
@@ -363,50 +443,37 @@ struct Bound {
         if (j == N) row[k] = -s * dj;
       }
     }
-    // its zeros lie inside (-1, 1); only the extreme two are kept
+    // its zeros lie inside (-1, 1)
     R xi[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) xi[i] = R(0);
     const int nz = poly_roots<N, R>(row, xi);
+    if (nz < N) return floored;  // cannot happen for a positive definite factor; no shortcut
+    sort_up(xi);
+    xlo = xi[0];
+    xhi = xi[N - 1];
+    if (zeros) {
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-      if (i < nz) {
-        xlo = m_min(xlo, xi[i]);
-        xhi = m_max(xhi, xi[i]);
-      }
-    }
-    if (nz < N) {  // cannot happen for a positive definite factor; disable the shortcut
-      xlo = R(1);
-      xhi = R(-1);
+      for (int i = 0; i < N; ++i) zeros[i] = xi[i];
     }
     return floored;
   }
 
-  // K(x, x) = |Li (1, x, ..., x^N)|^2
-  APC_HD R kernel_diag(R x) const {
-    R P[N + 1];
+  // ascending order of N values (odd-even transposition: fixed compare-exchanges)
+  APC_HD static void sort_up(R* x) {
 #pragma unroll
-    for (int k = 0; k <= N; ++k) P[k] = R(0);
-    R v = R(1);
+    for (int pass = 0; pass < N; ++pass) {
 #pragma unroll
-    for (int j = 0; j <= N; ++j) {
-#pragma unroll
-      for (int k = j; k <= N; ++k) P[k] += Li[k * (k + 1) / 2 + j] * v;
-      v *= x;
+      for (int i = pass & 1; i + 1 < N; i += 2) {
+        const R a = x[i], b = x[i + 1];
+        x[i] = m_min(a, b);
+        x[i + 1] = m_max(a, b);
+      }
     }
-    R K = R(0);
-#pragma unroll
-    for (int k = 0; k <= N; ++k) K += P[k] * P[k];
-    return K;
   }
 
-  // Fraction of the absorbance in front of warped depth z.
-  APC_HD R frac_before(R z, R eta) const {
-    if (mode == 1) {
-      if (m_abs(z1 - z) <= Num<R>::same_depth) return eta;
-      return z1 < z ? R(1) : R(0);
-    }
-    R P[N + 1];
+  // P = Li (1, z, ..., z^N): the orthonormal polynomials at z
+  APC_HD void values(R z, R* P) const {
 #pragma unroll
     for (int k = 0; k <= N; ++k) P[k] = R(0);
     R v = R(1);
@@ -416,13 +483,10 @@ struct Bound {
       for (int k = j; k <= N; ++k) P[k] += Li[k * (k + 1) / 2 + j] * v;
       v *= z;
     }
-    R K0 = R(0);
-#pragma unroll
-    for (int k = 0; k <= N; ++k) K0 += P[k] * P[k];
-    const R lam0 = m_rcp(K0);
-    if (z < xlo) return eta * lam0;                  // no node in front of z
-    if (z > xhi) return R(1) - (R(1) - eta) * lam0;  // every other node in front of z
-    R q[N + 1];
+  }
+
+  // q = Li^T P: power-basis coefficients of K(., z)
+  APC_HD void coeffs(const R* P, R* q) const {
 #pragma unroll
     for (int j = 0; j <= N; ++j) {
       R s = R(0);
@@ -430,6 +494,20 @@ struct Bound {
       for (int k = j; k <= N; ++k) s += Li[k * (k + 1) / 2 + j] * P[k];
       q[j] = s;
     }
+  }
+
+  // K(x, x) = |Li (1, x, ..., x^N)|^2
+  APC_HD R kernel_diag(R x) const {
+    R P[N + 1];
+    values(x, P);
+    R K = R(0);
+#pragma unroll
+    for (int k = 0; k <= N; ++k) K += P[k] * P[k];
+    return K;
+  }
+
+  // the bound from the closed-form roots of K(., z) = q
+  APC_HD R closed_tail(R z, R eta, R lam0, const R* q) const {
     R x[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) x[i] = R(0);
@@ -445,6 +523,154 @@ struct Bound {
     }
     // a node at infinity (nr < N) carries no weight, so the finite weights still sum to 1
     return use_below ? eta * lam0 + S : R(1) - (R(1) - eta) * lam0 - S;
+  }
+
+  // Fraction of the absorbance in front of warped depth z.
+  APC_HD R frac_before(R z, R eta) const {
+    if (mode == 1) {
+      if (m_abs(z1 - z) <= Num<R>::same_depth) return eta;
+      return z1 < z ? R(1) : R(0);
+    }
+    R P[N + 1];
+    values(z, P);
+    R K0 = R(0);
+#pragma unroll
+    for (int k = 0; k <= N; ++k) K0 += P[k] * P[k];
+    const R lam0 = m_rcp(K0);
+    if (z < xlo) return eta * lam0;                  // no node in front of z
+    if (z > xhi) return R(1) - (R(1) - eta) * lam0;  // every other node in front of z
+    R q[N + 1];
+    coeffs(P, q);
+    return closed_tail(z, eta, lam0, q);
+  }
+
+  // ---- gap tables (see the header comment); zs = the sorted zeros
+
+  // For z in gap k (zs[k-1] < z < zs[k], 1 <= k <= N-1) the nodes on the side
+  // of z with fewer of them: gaps 0..k-1 when 2k <= N, else gaps k+1..N.
+  APC_HD static int side_count(int k) { return 2 * k <= N ? k : N - k; }
+  APC_HD static int side_gap(int k, int c) { return 2 * k <= N ? c : k + 1 + c; }
+
+  // regularised position of root r of gap j, for z in gap (lo, hi) with
+  // sz = (z - lo) / (hi - z): finite and smooth in z up to both gap ends
+  template <class Z>
+  APC_HD static R to_table(const Z& zs, int j, R r, R sz) {
+    if (j == 0) return (r - zs[0]) * sz;
+    if (j == N) return (r - zs[N - 1]) / sz;
+    const R a = pick<N>(zs, j - 1), b = pick<N>(zs, j);
+    const R fr = (r - a) / (b - a);
+    return fr / ((R(1) - fr) * sz);
+  }
+  template <class Z>
+  APC_HD static R from_table(const Z& zs, int j, R v, R sz, R isz) {
+    if (j == 0) return zs[0] + v * isz;
+    if (j == N) return zs[N - 1] + v * sz;
+    const R a = pick<N>(zs, j - 1), b = pick<N>(zs, j);
+    const R e = v * sz;
+    return a + (b - a) * e * m_rcp(R(1) + e);
+  }
+
+  // Table entries of node l (0 <= l < NODES): gap k = l / NI + 1, depth
+  // zs[k-1] + (l % NI + 1/2) * (zs[k] - zs[k-1]) / NI.  Entries that cannot be
+  // formed are +inf, which makes every sample that would use them fall back.
+  template <class Z, class Tab>
+  APC_HD void gap_node(const Z& zs, int l, Tab& tab) const {
+    constexpr int NI = Gaps<N>::NI, NC = Gaps<N>::NC;
+    const int k = l / NI + 1, i = l - (k - 1) * NI;
+    const R lo = pick<N>(zs, k - 1), hi = pick<N>(zs, k);
+    const R z = lo + (R(i) + R(0.5)) * (hi - lo) / R(NI);
+    const R sz = (z - lo) / (hi - z);
+    R P[N + 1], q[N + 1], x[N];
+    values(z, P);
+    coeffs(P, q);
+#pragma unroll
+    for (int t = 0; t < N; ++t) x[t] = R(0);
+    const int nr = poly_roots<N, R>(q, x);
+    sort_up(x);
+    bool ok = nr == N && pick_reg<N>(x, k - 1) < z && pick_reg<N>(x, k) > z;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      R v = R(HUGE_VAL);
+      if (ok && c < side_count(k)) {
+        const int j = side_gap(k, c);
+        const R r = pick_reg<N>(x, j < k ? j : j - 1);
+        const bool in_gap = (j == 0 || r > pick<N>(zs, j - 1)) && (j == N || r < pick<N>(zs, j));
+        if (in_gap) v = to_table(zs, j, r, sz);
+      }
+      tab.at(l, c) = v;
+    }
+  }
+
+  // frac_before with the roots from the pixel's gap table.  Returns false
+  // (F unset) when a root did not converge: the caller then takes
+  // frac_before, the closed forms, for this sample.
+  template <class Z, class Tab>
+  APC_HD bool frac_before_tab(R z, R eta, const Z& zs, const Tab& tab, R& F) const {
+    constexpr int NI = Gaps<N>::NI, NC = Gaps<N>::NC;
+    R P[N + 1];
+    values(z, P);
+    R K0 = R(0);
+#pragma unroll
+    for (int k = 0; k <= N; ++k) K0 += P[k] * P[k];
+    const R lam0 = m_rcp(K0);
+    if (z < xlo) {
+      F = eta * lam0;
+      return true;
+    }
+    if (z > xhi) {
+      F = R(1) - (R(1) - eta) * lam0;
+      return true;
+    }
+    R q[N + 1];
+    coeffs(P, q);
+    int k = 0;
+#pragma unroll
+    for (int t = 0; t < N; ++t) k += zs[t] < z ? 1 : 0;
+    bool ok = k >= 1 && k <= N - 1;
+    const int kk = ok ? k : 1;
+    const R lo = pick<N>(zs, kk - 1), hi = pick<N>(zs, kk);
+    const R sz = (z - lo) * m_rcp(hi - z), isz = (hi - z) * m_rcp(z - lo);
+    const R u = (z - lo) * R(NI) * m_rcp(hi - lo) - R(0.5);
+    int i = int(floor(u + R(0.5)));
+    i = i < 1 ? 1 : (i > NI - 2 ? NI - 2 : i);
+    const R w = u - R(i);
+    const int node = (kk - 1) * NI + i;
+    const int nn = side_count(kk);
+    R S = R(0);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      if (c < nn) {
+        const int j = side_gap(kk, c);
+        const R v0 = tab.at(node - 1, c), v1 = tab.at(node, c), v2 = tab.at(node + 1, c);
+        const R v = v1 + R(0.5) * w * (v2 - v0) + R(0.5) * w * w * (v2 - R(2) * v1 + v0);
+        R x = from_table(zs, j, v, sz, isz);
+        R d = R(0);
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+          R p = q[N], dp = R(0);
+#pragma unroll
+          for (int t = N - 1; t >= 0; --t) {
+            dp = dp * x + p;
+            p = p * x + q[t];
+          }
+          d = p * m_rcp_est(dp);
+          x -= d;
+        }
+        const R blo = j == 0 ? -R(HUGE_VAL) : pick<N>(zs, j - 1);
+        const R bhi = j == N ? R(HUGE_VAL) : pick<N>(zs, j);
+        const R lam = m_rcp(kernel_diag(x));
+        const R ad = m_abs(d);
+        // converged: a small last step, or (outer gaps, where K grows away
+        // from the zeros) a weight too small for the step to matter
+        const R edge = j == 0 ? bhi : blo;
+        const bool conv = ad <= R(1e-7) * m_max(R(1), m_abs(x)) ||
+                          ((j == 0 || j == N) && lam * ad <= R(1e-12) * m_abs(x - edge));
+        ok = ok && x > blo && x < bhi && conv;
+        S += lam;
+      }
+    }
+    F = 2 * kk <= N ? eta * lam0 + S : R(1) - (R(1) - eta) * lam0 - S;
+    return ok;
   }
 };
 

@@ -302,3 +302,23 @@ def sandwich_scene(n: int = 24, n_sub: int = 3, slabs_per_sub: int = 2, m: int =
 def scene(name: str, **kw) -> Scene:
     return {"tiny": scene_tiny, "medium": scene_medium, "large": scene_large,
             "sandwich": sandwich_scene}[name](**kw)
+
+
+def scene_slabs(n_ranks: int = 16, slabs_per_rank: int = 4, cells_per_slab: int = 2, size: int = 1024,
+                m: int = 4, seed: int = 6, camera: int | None = None) -> Scene:
+    """Interleaved-slab stress volume: the cube is cut along z into
+    n_ranks * slabs_per_rank slabs of cells_per_slab cube layers, and slab q
+    belongs to subdomain q % n_ranks, so every subdomain's slabs are separated
+    by the other n_ranks - 1 subdomains' slabs.  Grid n^3 with
+    n = n_ranks * slabs_per_rank * cells_per_slab (16 ranks: 128^3 x 6 =
+    12,582,912 tets).  camera None: orthographic along +z (each ray crosses
+    every slab: n_ranks * slabs_per_rank segments); else a seeded perspective
+    camera on the radius-2 sphere."""
+    n = n_ranks * slabs_per_rank * cells_per_slab
+    sub = partition_slabs(n, n_ranks, slabs_per_rank)
+    mesh = grid_mesh(n, n_ranks, seed, n_gauss=8, jagged_seed=None, sub_of_cube=sub)
+    if camera is None:
+        view = ortho_view_z(size, size)
+    else:
+        view = perspective_view(sphere_eye(seed + 3 + 97 * camera), (0.5, 0.5, 0.5), size, size)
+    return _scene("slabs", mesh, view, n, m, tf_seed=seed + 11)

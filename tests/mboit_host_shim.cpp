@@ -43,3 +43,36 @@ extern "C" int shim_roots(const double* q, int n, int fp64, double* out) {
   }
   return k;
 }
+
+// The gap-table path for one moment vector: builds the pixel's table node by
+// node (as the lanes of a wavefront do), then evaluates n depths through the
+// table and through the closed forms.  Returns the number of table fallbacks,
+// or -1 when the pixel has no table (single-depth or no zeros).
+template <int N>
+static int run_table(const double* b, double alpha, const double* bias, double eta, const double* z, int n,
+                     double* f_tab, double* f_closed) {
+  double bb[2 * N + 1], bs[2 * N], zs[N];
+  for (int j = 0; j <= 2 * N; ++j) bb[j] = b[j];
+  for (int j = 0; j < 2 * N; ++j) bs[j] = bias[j];
+  apcm::Bound<N, double> B;
+  B.setup(bb, alpha, bs, zs);
+  if (B.mode != 2 || !(B.xlo < B.xhi)) return -1;
+  static apcm::TableArray<N, double> tab;
+  for (int l = 0; l < apcm::Gaps<N>::NODES; ++l) B.gap_node(zs, l, tab);
+  unsigned fb = 0;
+  for (int i = 0; i < n; ++i) {
+    f_closed[i] = B.frac_before(z[i], eta);
+    if (!B.frac_before_tab(z[i], eta, zs, tab, f_tab[i])) {
+      ++fb;
+      f_tab[i] = f_closed[i];
+    }
+  }
+  return int(fb);
+}
+
+extern "C" int shim_bound_table(const double* b, int m, double alpha, const double* bias, double eta,
+                                const double* z, int n, double* f_tab, double* f_closed) {
+  if (m == 6) return run_table<3>(b, alpha, bias, eta, z, n, f_tab, f_closed);
+  if (m == 8) return run_table<4>(b, alpha, bias, eta, z, n, f_tab, f_closed);
+  return -1;
+}

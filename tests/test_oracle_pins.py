@@ -534,3 +534,27 @@ def test_exact_compositing_of_two_constant_fragments():
     expect = [al[0] * rgba[0][c] + math.exp(-a[0]) * al[1] * rgba[1][c] for c in range(3)]
     assert np.allclose(r["exact"][0, :3], expect, atol=1e-14)
     assert abs(r["exact"][0, 3] - (-math.expm1(-(a[0] + a[1])))) <= 1e-14
+
+
+@pytest.mark.parametrize("n_ranks,slabs", [(4, 4), (3, 2), (5, 1)])
+def test_segment_counts_on_interleaved_slabs(n_ranks, slabs):
+    """Stress volume of the paper's weak-scaling test (Section 5, interleaved
+    slabs): a ray along z crosses every slab once and consecutive slabs belong
+    to different subdomains, so it has exactly n_ranks * slabs segments and
+    meets every subdomain."""
+    sc = synth.scene_slabs(n_ranks=n_ranks, slabs_per_rank=slabs, cells_per_slab=2, size=48)
+    r = oracle.render(sc, pass2=False, segments=True)
+    assert np.all(r["segments"][0] == n_ranks * slabs)
+    assert np.all(r["segments"][1] == n_ranks)
+
+
+def test_segment_counts_single_convex_subdomain():
+    """One subdomain filling the unit cube (convex): one segment on every ray
+    that meets it, none elsewhere."""
+    sc = synth.scene_tiny()
+    sc.mesh.tet_sub[:] = 0
+    sc.mesh.n_sub = 1
+    r = oracle.render(sc, pass2=False, segments=True)
+    covered = r["moments"][0] > 0
+    assert covered.all()
+    assert np.all(r["segments"][0] == 1) and np.all(r["segments"][1] == 1)
