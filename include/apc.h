@@ -232,6 +232,51 @@ apc_status apc_sum_images(apc_ctx ctx, const float* partials, int32_t n_sub, int
                           const int32_t* subdomains, const float* moments_global, const apc_mboit* mboit,
                           float* rgba_out, void* stream);
 
+/* ------------------------------------------------------------------ frame graphs */
+
+/* A whole frame (apc_moments_pass, apc_sum_moments, apc_resolve_pass for one
+ * mesh, camera, transfer-function buffer, moment parameters and subdomain
+ * list, into the given buffers) captured once in a HIP graph and replayed
+ * with one launch.  The graph owns a private workspace, sized by one eager
+ * frame that create runs first (so create is synchronous and its buffers
+ * hold that frame's results), and all its kernels take their sizes from the
+ * device: no host round trip, upload or allocation happens in a replay.  The
+ * camera, parameters and buffer addresses are fixed at capture; the contents
+ * of the transfer-function table and of the mesh may change between replays
+ * as long as the piece counts per pixel do not (the mesh's geometry, the
+ * camera and the lattice fix them; a staged piece beyond the capacity of the
+ * sizing frame is never written, and the entry_overflow counter says so).
+ * Calls that overlap on one graph race.
+ *   flags  APC_FINALIZE or 0, as for apc_resolve_pass
+ * Errors: APC_E_NOMEM when the frame's pieces do not fit one staging buffer. */
+typedef struct apc_graph_s* apc_graph;
+apc_status apc_frame_graph_create(apc_ctx ctx, apc_mesh mesh, const apc_view* view, const apc_tf* tf,
+                                  const apc_mboit* mboit, const int32_t* subdomains, int32_t n_sub,
+                                  float* moments_per_sub, float* moments_global, float* rgba_out, uint32_t flags,
+                                  apc_graph* out);
+apc_status apc_frame_graph_launch(apc_graph graph, void* stream);
+apc_status apc_frame_graph_destroy(apc_graph graph);
+
+/* ------------------------------------------------------------------ tile shape */
+
+/* Every pass maps one wavefront (64 lanes) to a tile of tile_width x
+ * (64 / tile_width) pixels; the shape changes which rays walk together, not
+ * any result (default 8 x 8).  The shape is a property of the context and
+ * applies to later passes; the resolve pass must run with the shape of the
+ * stage one whose piece counts it reuses (it counts again otherwise). */
+apc_status apc_set_tile_shape(apc_ctx ctx, int32_t tile_width);  /* 1, 2, 4, ..., 64; else APC_E_ARG */
+apc_status apc_get_tile_shape(apc_ctx ctx, int32_t* tile_width, int32_t* tile_height);
+
+/* Autotuner: times apc_moments_pass (one warm-up, then the best of `repeats`
+ * runs, HIP events on `stream`) for tile widths 2, 4, 8, 16, 32, sets the
+ * fastest on the context and returns it.  Synchronous.
+ *   moments_per_sub  device [n_sub][m+1][H][W] FP32 scratch (overwritten)
+ *   ms_per_width     host [7] or NULL: entry k = stage-one milliseconds for
+ *                    width 2^k, -1 where not timed */
+apc_status apc_autotune_tile_shape(apc_ctx ctx, apc_mesh mesh, const apc_view* view, const apc_tf* tf, int32_t m,
+                                   const int32_t* subdomains, int32_t n_sub, float* moments_per_sub, int32_t repeats,
+                                   int32_t* best_width, float* ms_per_width, void* stream);
+
 /* ------------------------------------------------------------------ diagnostics */
 
 /* Per-pixel segment statistics of the last apc_moments_pass on this context
@@ -257,12 +302,14 @@ typedef struct apc_counters {
   int64_t nonpd_pivots;     /* Cholesky pivots floored in the resolve pass */
   int64_t table_samples;    /* samples whose moment-bound roots came from their pixel's gap table (m >= 6) */
   int64_t table_fallback;   /* of those, samples that went back to the closed-form roots (~1e-4 expected) */
-  int64_t segments;         /* stage one: maximal ray intervals inside one subdomain with at least one piece */
+  int64_t segments;         /* maximal ray intervals inside one subdomain with at least one piece, both passes */
 } apc_counters;
 
 /* Read (and with reset != 0, clear) the counters accumulated by this context.
  * Synchronises the device. */
 apc_status apc_get_counters(apc_ctx ctx, apc_counters* out, int32_t reset);
+/* Counters of a frame graph's private workspace (see apc_frame_graph_create). */
+apc_status apc_frame_graph_counters(apc_graph graph, apc_counters* out, int32_t reset);
 
 /* Durations in milliseconds of the kernels of the most recent calls on this
  * context, measured with HIP events recorded on the caller's stream around

@@ -25,7 +25,8 @@ STATUS = {0: "APC_OK", 1: "APC_E_ARG", 2: "APC_E_MESH", 3: "APC_E_NOMEM", 4: "AP
 EXPORTS = ["apc_create", "apc_destroy", "apc_last_error", "apc_version", "apc_load_mesh", "apc_free_mesh",
            "apc_mesh_get_info", "apc_mesh_subdomain_info", "apc_moments_pass", "apc_sum_moments",
            "apc_resolve_pass", "apc_sum_images", "apc_pack_moments_f16", "apc_segment_counts", "apc_get_counters",
-           "apc_get_timings"]
+           "apc_get_timings", "apc_set_tile_shape", "apc_get_tile_shape", "apc_autotune_tile_shape",
+           "apc_frame_graph_create", "apc_frame_graph_launch", "apc_frame_graph_counters", "apc_frame_graph_destroy"]
 
 
 class ApcError(RuntimeError):
@@ -110,6 +111,22 @@ def lib():
                                        C.c_int32, vp, C.c_uint32, vp]
         L.apc_pack_moments_f16.restype = st
         L.apc_pack_moments_f16.argtypes = [vp, vp, C.c_int32, C.c_int32, C.c_int32, vp, vp]
+        L.apc_frame_graph_create.restype = st
+        L.apc_frame_graph_create.argtypes = [vp, vp, C.POINTER(View), C.POINTER(TF), C.POINTER(Mboit), vp, C.c_int32,
+                                             vp, vp, vp, C.c_uint32, C.POINTER(vp)]
+        L.apc_frame_graph_launch.restype = st
+        L.apc_frame_graph_launch.argtypes = [vp, vp]
+        L.apc_frame_graph_counters.restype = st
+        L.apc_frame_graph_counters.argtypes = [vp, C.POINTER(Counters), C.c_int32]
+        L.apc_frame_graph_destroy.restype = st
+        L.apc_frame_graph_destroy.argtypes = [vp]
+        L.apc_set_tile_shape.restype = st
+        L.apc_set_tile_shape.argtypes = [vp, C.c_int32]
+        L.apc_get_tile_shape.restype = st
+        L.apc_get_tile_shape.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.apc_autotune_tile_shape.restype = st
+        L.apc_autotune_tile_shape.argtypes = [vp, vp, C.POINTER(View), C.POINTER(TF), C.c_int32, vp, C.c_int32, vp,
+                                              C.c_int32, C.POINTER(C.c_int32), vp, vp]
         L.apc_segment_counts.restype = st
         L.apc_segment_counts.argtypes = [vp, vp, C.c_int32, C.c_int32, vp]
         L.apc_sum_images.restype = st
@@ -265,6 +282,26 @@ class Context:
                                         _dev_ptr(out, torch.float32, (view.height, view.width, 4), "rgba"),
                                         flags, _stream(stream)))
 
+    def set_tile_shape(self, tile_width):
+        self._ck(lib().apc_set_tile_shape(self.handle, int(tile_width)))
+
+    def tile_shape(self):
+        w, h = C.c_int32(0), C.c_int32(0)
+        self._ck(lib().apc_get_tile_shape(self.handle, C.byref(w), C.byref(h)))
+        return w.value, h.value
+
+    def autotune_tile_shape(self, mesh, view: View, tf: TF, m, subdomains, scratch, repeats=2, stream=None):
+        """Time stage one for tile widths 2..32, keep the fastest; returns (width, {width: ms})."""
+        import torch
+        ids, ptr = _ids(subdomains)
+        best = C.c_int32(0)
+        ms = np.full(7, -1.0, dtype=np.float32)
+        self._ck(lib().apc_autotune_tile_shape(self.handle, mesh.handle, C.byref(view), C.byref(tf), int(m), ptr,
+                                               len(ids), _dev_ptr(scratch, torch.float32, name="scratch"),
+                                               int(repeats), C.byref(best), C.c_void_p(ms.ctypes.data),
+                                               _stream(stream)))
+        return best.value, {1 << k: float(ms[k]) for k in range(7) if ms[k] >= 0}
+
     def segment_counts(self, height, width, stream=None):
         """[2][H][W] int32 of the last stage one: segments per pixel, subdomains met per pixel."""
         import torch
@@ -298,6 +335,45 @@ class Context:
         c = Counters()
         self._ck(lib().apc_get_counters(self.handle, C.byref(c), int(bool(reset))))
         return {n: getattr(c, n) for n, _ in Counters._fields_}
+
+
+class FrameGraph:
+    """A whole frame of a Renderer captured in a HIP graph (apc_frame_graph_create): one launch per frame,
+    writing the Renderer's moment and image buffers."""
+
+    def __init__(self, renderer, finalize=True):
+        import torch
+        r = renderer
+        ids, ptr = _ids(r.subs)
+        self._ids = ids
+        h = C.c_void_p()
+        _check(lib().apc_frame_graph_create(
+            r.ctx.handle, r.mesh.handle, C.byref(r.view), C.byref(r.tf), C.byref(r.mboit), ptr, len(ids),
+            _dev_ptr(r.per_sub, torch.float32, name="moments_per_sub"),
+            _dev_ptr(r.moments, torch.float32, name="moments"), _dev_ptr(r.rgba, torch.float32, name="rgba"),
+            APC_FINALIZE if finalize else 0, C.byref(h)), r.ctx.handle)
+        self.handle = h
+        self.renderer = r
+
+    def launch(self, stream=None):
+        _check(lib().apc_frame_graph_launch(self.handle, _stream(stream)))
+        return self.renderer.rgba
+
+    def counters(self, reset=False) -> dict:
+        c = Counters()
+        _check(lib().apc_frame_graph_counters(self.handle, C.byref(c), int(bool(reset))))
+        return {name: getattr(c, name) for name, _ in Counters._fields_}
+
+    def close(self):
+        if self.handle:
+            lib().apc_frame_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Renderer:

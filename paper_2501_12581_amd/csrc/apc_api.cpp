@@ -51,11 +51,16 @@ void parallel_for(int64_t n, Fn fn) {
   for (auto& t : th) t.join();
 }
 
+// Set while a frame is being captured into a HIP graph: workspace buffers
+// are sized by an eager frame beforehand and must not be reallocated.
+thread_local bool g_frozen = false;
+
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
   hipError_t ensure(size_t need) {
     if (need <= bytes) return hipSuccess;
+    if (g_frozen) return hipErrorOutOfMemory;
     if (p) {
       hipError_t e = hipFree(p);
       if (e != hipSuccess) return e;
@@ -93,19 +98,34 @@ struct apc_ctx_s {
   bool ev_used[6] = {};
   // stage two: pieces per pixel (tile-major), 64-bit piece offsets, staged pieces
   DevBuf pcount, tile_tot, tile_off, poff, stage;
+  // tile shape of both passes: (1 << tw_log2) x (64 >> tw_log2) pixels per wavefront
+  int tw_log2 = 3;
   // per-pixel segment statistics of the last stage one: [2][seg_h][seg_w]
   DevBuf segs;
   int seg_h = 0, seg_w = 0;
   // the pieces per pixel in `pcount` belong to this (mesh, view, subdomain list)
   const void* pc_mesh = nullptr;
   apc_view pc_view;
+  int pc_tw_log2 = -1;
   std::vector<int> pc_subs;
   bool pc_valid = false;
+  // capture mode (see apc_frame_graph_create): no host round trips, no uploads, no event marks
+  bool capturing = false;
+  long long last_pieces = 0;  // pieces of the last eager resolve pass
+  long long last_chunks = 0;  // and the number of staging chunks it took
+};
+
+struct apc_graph_s {
+  apc_ctx own = nullptr;         // private workspace, sized by the eager frame
+  hipStream_t cs = nullptr;      // capture stream
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
 };
 
 namespace {
 enum { EV_BIN = 0, EV_MOM, EV_SUM, EV_RES, EV_STG, EV_EVL, EV_COUNT };
 hipError_t ev_mark(apc_ctx ctx, int k, int which, hipStream_t s) {
+  if (ctx->capturing) return hipSuccess;
   if (which == 1) ctx->ev_used[k] = true;
   return hipEventRecord(ctx->ev[k][which], s);
 }
@@ -129,6 +149,8 @@ namespace {
 // buffer, ordered on `s`.  Waits for the previous staged copy first, so the
 // staging buffer is never overwritten while a copy still reads it.
 apc_status stage_upload(apc_ctx ctx, void* dst, const void* src, size_t bytes, hipStream_t s) {
+  // capture mode: the data is resident from the sizing frame, which had the same arguments
+  if (ctx->capturing) return APC_OK;
   if (ctx->staging_done) HIPCHK(hipEventSynchronize(ctx->staging_done));
   if (bytes > ctx->staging_bytes) {
     if (ctx->staging) HIPCHK(hipHostFree(ctx->staging));
@@ -187,13 +209,15 @@ apc_status check_view_tf(const apc_view* v, const apc_tf* tf) {
 
 // Frame constants shared by both passes.
 apc_status make_frame(const apc_mesh_s* m, const apc_view* v, const apc_tf* tf, int n_slots, int max_sub_tets,
-                      FrameDev& f) {
+                      int tw_log2, FrameDev& f) {
   std::memset(&f, 0, sizeof(f));
   f.W = v->width;
   f.H = v->height;
   f.proj = v->projection;
-  f.tiles_x = (v->width + apc::TILE - 1) / apc::TILE;
-  f.tiles_y = (v->height + apc::TILE - 1) / apc::TILE;
+  f.tw_log2 = tw_log2;
+  const int tw = 1 << tw_log2, th = 64 >> tw_log2;
+  f.tiles_x = (v->width + tw - 1) / tw;
+  f.tiles_y = (v->height + th - 1) / th;
   int64_t nt = int64_t(f.tiles_x) * f.tiles_y;
   if (nt * n_slots > (int64_t(1) << 31) - 1) return fail(APC_E_ARG, "too many tiles x subdomains");
   f.n_tiles = int(nt);
@@ -271,6 +295,9 @@ apc_status check_subdomains(const apc_mesh_s* m, const int32_t* subs, int32_t n_
   return APC_OK;
 }
 
+// records the bin buffer holds
+long long bin_cap(apc_ctx ctx) { return (long long)(ctx->records.bytes / sizeof(int)); }
+
 // Bin the boundary faces of the listed subdomains into (tile, slot) bins.
 apc_status build_bins(apc_ctx ctx, const apc_mesh_s* m, const FrameDev& f, const int32_t* subs, int32_t n_sub,
                       hipStream_t s, MeshDev& md) {
@@ -300,24 +327,28 @@ apc_status build_bins(apc_ctx ctx, const apc_mesh_s* m, const FrameDev& f, const
   HIPCHK(apc::launch_fill_i32(ctx->counts.as<int>(), 0, nb, s));
   HIPCHK(apc::launch_bin_count(md, f, ctx->slots.as<SlotDev>(), max_faces, m->bface, ctx->counts.as<int>(), s));
   HIPCHK(apc::launch_exclusive_scan(ctx->counts.as<int>(), ctx->offsets.as<int>(), nb, ctx->scan_tmp.as<int>(), s));
-  int tail[2];
-  HIPCHK(hipMemcpyAsync(&tail[0], ctx->offsets.as<int>() + nb - 1, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(&tail[1], ctx->counts.as<int>() + nb - 1, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  const int64_t total = int64_t(tail[0]) + tail[1];
-  if (total < 0 || total > (int64_t(1) << 31) - 1) return fail(APC_E_NUMERIC, "bin records overflow (%lld)", (long long)total);
-  HIPCHK(ctx->records.ensure(sizeof(int) * std::max<int64_t>(total, 1)));
+  if (!ctx->capturing) {  // size the record buffer from the counts
+    int tail[2];
+    HIPCHK(hipMemcpyAsync(&tail[0], ctx->offsets.as<int>() + nb - 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&tail[1], ctx->counts.as<int>() + nb - 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const int64_t total = int64_t(tail[0]) + tail[1];
+    if (total < 0 || total > (int64_t(1) << 31) - 1)
+      return fail(APC_E_NUMERIC, "bin records overflow (%lld)", (long long)total);
+    HIPCHK(ctx->records.ensure(sizeof(int) * std::max<int64_t>(total, 1)));
+    ctx->bin_records += total;
+  }
   HIPCHK(apc::launch_fill_i32(ctx->cursors.as<int>(), 0, nb, s));
   HIPCHK(apc::launch_bin_fill(md, f, ctx->slots.as<SlotDev>(), max_faces, m->bface, ctx->offsets.as<int>(),
-                              ctx->cursors.as<int>(), ctx->records.as<int>(), s));
+                              ctx->cursors.as<int>(), ctx->records.as<int>(), bin_cap(ctx), s));
   HIPCHK(ev_mark(ctx, EV_BIN, 1, s));
-  ctx->bin_records += total;
   return APC_OK;
 }
 
 void set_piece_key(apc_ctx ctx, const apc_mesh_s* m, const apc_view* v, const int32_t* subs, int32_t n_sub) {
   ctx->pc_mesh = m;
   ctx->pc_view = *v;
+  ctx->pc_tw_log2 = ctx->tw_log2;
   ctx->pc_subs.assign(subs, subs + n_sub);
   ctx->pc_valid = true;
 }
@@ -325,7 +356,8 @@ void set_piece_key(apc_ctx ctx, const apc_mesh_s* m, const apc_view* v, const in
 // Do the pieces per pixel in the context belong to this mesh, camera, lattice
 // and subdomain list?  (They do not depend on the transfer function or m.)
 bool piece_key_matches(apc_ctx ctx, const apc_mesh_s* m, const apc_view* v, const int32_t* subs, int32_t n_sub) {
-  return ctx->pc_valid && ctx->pc_mesh == m && std::memcmp(&ctx->pc_view, v, sizeof(apc_view)) == 0 &&
+  return ctx->pc_valid && ctx->pc_mesh == m && ctx->pc_tw_log2 == ctx->tw_log2 &&
+         std::memcmp(&ctx->pc_view, v, sizeof(apc_view)) == 0 &&
          ctx->pc_subs.size() == size_t(n_sub) && std::equal(ctx->pc_subs.begin(), ctx->pc_subs.end(), subs);
 }
 
@@ -618,7 +650,7 @@ apc_status apc_moments_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const
   if (!out) return fail(APC_E_ARG, "output is NULL");
   if (flags != 0) return fail(APC_E_ARG, "unknown flags 0x%x", flags);
   FrameDev f;
-  if ((st = make_frame(m, view, tf, n_sub, max_tets_of(m, subs, n_sub), f)) != APC_OK) return st;
+  if ((st = make_frame(m, view, tf, n_sub, max_tets_of(m, subs, n_sub), ctx->tw_log2, f)) != APC_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   MeshDev md;
   if ((st = build_bins(ctx, m, f, subs, n_sub, s, md)) != APC_OK) return st;
@@ -628,8 +660,8 @@ apc_status apc_moments_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const
   ctx->seg_w = view->width;
   HIPCHK(ev_mark(ctx, EV_MOM, 0, s));
   HIPCHK(apc::launch_moments(mm, md, f, ctx->slots.as<SlotDev>(), ctx->offsets.as<int>(), ctx->counts.as<int>(),
-                             ctx->records.as<int>(), tf->rgba, out, ctx->pcount.as<int>(), ctx->segs.as<int>(),
-                             ctx->counters.as<unsigned long long>(), s));
+                             ctx->records.as<int>(), bin_cap(ctx), tf->rgba, out, ctx->pcount.as<int>(),
+                             ctx->segs.as<int>(), ctx->counters.as<unsigned long long>(), s));
   HIPCHK(ev_mark(ctx, EV_MOM, 1, s));
   set_piece_key(ctx, m, view, subs, n_sub);
   return APC_OK;
@@ -690,7 +722,7 @@ apc_status apc_resolve_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const
   if (bp.moments_f16 && (reinterpret_cast<uintptr_t>(moments) & 1))
     return fail(APC_E_ARG, "packed FP16 moments must be 2-byte aligned");
   FrameDev f;
-  if ((st = make_frame(m, view, tf, n_sub, max_tets_of(m, subs, n_sub), f)) != APC_OK) return st;
+  if ((st = make_frame(m, view, tf, n_sub, max_tets_of(m, subs, n_sub), ctx->tw_log2, f)) != APC_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   MeshDev md;
   if ((st = build_bins(ctx, m, f, subs, n_sub, s, md)) != APC_OK) return st;
@@ -699,17 +731,32 @@ apc_status apc_resolve_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const
   HIPCHK(ev_mark(ctx, EV_RES, 0, s));
   // pieces per pixel: from stage one when it ran on the same geometry, else counted by a walk
   if (!piece_key_matches(ctx, m, view, subs, n_sub)) {
+    if (ctx->capturing) return fail(APC_E_ARG, "capture: stage one of the same view must precede the resolve");
     ctx->pc_valid = false;
     HIPCHK(ctx->pcount.ensure(sizeof(int) * size_t(nt) * 64));
     HIPCHK(apc::launch_stage(0, md, f, ctx->slots.as<SlotDev>(), ctx->offsets.as<int>(), ctx->counts.as<int>(),
-                             ctx->records.as<int>(), tf->rgba, 0, nt, ctx->pcount.as<int>(), nullptr, 0, nullptr,
-                             ctr, s));
+                             ctx->records.as<int>(), bin_cap(ctx), tf->rgba, 0, nt, ctx->pcount.as<int>(), nullptr, 0,
+                             0, nullptr, ctr, s));
     set_piece_key(ctx, m, view, subs, n_sub);
   }
   HIPCHK(ctx->tile_tot.ensure(sizeof(long long) * nt));
   HIPCHK(ctx->tile_off.ensure(sizeof(long long) * nt));
   HIPCHK(ctx->poff.ensure(sizeof(long long) * (size_t(nt) * 64 + 1)));
   HIPCHK(apc::launch_tile_sums(ctx->pcount.as<int>(), nt, ctx->tile_tot.as<long long>(), s));
+  if (ctx->capturing) {
+    // one chunk, offsets on the device; the staging buffer was sized by the eager frame and the
+    // kernels leave anything beyond it unwritten (counted as overflow)
+    const long long cap_pieces = (long long)(ctx->stage.bytes / (3 * sizeof(float)));
+    HIPCHK(apc::launch_tile_offsets(ctx->tile_tot.as<long long>(), nt, ctx->tile_off.as<long long>(), s));
+    HIPCHK(apc::launch_piece_offsets(ctx->pcount.as<int>(), ctx->tile_off.as<long long>(), nt,
+                                     ctx->poff.as<long long>(), s));
+    HIPCHK(apc::launch_stage(1, md, f, ctx->slots.as<SlotDev>(), ctx->offsets.as<int>(), ctx->counts.as<int>(),
+                             ctx->records.as<int>(), bin_cap(ctx), tf->rgba, 0, nt, nullptr,
+                             ctx->poff.as<long long>(), 0, cap_pieces, ctx->stage.as<float>(), ctr, s));
+    HIPCHK(apc::launch_eval(mb->m, f, 0, nt, ctx->poff.as<long long>(), 0, cap_pieces, ctx->stage.as<float>(),
+                            tf->rgba, moments, bp, rgba, ctr, s));
+    return APC_OK;
+  }
   std::vector<long long> tot(nt), toff(nt);
   HIPCHK(hipMemcpyAsync(tot.data(), ctx->tile_tot.p, sizeof(long long) * nt, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -736,6 +783,8 @@ apc_status apc_resolve_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const
     if (e != hipSuccess) return fail(APC_E_NOMEM, "staging %zu bytes: %s", need, hipGetErrorString(e));
   }
   const long long cap_pieces = (long long)(ctx->stage.bytes / rec_bytes);
+  ctx->last_pieces = total;
+  ctx->last_chunks = 0;
   bool first = true;
   for (int t0 = 0; t0 < nt;) {
     int t1 = t0;
@@ -744,20 +793,166 @@ apc_status apc_resolve_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const
     if (t1 == t0) return fail(APC_E_NOMEM, "tile %d does not fit in the staging buffer", t0);
     if (first) HIPCHK(ev_mark(ctx, EV_STG, 0, s));
     HIPCHK(apc::launch_stage(1, md, f, ctx->slots.as<SlotDev>(), ctx->offsets.as<int>(), ctx->counts.as<int>(),
-                             ctx->records.as<int>(), tf->rgba, t0, t1, nullptr, ctx->poff.as<long long>(), toff[t0],
-                             ctx->stage.as<float>(), ctr, s));
+                             ctx->records.as<int>(), bin_cap(ctx), tf->rgba, t0, t1, nullptr,
+                             ctx->poff.as<long long>(), toff[t0], cap_pieces, ctx->stage.as<float>(), ctr, s));
     if (first) {
       HIPCHK(ev_mark(ctx, EV_STG, 1, s));
       HIPCHK(ev_mark(ctx, EV_EVL, 0, s));
     }
-    HIPCHK(apc::launch_eval(mb->m, f, t0, t1, ctx->poff.as<long long>(), toff[t0], ctx->stage.as<float>(), tf->rgba,
-                            moments, bp, rgba, ctr, s));
+    HIPCHK(apc::launch_eval(mb->m, f, t0, t1, ctx->poff.as<long long>(), toff[t0], cap_pieces,
+                            ctx->stage.as<float>(), tf->rgba, moments, bp, rgba, ctr, s));
     if (first) HIPCHK(ev_mark(ctx, EV_EVL, 1, s));
     first = false;
     t0 = t1;
+    ++ctx->last_chunks;
   }
   HIPCHK(ev_mark(ctx, EV_RES, 1, s));
   return APC_OK;
+}
+
+apc_status apc_frame_graph_destroy(apc_graph g) {
+  if (!g) return APC_OK;
+  if (g->own) (void)hipSetDevice(g->own->device);
+  if (g->cs) (void)hipStreamSynchronize(g->cs);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->cs) (void)hipStreamDestroy(g->cs);
+  if (g->own) (void)apc_destroy(g->own);
+  delete g;
+  return APC_OK;
+}
+
+apc_status apc_frame_graph_create(apc_ctx ctx, apc_mesh m, const apc_view* view, const apc_tf* tf,
+                                  const apc_mboit* mb, const int32_t* subs, int32_t n_sub, float* moments_per_sub,
+                                  float* moments_global, float* rgba_out, uint32_t flags, apc_graph* out) {
+  apc_status st = check_ctx(ctx);
+  if (st != APC_OK) return st;
+  if (!out) return fail(APC_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (!mb) return fail(APC_E_ARG, "mboit is NULL");
+  if (flags & ~APC_FINALIZE) return fail(APC_E_ARG, "unknown flags 0x%x", flags);
+  apc_graph g = new (std::nothrow) apc_graph_s();
+  if (!g) return fail(APC_E_NOMEM, "host allocation failed");
+  if ((st = apc_create(ctx->device, &g->own)) != APC_OK) {
+    delete g;
+    return st;
+  }
+  g->own->tw_log2 = ctx->tw_log2;
+  if (hipStreamCreateWithFlags(&g->cs, hipStreamNonBlocking) != hipSuccess) {
+    apc_frame_graph_destroy(g);
+    return fail(APC_E_DEVICE, "stream creation failed");
+  }
+  apc_ctx w = g->own;
+  auto frame = [&]() -> apc_status {
+    apc_status r = apc_moments_pass(w, m, view, tf, mb->m, subs, n_sub, moments_per_sub, 0, g->cs);
+    if (r == APC_OK) r = apc_sum_moments(w, moments_per_sub, n_sub, mb->m, view->height, view->width, subs,
+                                         moments_global, g->cs);
+    if (r == APC_OK) r = apc_resolve_pass(w, m, view, tf, mb, moments_global, subs, n_sub, rgba_out, flags, g->cs);
+    return r;
+  };
+  // 1) an eager frame sizes every workspace buffer
+  st = frame();
+  if (st == APC_OK && hipStreamSynchronize(g->cs) != hipSuccess) st = fail(APC_E_DEVICE, "sizing frame failed");
+  if (st == APC_OK && w->last_chunks > 1)
+    st = fail(APC_E_NOMEM, "the frame's %lld pieces do not fit one staging buffer", (long long)w->last_pieces);
+  // 2) the same frame captured: kernels only (no uploads, host reads, event records or allocations)
+  if (st == APC_OK) {
+    if (hipStreamBeginCapture(g->cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      st = fail(APC_E_DEVICE, "stream capture could not start");
+    } else {
+      w->capturing = true;
+      g_frozen = true;
+      st = frame();
+      g_frozen = false;
+      w->capturing = false;
+      hipGraph_t gr = nullptr;
+      hipError_t e = hipStreamEndCapture(g->cs, &gr);
+      g->graph = gr;
+      if (st == APC_OK && (e != hipSuccess || !gr)) st = fail(APC_E_DEVICE, "capture failed: %s", hipGetErrorString(e));
+    }
+  }
+  if (st == APC_OK && hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess)
+    st = fail(APC_E_DEVICE, "graph instantiation failed");
+  if (st != APC_OK) {
+    apc_frame_graph_destroy(g);
+    return st;
+  }
+  *out = g;
+  return APC_OK;
+}
+
+apc_status apc_frame_graph_launch(apc_graph g, void* stream) {
+  if (!g || !g->exec) return fail(APC_E_ARG, "graph is NULL");
+  HIPCHK(hipSetDevice(g->own->device));
+  HIPCHK(hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)));
+  return APC_OK;
+}
+
+apc_status apc_frame_graph_counters(apc_graph g, apc_counters* out, int32_t reset) {
+  if (!g) return fail(APC_E_ARG, "graph is NULL");
+  return apc_get_counters(g->own, out, reset);
+}
+
+apc_status apc_set_tile_shape(apc_ctx ctx, int32_t tile_width) {
+  apc_status st = check_ctx(ctx);
+  if (st != APC_OK) return st;
+  int lg = -1;
+  for (int k = 0; k <= 6; ++k)
+    if (tile_width == (1 << k)) lg = k;
+  if (lg < 0) return fail(APC_E_ARG, "tile width %d is not a power of two in 1..64", tile_width);
+  ctx->tw_log2 = lg;
+  return APC_OK;
+}
+
+apc_status apc_get_tile_shape(apc_ctx ctx, int32_t* tile_width, int32_t* tile_height) {
+  apc_status st = check_ctx(ctx);
+  if (st != APC_OK) return st;
+  if (tile_width) *tile_width = 1 << ctx->tw_log2;
+  if (tile_height) *tile_height = 64 >> ctx->tw_log2;
+  return APC_OK;
+}
+
+apc_status apc_autotune_tile_shape(apc_ctx ctx, apc_mesh m, const apc_view* view, const apc_tf* tf, int32_t mm,
+                                   const int32_t* subs, int32_t n_sub, float* moments_per_sub, int32_t repeats,
+                                   int32_t* best_width, float* ms_per_width, void* stream) {
+  apc_status st = check_ctx(ctx);
+  if (st != APC_OK) return st;
+  if (repeats < 1 || repeats > 100) return fail(APC_E_ARG, "repeats must be in 1..100");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  const int old = ctx->tw_log2;
+  int best = old;
+  float best_ms = 0.0f;
+  for (int k = 0; k <= 6; ++k)
+    if (ms_per_width) ms_per_width[k] = -1.0f;
+  apc_status res = APC_OK;
+  for (int lg = 1; lg <= 5 && res == APC_OK; ++lg) {  // 2x32 .. 32x2
+    ctx->tw_log2 = lg;
+    float t_min = 0.0f;
+    for (int rep = 0; rep <= repeats && res == APC_OK; ++rep) {  // the first run is a warm-up
+      if (hipEventRecord(e0, s) != hipSuccess) res = fail(APC_E_DEVICE, "event record failed");
+      if (res == APC_OK) res = apc_moments_pass(ctx, m, view, tf, mm, subs, n_sub, moments_per_sub, 0, stream);
+      if (res == APC_OK && hipEventRecord(e1, s) != hipSuccess) res = fail(APC_E_DEVICE, "event record failed");
+      float ms = 0.0f;
+      if (res == APC_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        res = fail(APC_E_DEVICE, "event timing failed");
+      if (res == APC_OK && rep > 0) t_min = (rep == 1) ? ms : std::min(t_min, ms);
+    }
+    if (res != APC_OK) break;
+    if (ms_per_width) ms_per_width[lg] = t_min;
+    if (lg == 1 || t_min < best_ms) {
+      best_ms = t_min;
+      best = lg;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  ctx->tw_log2 = res == APC_OK ? best : old;
+  ctx->pc_valid = false;  // the piece counts of the last run belong to another tile shape
+  if (res == APC_OK && best_width) *best_width = 1 << best;
+  return res;
 }
 
 apc_status apc_segment_counts(apc_ctx ctx, int32_t* out, int32_t H, int32_t W, void* stream) {

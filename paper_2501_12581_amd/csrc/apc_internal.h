@@ -28,6 +28,7 @@ struct SlotDev {
 // function parameters.
 struct FrameDev {
   int W, H, proj, tiles_x, tiles_y, n_tiles, n_slots, n_tf;
+  int tw_log2;          // a tile (one wavefront) is (1 << tw_log2) x (64 >> tw_log2) pixels
   float ex, ey, ez;     // eye (perspective origin / orthographic image-plane origin)
   float dx, dy, dz;     // forward direction (unit for orthographic)
   float rx, ry, rz;     // right
@@ -57,29 +58,33 @@ struct BoundParams {
 enum { C_PIECES = 0, C_STEPS, C_ENTRIES, C_BINREC, C_STEPLIMIT, C_FALLBACK, C_OVERFLOW, C_NONPD, C_TABLED,
        C_TABFB, C_SEGMENTS, C_COUNT };
 
-constexpr int TILE = 8;   // 8x8 pixels per tile, one wavefront
 constexpr int MAX_TF = 1024;
 
 // ---- frame kernels (apc_kernels.hip)
 hipError_t launch_bin_count(const MeshDev& m, const FrameDev& f, const SlotDev* slots, int max_faces,
                             const int* bface, int* counts, hipStream_t s);
 hipError_t launch_bin_fill(const MeshDev& m, const FrameDev& f, const SlotDev* slots, int max_faces,
-                           const int* bface, const int* offsets, int* cursors, int* records, hipStream_t s);
+                           const int* bface, const int* offsets, int* cursors, int* records, long long rec_cap,
+                           hipStream_t s);
 // stage one; pcount (tile-major [n_tiles * 64], may be null) receives the pieces per pixel, segs
 // ([2][H][W], may be null) the segments per pixel and the subdomains with pieces on each ray
 hipError_t launch_moments(int mm, const MeshDev& m, const FrameDev& f, const SlotDev* slots, const int* offsets,
-                          const int* counts, const int* records, const float* tf_rgba, float* out, int* pcount,
-                          int* segs, unsigned long long* counters, hipStream_t s);
+                          const int* counts, const int* records, long long bin_cap, const float* tf_rgba, float* out,
+                          int* pcount, int* segs, unsigned long long* counters, hipStream_t s);
 // stage two, walk part: mode 0 counts pieces per pixel into pcount; mode 1 writes the
-// pieces of tiles [tile_lo, tile_hi) as (z, a, s) at rec + 3 * (poff[pixel] - base)
+// pieces of tiles [tile_lo, tile_hi) as (z, a, s) at rec + 3 * (poff[pixel] - base), for
+// pixels whose pieces end within rec_cap pieces of base.  Bins whose records end beyond
+// bin_cap are skipped.
 hipError_t launch_stage(int mode, const MeshDev& m, const FrameDev& f, const SlotDev* slots, const int* offsets,
-                        const int* counts, const int* records, const float* tf_rgba, int tile_lo, int tile_hi,
-                        int* pcount, const long long* poff, long long base, float* rec,
-                        unsigned long long* counters, hipStream_t s);
-// stage two, evaluation part for tiles [tile_lo, tile_hi)
+                        const int* counts, const int* records, long long bin_cap, const float* tf_rgba, int tile_lo,
+                        int tile_hi, int* pcount, const long long* poff, long long base, long long rec_cap,
+                        float* rec, unsigned long long* counters, hipStream_t s);
+// stage two, evaluation part for tiles [tile_lo, tile_hi) (tiles staged beyond rec_cap stay empty)
 hipError_t launch_eval(int mm, const FrameDev& f, int tile_lo, int tile_hi, const long long* poff, long long base,
-                       const float* rec, const float* tf_rgba, const void* moments, const BoundParams& bp,
-                       float* rgba, unsigned long long* counters, hipStream_t s);
+                       long long rec_cap, const float* rec, const float* tf_rgba, const void* moments,
+                       const BoundParams& bp, float* rgba, unsigned long long* counters, hipStream_t s);
+// exclusive scan of the per-tile piece totals on the device
+hipError_t launch_tile_offsets(const long long* tile_tot, int n_tiles, long long* tile_off, hipStream_t s);
 // FP16 packing of a global moment image
 hipError_t launch_pack_f16(const float* in, int m1, int64_t pixels, _Float16* out, hipStream_t s);
 hipError_t launch_tile_sums(const int* pcount, int n_tiles, long long* tile_tot, hipStream_t s);

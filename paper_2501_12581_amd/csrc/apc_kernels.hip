@@ -452,7 +452,8 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_WALK_W
                                                   const int* __restrict__ offsets, const int* __restrict__ counts,
                                                   const int* __restrict__ records, const float* __restrict__ tf_rgba,
                                                   float* __restrict__ out, int* __restrict__ pcount,
-                                                  int* __restrict__ segs, unsigned long long* ctr) {
+                                                  int* __restrict__ segs, long long bin_cap,
+                                                  unsigned long long* ctr) {
   extern __shared__ float4 dyn_lds[];
   float* tfa = reinterpret_cast<float*>(dyn_lds);  // [n_tf] alpha column
   __shared__ FaceL faces[CHUNK];
@@ -462,7 +463,8 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_WALK_W
   for (int i = lane; i < f.n_tf; i += WAVE) tfa[i] = tf_rgba[4 * i + 3];
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int tx = tile % f.tiles_x, ty = tile / f.tiles_x;
-  const int px = tx * TILE + (lane & (TILE - 1)), py = ty * TILE + (lane / TILE);
+  const int px = (tx << f.tw_log2) + (lane & ((1 << f.tw_log2) - 1)),
+            py = ty * (WAVE >> f.tw_log2) + (lane >> f.tw_log2);
   const bool valid = px < f.W && py < f.H;
   const Ray r = pixel_ray(f, valid ? py : 0, valid ? px : 0);
   const size_t HW = size_t(f.W) * f.H, pix = size_t(py) * f.W + px;
@@ -479,9 +481,11 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_WALK_W
     sink.pieces = 0;
 #pragma unroll
     for (int j = 0; j < M1; ++j) sink.b[j] = 0.0;
-    if (n_rec > 0) {
+    if (n_rec > 0 && offsets[bin] + n_rec <= bin_cap) {
       const SlotDev sl = slots[k];
       walk_subdomain(M, f, r, valid, records + offsets[bin], n_rec, sl, faces, L, sink, cnt);
+    } else if (n_rec > 0) {
+      ++cnt.overflow;  // binned beyond the record capacity (never on an eagerly sized workspace)
     }
     cnt.pieces += sink.pieces;
     covering += sink.pieces > 0 ? 1 : 0;
@@ -523,32 +527,15 @@ struct CountSink {
 
 // writes (z, a, s) of every piece of one pixel ray, in walk order; the walk
 // is the bit-identical repeat of the counting walk, and `cap` (the counted
-// pieces) bounds the writes regardless.  Pieces are gathered SB at a time in
-// registers and written as one contiguous burst: single 12-byte stores from
-// 64 lanes into 64 separate streams leave cache lines partly written long
-// enough to be written back several times.
-constexpr int SB = 8;
+// pieces) bounds the writes regardless.  (Gathering pieces in registers to
+// write them in bursts cuts the HBM write bytes from 3.3x to 1.4x the staged
+// bytes but costs more in selects than the writes cost: measured slower.)
 struct StageSink {
   const FrameDev* f;
   const float* tfa;  // LDS alpha column
   float* out;        // this pixel's records: 3 floats each
-  unsigned pieces;   // pieces generated so far
+  unsigned pieces;
   unsigned cap;
-  unsigned flushed;  // pieces already written
-  float bz[SB], ba[SB], bs[SB];
-  __device__ void flush() {
-    const unsigned n = pieces - flushed;  // 0..SB
-    float* o = out + 3 * size_t(flushed);
-#pragma unroll
-    for (int i = 0; i < SB; ++i) {
-      if (unsigned(i) < n && flushed + i < cap) {
-        o[3 * i] = bz[i];
-        o[3 * i + 1] = ba[i];
-        o[3 * i + 2] = bs[i];
-      }
-    }
-    flushed = pieces;
-  }
   __device__ void chord(float t0, float t1, float s0, float s1) {
     cut_chord(*f, t0, t1, s0, s1, [&](float tm, float len, float s) {
       int i0;
@@ -556,16 +543,13 @@ struct StageSink {
       tf_coord(*f, s, i0, fr);
       float A = lerp_nc(tfa[i0], tfa[i0 + 1], fr);
       piece_az(*f, tm, len, A, a, z);
-      const unsigned slot = pieces - flushed;  // < SB
-#pragma unroll
-      for (int i = 0; i < SB; ++i) {  // register slot by select (no indexed arrays)
-        const bool here = unsigned(i) == slot;
-        bz[i] = here ? z : bz[i];
-        ba[i] = here ? a : ba[i];
-        bs[i] = here ? s : bs[i];
+      if (pieces < cap) {
+        float* o = out + 3 * size_t(pieces);
+        o[0] = z;
+        o[1] = a;
+        o[2] = s;
       }
       ++pieces;
-      if (pieces - flushed == SB) flush();
     });
   }
 };
@@ -576,10 +560,11 @@ struct StageSink {
 __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_WALK_WAVES, 8))) void k_stage(
     MeshDev M, FrameDev f, const SlotDev* __restrict__ slots,
                                                 const int* __restrict__ offsets, const int* __restrict__ counts,
-                                                const int* __restrict__ records, const float* __restrict__ tf_rgba,
+                                                const int* __restrict__ records, long long bin_cap,
+                                                const float* __restrict__ tf_rgba,
                                                 int tile_lo, int mode, int* __restrict__ pcount,
                                                 const long long* __restrict__ poff, long long base,
-                                                float* __restrict__ rec, unsigned long long* ctr) {
+                                                long long rec_cap, float* __restrict__ rec, unsigned long long* ctr) {
   extern __shared__ float4 dyn_lds[];
   float* tfa = reinterpret_cast<float*>(dyn_lds);
   __shared__ FaceL faces[CHUNK];
@@ -589,7 +574,8 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_WALK_W
   for (int i = lane; i < f.n_tf; i += WAVE) tfa[i] = tf_rgba[4 * i + 3];
   const int tile = tile_lo + xcd_tile(blockIdx.x, gridDim.x);
   const int tx = tile % f.tiles_x, ty = tile / f.tiles_x;
-  const int px = tx * TILE + (lane & (TILE - 1)), py = ty * TILE + (lane / TILE);
+  const int px = (tx << f.tw_log2) + (lane & ((1 << f.tw_log2) - 1)),
+            py = ty * (WAVE >> f.tw_log2) + (lane >> f.tw_log2);
   const bool valid = px < f.W && py < f.H;
   const Ray r = pixel_ray(f, valid ? py : 0, valid ? px : 0);
   EntryList L{ent_t, ent_c, lane};
@@ -601,20 +587,24 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_WALK_W
     for (int k = 0; k < f.n_slots; ++k) {
       const int bin = tile * f.n_slots + k;
       const int n_rec = counts[bin];
-      if (n_rec > 0) walk_subdomain(M, f, r, valid, records + offsets[bin], n_rec, slots[k], faces, L, sink, cnt);
+      if (n_rec > 0 && offsets[bin] + n_rec <= bin_cap)
+        walk_subdomain(M, f, r, valid, records + offsets[bin], n_rec, slots[k], faces, L, sink, cnt);
     }
     pcount[slot] = int(sink.pieces);
   } else {
-    const unsigned cap = unsigned(poff[slot + 1] - poff[slot]);
-    StageSink sink{&f, tfa, rec + 3 * (poff[slot] - base), 0u, cap, 0u, {}, {}, {}};
+    // staged pieces beyond the buffer's capacity are not written (counted; never on an eagerly sized buffer)
+    const bool fits = poff[slot + 1] - base <= rec_cap;
+    const unsigned cap = fits ? unsigned(poff[slot + 1] - poff[slot]) : 0u;
+    cnt.overflow += fits ? 0u : 1u;
+    StageSink sink{&f, tfa, rec + 3 * (fits ? poff[slot] - base : 0), 0u, cap};
     for (int k = 0; k < f.n_slots; ++k) {
       const int bin = tile * f.n_slots + k;
       const int n_rec = counts[bin];
-      if (n_rec > 0) walk_subdomain(M, f, r, valid, records + offsets[bin], n_rec, slots[k], faces, L, sink, cnt);
+      if (n_rec > 0 && offsets[bin] + n_rec <= bin_cap)
+        walk_subdomain(M, f, r, valid, records + offsets[bin], n_rec, slots[k], faces, L, sink, cnt);
     }
-    sink.flush();
     cnt.pieces += sink.pieces;
-    if (sink.pieces != cap) ++cnt.overflow;  // a re-walk that disagrees with the count (never expected)
+    if (fits && sink.pieces != cap) ++cnt.overflow;  // a re-walk that disagrees with the count (never expected)
   }
   flush_counts(cnt, ctr);
 }
@@ -679,7 +669,7 @@ __device__ __forceinline__ void wave_sync() {
 template <int N, class R>
 __global__ __launch_bounds__(WAVE * EVAL_WPB) __attribute__((amdgpu_waves_per_eu(N >= 4 ? APC_EVAL_WAVES_N4 : APC_EVAL_WAVES, 8))) void k_eval(
     FrameDev f, int tile_lo, int tile_hi, const long long* __restrict__ poff,
-                                               long long base, const float* __restrict__ rec,
+                                               long long base, long long rec_cap, const float* __restrict__ rec,
                                                const float* __restrict__ tf_rgba, const void* __restrict__ moments,
                                                BoundParams bp, float* __restrict__ rgba,
                                                unsigned long long* ctr) {
@@ -709,14 +699,18 @@ __global__ __launch_bounds__(WAVE * EVAL_WPB) __attribute__((amdgpu_waves_per_eu
   int* mode_lds = mode_all[wv];
   int* off_lds = off_all[wv];
   const int tx = tile % f.tiles_x, ty = tile / f.tiles_x;
-  const int px = tx * TILE + (lane & (TILE - 1)), py = ty * TILE + (lane / TILE);
+  const int px = (tx << f.tw_log2) + (lane & ((1 << f.tw_log2) - 1)),
+            py = ty * (WAVE >> f.tw_log2) + (lane >> f.tw_log2);
   const bool valid = px < f.W && py < f.H;
   const size_t HW = size_t(f.W) * f.H, pix = size_t(py) * f.W + px;
   const size_t slot0 = size_t(tile) * WAVE;
   const long long tile_base = poff[slot0];
-  off_lds[lane] = int(poff[slot0 + lane] - tile_base);
-  if (lane == 0) off_lds[WAVE] = int(poff[slot0 + WAVE] - tile_base);
+  // a tile whose pieces lie beyond the staging buffer was not staged: it is left empty (counted)
+  const bool staged = poff[slot0 + WAVE] - base <= rec_cap;
+  off_lds[lane] = staged ? int(poff[slot0 + lane] - tile_base) : 0;
+  if (lane == 0) off_lds[WAVE] = staged ? int(poff[slot0 + WAVE] - tile_base) : 0;
   LaneCount cnt = {};
+  cnt.overflow += (!staged && lane == 0) ? 1u : 0u;
   // per-pixel part of Alg. 3, once per pixel instead of once per sample
   float b0f = 0.0f;
   {
@@ -841,6 +835,31 @@ __global__ void k_piece_offsets(const int* __restrict__ pcount, const long long*
   if (t == n_tiles - 1 && lane == WAVE - 1) poff[size_t(n_tiles) * WAVE] = tile_off[t] + part[lane];
 }
 
+// exclusive scan of the per-tile piece totals on the device (one workgroup;
+// each thread sums a contiguous run), for frames that may not wait on the host
+__global__ __launch_bounds__(1024) void k_tile_offsets(const long long* __restrict__ tot, int n,
+                                                       long long* __restrict__ off) {
+  __shared__ long long part[1024];
+  const int t = threadIdx.x;
+  const int per = (n + 1023) / 1024;
+  const int lo = min(n, t * per), hi = min(n, lo + per);
+  long long s = 0;
+  for (int i = lo; i < hi; ++i) s += tot[i];
+  part[t] = s;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const long long add = t >= o ? part[t - o] : 0;
+    __syncthreads();
+    part[t] += add;
+    __syncthreads();
+  }
+  long long run = part[t] - s;
+  for (int i = lo; i < hi; ++i) {
+    off[i] = run;
+    run += tot[i];
+  }
+}
+
 // ------------------------------------------------------------------ binning
 
 __device__ __forceinline__ void project_px(const FrameDev& f, float4 p, float& col, float& row, bool& ok) {
@@ -864,7 +883,7 @@ __device__ __forceinline__ void project_px(const FrameDev& f, float4 p, float& c
 
 __global__ void k_bin(MeshDev M, FrameDev f, const SlotDev* __restrict__ slots,
                       const int* __restrict__ bface, int* __restrict__ counts, const int* __restrict__ offsets,
-                      int* __restrict__ cursors, int* __restrict__ records, int fill) {
+                      int* __restrict__ cursors, int* __restrict__ records, int fill, long long rec_cap) {
   const int k = blockIdx.y;
   const SlotDev sl = slots[k];
   const int i = sl.face_begin + blockIdx.x * blockDim.x + threadIdx.x;
@@ -920,14 +939,15 @@ __global__ void k_bin(MeshDev M, FrameDev f, const SlotDev* __restrict__ slots,
     r1 = min(f.H - 1, int(ceilf(rmax)) + 1);
     if (c0 > c1 || r0 > r1) return;
   }
-  for (int ty = r0 / TILE; ty <= r1 / TILE; ++ty)
-    for (int tx = c0 / TILE; tx <= c1 / TILE; ++tx) {
+  const int th = WAVE >> f.tw_log2;
+  for (int ty = r0 / th; ty <= r1 / th; ++ty)
+    for (int tx = c0 >> f.tw_log2; tx <= (c1 >> f.tw_log2); ++tx) {
       const int bin = (ty * f.tiles_x + tx) * f.n_slots + k;
       if (!fill) {
         atomicAdd(counts + bin, 1);
       } else {
         const int pos = offsets[bin] + atomicAdd(cursors + bin, 1);
-        records[pos] = code;
+        if (pos < rec_cap) records[pos] = code;  // the walks skip bins beyond the capacity
       }
     }
 }
@@ -1091,68 +1111,76 @@ hipError_t launch_bin_count(const MeshDev& m, const FrameDev& f, const SlotDev* 
   if (max_faces <= 0 || f.n_slots <= 0) return hipSuccess;
   dim3 grid(grid1(max_faces, 256), f.n_slots);
   hipLaunchKernelGGL(k_bin, grid, dim3(256), 0, s, m, f, slots, bface, counts, (const int*)nullptr, (int*)nullptr,
-                     (int*)nullptr, 0);
+                     (int*)nullptr, 0, 0ll);
   return hipGetLastError();
 }
 
 hipError_t launch_bin_fill(const MeshDev& m, const FrameDev& f, const SlotDev* slots, int max_faces,
-                           const int* bface, const int* offsets, int* cursors, int* records, hipStream_t s) {
+                           const int* bface, const int* offsets, int* cursors, int* records, long long rec_cap,
+                           hipStream_t s) {
   if (max_faces <= 0 || f.n_slots <= 0) return hipSuccess;
   dim3 grid(grid1(max_faces, 256), f.n_slots);
   hipLaunchKernelGGL(k_bin, grid, dim3(256), 0, s, m, f, slots, bface, (int*)nullptr, offsets, cursors, records,
-                     1);
+                     1, rec_cap);
   return hipGetLastError();
 }
 
 hipError_t launch_moments(int mm, const MeshDev& m, const FrameDev& f, const SlotDev* slots, const int* offsets,
-                          const int* counts, const int* records, const float* tf_rgba, float* out, int* pcount,
-                          int* segs, unsigned long long* counters, hipStream_t s) {
+                          const int* counts, const int* records, long long bin_cap, const float* tf_rgba, float* out,
+                          int* pcount, int* segs, unsigned long long* counters, hipStream_t s) {
   const size_t lds = size_t(f.n_tf) * sizeof(float);
   const dim3 grid(f.n_tiles), block(WAVE);
   if (mm == 4)
     hipLaunchKernelGGL(k_moments<5>, grid, block, lds, s, m, f, slots, offsets, counts, records, tf_rgba, out,
-                       pcount, segs, counters);
+                       pcount, segs, bin_cap, counters);
   else if (mm == 6)
     hipLaunchKernelGGL(k_moments<7>, grid, block, lds, s, m, f, slots, offsets, counts, records, tf_rgba, out,
-                       pcount, segs, counters);
+                       pcount, segs, bin_cap, counters);
   else
     hipLaunchKernelGGL(k_moments<9>, grid, block, lds, s, m, f, slots, offsets, counts, records, tf_rgba, out,
-                       pcount, segs, counters);
+                       pcount, segs, bin_cap, counters);
   return hipGetLastError();
 }
 
 hipError_t launch_stage(int mode, const MeshDev& m, const FrameDev& f, const SlotDev* slots, const int* offsets,
-                        const int* counts, const int* records, const float* tf_rgba, int tile_lo, int tile_hi,
-                        int* pcount, const long long* poff, long long base, float* rec,
-                        unsigned long long* counters, hipStream_t s) {
+                        const int* counts, const int* records, long long bin_cap, const float* tf_rgba, int tile_lo,
+                        int tile_hi, int* pcount, const long long* poff, long long base, long long rec_cap,
+                        float* rec, unsigned long long* counters, hipStream_t s) {
   if (tile_hi <= tile_lo) return hipSuccess;
   const size_t lds = size_t(f.n_tf) * sizeof(float);
   hipLaunchKernelGGL(k_stage, dim3(tile_hi - tile_lo), dim3(WAVE), lds, s, m, f, slots, offsets, counts, records,
-                     tf_rgba, tile_lo, mode, pcount, poff, base, rec, counters);
+                     bin_cap, tf_rgba, tile_lo, mode, pcount, poff, base, rec_cap, rec, counters);
   return hipGetLastError();
 }
 
 hipError_t launch_eval(int mm, const FrameDev& f, int tile_lo, int tile_hi, const long long* poff, long long base,
-                       const float* rec, const float* tf_rgba, const void* moments, const BoundParams& bp,
+                       long long rec_cap, const float* rec, const float* tf_rgba, const void* moments,
+                       const BoundParams& bp,
                        float* rgba, unsigned long long* counters, hipStream_t s) {
   if (tile_hi <= tile_lo) return hipSuccess;
   const size_t lds = size_t(f.n_tf) * sizeof(float4);
   const dim3 grid((tile_hi - tile_lo + EVAL_WPB - 1) / EVAL_WPB), block(WAVE * EVAL_WPB);
   if (mm == 4)
-    hipLaunchKernelGGL((k_eval<2, float>), grid, block, lds, s, f, tile_lo, tile_hi, poff, base, rec, tf_rgba,
-                       moments, bp, rgba, counters);
+    hipLaunchKernelGGL((k_eval<2, float>), grid, block, lds, s, f, tile_lo, tile_hi, poff, base, rec_cap, rec,
+                       tf_rgba, moments, bp, rgba, counters);
   else if (mm == 6)
-    hipLaunchKernelGGL((k_eval<3, double>), grid, block, lds, s, f, tile_lo, tile_hi, poff, base, rec, tf_rgba,
-                       moments, bp, rgba, counters);
+    hipLaunchKernelGGL((k_eval<3, double>), grid, block, lds, s, f, tile_lo, tile_hi, poff, base, rec_cap, rec,
+                       tf_rgba, moments, bp, rgba, counters);
   else
-    hipLaunchKernelGGL((k_eval<4, double>), grid, block, lds, s, f, tile_lo, tile_hi, poff, base, rec, tf_rgba,
-                       moments, bp, rgba, counters);
+    hipLaunchKernelGGL((k_eval<4, double>), grid, block, lds, s, f, tile_lo, tile_hi, poff, base, rec_cap, rec,
+                       tf_rgba, moments, bp, rgba, counters);
   return hipGetLastError();
 }
 
 hipError_t launch_pack_f16(const float* in, int m1, int64_t pixels, _Float16* out, hipStream_t s) {
   if (pixels <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_pack_f16, dim3(grid1(pixels, 256)), dim3(256), 0, s, in, m1, pixels, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_offsets(const long long* tile_tot, int n_tiles, long long* tile_off, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tile_offsets, dim3(1), dim3(1024), 0, s, tile_tot, n_tiles, tile_off);
   return hipGetLastError();
 }
 

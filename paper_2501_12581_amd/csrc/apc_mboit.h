@@ -268,9 +268,41 @@ APC_HD int roots4(const R* c, R* x) {
   return 4;
 }
 
+// The closed-form solve runs out of line (see APC_HD_COLD) with its
+// coefficients and roots passed by value, which keeps them in registers
+// instead of a stack frame in scratch memory.
+template <int N, class R>
+struct RootSet {
+  R x[N];
+  int n;
+};
+template <int N, class R>
+struct PolyCoef {
+  R c[N + 1];
+};
+template <int N, class R>
+APC_HD int poly_roots_body(const R* q, R* x);
+template <int N, class R>
+APC_HD_COLD RootSet<N, R> poly_roots_v(PolyCoef<N, R> q) {
+  RootSet<N, R> r;
+#pragma unroll
+  for (int i = 0; i < N; ++i) r.x[i] = R(0);
+  r.n = poly_roots_body<N, R>(q.c, r.x);
+  return r;
+}
 // Roots of the polynomial q[0..N]; returns how many finite ones (x[0..nr)).
 template <int N, class R>
-APC_HD_COLD int poly_roots(const R* q, R* x) {
+APC_HD int poly_roots(const R* q, R* x) {
+  PolyCoef<N, R> c;
+#pragma unroll
+  for (int j = 0; j <= N; ++j) c.c[j] = q[j];
+  const RootSet<N, R> r = poly_roots_v<N, R>(c);
+#pragma unroll
+  for (int i = 0; i < N; ++i) x[i] = r.x[i];
+  return r.n;
+}
+template <int N, class R>
+APC_HD int poly_roots_body(const R* q, R* x) {
   R cmax = R(0);
 #pragma unroll
   for (int j = 0; j <= N; ++j) cmax = m_max(cmax, m_abs(q[j]));

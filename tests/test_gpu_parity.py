@@ -296,7 +296,7 @@ def test_slab_segments_and_parity(apc, ctx):
     r, rgba = _render(apc, ctx, sc)
     segs = ctx.segment_counts(128, 128).cpu().numpy().reshape(2, -1)
     assert np.all(segs[0] == 16) and np.all(segs[1] == 4)
-    assert ctx.counters()["segments"] == 16 * 128 * 128
+    assert ctx.counters()["segments"] == 2 * 16 * 128 * 128  # both walks count them
     ref = oracle.render(sc, segments=True)
     assert np.array_equal(segs, ref["segments"])
     assert _moment_err(_flat_moments(r.moments), ref["moments"]) <= 1e-5
@@ -330,3 +330,70 @@ def test_segment_counts_match_oracle_on_jagged_chunks(apc, ctx):
             lo = np.minimum(lo, rr["segments"])
             hi = np.maximum(hi, rr["segments"])
         assert np.all(got[:, bad] >= lo) and np.all(got[:, bad] <= hi)
+
+
+def test_tile_shapes_give_identical_results_and_autotuner(apc, ctx):
+    """Any tile shape (w x 64/w pixels per wavefront) gives bitwise the same
+    moments, segment counts and image: each ray walks alone and each pixel's
+    sums run in its own walk order.  The autotuner times stage one for widths
+    2..32, keeps the fastest, and the frame after it is unchanged."""
+    sc = synth.scene_medium(size=384)
+    r = apc.Renderer(ctx, sc)
+    outs = {}
+    try:
+        for w in (2, 8, 32, 64):
+            ctx.set_tile_shape(w)
+            assert ctx.tile_shape() == (w, 64 // w)
+            rgba = r.frame().clone()
+            outs[w] = (r.moments.clone(), rgba, ctx.segment_counts(384, 384))
+        for w in (2, 32, 64):
+            for a, b in zip(outs[w], outs[8]):
+                assert torch.equal(a, b), w
+        best, ms = ctx.autotune_tile_shape(r.mesh, r.view, r.tf, sc.m, r.subs, r.per_sub, repeats=1)
+        print("autotuned tile width", best, ms)
+        assert best in (2, 4, 8, 16, 32) and sorted(ms) == [2, 4, 8, 16, 32] and all(v > 0 for v in ms.values())
+        assert ctx.tile_shape()[0] == best
+        assert torch.equal(r.frame(), outs[8][1])
+        with pytest.raises(apc.ApcError):
+            ctx.set_tile_shape(3)
+    finally:
+        ctx.set_tile_shape(8)
+
+
+def test_frame_graph_replays_match_eager_frames(apc, ctx):
+    """A frame captured in a HIP graph: every replay (with eager work and
+    synchronisation between replays) gives bitwise the eager frame, and after
+    the transfer-function table is edited in place a replay gives bitwise the
+    eager frame with the new table."""
+    sc = synth.scene_medium(size=256)
+    r = apc.Renderer(ctx, sc)
+    eager = r.frame().clone()
+    eager_mom = r.moments.clone()
+    g = apc.FrameGraph(r)
+    try:
+        torch.cuda.synchronize()
+        assert torch.equal(r.rgba, eager)  # the sizing frame
+        for k in range(3):
+            r.rgba.fill_(-1.0)
+            r.moments.fill_(-1.0)
+            g.launch()
+            torch.cuda.synchronize()
+            assert torch.equal(r.rgba, eager), k
+            assert torch.equal(r.moments, eager_mom), k
+            junk = torch.randn(1 << 20, device="cuda") * 2.0  # eager work between replays
+            torch.cuda.synchronize()
+            del junk
+        cnt = g.counters()
+        assert cnt["pieces"] > 0 and cnt["walk_step_limit"] == 0
+        # edit the transfer function in place: the replay follows it
+        r.tf_dev[:, :3] = r.tf_dev[:, :3].flip(0).contiguous()
+        torch.cuda.synchronize()
+        g.launch()
+        torch.cuda.synchronize()
+        replay = r.rgba.clone()
+        again = r.frame()
+        torch.cuda.synchronize()
+        assert torch.equal(replay, again)
+        assert not torch.equal(replay, eager)
+    finally:
+        g.close()
