@@ -40,6 +40,29 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_large_2560_m8.json")
+
+
+def measured_traffic(args, kernel):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated) of `kernel` from the committed
+    rocprofv3 record of the default large workload, or None when the workload differs or the kernel
+    sources changed since the counters were taken."""
+    import hashlib
+    if args.workload != "large" or args.size or args.grid or args.m or not os.path.exists(TRAFFIC_RECORD):
+        return None, "no counter record for this workload"
+    rec = json.load(open(TRAFFIC_RECORD))
+    h = hashlib.sha256()
+    for f in rec["sources"]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest() != rec["sources_sha256"]:
+        return None, "kernel sources changed since the counters were taken"
+    b = rec["bytes_per_launch"].get(kernel)
+    if b is None:
+        return None, "kernel not in the counter record"
+    return int(b["fetch_bytes"] + b["write_bytes"]), "profiles/traffic_large_2560_m8.json (read %.3g B + write %.3g B)" % (
+        b["fetch_bytes"], b["write_bytes"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -168,8 +191,10 @@ def main():
     timed = {"k_moments": kern["moments_ms"], "k_stage": kern["stage_ms"], "k_eval": kern["eval_ms"]}
     dom = max(timed, key=timed.get)
     rf = rooflines[dom]
+    traffic, traffic_note = measured_traffic(args, dom)
     roofline = {"kernel": dom, "kernel_ms": round(timed[dom], 3), "bound": rf["bound"], "achieved": round(rf["achieved"], 4), "peak": rf["peak"],
-                "unit": rf["unit"], "frac": round(rf["achieved"] / rf["peak"], 5), "traffic": None,
+                "unit": rf["unit"], "frac": round(rf["achieved"] / rf["peak"], 5), "traffic": traffic,
+                "traffic_source": traffic_note,
                 "work_per_launch": rf["per_launch"],
                 "other": {k: {"bound": v["bound"], "achieved": round(v["achieved"], 4), "unit": v["unit"],
                               "frac": round(v["achieved"] / v["peak"], 5)} for k, v in rooflines.items()

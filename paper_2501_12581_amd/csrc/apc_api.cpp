@@ -137,6 +137,7 @@ struct apc_mesh_s {
   int32_t S = 0;
   float4* vert = nullptr;
   int4* tet = nullptr;
+  int4* wrec = nullptr;  // [8T] walk records (128 bytes per tet)
   int* bface = nullptr;
   std::vector<int> sub_begin, face_begin;  // [S+1] each
   double lo[3], hi[3];
@@ -321,6 +322,7 @@ apc_status build_bins(apc_ctx ctx, const apc_mesh_s* m, const FrameDev& f, const
   HIPCHK(ctx->scan_tmp.ensure(sizeof(int) * apc::scan_tmp_elems(nb)));
   md.vert = m->vert;
   md.tet = m->tet;
+  md.wrec = m->wrec;
   md.n_vertices = m->V;
   md.n_tets = m->T;
   HIPCHK(ev_mark(ctx, EV_BIN, 0, s));
@@ -516,6 +518,7 @@ apc_status apc_load_mesh(apc_ctx ctx, const apc_mesh_desc* d, apc_mesh* out, voi
     cleanup();
     if (m->vert) (void)hipFree(m->vert);
     if (m->tet) (void)hipFree(m->tet);
+    if (m->wrec) (void)hipFree(m->wrec);
     if (m->bface) (void)hipFree(m->bface);
     delete m;
     return fail(e == hipErrorOutOfMemory ? APC_E_NOMEM : APC_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
@@ -599,8 +602,10 @@ apc_status apc_load_mesh(apc_ctx ctx, const apc_mesh_desc* d, apc_mesh* out, voi
   if ((e = hipMemcpyAsync(m->bface, bface.data(), sizeof(int) * bface.size(), hipMemcpyHostToDevice, s)) !=
       hipSuccess)
     return dev_fail(e, "upload");
+  if ((e = hipMalloc(&m->wrec, sizeof(int4) * 8 * T)) != hipSuccess) return dev_fail(e, "alloc");
+  if ((e = apc::launch_walk_records(m->tet, m->vert, T, m->wrec, s)) != hipSuccess) return dev_fail(e, "records");
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return dev_fail(e, "upload");
-  m->device_bytes = int64_t(sizeof(float4) * V + sizeof(int4) * 2 * T + sizeof(int) * bface.size());
+  m->device_bytes = int64_t(sizeof(float4) * V + sizeof(int4) * 10 * T + sizeof(int) * bface.size());
   *out = m;
   return APC_OK;
 }
@@ -611,6 +616,7 @@ apc_status apc_free_mesh(apc_ctx ctx, apc_mesh m) {
   (void)hipDeviceSynchronize();
   if (m->vert) (void)hipFree(m->vert);
   if (m->tet) (void)hipFree(m->tet);
+  if (m->wrec) (void)hipFree(m->wrec);
   if (m->bface) (void)hipFree(m->bface);
   delete m;
   return APC_OK;

@@ -14,6 +14,9 @@ namespace apc {
 struct MeshDev {
   const float4* vert;  // [V]: x, y, z, scalar
   const int4* tet;     // [2T]
+  // [8T]: the walk's record of tet t, one 128-byte line: vertex ids, neighbour
+  // codes, then the four vertices (x, y, z, scalar) in vertex-id order
+  const int4* wrec;
   int64_t n_vertices;
   int64_t n_tets;
 };
@@ -94,6 +97,8 @@ hipError_t launch_sum_moments(const float* in, int n_slots, const int* order, in
                               hipStream_t s);
 hipError_t launch_sum_images(const float* in, int n_slots, const int* order, int64_t pixels, const float* b0,
                              const BoundParams& bp, float* out, hipStream_t s);
+// 128-byte walk records from the tet records and the vertices
+hipError_t launch_walk_records(const int4* tet, const float4* vert, int64_t n_tets, int4* wrec, hipStream_t s);
 // exclusive scan of n int32 values; tmp must hold scan_tmp_elems(n) ints
 int64_t scan_tmp_elems(int64_t n);
 hipError_t launch_exclusive_scan(const int* in, int* out, int64_t n, int* tmp, hipStream_t s);

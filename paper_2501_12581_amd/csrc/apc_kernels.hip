@@ -246,10 +246,14 @@ __device__ void walk(const MeshDev& M, const FrameDev& f, const Ray& r, int tet,
       ++cnt.steplimit;
       return;
     }
-    const int4 tv = M.tet[2 * tet];
-    const int4 tn = M.tet[2 * tet + 1];
+    // ids, neighbours and the apex vertex come from one 128-byte record, so
+    // the three loads go out together (no vertex load waiting on the ids)
+    const int4* rec = M.wrec + 8 * size_t(tet);
+    const int4 tv = rec[0];
+    const int4 tn = rec[1];
+    const float4 dp = reinterpret_cast<const float4*>(rec)[2 + apex];
     int did = sel4(tv, apex);
-    VS D = vstate(r, did, M.vert[did]);
+    VS D = vstate(r, did, dp);
     float qA = side(D, A), qB = side(D, B), qC = side(D, C);
     // exit through the face opposite X where q(next of X) > 0 > q(previous of X)
     int x;
@@ -860,6 +864,22 @@ __global__ __launch_bounds__(1024) void k_tile_offsets(const long long* __restri
   }
 }
 
+// walk records: [ids][neighbours][v0][v1][v2][v3], 8 x 16 bytes per tet
+__global__ void k_walk_records(const int4* __restrict__ tet, const float4* __restrict__ vert, int64_t n,
+                               int4* __restrict__ wrec) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int4 tv = tet[2 * t];
+  int4* o = wrec + 8 * t;
+  o[0] = tv;
+  o[1] = tet[2 * t + 1];
+  float4* ov = reinterpret_cast<float4*>(o + 2);
+  ov[0] = vert[tv.x];
+  ov[1] = vert[tv.y];
+  ov[2] = vert[tv.z];
+  ov[3] = vert[tv.w];
+}
+
 // ------------------------------------------------------------------ binning
 
 __device__ __forceinline__ void project_px(const FrameDev& f, float4 p, float& col, float& row, bool& ok) {
@@ -1175,6 +1195,12 @@ hipError_t launch_eval(int mm, const FrameDev& f, int tile_lo, int tile_hi, cons
 hipError_t launch_pack_f16(const float* in, int m1, int64_t pixels, _Float16* out, hipStream_t s) {
   if (pixels <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_pack_f16, dim3(grid1(pixels, 256)), dim3(256), 0, s, in, m1, pixels, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_walk_records(const int4* tet, const float4* vert, int64_t n_tets, int4* wrec, hipStream_t s) {
+  if (n_tets <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_walk_records, dim3(grid1(n_tets, 256)), dim3(256), 0, s, tet, vert, n_tets, wrec);
   return hipGetLastError();
 }
 
