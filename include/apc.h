@@ -170,7 +170,13 @@ typedef struct apc_mboit {
  *   subdomains      host [n_sub] distinct subdomain ids
  *   moments_per_sub device [n_sub][m+1][H][W] FP32, fully written (zero where
  *                   subdomain k is not hit)
- * m is 4, 6 or 8.  flags: reserved, 0. */
+ * m is 4, 6 or 8.
+ * The pieces are also kept in context-owned device memory (12 bytes per
+ * piece in chunks of 64, grown after a frame that did not fit) so that
+ * apc_resolve_pass of the same geometry, camera, transfer function and
+ * subdomain list evaluates them without walking the rays again; when they
+ * were not all kept it walks again (same pieces, same result).
+ * flags: 0, or APC_REWALK: keep no pieces (stage two walks again). */
 apc_status apc_moments_pass(apc_ctx ctx, apc_mesh mesh, const apc_view* view, const apc_tf* tf, int32_t m,
                             const int32_t* subdomains, int32_t n_sub, float* moments_per_sub, uint32_t flags,
                             void* stream);
@@ -187,6 +193,7 @@ apc_status apc_sum_moments(apc_ctx ctx, const float* moments_per_sub, int32_t n_
 
 #define APC_FINALIZE 1u
 #define APC_MOMENTS_F16 2u
+#define APC_REWALK 4u
 
 /* Pack a global moment image for FP16 storage: plane 0 holds ln(b0) (-inf
  * where b0 <= 0), planes j = 1..m hold b_j / b0 (in [-1, 1] since the warped
@@ -291,9 +298,9 @@ apc_status apc_autotune_tile_shape(apc_ctx ctx, apc_mesh mesh, const apc_view* v
 apc_status apc_segment_counts(apc_ctx ctx, int32_t* out, int32_t height, int32_t width, void* stream);
 
 typedef struct apc_counters {
-  int64_t pieces;           /* samples (pieces) generated, both passes */
-  int64_t tet_steps;        /* tets walked, both passes */
-  int64_t entries;          /* (ray, boundary face) entries walked, both passes */
+  int64_t pieces;           /* samples (pieces) generated, by every walk (stage one, and stage two when it walks) */
+  int64_t tet_steps;        /* tets walked, every walk */
+  int64_t entries;          /* (ray, boundary face) entries walked, every walk */
   int64_t bin_records;      /* (face, tile) records binned */
   int64_t walk_step_limit;  /* walks cut off by the step limit (should be 0) */
   int64_t exit_fallback;    /* exit faces chosen by the tie fallback (should be ~0) */
@@ -302,7 +309,7 @@ typedef struct apc_counters {
   int64_t nonpd_pivots;     /* Cholesky pivots floored in the resolve pass */
   int64_t table_samples;    /* samples whose moment-bound roots came from their pixel's gap table (m >= 6) */
   int64_t table_fallback;   /* of those, samples that went back to the closed-form roots (~1e-4 expected) */
-  int64_t segments;         /* maximal ray intervals inside one subdomain with at least one piece, both passes */
+  int64_t segments;         /* maximal ray intervals inside one subdomain with at least one piece, every walk */
 } apc_counters;
 
 /* Read (and with reset != 0, clear) the counters accumulated by this context.

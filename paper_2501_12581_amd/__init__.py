@@ -20,6 +20,7 @@ APC_ORTHOGRAPHIC = 0
 APC_PERSPECTIVE = 1
 APC_FINALIZE = 1
 APC_MOMENTS_F16 = 2
+APC_REWALK = 4
 STATUS = {0: "APC_OK", 1: "APC_E_ARG", 2: "APC_E_MESH", 3: "APC_E_NOMEM", 4: "APC_E_DEVICE",
           5: "APC_E_NUMERIC", 6: "APC_E_UNSUPPORTED"}
 EXPORTS = ["apc_create", "apc_destroy", "apc_last_error", "apc_version", "apc_load_mesh", "apc_free_mesh",
@@ -253,13 +254,14 @@ class Context:
         self._ck(lib().apc_load_mesh(self.handle, C.byref(d), C.byref(h), _stream(stream)))
         return Mesh(self, h)
 
-    def moments_pass(self, mesh, view: View, tf: TF, m, subdomains, out, stream=None):
+    def moments_pass(self, mesh, view: View, tf: TF, m, subdomains, out, stream=None, rewalk=False):
+        """Stage one; unless rewalk, its pieces are kept for the resolve pass of the same frame."""
         import torch
         ids, ptr = _ids(subdomains)
         shape = (len(ids), m + 1, view.height, view.width)
         self._ck(lib().apc_moments_pass(self.handle, mesh.handle, C.byref(view), C.byref(tf), int(m), ptr,
-                                        len(ids), _dev_ptr(out, torch.float32, shape, "moments_per_sub"), 0,
-                                        _stream(stream)))
+                                        len(ids), _dev_ptr(out, torch.float32, shape, "moments_per_sub"),
+                                        APC_REWALK if rewalk else 0, _stream(stream)))
 
     def sum_moments(self, per_sub, m, subdomains, out, stream=None):
         import torch
@@ -399,11 +401,12 @@ class Renderer:
         self.moments = torch.empty((m + 1, H, W), dtype=torch.float32, device=device)
         self.rgba = torch.empty((H, W, 4), dtype=torch.float32, device=device)
 
-    def frame(self, subdomains=None, finalize=True, stream=None, moments_f16=False):
-        """One frame; with moments_f16 the resolve reads the FP16-packed moment image (self.moments_h)."""
+    def frame(self, subdomains=None, finalize=True, stream=None, moments_f16=False, rewalk=False):
+        """One frame; with moments_f16 the resolve reads the FP16-packed moment image (self.moments_h); with
+        rewalk stage two walks the rays again instead of reading the pieces stage one kept."""
         subs = self.subs if subdomains is None else np.asarray(subdomains, np.int32)
         per_sub = self.per_sub if len(subs) == len(self.subs) else self.per_sub[:len(subs)]
-        self.ctx.moments_pass(self.mesh, self.view, self.tf, self.scene.m, subs, per_sub, stream)
+        self.ctx.moments_pass(self.mesh, self.view, self.tf, self.scene.m, subs, per_sub, stream, rewalk=rewalk)
         self.ctx.sum_moments(per_sub, self.scene.m, subs, self.moments, stream)
         mom = self.moments
         if moments_f16:

@@ -113,6 +113,14 @@ struct apc_ctx_s {
   bool capturing = false;
   long long last_pieces = 0;  // pieces of the last eager resolve pass
   long long last_chunks = 0;  // and the number of staging chunks it took
+  // pieces kept by stage one for stage two (see PieceStore)
+  DevBuf pool, ptab, store_next;
+  long long pool_chunks = 0;         // chunks the pool holds
+  long long pool_target = 0;         // chunks wanted (grown after a frame did not fit)
+  int maxc = 64;                     // chunk slots per pixel
+  bool store_ready = false;          // the last stage one kept its pieces (if none failed)
+  apc_tf store_tf = {};              // the transfer function they were made with
+  bool store_failed_last = false;    // the last resolve found that stage one could not keep every piece
 };
 
 struct apc_graph_s {
@@ -412,7 +420,7 @@ apc_status apc_destroy(apc_ctx ctx) {
   (void)hipDeviceSynchronize();
   for (DevBuf* b : {&ctx->counts, &ctx->offsets, &ctx->cursors, &ctx->records, &ctx->scan_tmp, &ctx->slots,
                     &ctx->order, &ctx->counters, &ctx->pcount, &ctx->tile_tot, &ctx->tile_off, &ctx->poff,
-                    &ctx->stage, &ctx->segs})
+                    &ctx->stage, &ctx->segs, &ctx->pool, &ctx->ptab, &ctx->store_next})
     b->release();
   if (ctx->staging) (void)hipHostFree(ctx->staging);
   if (ctx->staging_done) (void)hipEventDestroy(ctx->staging_done);
@@ -654,22 +662,53 @@ apc_status apc_moments_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const
   if (mm != 4 && mm != 6 && mm != 8) return fail(APC_E_ARG, "m = %d unsupported (4, 6 or 8)", mm);
   if ((st = check_subdomains(m, subs, n_sub)) != APC_OK) return st;
   if (!out) return fail(APC_E_ARG, "output is NULL");
-  if (flags != 0) return fail(APC_E_ARG, "unknown flags 0x%x", flags);
+  if (flags & ~APC_REWALK) return fail(APC_E_ARG, "unknown flags 0x%x", flags);
   FrameDev f;
   if ((st = make_frame(m, view, tf, n_sub, max_tets_of(m, subs, n_sub), ctx->tw_log2, f)) != APC_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   MeshDev md;
   if ((st = build_bins(ctx, m, f, subs, n_sub, s, md)) != APC_OK) return st;
   HIPCHK(ctx->pcount.ensure(sizeof(int) * size_t(f.n_tiles) * 64));
+  // keep the pieces for stage two unless asked not to (or the pool cannot be had)
+  apc::PieceStore ps = {};
+  ctx->store_ready = false;
+  if (!(flags & APC_REWALK)) {
+    const size_t slots = size_t(f.n_tiles) * 64;
+    if (ctx->pool_target == 0) ctx->pool_target = (long long)(slots * 2);  // 128 pieces per pixel to start
+    const size_t chunk_bytes = sizeof(float) * 3 * apc::PIECE_CHUNK;
+    bool ok = true;
+    if (ctx->pool_chunks < ctx->pool_target && !ctx->capturing) {
+      size_t free_b = 0, total_b = 0;
+      HIPCHK(hipMemGetInfo(&free_b, &total_b));
+      const size_t limit = size_t(0.6 * double(free_b + ctx->pool.bytes));
+      const size_t want = std::min(size_t(ctx->pool_target) * chunk_bytes, limit);
+      ctx->pool.release();
+      ctx->pool_chunks = 0;
+      if (ctx->pool.ensure(want) == hipSuccess) ctx->pool_chunks = (long long)(ctx->pool.bytes / chunk_bytes);
+      else ok = false;
+    }
+    if (ok && ctx->ptab.ensure(sizeof(int) * slots * ctx->maxc) != hipSuccess) ok = false;
+    if (ok && ctx->store_next.ensure(4 * sizeof(unsigned long long)) != hipSuccess) ok = false;
+    if (ok && ctx->pool_chunks > 0) {
+      HIPCHK(apc::launch_fill_i32(ctx->store_next.as<int>(), 0, 8, s));
+      ps.pool = ctx->pool.as<float>();
+      ps.n_chunks = std::min<long long>(ctx->pool_chunks, (long long)INT32_MAX);
+      ps.ptab = ctx->ptab.as<int>();
+      ps.maxc = ctx->maxc;
+      ps.next = ctx->store_next.as<unsigned long long>();
+    }
+  }
   HIPCHK(ctx->segs.ensure(sizeof(int) * 2 * size_t(view->width) * view->height));
   ctx->seg_h = view->height;
   ctx->seg_w = view->width;
   HIPCHK(ev_mark(ctx, EV_MOM, 0, s));
   HIPCHK(apc::launch_moments(mm, md, f, ctx->slots.as<SlotDev>(), ctx->offsets.as<int>(), ctx->counts.as<int>(),
                              ctx->records.as<int>(), bin_cap(ctx), tf->rgba, out, ctx->pcount.as<int>(),
-                             ctx->segs.as<int>(), ctx->counters.as<unsigned long long>(), s));
+                             ctx->segs.as<int>(), ps, ctx->counters.as<unsigned long long>(), s));
   HIPCHK(ev_mark(ctx, EV_MOM, 1, s));
   set_piece_key(ctx, m, view, subs, n_sub);
+  ctx->store_ready = ps.pool != nullptr;
+  ctx->store_tf = *tf;
   return APC_OK;
 }
 
@@ -730,11 +769,35 @@ apc_status apc_resolve_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const
   FrameDev f;
   if ((st = make_frame(m, view, tf, n_sub, max_tets_of(m, subs, n_sub), ctx->tw_log2, f)) != APC_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  MeshDev md;
-  if ((st = build_bins(ctx, m, f, subs, n_sub, s, md)) != APC_OK) return st;
   const int nt = f.n_tiles;
   unsigned long long* ctr = ctx->counters.as<unsigned long long>();
+  ctx->ev_used[EV_STG] = false;
+  ctx->ev_used[EV_EVL] = false;
+  // stage one's kept pieces, when they belong to this geometry and transfer function and all fitted
+  bool stored = ctx->store_ready && piece_key_matches(ctx, m, view, subs, n_sub) &&
+                std::memcmp(&ctx->store_tf, tf, sizeof(apc_tf)) == 0;
+  bool store_failed = false;
+  if (stored && !ctx->capturing) {
+    unsigned long long nx[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(nx, ctx->store_next.p, sizeof(nx), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    store_failed = nx[1] != 0;
+    stored = !store_failed;
+  }
+  ctx->store_failed_last = store_failed;
   HIPCHK(ev_mark(ctx, EV_RES, 0, s));
+  if (stored) {  // (in a replayed graph the kernel itself checks that no lane failed)
+    apc::PieceStore ps = {ctx->pool.as<float>(), ctx->pool_chunks, ctx->ptab.as<int>(), ctx->maxc,
+                          ctx->store_next.as<unsigned long long>()};
+    HIPCHK(ev_mark(ctx, EV_EVL, 0, s));
+    HIPCHK(apc::launch_eval(mb->m, f, 0, nt, nullptr, 0, 0, nullptr, ps, ctx->pcount.as<int>(), tf->rgba, moments,
+                            bp, rgba, ctr, s));
+    HIPCHK(ev_mark(ctx, EV_EVL, 1, s));
+    HIPCHK(ev_mark(ctx, EV_RES, 1, s));
+    return APC_OK;
+  }
+  MeshDev md;
+  if ((st = build_bins(ctx, m, f, subs, n_sub, s, md)) != APC_OK) return st;
   // pieces per pixel: from stage one when it ran on the same geometry, else counted by a walk
   if (!piece_key_matches(ctx, m, view, subs, n_sub)) {
     if (ctx->capturing) return fail(APC_E_ARG, "capture: stage one of the same view must precede the resolve");
@@ -745,6 +808,7 @@ apc_status apc_resolve_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const
                              0, nullptr, ctr, s));
     set_piece_key(ctx, m, view, subs, n_sub);
   }
+  const apc::PieceStore no_store = {};
   HIPCHK(ctx->tile_tot.ensure(sizeof(long long) * nt));
   HIPCHK(ctx->tile_off.ensure(sizeof(long long) * nt));
   HIPCHK(ctx->poff.ensure(sizeof(long long) * (size_t(nt) * 64 + 1)));
@@ -760,7 +824,7 @@ apc_status apc_resolve_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const
                              ctx->records.as<int>(), bin_cap(ctx), tf->rgba, 0, nt, nullptr,
                              ctx->poff.as<long long>(), 0, cap_pieces, ctx->stage.as<float>(), ctr, s));
     HIPCHK(apc::launch_eval(mb->m, f, 0, nt, ctx->poff.as<long long>(), 0, cap_pieces, ctx->stage.as<float>(),
-                            tf->rgba, moments, bp, rgba, ctr, s));
+                            no_store, nullptr, tf->rgba, moments, bp, rgba, ctr, s));
     return APC_OK;
   }
   std::vector<long long> tot(nt), toff(nt);
@@ -771,6 +835,19 @@ apc_status apc_resolve_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const
     toff[t] = total;
     total += tot[t];
     biggest = std::max(biggest, tot[t]);
+  }
+  if (store_failed) {  // size the piece store for the next frame from this frame's counts
+    std::vector<int> pc(size_t(nt) * 64);
+    HIPCHK(hipMemcpyAsync(pc.data(), ctx->pcount.p, sizeof(int) * pc.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    long long chunks = 0;
+    int most = 0;
+    for (int c : pc) {
+      chunks += (c + apc::PIECE_CHUNK - 1) / apc::PIECE_CHUNK;
+      most = std::max(most, c);
+    }
+    ctx->pool_target = std::max(ctx->pool_target, chunks + chunks / 50 + 1024);
+    ctx->maxc = std::max(ctx->maxc, (most + apc::PIECE_CHUNK - 1) / apc::PIECE_CHUNK + 8);
   }
   if ((st = stage_upload(ctx, ctx->tile_off.p, toff.data(), sizeof(long long) * nt, s)) != APC_OK) return st;
   HIPCHK(apc::launch_piece_offsets(ctx->pcount.as<int>(), ctx->tile_off.as<long long>(), nt,
@@ -806,7 +883,7 @@ apc_status apc_resolve_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const
       HIPCHK(ev_mark(ctx, EV_EVL, 0, s));
     }
     HIPCHK(apc::launch_eval(mb->m, f, t0, t1, ctx->poff.as<long long>(), toff[t0], cap_pieces,
-                            ctx->stage.as<float>(), tf->rgba, moments, bp, rgba, ctr, s));
+                            ctx->stage.as<float>(), no_store, nullptr, tf->rgba, moments, bp, rgba, ctr, s));
     if (first) HIPCHK(ev_mark(ctx, EV_EVL, 1, s));
     first = false;
     t0 = t1;
@@ -856,10 +933,15 @@ apc_status apc_frame_graph_create(apc_ctx ctx, apc_mesh m, const apc_view* view,
     if (r == APC_OK) r = apc_resolve_pass(w, m, view, tf, mb, moments_global, subs, n_sub, rgba_out, flags, g->cs);
     return r;
   };
-  // 1) an eager frame sizes every workspace buffer
-  st = frame();
-  if (st == APC_OK && hipStreamSynchronize(g->cs) != hipSuccess) st = fail(APC_E_DEVICE, "sizing frame failed");
-  if (st == APC_OK && w->last_chunks > 1)
+  // 1) eager frames size every workspace buffer (again while stage one's piece store overflowed: it grows
+  //    after such a frame)
+  for (int attempt = 0; attempt < 3; ++attempt) {
+    st = frame();
+    if (st == APC_OK && hipStreamSynchronize(g->cs) != hipSuccess) st = fail(APC_E_DEVICE, "sizing frame failed");
+    if (st != APC_OK || !w->store_failed_last) break;
+  }
+  if (st == APC_OK && w->store_failed_last) st = fail(APC_E_NOMEM, "the frame's pieces do not fit the piece store");
+  if (st == APC_OK && !w->store_ready && w->last_chunks > 1)
     st = fail(APC_E_NOMEM, "the frame's %lld pieces do not fit one staging buffer", (long long)w->last_pieces);
   // 2) the same frame captured: kernels only (no uploads, host reads, event records or allocations)
   if (st == APC_OK) {

@@ -49,6 +49,19 @@ struct FrameDev {
   float minv[9];  // inverse of the 3x3 matrix with columns dir, right, down (screen projection)
 };
 
+// Pieces kept by stage one for stage two: a pool of PIECE_CHUNK-piece chunks
+// handed out by a device counter, and per pixel (tile-major slot) the ids of
+// its chunks in walk order.  A lane that cannot get a chunk stops keeping
+// pieces and counts a failure; stage two then walks the frame again.
+constexpr int PIECE_CHUNK = 64;
+struct PieceStore {
+  float* pool;               // [n_chunks][PIECE_CHUNK][3]: z, a, s
+  long long n_chunks;
+  int* ptab;                 // [n_tiles * 64][maxc]
+  int maxc;
+  unsigned long long* next;  // [0]: chunks handed out, [1]: lanes that failed
+};
+
 // Moment-bound parameters in the precision of the resolve pass.
 struct BoundParams {
   double alpha, eta;
@@ -73,7 +86,8 @@ hipError_t launch_bin_fill(const MeshDev& m, const FrameDev& f, const SlotDev* s
 // ([2][H][W], may be null) the segments per pixel and the subdomains with pieces on each ray
 hipError_t launch_moments(int mm, const MeshDev& m, const FrameDev& f, const SlotDev* slots, const int* offsets,
                           const int* counts, const int* records, long long bin_cap, const float* tf_rgba, float* out,
-                          int* pcount, int* segs, unsigned long long* counters, hipStream_t s);
+                          int* pcount, int* segs, const PieceStore& store, unsigned long long* counters,
+                          hipStream_t s);
 // stage two, walk part: mode 0 counts pieces per pixel into pcount; mode 1 writes the
 // pieces of tiles [tile_lo, tile_hi) as (z, a, s) at rec + 3 * (poff[pixel] - base), for
 // pixels whose pieces end within rec_cap pieces of base.  Bins whose records end beyond
@@ -82,10 +96,12 @@ hipError_t launch_stage(int mode, const MeshDev& m, const FrameDev& f, const Slo
                         const int* counts, const int* records, long long bin_cap, const float* tf_rgba, int tile_lo,
                         int tile_hi, int* pcount, const long long* poff, long long base, long long rec_cap,
                         float* rec, unsigned long long* counters, hipStream_t s);
-// stage two, evaluation part for tiles [tile_lo, tile_hi) (tiles staged beyond rec_cap stay empty)
+// stage two, evaluation part for tiles [tile_lo, tile_hi) (tiles staged beyond rec_cap stay empty);
+// with store.pool set the pieces come from stage one's chunks (pcount per pixel) instead
 hipError_t launch_eval(int mm, const FrameDev& f, int tile_lo, int tile_hi, const long long* poff, long long base,
-                       long long rec_cap, const float* rec, const float* tf_rgba, const void* moments,
-                       const BoundParams& bp, float* rgba, unsigned long long* counters, hipStream_t s);
+                       long long rec_cap, const float* rec, const PieceStore& store, const int* pcount,
+                       const float* tf_rgba, const void* moments, const BoundParams& bp, float* rgba,
+                       unsigned long long* counters, hipStream_t s);
 // exclusive scan of the per-tile piece totals on the device
 hipError_t launch_tile_offsets(const long long* tile_tot, int n_tiles, long long* tile_off, hipStream_t s);
 // FP16 packing of a global moment image

@@ -422,12 +422,83 @@ __device__ __forceinline__ void flush_counts(const LaneCount& c, unsigned long l
 // subdomain at the largest workloads, where FP32 sums would drift by ~1e-5 of
 // b0; FP64 adds cost the same issue slot as FP32 ones here and need no
 // compensation terms.
+// A lane's share of the piece store: the chunk it is filling and the pieces
+// it kept so far (over all subdomains, in walk order).  Chunks come from a
+// block of STORE_BLOCK chunks that the wavefront takes with one atomic; the
+// block's state lives in LDS (its lanes diverge, so no register copy of it
+// stays current).  One atomic per chunk on a single counter was measured to
+// serialise: stage one took 5x as long.
+constexpr int STORE_BLOCK = 64;
+struct LaneStore {
+  PieceStore ps;
+  size_t slot;     // tile * 64 + lane
+  unsigned kept;
+  int chunk;
+  bool keep;
+  // LDS: first chunk of the wavefront's block and the chunks of it handed
+  // out.  Written by one lane and read by another lane in a later divergent
+  // region, so volatile: a value loaded earlier must not be reused.
+  volatile unsigned long long* blk_base;
+  volatile int* blk_used;
+  // append one piece; lanes that start a chunk at this point get consecutive
+  // chunks of the wavefront's block (and a new block when it runs out)
+  __device__ void put(float z, float a, float s, int lane) {
+    if (!keep) return;
+    if ((kept & (PIECE_CHUNK - 1)) == 0) {
+      const unsigned long long need = __ballot(1);
+      const int leader = __ffsll((long long)need) - 1;
+      const int n = __popcll(need);
+      const int r = __popcll(need & ((1ull << lane) - 1));
+      unsigned long long base = 0, fresh = 0;
+      int used = 0;
+      if (lane == leader) {
+        base = *blk_base;
+        used = *blk_used;
+      }
+      used = __shfl(used, leader, WAVE);
+      const int rem = STORE_BLOCK - used;
+      if (n > rem && lane == leader) fresh = atomicAdd(ps.next, (unsigned long long)STORE_BLOCK);
+      const unsigned b_lo = __shfl(unsigned(base & 0xffffffffull), leader, WAVE);
+      const unsigned b_hi = __shfl(unsigned(base >> 32), leader, WAVE);
+      const unsigned f_lo = __shfl(unsigned(fresh & 0xffffffffull), leader, WAVE);
+      const unsigned f_hi = __shfl(unsigned(fresh >> 32), leader, WAVE);
+      base = (static_cast<unsigned long long>(b_hi) << 32) | b_lo;
+      fresh = (static_cast<unsigned long long>(f_hi) << 32) | f_lo;
+      const unsigned long long id = r < rem ? base + used + r : fresh + (r - rem);
+      if (lane == leader) {
+        if (n > rem) {
+          *blk_base = fresh;
+          *blk_used = n - rem;
+        } else {
+          *blk_used = used + n;
+        }
+      }
+      const unsigned k = kept / PIECE_CHUNK;
+      if (id < static_cast<unsigned long long>(ps.n_chunks) && k < unsigned(ps.maxc)) {
+        chunk = int(id);
+        ps.ptab[slot * ps.maxc + k] = chunk;
+      } else {
+        keep = false;
+        atomicAdd(ps.next + 1, 1ull);
+        return;
+      }
+    }
+    float* o = ps.pool + (size_t(chunk) * PIECE_CHUNK + (kept & (PIECE_CHUNK - 1))) * 3;
+    o[0] = z;
+    o[1] = a;
+    o[2] = s;
+    ++kept;
+  }
+};
+
 template <int M1>
 struct MomentSink {
   const FrameDev* f;
   const float* tfa;  // LDS alpha column of the table
   double b[M1];
   unsigned pieces;
+  LaneStore st;      // st.keep false: pieces are not kept
+  int lane;
   __device__ void chord(float t0, float t1, float s0, float s1) {
     cut_chord(*f, t0, t1, s0, s1, [&](float tm, float len, float s) {
       int i0;
@@ -441,6 +512,7 @@ struct MomentSink {
         b[j] += double(term);
         term *= z;
       }
+      st.put(z, a, s, lane);
       ++pieces;
     });
   }
@@ -456,7 +528,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_WALK_W
                                                   const int* __restrict__ offsets, const int* __restrict__ counts,
                                                   const int* __restrict__ records, const float* __restrict__ tf_rgba,
                                                   float* __restrict__ out, int* __restrict__ pcount,
-                                                  int* __restrict__ segs, long long bin_cap,
+                                                  int* __restrict__ segs, long long bin_cap, PieceStore ps,
                                                   unsigned long long* ctr) {
   extern __shared__ float4 dyn_lds[];
   float* tfa = reinterpret_cast<float*>(dyn_lds);  // [n_tf] alpha column
@@ -475,13 +547,21 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_WALK_W
   EntryList L{ent_t, ent_c, lane};
   LaneCount cnt = {};
   int covering = 0;  // subdomains with at least one piece on this ray
+  MomentSink<M1> sink;  // one sink for all subdomains: its piece store runs across them
+  sink.f = &f;
+  sink.tfa = tfa;
+  __shared__ unsigned long long blk_base;
+  __shared__ int blk_used;
+  if (lane == 0) {
+    blk_base = 0;
+    blk_used = STORE_BLOCK;  // no block yet
+  }
+  sink.st = LaneStore{ps, size_t(tile) * WAVE + lane, 0u, -1, ps.pool != nullptr && valid, &blk_base, &blk_used};
+  sink.lane = lane;
   __syncthreads();
   for (int k = 0; k < f.n_slots; ++k) {
     const int bin = tile * f.n_slots + k;
     const int n_rec = counts[bin];
-    MomentSink<M1> sink;
-    sink.f = &f;
-    sink.tfa = tfa;
     sink.pieces = 0;
 #pragma unroll
     for (int j = 0; j < M1; ++j) sink.b[j] = 0.0;
@@ -674,6 +754,7 @@ template <int N, class R>
 __global__ __launch_bounds__(WAVE * EVAL_WPB) __attribute__((amdgpu_waves_per_eu(N >= 4 ? APC_EVAL_WAVES_N4 : APC_EVAL_WAVES, 8))) void k_eval(
     FrameDev f, int tile_lo, int tile_hi, const long long* __restrict__ poff,
                                                long long base, long long rec_cap, const float* __restrict__ rec,
+                                               PieceStore ps, const int* __restrict__ pcount,
                                                const float* __restrict__ tf_rgba, const void* __restrict__ moments,
                                                BoundParams bp, float* __restrict__ rgba,
                                                unsigned long long* ctr) {
@@ -708,11 +789,27 @@ __global__ __launch_bounds__(WAVE * EVAL_WPB) __attribute__((amdgpu_waves_per_eu
   const bool valid = px < f.W && py < f.H;
   const size_t HW = size_t(f.W) * f.H, pix = size_t(py) * f.W + px;
   const size_t slot0 = size_t(tile) * WAVE;
-  const long long tile_base = poff[slot0];
-  // a tile whose pieces lie beyond the staging buffer was not staged: it is left empty (counted)
-  const bool staged = poff[slot0 + WAVE] - base <= rec_cap;
-  off_lds[lane] = staged ? int(poff[slot0 + lane] - tile_base) : 0;
-  if (lane == 0) off_lds[WAVE] = staged ? int(poff[slot0 + WAVE] - tile_base) : 0;
+  const bool chunked = ps.pool != nullptr;  // pieces kept by stage one
+  long long tile_base = 0;
+  bool staged = true;
+  if (chunked) {  // per-pixel offsets within the tile: scan of the piece counts
+    // a lane of stage one that could not keep its pieces leaves its chunk table unset: then nothing is read
+    staged = ps.next[1] == 0;
+    int c = staged ? pcount[slot0 + lane] : 0;
+    const int own = c;
+    for (int o = 1; o < WAVE; o <<= 1) {
+      const int up = __shfl_up(c, o, WAVE);
+      if (lane >= o) c += up;
+    }
+    off_lds[lane] = c - own;
+    if (lane == WAVE - 1) off_lds[WAVE] = c;
+  } else {
+    // a tile whose pieces lie beyond the staging buffer was not staged: it is left empty (counted)
+    tile_base = poff[slot0];
+    staged = poff[slot0 + WAVE] - base <= rec_cap;
+    off_lds[lane] = staged ? int(poff[slot0 + lane] - tile_base) : 0;
+    if (lane == 0) off_lds[WAVE] = staged ? int(poff[slot0 + WAVE] - tile_base) : 0;
+  }
   LaneCount cnt = {};
   cnt.overflow += (!staged && lane == 0) ? 1u : 0u;
   // per-pixel part of Alg. 3, once per pixel instead of once per sample
@@ -744,7 +841,7 @@ __global__ __launch_bounds__(WAVE * EVAL_WPB) __attribute__((amdgpu_waves_per_eu
     mode_lds[lane] = valid ? bound.mode : 0;
   }
   wave_sync();
-  const float* trec = rec + 3 * (tile_base - base);
+  const float* trec = chunked ? nullptr : rec + 3 * (tile_base - base);
   const R eta = R(bp.eta);
   float4 mine = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   for (int p = 0; p < WAVE; ++p) {  // uniform loop over the tile's pixels
@@ -776,8 +873,25 @@ __global__ __launch_bounds__(WAVE * EVAL_WPB) __attribute__((amdgpu_waves_per_eu
       }
     }
     float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+    const int* chunks = chunked ? ps.ptab + (slot0 + p) * size_t(ps.maxc) : nullptr;
+    // the pixel's first 64 chunk ids, one per lane, fetched before the loop
+    const int n_ch = (hi - lo + PIECE_CHUNK - 1) / PIECE_CHUNK;
+    const int my_ch = (chunked && lane < n_ch && lane < ps.maxc) ? chunks[lane] : 0;
     for (int i = lo + lane; i < hi; i += WAVE) {
-      const float z = trec[3 * i], a = trec[3 * i + 1], s = trec[3 * i + 2];
+      // piece j = i - lo of the pixel: chunk j / 64 (the same for the whole wavefront), slot j % 64 = lane
+      const float* pr;
+      if (chunked) {
+        const int k = (i - lo) / PIECE_CHUNK;
+        const unsigned ch = unsigned(k < WAVE ? __shfl(my_ch, k, WAVE) : chunks[k]);
+        if (ch >= unsigned(ps.n_chunks)) {  // cannot happen when every lane kept its pieces; never read
+          cnt.overflow += 1u;
+          continue;
+        }
+        pr = ps.pool + (size_t(ch) * PIECE_CHUNK + (i - lo) % PIECE_CHUNK) * 3;
+      } else {
+        pr = trec + 3 * size_t(i);
+      }
+      const float z = pr[0], a = pr[1], s = pr[2];
       R F = R(0);
       bool closed = true;
       if constexpr (TABLES) {
@@ -1147,18 +1261,19 @@ hipError_t launch_bin_fill(const MeshDev& m, const FrameDev& f, const SlotDev* s
 
 hipError_t launch_moments(int mm, const MeshDev& m, const FrameDev& f, const SlotDev* slots, const int* offsets,
                           const int* counts, const int* records, long long bin_cap, const float* tf_rgba, float* out,
-                          int* pcount, int* segs, unsigned long long* counters, hipStream_t s) {
+                          int* pcount, int* segs, const PieceStore& store, unsigned long long* counters,
+                          hipStream_t s) {
   const size_t lds = size_t(f.n_tf) * sizeof(float);
   const dim3 grid(f.n_tiles), block(WAVE);
   if (mm == 4)
     hipLaunchKernelGGL(k_moments<5>, grid, block, lds, s, m, f, slots, offsets, counts, records, tf_rgba, out,
-                       pcount, segs, bin_cap, counters);
+                       pcount, segs, bin_cap, store, counters);
   else if (mm == 6)
     hipLaunchKernelGGL(k_moments<7>, grid, block, lds, s, m, f, slots, offsets, counts, records, tf_rgba, out,
-                       pcount, segs, bin_cap, counters);
+                       pcount, segs, bin_cap, store, counters);
   else
     hipLaunchKernelGGL(k_moments<9>, grid, block, lds, s, m, f, slots, offsets, counts, records, tf_rgba, out,
-                       pcount, segs, bin_cap, counters);
+                       pcount, segs, bin_cap, store, counters);
   return hipGetLastError();
 }
 
@@ -1174,21 +1289,21 @@ hipError_t launch_stage(int mode, const MeshDev& m, const FrameDev& f, const Slo
 }
 
 hipError_t launch_eval(int mm, const FrameDev& f, int tile_lo, int tile_hi, const long long* poff, long long base,
-                       long long rec_cap, const float* rec, const float* tf_rgba, const void* moments,
-                       const BoundParams& bp,
+                       long long rec_cap, const float* rec, const PieceStore& store, const int* pcount,
+                       const float* tf_rgba, const void* moments, const BoundParams& bp,
                        float* rgba, unsigned long long* counters, hipStream_t s) {
   if (tile_hi <= tile_lo) return hipSuccess;
   const size_t lds = size_t(f.n_tf) * sizeof(float4);
   const dim3 grid((tile_hi - tile_lo + EVAL_WPB - 1) / EVAL_WPB), block(WAVE * EVAL_WPB);
   if (mm == 4)
     hipLaunchKernelGGL((k_eval<2, float>), grid, block, lds, s, f, tile_lo, tile_hi, poff, base, rec_cap, rec,
-                       tf_rgba, moments, bp, rgba, counters);
+                       store, pcount, tf_rgba, moments, bp, rgba, counters);
   else if (mm == 6)
     hipLaunchKernelGGL((k_eval<3, double>), grid, block, lds, s, f, tile_lo, tile_hi, poff, base, rec_cap, rec,
-                       tf_rgba, moments, bp, rgba, counters);
+                       store, pcount, tf_rgba, moments, bp, rgba, counters);
   else
     hipLaunchKernelGGL((k_eval<4, double>), grid, block, lds, s, f, tile_lo, tile_hi, poff, base, rec_cap, rec,
-                       tf_rgba, moments, bp, rgba, counters);
+                       store, pcount, tf_rgba, moments, bp, rgba, counters);
   return hipGetLastError();
 }
 
