@@ -877,12 +877,15 @@ __global__ __launch_bounds__(WAVE * EVAL_WPB) __attribute__((amdgpu_waves_per_eu
     // the pixel's first 64 chunk ids, one per lane, fetched before the loop
     const int n_ch = (hi - lo + PIECE_CHUNK - 1) / PIECE_CHUNK;
     const int my_ch = (chunked && lane < n_ch && lane < ps.maxc) ? chunks[lane] : 0;
-    for (int i = lo + lane; i < hi; i += WAVE) {
+    for (int ib = lo; ib < hi; ib += WAVE) {  // uniform: every lane takes part in the shuffle below
+      const int i = ib + lane;
       // piece j = i - lo of the pixel: chunk j / 64 (the same for the whole wavefront), slot j % 64 = lane
+      const int k = (ib - lo) / PIECE_CHUNK;
+      const int ch_k = chunked ? (k < WAVE ? __shfl(my_ch, k, WAVE) : chunks[k]) : 0;
+      if (i >= hi) continue;
       const float* pr;
       if (chunked) {
-        const int k = (i - lo) / PIECE_CHUNK;
-        const unsigned ch = unsigned(k < WAVE ? __shfl(my_ch, k, WAVE) : chunks[k]);
+        const unsigned ch = unsigned(ch_k);
         if (ch >= unsigned(ps.n_chunks)) {  // cannot happen when every lane kept its pieces; never read
           cnt.overflow += 1u;
           continue;
