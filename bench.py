@@ -63,6 +63,36 @@ def measured_traffic(args, kernel):
         b["fetch_bytes"], b["write_bytes"])
 
 
+def serve_run(n_requests):
+    """p50/p99 frame latency of a served request stream, batched (4 slots) and one at a time."""
+    import synth
+    from paper_2501_12581_amd.serve import Server
+    t0 = time.time()
+    sc = synth.scene_batching(n=144)
+    m = sc.mesh
+    tfs = [synth.make_tf(s) for s in (21, 22, 23)]
+    srv = Server((m.xyz, m.scalar, m.tets, m.tet_sub, m.n_sub), sc.step, tfs, (sc.s_min, sc.s_max), slots=4,
+                 workspace_limit=32 << 30, hbm_budget=64 << 30)
+    log("serving: %d tets, 72 uneven subdomains, resident in %.1fs" % (m.n_tets, time.time() - t0))
+    warm = synth.request_stream(8, rate=1000.0, seed=99)
+    srv.run(warm, "batched")
+    srv.run(warm, "fifo")
+    res = {}
+    for rate in (50.0, 8.0):  # the specified rate, and one this GPU can sustain for this mix
+        reqs = synth.request_stream(n_requests, rate=rate, seed=12)
+        for mode in ("batched", "fifo"):
+            st = srv.run(reqs, mode)
+            st.pop("records")
+            res["%s_%g" % (mode, rate)] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
+            log("serving %g/s %s: %s" % (rate, mode, res["%s_%g" % (mode, rate)]))
+    srv.close()
+    return {"workload": "batching mesh: %d tets (jittered 144^3 Kuhn grid), 72 Morton subdomains of weight ratio 12; "
+                        "%d requests per run, Poisson arrivals, sizes {256,512,1024,2048}^2, m in {4,6,8}, "
+                        "3 transfer functions, cameras on the radius-2 sphere" % (m.n_tets, n_requests),
+            "rate_50_per_s": {"batched": res["batched_50"], "one_at_a_time": res["fifo_50"]},
+            "rate_8_per_s": {"batched": res["batched_8"], "one_at_a_time": res["fifo_8"]}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,7 +104,9 @@ def main():
     ap.add_argument("--size", type=int, default=None, help="override the image size (square)")
     ap.add_argument("--grid", type=int, default=None, help="override cubes per axis (large workload)")
     ap.add_argument("--cpu-pixels", type=int, default=65536, help="oracle sample size (0 = skip)")
-    ap.add_argument("--profile-steps", action="store_true", help="no oracle leg (for profiler runs)")
+    ap.add_argument("--profile-steps", action="store_true", help="no oracle leg and no serving run (for profiler runs)")
+    ap.add_argument("--serve-requests", type=int, default=120,
+                    help="requests of the serving run (Poisson, 50/s, batching mesh); 0 = skip")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (scales the HBM byte counters of a profiler run)")
     args = ap.parse_args()
@@ -241,6 +273,17 @@ def main():
             "moment_image_bytes": int(r.moments_h.numel() * 2), "fp32_moment_image_bytes": int(r.moments.numel() * 4)}}
         log("variants %s" % variants)
 
+    # ---- serving: continuous batching vs one request at a time (after the frame buffers are released)
+    serving = None
+    if args.serve_requests > 0 and not args.profile_steps:
+        del r
+        import gc
+        gc.collect()
+        ctx.close()
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        serving = serve_run(args.serve_requests)
+
     out = {
         "metric": METRIC, "value": round(samples_per_s, 1), "unit": "samples/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
@@ -255,6 +298,7 @@ def main():
         "kernels_ms": {k: round(v, 3) for k, v in kern.items()},
         "frame_ms_each": [round(x, 2) for x in frame_ms],
         "segments": seg_stats, "counters": cnt, "roofline": roofline, "cpu_baseline": cpu, "parity": parity, "variants": variants,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 

@@ -239,6 +239,14 @@ apc_status apc_sum_images(apc_ctx ctx, const float* partials, int32_t n_sub, int
                           const int32_t* subdomains, const float* moments_global, const apc_mboit* mboit,
                           float* rgba_out, void* stream);
 
+/* Bound the context's two large workspace buffers, the kept-piece pool and the
+ * re-walk staging buffer, to bytes/2 each (0: each may take 60 % of the free
+ * device memory, the default).  A frame whose pieces exceed the pool walks
+ * again in stage two; one that exceeds the staging buffer is resolved in
+ * chunks of tiles (same results).  Lets several contexts (e.g. a server's
+ * slots) share one GPU with a known footprint. */
+apc_status apc_set_workspace_limit(apc_ctx ctx, int64_t bytes);
+
 /* ------------------------------------------------------------------ frame graphs */
 
 /* A whole frame (apc_moments_pass, apc_sum_moments, apc_resolve_pass for one

@@ -27,7 +27,8 @@ EXPORTS = ["apc_create", "apc_destroy", "apc_last_error", "apc_version", "apc_lo
            "apc_mesh_get_info", "apc_mesh_subdomain_info", "apc_moments_pass", "apc_sum_moments",
            "apc_resolve_pass", "apc_sum_images", "apc_pack_moments_f16", "apc_segment_counts", "apc_get_counters",
            "apc_get_timings", "apc_set_tile_shape", "apc_get_tile_shape", "apc_autotune_tile_shape",
-           "apc_frame_graph_create", "apc_frame_graph_launch", "apc_frame_graph_counters", "apc_frame_graph_destroy"]
+           "apc_frame_graph_create", "apc_frame_graph_launch", "apc_frame_graph_counters", "apc_frame_graph_destroy",
+           "apc_set_workspace_limit"]
 
 
 class ApcError(RuntimeError):
@@ -112,6 +113,8 @@ def lib():
                                        C.c_int32, vp, C.c_uint32, vp]
         L.apc_pack_moments_f16.restype = st
         L.apc_pack_moments_f16.argtypes = [vp, vp, C.c_int32, C.c_int32, C.c_int32, vp, vp]
+        L.apc_set_workspace_limit.restype = st
+        L.apc_set_workspace_limit.argtypes = [vp, C.c_int64]
         L.apc_frame_graph_create.restype = st
         L.apc_frame_graph_create.argtypes = [vp, vp, C.POINTER(View), C.POINTER(TF), C.POINTER(Mboit), vp, C.c_int32,
                                              vp, vp, vp, C.c_uint32, C.POINTER(vp)]
@@ -283,6 +286,10 @@ class Context:
                                                  (mboit.m + 1, view.height, view.width), "moments"), ptr, len(ids),
                                         _dev_ptr(out, torch.float32, (view.height, view.width, 4), "rgba"),
                                         flags, _stream(stream)))
+
+    def set_workspace_limit(self, nbytes):
+        """Cap the kept-piece pool and the re-walk staging buffer at nbytes/2 each (0: default policy)."""
+        self._ck(lib().apc_set_workspace_limit(self.handle, int(nbytes)))
 
     def set_tile_shape(self, tile_width):
         self._ck(lib().apc_set_tile_shape(self.handle, int(tile_width)))

@@ -58,7 +58,7 @@ thread_local bool g_frozen = false;
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
-  hipError_t ensure(size_t need) {
+  hipError_t ensure(size_t need, bool slack = true) {
     if (need <= bytes) return hipSuccess;
     if (g_frozen) return hipErrorOutOfMemory;
     if (p) {
@@ -67,7 +67,7 @@ struct DevBuf {
       p = nullptr;
       bytes = 0;
     }
-    size_t nb = std::max<size_t>(need + need / 4, 4096);
+    size_t nb = std::max<size_t>(slack ? need + need / 4 : need, 4096);
     hipError_t e = hipMalloc(&p, nb);
     if (e != hipSuccess) return e;
     bytes = nb;
@@ -121,6 +121,7 @@ struct apc_ctx_s {
   bool store_ready = false;          // the last stage one kept its pieces (if none failed)
   apc_tf store_tf = {};              // the transfer function they were made with
   bool store_failed_last = false;    // the last resolve found that stage one could not keep every piece
+  int64_t ws_limit = 0;              // bytes for the piece pool + staging buffer (0: 60 % of free memory each)
 };
 
 struct apc_graph_s {
@@ -680,12 +681,16 @@ apc_status apc_moments_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const
     if (ctx->pool_chunks < ctx->pool_target && !ctx->capturing) {
       size_t free_b = 0, total_b = 0;
       HIPCHK(hipMemGetInfo(&free_b, &total_b));
-      const size_t limit = size_t(0.6 * double(free_b + ctx->pool.bytes));
+      const size_t limit = ctx->ws_limit > 0 ? size_t(ctx->ws_limit / 2) : size_t(0.6 * double(free_b + ctx->pool.bytes));
       const size_t want = std::min(size_t(ctx->pool_target) * chunk_bytes, limit);
-      ctx->pool.release();
-      ctx->pool_chunks = 0;
-      if (ctx->pool.ensure(want) == hipSuccess) ctx->pool_chunks = (long long)(ctx->pool.bytes / chunk_bytes);
-      else ok = false;
+      if (want > ctx->pool.bytes) {
+        ctx->pool.release();
+        ctx->pool_chunks = 0;
+        if (ctx->pool.ensure(want, ctx->ws_limit == 0) == hipSuccess)
+          ctx->pool_chunks = (long long)(ctx->pool.bytes / chunk_bytes);
+        else
+          ok = false;
+      }
     }
     if (ok && ctx->ptab.ensure(sizeof(int) * slots * ctx->maxc) != hipSuccess) ok = false;
     if (ok && ctx->store_next.ensure(4 * sizeof(unsigned long long)) != hipSuccess) ok = false;
@@ -858,11 +863,11 @@ apc_status apc_resolve_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const
   if (want > ctx->stage.bytes) {
     size_t free_b = 0, total_b = 0;
     HIPCHK(hipMemGetInfo(&free_b, &total_b));
-    size_t cap = size_t(0.6 * double(free_b + ctx->stage.bytes));
+    size_t cap = ctx->ws_limit > 0 ? size_t(ctx->ws_limit / 2) : size_t(0.6 * double(free_b + ctx->stage.bytes));
     size_t need = std::min(want, cap);
     if (need < size_t(biggest) * rec_bytes) return fail(APC_E_NOMEM, "one tile's pieces do not fit in device memory");
     ctx->stage.release();
-    hipError_t e = ctx->stage.ensure(need);
+    hipError_t e = ctx->stage.ensure(need, ctx->ws_limit == 0);
     if (e != hipSuccess) return fail(APC_E_NOMEM, "staging %zu bytes: %s", need, hipGetErrorString(e));
   }
   const long long cap_pieces = (long long)(ctx->stage.bytes / rec_bytes);
@@ -979,6 +984,26 @@ apc_status apc_frame_graph_launch(apc_graph g, void* stream) {
 apc_status apc_frame_graph_counters(apc_graph g, apc_counters* out, int32_t reset) {
   if (!g) return fail(APC_E_ARG, "graph is NULL");
   return apc_get_counters(g->own, out, reset);
+}
+
+apc_status apc_set_workspace_limit(apc_ctx ctx, int64_t bytes) {
+  apc_status st = check_ctx(ctx);
+  if (st != APC_OK) return st;
+  if (bytes < 0) return fail(APC_E_ARG, "negative limit");
+  ctx->ws_limit = bytes;
+  // buffers above the new limit are given back
+  const size_t half = size_t(bytes / 2);
+  if (bytes > 0 && ctx->pool.bytes > half) {
+    HIPCHK(hipDeviceSynchronize());
+    ctx->pool.release();
+    ctx->pool_chunks = 0;
+    ctx->store_ready = false;
+  }
+  if (bytes > 0 && ctx->stage.bytes > half) {
+    HIPCHK(hipDeviceSynchronize());
+    ctx->stage.release();
+  }
+  return APC_OK;
 }
 
 apc_status apc_set_tile_shape(apc_ctx ctx, int32_t tile_width) {

@@ -1,0 +1,173 @@
+"""Render-request serving over the library: a resident mesh, continuous batching, admission by HBM footprint.
+
+A `Server` keeps one mesh resident and runs frames for a stream of requests (image size, camera, number of
+moments, transfer function).  It has `slots`: each slot is a library context (its own workspace, capped by
+`apc_set_workspace_limit`) with its own HIP stream, driven by one worker thread.  In "batched" mode a request
+is admitted as soon as it has arrived, a slot is free and its buffers fit the HBM budget beside the requests
+already in flight, so frames of different requests overlap on the device.  In "fifo" mode one request runs at
+a time in arrival order (the plain per-request form).  Every step of a frame runs in the library's kernels;
+this module only schedules, allocates buffers and times.
+"""
+from __future__ import annotations
+
+import math
+import queue
+import threading
+import time
+
+import numpy as np
+
+from . import Context, make_mboit, make_tf, make_view
+
+
+def look_at_view(eye, target, width: int, height: int, fovy_deg: float = 45.0) -> dict:
+    """Pinhole camera frame for apc_view: un-normalised pixel direction dir + (j+1/2-W/2) right + (i+1/2-H/2) down."""
+    e = np.asarray(eye, dtype=np.float64)
+    f = np.asarray(target, dtype=np.float64) - e
+    f /= np.linalg.norm(f)
+    up = np.array([0.0, 0.0, 1.0]) if abs(f[2]) <= 0.99 else np.array([0.0, 1.0, 0.0])
+    r = np.cross(f, up)
+    r /= np.linalg.norm(r)
+    u = np.cross(r, f)
+    t = math.tan(math.radians(fovy_deg) / 2.0)
+    return dict(width=width, height=height, projection=1, eye=tuple(e), dir=tuple(f),
+                right=tuple(r * (2.0 * t / width)), down=tuple(-u * (2.0 * t / height)))
+
+
+class Server:
+    def __init__(self, mesh, step, tfs, s_range, kappa=4.0, absorbance_max=10.0, alpha=5e-5, eta=0.3,
+                 slots=4, workspace_limit=8 << 30, hbm_budget=64 << 30, max_size=2048, max_m=8, device=0):
+        """mesh: arrays (xyz, scalar, tets, tet_sub, n_sub); tfs: list of [n][4] float32 tables;
+        s_range: (s_min, s_max) of the transfer functions' domain; workspace_limit: bytes per slot for the
+        kept-piece pool + staging; hbm_budget: bytes of the requests' own buffers allowed in flight;
+        max_size, max_m: the largest request, for which every slot's buffers are allocated once (no
+        allocation while serving: device allocations would synchronise the other slots' work)."""
+        import torch
+        self.torch = torch
+        self.device = device
+        self.dev = torch.device("cuda:%d" % device)
+        self.owner = Context(device)
+        xyz, scalar, tets, tet_sub, n_sub = mesh
+        self.mesh = self.owner.load_mesh(xyz, scalar, tets, tet_sub, n_sub)
+        self.n_sub = n_sub
+        self.subs = np.arange(n_sub, dtype=np.int32)
+        self.step = step
+        self.tf_dev = [torch.as_tensor(np.ascontiguousarray(t, dtype=np.float32), device=self.dev) for t in tfs]
+        self.s_range = s_range
+        self.kappa, self.absorbance_max = kappa, absorbance_max
+        self.alpha, self.eta = alpha, eta
+        self.slots = []
+        self.bufs = []
+        self.max_size, self.max_m = max_size, max_m
+        px = max_size * max_size
+        for _ in range(slots):
+            c = Context(device)
+            c.set_workspace_limit(workspace_limit)
+            self.slots.append((c, torch.cuda.Stream(device=self.dev)))
+            self.bufs.append((torch.empty(n_sub * (max_m + 1) * px, dtype=torch.float32, device=self.dev),
+                              torch.empty((max_m + 1) * px, dtype=torch.float32, device=self.dev),
+                              torch.empty(4 * px, dtype=torch.float32, device=self.dev)))
+        self.workspace_limit = workspace_limit
+        self.hbm_budget = hbm_budget
+
+    def footprint(self, req) -> int:
+        """Bytes of one request's own buffers: per-subdomain and global moments, image."""
+        px = req["size"] ** 2
+        return px * (4 * (self.n_sub + 1) * (req["m"] + 1) + 16)
+
+    def _bias(self, m):
+        j = np.arange(1, m + 1)
+        return np.where(j % 2 == 0, 1.0 / (j + 1.0), 0.0)
+
+    def render(self, slot: int, req) -> "object":
+        """One frame for `req` on slot `slot` (stage one, moment sum, resolve); returns the RGBA image (a view
+        of the slot's buffer, valid until the slot's next request) after the slot's stream has finished it."""
+        torch = self.torch
+        ctx, stream = self.slots[slot]
+        W = H = req["size"]
+        m = req["m"]
+        view = make_view(look_at_view(req["eye"], (0.5, 0.5, 0.5), W, H), self.step)
+        tf = make_tf(self.tf_dev[req["tf"]], self.s_range[0], self.s_range[1], self.kappa, self.absorbance_max)
+        mb = make_mboit(m, self.alpha, self._bias(m), self.eta, 1)
+        if W > self.max_size or m > self.max_m:
+            raise ValueError("request larger than the server's slots (%d^2, m=%d)" % (self.max_size, self.max_m))
+        b_sub, b_mom, b_rgba = self.bufs[slot]
+        per_sub = b_sub[: self.n_sub * (m + 1) * H * W].view(self.n_sub, m + 1, H, W)
+        mom = b_mom[: (m + 1) * H * W].view(m + 1, H, W)
+        rgba = b_rgba[: 4 * H * W].view(H, W, 4)
+        s = stream.cuda_stream
+        ctx.moments_pass(self.mesh, view, tf, m, self.subs, per_sub, s)
+        ctx.sum_moments(per_sub, m, self.subs, mom, s)
+        ctx.resolve_pass(self.mesh, view, tf, mb, mom, self.subs, rgba, finalize=True, stream=s)
+        stream.synchronize()
+        return rgba
+
+    def run(self, requests, mode="batched", keep_images=False) -> dict:
+        """Serve `requests` (dicts with arrival [s], size, eye, m, tf) open loop: request k is released at
+        its arrival time after the start.  Returns per-request records and latency statistics."""
+        if mode not in ("batched", "fifo"):
+            raise ValueError(mode)
+        n_slots = len(self.slots) if mode == "batched" else 1
+        reqs = sorted(requests, key=lambda r: r["arrival"])
+        free = queue.Queue()
+        for k in range(n_slots):
+            free.put(k)
+        lock = threading.Lock()
+        inflight = [0]
+        done = {}
+        errors = []
+        t0 = time.perf_counter()
+
+        def work(slot, req):
+            start = time.perf_counter() - t0
+            try:
+                rgba = self.render(slot, req)
+                end = time.perf_counter() - t0
+                rec = {"id": req["id"], "arrival": req["arrival"], "start": start, "end": end,
+                       "latency": end - req["arrival"], "size": req["size"], "m": req["m"]}
+                if keep_images:
+                    rec["rgba"] = rgba.cpu()
+                done[req["id"]] = rec
+            except Exception as e:  # reported after the run
+                errors.append((req["id"], repr(e)))
+            finally:
+                with lock:
+                    inflight[0] -= self.footprint(req)
+                free.put(slot)
+
+        threads = []
+        for req in reqs:
+            wait = req["arrival"] - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(wait)
+            fp = self.footprint(req)
+            while True:  # admission: a free slot and room in the HBM budget (a lone request is always admitted)
+                slot = free.get()
+                with lock:
+                    fits = inflight[0] == 0 or inflight[0] + fp <= self.hbm_budget
+                    if fits:
+                        inflight[0] += fp
+                if fits:
+                    break
+                free.put(slot)
+                time.sleep(0.0005)
+            th = threading.Thread(target=work, args=(slot, req))
+            th.start()
+            threads.append(th)
+        for th in threads:
+            th.join()
+        if errors:
+            raise RuntimeError("requests failed: %s" % errors[:3])
+        recs = [done[r["id"]] for r in reqs]
+        lat = np.array([r["latency"] for r in recs]) * 1e3
+        span = max(r["end"] for r in recs) - min(r["arrival"] for r in recs)
+        return {"mode": mode, "slots": n_slots, "requests": len(recs),
+                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "mean_ms": float(lat.mean()), "frames_per_s": len(recs) / span, "records": recs}
+
+    def close(self):
+        self.torch.cuda.synchronize(self.dev)
+        for c, _ in self.slots:
+            c.close()
+        self.mesh.free()
+        self.owner.close()

@@ -147,12 +147,16 @@ def signed_volumes(xyz: np.ndarray, tets: np.ndarray) -> np.ndarray:
     return np.einsum("ij,ij->i", a, np.cross(b, c))
 
 
-def partition_chunks(n_cells: int, n_sub: int, seed: int | None, jagged: float = 0.5) -> np.ndarray:
+def partition_chunks(n_cells: int, n_sub: int, seed: int | None, jagged: float = 0.5,
+                     weights: np.ndarray | None = None) -> np.ndarray:
     """Chunk boundaries [n_sub+1] of contiguous runs of Morton-ordered cells.
 
-    Chunk weights are 1 + jagged*U(-1,1) (seeded) or equal when seed is None.
+    Chunk weights are `weights` when given, else 1 + jagged*U(-1,1) (seeded)
+    or equal when seed is None.
     """
-    if seed is None:
+    if weights is not None:
+        w = np.asarray(weights, dtype=np.float64)
+    elif seed is None:
         w = np.ones(n_sub)
     else:
         w = 1.0 + jagged * np.random.default_rng(seed).uniform(-1.0, 1.0, size=n_sub)
@@ -246,7 +250,7 @@ def default_bias(m: int) -> np.ndarray:
 # ----------------------------------------------------------------------------- workloads
 
 def grid_mesh(n: int, n_sub: int, seed: int, n_gauss: int, jagged_seed: int | None, jitter: float = 0.15,
-              sub_of_cube: np.ndarray | None = None) -> Mesh:
+              sub_of_cube: np.ndarray | None = None, chunk_weights: np.ndarray | None = None) -> Mesh:
     rng = np.random.default_rng(seed + 1)
     xyz = jittered_grid(n, seed, jitter)
     order = morton_order(n)
@@ -254,7 +258,7 @@ def grid_mesh(n: int, n_sub: int, seed: int, n_gauss: int, jagged_seed: int | No
     centres = rng.uniform(0.2, 0.8, size=(n_gauss, 3))
     scalar = gaussian_field(xyz, centres)
     if sub_of_cube is None:
-        bounds = partition_chunks(n ** 3, n_sub, jagged_seed)
+        bounds = partition_chunks(n ** 3, n_sub, jagged_seed, weights=chunk_weights)
         rank = np.empty(n ** 3, dtype=np.int64)
         rank[order] = np.arange(n ** 3)
         sub_of_cube = (np.searchsorted(bounds, rank, side="right") - 1).astype(np.int32)
@@ -322,3 +326,36 @@ def scene_slabs(n_ranks: int = 16, slabs_per_rank: int = 4, cells_per_slab: int 
     else:
         view = perspective_view(sphere_eye(seed + 3 + 97 * camera), (0.5, 0.5, 0.5), size, size)
     return _scene("slabs", mesh, view, n, m, tf_seed=seed + 11)
+
+
+def uneven_weights(n_sub: int, ratio: float, seed: int) -> np.ndarray:
+    """Chunk weights ratio^(k/(n_sub-1)), k = 0..n_sub-1, in a seeded order: max/min = ratio."""
+    w = ratio ** (np.arange(n_sub) / (n_sub - 1.0))
+    return np.random.default_rng(seed).permutation(w)
+
+
+def scene_batching(n: int = 144, size: int = 1024, m: int = 8, seed: int = 7, camera: int = 0) -> Scene:
+    """Uneven-subdomain workload: jittered n^3 grid x 6 tets (144: 17,915,904 tets), 72 Morton chunks with
+    weights 12^(k/71) in seeded order (largest / smallest = 12), perspective camera on the radius-2 sphere.
+    Uniform cells stand in for the 0-3 level refinement of an AMR mesh (not generated here)."""
+    w = uneven_weights(72, 12.0, seed + 5)
+    mesh = grid_mesh(n, 72, seed, n_gauss=16, jagged_seed=None, chunk_weights=w)
+    view = perspective_view(sphere_eye(seed + 3 + 97 * camera), (0.5, 0.5, 0.5), size, size)
+    return _scene("batching", mesh, view, n, m, tf_seed=seed + 11)
+
+
+def request_stream(n: int, rate: float = 50.0, seed: int = 12, sizes=(256, 512, 1024, 2048), ms=(4, 6, 8),
+                   n_tf: int = 3) -> list:
+    """Open-loop Poisson stream of render requests: exponential inter-arrival times (mean 1/rate seconds),
+    each with an image size, a camera on the radius-2 sphere around the cube's centre, a moment count and
+    one of n_tf transfer functions, all drawn from one seeded generator."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=n))
+    out = []
+    for k in range(n):
+        v = rng.normal(size=3)
+        v /= np.linalg.norm(v)
+        out.append({"id": k, "arrival": float(t[k]), "size": int(rng.choice(sizes)),
+                    "eye": tuple((np.array([0.5, 0.5, 0.5]) + 2.0 * v).tolist()),
+                    "m": int(rng.choice(ms)), "tf": int(rng.integers(n_tf))})
+    return out

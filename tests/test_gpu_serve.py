@@ -1,0 +1,54 @@
+"""Serving (continuous batching over the C ABI): every request's image is the
+same alone and in the mix, requests overlap on the device, and a served frame
+matches the oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def server():
+    import paper_2501_12581_amd as P
+    from paper_2501_12581_amd.serve import Server
+    P.lib()
+    sc = synth.scene_medium(size=128)
+    m = sc.mesh
+    tfs = [synth.make_tf(s) for s in (13, 14, 15)]
+    srv = Server((m.xyz, m.scalar, m.tets, m.tet_sub, m.n_sub), sc.step, tfs, (sc.s_min, sc.s_max), slots=3,
+                 workspace_limit=1 << 30, hbm_budget=1 << 30)
+    yield srv, sc, tfs
+    srv.close()
+
+
+def test_each_result_is_the_same_alone_and_in_the_mix(server):
+    srv, sc, tfs = server
+    reqs = synth.request_stream(18, rate=400.0, seed=3, sizes=(96, 128, 192), ms=(4, 6, 8))
+    mix = srv.run(reqs, "batched", keep_images=True)
+    alone = srv.run(reqs, "fifo", keep_images=True)
+    for a, b in zip(mix["records"], alone["records"]):
+        assert a["id"] == b["id"]
+        assert torch.equal(a["rgba"], b["rgba"]), a["id"]
+    rec = mix["records"]
+    overlapped = any(r["start"] < q["end"] and q["start"] < r["end"] for i, r in enumerate(rec) for q in rec[i + 1:])
+    assert overlapped
+    assert mix["p50_ms"] <= mix["p99_ms"] and alone["p50_ms"] <= alone["p99_ms"]
+    print("batched p50 %.2f p99 %.2f ms, %.1f frames/s; fifo p50 %.2f p99 %.2f ms, %.1f frames/s" % (
+        mix["p50_ms"], mix["p99_ms"], mix["frames_per_s"], alone["p50_ms"], alone["p99_ms"], alone["frames_per_s"]))
+
+
+def test_served_frame_matches_oracle(server):
+    srv, sc, tfs = server
+    req = {"id": 0, "arrival": 0.0, "size": 96, "eye": (2.1, 1.3, -0.4), "m": 8, "tf": 2}
+    got = srv.render(0, req).cpu().numpy().astype(np.float64).reshape(-1, 4)
+    sc2 = synth.Scene(**{**sc.__dict__, "view": synth.perspective_view(req["eye"], (0.5, 0.5, 0.5), 96, 96),
+                         "m": 8, "bias": synth.default_bias(8), "tf": tfs[2]})
+    ref = oracle.render(sc2)
+    d = got - ref["rgba"]
+    assert np.abs(d).max() <= 2e-3 and math.sqrt(np.mean(d ** 2)) <= 5e-4
