@@ -877,24 +877,38 @@ __global__ __launch_bounds__(WAVE * EVAL_WPB) __attribute__((amdgpu_waves_per_eu
     // the pixel's first 64 chunk ids, one per lane, fetched before the loop
     const int n_ch = (hi - lo + PIECE_CHUNK - 1) / PIECE_CHUNK;
     const int my_ch = (chunked && lane < n_ch && lane < ps.maxc) ? chunks[lane] : 0;
-    for (int ib = lo; ib < hi; ib += WAVE) {  // uniform: every lane takes part in the shuffle below
+    // the piece of step ib for this lane (z, a, s), or ok = false past the pixel's end; every lane takes
+    // part in the shuffle
+    auto fetch = [&](int ib, float& z, float& a, float& s, bool& ok) {
       const int i = ib + lane;
-      // piece j = i - lo of the pixel: chunk j / 64 (the same for the whole wavefront), slot j % 64 = lane
       const int k = (ib - lo) / PIECE_CHUNK;
       const int ch_k = chunked ? (k < WAVE ? __shfl(my_ch, k, WAVE) : chunks[k]) : 0;
-      if (i >= hi) continue;
+      ok = i < hi;
+      if (!ok) return;
       const float* pr;
       if (chunked) {
         const unsigned ch = unsigned(ch_k);
         if (ch >= unsigned(ps.n_chunks)) {  // cannot happen when every lane kept its pieces; never read
           cnt.overflow += 1u;
-          continue;
+          ok = false;
+          return;
         }
         pr = ps.pool + (size_t(ch) * PIECE_CHUNK + (i - lo) % PIECE_CHUNK) * 3;
       } else {
         pr = trec + 3 * size_t(i);
       }
-      const float z = pr[0], a = pr[1], s = pr[2];
+      z = pr[0];
+      a = pr[1];
+      s = pr[2];
+    };
+    float nz = 0.0f, na = 0.0f, ns = 0.0f;
+    bool nok = false;
+    if (lo < hi) fetch(lo, nz, na, ns, nok);
+    for (int ib = lo; ib < hi; ib += WAVE) {  // uniform loop; the next step's piece is loaded first
+      const float z = nz, a = na, s = ns;
+      const bool ok = nok;
+      if (ib + WAVE < hi) fetch(ib + WAVE, nz, na, ns, nok);
+      if (!ok) continue;
       R F = R(0);
       bool closed = true;
       if constexpr (TABLES) {
