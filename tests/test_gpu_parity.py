@@ -52,13 +52,13 @@ def _moment_err(got, ref, b0=None):
     return float(np.max(np.abs(got[:, ~bg] - ref[:, ~bg]) / den)) if np.any(~bg) else 0.0
 
 
-def _check_moments(sc, pix, got, ref, tol=1e-5, per_sub=False):
-    """Forward bar |got - ref| <= tol * max(b0, B0_FLOOR) per pixel; pixels that miss it (at most 0.5% of
-    the covered ones) must pass the backward-error bar of oracle.parity.  Returns the forward error and
-    the number of pixels that needed the backward bar."""
+def _check_moments(sc, pix, got, ref, tol=1e-5, per_sub=False, max_backward=0.005):
+    """Forward bar |got - ref| <= tol * max(b0, B0_FLOOR) per pixel; pixels that miss it (at most a fraction
+    max_backward of the covered ones) must pass the backward-error bar of oracle.parity.  Returns the forward
+    error and the number of pixels that needed the backward bar."""
     res = moment_parity(sc, pix, got, ref, tol=tol, floor=B0_FLOOR, per_sub=per_sub)
     assert res["background_exact"], "moments on background pixels"
-    assert res["backward_bar_pixels"] <= max(3, 0.005 * res["covered"]), ("too many pixels off", res)
+    assert res["backward_bar_pixels"] <= max(3, max_backward * res["covered"]), ("too many pixels off", res)
     assert res["outside_backward_band"] == 0, ("outside the backward-error band", res)
     return res["forward_max"], res["backward_bar_pixels"]
 
@@ -418,3 +418,45 @@ def test_kept_pieces_match_rewalk(apc, ctx, m):
     t = ctx.timings()
     assert t["stage_ms"] == 0 and t["eval_ms"] > 0  # no second walk
     assert torch.equal(kept, walked)
+
+
+def test_large_full_size_sampled_pixels_match_oracle(apc, ctx):
+    """The full-size configuration the benchmark times (256^3 x 6 = 100,663,296 tets, 72 subdomains,
+    2560^2 perspective, m = 8), in its launch configuration (a warm-up frame, then a frame that keeps its
+    pieces): 3,000 seeded pixels against the oracle (moments by the forward or backward-error bar, RGBA
+    by the image bar), and both frames' images equal."""
+    sc = synth.scene_large()
+    r = apc.Renderer(ctx, sc)
+    first = r.frame().clone()
+    ctx.counters(reset=True)
+    rgba = r.frame()
+    torch.cuda.synchronize()
+    assert ctx.timings()["stage_ms"] == 0  # the timed frame evaluates the kept pieces
+    assert torch.equal(rgba, first)
+    W, H = sc.view["width"], sc.view["height"]
+    pix = np.sort(np.random.default_rng(17).choice(W * H, 3000, replace=False))
+    ref = oracle.render(sc, pixels=pix)
+    # ~1,000 tets per ray: more rays graze a face than on the coarser meshes (1.2 % of covered pixels on a
+    # 65,536-pixel sample), every one of them inside the backward-error band
+    fwd, n_back = _check_moments(sc, pix, _flat_moments(r.moments)[:, pix], ref, max_backward=0.02)
+    d = _np(rgba).reshape(-1, 4)[pix] - ref["rgba"]
+    print("large: moments forward %.3g (%d on the backward bar), rgba max %.3g rmse %.3g" % (
+        fwd, n_back, np.abs(d).max(), math.sqrt(np.mean(d ** 2))))
+    assert np.abs(d).max() <= 2e-3 and math.sqrt(np.mean(d ** 2)) <= 5e-4
+    del r
+
+
+def test_uneven_batching_mesh_sampled_pixels_match_oracle(apc, ctx):
+    """The uneven-subdomain mesh the serving run uses (144^3 x 6 = 17,915,904 tets, 72 Morton chunks of
+    weight ratio 12), 1024^2, m = 8: 3,000 seeded pixels against the oracle."""
+    sc = synth.scene_batching(n=144, size=1024)
+    r = apc.Renderer(ctx, sc)
+    r.frame()
+    rgba = r.frame()
+    torch.cuda.synchronize()
+    W, H = sc.view["width"], sc.view["height"]
+    pix = np.sort(np.random.default_rng(19).choice(W * H, 3000, replace=False))
+    ref = oracle.render(sc, pixels=pix)
+    _check_moments(sc, pix, _flat_moments(r.moments)[:, pix], ref, max_backward=0.02)
+    d = _np(rgba).reshape(-1, 4)[pix] - ref["rgba"]
+    assert np.abs(d).max() <= 2e-3 and math.sqrt(np.mean(d ** 2)) <= 5e-4
