@@ -101,6 +101,8 @@ def main():
     ap.add_argument("--workload", default="large", choices=["large", "medium", "tiny", "slabs"])
     ap.add_argument("--ranks", type=int, default=16, help="slabs workload: subdomains (4 slabs each)")
     ap.add_argument("--m", type=int, default=None, help="override the number of moments (4, 6, 8)")
+    ap.add_argument("--tile-width", type=int, default=None, help="pixels per tile row (tile = w x 64/w)")
+    ap.add_argument("--autotune", action="store_true", help="pick the tile shape with the autotuner first")
     ap.add_argument("--size", type=int, default=None, help="override the image size (square)")
     ap.add_argument("--grid", type=int, default=None, help="override cubes per axis (large workload)")
     ap.add_argument("--cpu-pixels", type=int, default=65536, help="oracle sample size (0 = skip)")
@@ -161,6 +163,13 @@ def main():
     log("mesh resident in %.1fs: %d boundary faces, %.2f GB" % (
         time.time() - t0, info["n_boundary_faces"], info["device_bytes"] / 1e9))
 
+    tuned = None
+    if args.tile_width:
+        ctx.set_tile_shape(args.tile_width)
+    if args.autotune:
+        best, ms = ctx.autotune_tile_shape(r.mesh, r.view, r.tf, sc.m, r.subs, r.per_sub, repeats=1)
+        tuned = {"best_width": best, "stage_one_ms_by_width": {str(k): round(v, 3) for k, v in ms.items()}}
+        log("autotuned tile: %s" % tuned)
     for _ in range(args.warmup):
         r.frame()
     torch.cuda.synchronize()
@@ -184,6 +193,7 @@ def main():
             k, frame_ms[-1], tk["moments_ms"], tk["resolve_ms"], tk["stage_ms"], tk["eval_ms"]))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
+    tile_shape = list(ctx.tile_shape())
     ms_per_step = elapsed * 1e3 / args.steps
     cnt = ctx.counters()
     walks = 1 if kern["stage_ms"] == 0.0 else 2  # stage two walks again unless stage one kept the pieces
@@ -297,6 +307,7 @@ def main():
         "samples_per_frame": int(pieces_per_frame), "tet_steps_per_frame": int(steps_per_frame),
         "kernels_ms": {k: round(v, 3) for k, v in kern.items()},
         "frame_ms_each": [round(x, 2) for x in frame_ms],
+        "tile_shape": tile_shape, "autotune": tuned,
         "segments": seg_stats, "counters": cnt, "roofline": roofline, "cpu_baseline": cpu, "parity": parity, "variants": variants,
         "serving": serving,
     }
