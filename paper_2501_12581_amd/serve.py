@@ -108,62 +108,12 @@ class Server:
         if mode not in ("batched", "fifo"):
             raise ValueError(mode)
         n_slots = len(self.slots) if mode == "batched" else 1
-        reqs = sorted(requests, key=lambda r: r["arrival"])
-        free = queue.Queue()
-        for k in range(n_slots):
-            free.put(k)
-        lock = threading.Lock()
-        inflight = [0]
-        done = {}
-        errors = []
-        t0 = time.perf_counter()
 
-        def work(slot, req):
-            start = time.perf_counter() - t0
-            try:
-                rgba = self.render(slot, req)
-                end = time.perf_counter() - t0
-                rec = {"id": req["id"], "arrival": req["arrival"], "start": start, "end": end,
-                       "latency": end - req["arrival"], "size": req["size"], "m": req["m"]}
-                if keep_images:
-                    rec["rgba"] = rgba.cpu()
-                done[req["id"]] = rec
-            except Exception as e:  # reported after the run
-                errors.append((req["id"], repr(e)))
-            finally:
-                with lock:
-                    inflight[0] -= self.footprint(req)
-                free.put(slot)
+        def render(slot, req):
+            rgba = self.render(slot, req)
+            return rgba.cpu() if keep_images else None
 
-        threads = []
-        for req in reqs:
-            wait = req["arrival"] - (time.perf_counter() - t0)
-            if wait > 0:
-                time.sleep(wait)
-            fp = self.footprint(req)
-            while True:  # admission: a free slot and room in the HBM budget (a lone request is always admitted)
-                slot = free.get()
-                with lock:
-                    fits = inflight[0] == 0 or inflight[0] + fp <= self.hbm_budget
-                    if fits:
-                        inflight[0] += fp
-                if fits:
-                    break
-                free.put(slot)
-                time.sleep(0.0005)
-            th = threading.Thread(target=work, args=(slot, req))
-            th.start()
-            threads.append(th)
-        for th in threads:
-            th.join()
-        if errors:
-            raise RuntimeError("requests failed: %s" % errors[:3])
-        recs = [done[r["id"]] for r in reqs]
-        lat = np.array([r["latency"] for r in recs]) * 1e3
-        span = max(r["end"] for r in recs) - min(r["arrival"] for r in recs)
-        return {"mode": mode, "slots": n_slots, "requests": len(recs),
-                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                "mean_ms": float(lat.mean()), "frames_per_s": len(recs) / span, "records": recs}
+        return schedule(requests, n_slots, self.footprint, self.hbm_budget, render, mode)
 
     def close(self):
         self.torch.cuda.synchronize(self.dev)
@@ -171,3 +121,67 @@ class Server:
             c.close()
         self.mesh.free()
         self.owner.close()
+
+
+def schedule(requests, n_slots, footprint, hbm_budget, render, mode="batched") -> dict:
+    """Open-loop continuous batching.  Request k is released at requests[k]["arrival"] seconds after the
+    start and admitted, in arrival order, as soon as a slot is free and the footprints of the requests in
+    flight plus its own fit `hbm_budget` (a request alone is always admitted); `render(slot, req)` then runs
+    it on a worker thread (its return value, if not None, is kept as the record's "rgba").  Returns the
+    records (arrival, start, end, latency in seconds) and p50/p99/mean latency in ms and frames/s."""
+    reqs = sorted(requests, key=lambda r: r["arrival"])
+    free = queue.Queue()
+    for k in range(n_slots):
+        free.put(k)
+    lock = threading.Lock()
+    inflight = [0]
+    done = {}
+    errors = []
+    t0 = time.perf_counter()
+
+    def work(slot, req):
+        start = time.perf_counter() - t0
+        try:
+            img = render(slot, req)
+            end = time.perf_counter() - t0
+            rec = {"id": req["id"], "arrival": req["arrival"], "start": start, "end": end, "slot": slot,
+                   "latency": end - req["arrival"], "size": req.get("size"), "m": req.get("m")}
+            if img is not None:
+                rec["rgba"] = img
+            done[req["id"]] = rec
+        except Exception as e:  # reported after the run
+            errors.append((req["id"], repr(e)))
+        finally:
+            with lock:
+                inflight[0] -= footprint(req)
+            free.put(slot)
+
+    threads = []
+    for req in reqs:
+        wait = req["arrival"] - (time.perf_counter() - t0)
+        if wait > 0:
+            time.sleep(wait)
+        fp = footprint(req)
+        while True:  # admission: a free slot and room in the HBM budget
+            slot = free.get()
+            with lock:
+                fits = inflight[0] == 0 or inflight[0] + fp <= hbm_budget
+                if fits:
+                    inflight[0] += fp
+            if fits:
+                break
+            free.put(slot)
+            time.sleep(0.0005)
+        th = threading.Thread(target=work, args=(slot, req))
+        th.start()
+        threads.append(th)
+    for th in threads:
+        th.join()
+    if errors:
+        raise RuntimeError("requests failed: %s" % errors[:3])
+    recs = [done[r["id"]] for r in reqs]
+    lat = np.array([r["latency"] for r in recs]) * 1e3
+    span = max(r["end"] for r in recs) - min(r["arrival"] for r in recs)
+    return {"mode": mode, "slots": n_slots, "requests": len(recs),
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat.mean()), "frames_per_s": len(recs) / span, "records": recs}
