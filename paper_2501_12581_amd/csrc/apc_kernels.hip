@@ -46,13 +46,29 @@ __device__ __forceinline__ int sel4(const int4& v, int i) {
   return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
 }
 
-// Blocks are dispatched round-robin over the 8 XCDs; give every XCD a
-// contiguous run of tiles so that neighbouring tiles (which read the same
-// tets) share that XCD's L2.
-__device__ __forceinline__ int xcd_tile(int b, int nb) {
-  int q = nb >> 3, r = nb & 7;
-  int x = b & 7, i = b >> 3;
-  return x * q + (x < r ? x : r) + i;
+// Blocks are dispatched round-robin over the 8 XCDs (block b runs on XCD
+// b % 8).  The tiles are handed out in runs of XCD_RUN consecutive tiles, run
+// c to XCD c % 8, so neighbouring tiles (which read the same tets) share one
+// XCD's L2 while every XCD gets runs from all over the image: the work of a
+// view is concentrated where the volume projects, and one contiguous band of
+// the image per XCD gave the busiest XCD twice the mean work.  The blocks
+// beyond the last whole round of 8 runs take the remaining tiles in bands.
+#ifndef APC_XCD_RUN
+#define APC_XCD_RUN 64
+#endif
+constexpr int XCD_RUN = APC_XCD_RUN;
+__device__ __forceinline__ int xcd_tile(int b, int nb, int run = XCD_RUN) {
+  const int whole = nb / (8 * run) * (8 * run);
+  if (b < whole) {
+    const int x = b & 7, i = b >> 3;
+    const int k = i / run;
+    return (k * 8 + x) * run + (i - k * run);
+  }
+  b -= whole;
+  nb -= whole;
+  const int q = nb >> 3, r = nb & 7;
+  const int x = b & 7, i = b >> 3;
+  return whole + x * q + (x < r ? x : r) + i;
 }
 
 struct Ray {
@@ -774,7 +790,7 @@ __global__ __launch_bounds__(WAVE * EVAL_WPB) __attribute__((amdgpu_waves_per_eu
     tf[i] = make_float4(tf_rgba[4 * i], tf_rgba[4 * i + 1], tf_rgba[4 * i + 2], tf_rgba[4 * i + 3]);
   __syncthreads();  // the only workgroup barrier: every later wait is within a wavefront
   const int wv = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-  const int tile = tile_lo + xcd_tile(blockIdx.x, gridDim.x) * EVAL_WPB + wv;
+  const int tile = tile_lo + xcd_tile(blockIdx.x, gridDim.x, (XCD_RUN + EVAL_WPB - 1) / EVAL_WPB) * EVAL_WPB + wv;
   if (tile >= tile_hi) return;
   R* li_lds = li_all[wv];
   R* zs_lds = zs_all[wv];
