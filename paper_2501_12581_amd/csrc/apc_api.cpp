@@ -117,7 +117,7 @@ struct apc_ctx_s {
   DevBuf pool, ptab, store_next;
   long long pool_chunks = 0;         // chunks the pool holds
   long long pool_target = 0;         // chunks wanted (grown after a frame did not fit)
-  int maxc = 64;                     // chunk slots per pixel
+  int maxc = 4096 / apc::PIECE_CHUNK;  // chunk slots per pixel (4096 pieces to start)
   bool store_ready = false;          // the last stage one kept its pieces (if none failed)
   apc_tf store_tf = {};              // the transfer function they were made with
   bool store_failed_last = false;    // the last resolve found that stage one could not keep every piece
@@ -675,7 +675,7 @@ apc_status apc_moments_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const
   ctx->store_ready = false;
   if (!(flags & APC_REWALK)) {
     const size_t slots = size_t(f.n_tiles) * 64;
-    if (ctx->pool_target == 0) ctx->pool_target = (long long)(slots * 2);  // 128 pieces per pixel to start
+    if (ctx->pool_target == 0) ctx->pool_target = (long long)(slots * 128 / apc::PIECE_CHUNK);  // 128 pieces per pixel to start
     const size_t chunk_bytes = sizeof(float) * 3 * apc::PIECE_CHUNK;
     bool ok = true;
     if (ctx->pool_chunks < ctx->pool_target && !ctx->capturing) {

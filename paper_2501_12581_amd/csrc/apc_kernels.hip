@@ -445,6 +445,13 @@ __device__ __forceinline__ void flush_counts(const LaneCount& c, unsigned long l
 // stays current).  One atomic per chunk on a single counter was measured to
 // serialise: stage one took 5x as long.
 constexpr int STORE_BLOCK = 64;
+typedef __attribute__((address_space(3))) volatile unsigned long long lds_vu64;
+typedef __attribute__((address_space(3))) volatile int lds_vi32;
+__device__ __forceinline__ unsigned long long readlane_u64(unsigned long long v, int l) {
+  const unsigned lo = __builtin_amdgcn_readlane(unsigned(v & 0xffffffffull), l);
+  const unsigned hi = __builtin_amdgcn_readlane(unsigned(v >> 32), l);
+  return (static_cast<unsigned long long>(hi) << 32) | lo;
+}
 struct LaneStore {
   PieceStore ps;
   size_t slot;     // tile * 64 + lane
@@ -452,34 +459,29 @@ struct LaneStore {
   int chunk;
   bool keep;
   // LDS: first chunk of the wavefront's block and the chunks of it handed
-  // out.  Written by one lane and read by another lane in a later divergent
-  // region, so volatile: a value loaded earlier must not be reused.
-  volatile unsigned long long* blk_base;
-  volatile int* blk_used;
+  // out.  Written by one lane and read by others in later divergent regions,
+  // so volatile; LDS-addressed, so a read waits for LDS only (a generic
+  // access would also wait for every piece store still in flight).
+  lds_vu64* blk_base;
+  lds_vi32* blk_used;
   // append one piece; lanes that start a chunk at this point get consecutive
   // chunks of the wavefront's block (and a new block when it runs out)
   __device__ void put(float z, float a, float s, int lane) {
     if (!keep) return;
     if ((kept & (PIECE_CHUNK - 1)) == 0) {
       const unsigned long long need = __ballot(1);
-      const int leader = __ffsll((long long)need) - 1;
+      const int leader = __builtin_ffsll(static_cast<long long>(need)) - 1;
       const int n = __popcll(need);
       const int r = __popcll(need & ((1ull << lane) - 1));
-      unsigned long long base = 0, fresh = 0;
-      int used = 0;
-      if (lane == leader) {
-        base = *blk_base;
-        used = *blk_used;
-      }
-      used = __shfl(used, leader, WAVE);
+      const unsigned long long base = *blk_base;  // every lane reads the same word
+      const int used = *blk_used;
       const int rem = STORE_BLOCK - used;
-      if (n > rem && lane == leader) fresh = atomicAdd(ps.next, (unsigned long long)STORE_BLOCK);
-      const unsigned b_lo = __shfl(unsigned(base & 0xffffffffull), leader, WAVE);
-      const unsigned b_hi = __shfl(unsigned(base >> 32), leader, WAVE);
-      const unsigned f_lo = __shfl(unsigned(fresh & 0xffffffffull), leader, WAVE);
-      const unsigned f_hi = __shfl(unsigned(fresh >> 32), leader, WAVE);
-      base = (static_cast<unsigned long long>(b_hi) << 32) | b_lo;
-      fresh = (static_cast<unsigned long long>(f_hi) << 32) | f_lo;
+      unsigned long long fresh = 0;
+      if (n > rem) {
+        unsigned long long got = 0;
+        if (lane == leader) got = atomicAdd(ps.next, (unsigned long long)STORE_BLOCK);
+        fresh = readlane_u64(got, leader);
+      }
       const unsigned long long id = r < rem ? base + used + r : fresh + (r - rem);
       if (lane == leader) {
         if (n > rem) {
@@ -572,7 +574,8 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_WALK_W
     blk_base = 0;
     blk_used = STORE_BLOCK;  // no block yet
   }
-  sink.st = LaneStore{ps, size_t(tile) * WAVE + lane, 0u, -1, ps.pool != nullptr && valid, &blk_base, &blk_used};
+  sink.st = LaneStore{ps, size_t(tile) * WAVE + lane, 0u, -1, ps.pool != nullptr && valid, (lds_vu64*)&blk_base,
+                      (lds_vi32*)&blk_used};
   sink.lane = lane;
   __syncthreads();
   for (int k = 0; k < f.n_slots; ++k) {
