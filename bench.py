@@ -72,8 +72,9 @@ def serve_run(n_requests):
     m = sc.mesh
     tfs = [synth.make_tf(s) for s in (21, 22, 23)]
     srv = Server((m.xyz, m.scalar, m.tets, m.tet_sub, m.n_sub), sc.step, tfs, (sc.s_min, sc.s_max), slots=4,
-                 workspace_limit=32 << 30, hbm_budget=64 << 30)
-    log("serving: %d tets, 72 uneven subdomains, resident in %.1fs" % (m.n_tets, time.time() - t0))
+                 workspace_limit=40 << 30, hbm_budget=64 << 30)
+    srv.warm()  # every slot's library buffers at the largest request's size before serving
+    log("serving: %d tets, 72 uneven subdomains, resident and warm in %.1fs" % (m.n_tets, time.time() - t0))
     warm = synth.request_stream(8, rate=1000.0, seed=99)
     srv.run(warm, "batched")
     srv.run(warm, "fifo")

@@ -240,8 +240,9 @@ apc_status apc_sum_images(apc_ctx ctx, const float* partials, int32_t n_sub, int
                           float* rgba_out, void* stream);
 
 /* Bound the context's two large workspace buffers, the kept-piece pool and the
- * re-walk staging buffer, to bytes/2 each (0: each may take 60 % of the free
- * device memory, the default).  A frame whose pieces exceed the pool walks
+ * re-walk staging buffer, to 3/4 and 1/4 of bytes (0: each may take 60 % of
+ * the free device memory, the default; the staging buffer is only used when
+ * a frame's pieces did not fit the pool).  A frame whose pieces exceed the pool walks
  * again in stage two; one that exceeds the staging buffer is resolved in
  * chunks of tiles (same results).  Lets several contexts (e.g. a server's
  * slots) share one GPU with a known footprint. */

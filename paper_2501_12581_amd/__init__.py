@@ -288,7 +288,7 @@ class Context:
                                         flags, _stream(stream)))
 
     def set_workspace_limit(self, nbytes):
-        """Cap the kept-piece pool and the re-walk staging buffer at nbytes/2 each (0: default policy)."""
+        """Cap the kept-piece pool at 3/4 and the re-walk staging buffer at 1/4 of nbytes (0: default policy)."""
         self._ck(lib().apc_set_workspace_limit(self.handle, int(nbytes)))
 
     def set_tile_shape(self, tile_width):

@@ -675,13 +675,15 @@ apc_status apc_moments_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const
   ctx->store_ready = false;
   if (!(flags & APC_REWALK)) {
     const size_t slots = size_t(f.n_tiles) * 64;
-    if (ctx->pool_target == 0) ctx->pool_target = (long long)(slots * 128 / apc::PIECE_CHUNK);  // 128 pieces per pixel to start
+    if (ctx->pool_target == 0)  // 128 pieces per pixel to start
+      ctx->pool_target = (long long)(slots * 128 / apc::PIECE_CHUNK) + (long long)f.n_tiles * apc::STORE_BLOCK;
     const size_t chunk_bytes = sizeof(float) * 3 * apc::PIECE_CHUNK;
     bool ok = true;
     if (ctx->pool_chunks < ctx->pool_target && !ctx->capturing) {
       size_t free_b = 0, total_b = 0;
       HIPCHK(hipMemGetInfo(&free_b, &total_b));
-      const size_t limit = ctx->ws_limit > 0 ? size_t(ctx->ws_limit / 2) : size_t(0.6 * double(free_b + ctx->pool.bytes));
+      const size_t limit =
+          ctx->ws_limit > 0 ? size_t(ctx->ws_limit / 4 * 3) : size_t(0.6 * double(free_b + ctx->pool.bytes));
       const size_t want = std::min(size_t(ctx->pool_target) * chunk_bytes, limit);
       if (want > ctx->pool.bytes) {
         ctx->pool.release();
@@ -851,7 +853,7 @@ apc_status apc_resolve_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const
       chunks += (c + apc::PIECE_CHUNK - 1) / apc::PIECE_CHUNK;
       most = std::max(most, c);
     }
-    ctx->pool_target = std::max(ctx->pool_target, chunks + chunks / 50 + 1024);
+    ctx->pool_target = std::max(ctx->pool_target, chunks + chunks / 50 + (long long)nt * apc::STORE_BLOCK);
     ctx->maxc = std::max(ctx->maxc, (most + apc::PIECE_CHUNK - 1) / apc::PIECE_CHUNK + 8);
   }
   if ((st = stage_upload(ctx, ctx->tile_off.p, toff.data(), sizeof(long long) * nt, s)) != APC_OK) return st;
@@ -863,7 +865,7 @@ apc_status apc_resolve_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const
   if (want > ctx->stage.bytes) {
     size_t free_b = 0, total_b = 0;
     HIPCHK(hipMemGetInfo(&free_b, &total_b));
-    size_t cap = ctx->ws_limit > 0 ? size_t(ctx->ws_limit / 2) : size_t(0.6 * double(free_b + ctx->stage.bytes));
+    size_t cap = ctx->ws_limit > 0 ? size_t(ctx->ws_limit / 4) : size_t(0.6 * double(free_b + ctx->stage.bytes));
     size_t need = std::min(want, cap);
     if (need < size_t(biggest) * rec_bytes) return fail(APC_E_NOMEM, "one tile's pieces do not fit in device memory");
     ctx->stage.release();
@@ -991,15 +993,14 @@ apc_status apc_set_workspace_limit(apc_ctx ctx, int64_t bytes) {
   if (st != APC_OK) return st;
   if (bytes < 0) return fail(APC_E_ARG, "negative limit");
   ctx->ws_limit = bytes;
-  // buffers above the new limit are given back
-  const size_t half = size_t(bytes / 2);
-  if (bytes > 0 && ctx->pool.bytes > half) {
+  // buffers above their share of the new limit are given back
+  if (bytes > 0 && ctx->pool.bytes > size_t(bytes / 4 * 3)) {
     HIPCHK(hipDeviceSynchronize());
     ctx->pool.release();
     ctx->pool_chunks = 0;
     ctx->store_ready = false;
   }
-  if (bytes > 0 && ctx->stage.bytes > half) {
+  if (bytes > 0 && ctx->stage.bytes > size_t(bytes / 4)) {
     HIPCHK(hipDeviceSynchronize());
     ctx->stage.release();
   }

@@ -54,6 +54,10 @@ struct FrameDev {
 // its chunks in walk order.  A lane that cannot get a chunk stops keeping
 // pieces and counts a failure; stage two then walks the frame again.
 constexpr int PIECE_CHUNK = 64;
+// chunks a wavefront takes from the pool at a time; the unused rest of its
+// last block is lost for the frame, so a pool needs n_tiles * STORE_BLOCK
+// chunks beyond the pieces themselves
+constexpr int STORE_BLOCK = 64;
 struct PieceStore {
   float* pool;               // [n_chunks][PIECE_CHUNK][3]: z, a, s
   long long n_chunks;

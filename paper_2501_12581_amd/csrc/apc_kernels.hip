@@ -444,7 +444,6 @@ __device__ __forceinline__ void flush_counts(const LaneCount& c, unsigned long l
 // block's state lives in LDS (its lanes diverge, so no register copy of it
 // stays current).  One atomic per chunk on a single counter was measured to
 // serialise: stage one took 5x as long.
-constexpr int STORE_BLOCK = 64;
 typedef __attribute__((address_space(3))) volatile unsigned long long lds_vu64;
 typedef __attribute__((address_space(3))) volatile int lds_vi32;
 __device__ __forceinline__ unsigned long long readlane_u64(unsigned long long v, int l) {

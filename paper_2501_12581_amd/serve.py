@@ -70,6 +70,15 @@ class Server:
         self.workspace_limit = workspace_limit
         self.hbm_budget = hbm_budget
 
+    def warm(self, eye=(2.0, 0.9, 0.7), tf=0):
+        """One frame of the largest request (max_size^2, max_m) on every slot, one slot at a time: the
+        library grows a context's buffers (bins, piece pool, staging) to what a frame needs, and a device
+        allocation or release while other slots' frames run waits for all of them."""
+        req = {"id": -1, "arrival": 0.0, "size": self.max_size, "eye": eye, "m": self.max_m, "tf": tf}
+        for k in range(len(self.slots)):
+            for _ in range(2):  # the second frame runs at the grown size
+                self.render(k, req)
+
     def footprint(self, req) -> int:
         """Bytes of one request's own buffers: per-subdomain and global moments, image."""
         px = req["size"] ** 2

@@ -52,3 +52,20 @@ def test_served_frame_matches_oracle(server):
     ref = oracle.render(sc2)
     d = got - ref["rgba"]
     assert np.abs(d).max() <= 2e-3 and math.sqrt(np.mean(d ** 2)) <= 5e-4
+
+
+def test_served_frames_keep_their_pieces(server):
+    """A slot's workspace limit gives its pool no slack beyond the size it asks for: the pool must still
+    hold a repeated request's pieces, including the chunks each wavefront's last block leaves unused, so
+    from the second frame on stage two reads kept pieces (one walk per frame, no re-walk)."""
+    srv, sc, tfs = server
+    ctx = srv.slots[0][0]
+    req = {"id": 0, "arrival": 0.0, "size": 192, "eye": (0.3, 2.4, 0.9), "m": 6, "tf": 1}
+    first = srv.render(0, req).clone()
+    for _ in range(2):
+        ctx.counters(reset=True)
+        again = srv.render(0, req)
+        t, c = ctx.timings(), ctx.counters()
+        assert t["stage_ms"] == 0.0, t
+        assert torch.equal(first, again)
+    assert c["pieces"] > 0
