@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 METRIC = "ray samples/s + frames/s at 2560², m=8; p50/p99 frame latency (served)"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
-# algorithmic work per unit (measurement section)
+# algorithmic work per unit: FP64 flops of one sample's moment bound, bytes of one tet, vertex and piece
 FP64_FLOPS_PER_PIECE_M8 = 250.0   # per-sample moment bound at m = 8
 TET_BYTES = 32.0                  # vertex ids + neighbour codes of one tet
 VERT_BYTES = 16.0                 # x, y, z, scalar
@@ -115,7 +115,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the multi-GPU path (subdomains sharded over GPUs with an "
-              "all-reduce of the moment image) is not part of this build; run with --gpus 1", file=sys.stderr)
+              "all-reduce of the moment image) is not implemented; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
