@@ -420,6 +420,29 @@ def test_kept_pieces_match_rewalk(apc, ctx, m):
     assert torch.equal(kept, walked)
 
 
+def test_workspace_limit_stages_in_chunks_with_the_same_image(apc, ctx):
+    """A context whose workspace limit is far below the frame's pieces (48 MB of pool, 16 MB of staging for
+    more than four times that in pieces) re-walks in stage two and stages its tiles in several chunks: the
+    image is bitwise that of an unlimited context, frame after frame."""
+    sc = synth.scene_medium(size=256)
+    ref = apc.Renderer(ctx, sc).frame().clone()
+    small = apc.Context(0)
+    try:
+        small.set_workspace_limit(64 << 20)
+        r = apc.Renderer(small, sc)
+        for _ in range(2):
+            small.counters(reset=True)
+            got = r.frame()
+            torch.cuda.synchronize()
+            t, c = small.timings(), small.counters()
+            assert t["stage_ms"] > 0  # the pieces do not fit the pool: stage two walked again
+            assert c["pieces"] // 2 * 12 > 4 * (16 << 20)  # each of the two walks: pieces for 4+ chunks
+            assert torch.equal(got, ref)
+    finally:
+        del r
+        small.close()
+
+
 def test_large_full_size_sampled_pixels_match_oracle(apc, ctx):
     """The full-size configuration the benchmark times (256^3 x 6 = 100,663,296 tets, 72 subdomains,
     2560^2 perspective, m = 8), in its launch configuration (a warm-up frame, then a frame that keeps its
