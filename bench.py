@@ -108,6 +108,9 @@ def main():
     ap.add_argument("--grid", type=int, default=None, help="override cubes per axis (large workload)")
     ap.add_argument("--cpu-pixels", type=int, default=65536, help="oracle sample size (0 = skip)")
     ap.add_argument("--profile-steps", action="store_true", help="no oracle leg and no serving run (for profiler runs)")
+    ap.add_argument("--separate-sum", action="store_true",
+                    help="time frames with per-subdomain moment images + apc_sum_moments (the form several GPUs "
+                         "would run) instead of stage one summing the subdomains itself")
     ap.add_argument("--serve-requests", type=int, default=120,
                     help="requests of the serving run (Poisson, 50/s, batching mesh); 0 = skip")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -171,8 +174,9 @@ def main():
         best, ms = ctx.autotune_tile_shape(r.mesh, r.view, r.tf, sc.m, r.subs, r.per_sub, repeats=1)
         tuned = {"best_width": best, "stage_one_ms_by_width": {str(k): round(v, 3) for k, v in ms.items()}}
         log("autotuned tile: %s" % tuned)
+    fused = not args.separate_sum  # one GPU holds every subdomain: stage one sums them (APC_MOMENTS_GLOBAL)
     for _ in range(args.warmup):
-        r.frame()
+        r.frame(fused=fused)
     torch.cuda.synchronize()
     log("warmup done")
     ctx.counters(reset=True)
@@ -183,7 +187,7 @@ def main():
     frame_ms = []
     for k in range(args.steps):
         f0 = time.perf_counter()
-        r.frame()
+        r.frame(fused=fused)
         # the library records HIP events around each kernel on this stream; reading them waits for the frame
         tk = ctx.timings()
         stream.synchronize()
@@ -220,14 +224,20 @@ def main():
     H, W, m = r.view.height, r.view.width, sc.m
     S = mesh.n_sub
     mesh_bytes = mesh.n_tets * TET_BYTES + mesh.n_vertices * VERT_BYTES
-    mom_bytes = S * (m + 1) * H * W * 4.0
+    pairs = int(met.sum().item())  # (pixel, subdomain) pairs with pieces
+    if fused:  # each pair's moments enter the sum once; the global image is written once
+        mom_bytes = (pairs + H * W) * (m + 1) * 4.0
+        mom_label = "per-pair moments + global image"
+    else:  # the API's dense per-subdomain images
+        mom_bytes = S * (m + 1) * H * W * 4.0
+        mom_label = "dense per-subdomain moments"
     kept = kern["stage_ms"] == 0.0  # stage one kept its pieces: no second walk
     kept_bytes = pieces_per_frame * STAGE_BYTES if kept else 0.0
     rooflines = {
         "k_moments": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
                       "achieved": (mesh_bytes + mom_bytes + kept_bytes) / (kern["moments_ms"] / 1e3) / 1e9,
-                      "per_launch": "mesh %.3g B + dense per-subdomain moments %.3g B + kept pieces %.3g B" % (
-                          mesh_bytes, mom_bytes, kept_bytes)},
+                      "per_launch": "mesh %.3g B + %s %.3g B + kept pieces %.3g B" % (
+                          mesh_bytes, mom_label, mom_bytes, kept_bytes)},
         "k_stage": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
                     "achieved": (mesh_bytes + pieces_per_frame * STAGE_BYTES) / (max(kern["stage_ms"], 1e-9) / 1e3) / 1e9,
                     "per_launch": "mesh %.3g B + staged pieces %.3g B" % (mesh_bytes, pieces_per_frame * STAGE_BYTES)},
@@ -276,12 +286,25 @@ def main():
                   "rgba_max_abs": float(np.abs(d).max()), "rgba_rmse": float(math.sqrt(np.mean(d ** 2)))}
         log("parity %s" % parity)
         # FP16 moment-image variant (ln b0, b_j / b0), run after the timed frames on the same sample
-        r.frame(moments_f16=True)
+        mom_timed = r.moments.clone()
+        r.frame(moments_f16=True, fused=fused)
         rgba16 = r.rgba.reshape(-1, 4)[torch.as_tensor(pix, device=dev)].double().cpu().numpy()
         d16 = rgba16 - ref["rgba"]
         variants = {"fp16_moments": {
             "rgba_max_abs": float(np.abs(d16).max()), "rgba_rmse": float(math.sqrt(np.mean(d16 ** 2))),
             "moment_image_bytes": int(r.moments_h.numel() * 2), "fp32_moment_image_bytes": int(r.moments.numel() * 4)}}
+        # the other form of stage one + sum: its frames' time and whether its global moments are bitwise equal
+        other = []
+        for _ in range(2):
+            f0 = time.perf_counter()
+            r.frame(fused=not fused)
+            tk = ctx.timings()
+            torch.cuda.synchronize()
+            other.append(((time.perf_counter() - f0) * 1e3, tk["moments_ms"], tk["sum_ms"]))
+        variants["separate_sum" if fused else "fused_sum"] = {
+            "frame_ms": round(other[-1][0], 2), "moments_ms": round(other[-1][1], 3),
+            "sum_ms": round(other[-1][2], 3) if fused else 0.0,
+            "global_moments_bitwise_equal": bool(torch.equal(r.moments, mom_timed))}
         log("variants %s" % variants)
 
     # ---- serving: continuous batching vs one request at a time (after the frame buffers are released)
@@ -307,6 +330,7 @@ def main():
         "frames_per_s": round(1e3 / ms_per_step, 4),
         "samples_per_frame": int(pieces_per_frame), "tet_steps_per_frame": int(steps_per_frame),
         "kernels_ms": {k: round(v, 3) for k, v in kern.items()},
+        "stage_one_sums_subdomains": fused,
         "frame_ms_each": [round(x, 2) for x in frame_ms],
         "tile_shape": tile_shape, "autotune": tuned,
         "segments": seg_stats, "counters": cnt, "roofline": roofline, "cpu_baseline": cpu, "parity": parity, "variants": variants,

@@ -176,7 +176,15 @@ typedef struct apc_mboit {
  * apc_resolve_pass of the same geometry, camera, transfer function and
  * subdomain list evaluates them without walking the rays again; when they
  * were not all kept it walks again (same pieces, same result).
- * flags: 0, or APC_REWALK: keep no pieces (stage two walks again). */
+ * flags: 0, or APC_REWALK: keep no pieces (stage two walks again), and/or
+ * APC_MOMENTS_GLOBAL: the listed subdomains are all that the frame has and
+ * stage one sums them itself: `moments_per_sub` is then the global image
+ * device [m+1][H][W] FP32, bitwise what apc_sum_moments returns for the
+ * per-subdomain images of the same call (each subdomain's FP32 value added
+ * in FP64 in ascending subdomain-id order).  The ids must be listed in
+ * ascending order (APC_E_ARG otherwise).  Needs an FP64 accumulator of
+ * 8*(m+1)*H*W bytes in context-owned device memory; the per-subdomain images
+ * are never formed. */
 apc_status apc_moments_pass(apc_ctx ctx, apc_mesh mesh, const apc_view* view, const apc_tf* tf, int32_t m,
                             const int32_t* subdomains, int32_t n_sub, float* moments_per_sub, uint32_t flags,
                             void* stream);
@@ -194,6 +202,7 @@ apc_status apc_sum_moments(apc_ctx ctx, const float* moments_per_sub, int32_t n_
 #define APC_FINALIZE 1u
 #define APC_MOMENTS_F16 2u
 #define APC_REWALK 4u
+#define APC_MOMENTS_GLOBAL 8u
 
 /* Pack a global moment image for FP16 storage: plane 0 holds ln(b0) (-inf
  * where b0 <= 0), planes j = 1..m hold b_j / b0 (in [-1, 1] since the warped
@@ -334,7 +343,7 @@ apc_status apc_frame_graph_counters(apc_graph graph, apc_counters* out, int32_t 
 typedef struct apc_timings {
   double bin_ms;       /* binning of the most recent pass (count + scan + fill) */
   double moments_ms;   /* stage-one walk kernel of the last apc_moments_pass */
-  double sum_ms;       /* last apc_sum_moments */
+  double sum_ms;       /* last apc_sum_moments (0 after an APC_MOMENTS_GLOBAL stage one) */
   double resolve_ms;   /* everything after binning in the last apc_resolve_pass */
   double stage_ms;     /* its re-walk kernel (first chunk of tiles) */
   double eval_ms;      /* its moment-bound evaluation kernel (first chunk of tiles) */

@@ -21,6 +21,7 @@ APC_PERSPECTIVE = 1
 APC_FINALIZE = 1
 APC_MOMENTS_F16 = 2
 APC_REWALK = 4
+APC_MOMENTS_GLOBAL = 8
 STATUS = {0: "APC_OK", 1: "APC_E_ARG", 2: "APC_E_MESH", 3: "APC_E_NOMEM", 4: "APC_E_DEVICE",
           5: "APC_E_NUMERIC", 6: "APC_E_UNSUPPORTED"}
 EXPORTS = ["apc_create", "apc_destroy", "apc_last_error", "apc_version", "apc_load_mesh", "apc_free_mesh",
@@ -257,14 +258,19 @@ class Context:
         self._ck(lib().apc_load_mesh(self.handle, C.byref(d), C.byref(h), _stream(stream)))
         return Mesh(self, h)
 
-    def moments_pass(self, mesh, view: View, tf: TF, m, subdomains, out, stream=None, rewalk=False):
-        """Stage one; unless rewalk, its pieces are kept for the resolve pass of the same frame."""
+    def moments_pass(self, mesh, view: View, tf: TF, m, subdomains, out, stream=None, rewalk=False,
+                     global_sum=False):
+        """Stage one; unless rewalk, its pieces are kept for the resolve pass of the same frame.  With
+        global_sum (ascending subdomain ids), `out` is the global [m+1][H][W] image, summed by stage one
+        itself (bitwise what sum_moments gives for the per-subdomain images), instead of [n][m+1][H][W]."""
         import torch
         ids, ptr = _ids(subdomains)
-        shape = (len(ids), m + 1, view.height, view.width)
+        shape = (m + 1, view.height, view.width) if global_sum else (len(ids), m + 1, view.height, view.width)
+        flags = (APC_REWALK if rewalk else 0) | (APC_MOMENTS_GLOBAL if global_sum else 0)
         self._ck(lib().apc_moments_pass(self.handle, mesh.handle, C.byref(view), C.byref(tf), int(m), ptr,
-                                        len(ids), _dev_ptr(out, torch.float32, shape, "moments_per_sub"),
-                                        APC_REWALK if rewalk else 0, _stream(stream)))
+                                        len(ids), _dev_ptr(out, torch.float32, shape,
+                                                           "moments" if global_sum else "moments_per_sub"),
+                                        flags, _stream(stream)))
 
     def sum_moments(self, per_sub, m, subdomains, out, stream=None):
         import torch
@@ -408,13 +414,18 @@ class Renderer:
         self.moments = torch.empty((m + 1, H, W), dtype=torch.float32, device=device)
         self.rgba = torch.empty((H, W, 4), dtype=torch.float32, device=device)
 
-    def frame(self, subdomains=None, finalize=True, stream=None, moments_f16=False, rewalk=False):
+    def frame(self, subdomains=None, finalize=True, stream=None, moments_f16=False, rewalk=False, fused=False):
         """One frame; with moments_f16 the resolve reads the FP16-packed moment image (self.moments_h); with
-        rewalk stage two walks the rays again instead of reading the pieces stage one kept."""
+        rewalk stage two walks the rays again instead of reading the pieces stage one kept; with fused (all
+        subdomains, ascending) stage one writes the global moments itself and self.per_sub is not written."""
         subs = self.subs if subdomains is None else np.asarray(subdomains, np.int32)
-        per_sub = self.per_sub if len(subs) == len(self.subs) else self.per_sub[:len(subs)]
-        self.ctx.moments_pass(self.mesh, self.view, self.tf, self.scene.m, subs, per_sub, stream, rewalk=rewalk)
-        self.ctx.sum_moments(per_sub, self.scene.m, subs, self.moments, stream)
+        if fused:
+            self.ctx.moments_pass(self.mesh, self.view, self.tf, self.scene.m, subs, self.moments, stream,
+                                  rewalk=rewalk, global_sum=True)
+        else:
+            per_sub = self.per_sub if len(subs) == len(self.subs) else self.per_sub[:len(subs)]
+            self.ctx.moments_pass(self.mesh, self.view, self.tf, self.scene.m, subs, per_sub, stream, rewalk=rewalk)
+            self.ctx.sum_moments(per_sub, self.scene.m, subs, self.moments, stream)
         mom = self.moments
         if moments_f16:
             import torch

@@ -102,6 +102,7 @@ struct apc_ctx_s {
   int tw_log2 = 3;
   // per-pixel segment statistics of the last stage one: [2][seg_h][seg_w]
   DevBuf segs;
+  DevBuf gacc;  // FP64 [m+1][H][W] partial sums of APC_MOMENTS_GLOBAL
   int seg_h = 0, seg_w = 0;
   // the pieces per pixel in `pcount` belong to this (mesh, view, subdomain list)
   const void* pc_mesh = nullptr;
@@ -663,7 +664,11 @@ apc_status apc_moments_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const
   if (mm != 4 && mm != 6 && mm != 8) return fail(APC_E_ARG, "m = %d unsupported (4, 6 or 8)", mm);
   if ((st = check_subdomains(m, subs, n_sub)) != APC_OK) return st;
   if (!out) return fail(APC_E_ARG, "output is NULL");
-  if (flags & ~APC_REWALK) return fail(APC_E_ARG, "unknown flags 0x%x", flags);
+  if (flags & ~(APC_REWALK | APC_MOMENTS_GLOBAL)) return fail(APC_E_ARG, "unknown flags 0x%x", flags);
+  const bool global = (flags & APC_MOMENTS_GLOBAL) != 0;
+  if (global)
+    for (int k = 1; k < n_sub; ++k)
+      if (!(subs[k - 1] < subs[k])) return fail(APC_E_ARG, "APC_MOMENTS_GLOBAL needs ascending subdomain ids");
   FrameDev f;
   if ((st = make_frame(m, view, tf, n_sub, max_tets_of(m, subs, n_sub), ctx->tw_log2, f)) != APC_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -709,9 +714,14 @@ apc_status apc_moments_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const
   ctx->seg_h = view->height;
   ctx->seg_w = view->width;
   HIPCHK(ev_mark(ctx, EV_MOM, 0, s));
+  if (global) {
+    HIPCHK(ctx->gacc.ensure(sizeof(double) * size_t(mm + 1) * view->width * view->height));
+    ctx->ev_used[EV_SUM] = false;  // no separate sum in this frame
+  }
   HIPCHK(apc::launch_moments(mm, md, f, ctx->slots.as<SlotDev>(), ctx->offsets.as<int>(), ctx->counts.as<int>(),
-                             ctx->records.as<int>(), bin_cap(ctx), tf->rgba, out, ctx->pcount.as<int>(),
-                             ctx->segs.as<int>(), ps, ctx->counters.as<unsigned long long>(), s));
+                             ctx->records.as<int>(), bin_cap(ctx), tf->rgba, out,
+                             global ? ctx->gacc.as<double>() : nullptr, ctx->pcount.as<int>(), ctx->segs.as<int>(), ps,
+                             ctx->counters.as<unsigned long long>(), s));
   HIPCHK(ev_mark(ctx, EV_MOM, 1, s));
   set_piece_key(ctx, m, view, subs, n_sub);
   ctx->store_ready = ps.pool != nullptr;

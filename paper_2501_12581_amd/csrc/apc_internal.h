@@ -87,11 +87,13 @@ hipError_t launch_bin_fill(const MeshDev& m, const FrameDev& f, const SlotDev* s
                            const int* bface, const int* offsets, int* cursors, int* records, long long rec_cap,
                            hipStream_t s);
 // stage one; pcount (tile-major [n_tiles * 64], may be null) receives the pieces per pixel, segs
-// ([2][H][W], may be null) the segments per pixel and the subdomains with pieces on each ray
+// ([2][H][W], may be null) the segments per pixel and the subdomains with pieces on each ray.  With gacc
+// ([m+1][H][W] FP64 scratch) set, out is the global [m+1][H][W] image: the slots' FP32 moments summed in
+// FP64 in slot order; else out is [n_slots][m+1][H][W]
 hipError_t launch_moments(int mm, const MeshDev& m, const FrameDev& f, const SlotDev* slots, const int* offsets,
                           const int* counts, const int* records, long long bin_cap, const float* tf_rgba, float* out,
-                          int* pcount, int* segs, const PieceStore& store, unsigned long long* counters,
-                          hipStream_t s);
+                          double* gacc, int* pcount, int* segs, const PieceStore& store,
+                          unsigned long long* counters, hipStream_t s);
 // stage two, walk part: mode 0 counts pieces per pixel into pcount; mode 1 writes the
 // pieces of tiles [tile_lo, tile_hi) as (z, a, s) at rec + 3 * (poff[pixel] - base), for
 // pixels whose pieces end within rec_cap pieces of base.  Bins whose records end beyond

@@ -544,9 +544,9 @@ template <int M1>
 __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_WALK_WAVES, 8))) void k_moments(MeshDev M, FrameDev f, const SlotDev* __restrict__ slots,
                                                   const int* __restrict__ offsets, const int* __restrict__ counts,
                                                   const int* __restrict__ records, const float* __restrict__ tf_rgba,
-                                                  float* __restrict__ out, int* __restrict__ pcount,
-                                                  int* __restrict__ segs, long long bin_cap, PieceStore ps,
-                                                  unsigned long long* ctr) {
+                                                  float* __restrict__ out, double* __restrict__ gacc,
+                                                  int* __restrict__ pcount, int* __restrict__ segs, long long bin_cap,
+                                                  PieceStore ps, unsigned long long* ctr) {
   extern __shared__ float4 dyn_lds[];
   float* tfa = reinterpret_cast<float*>(dyn_lds);  // [n_tf] alpha column
   __shared__ FaceL faces[CHUNK];
@@ -590,12 +590,28 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_WALK_W
       ++cnt.overflow;  // binned beyond the record capacity (never on an eagerly sized workspace)
     }
     cnt.pieces += sink.pieces;
-    covering += sink.pieces > 0 ? 1 : 0;
-    if (valid) {
+    if (gacc) {
+      // the global sum in slot order, one FP64 partial per pixel: a subdomain without pieces adds an exact
+      // zero, so only the others are read and written, and the first one needs no read
+      if (valid && sink.pieces > 0) {
+        double* g = gacc + pix;
+#pragma unroll
+        for (int j = 0; j < M1; ++j) {
+          const double v = double(float(sink.b[j]));
+          g[size_t(j) * HW] = covering > 0 ? g[size_t(j) * HW] + v : v;
+        }
+      }
+    } else if (valid) {
       float* o = out + size_t(k) * M1 * HW + pix;
 #pragma unroll
       for (int j = 0; j < M1; ++j) o[size_t(j) * HW] = float(sink.b[j]);
     }
+    covering += sink.pieces > 0 ? 1 : 0;
+  }
+  if (gacc && valid) {
+    float* o = out + pix;
+#pragma unroll
+    for (int j = 0; j < M1; ++j) o[size_t(j) * HW] = covering > 0 ? float(gacc[size_t(j) * HW + pix]) : 0.0f;
   }
   if (pcount) pcount[size_t(tile) * WAVE + lane] = int(cnt.pieces);
   if (segs && valid) {  // [2][H][W]: segments, covering subdomains
@@ -1296,19 +1312,19 @@ hipError_t launch_bin_fill(const MeshDev& m, const FrameDev& f, const SlotDev* s
 
 hipError_t launch_moments(int mm, const MeshDev& m, const FrameDev& f, const SlotDev* slots, const int* offsets,
                           const int* counts, const int* records, long long bin_cap, const float* tf_rgba, float* out,
-                          int* pcount, int* segs, const PieceStore& store, unsigned long long* counters,
-                          hipStream_t s) {
+                          double* gacc, int* pcount, int* segs, const PieceStore& store,
+                          unsigned long long* counters, hipStream_t s) {
   const size_t lds = size_t(f.n_tf) * sizeof(float);
   const dim3 grid(f.n_tiles), block(WAVE);
   if (mm == 4)
     hipLaunchKernelGGL(k_moments<5>, grid, block, lds, s, m, f, slots, offsets, counts, records, tf_rgba, out,
-                       pcount, segs, bin_cap, store, counters);
+                       gacc, pcount, segs, bin_cap, store, counters);
   else if (mm == 6)
     hipLaunchKernelGGL(k_moments<7>, grid, block, lds, s, m, f, slots, offsets, counts, records, tf_rgba, out,
-                       pcount, segs, bin_cap, store, counters);
+                       gacc, pcount, segs, bin_cap, store, counters);
   else
     hipLaunchKernelGGL(k_moments<9>, grid, block, lds, s, m, f, slots, offsets, counts, records, tf_rgba, out,
-                       pcount, segs, bin_cap, store, counters);
+                       gacc, pcount, segs, bin_cap, store, counters);
   return hipGetLastError();
 }
 

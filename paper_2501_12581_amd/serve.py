@@ -5,8 +5,9 @@ moments, transfer function).  It has `slots`: each slot is a library context (it
 `apc_set_workspace_limit`) with its own HIP stream, driven by one worker thread.  In "batched" mode a request
 is admitted as soon as it has arrived, a slot is free and its buffers fit the HBM budget beside the requests
 already in flight, so frames of different requests overlap on the device.  In "fifo" mode one request runs at
-a time in arrival order (the plain per-request form).  Every step of a frame runs in the library's kernels;
-this module only schedules, allocates buffers and times.
+a time in arrival order (the plain per-request form).  A frame is stage one summing every subdomain itself
+(`APC_MOMENTS_GLOBAL`: the server holds the whole mesh) and the resolve pass.  Every step of a frame runs in
+the library's kernels; this module only schedules, allocates buffers and times.
 """
 from __future__ import annotations
 
@@ -64,8 +65,7 @@ class Server:
             c = Context(device)
             c.set_workspace_limit(workspace_limit)
             self.slots.append((c, torch.cuda.Stream(device=self.dev)))
-            self.bufs.append((torch.empty(n_sub * (max_m + 1) * px, dtype=torch.float32, device=self.dev),
-                              torch.empty((max_m + 1) * px, dtype=torch.float32, device=self.dev),
+            self.bufs.append((torch.empty((max_m + 1) * px, dtype=torch.float32, device=self.dev),
                               torch.empty(4 * px, dtype=torch.float32, device=self.dev)))
         self.workspace_limit = workspace_limit
         self.hbm_budget = hbm_budget
@@ -80,9 +80,10 @@ class Server:
                 self.render(k, req)
 
     def footprint(self, req) -> int:
-        """Bytes of one request's own buffers: per-subdomain and global moments, image."""
+        """Bytes of one request's own buffers: global moments and image (the FP64 sums and the kept pieces
+        live in the slot's context, bounded by its workspace and grown by warm())."""
         px = req["size"] ** 2
-        return px * (4 * (self.n_sub + 1) * (req["m"] + 1) + 16)
+        return px * (4 * (req["m"] + 1) + 16)
 
     def _bias(self, m):
         j = np.arange(1, m + 1)
@@ -100,13 +101,11 @@ class Server:
         mb = make_mboit(m, self.alpha, self._bias(m), self.eta, 1)
         if W > self.max_size or m > self.max_m:
             raise ValueError("request larger than the server's slots (%d^2, m=%d)" % (self.max_size, self.max_m))
-        b_sub, b_mom, b_rgba = self.bufs[slot]
-        per_sub = b_sub[: self.n_sub * (m + 1) * H * W].view(self.n_sub, m + 1, H, W)
+        b_mom, b_rgba = self.bufs[slot]
         mom = b_mom[: (m + 1) * H * W].view(m + 1, H, W)
         rgba = b_rgba[: 4 * H * W].view(H, W, 4)
         s = stream.cuda_stream
-        ctx.moments_pass(self.mesh, view, tf, m, self.subs, per_sub, s)
-        ctx.sum_moments(per_sub, m, self.subs, mom, s)
+        ctx.moments_pass(self.mesh, view, tf, m, self.subs, mom, s, global_sum=True)
         ctx.resolve_pass(self.mesh, view, tf, mb, mom, self.subs, rgba, finalize=True, stream=s)
         stream.synchronize()
         return rgba

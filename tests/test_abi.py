@@ -79,3 +79,12 @@ def test_missing_library_fails_loudly(apc, monkeypatch):
     monkeypatch.setattr(apc, "LIB_PATH", "/nonexistent/libapc.so")
     with pytest.raises(ImportError):
         apc.lib()
+
+
+def test_flag_constants_match_the_header(apc):
+    text = open(HEADER).read()
+    defs = dict((k, int(v)) for k, v in re.findall(r"#define (APC_[A-Z0-9_]+) (\d+)u\b", text))
+    for name in ("APC_FINALIZE", "APC_MOMENTS_F16", "APC_REWALK", "APC_MOMENTS_GLOBAL"):
+        assert getattr(apc, name) == defs[name], name
+    flags = [defs[n] for n in ("APC_FINALIZE", "APC_MOMENTS_F16", "APC_REWALK", "APC_MOMENTS_GLOBAL")]
+    assert all(f & (f - 1) == 0 for f in flags) and len(set(flags)) == len(flags)  # distinct single bits

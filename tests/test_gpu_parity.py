@@ -420,6 +420,26 @@ def test_kept_pieces_match_rewalk(apc, ctx, m):
     assert torch.equal(kept, walked)
 
 
+@pytest.mark.parametrize("m", [4, 8])
+def test_fused_global_sum_is_bitwise_the_separate_sum(apc, ctx, m):
+    """Stage one summing the subdomains itself (APC_MOMENTS_GLOBAL) gives bitwise the global moments of the
+    per-subdomain images summed by apc_sum_moments, and the same image; the ids must be ascending."""
+    sc = synth.scene_medium(size=256)
+    sc.m = m
+    sc.bias = synth.default_bias(m)
+    r = apc.Renderer(ctx, sc)
+    sep = r.frame().clone()
+    mom_sep = r.moments.clone()
+    for _ in range(2):  # the first fused frame may still re-walk after the store grew; both must match
+        r.moments.fill_(float("nan"))
+        fused = r.frame(fused=True)
+        torch.cuda.synchronize()
+        assert torch.equal(r.moments, mom_sep)
+        assert torch.equal(fused, sep)
+    with pytest.raises(RuntimeError):
+        ctx.moments_pass(r.mesh, r.view, r.tf, m, r.subs[::-1].copy(), r.moments, global_sum=True)
+
+
 def test_workspace_limit_stages_in_chunks_with_the_same_image(apc, ctx):
     """A context whose workspace limit is far below the frame's pieces (48 MB of pool, 16 MB of staging for
     more than four times that in pieces) re-walks in stage two and stages its tiles in several chunks: the
