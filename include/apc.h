@@ -272,7 +272,9 @@ apc_status apc_set_workspace_limit(apc_ctx ctx, int64_t bytes);
  * camera and the lattice fix them; a staged piece beyond the capacity of the
  * sizing frame is never written, and the entry_overflow counter says so).
  * Calls that overlap on one graph race.
- *   flags  APC_FINALIZE or 0, as for apc_resolve_pass
+ *   flags  APC_FINALIZE or 0, as for apc_resolve_pass, and/or APC_MOMENTS_GLOBAL:
+ *          stage one sums the subdomains itself (as apc_moments_pass with that
+ *          flag: ascending ids; moments_per_sub is not used and may be NULL)
  * Errors: APC_E_NOMEM when the frame's pieces do not fit one staging buffer. */
 typedef struct apc_graph_s* apc_graph;
 apc_status apc_frame_graph_create(apc_ctx ctx, apc_mesh mesh, const apc_view* view, const apc_tf* tf,

@@ -356,7 +356,8 @@ class FrameGraph:
     """A whole frame of a Renderer captured in a HIP graph (apc_frame_graph_create): one launch per frame,
     writing the Renderer's moment and image buffers."""
 
-    def __init__(self, renderer, finalize=True):
+    def __init__(self, renderer, finalize=True, fused=False):
+        """fused: stage one sums the subdomains itself (Renderer.frame(fused=True)); per_sub is not written."""
         import torch
         r = renderer
         ids, ptr = _ids(r.subs)
@@ -364,9 +365,9 @@ class FrameGraph:
         h = C.c_void_p()
         _check(lib().apc_frame_graph_create(
             r.ctx.handle, r.mesh.handle, C.byref(r.view), C.byref(r.tf), C.byref(r.mboit), ptr, len(ids),
-            _dev_ptr(r.per_sub, torch.float32, name="moments_per_sub"),
+            None if fused else _dev_ptr(r.per_sub, torch.float32, name="moments_per_sub"),
             _dev_ptr(r.moments, torch.float32, name="moments"), _dev_ptr(r.rgba, torch.float32, name="rgba"),
-            APC_FINALIZE if finalize else 0, C.byref(h)), r.ctx.handle)
+            (APC_FINALIZE if finalize else 0) | (APC_MOMENTS_GLOBAL if fused else 0), C.byref(h)), r.ctx.handle)
         self.handle = h
         self.renderer = r
 

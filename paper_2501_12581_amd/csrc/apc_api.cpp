@@ -930,7 +930,9 @@ apc_status apc_frame_graph_create(apc_ctx ctx, apc_mesh m, const apc_view* view,
   if (!out) return fail(APC_E_ARG, "out is NULL");
   *out = nullptr;
   if (!mb) return fail(APC_E_ARG, "mboit is NULL");
-  if (flags & ~APC_FINALIZE) return fail(APC_E_ARG, "unknown flags 0x%x", flags);
+  if (flags & ~(APC_FINALIZE | APC_MOMENTS_GLOBAL)) return fail(APC_E_ARG, "unknown flags 0x%x", flags);
+  const bool global = (flags & APC_MOMENTS_GLOBAL) != 0;
+  if (!global && !moments_per_sub) return fail(APC_E_ARG, "moments_per_sub is NULL");
   apc_graph g = new (std::nothrow) apc_graph_s();
   if (!g) return fail(APC_E_NOMEM, "host allocation failed");
   if ((st = apc_create(ctx->device, &g->own)) != APC_OK) {
@@ -944,10 +946,17 @@ apc_status apc_frame_graph_create(apc_ctx ctx, apc_mesh m, const apc_view* view,
   }
   apc_ctx w = g->own;
   auto frame = [&]() -> apc_status {
-    apc_status r = apc_moments_pass(w, m, view, tf, mb->m, subs, n_sub, moments_per_sub, 0, g->cs);
-    if (r == APC_OK) r = apc_sum_moments(w, moments_per_sub, n_sub, mb->m, view->height, view->width, subs,
-                                         moments_global, g->cs);
-    if (r == APC_OK) r = apc_resolve_pass(w, m, view, tf, mb, moments_global, subs, n_sub, rgba_out, flags, g->cs);
+    apc_status r;
+    if (global) {
+      r = apc_moments_pass(w, m, view, tf, mb->m, subs, n_sub, moments_global, APC_MOMENTS_GLOBAL, g->cs);
+    } else {
+      r = apc_moments_pass(w, m, view, tf, mb->m, subs, n_sub, moments_per_sub, 0, g->cs);
+      if (r == APC_OK)
+        r = apc_sum_moments(w, moments_per_sub, n_sub, mb->m, view->height, view->width, subs, moments_global,
+                            g->cs);
+    }
+    if (r == APC_OK)
+      r = apc_resolve_pass(w, m, view, tf, mb, moments_global, subs, n_sub, rgba_out, flags & APC_FINALIZE, g->cs);
     return r;
   };
   // 1) eager frames size every workspace buffer (again while stage one's piece store overflowed: it grows

@@ -362,16 +362,17 @@ def test_tile_shapes_give_identical_results_and_autotuner(apc, ctx):
         ctx.set_tile_shape(8)
 
 
-def test_frame_graph_replays_match_eager_frames(apc, ctx):
-    """A frame captured in a HIP graph: every replay (with eager work and
-    synchronisation between replays) gives bitwise the eager frame, and after
-    the transfer-function table is edited in place a replay gives bitwise the
+@pytest.mark.parametrize("fused", [False, True])
+def test_frame_graph_replays_match_eager_frames(apc, ctx, fused):
+    """A frame captured in a HIP graph (with the separate moment sum, or with stage one summing the
+    subdomains itself): every replay (with eager work and synchronisation between replays) gives bitwise
+    the eager frame, and after the transfer-function table is edited in place a replay gives bitwise the
     eager frame with the new table."""
     sc = synth.scene_medium(size=256)
     r = apc.Renderer(ctx, sc)
-    eager = r.frame().clone()
+    eager = r.frame(fused=fused).clone()
     eager_mom = r.moments.clone()
-    g = apc.FrameGraph(r)
+    g = apc.FrameGraph(r, fused=fused)
     try:
         torch.cuda.synchronize()
         assert torch.equal(r.rgba, eager)  # the sizing frame
@@ -393,7 +394,7 @@ def test_frame_graph_replays_match_eager_frames(apc, ctx):
         g.launch()
         torch.cuda.synchronize()
         replay = r.rgba.clone()
-        again = r.frame()
+        again = r.frame(fused=fused)
         torch.cuda.synchronize()
         assert torch.equal(replay, again)
         assert not torch.equal(replay, eager)
