@@ -599,7 +599,7 @@ struct Bound {
     if (j == N) return zs[N - 1] + v * sz;
     const R a = pick<N>(zs, j - 1), b = pick<N>(zs, j);
     const R e = v * sz;
-    return a + (b - a) * e * m_rcp(R(1) + e);
+    return a + (b - a) * e * m_rcp_est(R(1) + e);  // a Newton start: the estimate suffices
   }
 
   // Table entries of node l (0 <= l < NODES): gap k = l / NI + 1, depth
@@ -661,8 +661,9 @@ struct Bound {
     bool ok = k >= 1 && k <= N - 1;
     const int kk = ok ? k : 1;
     const R lo = pick<N>(zs, kk - 1), hi = pick<N>(zs, kk);
-    const R sz = (z - lo) * m_rcp(hi - z), isz = (hi - z) * m_rcp(z - lo);
-    const R u = (z - lo) * R(NI) * m_rcp(hi - lo) - R(0.5);
+    // the interpolation coordinates only shape the Newton start: reciprocal estimates suffice
+    const R sz = (z - lo) * m_rcp_est(hi - z), isz = (hi - z) * m_rcp_est(z - lo);
+    const R u = (z - lo) * R(NI) * m_rcp_est(hi - lo) - R(0.5);
     int i = int(floor(u + R(0.5)));
     i = i < 1 ? 1 : (i > NI - 2 ? NI - 2 : i);
     const R w = u - R(i);
