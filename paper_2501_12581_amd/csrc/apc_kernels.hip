@@ -71,8 +71,11 @@ __device__ __forceinline__ int xcd_tile(int b, int nb, int run = XCD_RUN) {
   return whole + x * q + (x < r ? x : r) + i;
 }
 
+// A pixel ray: origin o, unit direction d, and unit vectors a, b = d x a
+// perpendicular to d, so that (a, b, d) is a right-handed orthonormal frame.
 struct Ray {
   float ox, oy, oz, dx, dy, dz;
+  float ax, ay, az, bx, by, bz;
 };
 
 __device__ __forceinline__ Ray pixel_ray(const FrameDev& f, int i, int j) {
@@ -100,6 +103,19 @@ __device__ __forceinline__ Ray pixel_ray(const FrameDev& f, int i, int j) {
   r.dx = dx * inv;
   r.dy = dy * inv;
   r.dz = dz * inv;
+  {
+    // a = d x h / |d x h| for a coordinate axis h far from parallel to d
+    const bool xs = fabsf(r.dx) < 0.9f;
+    const float hx = xs ? 1.0f : 0.0f, hy = xs ? 0.0f : 1.0f;
+    const float ax = -r.dz * hy, ay = r.dz * hx, az = r.dx * hy - r.dy * hx;
+    const float ia = 1.0f / sqrtf(ax * ax + ay * ay + az * az);
+    r.ax = ax * ia;
+    r.ay = ay * ia;
+    r.az = az * ia;
+    r.bx = r.dy * r.az - r.dz * r.ay;
+    r.by = r.dz * r.ax - r.dx * r.az;
+    r.bz = r.dx * r.ay - r.dy * r.ax;
+  }
   // depth 0 at the middle of the depth range
   r.ox = r.ox + f.t_mid * r.dx;
   r.oy = r.oy + f.t_mid * r.dy;
@@ -107,34 +123,31 @@ __device__ __forceinline__ Ray pixel_ray(const FrameDev& f, int i, int j) {
   return r;
 }
 
-// A vertex as seen from one ray: id, position, scalar, depth t = d.(P-o) and
-// w = d x (P-o).
+// A vertex as seen from one ray: id, scalar, depth t = d.(P-o) and its
+// coordinates u = a.(P-o), v = b.(P-o) in the plane perpendicular to the ray.
 struct VS {
   int id;
-  float x, y, z, s, t, wx, wy, wz;
+  float s, t, u, v;
 };
 
 __device__ __forceinline__ VS vstate(const Ray& r, int id, float4 p) {
 #pragma clang fp contract(off)
   VS v;
   v.id = id;
-  v.x = p.x;
-  v.y = p.y;
-  v.z = p.z;
   v.s = p.w;
   float px = p.x - r.ox, py = p.y - r.oy, pz = p.z - r.oz;
   v.t = r.dx * px + r.dy * py + r.dz * pz;
-  v.wx = r.dy * pz - r.dz * py;
-  v.wy = r.dz * px - r.dx * pz;
-  v.wz = r.dx * py - r.dy * px;
+  v.u = r.ax * px + r.ay * py + r.az * pz;
+  v.v = r.bx * px + r.by * py + r.bz * pz;
   return v;
 }
 
-// Plücker side product d.((lo-o) x (hi-o)) = (d x (lo-o)).(hi-lo) of the ray
-// with the edge lo -> hi, lo.id < hi.id.  Exact zero counts as positive.
+// Plücker side product d.((lo-o) x (hi-o)) of the ray with the edge lo -> hi,
+// lo.id < hi.id: only the components perpendicular to d contribute, so it is
+// the 2D cross product u_lo v_hi - v_lo u_hi.  Exact zero counts as positive.
 __device__ __forceinline__ float side_canon(const VS& lo, const VS& hi) {
 #pragma clang fp contract(off)
-  float p = lo.wx * (hi.x - lo.x) + lo.wy * (hi.y - lo.y) + lo.wz * (hi.z - lo.z);
+  float p = lo.u * hi.v - lo.v * hi.u;
   return p == 0.0f ? FLT_MIN : p;
 }
 
