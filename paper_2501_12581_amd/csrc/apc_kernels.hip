@@ -17,12 +17,13 @@
 //   k_sum_images canonical-order sum of partial images + renormalisation
 //
 // Geometry.  A ray crosses a face iff its Plücker side products with the
-// face's three edges share one sign.  Every edge product is computed from the
-// edge's lower-id vertex towards its higher-id vertex, with one formula, and
-// an exact zero counts as positive; the entry test of one subdomain and the
-// exit test of the walk in its neighbour therefore see identical signs for
-// the face they share, so every ray crosses each subdomain interface exactly
-// once (no gaps, no double counting).  The barycentric coordinates of the
+// face's three edges share one sign.  Every edge product is computed with one
+// formula whose two orientations give exactly opposite values, and an exact
+// zero counts as positive in the orientation from the lower vertex id to the
+// higher; the entry test of one subdomain and the exit test of the walk in
+// its neighbour therefore see identical signs for the face they share, so
+// every ray crosses each subdomain interface exactly once (no gaps, no double
+// counting).  The barycentric coordinates of the
 // crossing point are the three edge products of the face, which give the
 // depth t and the scalar at the crossing.  Functions whose results must agree
 // bit for bit between the two passes or between the entry test and the walk
@@ -142,18 +143,17 @@ __device__ __forceinline__ VS vstate(const Ray& r, int id, float4 p) {
   return v;
 }
 
-// Plücker side product d.((lo-o) x (hi-o)) of the ray with the edge lo -> hi,
-// lo.id < hi.id: only the components perpendicular to d contribute, so it is
-// the 2D cross product u_lo v_hi - v_lo u_hi.  Exact zero counts as positive.
-__device__ __forceinline__ float side_canon(const VS& lo, const VS& hi) {
-#pragma clang fp contract(off)
-  float p = lo.u * hi.v - lo.v * hi.u;
-  return p == 0.0f ? FLT_MIN : p;
-}
-
-// oriented side product of a -> b
+// Oriented Plücker side product d.((a-o) x (b-o)) of the ray with the edge
+// a -> b: only the components perpendicular to d contribute, so it is the 2D
+// cross product u_a v_b - v_a u_b.  Without contraction the two orientations
+// of an edge give exactly opposite values (the products are the same two
+// roundings in either order), so every test that meets the edge sees one
+// value up to sign; an exact zero counts as positive in the orientation from
+// the lower vertex id to the higher.
 __device__ __forceinline__ float side(const VS& a, const VS& b) {
-  return a.id < b.id ? side_canon(a, b) : -side_canon(b, a);
+#pragma clang fp contract(off)
+  const float p = a.u * b.v - a.v * b.u;
+  return p == 0.0f ? (a.id < b.id ? FLT_MIN : -FLT_MIN) : p;
 }
 
 // Crossing point of the ray with the face (A, B, C) whose oriented products
