@@ -112,6 +112,7 @@ struct apc_ctx_s {
   bool pc_valid = false;
   // capture mode (see apc_frame_graph_create): no host round trips, no uploads, no event marks
   bool capturing = false;
+  size_t store_slots = 0;     // pixels (tiles * 64) of the last stage one that kept pieces
   long long last_pieces = 0;  // pieces of the last eager resolve pass
   long long last_chunks = 0;  // and the number of staging chunks it took
   // pieces kept by stage one for stage two (see PieceStore)
@@ -655,6 +656,27 @@ apc_status apc_mesh_subdomain_info(apc_mesh m, int32_t sub, int64_t* n_tets, int
   return APC_OK;
 }
 
+// Grows the piece pool to pool_target chunks (capped by the workspace limit, else by 60 % of free memory)
+// and the chunk table to `slots` pixels of maxc chunks.  Returns false when the memory cannot be had.
+static bool grow_piece_store(apc_ctx ctx, size_t slots) {
+  const size_t chunk_bytes = sizeof(float) * 3 * apc::PIECE_CHUNK;
+  if (ctx->pool_chunks < ctx->pool_target && !ctx->capturing) {
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return false;
+    const size_t limit =
+        ctx->ws_limit > 0 ? size_t(ctx->ws_limit / 4 * 3) : size_t(0.6 * double(free_b + ctx->pool.bytes));
+    const size_t want = std::min(size_t(ctx->pool_target) * chunk_bytes, limit);
+    if (want > ctx->pool.bytes) {
+      ctx->pool.release();
+      ctx->pool_chunks = 0;
+      if (ctx->pool.ensure(want, ctx->ws_limit == 0) != hipSuccess) return false;
+      ctx->pool_chunks = (long long)(ctx->pool.bytes / chunk_bytes);
+    }
+  }
+  if (ctx->ptab.ensure(sizeof(int) * slots * ctx->maxc) != hipSuccess) return false;
+  return ctx->store_next.ensure(4 * sizeof(unsigned long long)) == hipSuccess;
+}
+
 apc_status apc_moments_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const apc_tf* tf, int32_t mm,
                             const int32_t* subs, int32_t n_sub, float* out, uint32_t flags, void* stream) {
   apc_status st = check_ctx(ctx);
@@ -682,25 +704,8 @@ apc_status apc_moments_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const
     const size_t slots = size_t(f.n_tiles) * 64;
     if (ctx->pool_target == 0)  // 128 pieces per pixel to start
       ctx->pool_target = (long long)(slots * 128 / apc::PIECE_CHUNK) + (long long)f.n_tiles * apc::STORE_BLOCK;
-    const size_t chunk_bytes = sizeof(float) * 3 * apc::PIECE_CHUNK;
-    bool ok = true;
-    if (ctx->pool_chunks < ctx->pool_target && !ctx->capturing) {
-      size_t free_b = 0, total_b = 0;
-      HIPCHK(hipMemGetInfo(&free_b, &total_b));
-      const size_t limit =
-          ctx->ws_limit > 0 ? size_t(ctx->ws_limit / 4 * 3) : size_t(0.6 * double(free_b + ctx->pool.bytes));
-      const size_t want = std::min(size_t(ctx->pool_target) * chunk_bytes, limit);
-      if (want > ctx->pool.bytes) {
-        ctx->pool.release();
-        ctx->pool_chunks = 0;
-        if (ctx->pool.ensure(want, ctx->ws_limit == 0) == hipSuccess)
-          ctx->pool_chunks = (long long)(ctx->pool.bytes / chunk_bytes);
-        else
-          ok = false;
-      }
-    }
-    if (ok && ctx->ptab.ensure(sizeof(int) * slots * ctx->maxc) != hipSuccess) ok = false;
-    if (ok && ctx->store_next.ensure(4 * sizeof(unsigned long long)) != hipSuccess) ok = false;
+    const bool ok = grow_piece_store(ctx, slots);
+    ctx->store_slots = slots;
     if (ok && ctx->pool_chunks > 0) {
       HIPCHK(apc::launch_fill_i32(ctx->store_next.as<int>(), 0, 8, s));
       ps.pool = ctx->pool.as<float>();
@@ -767,9 +772,24 @@ static apc_status bound_params(const apc_mboit* mb, apc::BoundParams& bp, int fi
   return APC_OK;
 }
 
+static apc_status resolve_frame(apc_ctx ctx, apc_mesh m, const apc_view* view, const apc_tf* tf,
+                                const apc_mboit* mb, const void* moments, const int32_t* subs, int32_t n_sub,
+                                float* rgba, uint32_t flags, void* stream);
+
 apc_status apc_resolve_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const apc_tf* tf, const apc_mboit* mb,
                             const void* moments, const int32_t* subs, int32_t n_sub, float* rgba, uint32_t flags,
                             void* stream) {
+  const apc_status st = resolve_frame(ctx, m, view, tf, mb, moments, subs, n_sub, rgba, flags, stream);
+  // a frame whose pieces did not fit the store has sized it anew: grow it now, at the end of this frame,
+  // so that the next frame's stage one does not allocate (an allocation waits for the whole device)
+  if (st == APC_OK && ctx->store_failed_last && !ctx->capturing && ctx->store_slots > 0)
+    (void)grow_piece_store(ctx, ctx->store_slots);  // on failure the next stage one tries again
+  return st;
+}
+
+static apc_status resolve_frame(apc_ctx ctx, apc_mesh m, const apc_view* view, const apc_tf* tf,
+                                const apc_mboit* mb, const void* moments, const int32_t* subs, int32_t n_sub,
+                                float* rgba, uint32_t flags, void* stream) {
   apc_status st = check_ctx(ctx);
   if (st != APC_OK) return st;
   if (!m) return fail(APC_E_ARG, "mesh is NULL");

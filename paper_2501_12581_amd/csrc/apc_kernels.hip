@@ -577,6 +577,10 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_WALK_W
   EntryList L{ent_t, ent_c, lane};
   LaneCount cnt = {};
   int covering = 0;  // subdomains with at least one piece on this ray
+  // the global sum's FP64 partials: in registers for m <= 6 (room within the register budget of 3
+  // wavefronts per SIMD), else in the per-pixel scratch gacc; the same additions either way
+  constexpr bool REG_ACC = M1 <= 7;
+  double acc[REG_ACC ? M1 : 1];
   MomentSink<M1> sink;  // one sink for all subdomains: its piece store runs across them
   sink.f = &f;
   sink.tfa = tfa;
@@ -611,7 +615,10 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_WALK_W
 #pragma unroll
         for (int j = 0; j < M1; ++j) {
           const double v = double(float(sink.b[j]));
-          g[size_t(j) * HW] = covering > 0 ? g[size_t(j) * HW] + v : v;
+          if constexpr (REG_ACC)
+            acc[j] = covering > 0 ? acc[j] + v : v;
+          else
+            g[size_t(j) * HW] = covering > 0 ? g[size_t(j) * HW] + v : v;
         }
       }
     } else if (valid) {
@@ -624,7 +631,16 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_WALK_W
   if (gacc && valid) {
     float* o = out + pix;
 #pragma unroll
-    for (int j = 0; j < M1; ++j) o[size_t(j) * HW] = covering > 0 ? float(gacc[size_t(j) * HW + pix]) : 0.0f;
+    for (int j = 0; j < M1; ++j) {
+      double t = 0.0;
+      if (covering > 0) {
+        if constexpr (REG_ACC)
+          t = acc[j];
+        else
+          t = gacc[size_t(j) * HW + pix];
+      }
+      o[size_t(j) * HW] = float(t);
+    }
   }
   if (pcount) pcount[size_t(tile) * WAVE + lane] = int(cnt.pieces);
   if (segs && valid) {  // [2][H][W]: segments, covering subdomains
