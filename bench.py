@@ -68,13 +68,14 @@ def serve_run(n_requests):
     import synth
     from paper_2501_12581_amd.serve import Server
     t0 = time.time()
-    sc = synth.scene_batching(n=144)
+    sc = synth.scene_batching(size=1024)
     m = sc.mesh
     tfs = [synth.make_tf(s) for s in (21, 22, 23)]
     srv = Server((m.xyz, m.scalar, m.tets, m.tet_sub, m.n_sub), sc.step, tfs, (sc.s_min, sc.s_max), slots=4,
                  workspace_limit=40 << 30, hbm_budget=64 << 30)
     srv.warm()  # every slot's library buffers at the largest request's size before serving
-    log("serving: %d tets, 72 uneven subdomains, resident and warm in %.1fs" % (m.n_tets, time.time() - t0))
+    log("serving: %d tets (adaptive), 72 uneven subdomains, generated, resident and warm in %.1fs" % (
+        m.n_tets, time.time() - t0))
     warm = synth.request_stream(8, rate=1000.0, seed=99)
     srv.run(warm, "batched")
     srv.run(warm, "fifo")
@@ -87,7 +88,8 @@ def serve_run(n_requests):
             res["%s_%g" % (mode, rate)] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
             log("serving %g/s %s: %s" % (rate, mode, res["%s_%g" % (mode, rate)]))
     srv.close()
-    return {"workload": "batching mesh: %d tets (jittered 144^3 Kuhn grid), 72 Morton subdomains of weight ratio 12; "
+    return {"workload": "batching mesh: %d tets (32^3 base refined 0-3 levels, cone decomposition), 72 Morton "
+                        "subdomains of tet-count ratio 12; "
                         "%d requests per run, Poisson arrivals, sizes {256,512,1024,2048}^2, m in {4,6,8}, "
                         "3 transfer functions, cameras on the radius-2 sphere" % (m.n_tets, n_requests),
             "rate_50_per_s": {"batched": res["batched_50"], "one_at_a_time": res["fifo_50"]},
@@ -99,7 +101,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="large", choices=["large", "medium", "tiny", "slabs"])
+    ap.add_argument("--workload", default="large", choices=["large", "batching", "medium", "tiny", "slabs"])
     ap.add_argument("--ranks", type=int, default=16, help="slabs workload: subdomains (4 slabs each)")
     ap.add_argument("--m", type=int, default=None, help="override the number of moments (4, 6, 8)")
     ap.add_argument("--tile-width", type=int, default=None, help="pixels per tile row (tile = w x 64/w)")
@@ -145,6 +147,8 @@ def main():
         if args.grid:
             kw["n"] = args.grid
         sc = synth.scene_large(**kw)
+    elif args.workload == "batching":
+        sc = synth.scene_batching(**({"size": args.size} if args.size else {}))
     elif args.workload == "medium":
         sc = synth.scene_medium(**({"size": args.size} if args.size else {}))
     elif args.workload == "slabs":
@@ -323,8 +327,11 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "%s: %d tets (jittered Kuhn grid), %d %s subdomains, %dx%d %s view, m=%d" % (
-            sc.name, mesh.n_tets, S, "interleaved-slab (4 slabs each)" if args.workload == "slabs" else "Morton",
+        "config": {"workload": "%s: %d tets (%s), %d %s subdomains, %dx%d %s view, m=%d" % (
+            sc.name, mesh.n_tets, "adaptive: 32^3 base refined 0-3 levels, cone decomposition"
+            if args.workload == "batching" else "jittered Kuhn grid", S,
+            {"slabs": "interleaved-slab (4 slabs each)", "batching": "Morton (tet-count ratio 12)"}.get(
+                args.workload, "Morton"),
             W, H, "perspective" if sc.view["projection"] else "orthographic", m),
             "global_batch": 1, "seq_len": None, "parallelism": "single GPU, all subdomains on device"},
         "frames_per_s": round(1e3 / ms_per_step, 4),

@@ -13,6 +13,9 @@ one GPU; the paper's FUN3D and Exajet meshes are not available, these stand in):
   tiny      16^3 cubes x 6 = 24,576 tets, 4 subdomains, orthographic 128^2, m=4
   medium    64^3 cubes x 6 = 1,572,864 tets, 16 subdomains, perspective 1024^2, m=6
   large     256^3 cubes x 6 = 100,663,296 tets, 72 subdomains, perspective 2560^2, m=8
+  batching  adaptive mesh (32^3 base refined 0-3 levels, 19M-21M tets, synth.amr), 72 subdomains of
+            tet-count ratio 12, perspective 2560^2, m=8
+  slabs     interleaved z-slabs (each subdomain owns 4 separated slabs)
 """
 from __future__ import annotations
 
@@ -25,7 +28,7 @@ __all__ = [
     "Mesh", "Scene", "jittered_grid", "kuhn_tets", "morton_order", "partition_chunks",
     "partition_slabs", "gaussian_field", "make_tf", "ortho_view_z", "perspective_view",
     "sphere_eye", "default_bias", "scene_tiny", "scene_medium", "scene_large", "scene",
-    "sandwich_scene",
+    "sandwich_scene", "scene_batching", "scene_amr_small", "scene_slabs",
 ]
 
 
@@ -334,14 +337,29 @@ def uneven_weights(n_sub: int, ratio: float, seed: int) -> np.ndarray:
     return np.random.default_rng(seed).permutation(w)
 
 
-def scene_batching(n: int = 144, size: int = 1024, m: int = 8, seed: int = 7, camera: int = 0) -> Scene:
-    """Uneven-subdomain workload: jittered n^3 grid x 6 tets (144: 17,915,904 tets), 72 Morton chunks with
-    weights 12^(k/71) in seeded order (largest / smallest = 12), perspective camera on the radius-2 sphere.
-    Uniform cells stand in for the 0-3 level refinement of an AMR mesh (not generated here)."""
-    w = uneven_weights(72, 12.0, seed + 5)
-    mesh = grid_mesh(n, 72, seed, n_gauss=16, jagged_seed=None, chunk_weights=w)
+def scene_batching(size: int = 2560, m: int = 8, seed: int = 7, camera: int = 0, base: int = 32, levels: int = 3,
+                   tet_range: tuple = (19_000_000, 21_000_000), n_sub: int = 72) -> Scene:
+    """Uneven-subdomain workload on an adaptive mesh: a base^3 grid of cubes refined 0..levels times where
+    |grad f| * h exceeds a threshold chosen so that the tet count falls in tet_range, 2:1 balanced and cut
+    into conforming tets by cone decomposition (synth.amr; defaults: 32^3 base, finest 256^3, 19M-21M tets);
+    n_sub chunks of whole leaves in Morton order with tet counts in ratio 12^(k/(n_sub-1)), seeded order
+    (largest / smallest = 12); perspective camera on the radius-2 sphere; step a quarter of the finest
+    cell (1/1024)."""
+    from .amr import amr_mesh
+    w = uneven_weights(n_sub, 12.0, seed + 5)
+    mesh, _, _ = amr_mesh(base, levels, n_sub, seed, tet_range=tet_range, chunk_weights=w)
     view = perspective_view(sphere_eye(seed + 3 + 97 * camera), (0.5, 0.5, 0.5), size, size)
-    return _scene("batching", mesh, view, n, m, tf_seed=seed + 11)
+    return _scene("batching", mesh, view, base << levels, m, tf_seed=seed + 11)
+
+
+def scene_amr_small(size: int = 256, m: int = 8, seed: int = 8, threshold: float = 0.3, n_sub: int = 8) -> Scene:
+    """A small adaptive mesh with leaves of all four levels (8^3 base, finest 64^3, about 480K tets at the
+    default threshold), n_sub uneven chunks (ratio 12), perspective camera."""
+    from .amr import amr_mesh
+    w = uneven_weights(n_sub, 12.0, seed + 5)
+    mesh, _, _ = amr_mesh(8, 3, n_sub, seed, threshold=threshold, chunk_weights=w)
+    view = perspective_view(sphere_eye(seed + 3), (0.5, 0.5, 0.5), size, size)
+    return _scene("amr_small", mesh, view, 64, m, tf_seed=seed + 11)
 
 
 def request_stream(n: int, rate: float = 50.0, seed: int = 12, sizes=(256, 512, 1024, 2048), ms=(4, 6, 8),
