@@ -105,7 +105,8 @@ def main():
     ap.add_argument("--ranks", type=int, default=16, help="slabs workload: subdomains (4 slabs each)")
     ap.add_argument("--m", type=int, default=None, help="override the number of moments (4, 6, 8)")
     ap.add_argument("--tile-width", type=int, default=None, help="pixels per tile row (tile = w x 64/w)")
-    ap.add_argument("--autotune", action="store_true", help="pick the tile shape with the autotuner first")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the tile shape with the autotuner first (on by default for the batching workload)")
     ap.add_argument("--size", type=int, default=None, help="override the image size (square)")
     ap.add_argument("--grid", type=int, default=None, help="override cubes per axis (large workload)")
     ap.add_argument("--cpu-pixels", type=int, default=65536, help="oracle sample size (0 = skip)")
@@ -174,9 +175,9 @@ def main():
     tuned = None
     if args.tile_width:
         ctx.set_tile_shape(args.tile_width)
-    if args.autotune:
-        best, ms = ctx.autotune_tile_shape(r.mesh, r.view, r.tf, sc.m, r.subs, r.per_sub, repeats=1)
-        tuned = {"best_width": best, "stage_one_ms_by_width": {str(k): round(v, 3) for k, v in ms.items()}}
+    if args.autotune or (args.workload == "batching" and not args.tile_width):
+        best, ms = ctx.autotune_tile_shape(r.mesh, r.view, r.tf, r.mboit, r.subs, r.moments, r.rgba, repeats=1)
+        tuned = {"best_width": best, "frame_ms_by_width": {str(k): round(v, 3) for k, v in ms.items()}}
         log("autotuned tile: %s" % tuned)
     fused = not args.separate_sum  # one GPU holds every subdomain: stage one sums them (APC_MOMENTS_GLOBAL)
     for _ in range(args.warmup):

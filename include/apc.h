@@ -294,15 +294,22 @@ apc_status apc_frame_graph_destroy(apc_graph graph);
 apc_status apc_set_tile_shape(apc_ctx ctx, int32_t tile_width);  /* 1, 2, 4, ..., 64; else APC_E_ARG */
 apc_status apc_get_tile_shape(apc_ctx ctx, int32_t* tile_width, int32_t* tile_height);
 
-/* Autotuner: times apc_moments_pass (one warm-up, then the best of `repeats`
- * runs, HIP events on `stream`) for tile widths 2, 4, 8, 16, 32, sets the
- * fastest on the context and returns it.  Synchronous.
- *   moments_per_sub  device [n_sub][m+1][H][W] FP32 scratch (overwritten)
- *   ms_per_width     host [7] or NULL: entry k = stage-one milliseconds for
- *                    width 2^k, -1 where not timed */
-apc_status apc_autotune_tile_shape(apc_ctx ctx, apc_mesh mesh, const apc_view* view, const apc_tf* tf, int32_t m,
-                                   const int32_t* subdomains, int32_t n_sub, float* moments_per_sub, int32_t repeats,
-                                   int32_t* best_width, float* ms_per_width, void* stream);
+/* Autotuner: times whole frames -- stage one summing the subdomains itself
+ * (APC_MOMENTS_GLOBAL: `subdomains` ascending, else APC_E_ARG) followed by
+ * the finalising resolve, as a frame on one GPU runs them -- for tile widths
+ * 2, 4, 8, 16, 32 (one warm-up frame per width, then the best of `repeats`,
+ * HIP events on `stream`), sets the fastest on the context and returns it.
+ * Synchronous.  The tile shape changes both passes' cost (which rays walk
+ * together in stage one; which pieces stage two reads together), so a frame,
+ * not stage one alone, is timed.
+ *   moments       device [m+1][H][W] FP32 scratch (overwritten), m = mboit->m
+ *   rgba_out      device [H][W][4] FP32 scratch (overwritten)
+ *   ms_per_width  host [7] or NULL: entry k = frame milliseconds for width
+ *                 2^k, -1 where not timed */
+apc_status apc_autotune_tile_shape(apc_ctx ctx, apc_mesh mesh, const apc_view* view, const apc_tf* tf,
+                                   const apc_mboit* mboit, const int32_t* subdomains, int32_t n_sub, float* moments,
+                                   float* rgba_out, int32_t repeats, int32_t* best_width, float* ms_per_width,
+                                   void* stream);
 
 /* ------------------------------------------------------------------ diagnostics */
 

@@ -130,8 +130,8 @@ def lib():
         L.apc_get_tile_shape.restype = st
         L.apc_get_tile_shape.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.apc_autotune_tile_shape.restype = st
-        L.apc_autotune_tile_shape.argtypes = [vp, vp, C.POINTER(View), C.POINTER(TF), C.c_int32, vp, C.c_int32, vp,
-                                              C.c_int32, C.POINTER(C.c_int32), vp, vp]
+        L.apc_autotune_tile_shape.argtypes = [vp, vp, C.POINTER(View), C.POINTER(TF), C.POINTER(Mboit), vp,
+                                              C.c_int32, vp, vp, C.c_int32, C.POINTER(C.c_int32), vp, vp]
         L.apc_segment_counts.restype = st
         L.apc_segment_counts.argtypes = [vp, vp, C.c_int32, C.c_int32, vp]
         L.apc_sum_images.restype = st
@@ -305,16 +305,20 @@ class Context:
         self._ck(lib().apc_get_tile_shape(self.handle, C.byref(w), C.byref(h)))
         return w.value, h.value
 
-    def autotune_tile_shape(self, mesh, view: View, tf: TF, m, subdomains, scratch, repeats=2, stream=None):
-        """Time stage one for tile widths 2..32, keep the fastest; returns (width, {width: ms})."""
+    def autotune_tile_shape(self, mesh, view: View, tf: TF, mboit: Mboit, subdomains, moments, rgba, repeats=2,
+                            stream=None):
+        """Time whole frames (stage one summing the subdomains, then the finalising resolve) for tile widths
+        2..32 and keep the fastest; moments [m+1][H][W] and rgba [H][W][4] are scratch.  Returns
+        (width, {width: frame ms})."""
         import torch
         ids, ptr = _ids(subdomains)
         best = C.c_int32(0)
         ms = np.full(7, -1.0, dtype=np.float32)
-        self._ck(lib().apc_autotune_tile_shape(self.handle, mesh.handle, C.byref(view), C.byref(tf), int(m), ptr,
-                                               len(ids), _dev_ptr(scratch, torch.float32, name="scratch"),
-                                               int(repeats), C.byref(best), C.c_void_p(ms.ctypes.data),
-                                               _stream(stream)))
+        self._ck(lib().apc_autotune_tile_shape(self.handle, mesh.handle, C.byref(view), C.byref(tf),
+                                               C.byref(mboit), ptr, len(ids),
+                                               _dev_ptr(moments, torch.float32, name="moments"),
+                                               _dev_ptr(rgba, torch.float32, name="rgba"), int(repeats),
+                                               C.byref(best), C.c_void_p(ms.ctypes.data), _stream(stream)))
         return best.value, {1 << k: float(ms[k]) for k in range(7) if ms[k] >= 0}
 
     def segment_counts(self, height, width, stream=None):

@@ -1065,12 +1065,14 @@ apc_status apc_get_tile_shape(apc_ctx ctx, int32_t* tile_width, int32_t* tile_he
   return APC_OK;
 }
 
-apc_status apc_autotune_tile_shape(apc_ctx ctx, apc_mesh m, const apc_view* view, const apc_tf* tf, int32_t mm,
-                                   const int32_t* subs, int32_t n_sub, float* moments_per_sub, int32_t repeats,
-                                   int32_t* best_width, float* ms_per_width, void* stream) {
+apc_status apc_autotune_tile_shape(apc_ctx ctx, apc_mesh m, const apc_view* view, const apc_tf* tf,
+                                   const apc_mboit* mboit, const int32_t* subs, int32_t n_sub, float* moments,
+                                   float* rgba_out, int32_t repeats, int32_t* best_width, float* ms_per_width,
+                                   void* stream) {
   apc_status st = check_ctx(ctx);
   if (st != APC_OK) return st;
   if (repeats < 1 || repeats > 100) return fail(APC_E_ARG, "repeats must be in 1..100");
+  if (!mboit) return fail(APC_E_ARG, "mboit is NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(hipEventCreate(&e0));
@@ -1086,7 +1088,10 @@ apc_status apc_autotune_tile_shape(apc_ctx ctx, apc_mesh m, const apc_view* view
     float t_min = 0.0f;
     for (int rep = 0; rep <= repeats && res == APC_OK; ++rep) {  // the first run is a warm-up
       if (hipEventRecord(e0, s) != hipSuccess) res = fail(APC_E_DEVICE, "event record failed");
-      if (res == APC_OK) res = apc_moments_pass(ctx, m, view, tf, mm, subs, n_sub, moments_per_sub, 0, stream);
+      if (res == APC_OK)
+        res = apc_moments_pass(ctx, m, view, tf, mboit->m, subs, n_sub, moments, APC_MOMENTS_GLOBAL, stream);
+      if (res == APC_OK)
+        res = apc_resolve_pass(ctx, m, view, tf, mboit, moments, subs, n_sub, rgba_out, APC_FINALIZE, stream);
       if (res == APC_OK && hipEventRecord(e1, s) != hipSuccess) res = fail(APC_E_DEVICE, "event record failed");
       float ms = 0.0f;
       if (res == APC_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))

@@ -337,8 +337,10 @@ def test_segment_counts_match_oracle_on_jagged_chunks(apc, ctx):
 def test_tile_shapes_give_identical_results_and_autotuner(apc, ctx):
     """Any tile shape (w x 64/w pixels per wavefront) gives bitwise the same
     moments, segment counts and image: each ray walks alone and each pixel's
-    sums run in its own walk order.  The autotuner times stage one for widths
-    2..32, keeps the fastest, and the frame after it is unchanged."""
+    sums run in its own walk order.  The autotuner times whole frames (stage
+    one summing the subdomains, then the resolve) for widths 2..32, keeps the
+    fastest, and the frame after it is unchanged; it needs the subdomains in
+    ascending order, as a frame that sums them in stage one does."""
     sc = synth.scene_medium(size=384)
     r = apc.Renderer(ctx, sc)
     outs = {}
@@ -351,7 +353,11 @@ def test_tile_shapes_give_identical_results_and_autotuner(apc, ctx):
         for w in (2, 32, 64):
             for a, b in zip(outs[w], outs[8]):
                 assert torch.equal(a, b), w
-        best, ms = ctx.autotune_tile_shape(r.mesh, r.view, r.tf, sc.m, r.subs, r.per_sub, repeats=1)
+        before = ctx.tile_shape()
+        with pytest.raises(apc.ApcError):
+            ctx.autotune_tile_shape(r.mesh, r.view, r.tf, r.mboit, r.subs[::-1].copy(), r.moments, r.rgba)
+        assert ctx.tile_shape() == before  # a rejected call leaves the shape as it was
+        best, ms = ctx.autotune_tile_shape(r.mesh, r.view, r.tf, r.mboit, r.subs, r.moments, r.rgba, repeats=1)
         print("autotuned tile width", best, ms)
         assert best in (2, 4, 8, 16, 32) and sorted(ms) == [2, 4, 8, 16, 32] and all(v > 0 for v in ms.values())
         assert ctx.tile_shape()[0] == best
