@@ -63,16 +63,18 @@ def measured_traffic(args, kernel):
         b["fetch_bytes"], b["write_bytes"])
 
 
-def serve_run(n_requests):
-    """p50/p99 frame latency of a served request stream, batched (4 slots) and one at a time."""
+def serve_run(n_requests, slots=4, workspace_limit=40 << 30, small_slots=0, small_workspace_limit=12 << 30):
+    """p50/p99 frame latency of a served request stream, batched (`slots` slots for any size and `small_slots`
+    for sizes up to 1024^2) and one at a time."""
     import synth
     from paper_2501_12581_amd.serve import Server
     t0 = time.time()
     sc = synth.scene_batching(size=1024)
     m = sc.mesh
     tfs = [synth.make_tf(s) for s in (21, 22, 23)]
-    srv = Server((m.xyz, m.scalar, m.tets, m.tet_sub, m.n_sub), sc.step, tfs, (sc.s_min, sc.s_max), slots=4,
-                 workspace_limit=40 << 30, hbm_budget=64 << 30)
+    srv = Server((m.xyz, m.scalar, m.tets, m.tet_sub, m.n_sub), sc.step, tfs, (sc.s_min, sc.s_max), slots=slots,
+                 workspace_limit=workspace_limit, hbm_budget=64 << 30, small_slots=small_slots, small_size=1024,
+                 small_workspace_limit=small_workspace_limit)
     srv.warm()  # every slot's library buffers at the largest request's size before serving
     log("serving: %d tets (adaptive), 72 uneven subdomains, generated, resident and warm in %.1fs" % (
         m.n_tets, time.time() - t0))

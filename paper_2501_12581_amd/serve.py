@@ -3,8 +3,10 @@
 A `Server` keeps one mesh resident and runs frames for a stream of requests (image size, camera, number of
 moments, transfer function).  It has `slots`: each slot is a library context (its own workspace, capped by
 `apc_set_workspace_limit`) with its own HIP stream, driven by one worker thread.  In "batched" mode a request
-is admitted as soon as it has arrived, a slot is free and its buffers fit the HBM budget beside the requests
-already in flight, so frames of different requests overlap on the device.  In "fifo" mode one request runs at
+is admitted as soon as it has arrived, a slot that can hold its size is free and its buffers fit the HBM budget
+beside the requests already in flight, so frames of different requests overlap on the device.  Slots come in
+two sizes: large ones take any request, small ones only requests up to a smaller image size, with a workspace
+sized for those (the kept pieces of a frame grow with its pixels, so HBM holds more small slots).  In "fifo" mode one request runs at
 a time in arrival order (the plain per-request form).  A frame is stage one summing every subdomain itself
 (`APC_MOMENTS_GLOBAL`: the server holds the whole mesh) and the resolve pass.  Every step of a frame runs in
 the library's kernels; this module only schedules, allocates buffers and times.
@@ -37,12 +39,16 @@ def look_at_view(eye, target, width: int, height: int, fovy_deg: float = 45.0) -
 
 class Server:
     def __init__(self, mesh, step, tfs, s_range, kappa=4.0, absorbance_max=10.0, alpha=5e-5, eta=0.3,
-                 slots=4, workspace_limit=8 << 30, hbm_budget=64 << 30, max_size=2048, max_m=8, device=0):
+                 slots=4, workspace_limit=8 << 30, hbm_budget=64 << 30, max_size=2048, max_m=8, device=0,
+                 small_slots=0, small_size=1024, small_workspace_limit=None):
         """mesh: arrays (xyz, scalar, tets, tet_sub, n_sub); tfs: list of [n][4] float32 tables;
         s_range: (s_min, s_max) of the transfer functions' domain; workspace_limit: bytes per slot for the
         kept-piece pool + staging; hbm_budget: bytes of the requests' own buffers allowed in flight;
         max_size, max_m: the largest request, for which every slot's buffers are allocated once (no
-        allocation while serving: device allocations would synchronise the other slots' work)."""
+        allocation while serving: device allocations would synchronise the other slots' work).
+        small_slots more slots take only requests up to small_size^2, with small_workspace_limit bytes each
+        (default: workspace_limit scaled by the pixel ratio): a slot's workspace must hold the kept pieces
+        of its largest frame, so HBM allows more small slots than large ones."""
         import torch
         self.torch = torch
         self.device = device
@@ -60,22 +66,27 @@ class Server:
         self.slots = []
         self.bufs = []
         self.max_size, self.max_m = max_size, max_m
-        px = max_size * max_size
-        for _ in range(slots):
+        if small_slots and not 0 < small_size < max_size:
+            raise ValueError("small_size must lie below max_size")
+        if small_workspace_limit is None:
+            small_workspace_limit = workspace_limit * small_size * small_size // (max_size * max_size)
+        self.slot_size = [max_size] * slots + [small_size] * small_slots
+        for k, size in enumerate(self.slot_size):
             c = Context(device)
-            c.set_workspace_limit(workspace_limit)
+            c.set_workspace_limit(workspace_limit if k < slots else small_workspace_limit)
             self.slots.append((c, torch.cuda.Stream(device=self.dev)))
+            px = size * size
             self.bufs.append((torch.empty((max_m + 1) * px, dtype=torch.float32, device=self.dev),
                               torch.empty(4 * px, dtype=torch.float32, device=self.dev)))
         self.workspace_limit = workspace_limit
         self.hbm_budget = hbm_budget
 
     def warm(self, eye=(2.0, 0.9, 0.7), tf=0):
-        """One frame of the largest request (max_size^2, max_m) on every slot, one slot at a time: the
+        """One frame of each slot's largest request (its size, max_m) on every slot, one slot at a time: the
         library grows a context's buffers (bins, piece pool, staging) to what a frame needs, and a device
         allocation or release while other slots' frames run waits for all of them."""
-        req = {"id": -1, "arrival": 0.0, "size": self.max_size, "eye": eye, "m": self.max_m, "tf": tf}
         for k in range(len(self.slots)):
+            req = {"id": -1, "arrival": 0.0, "size": self.slot_size[k], "eye": eye, "m": self.max_m, "tf": tf}
             for _ in range(2):  # the second frame runs at the grown size
                 self.render(k, req)
 
@@ -99,8 +110,8 @@ class Server:
         view = make_view(look_at_view(req["eye"], (0.5, 0.5, 0.5), W, H), self.step)
         tf = make_tf(self.tf_dev[req["tf"]], self.s_range[0], self.s_range[1], self.kappa, self.absorbance_max)
         mb = make_mboit(m, self.alpha, self._bias(m), self.eta, 1)
-        if W > self.max_size or m > self.max_m:
-            raise ValueError("request larger than the server's slots (%d^2, m=%d)" % (self.max_size, self.max_m))
+        if W > self.slot_size[slot] or m > self.max_m:
+            raise ValueError("request larger than slot %d (%d^2, m=%d)" % (slot, self.slot_size[slot], self.max_m))
         b_mom, b_rgba = self.bufs[slot]
         mom = b_mom[: (m + 1) * H * W].view(m + 1, H, W)
         rgba = b_rgba[: 4 * H * W].view(H, W, 4)
@@ -121,7 +132,7 @@ class Server:
             rgba = self.render(slot, req)
             return rgba.cpu() if keep_images else None
 
-        return schedule(requests, n_slots, self.footprint, self.hbm_budget, render, mode)
+        return schedule(requests, n_slots, self.footprint, self.hbm_budget, render, mode, slot_size=self.slot_size)
 
     def close(self):
         self.torch.cuda.synchronize(self.dev)
@@ -131,17 +142,25 @@ class Server:
         self.owner.close()
 
 
-def schedule(requests, n_slots, footprint, hbm_budget, render, mode="batched") -> dict:
+def schedule(requests, n_slots, footprint, hbm_budget, render, mode="batched", slot_size=None) -> dict:
     """Open-loop continuous batching.  Request k is released at requests[k]["arrival"] seconds after the
-    start and admitted, in arrival order, as soon as a slot is free and the footprints of the requests in
-    flight plus its own fit `hbm_budget` (a request alone is always admitted); `render(slot, req)` then runs
-    it on a worker thread (its return value, if not None, is kept as the record's "rgba").  Returns the
-    records (arrival, start, end, latency in seconds) and p50/p99/mean latency in ms and frames/s."""
+    start and admitted, in arrival order, as soon as a slot that can hold it is free (slot_size[s] >= its
+    "size"; every slot when slot_size is None) and the footprints of the requests in flight plus its own fit
+    `hbm_budget` (a request alone is always admitted).  Of the free slots that can hold it, it takes the
+    smallest (then the lowest index), so that large slots stay free for large requests.  `render(slot, req)`
+    then runs it on a worker thread (its return value, if not None, is kept as the record's "rgba").
+    Returns the records (arrival, start, end, latency in seconds) and p50/p99/mean latency in ms and
+    frames/s."""
     reqs = sorted(requests, key=lambda r: r["arrival"])
-    free = queue.Queue()
-    for k in range(n_slots):
-        free.put(k)
-    lock = threading.Lock()
+    if slot_size is not None:
+        if len(slot_size) < n_slots:
+            raise ValueError("slot_size lists %d slots, %d are used" % (len(slot_size), n_slots))
+        biggest = max(slot_size[:n_slots])
+        too_big = [r["id"] for r in reqs if r.get("size", 0) > biggest]
+        if too_big:
+            raise ValueError("requests %s are larger than every slot (%d)" % (too_big[:3], biggest))
+    cv = threading.Condition()
+    free = set(range(n_slots))
     inflight = [0]
     done = {}
     errors = []
@@ -160,9 +179,10 @@ def schedule(requests, n_slots, footprint, hbm_budget, render, mode="batched") -
         except Exception as e:  # reported after the run
             errors.append((req["id"], repr(e)))
         finally:
-            with lock:
+            with cv:
                 inflight[0] -= footprint(req)
-            free.put(slot)
+                free.add(slot)
+                cv.notify_all()
 
     threads = []
     for req in reqs:
@@ -170,16 +190,16 @@ def schedule(requests, n_slots, footprint, hbm_budget, render, mode="batched") -
         if wait > 0:
             time.sleep(wait)
         fp = footprint(req)
-        while True:  # admission: a free slot and room in the HBM budget
-            slot = free.get()
-            with lock:
-                fits = inflight[0] == 0 or inflight[0] + fp <= hbm_budget
-                if fits:
+        size = req.get("size", 0)
+        with cv:
+            while True:  # admission: a free slot that holds the request and room in the HBM budget
+                cands = [k for k in free if slot_size is None or slot_size[k] >= size]
+                if cands and (inflight[0] == 0 or inflight[0] + fp <= hbm_budget):
+                    slot = min(cands, key=lambda k: (0 if slot_size is None else slot_size[k], k))
+                    free.discard(slot)
                     inflight[0] += fp
-            if fits:
-                break
-            free.put(slot)
-            time.sleep(0.0005)
+                    break
+                cv.wait(0.05)
         th = threading.Thread(target=work, args=(slot, req))
         th.start()
         threads.append(th)

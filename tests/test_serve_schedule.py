@@ -4,6 +4,7 @@ import threading
 import time
 
 import numpy as np
+import pytest
 
 from paper_2501_12581_amd.serve import schedule
 
@@ -60,3 +61,27 @@ def test_admission_by_footprint_limits_concurrency():
     # a request larger than the whole budget still runs (alone)
     st = schedule([{"id": 0, "arrival": 0.0}], 2, lambda r: 100, 10, _stub({0: 0.0})[0])
     assert st["requests"] == 1
+
+
+def test_size_aware_slots_take_the_smallest_slot_that_holds_the_request():
+    # slots 0, 1 hold 2048^2, slots 2, 3 only 512^2
+    sizes = [2048, 2048, 512, 512]
+    reqs = [{"id": 0, "arrival": 0.0, "size": 256}, {"id": 1, "arrival": 0.0, "size": 2048},
+            {"id": 2, "arrival": 0.0, "size": 512}, {"id": 3, "arrival": 0.0, "size": 1024},
+            {"id": 4, "arrival": 0.0, "size": 2048}, {"id": 5, "arrival": 0.2, "size": 256}]
+    render, _ = _stub({k: 0.05 for k in range(6)})
+    st = schedule(reqs, 4, lambda r: 1, 1 << 30, render, slot_size=sizes)
+    by = {r["id"]: r for r in st["records"]}
+    for r in st["records"]:
+        assert sizes[r["slot"]] >= r["size"]  # a request only runs on a slot that holds it
+    assert by[0]["slot"] == 2 and by[2]["slot"] == 3  # small requests go to the small slots first
+    assert by[1]["slot"] == 0
+    # request 3 (1024^2) needs a large slot: slot 1; request 4 waits for a large slot to free up
+    assert by[3]["slot"] == 1 and by[4]["start"] >= min(by[1]["end"], by[3]["end"]) - 1e-3
+    assert by[5]["slot"] in (2, 3)
+
+
+def test_request_larger_than_every_slot_is_rejected_up_front():
+    with pytest.raises(ValueError):
+        schedule([{"id": 0, "arrival": 0.0, "size": 4096}], 2, lambda r: 1, 1 << 30, _stub({0: 0.0})[0],
+                 slot_size=[2048, 1024])
