@@ -127,7 +127,11 @@ apc_status apc_mesh_subdomain_info(apc_mesh mesh, int32_t subdomain, int64_t* n_
  * bounding sphere of the whole mesh (centre c, radius R of its bounding box):
  * t_near = dist - R, t_far = dist + R with dist = |c - eye| (perspective) or
  * (c - eye).dir/|dir| (orthographic).  The same range must be used by every
- * subdomain and by both passes.  t_near must come out positive. */
+ * subdomain and by both passes.  t_near must come out positive.  Every ray
+ * must start outside the mesh (the walk enters each subdomain through its
+ * boundary faces): a perspective eye outside the mesh's bounding box, an
+ * orthographic image plane with the whole box in front of it; APC_E_ARG
+ * otherwise.  Depths outside [t_near, t_far] warp outside [-1, 1]. */
 typedef struct apc_view {
   int32_t width, height;
   int32_t projection;   /* APC_ORTHOGRAPHIC or APC_PERSPECTIVE */

@@ -257,6 +257,19 @@ apc_status make_frame(const apc_mesh_s* m, const apc_view* v, const apc_tf* tf, 
   double minv[9];
   if (!inverse3(dir, v->right, v->down, minv)) return fail(APC_E_ARG, "dir, right and down are not independent");
   for (int k = 0; k < 9; ++k) f.minv[k] = float(minv[k]);
+  // the walk enters each subdomain through its boundary faces, so no ray may start inside the mesh: a
+  // perspective eye lies outside the mesh's bounding box, an orthographic image plane has the box in front
+  if (v->projection == APC_PERSPECTIVE) {
+    bool inside = true;
+    for (int k = 0; k < 3; ++k) inside = inside && v->eye[k] >= m->lo[k] && v->eye[k] <= m->hi[k];
+    if (inside) return fail(APC_E_ARG, "camera inside the mesh's bounding box");
+  } else {
+    for (int c = 0; c < 8; ++c) {  // dir is normalised here
+      double d = 0.0;
+      for (int k = 0; k < 3; ++k) d += (((c >> k) & 1 ? m->hi[k] : m->lo[k]) - v->eye[k]) * dir[k];
+      if (!(d > 0.0)) return fail(APC_E_ARG, "the mesh's bounding box is not in front of the image plane");
+    }
+  }
   // one depth range for every subdomain and both passes
   double tn = v->t_near, tfar = v->t_far;
   if (tn <= 0.0 && tfar <= 0.0) {

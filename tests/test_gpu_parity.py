@@ -205,6 +205,44 @@ def test_single_fragment_without_bias_is_exact(apc, ctx):
     assert np.abs(got - ref["exact"]).max() <= 1e-6
 
 
+@pytest.mark.parametrize("W,H,proj", [(1, 1, 0), (1, 97, 0), (97, 1, 0), (13, 7, 0), (45, 31, 1), (1, 1, 1)])
+def test_ragged_and_one_pixel_images_match_oracle(apc, ctx, W, H, proj):
+    """Images of one pixel, one row, one column and sizes that fill no tile: every pixel against the oracle
+    (tiny mesh, m = 4), so tiles that hang over the image edge write nothing outside it."""
+    sc = synth.scene_tiny()
+    if proj == 0:
+        sc.view = synth.ortho_view_z(W, H)
+    else:
+        sc.view = synth.perspective_view(synth.sphere_eye(5), (0.5, 0.5, 0.5), W, H)
+    ref = oracle.render(sc)
+    r, rgba = _render(apc, ctx, sc)
+    assert tuple(rgba.shape) == (H, W, 4)
+    # at 45 x 31 about a seventh of the covered pixels lie on the cube's silhouette, where rays graze its flat
+    # boundary faces: 11 of 880 need the backward bar (every one inside the band)
+    _check_moments(sc, np.arange(W * H), _flat_moments(r.moments), ref, max_backward=0.03)
+    d = _np(rgba).reshape(-1, 4) - ref["rgba"]
+    assert np.abs(d).max() <= 2e-3 and math.sqrt(np.mean(d ** 2)) <= 5e-4
+
+
+def test_views_whose_rays_start_inside_the_mesh_are_rejected(apc, ctx):
+    """The walk enters subdomains through their boundary faces, so a ray may not start inside the mesh: a
+    perspective eye inside the mesh's bounding box, or an orthographic image plane cutting it, is an argument
+    error even with a caller-given depth range; nothing is rendered."""
+    sc = synth.scene_tiny()
+    r = apc.Renderer(ctx, sc)
+    inside = synth.perspective_view((0.5, 0.4, 0.5), (0.5, 1.0, 0.5), 128, 128)
+    r.view = apc.make_view(inside, sc.step, t_near=0.05, t_far=2.0)
+    with pytest.raises(apc.ApcError):
+        r.frame()
+    cut = dict(synth.ortho_view_z(128, 128), eye=(0.0, 0.0, 0.5))
+    r.view = apc.make_view(cut, sc.step, t_near=0.05, t_far=2.0)
+    with pytest.raises(apc.ApcError):
+        r.frame()
+    r.view = apc.make_view(sc.view, sc.step)  # the same renderer still works with a valid view
+    r.frame()
+    torch.cuda.synchronize()
+
+
 @pytest.mark.parametrize("m", [4, 6, 8])
 def test_tiny_all_moment_orders(apc, ctx, m):
     sc = synth.scene_tiny()
