@@ -58,11 +58,16 @@ class OOut(C.Structure):
 
 
 def lib():
+    """The compiled oracle.  APC_ORACLE_LIB names another build of it instead: the planted-mistake test runs
+    the oracle's pins against copies of oracle.cpp with one mistake each, which the pins must catch."""
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build(force=True)
-        L = C.CDLL(_LIB)
+        path = os.environ.get("APC_ORACLE_LIB")
+        if not path:
+            path = _LIB
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)
+        L = C.CDLL(path)
         d = C.c_double
         L.oracle_warp.restype = d
         L.oracle_warp.argtypes = [d, d, d]

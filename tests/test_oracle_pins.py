@@ -244,6 +244,36 @@ def _single_tet_scene(o, d, step=100.0, m=4, scalar=(0.125, 0.375, 0.625, 0.875)
                        renormalize=renorm)
 
 
+def test_piece_absorbance_is_capped():
+    """Alg. 2 caps the absorbance of a piece: one piece (the step is longer than the chord) on the ray along z
+    through (0.2, 0.25) of the unit tet, chord length 1 - 0.2 - 0.25 = 0.55, constant table alpha A: b0 =
+    min(kappa A 0.55, cap), below and above the cap."""
+    o = np.array([0.2, 0.25, -1.0])
+    d = np.array([0.0, 0.0, 1.0])
+    A = float(np.float32(0.37))
+    for kappa, cap in ((4.0, 10.0), (4.0, 0.5), (40.0, 3.0), (40.0, 100.0)):
+        sc = _single_tet_scene(o, d, step=100.0, m=4, scalar=(0.5, 0.5, 0.5, 0.5))
+        sc.tf = sc.tf.copy()
+        sc.tf[:, 3] = 0.37
+        sc.kappa, sc.absorbance_max = kappa, cap
+        b0 = oracle.render(sc, pass2=False)["moments"][0, 0]
+        want = min(kappa * A * 0.55, cap)
+        assert abs(b0 - want) <= 1e-12 * max(1.0, want), (kappa, cap, b0, want)
+
+
+@pytest.mark.parametrize("m", [4, 6, 8])
+def test_bound_of_a_single_depth_is_a_step(m):
+    """All absorbance at one depth z1 (b_j = b0 z1^j) and no bias: the bound is exact, a step from 0 in
+    front of z1 to 1 behind it, with the overestimation weight eta at z1 itself."""
+    bias = synth.default_bias(m)
+    eta = 0.3
+    for z1 in (-0.6, 0.1, 0.75):
+        b = 1.7 * z1 ** np.arange(m + 1)
+        for zf, want in ((z1 - 0.3, 0.0), (z1 - 1e-3, 0.0), (z1, eta), (z1 + 1e-3, 1.0), (z1 + 0.2, 1.0)):
+            F = oracle.bound(b, 0.0, bias, eta, zf)[0]
+            assert F == want, (m, z1, zf, F)
+
+
 def test_single_piece_moments_closed_form():
     o = np.array([0.2, 0.25, -1.0])
     d = np.array([0.0, 0.0, 1.0])
