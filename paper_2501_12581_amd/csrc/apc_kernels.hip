@@ -813,7 +813,9 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int N, class R>
+// CHUNKED: the pieces come from the store stage one kept (else from the staging buffer a re-walk filled);
+// fixed per launch, so the choice is a template parameter and the sample loop carries no branch on it
+template <int N, class R, bool CHUNKED>
 __global__ __launch_bounds__(WAVE * EVAL_WPB) __attribute__((amdgpu_waves_per_eu(N >= 4 ? APC_EVAL_WAVES_N4 : APC_EVAL_WAVES, 8))) void k_eval(
     FrameDev f, int tile_lo, int tile_hi, const long long* __restrict__ poff,
                                                long long base, long long rec_cap, const float* __restrict__ rec,
@@ -852,7 +854,7 @@ __global__ __launch_bounds__(WAVE * EVAL_WPB) __attribute__((amdgpu_waves_per_eu
   const bool valid = px < f.W && py < f.H;
   const size_t HW = size_t(f.W) * f.H, pix = size_t(py) * f.W + px;
   const size_t slot0 = size_t(tile) * WAVE;
-  const bool chunked = ps.pool != nullptr;  // pieces kept by stage one
+  constexpr bool chunked = CHUNKED;  // pieces kept by stage one
   long long tile_base = 0;
   bool staged = true;
   if (chunked) {  // per-pixel offsets within the tile: scan of the piece counts
@@ -940,26 +942,26 @@ __global__ __launch_bounds__(WAVE * EVAL_WPB) __attribute__((amdgpu_waves_per_eu
     // the pixel's first 64 chunk ids, one per lane, fetched before the loop
     const int n_ch = (hi - lo + PIECE_CHUNK - 1) / PIECE_CHUNK;
     const int my_ch = (chunked && lane < n_ch && lane < ps.maxc) ? chunks[lane] : 0;
-    // the piece of step ib for this lane (z, a, s), or ok = false past the pixel's end; every lane takes
-    // part in the shuffle
+    // the piece of step ib for this lane (z, a, s), or ok = false past the pixel's end.  Steps start at
+    // lo + 64 k and a chunk holds 64 pieces, so a step's pieces are exactly chunk k of the pixel: its id is
+    // the same for the whole wavefront (a scalar), and lane l reads the chunk's l-th record
+    static_assert(PIECE_CHUNK == WAVE, "one evaluation step reads one chunk");
     auto fetch = [&](int ib, float& z, float& a, float& s, bool& ok) {
-      const int i = ib + lane;
-      const int k = (ib - lo) / PIECE_CHUNK;
-      const int ch_k = chunked ? (k < WAVE ? __shfl(my_ch, k, WAVE) : chunks[k]) : 0;
-      ok = i < hi;
-      if (!ok) return;
+      ok = ib + lane < hi;
       const float* pr;
       if (chunked) {
-        const unsigned ch = unsigned(ch_k);
-        if (ch >= unsigned(ps.n_chunks)) {  // cannot happen when every lane kept its pieces; never read
-          cnt.overflow += 1u;
+        const int k = (ib - lo) / PIECE_CHUNK;  // uniform
+        const int ch = k < WAVE ? __builtin_amdgcn_readlane(my_ch, k) : __builtin_amdgcn_readfirstlane(chunks[k]);
+        if (unsigned(ch) >= unsigned(ps.n_chunks)) {  // cannot happen when every lane kept its pieces; never read
+          cnt.overflow += ok ? 1u : 0u;
           ok = false;
           return;
         }
-        pr = ps.pool + (size_t(ch) * PIECE_CHUNK + (i - lo) % PIECE_CHUNK) * 3;
+        pr = ps.pool + (size_t(ch) * PIECE_CHUNK + lane) * 3;
       } else {
-        pr = trec + 3 * size_t(i);
+        pr = trec + 3 * size_t(ib + lane);
       }
+      if (!ok) return;
       z = pr[0];
       a = pr[1];
       s = pr[2];
@@ -1375,15 +1377,22 @@ hipError_t launch_eval(int mm, const FrameDev& f, int tile_lo, int tile_hi, cons
   if (tile_hi <= tile_lo) return hipSuccess;
   const size_t lds = size_t(f.n_tf) * sizeof(float4);
   const dim3 grid((tile_hi - tile_lo + EVAL_WPB - 1) / EVAL_WPB), block(WAVE * EVAL_WPB);
+#define APC_LAUNCH_EVAL(N, R)                                                                                  \
+  do {                                                                                                         \
+    if (store.pool)                                                                                            \
+      hipLaunchKernelGGL((k_eval<N, R, true>), grid, block, lds, s, f, tile_lo, tile_hi, poff, base, rec_cap,  \
+                         rec, store, pcount, tf_rgba, moments, bp, rgba, counters);                            \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_eval<N, R, false>), grid, block, lds, s, f, tile_lo, tile_hi, poff, base, rec_cap, \
+                         rec, store, pcount, tf_rgba, moments, bp, rgba, counters);                            \
+  } while (0)
   if (mm == 4)
-    hipLaunchKernelGGL((k_eval<2, float>), grid, block, lds, s, f, tile_lo, tile_hi, poff, base, rec_cap, rec,
-                       store, pcount, tf_rgba, moments, bp, rgba, counters);
+    APC_LAUNCH_EVAL(2, float);
   else if (mm == 6)
-    hipLaunchKernelGGL((k_eval<3, double>), grid, block, lds, s, f, tile_lo, tile_hi, poff, base, rec_cap, rec,
-                       store, pcount, tf_rgba, moments, bp, rgba, counters);
+    APC_LAUNCH_EVAL(3, double);
   else
-    hipLaunchKernelGGL((k_eval<4, double>), grid, block, lds, s, f, tile_lo, tile_hi, poff, base, rec_cap, rec,
-                       store, pcount, tf_rgba, moments, bp, rgba, counters);
+    APC_LAUNCH_EVAL(4, double);
+#undef APC_LAUNCH_EVAL
   return hipGetLastError();
 }
 
