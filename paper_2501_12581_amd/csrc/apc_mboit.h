@@ -30,7 +30,7 @@
 //
 // Roots: closed forms (quadratic; trigonometric cubic; Ferrari quartic whose
 // resolvent's largest root comes from the trigonometric cubic), each root
-// polished by one Newton step on the kernel polynomial.  A vanishing leading
+// polished by Newton steps on the kernel polynomial.  A vanishing leading
 // coefficient means one node has gone to infinity with zero weight; the
 // degree is lowered instead of dividing by it.  Reciprocals use the hardware
 // estimate (plus two Newton-Raphson steps in FP64) on the device.
@@ -280,28 +280,30 @@ template <int N, class R>
 struct PolyCoef {
   R c[N + 1];
 };
-template <int N, class R>
+template <int N, class R, int POLISH>
 APC_HD int poly_roots_body(const R* q, R* x);
-template <int N, class R>
+template <int N, class R, int POLISH>
 APC_HD_COLD RootSet<N, R> poly_roots_v(PolyCoef<N, R> q) {
   RootSet<N, R> r;
 #pragma unroll
   for (int i = 0; i < N; ++i) r.x[i] = R(0);
-  r.n = poly_roots_body<N, R>(q.c, r.x);
+  r.n = poly_roots_body<N, R, POLISH>(q.c, r.x);
   return r;
 }
-// Roots of the polynomial q[0..N]; returns how many finite ones (x[0..nr)).
-template <int N, class R>
+// Roots of the polynomial q[0..N]; returns how many finite ones (x[0..nr)).  POLISH Newton steps on the
+// full polynomial follow the closed forms: three give working precision even when the leading coefficient
+// nearly vanishes; one suffices where the roots only start further Newton iterations.
+template <int N, class R, int POLISH = 3>
 APC_HD int poly_roots(const R* q, R* x) {
   PolyCoef<N, R> c;
 #pragma unroll
   for (int j = 0; j <= N; ++j) c.c[j] = q[j];
-  const RootSet<N, R> r = poly_roots_v<N, R>(c);
+  const RootSet<N, R> r = poly_roots_v<N, R, POLISH>(c);
 #pragma unroll
   for (int i = 0; i < N; ++i) x[i] = r.x[i];
   return r.n;
 }
-template <int N, class R>
+template <int N, class R, int POLISH>
 APC_HD int poly_roots_body(const R* q, R* x) {
   R cmax = R(0);
 #pragma unroll
@@ -327,20 +329,27 @@ APC_HD int poly_roots_body(const R* q, R* x) {
   } else if (N >= 4 && deg == 4) {
     nr = roots4(q, x);
   }
+  // Newton steps on the full polynomial (fixed trip counts: no indexed arrays).  A vanishing leading
+  // coefficient (one root far out) makes the monic closed forms lose digits of the other roots: one step
+  // left F off by up to 1.5e-7 on rendered pixels at m = 8, three keep it within 1e-12.
 #pragma unroll
-  for (int i = 0; i < N; ++i) {  // one Newton step on the full polynomial (fixed trip count: no indexed arrays)
+  for (int i = 0; i < N; ++i) {
     if (i >= nr) continue;
     R xi = x[i];
-    R p = q[N], dp = R(0);
 #pragma unroll
-    for (int j = N - 1; j >= 0; --j) {
-      dp = dp * xi + p;
-      p = p * xi + q[j];
+    for (int it = 0; it < POLISH; ++it) {
+      R p = q[N], dp = R(0);
+#pragma unroll
+      for (int j = N - 1; j >= 0; --j) {
+        dp = dp * xi + p;
+        p = p * xi + q[j];
+      }
+      if (dp != R(0)) {
+        R xn = xi - p * m_rcp(dp);
+        if (m_finite(xn)) xi = xn;
+      }
     }
-    if (dp != R(0)) {
-      R xn = xi - p * m_rcp(dp);
-      if (m_finite(xn)) x[i] = xn;
-    }
+    x[i] = xi;
   }
   return nr;
 }
@@ -617,7 +626,7 @@ struct Bound {
     coeffs(P, q);
 #pragma unroll
     for (int t = 0; t < N; ++t) x[t] = R(0);
-    const int nr = poly_roots<N, R>(q, x);
+    const int nr = poly_roots<N, R, 1>(q, x);  // table entries only start Newton iterations
     sort_up(x);
     bool ok = nr == N && pick_reg<N>(x, k - 1) < z && pick_reg<N>(x, k) > z;
 #pragma unroll
