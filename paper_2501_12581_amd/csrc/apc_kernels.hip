@@ -468,7 +468,7 @@ struct LaneStore {
   PieceStore ps;
   size_t slot;     // tile * 64 + lane
   unsigned kept;
-  int chunk;
+  float* cur;      // where the next piece goes in the current chunk
   bool keep;
   // LDS: first chunk of the wavefront's block and the chunks of it handed
   // out.  Written by one lane and read by others in later divergent regions,
@@ -505,18 +505,18 @@ struct LaneStore {
       }
       const unsigned k = kept / PIECE_CHUNK;
       if (id < static_cast<unsigned long long>(ps.n_chunks) && k < unsigned(ps.maxc)) {
-        chunk = int(id);
-        ps.ptab[slot * ps.maxc + k] = chunk;
+        ps.ptab[slot * ps.maxc + k] = int(id);
+        cur = ps.pool + size_t(id) * (PIECE_CHUNK * 3);
       } else {
         keep = false;
         atomicAdd(ps.next + 1, 1ull);
         return;
       }
     }
-    float* o = ps.pool + (size_t(chunk) * PIECE_CHUNK + (kept & (PIECE_CHUNK - 1))) * 3;
-    o[0] = z;
-    o[1] = a;
-    o[2] = s;
+    cur[0] = z;
+    cur[1] = a;
+    cur[2] = s;
+    cur += 3;
     ++kept;
   }
 };
@@ -590,7 +590,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_WALK_W
     blk_base = 0;
     blk_used = STORE_BLOCK;  // no block yet
   }
-  sink.st = LaneStore{ps, size_t(tile) * WAVE + lane, 0u, -1, ps.pool != nullptr && valid, (lds_vu64*)&blk_base,
+  sink.st = LaneStore{ps, size_t(tile) * WAVE + lane, 0u, nullptr, ps.pool != nullptr && valid, (lds_vu64*)&blk_base,
                       (lds_vi32*)&blk_used};
   sink.lane = lane;
   __syncthreads();
