@@ -291,9 +291,10 @@ APC_HD_COLD RootSet<N, R> poly_roots_v(PolyCoef<N, R> q) {
   return r;
 }
 // Roots of the polynomial q[0..N]; returns how many finite ones (x[0..nr)).  POLISH Newton steps on the
-// full polynomial follow the closed forms: three give working precision even when the leading coefficient
-// nearly vanishes; one suffices where the roots only start further Newton iterations.
-template <int N, class R, int POLISH = 3>
+// full polynomial follow the closed forms: for cubics and quartics, made monic first, three give working
+// precision even when the leading coefficient nearly vanishes (one suffices where the roots only start
+// further Newton iterations); the quadratic formula here divides by no small coefficient, so one step.
+template <int N, class R, int POLISH = (N >= 3 ? 3 : 1)>
 APC_HD int poly_roots(const R* q, R* x) {
   PolyCoef<N, R> c;
 #pragma unroll
