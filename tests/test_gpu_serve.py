@@ -69,3 +69,28 @@ def test_served_frames_keep_their_pieces(server):
         assert t["stage_ms"] == 0.0, t
         assert torch.equal(first, again)
     assert c["pieces"] > 0
+
+
+def test_small_slots_take_small_requests_with_the_same_results():
+    """Slots of two sizes: 2 that take any request and 2 that take requests up to 128^2 (with a smaller
+    workspace).  Every request runs on a slot that holds it, the small slots are used, and each image is
+    bitwise the one-at-a-time image."""
+    from paper_2501_12581_amd.serve import Server
+    sc = synth.scene_medium(size=128)
+    m = sc.mesh
+    tfs = [synth.make_tf(s) for s in (13, 14)]
+    srv = Server((m.xyz, m.scalar, m.tets, m.tet_sub, m.n_sub), sc.step, tfs, (sc.s_min, sc.s_max), slots=2,
+                 workspace_limit=1 << 30, hbm_budget=1 << 30, max_size=192, small_slots=2, small_size=128,
+                 small_workspace_limit=512 << 20)
+    try:
+        srv.warm()
+        reqs = synth.request_stream(16, rate=400.0, seed=5, sizes=(96, 128, 192), ms=(4, 8), n_tf=2)
+        mix = srv.run(reqs, "batched", keep_images=True)
+        alone = srv.run(reqs, "fifo", keep_images=True)
+        for a, b in zip(mix["records"], alone["records"]):
+            assert a["id"] == b["id"]
+            assert srv.slot_size[a["slot"]] >= a["size"]
+            assert torch.equal(a["rgba"], b["rgba"]), a["id"]
+        assert any(r["slot"] >= 2 for r in mix["records"])  # the small slots served requests
+    finally:
+        srv.close()
