@@ -208,19 +208,20 @@ apc_status apc_sum_moments(apc_ctx ctx, const float* moments_per_sub, int32_t n_
 #define APC_REWALK 4u
 #define APC_MOMENTS_GLOBAL 8u
 
-/* Pack a global moment image for FP16 storage, m + 2 planes each rounded to
- * the nearest FP16 value: plane 0 holds ln(b0) (-inf where b0 <= 0); planes
- * 1 and 2 the mean warped depth mu = b1 / b0 as two halves (hi, then the rest
- * lo; mu = hi + lo); planes 3..m+1 the central moments E[(z - mu)^k] for
- * k = 2..m of the pixel's normalised depth distribution (0 where b0 <= 0).
- * Central moments keep a concentrated distribution's spread at FP16's
- * relative precision, which raw moments b_j / b0 (all near mu^j) lose.
- * 2(m + 2) bytes per pixel instead of 4(m + 1); apc_resolve_pass reads it
- * with APC_MOMENTS_F16.  The rounding perturbs the moments by up to about
- * 2^-11 relative, far beyond the FP32 bar: the resulting image error is a
- * property of the variant, not a parity result.
+/* Pack a global moment image for FP16 storage, m + 3 planes each rounded to
+ * the nearest FP16 value: planes 0 and 1 hold ln(b0) as two halves (hi, then
+ * the rest lo; plane 0 is -inf and the others 0 where b0 <= 0); planes 2 and
+ * 3 the mean warped depth mu = b1 / b0 as two halves (mu = hi + lo); planes
+ * 4..m+2 the central moments E[(z - mu)^k] for k = 2..m of the pixel's
+ * normalised depth distribution.  Central moments keep a concentrated
+ * distribution's spread at FP16's relative precision, which raw moments
+ * b_j / b0 (all near mu^j) lose; the split ln b0 keeps the opacity near FP32
+ * precision.  2(m + 3) bytes per pixel instead of 4(m + 1); apc_resolve_pass
+ * reads it with APC_MOMENTS_F16.  The rounding perturbs the moments by up to
+ * about 2^-11 relative, far beyond the FP32 bar: the resulting image error is
+ * a property of the variant, not a parity result.
  *   moments_global  device [m+1][H][W] FP32 (from apc_sum_moments)
- *   packed          device [m+2][H][W] FP16 (2-byte aligned), written */
+ *   packed          device [m+3][H][W] FP16 (2-byte aligned), written */
 apc_status apc_pack_moments_f16(apc_ctx ctx, const float* moments_global, int32_t m, int32_t height, int32_t width,
                                 void* packed, void* stream);
 
@@ -233,7 +234,7 @@ apc_status apc_pack_moments_f16(apc_ctx ctx, const float* moments_global, int32_
  * bound at the piece's warped depth computed from `moments_global`.
  *   moments_global  device [m+1][H][W] FP32 (from apc_sum_moments), or with
  *                   APC_MOMENTS_F16 the FP16 image of apc_pack_moments_f16
- *                   ([m+2][H][W])
+ *                   ([m+3][H][W])
  *   rgba_out        device [H][W][4] FP32.  Without APC_FINALIZE: the additive
  *                   partial image (sum T*a*rgb, sum T*a) of the listed
  *                   subdomains, summed in the listed order.  With

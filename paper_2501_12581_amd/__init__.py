@@ -289,7 +289,7 @@ class Context:
         flags = (APC_FINALIZE if finalize else 0) | (APC_MOMENTS_F16 if f16 else 0)
         self._ck(lib().apc_resolve_pass(self.handle, mesh.handle, C.byref(view), C.byref(tf), C.byref(mboit),
                                         _dev_ptr(moments, torch.float16 if f16 else torch.float32,
-                                                 (mboit.m + (2 if f16 else 1), view.height, view.width),
+                                                 (mboit.m + (3 if f16 else 1), view.height, view.width),
                                                  "moments"), ptr, len(ids),
                                         _dev_ptr(out, torch.float32, (view.height, view.width, 4), "rgba"),
                                         flags, _stream(stream)))
@@ -331,12 +331,12 @@ class Context:
         return out
 
     def pack_moments_f16(self, moments, m, out, stream=None):
-        """FP16 form of a global moment image ([m+2][H][W]): ln b0, the mean depth as two halves, the central
-        moments of orders 2..m (include/apc.h)."""
+        """FP16 form of a global moment image ([m+3][H][W]): ln b0 and the mean depth, each as two halves, and
+        the central moments of orders 2..m (include/apc.h)."""
         import torch
         m1, H, W = moments.shape
         self._ck(lib().apc_pack_moments_f16(self.handle, _dev_ptr(moments, torch.float32, (m1, H, W), "moments"),
-                                            int(m), H, W, _dev_ptr(out, torch.float16, (m1 + 1, H, W), "packed"),
+                                            int(m), H, W, _dev_ptr(out, torch.float16, (m1 + 2, H, W), "packed"),
                                             _stream(stream)))
 
     def sum_images(self, partials, subdomains, moments, mboit: Mboit, out, stream=None):
@@ -438,7 +438,7 @@ class Renderer:
             import torch
             if getattr(self, "moments_h", None) is None:
                 m1, H, W = self.moments.shape
-                self.moments_h = torch.empty((m1 + 1, H, W), dtype=torch.float16, device=self.moments.device)
+                self.moments_h = torch.empty((m1 + 2, H, W), dtype=torch.float16, device=self.moments.device)
             self.ctx.pack_moments_f16(self.moments, self.scene.m, self.moments_h, stream)
             mom = self.moments_h
         self.ctx.resolve_pass(self.mesh, self.view, self.tf, self.mboit, mom, subs, self.rgba,

@@ -883,16 +883,16 @@ __global__ __launch_bounds__(WAVE * EVAL_WPB) __attribute__((amdgpu_waves_per_eu
     LdsBound<N, R> bound;
     bound.Li.base = li_lds + lane;
     R b[M1], bias[2 * N], zs[N];
-    if (bp.moments_f16) {  // ln b0, the mean as two halves and the central moments, in FP16
+    if (bp.moments_f16) {  // ln b0 and the mean, each as two halves, and the central moments, in FP16
       const _Float16* hm = static_cast<const _Float16*>(moments);
-      const float lb0 = valid ? float(hm[pix]) : -HUGE_VALF;
-      b0f = expf(lb0);  // exp(-inf) = 0: background
+      const double lb0 = valid ? double(hm[pix]) + double(hm[HW + pix]) : -HUGE_VAL;
+      b0f = float(exp(lb0));  // exp(-inf) = 0: background
       double c[M1];
       c[0] = 1.0;
       c[1] = 0.0;
 #pragma unroll
-      for (int k = 2; k < M1; ++k) c[k] = valid ? double(hm[size_t(k + 1) * HW + pix]) : 0.0;
-      const double mu = valid ? double(hm[HW + pix]) + double(hm[2 * HW + pix]) : 0.0;
+      for (int k = 2; k < M1; ++k) c[k] = valid ? double(hm[size_t(k + 2) * HW + pix]) : 0.0;
+      const double mu = valid ? double(hm[2 * HW + pix]) + double(hm[3 * HW + pix]) : 0.0;
       b[0] = R(b0f);
 #pragma unroll
       for (int j = 1; j < M1; ++j) {  // beta_j = E[z^j] = sum_k C(j, k) mu^(j-k) E[(z - mu)^k]
@@ -1209,15 +1209,19 @@ __global__ void k_sum_moments(const float* __restrict__ in, int n_slots, const i
 }
 
 // FP16 form of a global moment image: ln b0 (-inf on background) and b_j / b0
-// FP16 moment image, planes [m+2][pixels]: ln b0; the mean depth mu = beta_1 as two FP16 halves (hi, and the
-// rest lo); the central moments E[(z - mu)^k] (mu = hi + lo), k = 2..m.  Central moments keep the spread of a
-// concentrated depth distribution at FP16's relative precision, which raw moments (all near mu^j) lose.
+// FP16 moment image, planes [m+3][pixels]: ln b0 and the mean depth mu = beta_1, each as two FP16 halves (hi,
+// and the rest lo); the central moments E[(z - mu)^k] (mu = hi + lo), k = 2..m.  Central moments keep the
+// spread of a concentrated depth distribution at FP16's relative precision, which raw moments (all near mu^j)
+// lose; the split ln b0 keeps the opacity 1 - exp(-b0) near FP32 precision.
 __global__ void k_pack_f16(const float* __restrict__ in, int m1, int64_t pixels, _Float16* __restrict__ out) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= pixels) return;
   const float b0 = in[i];
   const bool bg = !(b0 > 0.0f);
-  out[i] = bg ? _Float16(-HUGE_VALF) : _Float16(logf(b0));
+  const double lb0 = bg ? 0.0 : log(double(b0));
+  const _Float16 lhi = _Float16(lb0);
+  out[i] = bg ? _Float16(-HUGE_VALF) : lhi;
+  out[pixels + i] = bg ? _Float16(0.0f) : _Float16(lb0 - double(lhi));
   const double inv = bg ? 0.0 : 1.0 / double(b0);
   double beta[9];
   beta[0] = 1.0;
@@ -1225,8 +1229,8 @@ __global__ void k_pack_f16(const float* __restrict__ in, int m1, int64_t pixels,
   const _Float16 hi = _Float16(beta[1]);
   const _Float16 lo = _Float16(beta[1] - double(hi));
   const double mu = double(hi) + double(lo);
-  out[pixels + i] = bg ? _Float16(0.0f) : hi;
-  out[2 * pixels + i] = bg ? _Float16(0.0f) : lo;
+  out[2 * pixels + i] = bg ? _Float16(0.0f) : hi;
+  out[3 * pixels + i] = bg ? _Float16(0.0f) : lo;
   for (int k = 2; k < m1; ++k) {
     // E[(z - mu)^k] = sum_i C(k, i) (-mu)^(k-i) beta_i, Horner in (-mu) with running binomials
     double c = 0.0, binom = 1.0, pw = 1.0;
@@ -1235,7 +1239,7 @@ __global__ void k_pack_f16(const float* __restrict__ in, int m1, int64_t pixels,
       pw *= -mu;
       binom = binom * double(t) / double(k - t + 1);
     }
-    out[int64_t(k + 1) * pixels + i] = bg ? _Float16(0.0f) : _Float16(c);
+    out[int64_t(k + 2) * pixels + i] = bg ? _Float16(0.0f) : _Float16(c);
   }
 }
 

@@ -297,8 +297,8 @@ def test_medium_m8_gap_tables(apc, ctx):
 
 @pytest.mark.parametrize("m", [4, 6, 8])
 def test_fp16_moment_storage_variant(apc, ctx, m):
-    """FP16 moment image (ln b0; the mean depth as two FP16 halves; the central moments of orders 2..m):
-    2(m + 2) bytes per pixel against 4(m + 1).  The planes decode to the FP32 moments within FP16 rounding,
+    """FP16 moment image (ln b0 and the mean depth, each as two FP16 halves; the central moments of orders
+    2..m): 2(m + 3) bytes per pixel against 4(m + 1).  The planes decode to the FP32 moments within FP16 rounding,
     background stays exactly empty, and the image error against the oracle is reported beside the FP32
     path's (a property of the variant, bounded loosely here)."""
     from math import comb
@@ -309,19 +309,19 @@ def test_fp16_moment_storage_variant(apc, ctx, m):
     rgba32 = _np(r.frame()).reshape(-1, 4)
     rgba16 = _np(r.frame(moments_f16=True)).reshape(-1, 4)
     torch.cuda.synchronize()
-    assert tuple(r.moments_h.shape) == (m + 2,) + tuple(r.moments.shape[1:])  # m + 2 FP16 planes
+    assert tuple(r.moments_h.shape) == (m + 3,) + tuple(r.moments.shape[1:])  # m + 3 FP16 planes
     mom = _flat_moments(r.moments)
-    h = r.moments_h.float().cpu().numpy().astype(np.float64).reshape(m + 2, -1)
+    h = r.moments_h.float().cpu().numpy().astype(np.float64).reshape(m + 3, -1)
     cov = mom[0] > 0
     assert np.all(np.isneginf(h[0, ~cov])) and np.all(h[1:, ~cov] == 0.0) and np.all(rgba16[~cov] == 0.0)
-    b0 = np.exp(h[0, cov])
-    assert np.all(np.abs(b0 / mom[0, cov] - 1) <= 2.0 ** -11 * np.maximum(1.0, np.abs(np.log(mom[0, cov]))) + 1e-6)
+    lb0 = h[0, cov] + h[1, cov]
+    assert np.all(np.abs(lb0 - np.log(mom[0, cov])) <= 2.0 ** -22 * np.abs(np.log(mom[0, cov])) + 2.0 ** -25)
     beta = mom[:, cov] / mom[0, cov]
-    mu = h[1, cov] + h[2, cov]
+    mu = h[2, cov] + h[3, cov]
     assert np.all(np.abs(mu - beta[1]) <= 2.0 ** -22 * np.abs(beta[1]) + 2.0 ** -25)
     for k in range(2, m + 1):  # central moments about the stored mean, in FP64
         c = sum(comb(k, i) * beta[i] * (-mu) ** (k - i) for i in range(k + 1))
-        assert np.all(np.abs(h[k + 1, cov] - c) <= 2.0 ** -11 * np.abs(c) + 2.0 ** -25 + 1e-12), k
+        assert np.all(np.abs(h[k + 2, cov] - c) <= 2.0 ** -11 * np.abs(c) + 2.0 ** -25 + 1e-12), k
     ref = oracle.render(sc)
     e32 = rgba32 - ref["rgba"]
     e16 = rgba16 - ref["rgba"]
