@@ -62,7 +62,15 @@ typedef struct apc_mesh_s* apc_mesh; /* device-resident mesh of all subdomains, 
 
 /* Create a context on HIP device `device`.  The context owns growable device
  * workspace; calls on one context must not overlap in time (one host thread
- * at a time, one stream at a time). */
+ * at a time, one stream at a time).
+ * device = APC_DEVICE_NONE creates a host-only context, which makes no HIP
+ * call at all: every call validates its arguments exactly as on a device and
+ * then returns APC_E_DEVICE ("nothing was launched") instead of doing device
+ * work, so requests can be checked where no GPU is present.  apc_load_mesh
+ * on such a context validates and groups the mesh on the host (face
+ * adjacency included) and returns a mesh that holds no device memory; it can
+ * only be passed to host-only calls. */
+#define APC_DEVICE_NONE (-1)
 apc_status apc_create(int device, apc_ctx* out);
 apc_status apc_destroy(apc_ctx ctx);
 
@@ -82,13 +90,14 @@ typedef struct apc_mesh_desc {
   int64_t n_vertices;           /* V >= 4 */
   int64_t n_tets;               /* 1 <= T < 2^29 */
   int32_t n_subdomains;         /* S >= 1 */
-  int32_t flags;                /* reserved, must be 0 (all pointers are host memory) */
-  const float* xyz;             /* host [V][3] vertex positions */
-  const float* scalar;          /* host [V] vertex scalars, linearly interpolated inside each tet */
-  const int32_t* tet_vertices;  /* host [T][4] vertex ids; every tet must have positive signed volume
+  int32_t flags;                /* 0: the four arrays are host memory; APC_MESH_DEVICE: device memory */
+  const float* xyz;             /* [V][3] vertex positions */
+  const float* scalar;          /* [V] vertex scalars, linearly interpolated inside each tet */
+  const int32_t* tet_vertices;  /* [T][4] vertex ids; every tet must have positive signed volume
                                    det(v1-v0, v2-v0, v3-v0) > 0 */
-  const int32_t* tet_subdomain; /* host [T] subdomain id in [0, S) */
+  const int32_t* tet_subdomain; /* [T] subdomain id in [0, S) */
 } apc_mesh_desc;
+#define APC_MESH_DEVICE 1 /* apc_mesh_desc.flags: the arrays are device memory (copied to the host to validate) */
 
 /* Copy a mesh to the device and build its residency structures: face
  * adjacency (each face is shared by at most two tets), tets grouped by
@@ -96,10 +105,13 @@ typedef struct apc_mesh_desc {
  * spatially coherent order such as Morton order), and per subdomain the list
  * of boundary faces -- faces on the mesh hull or shared with another
  * subdomain -- through which rays enter it.
- * Errors: APC_E_ARG (null pointers, sizes), APC_E_MESH (vertex id out of
- * range, repeated vertex in a tet, non-positive volume, subdomain id out of
- * range, a face shared by more than two tets), APC_E_NOMEM, APC_E_DEVICE.
- * Synchronous: the caller may free its arrays when the call returns. */
+ * Errors: APC_E_ARG (null pointers, sizes, unknown flags), APC_E_MESH
+ * (vertex id out of range, repeated vertex in a tet, non-positive volume,
+ * subdomain id out of range, non-finite coordinate, a face shared by more
+ * than two tets), APC_E_NOMEM, APC_E_DEVICE.  A failed call creates no mesh.
+ * Synchronous (the validation reads the arrays on the host; device arrays are
+ * first copied there on `stream`): the caller may free its arrays when the
+ * call returns. */
 apc_status apc_load_mesh(apc_ctx ctx, const apc_mesh_desc* desc, apc_mesh* out, void* stream);
 apc_status apc_free_mesh(apc_ctx ctx, apc_mesh mesh);
 

@@ -58,6 +58,9 @@ def moment_parity(sc, pix, got, ref, tol=1e-5, floor=1e-3, per_sub=False, thread
         slack = tol * den[bad]
         ok = (g >= lo - slack) & (g <= hi + slack)
         outside = int(np.count_nonzero(~ok.reshape(-1, len(bad)).all(axis=0)))
+    cov_err = per_pix[~bg] if per_pix.shape[-1] == bg.shape[-1] else per_pix
+    q = np.quantile(cov_err, [0.5, 0.99, 0.999]) if cov_err.size else np.zeros(3)
     return {"covered": int(np.count_nonzero(~bg)), "background_exact": background_exact,
             "forward_max": float(per_pix.max()) if per_pix.size else 0.0,
+            "forward_p50": float(q[0]), "forward_p99": float(q[1]), "forward_p999": float(q[2]),
             "backward_bar_pixels": int(len(bad)), "outside_backward_band": outside}

@@ -22,6 +22,8 @@ APC_FINALIZE = 1
 APC_MOMENTS_F16 = 2
 APC_REWALK = 4
 APC_MOMENTS_GLOBAL = 8
+APC_DEVICE_NONE = -1   # apc_create: a host-only context (validates, launches nothing)
+APC_MESH_DEVICE = 1    # apc_mesh_desc.flags: the mesh arrays are device memory
 STATUS = {0: "APC_OK", 1: "APC_E_ARG", 2: "APC_E_MESH", 3: "APC_E_NOMEM", 4: "APC_E_DEVICE",
           5: "APC_E_NUMERIC", 6: "APC_E_UNSUPPORTED"}
 EXPORTS = ["apc_create", "apc_destroy", "apc_last_error", "apc_version", "apc_load_mesh", "apc_free_mesh",
@@ -247,13 +249,24 @@ class Context:
         _check(st, self.handle)
 
     def load_mesh(self, xyz, scalar, tets, tet_sub, n_sub, stream=None) -> Mesh:
-        xyz = np.ascontiguousarray(xyz, dtype=np.float32)
-        scalar = np.ascontiguousarray(scalar, dtype=np.float32)
-        tets = np.ascontiguousarray(tets, dtype=np.int32)
-        tet_sub = np.ascontiguousarray(tet_sub, dtype=np.int32)
-        d = MeshDesc(n_vertices=xyz.shape[0], n_tets=tets.shape[0], n_subdomains=int(n_sub), flags=0,
-                     xyz=xyz.ctypes.data, scalar=scalar.ctypes.data, tet_vertices=tets.ctypes.data,
-                     tet_subdomain=tet_sub.ctypes.data)
+        """Host arrays (numpy), or device arrays (CUDA torch tensors, APC_MESH_DEVICE)."""
+        dev = all(getattr(a, "is_cuda", False) for a in (xyz, scalar, tets, tet_sub))
+        if dev:
+            import torch
+            xyz_p = _dev_ptr(xyz, torch.float32, name="xyz")
+            sc_p = _dev_ptr(scalar, torch.float32, name="scalar")
+            tv_p = _dev_ptr(tets, torch.int32, name="tets")
+            ts_p = _dev_ptr(tet_sub, torch.int32, name="tet_sub")
+            nv, nt = xyz.shape[0], tets.shape[0]
+        else:
+            xyz = np.ascontiguousarray(xyz, dtype=np.float32)
+            scalar = np.ascontiguousarray(scalar, dtype=np.float32)
+            tets = np.ascontiguousarray(tets, dtype=np.int32)
+            tet_sub = np.ascontiguousarray(tet_sub, dtype=np.int32)
+            xyz_p, sc_p, tv_p, ts_p = (a.ctypes.data for a in (xyz, scalar, tets, tet_sub))
+            nv, nt = xyz.shape[0], tets.shape[0]
+        d = MeshDesc(n_vertices=nv, n_tets=nt, n_subdomains=int(n_sub), flags=APC_MESH_DEVICE if dev else 0,
+                     xyz=xyz_p, scalar=sc_p, tet_vertices=tv_p, tet_subdomain=ts_p)
         h = C.c_void_p()
         self._ck(lib().apc_load_mesh(self.handle, C.byref(d), C.byref(h), _stream(stream)))
         return Mesh(self, h)

@@ -88,6 +88,7 @@ struct DevBuf {
 
 struct apc_ctx_s {
   int device = 0;
+  bool host_only = false;  // APC_DEVICE_NONE: validates arguments, launches nothing
   DevBuf counts, offsets, cursors, records, scan_tmp, slots, order, counters;
   void* staging = nullptr;  // pinned host memory for small uploads
   size_t staging_bytes = 0;
@@ -153,6 +154,7 @@ struct apc_mesh_s {
   std::vector<int> sub_begin, face_begin;  // [S+1] each
   double lo[3], hi[3];
   int64_t device_bytes = 0;
+  bool host_only = false;  // loaded by a host-only context: no device arrays
 };
 
 namespace {
@@ -254,6 +256,12 @@ apc_status make_frame(const apc_mesh_s* m, const apc_view* v, const apc_tf* tf, 
   f.wz = float(v->down[2]);
   f.half_w = 0.5f * float(v->width);
   f.half_h = 0.5f * float(v->height);
+  for (int k = 0; k < 3; ++k) {
+    f.ceye[k] = v->eye[k];
+    f.cdir[k] = dir[k];
+    f.cright[k] = v->right[k];
+    f.cdown[k] = v->down[k];
+  }
   double minv[9];
   if (!inverse3(dir, v->right, v->down, minv)) return fail(APC_E_ARG, "dir, right and down are not independent");
   for (int k = 0; k < 9; ++k) f.minv[k] = float(minv[k]);
@@ -293,10 +301,10 @@ apc_status make_frame(const apc_mesh_s* m, const apc_view* v, const apc_tf* tf, 
   if (!(tn > 0.0) || !(tfar > tn)) return fail(APC_E_ARG, "depth range [%g, %g] invalid (camera inside the mesh?)", tn, tfar);
   if ((tfar - tn) / v->step > double(1 << 22)) return fail(APC_E_ARG, "step too small for the depth range");
   const double tmid = 0.5 * (tn + tfar);
-  f.t_mid = float(tmid);
-  f.t_near = float(tn - double(f.t_mid));
-  f.step = float(v->step);
-  f.inv_step = float(1.0 / v->step);
+  f.t_mid = tmid;
+  f.t_near = tn - tmid;
+  f.step = v->step;
+  f.inv_step = 1.0 / v->step;
   double lg0 = std::log2(tn), lg1 = std::log2(tfar);
   f.lg_near = float(lg0);
   f.warp_scale = float(2.0 / (lg1 - lg0));
@@ -395,8 +403,83 @@ int max_tets_of(const apc_mesh_s* m, const int32_t* subs, int32_t n_sub) {
 
 apc_status check_ctx(apc_ctx ctx) {
   if (!ctx) return fail(APC_E_ARG, "context is NULL");
+  if (ctx->host_only) return APC_OK;
   HIPCHK(hipSetDevice(ctx->device));
   return APC_OK;
+}
+
+// A host-only context stops here, after every argument of the call was validated.
+apc_status no_device(const char* call) {
+  return fail(APC_E_DEVICE, "%s: host-only context (APC_DEVICE_NONE): the arguments are valid, nothing was launched",
+              call);
+}
+
+// A mesh and a context must agree on having a device.
+apc_status check_mesh(apc_ctx ctx, const apc_mesh_s* m) {
+  if (!m) return fail(APC_E_ARG, "mesh is NULL");
+  if (m->host_only != ctx->host_only)
+    return fail(APC_E_ARG, "mesh and context differ in having a device (one is host-only)");
+  return APC_OK;
+}
+
+// Face adjacency on the host (host-only contexts): through vertex -> tet
+// incidence lists, every (tet, face) looks for the other tets holding the
+// face's three vertices among those incident to its lowest vertex.  Returns
+// false when a face is shared by more than two tets.
+bool host_adjacency(const std::vector<int4>& tv, int64_t V, std::vector<int>& nbr) {
+  const int64_t T = int64_t(tv.size());
+  std::vector<int64_t> off(V + 1, 0);
+  for (int64_t t = 0; t < T; ++t) {
+    ++off[tv[t].x + 1];
+    ++off[tv[t].y + 1];
+    ++off[tv[t].z + 1];
+    ++off[tv[t].w + 1];
+  }
+  for (int64_t v = 0; v < V; ++v) off[v + 1] += off[v];
+  std::vector<int> inc(static_cast<size_t>(off[V]));
+  {
+    std::vector<int64_t> cur(off.begin(), off.end() - 1);
+    for (int64_t t = 0; t < T; ++t) {
+      inc[cur[tv[t].x]++] = int(t);
+      inc[cur[tv[t].y]++] = int(t);
+      inc[cur[tv[t].z]++] = int(t);
+      inc[cur[tv[t].w]++] = int(t);
+    }
+  }
+  nbr.assign(size_t(4 * T), -1);
+  std::vector<char> bad(16, 0);
+  parallel_for(4 * T, [&](int64_t lo, int64_t hi, int k) {
+    for (int64_t g = lo; g < hi; ++g) {
+      const int t = int(g >> 2), fc = int(g & 3);
+      const int v[4] = {tv[t].x, tv[t].y, tv[t].z, tv[t].w};
+      int f3[3], q = 0;
+      for (int i = 0; i < 4; ++i)
+        if (i != fc) f3[q++] = v[i];
+      const int a = std::min(f3[0], std::min(f3[1], f3[2]));
+      int found = -1, n_found = 0;
+      for (int64_t p = off[a]; p < off[a + 1]; ++p) {
+        const int t2 = inc[size_t(p)];
+        if (t2 == t) continue;
+        const int w[4] = {tv[t2].x, tv[t2].y, tv[t2].z, tv[t2].w};
+        int hit = 0, miss = -1;
+        for (int i = 0; i < 4; ++i) {
+          if (w[i] == f3[0] || w[i] == f3[1] || w[i] == f3[2])
+            ++hit;
+          else
+            miss = i;
+        }
+        if (hit == 3) {
+          found = (t2 << 2) | miss;
+          ++n_found;
+        }
+      }
+      if (n_found > 1) bad[k] = 1;
+      nbr[size_t(g)] = n_found == 1 ? found : -1;
+    }
+  });
+  for (char b : bad)
+    if (b) return false;
+  return true;
 }
 
 }  // namespace
@@ -410,6 +493,14 @@ const char* apc_last_error(apc_ctx) { return g_error.c_str(); }
 apc_status apc_create(int device, apc_ctx* out) {
   if (!out) return fail(APC_E_ARG, "out is NULL");
   *out = nullptr;
+  if (device == APC_DEVICE_NONE) {  // no HIP call at all
+    apc_ctx c = new (std::nothrow) apc_ctx_s();
+    if (!c) return fail(APC_E_NOMEM, "host allocation failed");
+    c->device = APC_DEVICE_NONE;
+    c->host_only = true;
+    *out = c;
+    return APC_OK;
+  }
   int n = 0;
   HIPCHK(hipGetDeviceCount(&n));
   if (device < 0 || device >= n) return fail(APC_E_ARG, "device %d not present (%d devices)", device, n);
@@ -432,6 +523,10 @@ apc_status apc_create(int device, apc_ctx* out) {
 
 apc_status apc_destroy(apc_ctx ctx) {
   if (!ctx) return APC_OK;
+  if (ctx->host_only) {
+    delete ctx;
+    return APC_OK;
+  }
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   for (DevBuf* b : {&ctx->counts, &ctx->offsets, &ctx->cursors, &ctx->records, &ctx->scan_tmp, &ctx->slots,
@@ -452,7 +547,7 @@ apc_status apc_load_mesh(apc_ctx ctx, const apc_mesh_desc* d, apc_mesh* out, voi
   if (st != APC_OK) return st;
   if (!d || !out) return fail(APC_E_ARG, "desc/out is NULL");
   *out = nullptr;
-  if (d->flags != 0) return fail(APC_E_UNSUPPORTED, "mesh flags must be 0 (host pointers)");
+  if (d->flags & ~int32_t(APC_MESH_DEVICE)) return fail(APC_E_ARG, "unknown mesh flags 0x%x", unsigned(d->flags));
   if (!d->xyz || !d->scalar || !d->tet_vertices || !d->tet_subdomain) return fail(APC_E_ARG, "mesh array is NULL");
   const int64_t V = d->n_vertices, T = d->n_tets;
   const int S = d->n_subdomains;
@@ -463,7 +558,33 @@ apc_status apc_load_mesh(apc_ctx ctx, const apc_mesh_desc* d, apc_mesh* out, voi
   const int32_t* tv = d->tet_vertices;
   const int32_t* ts = d->tet_subdomain;
   const float* xyz = d->xyz;
-  // ---- validation (indices first: nothing touches memory through an unchecked id)
+  const float* scal = d->scalar;
+  // device arrays are validated from a host copy (the validation and the grouping run on the host)
+  std::vector<float> h_xyz, h_scal;
+  std::vector<int32_t> h_tv, h_ts;
+  if (d->flags & APC_MESH_DEVICE) {
+    if (ctx->host_only) return no_device("apc_load_mesh");
+    try {
+      h_xyz.resize(size_t(3 * V));
+      h_scal.resize(size_t(V));
+      h_tv.resize(size_t(4 * T));
+      h_ts.resize(size_t(T));
+    } catch (...) {
+      return fail(APC_E_NOMEM, "host copy of the mesh arrays");
+    }
+    HIPCHK(hipMemcpyAsync(h_xyz.data(), xyz, sizeof(float) * 3 * V, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(h_scal.data(), scal, sizeof(float) * V, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(h_tv.data(), tv, sizeof(int32_t) * 4 * T, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(h_ts.data(), ts, sizeof(int32_t) * T, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    xyz = h_xyz.data();
+    scal = h_scal.data();
+    tv = h_tv.data();
+    ts = h_ts.data();
+  }
+  // ---- validation (coordinates, then indices: nothing touches memory through an unchecked id)
+  for (int64_t q = 0; q < 3 * V; ++q)
+    if (!std::isfinite(xyz[q])) return fail(APC_E_MESH, "vertex %lld: coordinate is not finite", (long long)(q / 3));
   std::vector<int64_t> bad(16, -1);
   std::vector<int> why(16, 0);
   parallel_for(T, [&](int64_t lo, int64_t hi, int k) {
@@ -502,8 +623,6 @@ apc_status apc_load_mesh(apc_ctx ctx, const apc_mesh_desc* d, apc_mesh* out, voi
                                   "non-positive signed volume"};
       return fail(APC_E_MESH, "tet %lld: %s", (long long)bad[k], msg[why[k]]);
     }
-  for (int64_t q = 0; q < 3 * V; ++q)
-    if (!std::isfinite(xyz[q])) return fail(APC_E_MESH, "vertex coordinate %lld is not finite", (long long)(q / 3));
   // ---- group tets by subdomain, keeping input order inside each (stable counting sort)
   apc_mesh_s* m = new (std::nothrow) apc_mesh_s();
   if (!m) return fail(APC_E_NOMEM, "host allocation failed");
@@ -532,7 +651,7 @@ apc_status apc_load_mesh(apc_ctx ctx, const apc_mesh_desc* d, apc_mesh* out, voi
       m->hi[c] = std::max(m->hi[c], double(xyz[3 * v + c]));
     }
   std::vector<float4> vert(V);
-  for (int64_t v = 0; v < V; ++v) vert[v] = make_float4(xyz[3 * v], xyz[3 * v + 1], xyz[3 * v + 2], d->scalar[v]);
+  for (int64_t v = 0; v < V; ++v) vert[v] = make_float4(xyz[3 * v], xyz[3 * v + 1], xyz[3 * v + 2], scal[v]);
   // ---- face adjacency on the device through vertex -> tet incidence lists
   DevBuf d_tv, d_cnt, d_off, d_cur, d_inc, d_nbr, d_err, d_tmp;
   auto cleanup = [&]() {
@@ -549,7 +668,12 @@ apc_status apc_load_mesh(apc_ctx ctx, const apc_mesh_desc* d, apc_mesh* out, voi
   };
   hipError_t e;
   std::vector<int> nbr(4 * T);
-  {
+  if (ctx->host_only) {
+    if (!host_adjacency(tv_sorted, V, nbr)) {
+      delete m;
+      return fail(APC_E_MESH, "a face is shared by more than two tets (non-manifold mesh)");
+    }
+  } else {
     if ((e = d_tv.ensure(sizeof(int4) * T)) != hipSuccess) return dev_fail(e, "alloc");
     if ((e = d_cnt.ensure(sizeof(int) * (V + 1))) != hipSuccess) return dev_fail(e, "alloc");
     if ((e = d_off.ensure(sizeof(int) * (V + 1))) != hipSuccess) return dev_fail(e, "alloc");
@@ -608,6 +732,11 @@ apc_status apc_load_mesh(apc_ctx ctx, const apc_mesh_desc* d, apc_mesh* out, voi
   m->NB = m->face_begin[S];
   std::vector<int> bface(std::max<int64_t>(m->NB, 1));
   for (int k = 0; k < S; ++k) std::copy(bf[k].begin(), bf[k].end(), bface.begin() + m->face_begin[k]);
+  if (ctx->host_only) {  // validated and grouped; nothing goes to a device
+    m->host_only = true;
+    *out = m;
+    return APC_OK;
+  }
   std::vector<int4> rec(2 * T);
   parallel_for(T, [&](int64_t lo, int64_t hi, int) {
     for (int64_t t = lo; t < hi; ++t) {
@@ -636,6 +765,10 @@ apc_status apc_load_mesh(apc_ctx ctx, const apc_mesh_desc* d, apc_mesh* out, voi
 
 apc_status apc_free_mesh(apc_ctx ctx, apc_mesh m) {
   if (!m) return APC_OK;
+  if (m->host_only) {
+    delete m;
+    return APC_OK;
+  }
   if (ctx) (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   if (m->vert) (void)hipFree(m->vert);
@@ -694,7 +827,7 @@ apc_status apc_moments_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const
                             const int32_t* subs, int32_t n_sub, float* out, uint32_t flags, void* stream) {
   apc_status st = check_ctx(ctx);
   if (st != APC_OK) return st;
-  if (!m) return fail(APC_E_ARG, "mesh is NULL");
+  if ((st = check_mesh(ctx, m)) != APC_OK) return st;
   if ((st = check_view_tf(view, tf)) != APC_OK) return st;
   if (mm != 4 && mm != 6 && mm != 8) return fail(APC_E_ARG, "m = %d unsupported (4, 6 or 8)", mm);
   if ((st = check_subdomains(m, subs, n_sub)) != APC_OK) return st;
@@ -706,6 +839,7 @@ apc_status apc_moments_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const
       if (!(subs[k - 1] < subs[k])) return fail(APC_E_ARG, "APC_MOMENTS_GLOBAL needs ascending subdomain ids");
   FrameDev f;
   if ((st = make_frame(m, view, tf, n_sub, max_tets_of(m, subs, n_sub), ctx->tw_log2, f)) != APC_OK) return st;
+  if (ctx->host_only) return no_device("apc_moments_pass");
   hipStream_t s = static_cast<hipStream_t>(stream);
   MeshDev md;
   if ((st = build_bins(ctx, m, f, subs, n_sub, s, md)) != APC_OK) return st;
@@ -762,6 +896,7 @@ apc_status apc_sum_moments(apc_ctx ctx, const float* in, int32_t n_sub, int32_t 
         if (subs[q] == subs[k]) return fail(APC_E_ARG, "subdomain id %d listed twice", subs[k]);
     std::sort(order.begin(), order.end(), [&](int a, int b) { return subs[a] < subs[b]; });
   }
+  if (ctx->host_only) return no_device("apc_sum_moments");
   hipStream_t s = static_cast<hipStream_t>(stream);
   HIPCHK(ctx->order.ensure(sizeof(int) * n_sub));
   if ((st = stage_upload(ctx, ctx->order.p, order.data(), sizeof(int) * n_sub, s)) != APC_OK) return st;
@@ -795,7 +930,7 @@ apc_status apc_resolve_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const
   const apc_status st = resolve_frame(ctx, m, view, tf, mb, moments, subs, n_sub, rgba, flags, stream);
   // a frame whose pieces did not fit the store has sized it anew: grow it now, at the end of this frame,
   // so that the next frame's stage one does not allocate (an allocation waits for the whole device)
-  if (st == APC_OK && ctx->store_failed_last && !ctx->capturing && ctx->store_slots > 0)
+  if (st == APC_OK && !ctx->host_only && ctx->store_failed_last && !ctx->capturing && ctx->store_slots > 0)
     (void)grow_piece_store(ctx, ctx->store_slots);  // on failure the next stage one tries again
   return st;
 }
@@ -805,7 +940,7 @@ static apc_status resolve_frame(apc_ctx ctx, apc_mesh m, const apc_view* view, c
                                 float* rgba, uint32_t flags, void* stream) {
   apc_status st = check_ctx(ctx);
   if (st != APC_OK) return st;
-  if (!m) return fail(APC_E_ARG, "mesh is NULL");
+  if ((st = check_mesh(ctx, m)) != APC_OK) return st;
   if ((st = check_view_tf(view, tf)) != APC_OK) return st;
   apc::BoundParams bp;
   if ((st = bound_params(mb, bp, (flags & APC_FINALIZE) ? 1 : 0)) != APC_OK) return st;
@@ -818,6 +953,7 @@ static apc_status resolve_frame(apc_ctx ctx, apc_mesh m, const apc_view* view, c
     return fail(APC_E_ARG, "packed FP16 moments must be 2-byte aligned");
   FrameDev f;
   if ((st = make_frame(m, view, tf, n_sub, max_tets_of(m, subs, n_sub), ctx->tw_log2, f)) != APC_OK) return st;
+  if (ctx->host_only) return no_device("apc_resolve_pass");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int nt = f.n_tiles;
   unsigned long long* ctr = ctx->counters.as<unsigned long long>();
@@ -966,6 +1102,8 @@ apc_status apc_frame_graph_create(apc_ctx ctx, apc_mesh m, const apc_view* view,
   if (flags & ~(APC_FINALIZE | APC_MOMENTS_GLOBAL)) return fail(APC_E_ARG, "unknown flags 0x%x", flags);
   const bool global = (flags & APC_MOMENTS_GLOBAL) != 0;
   if (!global && !moments_per_sub) return fail(APC_E_ARG, "moments_per_sub is NULL");
+  if ((st = check_mesh(ctx, m)) != APC_OK) return st;
+  if (ctx->host_only) return no_device("apc_frame_graph_create");
   apc_graph g = new (std::nothrow) apc_graph_s();
   if (!g) return fail(APC_E_NOMEM, "host allocation failed");
   if ((st = apc_create(ctx->device, &g->own)) != APC_OK) {
@@ -1045,6 +1183,7 @@ apc_status apc_set_workspace_limit(apc_ctx ctx, int64_t bytes) {
   if (st != APC_OK) return st;
   if (bytes < 0) return fail(APC_E_ARG, "negative limit");
   ctx->ws_limit = bytes;
+  if (ctx->host_only) return APC_OK;
   // buffers above their share of the new limit are given back
   if (bytes > 0 && ctx->pool.bytes > size_t(bytes / 4 * 3)) {
     HIPCHK(hipDeviceSynchronize());
@@ -1086,6 +1225,8 @@ apc_status apc_autotune_tile_shape(apc_ctx ctx, apc_mesh m, const apc_view* view
   if (st != APC_OK) return st;
   if (repeats < 1 || repeats > 100) return fail(APC_E_ARG, "repeats must be in 1..100");
   if (!mboit) return fail(APC_E_ARG, "mboit is NULL");
+  if ((st = check_mesh(ctx, m)) != APC_OK) return st;
+  if (ctx->host_only) return no_device("apc_autotune_tile_shape");
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(hipEventCreate(&e0));
@@ -1133,6 +1274,7 @@ apc_status apc_segment_counts(apc_ctx ctx, int32_t* out, int32_t H, int32_t W, v
   if (ctx->seg_h == 0) return fail(APC_E_ARG, "no stage one has run on this context");
   if (H != ctx->seg_h || W != ctx->seg_w)
     return fail(APC_E_ARG, "image is %dx%d, the last stage one was %dx%d", W, H, ctx->seg_w, ctx->seg_h);
+  if (ctx->host_only) return no_device("apc_segment_counts");
   HIPCHK(hipMemcpyAsync(out, ctx->segs.p, sizeof(int) * 2 * size_t(H) * W, hipMemcpyDeviceToDevice,
                         static_cast<hipStream_t>(stream)));
   return APC_OK;
@@ -1146,7 +1288,8 @@ apc_status apc_pack_moments_f16(apc_ctx ctx, const float* moments, int32_t mm, i
   if (mm != 4 && mm != 6 && mm != 8) return fail(APC_E_ARG, "m = %d unsupported", mm);
   if (H <= 0 || W <= 0) return fail(APC_E_ARG, "sizes out of range");
   if (reinterpret_cast<uintptr_t>(packed) & 1) return fail(APC_E_ARG, "packed must be 2-byte aligned");
-  HIPCHK(apc::launch_pack_f16(moments, mm + 1, int64_t(H) * W, static_cast<_Float16*>(packed),
+  if (ctx->host_only) return no_device("apc_pack_moments_f16");
+  HIPCHK(apc::launch_pack_f16(moments, mm + 1, int64_t(H) * W, packed,
                               static_cast<hipStream_t>(stream)));
   return APC_OK;
 }
@@ -1170,6 +1313,7 @@ apc_status apc_sum_images(apc_ctx ctx, const float* partials, int32_t n_sub, int
         if (subs[q] == subs[k]) return fail(APC_E_ARG, "subdomain id %d listed twice", subs[k]);
     std::sort(order.begin(), order.end(), [&](int a, int b) { return subs[a] < subs[b]; });
   }
+  if (ctx->host_only) return no_device("apc_sum_images");
   hipStream_t s = static_cast<hipStream_t>(stream);
   HIPCHK(ctx->order.ensure(sizeof(int) * n_sub));
   if ((st = stage_upload(ctx, ctx->order.p, order.data(), sizeof(int) * n_sub, s)) != APC_OK) return st;
@@ -1181,6 +1325,7 @@ apc_status apc_get_counters(apc_ctx ctx, apc_counters* out, int32_t reset) {
   apc_status st = check_ctx(ctx);
   if (st != APC_OK) return st;
   if (!out) return fail(APC_E_ARG, "out is NULL");
+  if (ctx->host_only) return no_device("apc_get_counters");
   HIPCHK(hipDeviceSynchronize());
   unsigned long long c[apc::C_COUNT];
   HIPCHK(hipMemcpy(c, ctx->counters.p, sizeof(c), hipMemcpyDeviceToHost));
@@ -1206,6 +1351,7 @@ apc_status apc_get_timings(apc_ctx ctx, apc_timings* out) {
   apc_status st = check_ctx(ctx);
   if (st != APC_OK) return st;
   if (!out) return fail(APC_E_ARG, "out is NULL");
+  if (ctx->host_only) return no_device("apc_get_timings");
   double ms[EV_COUNT] = {};
   for (int k = 0; k < EV_COUNT; ++k) {
     if (!ctx->ev_used[k]) continue;

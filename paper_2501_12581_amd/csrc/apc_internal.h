@@ -27,8 +27,8 @@ struct SlotDev {
   int face_begin, face_end;  // range in the boundary-face array
 };
 
-// Per-call constants, FP32 copies of the camera, lattice, warp and transfer
-// function parameters.
+// Per-call constants: the camera (FP32 for binning, FP64 for the rays), the
+// lattice, the warp and the transfer-function parameters.
 struct FrameDev {
   int W, H, proj, tiles_x, tiles_y, n_tiles, n_slots, n_tf;
   int tw_log2;          // a tile (one wavefront) is (1 << tw_log2) x (64 >> tw_log2) pixels
@@ -37,11 +37,17 @@ struct FrameDev {
   float rx, ry, rz;     // right
   float wx, wy, wz;     // down
   float half_w, half_h; // W/2, H/2
+  // The walk's ray geometry is FP64: the camera below, the ray's orthonormal
+  // frame, every vertex depth and the lattice cuts.  A grazing ray's chord
+  // through a face changes by the lateral ray error over the tangent of the
+  // incidence angle, so FP32 rays (~3e-7 lateral error at distance 2) moved
+  // silhouette moments by up to 6e-4 of b0; in FP64 only the FP32 side
+  // products remain (~1e-7 of a face's size).
+  double ceye[3], cdir[3], cright[3], cdown[3];
   // Depths inside the kernels are measured from a ray origin moved forward by
-  // t_mid = (t_near + t_far) / 2, so |t| <= (t_far - t_near) / 2 and FP32
-  // depths resolve ~4x finer than absolute distances would.  t_near below is
-  // the lattice origin in those shifted units (t_near - t_mid).
-  float t_mid, t_near, step, inv_step;
+  // t_mid = (t_near + t_far) / 2.  t_near below is the lattice origin in
+  // those shifted units (t_near - t_mid).
+  double t_mid, t_near, step, inv_step;
   float lg_near, warp_scale;  // log2(t_near), 2 / (log2 t_far - log2 t_near), absolute units
   float s_min, tf_scale;      // table coordinate = (s - s_min) * tf_scale
   float kappa, amax;
@@ -111,7 +117,7 @@ hipError_t launch_eval(int mm, const FrameDev& f, int tile_lo, int tile_hi, cons
 // exclusive scan of the per-tile piece totals on the device
 hipError_t launch_tile_offsets(const long long* tile_tot, int n_tiles, long long* tile_off, hipStream_t s);
 // FP16 packing of a global moment image
-hipError_t launch_pack_f16(const float* in, int m1, int64_t pixels, _Float16* out, hipStream_t s);
+hipError_t launch_pack_f16(const float* in, int m1, int64_t pixels, void* out_f16, hipStream_t s);
 hipError_t launch_tile_sums(const int* pcount, int n_tiles, long long* tile_tot, hipStream_t s);
 hipError_t launch_piece_offsets(const int* pcount, const long long* tile_off, int n_tiles, long long* poff,
                                 hipStream_t s);

@@ -72,44 +72,45 @@ __device__ __forceinline__ int xcd_tile(int b, int nb, int run = XCD_RUN) {
   return whole + x * q + (x < r ? x : r) + i;
 }
 
-// A pixel ray: origin o, unit direction d, and unit vectors a, b = d x a
-// perpendicular to d, so that (a, b, d) is a right-handed orthonormal frame.
+// A pixel ray in FP64: origin o (moved forward by t_mid), unit direction d,
+// and unit vectors a, b = d x a perpendicular to d, so that (a, b, d) is a
+// right-handed orthonormal frame.
 struct Ray {
-  float ox, oy, oz, dx, dy, dz;
-  float ax, ay, az, bx, by, bz;
+  double ox, oy, oz, dx, dy, dz;
+  double ax, ay, az, bx, by, bz;
 };
 
 __device__ __forceinline__ Ray pixel_ray(const FrameDev& f, int i, int j) {
 #pragma clang fp contract(off)
-  float a = float(j) + 0.5f, b = float(i) + 0.5f;
+  const double a = double(j) + 0.5, b = double(i) + 0.5;
   Ray r;
-  float dx, dy, dz;
+  double dx, dy, dz;
   if (f.proj == 0) {
-    r.ox = f.ex + a * f.rx + b * f.wx;
-    r.oy = f.ey + a * f.ry + b * f.wy;
-    r.oz = f.ez + a * f.rz + b * f.wz;
-    dx = f.dx;
-    dy = f.dy;
-    dz = f.dz;
+    r.ox = f.ceye[0] + a * f.cright[0] + b * f.cdown[0];
+    r.oy = f.ceye[1] + a * f.cright[1] + b * f.cdown[1];
+    r.oz = f.ceye[2] + a * f.cright[2] + b * f.cdown[2];
+    dx = f.cdir[0];
+    dy = f.cdir[1];
+    dz = f.cdir[2];
   } else {
-    r.ox = f.ex;
-    r.oy = f.ey;
-    r.oz = f.ez;
-    float aa = a - f.half_w, bb = b - f.half_h;
-    dx = f.dx + aa * f.rx + bb * f.wx;
-    dy = f.dy + aa * f.ry + bb * f.wy;
-    dz = f.dz + aa * f.rz + bb * f.wz;
+    r.ox = f.ceye[0];
+    r.oy = f.ceye[1];
+    r.oz = f.ceye[2];
+    const double aa = a - 0.5 * double(f.W), bb = b - 0.5 * double(f.H);
+    dx = f.cdir[0] + aa * f.cright[0] + bb * f.cdown[0];
+    dy = f.cdir[1] + aa * f.cright[1] + bb * f.cdown[1];
+    dz = f.cdir[2] + aa * f.cright[2] + bb * f.cdown[2];
   }
-  float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+  const double inv = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
   r.dx = dx * inv;
   r.dy = dy * inv;
   r.dz = dz * inv;
   {
     // a = d x h / |d x h| for a coordinate axis h far from parallel to d
-    const bool xs = fabsf(r.dx) < 0.9f;
-    const float hx = xs ? 1.0f : 0.0f, hy = xs ? 0.0f : 1.0f;
-    const float ax = -r.dz * hy, ay = r.dz * hx, az = r.dx * hy - r.dy * hx;
-    const float ia = 1.0f / sqrtf(ax * ax + ay * ay + az * az);
+    const bool xs = fabs(r.dx) < 0.9;
+    const double hx = xs ? 1.0 : 0.0, hy = xs ? 0.0 : 1.0;
+    const double ax = -r.dz * hy, ay = r.dz * hx, az = r.dx * hy - r.dy * hx;
+    const double ia = 1.0 / sqrt(ax * ax + ay * ay + az * az);
     r.ax = ax * ia;
     r.ay = ay * ia;
     r.az = az * ia;
@@ -124,11 +125,15 @@ __device__ __forceinline__ Ray pixel_ray(const FrameDev& f, int i, int j) {
   return r;
 }
 
-// A vertex as seen from one ray: id, scalar, depth t = d.(P-o) and its
-// coordinates u = a.(P-o), v = b.(P-o) in the plane perpendicular to the ray.
+// A vertex as seen from one ray: id, scalar, depth t = d.(P-o) (FP64) and its
+// coordinates u = a.(P-o), v = b.(P-o) in the plane perpendicular to the ray,
+// computed in FP64 and rounded to FP32 (near the ray |u|, |v| are about a
+// cell's size, so the rounding is ~1e-7 of a cell, not of the distance to
+// the eye).
 struct VS {
   int id;
-  float s, t, u, v;
+  float s, u, v;
+  double t;
 };
 
 __device__ __forceinline__ VS vstate(const Ray& r, int id, float4 p) {
@@ -136,10 +141,10 @@ __device__ __forceinline__ VS vstate(const Ray& r, int id, float4 p) {
   VS v;
   v.id = id;
   v.s = p.w;
-  float px = p.x - r.ox, py = p.y - r.oy, pz = p.z - r.oz;
+  const double px = double(p.x) - r.ox, py = double(p.y) - r.oy, pz = double(p.z) - r.oz;
   v.t = r.dx * px + r.dy * py + r.dz * pz;
-  v.u = r.ax * px + r.ay * py + r.az * pz;
-  v.v = r.bx * px + r.by * py + r.bz * pz;
+  v.u = float(r.ax * px + r.ay * py + r.az * pz);
+  v.v = float(r.bx * px + r.by * py + r.bz * pz);
   return v;
 }
 
@@ -161,14 +166,17 @@ __device__ __forceinline__ float side(const VS& a, const VS& b) {
 // sums start at the vertex with the smallest id, so the walk that leaves a
 // tet through a face and the entry test of the tet behind it (which list the
 // face's vertices in different rotations) get the same depth bit for bit.
+// The depth is that vertex's FP64 depth plus the weighted depth differences
+// across the face (at most a cell's extent, so FP32 keeps them to ~1e-7 of a
+// cell, the precision of the weights themselves).
 __device__ __forceinline__ void face_point(const VS& A, const VS& B, const VS& C, float pAB, float pBC, float pCA,
-                                           float& t, float& s) {
+                                           double& t, float& s) {
 #pragma clang fp contract(off)
   float uA = fmaxf(pBC, 0.0f), uB = fmaxf(pCA, 0.0f), uC = fmaxf(pAB, 0.0f);
   const bool bmin = B.id < A.id && B.id < C.id, cmin = C.id < A.id && C.id < B.id;
   const float u0 = bmin ? uB : (cmin ? uC : uA), u1 = bmin ? uC : (cmin ? uA : uB), u2 = bmin ? uA : (cmin ? uB : uC);
-  const float t0 = bmin ? B.t : (cmin ? C.t : A.t), t1 = bmin ? C.t : (cmin ? A.t : B.t),
-              t2 = bmin ? A.t : (cmin ? B.t : C.t);
+  const double t0 = bmin ? B.t : (cmin ? C.t : A.t), t1 = bmin ? C.t : (cmin ? A.t : B.t),
+               t2 = bmin ? A.t : (cmin ? B.t : C.t);
   const float s0 = bmin ? B.s : (cmin ? C.s : A.s), s1 = bmin ? C.s : (cmin ? A.s : B.s),
               s2 = bmin ? A.s : (cmin ? B.s : C.s);
   float sum = u0 + u1 + u2;
@@ -178,7 +186,7 @@ __device__ __forceinline__ void face_point(const VS& A, const VS& B, const VS& C
     return;
   }
   float inv = 1.0f / sum;
-  t = (u0 * t0 + u1 * t1 + u2 * t2) * inv;
+  t = t0 + double((u1 * float(t1 - t0) + u2 * float(t2 - t0)) * inv);
   s = (u0 * s0 + u1 * s1 + u2 * s2) * inv;
 }
 
@@ -194,7 +202,8 @@ struct FaceL {
 // products, and the entry depth/scalar.
 struct Entry {
   VS A, B, C;
-  float pAB, pBC, pCA, t, s;
+  float pAB, pBC, pCA, s;
+  double t;
 };
 
 __device__ __forceinline__ bool enter_face(const Ray& r, int id0, int id1, int id2, float4 p0, float4 p1,
@@ -218,23 +227,25 @@ struct LaneCount {
 };
 
 // Cut the chord [t0, t1] (scalar s0 -> s1) at the lattice t_near + k*step and
-// hand each piece (mid depth, length, scalar at the mid point) to fn.
+// hand each piece (mid depth, length, scalar at the mid point) to fn.  The cut
+// points and mid depths are FP64 (depths are absolute positions along the
+// ray); lengths and scalars are FP32.
 template <class Fn>
-__device__ __forceinline__ void cut_chord(const FrameDev& f, float t0, float t1, float s0, float s1, Fn&& fn) {
+__device__ __forceinline__ void cut_chord(const FrameDev& f, double t0, double t1, float s0, float s1, Fn&& fn) {
 #pragma clang fp contract(off)
-  float len = t1 - t0;
-  if (!(len > 0.0f)) return;
-  float slope = (s1 - s0) / len;
-  float kf = floorf((t0 - f.t_near) * f.inv_step) + 1.0f;
-  float u = t0;
+  const double len = t1 - t0;
+  if (!(len > 0.0)) return;
+  const float slope = (s1 - s0) / float(len);
+  double kf = floor((t0 - f.t_near) * f.inv_step) + 1.0;
+  double u = t0;
   for (int guard = 0; u < t1 && guard < (1 << 22); ++guard) {
-    float nxt = f.t_near + kf * f.step;
-    kf += 1.0f;
+    const double nxt = f.t_near + kf * f.step;
+    kf += 1.0;
     if (nxt <= u) continue;
-    float v = fminf(nxt, t1);
-    float tm = 0.5f * (u + v);
-    float s = s0 + slope * (tm - t0);
-    fn(tm, v - u, s);
+    const double v = fmin(nxt, t1);
+    const double tm = 0.5 * (u + v);
+    const float s = s0 + slope * float(tm - t0);
+    fn(tm, float(v - u), s);
     u = v;
   }
 }
@@ -250,10 +261,10 @@ __device__ __forceinline__ void tf_coord(const FrameDev& f, float s, int& i0, fl
 
 // Optical depth of a piece and its warped depth (Alg. 2: absorbance capped,
 // log depth rescaled to [-1, 1]).
-__device__ __forceinline__ void piece_az(const FrameDev& f, float tm, float len, float A, float& a, float& z) {
+__device__ __forceinline__ void piece_az(const FrameDev& f, double tm, float len, float A, float& a, float& z) {
 #pragma clang fp contract(off)
   a = fminf(f.kappa * A * len, f.amax);
-  z = (__log2f(tm + f.t_mid) - f.lg_near) * f.warp_scale - 1.0f;
+  z = (__log2f(float(tm + f.t_mid)) - f.lg_near) * f.warp_scale - 1.0f;
   z = fminf(fmaxf(z, -1.0f), 1.0f);
 }
 
@@ -269,7 +280,8 @@ template <class Sink>
 __device__ void walk(const MeshDev& M, const FrameDev& f, const Ray& r, int tet, int apex, Entry e, int t_lo,
                      int t_hi, Sink& sink, LaneCount& cnt) {
   VS A = e.A, B = e.B, C = e.C;
-  float pAB = e.pAB, pBC = e.pBC, pCA = e.pCA, tin = e.t, sin_ = e.s;
+  float pAB = e.pAB, pBC = e.pBC, pCA = e.pCA, sin_ = e.s;
+  double tin = e.t;
   for (int step = 0;; ++step) {
     if (step >= f.max_steps) {
       ++cnt.steplimit;
@@ -310,7 +322,8 @@ __device__ void walk(const MeshDev& M, const FrameDev& f, const Ray& r, int tet,
     pAB = nAB;
     pBC = nBC;
     pCA = nCA;
-    float tout, sout;
+    double tout;
+    float sout;
     face_point(A, B, C, pAB, pBC, pCA, tout, sout);
     if (!(tout >= tin)) tout = tin;
     ++cnt.steps;
@@ -385,19 +398,20 @@ __device__ void walk_subdomain(const MeshDev& M, const FrameDev& f, const Ray& r
         const FaceL& F = faces[k];
         Entry e;
         if (!enter_face(r, F.id0, F.id1, F.id2, F.p0, F.p1, F.p2, e)) continue;
-        if (!key_less(last_t, last_c, e.t, F.code)) continue;  // walked in an earlier round
+        const float et = float(e.t);  // sort key: the entry depth rounded to FP32
+        if (!key_less(last_t, last_c, et, F.code)) continue;  // walked in an earlier round
         if (n == E_MAX) {
           more = true;
-          if (!key_less(e.t, F.code, L.T(n - 1), L.Cd(n - 1))) continue;
+          if (!key_less(et, F.code, L.T(n - 1), L.Cd(n - 1))) continue;
           --n;  // evict the largest
         }
         int pos = n;
-        while (pos > 0 && key_less(e.t, F.code, L.T(pos - 1), L.Cd(pos - 1))) {
+        while (pos > 0 && key_less(et, F.code, L.T(pos - 1), L.Cd(pos - 1))) {
           L.T(pos) = L.T(pos - 1);
           L.Cd(pos) = L.Cd(pos - 1);
           --pos;
         }
-        L.T(pos) = e.t;
+        L.T(pos) = et;
         L.Cd(pos) = F.code;
         ++n;
       }
@@ -521,7 +535,10 @@ struct LaneStore {
   }
 };
 
-template <int M1>
+// KEEP: stage one also keeps every piece for stage two (the pieces then need
+// not be walked again); fixed per launch, so the store costs no registers
+// when it is off.
+template <int M1, bool KEEP>
 struct MomentSink {
   const FrameDev* f;
   const float* tfa;  // LDS alpha column of the table
@@ -529,8 +546,8 @@ struct MomentSink {
   unsigned pieces;
   LaneStore st;      // st.keep false: pieces are not kept
   int lane;
-  __device__ void chord(float t0, float t1, float s0, float s1) {
-    cut_chord(*f, t0, t1, s0, s1, [&](float tm, float len, float s) {
+  __device__ void chord(double t0, double t1, float s0, float s1) {
+    cut_chord(*f, t0, t1, s0, s1, [&](double tm, float len, float s) {
       int i0;
       float fr, a, z;
       tf_coord(*f, s, i0, fr);
@@ -542,7 +559,7 @@ struct MomentSink {
         b[j] += double(term);
         term *= z;
       }
-      st.put(z, a, s, lane);
+      if constexpr (KEEP) st.put(z, a, s, lane);
       ++pieces;
     });
   }
@@ -553,7 +570,7 @@ struct MomentSink {
 #define APC_WALK_WAVES 3
 #endif
 
-template <int M1>
+template <int M1, bool KEEP>
 __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_WALK_WAVES, 8))) void k_moments(MeshDev M, FrameDev f, const SlotDev* __restrict__ slots,
                                                   const int* __restrict__ offsets, const int* __restrict__ counts,
                                                   const int* __restrict__ records, const float* __restrict__ tf_rgba,
@@ -581,7 +598,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_WALK_W
   // wavefronts per SIMD), else in the per-pixel scratch gacc; the same additions either way
   constexpr bool REG_ACC = M1 <= 7;
   double acc[REG_ACC ? M1 : 1];
-  MomentSink<M1> sink;  // one sink for all subdomains: its piece store runs across them
+  MomentSink<M1, KEEP> sink;  // one sink for all subdomains: its piece store runs across them
   sink.f = &f;
   sink.tfa = tfa;
   __shared__ unsigned long long blk_base;
@@ -667,8 +684,8 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_WALK_W
 struct CountSink {
   const FrameDev* f;
   unsigned pieces;
-  __device__ void chord(float t0, float t1, float s0, float s1) {
-    cut_chord(*f, t0, t1, s0, s1, [&](float, float, float) { ++pieces; });
+  __device__ void chord(double t0, double t1, float s0, float s1) {
+    cut_chord(*f, t0, t1, s0, s1, [&](double, float, float) { ++pieces; });
   }
 };
 
@@ -683,8 +700,8 @@ struct StageSink {
   float* out;        // this pixel's records: 3 floats each
   unsigned pieces;
   unsigned cap;
-  __device__ void chord(float t0, float t1, float s0, float s1) {
-    cut_chord(*f, t0, t1, s0, s1, [&](float tm, float len, float s) {
+  __device__ void chord(double t0, double t1, float s0, float s1) {
+    cut_chord(*f, t0, t1, s0, s1, [&](double tm, float len, float s) {
       int i0;
       float fr, a, z;
       tf_coord(*f, s, i0, fr);
@@ -1386,15 +1403,22 @@ hipError_t launch_moments(int mm, const MeshDev& m, const FrameDev& f, const Slo
                           unsigned long long* counters, hipStream_t s) {
   const size_t lds = size_t(f.n_tf) * sizeof(float);
   const dim3 grid(f.n_tiles), block(WAVE);
+#define APC_LAUNCH_MOMENTS(M1)                                                                          \
+  do {                                                                                                  \
+    if (store.pool)                                                                                     \
+      hipLaunchKernelGGL((k_moments<M1, true>), grid, block, lds, s, m, f, slots, offsets, counts, records, \
+                         tf_rgba, out, gacc, pcount, segs, bin_cap, store, counters);                   \
+    else                                                                                                \
+      hipLaunchKernelGGL((k_moments<M1, false>), grid, block, lds, s, m, f, slots, offsets, counts,     \
+                         records, tf_rgba, out, gacc, pcount, segs, bin_cap, store, counters);          \
+  } while (0)
   if (mm == 4)
-    hipLaunchKernelGGL(k_moments<5>, grid, block, lds, s, m, f, slots, offsets, counts, records, tf_rgba, out,
-                       gacc, pcount, segs, bin_cap, store, counters);
+    APC_LAUNCH_MOMENTS(5);
   else if (mm == 6)
-    hipLaunchKernelGGL(k_moments<7>, grid, block, lds, s, m, f, slots, offsets, counts, records, tf_rgba, out,
-                       gacc, pcount, segs, bin_cap, store, counters);
+    APC_LAUNCH_MOMENTS(7);
   else
-    hipLaunchKernelGGL(k_moments<9>, grid, block, lds, s, m, f, slots, offsets, counts, records, tf_rgba, out,
-                       gacc, pcount, segs, bin_cap, store, counters);
+    APC_LAUNCH_MOMENTS(9);
+#undef APC_LAUNCH_MOMENTS
   return hipGetLastError();
 }
 
@@ -1435,9 +1459,10 @@ hipError_t launch_eval(int mm, const FrameDev& f, int tile_lo, int tile_hi, cons
   return hipGetLastError();
 }
 
-hipError_t launch_pack_f16(const float* in, int m1, int64_t pixels, _Float16* out, hipStream_t s) {
+hipError_t launch_pack_f16(const float* in, int m1, int64_t pixels, void* out_f16, hipStream_t s) {
   if (pixels <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pack_f16, dim3(grid1(pixels, 256)), dim3(256), 0, s, in, m1, pixels, out);
+  hipLaunchKernelGGL(k_pack_f16, dim3(grid1(pixels, 256)), dim3(256), 0, s, in, m1, pixels,
+                     static_cast<_Float16*>(out_f16));
   return hipGetLastError();
 }
 
