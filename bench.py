@@ -1,16 +1,22 @@
 """Throughput of the APC hot path on one MI355X.
 
-One step = one frame of the whole path on the largest single-GPU workload:
-stage one (boundary-face binning + tet walk + power moments) for all 72
-subdomains, the canonical-order moment sum, and stage two (the same walk with
-the FP64 moment bound) with the final renormalised image.  Inputs (mesh,
-transfer function, camera) are resident in HBM before timing starts.
+One step = one frame of the whole path in its plain form on the largest
+single-GPU workload (256^3 x 6 = 100,663,296 tets, 72 Morton subdomains,
+2560^2, m = 8): stage one (boundary-face binning, tet walk, power moments) for
+all 72 subdomains with the canonical-order moment sum, then stage two (the
+same walk again, every piece weighted at once by the FP64 moment bound) with
+the final renormalised image.  Frames cycle over the workload's 5 seeded orbit
+cameras.  Inputs (mesh, transfer function, cameras) are resident in HBM before
+timing starts.
 
-Prints ONE JSON line.  `value` is ray samples per second (pieces generated
-per frame / frame time); frames/s, per-kernel times, the roofline figure of
-the dominant kernel, sampled parity against the FP64 oracle, and the oracle's
-own throughput on a bounded pixel sample of the same frame are reported beside
-it.
+Prints ONE JSON line.  `value` is ray samples per second over the timed frames
+(pieces generated per frame / frame time); frames/s is 1 / the median over the
+cameras of their mean frame time.  Reported beside it: per-kernel times, the
+roofline figure of the dominant kernel (algorithmic bytes or flops of the
+method only), sampled parity against the FP64 oracle, the oracle's own
+throughput on a bounded pixel sample, labelled variants (kept pieces, the
+separate moment sum, FP16 moment images, a HIP-graph replay, the RGBA copy to
+the host), the batching configuration and the serving run.
 """
 from __future__ import annotations
 
@@ -18,6 +24,7 @@ import argparse
 import json
 import math
 import os
+import platform
 import sys
 import time
 
@@ -29,11 +36,12 @@ sys.path.insert(0, ROOT)
 METRIC = "ray samples/s + frames/s at 2560², m=8; p50/p99 frame latency (served)"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
-# algorithmic work per unit: FP64 flops of one sample's moment bound, bytes of one tet, vertex and piece
-FP64_FLOPS_PER_PIECE_M8 = 250.0   # per-sample moment bound at m = 8
+# algorithmic work per unit: FP64 flops of one sample's moment bound at m = 8, bytes of one tet and vertex
+FP64_FLOPS_PER_PIECE_M8 = 250.0
 TET_BYTES = 32.0                  # vertex ids + neighbour codes of one tet
 VERT_BYTES = 16.0                 # x, y, z, scalar
-STAGE_BYTES = 12.0                # one staged piece of stage two: z, a, s
+PIECE_BYTES = 12.0                # one kept piece: z, a, s
+N_CAMERAS = 5
 
 
 def log(msg):
@@ -59,111 +67,418 @@ def measured_traffic(args, kernel):
     b = rec["bytes_per_launch"].get(kernel)
     if b is None:
         return None, "kernel not in the counter record"
-    return int(b["fetch_bytes"] + b["write_bytes"]), "profiles/traffic_large_2560_m8.json (read %.3g B + write %.3g B)" % (
-        b["fetch_bytes"], b["write_bytes"])
+    return int(b["fetch_bytes"] + b["write_bytes"]), "%s (read %.3g B + write %.3g B)" % (
+        os.path.relpath(TRAFFIC_RECORD, ROOT), b["fetch_bytes"], b["write_bytes"])
 
 
-def batching_frames(sc, steps=3):
-    """Frames of the batching configuration (its adaptive mesh, 72 uneven subdomains, 2560^2, m = 8, stage one
-    summing the subdomains): two untimed frames (the first sizes the piece store), then `steps` timed ones."""
-    import torch
-    import paper_2501_12581_amd as apc
-    ctx = apc.Context(0)
-    r = apc.Renderer(ctx, sc)
-    for _ in range(2):
-        r.frame(fused=True)
-    torch.cuda.synchronize()
-    ctx.counters(reset=True)
-    stream = torch.cuda.current_stream()
-    t0 = time.perf_counter()
-    kern = {"moments_ms": 0.0, "eval_ms": 0.0, "stage_ms": 0.0}
-    for _ in range(steps):
-        r.frame(fused=True)
-        tk = ctx.timings()
-        for key in kern:
-            kern[key] += tk[key] / steps
-    stream.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / steps
-    cnt = ctx.counters()
-    walks = 1 if kern["stage_ms"] == 0.0 else 2
-    pieces = cnt["pieces"] / (walks * float(steps))
-    del r
-    ctx.close()
-    torch.cuda.synchronize()
-    torch.cuda.empty_cache()
-    out = {"workload": "batching: %d tets (32^3 base refined 0-3 levels, cone decomposition), 72 Morton subdomains "
-                       "of tet-count ratio 12, %dx%d perspective view, m=%d" % (
-                           sc.mesh.n_tets, sc.view["width"], sc.view["height"], sc.m),
-           "steps": steps, "ms_per_step": round(ms, 3), "frames_per_s": round(1e3 / ms, 3),
-           "samples_per_s": round(pieces / (ms / 1e3), 1), "samples_per_frame": int(pieces),
-           "kernels_ms": {k: round(v, 3) for k, v in kern.items()}}
-    log("batching frames: %s" % out)
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def host_threads():
+    """Threads for the oracle: the job's CPU share (OMP_NUM_THREADS where the host sets it, else the CPUs
+    this process may run on)."""
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        return int(env)
+    return len(os.sched_getaffinity(0))
+
+
+def camera_views(args, sc):
+    import synth
+    seed = {"large": synth.LARGE_SEED, "batching": synth.BATCHING_SEED}.get(args.workload)
+    if seed is None:  # the other workloads have one camera
+        return [sc.view]
+    W = sc.view["width"]
+    return [synth.orbit_view(seed, c, W) for c in range(N_CAMERAS)]
+
+
+class Frames:
+    """Frames of one renderer over a list of cameras, in the plain form unless `keep`."""
+
+    def __init__(self, r, ctx, views, global_sum=True, keep=False):
+        """views: camera dicts, or the apc_view structures of another Frames."""
+        import paper_2501_12581_amd as apc
+        self.r, self.ctx, self.global_sum, self.keep = r, ctx, global_sum, keep
+        self.views = [apc.make_view(v, r.scene.step) if isinstance(v, dict) else v for v in views]
+
+    def frame(self, c, **kw):
+        self.r.view = self.views[c]
+        return self.r.frame(global_sum=self.global_sum, keep=self.keep, **kw)
+
+    def survey(self):
+        """One untimed frame per camera (sizes the library's buffers): pieces, segment statistics and
+        (pixel, subdomain) pairs of every camera."""
+        import torch
+        out = []
+        for c in range(len(self.views)):
+            self.ctx.counters(reset=True)
+            self.frame(c)
+            torch.cuda.synchronize()
+            cnt = self.ctx.counters()
+            walks = 2 if self.ctx.timings()["rewalk_ms"] > 0 else 1
+            v = self.views[c]
+            segs = self.ctx.segment_counts(v.height, v.width).reshape(2, -1)
+            met = segs[1]
+            cov = met > 0
+            n_cov = int(cov.sum().item())
+            out.append({"pieces": cnt["pieces"] / walks, "tet_steps": cnt["tet_steps"] / walks,
+                        "pairs": int(met.sum().item()), "covered_pixels": n_cov,
+                        "segments_mean": segs[0][cov].double().mean().item() if n_cov else 0.0,
+                        "segments_max": int(segs[0].max().item()),
+                        "subdomains_met_mean": met[cov].double().mean().item() if n_cov else 0.0,
+                        "counters": cnt})
+        return out
+
+    def timed(self, steps, first=0):
+        """`steps` frames, camera (first + k) mod n for frame k, each timed from the host (the library's
+        HIP events are read after each frame, which waits for it)."""
+        import torch
+        keys = ("bin_ms", "moments_ms", "sum_ms", "resolve_ms", "rewalk_ms", "eval_ms")
+        kern = {k: [] for k in keys}
+        frame_ms, cams = [], []
+        stream = torch.cuda.current_stream()
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for k in range(steps):
+            c = (first + k) % len(self.views)
+            f0 = time.perf_counter()
+            self.frame(c)
+            tk = self.ctx.timings()
+            stream.synchronize()
+            frame_ms.append((time.perf_counter() - f0) * 1e3)
+            cams.append(c)
+            for key in keys:
+                kern[key].append(tk[key])
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+        per_cam = {}
+        for c, ms in zip(cams, frame_ms):
+            per_cam.setdefault(c, []).append(ms)
+        cam_mean = {c: float(np.mean(v)) for c, v in per_cam.items()}
+        return {"elapsed_s": elapsed, "frame_ms": frame_ms, "cameras": cams, "kernels": kern,
+                "camera_mean_ms": cam_mean, "median_camera_ms": float(np.median(list(cam_mean.values())))}
+
+
+def roofline_figures(mesh, m, H, W, survey, run):
+    """Per-kernel rooflines from the method's own work (algorithmic bytes and flops): stage one
+    reads each touched tet and vertex once and writes each (pixel, subdomain) pair's m+1 moments into the
+    sum plus the global image; stage two reads the mesh again and the global image and writes the colour;
+    its dominant cost is the moment bound, ~250 FP64 flops per piece at m = 8."""
+    mesh_bytes = mesh.n_tets * TET_BYTES + mesh.n_vertices * VERT_BYTES
+    cams, kern = run["cameras"], run["kernels"]
+    mom_bytes = sum(mesh_bytes + (survey[c]["pairs"] + H * W) * (m + 1) * 4.0 for c in cams)
+    res_bytes = sum(mesh_bytes + H * W * ((m + 1) * 4.0 + 16.0) for c in cams)
+    flops = sum(FP64_FLOPS_PER_PIECE_M8 * survey[c]["pieces"] for c in cams) if m == 8 else None
+    t_mom = sum(kern["moments_ms"]) / 1e3
+    t_res = sum(kern["rewalk_ms"]) / 1e3
+    n = len(cams)
+    out = {
+        "k_moments": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS, "kernel_ms": 1e3 * t_mom / n,
+                      "achieved": mom_bytes / t_mom / 1e9,
+                      "work_per_launch": "mesh %.3g B (each tet 32 B + each vertex 16 B) + (pairs + pixels) x "
+                                         "(m+1) x 4 B moments, %.3g B on average" % (mesh_bytes, mom_bytes / n)},
+    }
+    if t_res > 0 and flops is not None:
+        out["k_resolve"] = {"bound": "alu", "unit": "TFLOP/s", "peak": FP64_PEAK_TFLOPS, "kernel_ms": 1e3 * t_res / n,
+                            "achieved": flops / t_res / 1e12,
+                            "work_per_launch": "%d FP64 flops x %.4g pieces (moment bound per piece, m = 8)" % (
+                                FP64_FLOPS_PER_PIECE_M8, flops / n / FP64_FLOPS_PER_PIECE_M8),
+                            "hbm_view": {"achieved_gbs": res_bytes / t_res / 1e9,
+                                         "frac": res_bytes / t_res / 1e9 / HBM_PEAK_GBS,
+                                         "bytes_per_launch": res_bytes / n}}
+    for v in out.values():
+        v["frac"] = v["achieved"] / v["peak"]
     return out
 
 
-def serve_run(n_requests, slots=4, workspace_limit=40 << 30, small_slots=0, small_workspace_limit=12 << 30,
-              sc=None):
-    """p50/p99 frame latency of a served request stream, batched (`slots` slots for any size and `small_slots`
-    for sizes up to 1024^2) and one at a time, on the batching configuration's mesh (`sc`, else generated)."""
+def oracle_leg(args, sc, r, ctx, survey0, rgba_cam0, mom_cam0, kept_rgba0):
+    """Sampled parity (camera 0) and the oracle's throughput on the same sample."""
+    import torch
+    import oracle
+    import synth
+    from oracle.parity import moment_parity
+    H, W, m = sc.view["height"], sc.view["width"], sc.m
+    dev = rgba_cam0.device
+    pix = np.sort(np.random.default_rng(11).choice(H * W, min(args.cpu_pixels, H * W), replace=False))
+    threads = host_threads()
+    log("oracle on %d sampled pixels with %d threads" % (len(pix), threads))
+    t0 = time.perf_counter()
+    ref = oracle.render(sc, pixels=pix, threads=threads)
+    cpu_s = time.perf_counter() - t0
+    rate = ref["n_pieces"] / cpu_s
+    idx = torch.as_tensor(pix, device=dev)
+    mom = mom_cam0.reshape(m + 1, -1)[:, idx].double().cpu().numpy()
+    rgba = rgba_cam0.reshape(-1, 4)[idx].double().cpu().numpy()
+    mp = moment_parity(sc, pix, mom, ref, tol=1e-5, floor=1e-3, threads=threads)
+    d = rgba - ref["rgba"]
+    parity = {"pixels": int(len(pix)), "camera": 0, "covered": mp["covered"],
+              "background_exact": mp["background_exact"],
+              "moments_rel_forward": {k: mp[k] for k in ("forward_max", "forward_p50", "forward_p99", "forward_p999")},
+              "moments_backward_bar_pixels": mp["backward_bar_pixels"],
+              "moments_outside_backward_band": mp["outside_backward_band"],
+              "rgba_max_abs": float(np.abs(d).max()), "rgba_rmse": float(math.sqrt(np.mean(d ** 2)))}
+    if kept_rgba0 is not None:
+        dk = kept_rgba0.reshape(-1, 4)[idx].double().cpu().numpy() - ref["rgba"]
+        parity["kept_pieces_rgba_max_abs"] = float(np.abs(dk).max())
+        parity["kept_pieces_rgba_rmse"] = float(math.sqrt(np.mean(dk ** 2)))
+    log("parity %s" % parity)
+    # the tiny workload's full frame on one thread, and on the job's threads
+    tiny = synth.scene_tiny()
+    t0 = time.perf_counter()
+    rt = oracle.render(tiny, threads=1)
+    tiny_1 = time.perf_counter() - t0
+    cpu = {"value": round(rate, 1), "unit": "samples/s", "cores": threads, "kind": "oracle",
+           "sample": "%d seeded pixels of the same %dx%d frame, camera 0 (%d samples, both passes, %.1f s)" % (
+               len(pix), W, H, ref["n_pieces"], cpu_s),
+           "nproc": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0)), "cpu_model": cpu_model(),
+           "extrapolated_s_per_frame": round(survey0["pieces"] / rate, 1),
+           "extrapolated_note": "camera 0's samples per frame / the sample's samples/s (extrapolated, not run)",
+           "tiny_full_frame_1_thread_s": round(tiny_1, 3), "tiny_samples": int(rt["n_pieces"])}
+    return ref, pix, parity, cpu
+
+
+def apc_vs_exact(threads):
+    """The method against exact sorted compositing of the same pieces (a report, not a bar): the tiny
+    workload in full and the medium workload on a seeded pixel sample."""
+    import oracle
+    import synth
+    out = {}
+    for name, sc, pix in (("tiny_128", synth.scene_tiny(), None),
+                          ("medium_1024_sampled", synth.scene_medium(), np.sort(
+                              np.random.default_rng(5).choice(1024 * 1024, 16384, replace=False)))):
+        ref = oracle.render(sc, pixels=pix, exact=True, threads=threads)
+        d = ref["rgba"] - ref["exact"]
+        mse = float(np.mean(d ** 2))
+        out[name] = {"pixels": int(ref["rgba"].shape[0]), "max_abs": float(np.abs(d).max()),
+                     "rmse": math.sqrt(mse), "psnr_db": 10 * math.log10(1.0 / mse) if mse > 0 else None,
+                     "mean_alpha_apc": float(ref["rgba"][:, 3].mean()),
+                     "mean_alpha_exact": float(ref["exact"][:, 3].mean())}
+    return out
+
+
+def variants_leg(args, sc, r, ctx, fr, survey, rgba0, mom0):
+    """Labelled variants of the same frames: kept pieces (stage one keeps every piece, stage two evaluates
+    them without walking again), the separate moment sum (per-subdomain images + apc_sum_moments, the form
+    several GPUs would run), FP16 moment images, a HIP-graph replay of the frame, and the frame with the
+    RGBA image copied to host memory."""
+    import torch
+    import paper_2501_12581_amd as apc
+    out = {}
+    n_cam = len(fr.views)
+    # kept pieces, every camera: a sizing frame, then a timed one
+    kf = Frames(r, ctx, fr.views, keep=True)
+    kept_ms, kern = [], {"moments_ms": [], "eval_ms": []}
+    kept0 = None
+    for c in range(n_cam):
+        kf.frame(c)
+        torch.cuda.synchronize()
+        f0 = time.perf_counter()
+        kf.frame(c)
+        tk = ctx.timings()
+        torch.cuda.synchronize()
+        kept_ms.append((time.perf_counter() - f0) * 1e3)
+        kern["moments_ms"].append(tk["moments_ms"])
+        kern["eval_ms"].append(tk["eval_ms"])
+        if c == 0:
+            kept0 = r.rgba.clone()
+    kept_pieces = float(np.mean([s["pieces"] for s in survey]))
+    out["kept_pieces"] = {
+        "frame_ms_by_camera": [round(x, 2) for x in kept_ms], "median_frame_ms": round(float(np.median(kept_ms)), 3),
+        "frames_per_s": round(1e3 / float(np.median(kept_ms)), 4),
+        "kernels_ms_mean": {k: round(float(np.mean(v)), 3) for k, v in kern.items()},
+        "piece_store_bytes_per_frame": kept_pieces * PIECE_BYTES,
+        "rgba_max_abs_vs_plain_camera0": float((kept0 - rgba0).abs().max().item())}
+    ctx.set_workspace_limit(1 << 20)  # gives the pool back
+    ctx.set_workspace_limit(0)
+    log("kept pieces %s" % out["kept_pieces"])
+    # the separate moment sum (camera 0)
+    sf = Frames(r, ctx, fr.views, global_sum=False)
+    other = []
+    for _ in range(2):
+        f0 = time.perf_counter()
+        sf.frame(0)
+        tk = ctx.timings()
+        torch.cuda.synchronize()
+        other.append(((time.perf_counter() - f0) * 1e3, tk["moments_ms"], tk["sum_ms"]))
+    out["separate_sum"] = {"frame_ms": round(other[-1][0], 2), "moments_ms": round(other[-1][1], 3),
+                           "sum_ms": round(other[-1][2], 3),
+                           "global_moments_bitwise_equal": bool(torch.equal(r.moments, mom0)),
+                           "rgba_bitwise_equal": bool(torch.equal(r.rgba, rgba0))}
+    r._per_sub = None
+    torch.cuda.empty_cache()
+    log("separate sum %s" % out["separate_sum"])
+    # FP16 moment images (camera 0); their error against the oracle is added by the oracle leg
+    fr.frame(0, moments_f16=True)
+    torch.cuda.synchronize()
+    out["fp16_moments"] = {"moment_image_bytes": int(r.moments_h.numel() * 2),
+                           "fp32_moment_image_bytes": int(r.moments.numel() * 4)}
+    rgba16 = r.rgba.clone()
+    # HIP graph of the plain frame (camera 0): replays timed with events on the current stream
+    r.view = fr.views[0]
+    g = apc.FrameGraph(r, global_sum=True)
+    try:
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        g.launch()
+        torch.cuda.synchronize()
+        reps = 3
+        e0.record(stream)
+        for _ in range(reps):
+            g.launch()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out["graph_replay"] = {"ms_per_frame": round(e0.elapsed_time(e1) / reps, 3),
+                               "rgba_bitwise_equal_to_eager": bool(torch.equal(r.rgba, rgba0))}
+    finally:
+        g.close()
+    # the frame with its image copied to pinned host memory (camera 0)
+    host = torch.empty(r.rgba.shape, dtype=torch.float32, pin_memory=True)
+    d2h = []
+    for _ in range(3):
+        f0 = time.perf_counter()
+        fr.frame(0)
+        host.copy_(r.rgba, non_blocking=True)
+        torch.cuda.synchronize()
+        d2h.append((time.perf_counter() - f0) * 1e3)
+    out["with_rgba_d2h"] = {"frame_ms": round(float(np.median(d2h)), 3), "rgba_bytes": int(r.rgba.numel() * 4)}
+    log("variants %s" % {k: out[k] for k in ("fp16_moments", "graph_replay", "with_rgba_d2h")})
+    return out, kept0, rgba16
+
+
+def batching_leg(bsc, steps=5):
+    """The batching configuration (adaptive mesh, 72 uneven subdomains, 2560^2, m = 8): the autotuned tile
+    shape, plain frames over the 5 orbit cameras, the kept-piece variant, and a HIP-graph replay of the
+    plain frame against the eager one."""
+    import torch
+    import paper_2501_12581_amd as apc
+    import synth
+    ctx = apc.Context(0)
+    r = apc.Renderer(ctx, bsc)
+    best, ms = ctx.autotune_tile_shape(r.mesh, r.view, r.tf, r.mboit, r.subs, r.moments, r.rgba, repeats=1)
+    views = [synth.orbit_view(synth.BATCHING_SEED, c, bsc.view["width"]) for c in range(N_CAMERAS)]
+    fr = Frames(r, ctx, views)
+    survey = fr.survey()
+    run = fr.timed(steps)
+    pieces = [survey[c]["pieces"] for c in run["cameras"]]
+    out = {"workload": "batching: %d tets (32^3 base refined 0-3 levels, cone decomposition), 72 Morton subdomains "
+                       "of tet-count ratio 12, %dx%d perspective views (5 orbit cameras), m=%d" % (
+                           bsc.mesh.n_tets, bsc.view["width"], bsc.view["height"], bsc.m),
+           "autotune": {"best_width": best, "frame_ms_by_width": {str(k): round(v, 3) for k, v in ms.items()}},
+           "steps": steps, "ms_per_step": round(run["elapsed_s"] * 1e3 / steps, 3),
+           "median_camera_frame_ms": round(run["median_camera_ms"], 3),
+           "frames_per_s": round(1e3 / run["median_camera_ms"], 3),
+           "samples_per_s": round(sum(pieces) / run["elapsed_s"], 1),
+           "kernels_ms_mean": {k: round(float(np.mean(v)), 3) for k, v in run["kernels"].items()}}
+    # kept pieces (camera 0) and the graph of the plain frame (camera 0)
+    kf = Frames(r, ctx, views, keep=True)
+    for _ in range(2):
+        f0 = time.perf_counter()
+        kf.frame(0)
+        torch.cuda.synchronize()
+    out["kept_pieces_frame_ms_camera0"] = round((time.perf_counter() - f0) * 1e3, 3)
+    ctx.set_workspace_limit(1 << 20)
+    ctx.set_workspace_limit(0)
+    eager = []
+    for _ in range(3):
+        f0 = time.perf_counter()
+        fr.frame(0)
+        torch.cuda.synchronize()
+        eager.append((time.perf_counter() - f0) * 1e3)
+    rgba0 = r.rgba.clone()
+    r.view = fr.views[0]
+    g = apc.FrameGraph(r, global_sum=True)
+    try:
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        g.launch()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(3):
+            g.launch()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out["camera0_eager_frame_ms"] = round(float(np.median(eager)), 3)
+        out["camera0_graph_replay_ms"] = round(e0.elapsed_time(e1) / 3, 3)
+        out["graph_rgba_bitwise_equal"] = bool(torch.equal(r.rgba, rgba0))
+    finally:
+        g.close()
+    del fr, kf, r
+    ctx.close()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    log("batching %s" % out)
+    return out
+
+
+def serve_leg(n_requests, n_requests_30, sc):
+    """p50/p99 frame latency of a served request stream on the batching configuration's mesh: batched
+    (continuous batching over slots) against one request at a time, both in the plain form."""
     import synth
     from paper_2501_12581_amd.serve import Server
     t0 = time.time()
-    if sc is None:
-        sc = synth.scene_batching(size=1024)
     m = sc.mesh
     tfs = [synth.make_tf(s) for s in (21, 22, 23)]
-    srv = Server((m.xyz, m.scalar, m.tets, m.tet_sub, m.n_sub), sc.step, tfs, (sc.s_min, sc.s_max), slots=slots,
-                 workspace_limit=workspace_limit, hbm_budget=64 << 30, small_slots=small_slots, small_size=1024,
-                 small_workspace_limit=small_workspace_limit)
-    srv.warm()  # every slot's library buffers at the largest request's size before serving
-    log("serving: %d tets (adaptive), 72 uneven subdomains, generated, resident and warm in %.1fs" % (
-        m.n_tets, time.time() - t0))
+    srv = Server((m.xyz, m.scalar, m.tets, m.tet_sub, m.n_sub), sc.step, tfs, (sc.s_min, sc.s_max), slots=4,
+                 hbm_budget=16 << 30)
+    srv.warm()
+    log("serving: %d tets, resident and warm in %.1fs" % (m.n_tets, time.time() - t0))
     warm = synth.request_stream(8, rate=1000.0, seed=99)
     srv.run(warm, "batched")
     srv.run(warm, "fifo")
     res = {}
-    for rate in (50.0, 30.0):  # the specified rate, and one below what this GPU sustains for this mix
-        reqs = synth.request_stream(n_requests, rate=rate, seed=12)
+    for rate, n in ((50.0, n_requests), (30.0, n_requests_30)):
+        if n <= 0:
+            continue
+        reqs = synth.request_stream(n, rate=rate, seed=12)
         for mode in ("batched", "fifo"):
             st = srv.run(reqs, mode)
             st.pop("records")
             res["%s_%g" % (mode, rate)] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
             log("serving %g/s %s: %s" % (rate, mode, res["%s_%g" % (mode, rate)]))
     srv.close()
-    return {"workload": "batching mesh: %d tets (32^3 base refined 0-3 levels, cone decomposition), 72 Morton "
-                        "subdomains of tet-count ratio 12; "
-                        "%d requests per run, Poisson arrivals, sizes {256,512,1024,2048}^2, m in {4,6,8}, "
-                        "3 transfer functions, cameras on the radius-2 sphere" % (m.n_tets, n_requests),
-            "rate_50_per_s": {"batched": res["batched_50"], "one_at_a_time": res["fifo_50"]},
-            "rate_30_per_s": {"batched": res["batched_30"], "one_at_a_time": res["fifo_30"]}}
+    out = {"workload": "batching mesh: %d tets, 72 Morton subdomains of tet-count ratio 12; Poisson arrivals, sizes "
+                       "{256,512,1024,2048}^2, m in {4,6,8}, 3 transfer functions, cameras on the radius-2 sphere; "
+                       "plain form (stage two walks again)" % m.n_tets}
+    for rate in (50, 30):
+        if "batched_%d" % rate in res:
+            out["rate_%d_per_s" % rate] = {"batched": res["batched_%d" % rate], "one_at_a_time": res["fifo_%d" % rate]}
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="large", choices=["large", "batching", "medium", "tiny", "slabs"])
     ap.add_argument("--ranks", type=int, default=16, help="slabs workload: subdomains (4 slabs each)")
     ap.add_argument("--m", type=int, default=None, help="override the number of moments (4, 6, 8)")
     ap.add_argument("--tile-width", type=int, default=None, help="pixels per tile row (tile = w x 64/w)")
-    ap.add_argument("--autotune", action="store_true",
-                    help="pick the tile shape with the autotuner first (on by default for the batching workload)")
+    ap.add_argument("--autotune", action="store_true", help="pick the tile shape with the autotuner first")
     ap.add_argument("--size", type=int, default=None, help="override the image size (square)")
     ap.add_argument("--grid", type=int, default=None, help="override cubes per axis (large workload)")
+    ap.add_argument("--keep", action="store_true",
+                    help="time the kept-piece variant (stage one keeps every piece for stage two) instead of the "
+                         "plain form")
     ap.add_argument("--cpu-pixels", type=int, default=65536, help="oracle sample size (0 = skip)")
-    ap.add_argument("--profile-steps", action="store_true", help="no oracle leg and no serving run (for profiler runs)")
-    ap.add_argument("--separate-sum", action="store_true",
-                    help="time frames with per-subdomain moment images + apc_sum_moments (the form several GPUs "
-                         "would run) instead of stage one summing the subdomains itself")
-    ap.add_argument("--serve-requests", type=int, default=120,
-                    help="requests of the serving run (Poisson, 50/s, batching mesh); 0 = skip")
+    ap.add_argument("--profile-steps", action="store_true",
+                    help="only the timed frames (no variants, oracle, batching or serving legs; for profiler runs)")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="requests per mode of the 50/s serving run (batching mesh); 0 = no serving")
+    ap.add_argument("--serve-requests-30", type=int, default=600, help="requests per mode at 30/s")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (scales the HBM byte counters of a profiler run)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: the multi-GPU path (subdomains sharded over GPUs with an "
-              "all-reduce of the moment image) is not implemented; run with --gpus 1", file=sys.stderr)
+        print("bench.py runs on exactly one GPU (every subdomain of the frame on one device); a run on %d GPUs "
+              "is not available" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -213,151 +528,80 @@ def main():
     info = r.mesh.info()
     log("mesh resident in %.1fs: %d boundary faces, %.2f GB" % (
         time.time() - t0, info["n_boundary_faces"], info["device_bytes"] / 1e9))
-
     tuned = None
     if args.tile_width:
         ctx.set_tile_shape(args.tile_width)
-    if args.autotune or (args.workload == "batching" and not args.tile_width):
+    if args.autotune:
         best, ms = ctx.autotune_tile_shape(r.mesh, r.view, r.tf, r.mboit, r.subs, r.moments, r.rgba, repeats=1)
         tuned = {"best_width": best, "frame_ms_by_width": {str(k): round(v, 3) for k, v in ms.items()}}
         log("autotuned tile: %s" % tuned)
-    fused = not args.separate_sum  # one GPU holds every subdomain: stage one sums them (APC_MOMENTS_GLOBAL)
-    for _ in range(args.warmup):
-        r.frame(fused=fused)
+
+    views = camera_views(args, sc)
+    fr = Frames(r, ctx, views, keep=args.keep)
+    survey = fr.survey()  # one untimed frame per camera
+    rgba0, mom0 = None, None
+    for k in range(args.warmup):
+        fr.frame(k % len(views))
     torch.cuda.synchronize()
-    log("warmup done")
+    log("survey + %d warm-up frames done" % args.warmup)
     ctx.counters(reset=True)
-    kern = {"bin_ms": 0.0, "moments_ms": 0.0, "sum_ms": 0.0, "resolve_ms": 0.0, "stage_ms": 0.0, "eval_ms": 0.0}
-    stream = torch.cuda.current_stream()
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    frame_ms = []
-    for k in range(args.steps):
-        f0 = time.perf_counter()
-        r.frame(fused=fused)
-        # the library records HIP events around each kernel on this stream; reading them waits for the frame
-        tk = ctx.timings()
-        stream.synchronize()
-        frame_ms.append((time.perf_counter() - f0) * 1e3)
-        for key in kern:
-            kern[key] += tk[key]
-        log("step %d: %.1f ms (moments %.1f, resolve %.1f = re-walk %.1f + evaluation %.1f)" % (
-            k, frame_ms[-1], tk["moments_ms"], tk["resolve_ms"], tk["stage_ms"], tk["eval_ms"]))
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    tile_shape = list(ctx.tile_shape())
-    ms_per_step = elapsed * 1e3 / args.steps
+    run = fr.timed(args.steps)
     cnt = ctx.counters()
-    walks = 1 if kern["stage_ms"] == 0.0 else 2  # stage two walks again unless stage one kept the pieces
-    pieces_per_frame = cnt["pieces"] / (walks * float(args.steps))   # every walk counts its pieces
-    steps_per_frame = cnt["tet_steps"] / (walks * float(args.steps))
-    for key in kern:
-        kern[key] /= args.steps
-    samples_per_s = pieces_per_frame / (ms_per_step / 1e3)
-
-    # ---- segments per pixel (what a sort-last compositor would exchange) vs APC's fixed exchange
-    segs = ctx.segment_counts(r.view.height, r.view.width).reshape(2, -1)
-    met = segs[1]
-    cov = met > 0
-    n_cov = int(cov.sum().item())
-    seg_stats = {"covered_pixels": n_cov,
-                 "segments_mean": round(segs[0][cov].double().mean().item(), 4) if n_cov else 0.0,
-                 "segments_max": int(segs[0].max().item()),
-                 "subdomains_met_mean": round(met[cov].double().mean().item(), 4) if n_cov else 0.0,
-                 "apc_exchanged_per_pixel_mean": round(2.0 * met[cov].double().mean().item(), 4) if n_cov else 0.0,
-                 "apc_exchanged_upper_bound": 2 * mesh.n_sub}
-
-    # ---- roofline of the dominant kernel
+    tile_shape = list(ctx.tile_shape())
     H, W, m = r.view.height, r.view.width, sc.m
-    S = mesh.n_sub
-    mesh_bytes = mesh.n_tets * TET_BYTES + mesh.n_vertices * VERT_BYTES
-    pairs = int(met.sum().item())  # (pixel, subdomain) pairs with pieces
-    if fused:  # each pair's moments enter the sum once; the global image is written once
-        mom_bytes = (pairs + H * W) * (m + 1) * 4.0
-        mom_label = "per-pair moments + global image"
-    else:  # the API's dense per-subdomain images
-        mom_bytes = S * (m + 1) * H * W * 4.0
-        mom_label = "dense per-subdomain moments"
-    kept = kern["stage_ms"] == 0.0  # stage one kept its pieces: no second walk
-    kept_bytes = pieces_per_frame * STAGE_BYTES if kept else 0.0
-    rooflines = {
-        "k_moments": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
-                      "achieved": (mesh_bytes + mom_bytes + kept_bytes) / (kern["moments_ms"] / 1e3) / 1e9,
-                      "per_launch": "mesh %.3g B + %s %.3g B + kept pieces %.3g B" % (
-                          mesh_bytes, mom_label, mom_bytes, kept_bytes)},
-        "k_stage": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
-                    "achieved": (mesh_bytes + pieces_per_frame * STAGE_BYTES) / (max(kern["stage_ms"], 1e-9) / 1e3) / 1e9,
-                    "per_launch": "mesh %.3g B + staged pieces %.3g B" % (mesh_bytes, pieces_per_frame * STAGE_BYTES)},
-        "k_eval": {"bound": "alu", "unit": "TFLOP/s", "peak": FP64_PEAK_TFLOPS,
-                   "achieved": FP64_FLOPS_PER_PIECE_M8 * pieces_per_frame / (kern["eval_ms"] / 1e3) / 1e12,
-                   "per_launch": "%d FP64 flops x %.4g pieces" % (FP64_FLOPS_PER_PIECE_M8, pieces_per_frame)},
-    }
-    timed = {"k_moments": kern["moments_ms"], "k_stage": kern["stage_ms"], "k_eval": kern["eval_ms"]}
-    if kept:
-        del rooflines["k_stage"], timed["k_stage"]
+    samples = sum(survey[c]["pieces"] for c in run["cameras"])
+    samples_per_s = samples / run["elapsed_s"]
+    ms_per_step = run["elapsed_s"] * 1e3 / args.steps
+    for k in range(args.steps):
+        log("step %d (camera %d): %.1f ms (moments %.1f, re-walk %.1f, evaluation %.1f)" % (
+            k, run["cameras"][k], run["frame_ms"][k], run["kernels"]["moments_ms"][k], run["kernels"]["rewalk_ms"][k],
+            run["kernels"]["eval_ms"][k]))
+    kern_mean = {k: round(float(np.mean(v)), 3) for k, v in run["kernels"].items()}
+
+    rooflines = roofline_figures(mesh, m, H, W, survey, run)
+    timed = {k: v["kernel_ms"] for k, v in rooflines.items()}
     dom = max(timed, key=timed.get)
     rf = rooflines[dom]
     traffic, traffic_note = measured_traffic(args, dom)
-    roofline = {"kernel": dom, "kernel_ms": round(timed[dom], 3), "bound": rf["bound"], "achieved": round(rf["achieved"], 4), "peak": rf["peak"],
-                "unit": rf["unit"], "frac": round(rf["achieved"] / rf["peak"], 5), "traffic": traffic,
-                "traffic_source": traffic_note,
-                "work_per_launch": rf["per_launch"],
-                "other": {k: {"bound": v["bound"], "achieved": round(v["achieved"], 4), "unit": v["unit"],
-                              "frac": round(v["achieved"] / v["peak"], 5)} for k, v in rooflines.items()
-                          if k != dom}}
+    algo_bytes = None
+    if rf["bound"] == "hbm":
+        algo_bytes = rf["achieved"] * 1e9 * rf["kernel_ms"] / 1e3
+    roofline = {"kernel": dom, "kernel_ms": round(rf["kernel_ms"], 3), "bound": rf["bound"],
+                "achieved": round(rf["achieved"], 4), "peak": rf["peak"], "unit": rf["unit"],
+                "frac": round(rf["frac"], 5), "traffic": traffic, "traffic_source": traffic_note,
+                "traffic_over_algorithmic": round(traffic / algo_bytes, 2) if (traffic and algo_bytes) else None,
+                "work_per_launch": rf["work_per_launch"],
+                "other": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                          for k, v in rooflines.items() if k != dom}}
 
-    # ---- sampled parity + CPU baseline (FP64 oracle on a bounded pixel sample)
-    cpu = None
-    parity = None
-    variants = None
-    if args.cpu_pixels > 0 and not args.profile_steps:
-        import oracle
-        pix = np.sort(np.random.default_rng(11).choice(H * W, min(args.cpu_pixels, H * W), replace=False))
-        threads = min(16, os.cpu_count() or 1)  # the host share of one GPU
-        log("oracle on %d sampled pixels with %d threads" % (len(pix), threads))
-        t0 = time.perf_counter()
-        ref = oracle.render(sc, pixels=pix, threads=threads)
-        cpu_s = time.perf_counter() - t0
-        cpu = {"value": round(ref["n_pieces"] / cpu_s, 1), "unit": "samples/s", "cores": threads, "kind": "oracle",
-               "sample": "%d seeded pixels of the same %dx%d frame (%d samples, both passes, %.1f s)" % (
-                   len(pix), W, H, ref["n_pieces"], cpu_s)}
-        mom = r.moments.reshape(m + 1, -1)[:, torch.as_tensor(pix, device=dev)].double().cpu().numpy()
-        rgba = r.rgba.reshape(-1, 4)[torch.as_tensor(pix, device=dev)].double().cpu().numpy()
-        from oracle.parity import moment_parity
-        mp = moment_parity(sc, pix, mom, ref, tol=1e-5, floor=1e-3, threads=threads)
-        d = rgba - ref["rgba"]
-        parity = {"pixels": int(len(pix)), "covered": mp["covered"], "background_exact": mp["background_exact"],
-                  "moments_rel_max_forward": mp["forward_max"],
-                  "moments_backward_bar_pixels": mp["backward_bar_pixels"],
-                  "moments_outside_backward_band": mp["outside_backward_band"],
-                  "rgba_max_abs": float(np.abs(d).max()), "rgba_rmse": float(math.sqrt(np.mean(d ** 2)))}
-        log("parity %s" % parity)
-        # FP16 moment-image variant (ln b0, b_j / b0), run after the timed frames on the same sample
-        mom_timed = r.moments.clone()
-        r.frame(moments_f16=True, fused=fused)
-        rgba16 = r.rgba.reshape(-1, 4)[torch.as_tensor(pix, device=dev)].double().cpu().numpy()
-        d16 = rgba16 - ref["rgba"]
-        variants = {"fp16_moments": {
-            "rgba_max_abs": float(np.abs(d16).max()), "rgba_rmse": float(math.sqrt(np.mean(d16 ** 2))),
-            "moment_image_bytes": int(r.moments_h.numel() * 2), "fp32_moment_image_bytes": int(r.moments.numel() * 4)}}
-        # the other form of stage one + sum: its frames' time and whether its global moments are bitwise equal
-        other = []
-        for _ in range(2):
-            f0 = time.perf_counter()
-            r.frame(fused=not fused)
-            tk = ctx.timings()
-            torch.cuda.synchronize()
-            other.append(((time.perf_counter() - f0) * 1e3, tk["moments_ms"], tk["sum_ms"]))
-        variants["separate_sum" if fused else "fused_sum"] = {
-            "frame_ms": round(other[-1][0], 2), "moments_ms": round(other[-1][1], 3),
-            "sum_ms": round(other[-1][2], 3) if fused else 0.0,
-            "global_moments_bitwise_equal": bool(torch.equal(r.moments, mom_timed))}
-        log("variants %s" % variants)
+    seg_stats = {k: round(float(np.mean([s[k] for s in survey])), 4)
+                 for k in ("covered_pixels", "segments_mean", "subdomains_met_mean")}
+    seg_stats["segments_max"] = int(max(s["segments_max"] for s in survey))
+    seg_stats["apc_exchanged_per_pixel_mean"] = round(2.0 * seg_stats["subdomains_met_mean"], 4)
+    seg_stats["apc_exchanged_upper_bound"] = 2 * mesh.n_sub
 
-    # ---- serving: continuous batching vs one request at a time (after the frame buffers are released)
-    serving = batching = None
-    if args.serve_requests > 0 and not args.profile_steps:
-        del r
+    cpu = parity = variants = None
+    exact_report = None
+    if not args.profile_steps:
+        fr.frame(0)
+        torch.cuda.synchronize()
+        rgba0, mom0 = r.rgba.clone(), r.moments.clone()
+        kept0 = rgba16 = None
+        if not args.keep:
+            variants, kept0, rgba16 = variants_leg(args, sc, r, ctx, fr, survey, rgba0, mom0)
+        if args.cpu_pixels > 0:
+            sc0 = synth.Scene(**{**sc.__dict__, "view": views[0]})
+            ref, pix, parity, cpu = oracle_leg(args, sc0, r, ctx, survey[0], rgba0, mom0, kept0)
+            if rgba16 is not None:
+                d16 = rgba16.reshape(-1, 4)[torch.as_tensor(pix, device=dev)].double().cpu().numpy() - ref["rgba"]
+                variants["fp16_moments"].update(rgba_max_abs=float(np.abs(d16).max()),
+                                                rgba_rmse=float(math.sqrt(np.mean(d16 ** 2))))
+            exact_report = apc_vs_exact(host_threads())
+            log("APC vs exact compositing %s" % exact_report)
+
+    batching = serving = None
+    if not args.profile_steps and (args.serve_requests > 0 or args.workload != "batching"):
+        del r, fr
         import gc
         gc.collect()
         ctx.close()
@@ -366,30 +610,35 @@ def main():
         t0 = time.time()
         bsc = synth.scene_batching() if args.workload != "batching" else sc
         log("batching mesh: %d tets in %.1fs" % (bsc.mesh.n_tets, time.time() - t0))
-        if args.workload != "batching":  # the batching configuration's frames, beside the headline workload's
-            batching = batching_frames(bsc)
-        serving = serve_run(args.serve_requests, sc=bsc)
+        if args.workload != "batching":
+            batching = batching_leg(bsc)
+        if args.serve_requests > 0:
+            serving = serve_leg(args.serve_requests, args.serve_requests_30, bsc)
 
     out = {
         "metric": METRIC, "value": round(samples_per_s, 1), "unit": "samples/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "%s: %d tets (%s), %d %s subdomains, %dx%d %s view, m=%d" % (
+        "config": {"workload": "%s: %d tets (%s), %d %s subdomains, %dx%d %s view%s, m=%d, %s" % (
             sc.name, mesh.n_tets, "adaptive: 32^3 base refined 0-3 levels, cone decomposition"
-            if args.workload == "batching" else "jittered Kuhn grid", S,
+            if args.workload == "batching" else "jittered Kuhn grid", mesh.n_sub,
             {"slabs": "interleaved-slab (4 slabs each)", "batching": "Morton (tet-count ratio 12)"}.get(
                 args.workload, "Morton"),
-            W, H, "perspective" if sc.view["projection"] else "orthographic", m),
+            W, H, "perspective" if sc.view["projection"] else "orthographic",
+            "s (%d orbit cameras)" % len(views) if len(views) > 1 else "", m,
+            "kept-piece variant" if args.keep else "plain form: stage two walks the rays again"),
             "global_batch": 1, "seq_len": None, "parallelism": "single GPU, all subdomains on device"},
-        "frames_per_s": round(1e3 / ms_per_step, 4),
-        "samples_per_frame": int(pieces_per_frame), "tet_steps_per_frame": int(steps_per_frame),
-        "kernels_ms": {k: round(v, 3) for k, v in kern.items()},
-        "stage_one_sums_subdomains": fused,
-        "frame_ms_each": [round(x, 2) for x in frame_ms],
+        "frames_per_s": round(1e3 / run["median_camera_ms"], 4),
+        "frames_per_s_definition": "1 / median over the cameras of their mean frame time (RGBA stays on the device)",
+        "camera_mean_frame_ms": {str(c): round(v, 3) for c, v in sorted(run["camera_mean_ms"].items())},
+        "samples_per_frame_by_camera": [int(s["pieces"]) for s in survey],
+        "tet_steps_per_frame_by_camera": [int(s["tet_steps"]) for s in survey],
+        "kernels_ms": kern_mean,
+        "frame_ms_each": [round(x, 2) for x in run["frame_ms"]],
         "tile_shape": tile_shape, "autotune": tuned,
-        "segments": seg_stats, "counters": cnt, "roofline": roofline, "cpu_baseline": cpu, "parity": parity, "variants": variants,
-        "batching": batching, "serving": serving,
+        "segments": seg_stats, "counters": cnt, "roofline": roofline, "cpu_baseline": cpu, "parity": parity,
+        "apc_vs_exact_compositing": exact_report, "variants": variants, "batching": batching, "serving": serving,
     }
     print(json.dumps(out), flush=True)
 

@@ -187,20 +187,23 @@ typedef struct apc_mboit {
  *   moments_per_sub device [n_sub][m+1][H][W] FP32, fully written (zero where
  *                   subdomain k is not hit)
  * m is 4, 6 or 8.
- * The pieces are also kept in context-owned device memory (12 bytes per
- * piece in chunks of 64, grown after a frame that did not fit) so that
- * apc_resolve_pass of the same geometry, camera, transfer function and
- * subdomain list evaluates them without walking the rays again; when they
- * were not all kept it walks again (same pieces, same result).
- * flags: 0, or APC_REWALK: keep no pieces (stage two walks again), and/or
- * APC_MOMENTS_GLOBAL: the listed subdomains are all that the frame has and
- * stage one sums them itself: `moments_per_sub` is then the global image
- * device [m+1][H][W] FP32, bitwise what apc_sum_moments returns for the
- * per-subdomain images of the same call (each subdomain's FP32 value added
- * in FP64 in ascending subdomain-id order).  The ids must be listed in
- * ascending order (APC_E_ARG otherwise).  Needs an FP64 accumulator of
- * 8*(m+1)*H*W bytes in context-owned device memory; the per-subdomain images
- * are never formed. */
+ * flags: 0, or any of
+ *   APC_MOMENTS_GLOBAL: the listed subdomains are all that the frame has and
+ *     stage one sums them itself: `moments_per_sub` is then the global image
+ *     device [m+1][H][W] FP32, bitwise what apc_sum_moments returns for the
+ *     per-subdomain images of the same call (each subdomain's FP32 value added
+ *     in FP64 in ascending subdomain-id order).  The ids must be listed in
+ *     ascending order (APC_E_ARG otherwise).  Needs an FP64 accumulator of
+ *     8*(m+1)*H*W bytes in context-owned device memory; the per-subdomain
+ *     images are never formed.
+ *   APC_KEEP_PIECES: also keep every piece (12 bytes each, in chunks of 64, in
+ *     context-owned device memory grown after a frame that did not fit) so that
+ *     apc_resolve_pass of the same geometry, camera, transfer function and
+ *     subdomain list evaluates them instead of walking the rays again.  A
+ *     variant that trades memory (about 67 GB at 2560^2 on a 100M-tet mesh)
+ *     for the second walk; results equal the plain form's to rounding.
+ * Without APC_KEEP_PIECES nothing per piece is stored (the paper's method: the
+ * per-pixel state is the m + 1 moments). */
 apc_status apc_moments_pass(apc_ctx ctx, apc_mesh mesh, const apc_view* view, const apc_tf* tf, int32_t m,
                             const int32_t* subdomains, int32_t n_sub, float* moments_per_sub, uint32_t flags,
                             void* stream);
@@ -217,8 +220,8 @@ apc_status apc_sum_moments(apc_ctx ctx, const float* moments_per_sub, int32_t n_
 
 #define APC_FINALIZE 1u
 #define APC_MOMENTS_F16 2u
-#define APC_REWALK 4u
 #define APC_MOMENTS_GLOBAL 8u
+#define APC_KEEP_PIECES 16u
 
 /* Pack a global moment image for FP16 storage, m + 3 planes each rounded to
  * the nearest FP16 value: planes 0 and 1 hold ln(b0) as two halves (hi, then
@@ -238,22 +241,26 @@ apc_status apc_pack_moments_f16(apc_ctx ctx, const float* moments_global, int32_
                                 void* packed, void* stream);
 
 /* Stage two for a list of subdomains (Section 4.2, Alg. 1 second loop and
- * Alg. 3).  The same pieces as stage one are generated again (a second walk),
- * staged in context-owned device memory (12 bytes per piece; the frame is
- * processed in chunks of tiles when the pieces do not fit), and each piece of
- * opacity alpha_p = 1 - exp(-a) and colour c (transfer-function RGB) adds
- * T * alpha_p * (c, 1), where T = clamp(exp(-b0 * F)) and F is the moment
- * bound at the piece's warped depth computed from `moments_global`.
+ * Alg. 3).  The rays are walked again exactly like stage one (the same pieces,
+ * bit for bit the same depths and optical depths), and each piece of opacity
+ * alpha_p = 1 - exp(-a) and colour c (transfer-function RGB) adds
+ * T * alpha_p * (c, 1) to its pixel at once, where T = clamp(exp(-b0 * F))
+ * and F is the moment bound at the piece's warped depth computed from
+ * `moments_global`; nothing per piece is stored.  When the preceding
+ * apc_moments_pass on this context kept its pieces (APC_KEEP_PIECES) for the
+ * same mesh, camera, transfer function and subdomain list, those pieces are
+ * evaluated instead of walking again.
  *   moments_global  device [m+1][H][W] FP32 (from apc_sum_moments), or with
  *                   APC_MOMENTS_F16 the FP16 image of apc_pack_moments_f16
  *                   ([m+3][H][W])
- *   rgba_out        device [H][W][4] FP32.  Without APC_FINALIZE: the additive
- *                   partial image (sum T*a*rgb, sum T*a) of the listed
- *                   subdomains, summed in the listed order.  With
- *                   APC_FINALIZE: the final image of those subdomains
- *                   (renormalised when mboit->renormalize, see apc_mboit).
+ *   rgba_out        device [H][W][4] FP32, 16-byte aligned.  Without
+ *                   APC_FINALIZE: the additive partial image (sum T*a*rgb,
+ *                   sum T*a) of the listed subdomains.  With APC_FINALIZE:
+ *                   the final image of those subdomains (renormalised when
+ *                   mboit->renormalize, see apc_mboit).
  * The per-pixel Hankel/Cholesky set-up and the per-piece solve run in FP64
- * when m = 6 or 8 and in FP32 when m = 4; everything else runs in FP32.
+ * when m = 6 or 8 and in FP32 when m = 4; everything else runs in FP32, the
+ * walk's ray geometry in FP64.
  * flags: APC_FINALIZE, APC_MOMENTS_F16. */
 apc_status apc_resolve_pass(apc_ctx ctx, apc_mesh mesh, const apc_view* view, const apc_tf* tf,
                             const apc_mboit* mboit, const void* moments_global, const int32_t* subdomains,
@@ -270,14 +277,18 @@ apc_status apc_sum_images(apc_ctx ctx, const float* partials, int32_t n_sub, int
                           const int32_t* subdomains, const float* moments_global, const apc_mboit* mboit,
                           float* rgba_out, void* stream);
 
-/* Bound the context's two large workspace buffers, the kept-piece pool and the
- * re-walk staging buffer, to 3/4 and 1/4 of bytes (0: each may take 60 % of
- * the free device memory, the default; the staging buffer is only used when
- * a frame's pieces did not fit the pool).  A frame whose pieces exceed the pool walks
- * again in stage two; one that exceeds the staging buffer is resolved in
- * chunks of tiles (same results).  Lets several contexts (e.g. a server's
- * slots) share one GPU with a known footprint. */
+/* Bound the context's kept-piece pool (APC_KEEP_PIECES) to `bytes` (0: it
+ * may take up to 60 % of the free device memory, the default).  A frame whose
+ * pieces exceed the pool walks again in stage two (same results).  Lets
+ * several contexts (e.g. a server's slots) share one GPU with a known
+ * footprint. */
 apc_status apc_set_workspace_limit(apc_ctx ctx, int64_t bytes);
+
+/* Device memory the context holds now (binning state, FP64 moment partials,
+ * segment statistics, the kept-piece pool): it grows to what the largest
+ * frame so far needed and is kept for the next frames.  A server adds it to
+ * a request's own buffers to admit requests by their HBM footprint. */
+apc_status apc_get_workspace_bytes(apc_ctx ctx, int64_t* bytes);
 
 /* ------------------------------------------------------------------ frame graphs */
 
@@ -290,14 +301,18 @@ apc_status apc_set_workspace_limit(apc_ctx ctx, int64_t bytes);
  * device: no host round trip, upload or allocation happens in a replay.  The
  * camera, parameters and buffer addresses are fixed at capture; the contents
  * of the transfer-function table and of the mesh may change between replays
- * as long as the piece counts per pixel do not (the mesh's geometry, the
- * camera and the lattice fix them; a staged piece beyond the capacity of the
- * sizing frame is never written, and the entry_overflow counter says so).
- * Calls that overlap on one graph race.
+ * as long as the binned boundary faces do not (the mesh's geometry and the
+ * camera fix them; with APC_KEEP_PIECES also the piece counts per pixel: a
+ * piece beyond the pool of the sizing frame is not kept, and that pixel's
+ * pieces are then left out and counted in entry_overflow).  Calls that
+ * overlap on one graph race.
  *   flags  APC_FINALIZE or 0, as for apc_resolve_pass, and/or APC_MOMENTS_GLOBAL:
  *          stage one sums the subdomains itself (as apc_moments_pass with that
- *          flag: ascending ids; moments_per_sub is not used and may be NULL)
- * Errors: APC_E_NOMEM when the frame's pieces do not fit one staging buffer. */
+ *          flag: ascending ids; moments_per_sub is not used and may be NULL),
+ *          and/or APC_KEEP_PIECES: stage two evaluates the pieces stage one kept
+ *          (else it walks again, the plain form)
+ * Errors: APC_E_NOMEM when APC_KEEP_PIECES is set and the frame's pieces do
+ * not fit the pool. */
 typedef struct apc_graph_s* apc_graph;
 apc_status apc_frame_graph_create(apc_ctx ctx, apc_mesh mesh, const apc_view* view, const apc_tf* tf,
                                   const apc_mboit* mboit, const int32_t* subdomains, int32_t n_sub,
@@ -356,8 +371,12 @@ typedef struct apc_counters {
   int64_t entry_overflow;   /* per-ray entry lists refilled in extra rounds (results stay correct), plus
                                stage-two re-walks whose piece count differed from the count (never expected) */
   int64_t nonpd_pivots;     /* Cholesky pivots floored in the resolve pass */
-  int64_t table_samples;    /* samples whose moment-bound roots came from their pixel's gap table (m >= 6) */
-  int64_t table_fallback;   /* of those, samples that went back to the closed-form roots (~1e-4 expected) */
+  int64_t table_samples;    /* samples (m >= 6) whose moment bound needed roots, found by Newton from a
+                               start: their pixel's gap table (kept pieces) or the ray's previous sample
+                               (re-walk) */
+  int64_t table_fallback;   /* of those, samples that took the closed-form roots: a start that did not
+                               converge (~1e-4 with tables), and in the re-walk every first sample of a ray
+                               in a new gap of the bound (a few percent) */
   int64_t segments;         /* maximal ray intervals inside one subdomain with at least one piece, every walk */
 } apc_counters;
 
@@ -376,8 +395,8 @@ typedef struct apc_timings {
   double moments_ms;   /* stage-one walk kernel of the last apc_moments_pass */
   double sum_ms;       /* last apc_sum_moments (0 after an APC_MOMENTS_GLOBAL stage one) */
   double resolve_ms;   /* everything after binning in the last apc_resolve_pass */
-  double stage_ms;     /* its re-walk kernel (first chunk of tiles) */
-  double eval_ms;      /* its moment-bound evaluation kernel (first chunk of tiles) */
+  double rewalk_ms;    /* its walk-and-evaluate kernel (0 when it evaluated kept pieces) */
+  double eval_ms;      /* its evaluation of kept pieces (0 when it walked again) */
 } apc_timings;
 apc_status apc_get_timings(apc_ctx ctx, apc_timings* out);
 

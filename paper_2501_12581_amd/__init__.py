@@ -20,8 +20,8 @@ APC_ORTHOGRAPHIC = 0
 APC_PERSPECTIVE = 1
 APC_FINALIZE = 1
 APC_MOMENTS_F16 = 2
-APC_REWALK = 4
 APC_MOMENTS_GLOBAL = 8
+APC_KEEP_PIECES = 16
 APC_DEVICE_NONE = -1   # apc_create: a host-only context (validates, launches nothing)
 APC_MESH_DEVICE = 1    # apc_mesh_desc.flags: the mesh arrays are device memory
 STATUS = {0: "APC_OK", 1: "APC_E_ARG", 2: "APC_E_MESH", 3: "APC_E_NOMEM", 4: "APC_E_DEVICE",
@@ -31,7 +31,7 @@ EXPORTS = ["apc_create", "apc_destroy", "apc_last_error", "apc_version", "apc_lo
            "apc_resolve_pass", "apc_sum_images", "apc_pack_moments_f16", "apc_segment_counts", "apc_get_counters",
            "apc_get_timings", "apc_set_tile_shape", "apc_get_tile_shape", "apc_autotune_tile_shape",
            "apc_frame_graph_create", "apc_frame_graph_launch", "apc_frame_graph_counters", "apc_frame_graph_destroy",
-           "apc_set_workspace_limit"]
+           "apc_set_workspace_limit", "apc_get_workspace_bytes"]
 
 
 class ApcError(RuntimeError):
@@ -70,7 +70,7 @@ class Mboit(C.Structure):
 
 class Timings(C.Structure):
     _fields_ = [("bin_ms", C.c_double), ("moments_ms", C.c_double), ("sum_ms", C.c_double),
-                ("resolve_ms", C.c_double), ("stage_ms", C.c_double), ("eval_ms", C.c_double)]
+                ("resolve_ms", C.c_double), ("rewalk_ms", C.c_double), ("eval_ms", C.c_double)]
 
 
 class Counters(C.Structure):
@@ -114,6 +114,8 @@ def lib():
         L.apc_resolve_pass.restype = st
         L.apc_resolve_pass.argtypes = [vp, vp, C.POINTER(View), C.POINTER(TF), C.POINTER(Mboit), vp, vp,
                                        C.c_int32, vp, C.c_uint32, vp]
+        L.apc_get_workspace_bytes.restype = st
+        L.apc_get_workspace_bytes.argtypes = [vp, C.POINTER(C.c_int64)]
         L.apc_pack_moments_f16.restype = st
         L.apc_pack_moments_f16.argtypes = [vp, vp, C.c_int32, C.c_int32, C.c_int32, vp, vp]
         L.apc_set_workspace_limit.restype = st
@@ -271,15 +273,15 @@ class Context:
         self._ck(lib().apc_load_mesh(self.handle, C.byref(d), C.byref(h), _stream(stream)))
         return Mesh(self, h)
 
-    def moments_pass(self, mesh, view: View, tf: TF, m, subdomains, out, stream=None, rewalk=False,
+    def moments_pass(self, mesh, view: View, tf: TF, m, subdomains, out, stream=None, keep=False,
                      global_sum=False):
-        """Stage one; unless rewalk, its pieces are kept for the resolve pass of the same frame.  With
-        global_sum (ascending subdomain ids), `out` is the global [m+1][H][W] image, summed by stage one
+        """Stage one; with keep its pieces are kept for the resolve pass of the same frame (APC_KEEP_PIECES).
+        With global_sum (ascending subdomain ids), `out` is the global [m+1][H][W] image, summed by stage one
         itself (bitwise what sum_moments gives for the per-subdomain images), instead of [n][m+1][H][W]."""
         import torch
         ids, ptr = _ids(subdomains)
         shape = (m + 1, view.height, view.width) if global_sum else (len(ids), m + 1, view.height, view.width)
-        flags = (APC_REWALK if rewalk else 0) | (APC_MOMENTS_GLOBAL if global_sum else 0)
+        flags = (APC_KEEP_PIECES if keep else 0) | (APC_MOMENTS_GLOBAL if global_sum else 0)
         self._ck(lib().apc_moments_pass(self.handle, mesh.handle, C.byref(view), C.byref(tf), int(m), ptr,
                                         len(ids), _dev_ptr(out, torch.float32, shape,
                                                            "moments" if global_sum else "moments_per_sub"),
@@ -306,6 +308,12 @@ class Context:
                                                  "moments"), ptr, len(ids),
                                         _dev_ptr(out, torch.float32, (view.height, view.width, 4), "rgba"),
                                         flags, _stream(stream)))
+
+    def workspace_bytes(self) -> int:
+        """Device memory the context holds now (apc_get_workspace_bytes)."""
+        b = C.c_int64(0)
+        self._ck(lib().apc_get_workspace_bytes(self.handle, C.byref(b)))
+        return b.value
 
     def set_workspace_limit(self, nbytes):
         """Cap the kept-piece pool at 3/4 and the re-walk staging buffer at 1/4 of nbytes (0: default policy)."""
@@ -375,8 +383,9 @@ class FrameGraph:
     """A whole frame of a Renderer captured in a HIP graph (apc_frame_graph_create): one launch per frame,
     writing the Renderer's moment and image buffers."""
 
-    def __init__(self, renderer, finalize=True, fused=False):
-        """fused: stage one sums the subdomains itself (Renderer.frame(fused=True)); per_sub is not written."""
+    def __init__(self, renderer, finalize=True, global_sum=False, keep=False):
+        """global_sum: stage one sums the subdomains itself (per_sub is not written); keep: stage two evaluates
+        the pieces stage one kept instead of walking again."""
         import torch
         r = renderer
         ids, ptr = _ids(r.subs)
@@ -384,9 +393,10 @@ class FrameGraph:
         h = C.c_void_p()
         _check(lib().apc_frame_graph_create(
             r.ctx.handle, r.mesh.handle, C.byref(r.view), C.byref(r.tf), C.byref(r.mboit), ptr, len(ids),
-            None if fused else _dev_ptr(r.per_sub, torch.float32, name="moments_per_sub"),
+            None if global_sum else _dev_ptr(r.per_sub, torch.float32, name="moments_per_sub"),
             _dev_ptr(r.moments, torch.float32, name="moments"), _dev_ptr(r.rgba, torch.float32, name="rgba"),
-            (APC_FINALIZE if finalize else 0) | (APC_MOMENTS_GLOBAL if fused else 0), C.byref(h)), r.ctx.handle)
+            (APC_FINALIZE if finalize else 0) | (APC_MOMENTS_GLOBAL if global_sum else 0) |
+            (APC_KEEP_PIECES if keep else 0), C.byref(h)), r.ctx.handle)
         self.handle = h
         self.renderer = r
 
@@ -430,21 +440,32 @@ class Renderer:
         self.mboit = make_mboit(scene.m, scene.alpha, scene.bias, scene.eta, scene.renormalize)
         self.subs = np.arange(mesh.n_sub, dtype=np.int32)
         H, W, m = self.view.height, self.view.width, scene.m
-        self.per_sub = torch.empty((mesh.n_sub, m + 1, H, W), dtype=torch.float32, device=device)
+        self._per_sub = None  # [S][m+1][H][W], allocated by the first frame that needs it (separate sum)
+        self._device = device
         self.moments = torch.empty((m + 1, H, W), dtype=torch.float32, device=device)
         self.rgba = torch.empty((H, W, 4), dtype=torch.float32, device=device)
 
-    def frame(self, subdomains=None, finalize=True, stream=None, moments_f16=False, rewalk=False, fused=False):
-        """One frame; with moments_f16 the resolve reads the FP16-packed moment image (self.moments_h); with
-        rewalk stage two walks the rays again instead of reading the pieces stage one kept; with fused (all
-        subdomains, ascending) stage one writes the global moments itself and self.per_sub is not written."""
+    @property
+    def per_sub(self):
+        """Per-subdomain moment images of the separate-sum form (17 GB at 2560^2, m = 8, 72 subdomains)."""
+        if self._per_sub is None:
+            import torch
+            m1, H, W = self.moments.shape
+            self._per_sub = torch.empty((len(self.subs), m1, H, W), dtype=torch.float32, device=self._device)
+        return self._per_sub
+
+    def frame(self, subdomains=None, finalize=True, stream=None, moments_f16=False, keep=False, global_sum=False):
+        """One frame.  moments_f16: the resolve reads the FP16-packed moment image (self.moments_h); keep:
+        stage one keeps its pieces and stage two evaluates them (else stage two walks the rays again, the
+        plain form); global_sum (all subdomains, ascending): stage one writes the global moments itself and
+        self.per_sub is not written."""
         subs = self.subs if subdomains is None else np.asarray(subdomains, np.int32)
-        if fused:
+        if global_sum:
             self.ctx.moments_pass(self.mesh, self.view, self.tf, self.scene.m, subs, self.moments, stream,
-                                  rewalk=rewalk, global_sum=True)
+                                  keep=keep, global_sum=True)
         else:
             per_sub = self.per_sub if len(subs) == len(self.subs) else self.per_sub[:len(subs)]
-            self.ctx.moments_pass(self.mesh, self.view, self.tf, self.scene.m, subs, per_sub, stream, rewalk=rewalk)
+            self.ctx.moments_pass(self.mesh, self.view, self.tf, self.scene.m, subs, per_sub, stream, keep=keep)
             self.ctx.sum_moments(per_sub, self.scene.m, subs, self.moments, stream)
         mom = self.moments
         if moments_f16:

@@ -98,7 +98,8 @@ struct apc_ctx_s {
   hipEvent_t ev[6][2] = {};
   bool ev_used[6] = {};
   // stage two: pieces per pixel (tile-major), 64-bit piece offsets, staged pieces
-  DevBuf pcount, tile_tot, tile_off, poff, stage;
+  // pieces per pixel of the last stage one (tile-major), for the evaluation of kept pieces
+  DevBuf pcount;
   // tile shape of both passes: (1 << tw_log2) x (64 >> tw_log2) pixels per wavefront
   int tw_log2 = 3;
   // per-pixel segment statistics of the last stage one: [2][seg_h][seg_w]
@@ -114,8 +115,6 @@ struct apc_ctx_s {
   // capture mode (see apc_frame_graph_create): no host round trips, no uploads, no event marks
   bool capturing = false;
   size_t store_slots = 0;     // pixels (tiles * 64) of the last stage one that kept pieces
-  long long last_pieces = 0;  // pieces of the last eager resolve pass
-  long long last_chunks = 0;  // and the number of staging chunks it took
   // pieces kept by stage one for stage two (see PieceStore)
   DevBuf pool, ptab, store_next;
   long long pool_chunks = 0;         // chunks the pool holds
@@ -124,7 +123,7 @@ struct apc_ctx_s {
   bool store_ready = false;          // the last stage one kept its pieces (if none failed)
   apc_tf store_tf = {};              // the transfer function they were made with
   bool store_failed_last = false;    // the last resolve found that stage one could not keep every piece
-  int64_t ws_limit = 0;              // bytes for the piece pool + staging buffer (0: 60 % of free memory each)
+  int64_t ws_limit = 0;              // bytes for the piece pool (0: up to 60 % of free memory)
 };
 
 struct apc_graph_s {
@@ -331,10 +330,28 @@ apc_status check_subdomains(const apc_mesh_s* m, const int32_t* subs, int32_t n_
 // records the bin buffer holds
 long long bin_cap(apc_ctx ctx) { return (long long)(ctx->records.bytes / sizeof(int)); }
 
-// Bin the boundary faces of the listed subdomains into (tile, slot) bins.
-apc_status build_bins(apc_ctx ctx, const apc_mesh_s* m, const FrameDev& f, const int32_t* subs, int32_t n_sub,
-                      hipStream_t s, MeshDev& md) {
-  std::vector<SlotDev> sl(n_sub);
+// Where a frame's binning state lives: the context's growable buffers, or
+// fixed slices of a caller-independent workspace.
+struct BinSpace {
+  SlotDev* slots;
+  int *counts, *offsets, *cursors, *tmp, *records;
+  long long rec_cap;  // records the record buffer holds (sized after counting when `grow`)
+  bool grow;          // records live in ctx->records and may be grown
+};
+
+// Bin the boundary faces of the listed subdomains into (tile, slot) bins:
+// slot table upload, count pass, exclusive scan, the record total read back
+// (to size or check the record buffer; not while capturing a graph, whose
+// buffers were sized by an eager frame), fill pass.
+apc_status bin_faces(apc_ctx ctx, const apc_mesh_s* m, const FrameDev& f, const int32_t* subs, int32_t n_sub,
+                     BinSpace& B, hipStream_t s, MeshDev& md) {
+  SlotDev sl_fixed[64];
+  std::vector<SlotDev> sl_big;
+  SlotDev* sl = sl_fixed;
+  if (n_sub > 64) {
+    sl_big.resize(n_sub);
+    sl = sl_big.data();
+  }
   int max_faces = 0;
   for (int k = 0; k < n_sub; ++k) {
     int id = subs[k];
@@ -344,39 +361,58 @@ apc_status build_bins(apc_ctx ctx, const apc_mesh_s* m, const FrameDev& f, const
     sl[k].face_end = m->face_begin[id + 1];
     max_faces = std::max(max_faces, sl[k].face_end - sl[k].face_begin);
   }
-  HIPCHK(ctx->slots.ensure(sizeof(SlotDev) * n_sub));
-  apc_status st = stage_upload(ctx, ctx->slots.p, sl.data(), sizeof(SlotDev) * n_sub, s);
-  if (st != APC_OK) return st;
+  if (B.grow) {  // through the context's pinned staging buffer
+    apc_status st = stage_upload(ctx, B.slots, sl, sizeof(SlotDev) * n_sub, s);
+    if (st != APC_OK) return st;
+  } else {  // a plain copy, complete once the record total has been read back below
+    HIPCHK(hipMemcpyAsync(B.slots, sl, sizeof(SlotDev) * n_sub, hipMemcpyHostToDevice, s));
+  }
   const int64_t nb = int64_t(f.n_tiles) * n_sub;
-  HIPCHK(ctx->counts.ensure(sizeof(int) * nb));
-  HIPCHK(ctx->offsets.ensure(sizeof(int) * (nb + 1)));
-  HIPCHK(ctx->cursors.ensure(sizeof(int) * nb));
-  HIPCHK(ctx->scan_tmp.ensure(sizeof(int) * apc::scan_tmp_elems(nb)));
   md.vert = m->vert;
   md.tet = m->tet;
   md.wrec = m->wrec;
   md.n_vertices = m->V;
   md.n_tets = m->T;
   HIPCHK(ev_mark(ctx, EV_BIN, 0, s));
-  HIPCHK(apc::launch_fill_i32(ctx->counts.as<int>(), 0, nb, s));
-  HIPCHK(apc::launch_bin_count(md, f, ctx->slots.as<SlotDev>(), max_faces, m->bface, ctx->counts.as<int>(), s));
-  HIPCHK(apc::launch_exclusive_scan(ctx->counts.as<int>(), ctx->offsets.as<int>(), nb, ctx->scan_tmp.as<int>(), s));
-  if (!ctx->capturing) {  // size the record buffer from the counts
+  HIPCHK(apc::launch_fill_i32(B.counts, 0, nb, s));
+  HIPCHK(apc::launch_bin_count(md, f, B.slots, max_faces, m->bface, B.counts, s));
+  HIPCHK(apc::launch_exclusive_scan(B.counts, B.offsets, nb, B.tmp, s));
+  if (!ctx->capturing) {
     int tail[2];
-    HIPCHK(hipMemcpyAsync(&tail[0], ctx->offsets.as<int>() + nb - 1, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(&tail[1], ctx->counts.as<int>() + nb - 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&tail[0], B.offsets + nb - 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&tail[1], B.counts + nb - 1, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     const int64_t total = int64_t(tail[0]) + tail[1];
     if (total < 0 || total > (int64_t(1) << 31) - 1)
       return fail(APC_E_NUMERIC, "bin records overflow (%lld)", (long long)total);
-    HIPCHK(ctx->records.ensure(sizeof(int) * std::max<int64_t>(total, 1)));
+    if (B.grow) {
+      HIPCHK(ctx->records.ensure(sizeof(int) * std::max<int64_t>(total, 1)));
+      B.records = ctx->records.as<int>();
+      B.rec_cap = bin_cap(ctx);
+    } else if (total > B.rec_cap) {
+      return fail(APC_E_NOMEM, "the frame bins %lld (face, tile) records; the workspace holds %lld",
+                  (long long)total, B.rec_cap);
+    }
     ctx->bin_records += total;
   }
-  HIPCHK(apc::launch_fill_i32(ctx->cursors.as<int>(), 0, nb, s));
-  HIPCHK(apc::launch_bin_fill(md, f, ctx->slots.as<SlotDev>(), max_faces, m->bface, ctx->offsets.as<int>(),
-                              ctx->cursors.as<int>(), ctx->records.as<int>(), bin_cap(ctx), s));
+  HIPCHK(apc::launch_fill_i32(B.cursors, 0, nb, s));
+  HIPCHK(apc::launch_bin_fill(md, f, B.slots, max_faces, m->bface, B.offsets, B.cursors, B.records, B.rec_cap, s));
   HIPCHK(ev_mark(ctx, EV_BIN, 1, s));
   return APC_OK;
+}
+
+// bin_faces into the context's growable buffers
+apc_status build_bins(apc_ctx ctx, const apc_mesh_s* m, const FrameDev& f, const int32_t* subs, int32_t n_sub,
+                      hipStream_t s, MeshDev& md) {
+  const int64_t nb = int64_t(f.n_tiles) * n_sub;
+  HIPCHK(ctx->slots.ensure(sizeof(SlotDev) * n_sub));
+  HIPCHK(ctx->counts.ensure(sizeof(int) * nb));
+  HIPCHK(ctx->offsets.ensure(sizeof(int) * (nb + 1)));
+  HIPCHK(ctx->cursors.ensure(sizeof(int) * nb));
+  HIPCHK(ctx->scan_tmp.ensure(sizeof(int) * apc::scan_tmp_elems(nb)));
+  BinSpace B = {ctx->slots.as<SlotDev>(), ctx->counts.as<int>(), ctx->offsets.as<int>(), ctx->cursors.as<int>(),
+                ctx->scan_tmp.as<int>(), ctx->records.as<int>(), bin_cap(ctx), true};
+  return bin_faces(ctx, m, f, subs, n_sub, B, s, md);
 }
 
 void set_piece_key(apc_ctx ctx, const apc_mesh_s* m, const apc_view* v, const int32_t* subs, int32_t n_sub) {
@@ -514,8 +550,9 @@ apc_status apc_create(int device, apc_ctx* out) {
   for (int k = 0; k < EV_COUNT && e == hipSuccess; ++k)
     for (int w = 0; w < 2 && e == hipSuccess; ++w) e = hipEventCreate(&c->ev[k][w]);
   if (e != hipSuccess) {
-    delete c;
-    return fail(APC_E_DEVICE, "context set-up failed: %s", hipGetErrorString(e));
+    const char* msg = hipGetErrorString(e);
+    apc_destroy(c);
+    return fail(APC_E_DEVICE, "context set-up failed: %s", msg);
   }
   *out = c;
   return APC_OK;
@@ -530,8 +567,8 @@ apc_status apc_destroy(apc_ctx ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   for (DevBuf* b : {&ctx->counts, &ctx->offsets, &ctx->cursors, &ctx->records, &ctx->scan_tmp, &ctx->slots,
-                    &ctx->order, &ctx->counters, &ctx->pcount, &ctx->tile_tot, &ctx->tile_off, &ctx->poff,
-                    &ctx->stage, &ctx->segs, &ctx->pool, &ctx->ptab, &ctx->store_next})
+                    &ctx->order, &ctx->counters, &ctx->pcount, &ctx->segs, &ctx->gacc, &ctx->pool, &ctx->ptab,
+                    &ctx->store_next})
     b->release();
   if (ctx->staging) (void)hipHostFree(ctx->staging);
   if (ctx->staging_done) (void)hipEventDestroy(ctx->staging_done);
@@ -810,7 +847,7 @@ static bool grow_piece_store(apc_ctx ctx, size_t slots) {
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return false;
     const size_t limit =
-        ctx->ws_limit > 0 ? size_t(ctx->ws_limit / 4 * 3) : size_t(0.6 * double(free_b + ctx->pool.bytes));
+        ctx->ws_limit > 0 ? size_t(ctx->ws_limit) : size_t(0.6 * double(free_b + ctx->pool.bytes));
     const size_t want = std::min(size_t(ctx->pool_target) * chunk_bytes, limit);
     if (want > ctx->pool.bytes) {
       ctx->pool.release();
@@ -832,7 +869,7 @@ apc_status apc_moments_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const
   if (mm != 4 && mm != 6 && mm != 8) return fail(APC_E_ARG, "m = %d unsupported (4, 6 or 8)", mm);
   if ((st = check_subdomains(m, subs, n_sub)) != APC_OK) return st;
   if (!out) return fail(APC_E_ARG, "output is NULL");
-  if (flags & ~(APC_REWALK | APC_MOMENTS_GLOBAL)) return fail(APC_E_ARG, "unknown flags 0x%x", flags);
+  if (flags & ~(APC_KEEP_PIECES | APC_MOMENTS_GLOBAL)) return fail(APC_E_ARG, "unknown flags 0x%x", flags);
   const bool global = (flags & APC_MOMENTS_GLOBAL) != 0;
   if (global)
     for (int k = 1; k < n_sub; ++k)
@@ -847,7 +884,7 @@ apc_status apc_moments_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const
   // keep the pieces for stage two unless asked not to (or the pool cannot be had)
   apc::PieceStore ps = {};
   ctx->store_ready = false;
-  if (!(flags & APC_REWALK)) {
+  if (flags & APC_KEEP_PIECES) {
     const size_t slots = size_t(f.n_tiles) * 64;
     if (ctx->pool_target == 0)  // 128 pieces per pixel to start
       ctx->pool_target = (long long)(slots * 128 / apc::PIECE_CHUNK) + (long long)f.n_tiles * apc::STORE_BLOCK;
@@ -935,14 +972,16 @@ apc_status apc_resolve_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const
   return st;
 }
 
-static apc_status resolve_frame(apc_ctx ctx, apc_mesh m, const apc_view* view, const apc_tf* tf,
+// Validation shared by the resolve entry points; fills the bound parameters and the frame constants.  A
+// host-only context stops here.
+static apc_status check_resolve(apc_ctx ctx, apc_mesh m, const apc_view* view, const apc_tf* tf,
                                 const apc_mboit* mb, const void* moments, const int32_t* subs, int32_t n_sub,
-                                float* rgba, uint32_t flags, void* stream) {
+                                const float* rgba, uint32_t flags, apc::BoundParams& bp, FrameDev& f,
+                                const char* call) {
   apc_status st = check_ctx(ctx);
   if (st != APC_OK) return st;
   if ((st = check_mesh(ctx, m)) != APC_OK) return st;
   if ((st = check_view_tf(view, tf)) != APC_OK) return st;
-  apc::BoundParams bp;
   if ((st = bound_params(mb, bp, (flags & APC_FINALIZE) ? 1 : 0)) != APC_OK) return st;
   if ((st = check_subdomains(m, subs, n_sub)) != APC_OK) return st;
   if (!moments || !rgba) return fail(APC_E_ARG, "buffer is NULL");
@@ -951,9 +990,18 @@ static apc_status resolve_frame(apc_ctx ctx, apc_mesh m, const apc_view* view, c
   bp.moments_f16 = (flags & APC_MOMENTS_F16) ? 1 : 0;
   if (bp.moments_f16 && (reinterpret_cast<uintptr_t>(moments) & 1))
     return fail(APC_E_ARG, "packed FP16 moments must be 2-byte aligned");
-  FrameDev f;
   if ((st = make_frame(m, view, tf, n_sub, max_tets_of(m, subs, n_sub), ctx->tw_log2, f)) != APC_OK) return st;
-  if (ctx->host_only) return no_device("apc_resolve_pass");
+  if (ctx->host_only) return no_device(call);
+  return APC_OK;
+}
+
+static apc_status resolve_frame(apc_ctx ctx, apc_mesh m, const apc_view* view, const apc_tf* tf,
+                                const apc_mboit* mb, const void* moments, const int32_t* subs, int32_t n_sub,
+                                float* rgba, uint32_t flags, void* stream) {
+  apc::BoundParams bp;
+  FrameDev f;
+  apc_status st = check_resolve(ctx, m, view, tf, mb, moments, subs, n_sub, rgba, flags, bp, f, "apc_resolve_pass");
+  if (st != APC_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int nt = f.n_tiles;
   unsigned long long* ctr = ctx->counters.as<unsigned long long>();
@@ -971,57 +1019,6 @@ static apc_status resolve_frame(apc_ctx ctx, apc_mesh m, const apc_view* view, c
     stored = !store_failed;
   }
   ctx->store_failed_last = store_failed;
-  HIPCHK(ev_mark(ctx, EV_RES, 0, s));
-  if (stored) {  // (in a replayed graph the kernel itself checks that no lane failed)
-    apc::PieceStore ps = {ctx->pool.as<float>(), ctx->pool_chunks, ctx->ptab.as<int>(), ctx->maxc,
-                          ctx->store_next.as<unsigned long long>()};
-    HIPCHK(ev_mark(ctx, EV_EVL, 0, s));
-    HIPCHK(apc::launch_eval(mb->m, f, 0, nt, nullptr, 0, 0, nullptr, ps, ctx->pcount.as<int>(), tf->rgba, moments,
-                            bp, rgba, ctr, s));
-    HIPCHK(ev_mark(ctx, EV_EVL, 1, s));
-    HIPCHK(ev_mark(ctx, EV_RES, 1, s));
-    return APC_OK;
-  }
-  MeshDev md;
-  if ((st = build_bins(ctx, m, f, subs, n_sub, s, md)) != APC_OK) return st;
-  // pieces per pixel: from stage one when it ran on the same geometry, else counted by a walk
-  if (!piece_key_matches(ctx, m, view, subs, n_sub)) {
-    if (ctx->capturing) return fail(APC_E_ARG, "capture: stage one of the same view must precede the resolve");
-    ctx->pc_valid = false;
-    HIPCHK(ctx->pcount.ensure(sizeof(int) * size_t(nt) * 64));
-    HIPCHK(apc::launch_stage(0, md, f, ctx->slots.as<SlotDev>(), ctx->offsets.as<int>(), ctx->counts.as<int>(),
-                             ctx->records.as<int>(), bin_cap(ctx), tf->rgba, 0, nt, ctx->pcount.as<int>(), nullptr, 0,
-                             0, nullptr, ctr, s));
-    set_piece_key(ctx, m, view, subs, n_sub);
-  }
-  const apc::PieceStore no_store = {};
-  HIPCHK(ctx->tile_tot.ensure(sizeof(long long) * nt));
-  HIPCHK(ctx->tile_off.ensure(sizeof(long long) * nt));
-  HIPCHK(ctx->poff.ensure(sizeof(long long) * (size_t(nt) * 64 + 1)));
-  HIPCHK(apc::launch_tile_sums(ctx->pcount.as<int>(), nt, ctx->tile_tot.as<long long>(), s));
-  if (ctx->capturing) {
-    // one chunk, offsets on the device; the staging buffer was sized by the eager frame and the
-    // kernels leave anything beyond it unwritten (counted as overflow)
-    const long long cap_pieces = (long long)(ctx->stage.bytes / (3 * sizeof(float)));
-    HIPCHK(apc::launch_tile_offsets(ctx->tile_tot.as<long long>(), nt, ctx->tile_off.as<long long>(), s));
-    HIPCHK(apc::launch_piece_offsets(ctx->pcount.as<int>(), ctx->tile_off.as<long long>(), nt,
-                                     ctx->poff.as<long long>(), s));
-    HIPCHK(apc::launch_stage(1, md, f, ctx->slots.as<SlotDev>(), ctx->offsets.as<int>(), ctx->counts.as<int>(),
-                             ctx->records.as<int>(), bin_cap(ctx), tf->rgba, 0, nt, nullptr,
-                             ctx->poff.as<long long>(), 0, cap_pieces, ctx->stage.as<float>(), ctr, s));
-    HIPCHK(apc::launch_eval(mb->m, f, 0, nt, ctx->poff.as<long long>(), 0, cap_pieces, ctx->stage.as<float>(),
-                            no_store, nullptr, tf->rgba, moments, bp, rgba, ctr, s));
-    return APC_OK;
-  }
-  std::vector<long long> tot(nt), toff(nt);
-  HIPCHK(hipMemcpyAsync(tot.data(), ctx->tile_tot.p, sizeof(long long) * nt, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  long long total = 0, biggest = 0;
-  for (int t = 0; t < nt; ++t) {
-    toff[t] = total;
-    total += tot[t];
-    biggest = std::max(biggest, tot[t]);
-  }
   if (store_failed) {  // size the piece store for the next frame from this frame's counts
     std::vector<int> pc(size_t(nt) * 64);
     HIPCHK(hipMemcpyAsync(pc.data(), ctx->pcount.p, sizeof(int) * pc.size(), hipMemcpyDeviceToHost, s));
@@ -1035,46 +1032,23 @@ static apc_status resolve_frame(apc_ctx ctx, apc_mesh m, const apc_view* view, c
     ctx->pool_target = std::max(ctx->pool_target, chunks + chunks / 50 + (long long)nt * apc::STORE_BLOCK);
     ctx->maxc = std::max(ctx->maxc, (most + apc::PIECE_CHUNK - 1) / apc::PIECE_CHUNK + 8);
   }
-  if ((st = stage_upload(ctx, ctx->tile_off.p, toff.data(), sizeof(long long) * nt, s)) != APC_OK) return st;
-  HIPCHK(apc::launch_piece_offsets(ctx->pcount.as<int>(), ctx->tile_off.as<long long>(), nt,
-                                   ctx->poff.as<long long>(), s));
-  // staging capacity: all pieces if they fit in 60% of the free device memory, else chunks of tiles
-  const size_t rec_bytes = 3 * sizeof(float);
-  size_t want = size_t(std::max<long long>(total, 1)) * rec_bytes;
-  if (want > ctx->stage.bytes) {
-    size_t free_b = 0, total_b = 0;
-    HIPCHK(hipMemGetInfo(&free_b, &total_b));
-    size_t cap = ctx->ws_limit > 0 ? size_t(ctx->ws_limit / 4) : size_t(0.6 * double(free_b + ctx->stage.bytes));
-    size_t need = std::min(want, cap);
-    if (need < size_t(biggest) * rec_bytes) return fail(APC_E_NOMEM, "one tile's pieces do not fit in device memory");
-    ctx->stage.release();
-    hipError_t e = ctx->stage.ensure(need, ctx->ws_limit == 0);
-    if (e != hipSuccess) return fail(APC_E_NOMEM, "staging %zu bytes: %s", need, hipGetErrorString(e));
+  HIPCHK(ev_mark(ctx, EV_RES, 0, s));
+  if (stored) {  // (in a replayed graph the kernel itself checks that no lane failed)
+    apc::PieceStore ps = {ctx->pool.as<float>(), ctx->pool_chunks, ctx->ptab.as<int>(), ctx->maxc,
+                          ctx->store_next.as<unsigned long long>()};
+    HIPCHK(ev_mark(ctx, EV_EVL, 0, s));
+    HIPCHK(apc::launch_eval(mb->m, f, 0, nt, ps, ctx->pcount.as<int>(), tf->rgba, moments, bp, rgba, ctr, s));
+    HIPCHK(ev_mark(ctx, EV_EVL, 1, s));
+    HIPCHK(ev_mark(ctx, EV_RES, 1, s));
+    return APC_OK;
   }
-  const long long cap_pieces = (long long)(ctx->stage.bytes / rec_bytes);
-  ctx->last_pieces = total;
-  ctx->last_chunks = 0;
-  bool first = true;
-  for (int t0 = 0; t0 < nt;) {
-    int t1 = t0;
-    long long used = 0;
-    while (t1 < nt && used + tot[t1] <= cap_pieces) used += tot[t1++];
-    if (t1 == t0) return fail(APC_E_NOMEM, "tile %d does not fit in the staging buffer", t0);
-    if (first) HIPCHK(ev_mark(ctx, EV_STG, 0, s));
-    HIPCHK(apc::launch_stage(1, md, f, ctx->slots.as<SlotDev>(), ctx->offsets.as<int>(), ctx->counts.as<int>(),
-                             ctx->records.as<int>(), bin_cap(ctx), tf->rgba, t0, t1, nullptr,
-                             ctx->poff.as<long long>(), toff[t0], cap_pieces, ctx->stage.as<float>(), ctr, s));
-    if (first) {
-      HIPCHK(ev_mark(ctx, EV_STG, 1, s));
-      HIPCHK(ev_mark(ctx, EV_EVL, 0, s));
-    }
-    HIPCHK(apc::launch_eval(mb->m, f, t0, t1, ctx->poff.as<long long>(), toff[t0], cap_pieces,
-                            ctx->stage.as<float>(), no_store, nullptr, tf->rgba, moments, bp, rgba, ctr, s));
-    if (first) HIPCHK(ev_mark(ctx, EV_EVL, 1, s));
-    first = false;
-    t0 = t1;
-    ++ctx->last_chunks;
-  }
+  // the plain form: walk the rays again and evaluate every piece at once
+  MeshDev md;
+  if ((st = build_bins(ctx, m, f, subs, n_sub, s, md)) != APC_OK) return st;
+  HIPCHK(ev_mark(ctx, EV_STG, 0, s));
+  HIPCHK(apc::launch_resolve(mb->m, md, f, ctx->slots.as<SlotDev>(), ctx->offsets.as<int>(), ctx->counts.as<int>(),
+                             ctx->records.as<int>(), bin_cap(ctx), tf->rgba, moments, bp, rgba, ctr, s));
+  HIPCHK(ev_mark(ctx, EV_STG, 1, s));
   HIPCHK(ev_mark(ctx, EV_RES, 1, s));
   return APC_OK;
 }
@@ -1099,8 +1073,10 @@ apc_status apc_frame_graph_create(apc_ctx ctx, apc_mesh m, const apc_view* view,
   if (!out) return fail(APC_E_ARG, "out is NULL");
   *out = nullptr;
   if (!mb) return fail(APC_E_ARG, "mboit is NULL");
-  if (flags & ~(APC_FINALIZE | APC_MOMENTS_GLOBAL)) return fail(APC_E_ARG, "unknown flags 0x%x", flags);
+  if (flags & ~(APC_FINALIZE | APC_MOMENTS_GLOBAL | APC_KEEP_PIECES))
+    return fail(APC_E_ARG, "unknown flags 0x%x", flags);
   const bool global = (flags & APC_MOMENTS_GLOBAL) != 0;
+  const uint32_t keep = flags & APC_KEEP_PIECES;
   if (!global && !moments_per_sub) return fail(APC_E_ARG, "moments_per_sub is NULL");
   if ((st = check_mesh(ctx, m)) != APC_OK) return st;
   if (ctx->host_only) return no_device("apc_frame_graph_create");
@@ -1119,9 +1095,9 @@ apc_status apc_frame_graph_create(apc_ctx ctx, apc_mesh m, const apc_view* view,
   auto frame = [&]() -> apc_status {
     apc_status r;
     if (global) {
-      r = apc_moments_pass(w, m, view, tf, mb->m, subs, n_sub, moments_global, APC_MOMENTS_GLOBAL, g->cs);
+      r = apc_moments_pass(w, m, view, tf, mb->m, subs, n_sub, moments_global, APC_MOMENTS_GLOBAL | keep, g->cs);
     } else {
-      r = apc_moments_pass(w, m, view, tf, mb->m, subs, n_sub, moments_per_sub, 0, g->cs);
+      r = apc_moments_pass(w, m, view, tf, mb->m, subs, n_sub, moments_per_sub, keep, g->cs);
       if (r == APC_OK)
         r = apc_sum_moments(w, moments_per_sub, n_sub, mb->m, view->height, view->width, subs, moments_global,
                             g->cs);
@@ -1138,8 +1114,6 @@ apc_status apc_frame_graph_create(apc_ctx ctx, apc_mesh m, const apc_view* view,
     if (st != APC_OK || !w->store_failed_last) break;
   }
   if (st == APC_OK && w->store_failed_last) st = fail(APC_E_NOMEM, "the frame's pieces do not fit the piece store");
-  if (st == APC_OK && !w->store_ready && w->last_chunks > 1)
-    st = fail(APC_E_NOMEM, "the frame's %lld pieces do not fit one staging buffer", (long long)w->last_pieces);
   // 2) the same frame captured: kernels only (no uploads, host reads, event records or allocations)
   if (st == APC_OK) {
     if (hipStreamBeginCapture(g->cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
@@ -1184,17 +1158,25 @@ apc_status apc_set_workspace_limit(apc_ctx ctx, int64_t bytes) {
   if (bytes < 0) return fail(APC_E_ARG, "negative limit");
   ctx->ws_limit = bytes;
   if (ctx->host_only) return APC_OK;
-  // buffers above their share of the new limit are given back
-  if (bytes > 0 && ctx->pool.bytes > size_t(bytes / 4 * 3)) {
+  // a pool above the new limit is given back
+  if (bytes > 0 && ctx->pool.bytes > size_t(bytes)) {
     HIPCHK(hipDeviceSynchronize());
     ctx->pool.release();
     ctx->pool_chunks = 0;
     ctx->store_ready = false;
   }
-  if (bytes > 0 && ctx->stage.bytes > size_t(bytes / 4)) {
-    HIPCHK(hipDeviceSynchronize());
-    ctx->stage.release();
-  }
+  return APC_OK;
+}
+
+apc_status apc_get_workspace_bytes(apc_ctx ctx, int64_t* bytes) {
+  if (!ctx) return fail(APC_E_ARG, "context is NULL");
+  if (!bytes) return fail(APC_E_ARG, "bytes is NULL");
+  int64_t total = 0;
+  for (const DevBuf* b : {&ctx->counts, &ctx->offsets, &ctx->cursors, &ctx->records, &ctx->scan_tmp, &ctx->slots,
+                          &ctx->order, &ctx->counters, &ctx->pcount, &ctx->segs, &ctx->gacc, &ctx->pool, &ctx->ptab,
+                          &ctx->store_next})
+    total += int64_t(b->bytes);
+  *bytes = total;
   return APC_OK;
 }
 
@@ -1364,7 +1346,7 @@ apc_status apc_get_timings(apc_ctx ctx, apc_timings* out) {
   out->moments_ms = ms[EV_MOM];
   out->sum_ms = ms[EV_SUM];
   out->resolve_ms = ms[EV_RES];
-  out->stage_ms = ms[EV_STG];
+  out->rewalk_ms = ms[EV_STG];
   out->eval_ms = ms[EV_EVL];
   return APC_OK;
 }

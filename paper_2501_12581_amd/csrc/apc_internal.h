@@ -100,27 +100,18 @@ hipError_t launch_moments(int mm, const MeshDev& m, const FrameDev& f, const Slo
                           const int* counts, const int* records, long long bin_cap, const float* tf_rgba, float* out,
                           double* gacc, int* pcount, int* segs, const PieceStore& store,
                           unsigned long long* counters, hipStream_t s);
-// stage two, walk part: mode 0 counts pieces per pixel into pcount; mode 1 writes the
-// pieces of tiles [tile_lo, tile_hi) as (z, a, s) at rec + 3 * (poff[pixel] - base), for
-// pixels whose pieces end within rec_cap pieces of base.  Bins whose records end beyond
-// bin_cap are skipped.
-hipError_t launch_stage(int mode, const MeshDev& m, const FrameDev& f, const SlotDev* slots, const int* offsets,
-                        const int* counts, const int* records, long long bin_cap, const float* tf_rgba, int tile_lo,
-                        int tile_hi, int* pcount, const long long* poff, long long base, long long rec_cap,
-                        float* rec, unsigned long long* counters, hipStream_t s);
-// stage two, evaluation part for tiles [tile_lo, tile_hi) (tiles staged beyond rec_cap stay empty);
-// with store.pool set the pieces come from stage one's chunks (pcount per pixel) instead
-hipError_t launch_eval(int mm, const FrameDev& f, int tile_lo, int tile_hi, const long long* poff, long long base,
-                       long long rec_cap, const float* rec, const PieceStore& store, const int* pcount,
-                       const float* tf_rgba, const void* moments, const BoundParams& bp, float* rgba,
-                       unsigned long long* counters, hipStream_t s);
-// exclusive scan of the per-tile piece totals on the device
-hipError_t launch_tile_offsets(const long long* tile_tot, int n_tiles, long long* tile_off, hipStream_t s);
+// stage two, plain form: the rays are walked again and every piece is evaluated at once (no piece
+// is kept); rgba [H][W][4] receives the listed subdomains' colour sums, finalised with bp.finalize
+hipError_t launch_resolve(int mm, const MeshDev& m, const FrameDev& f, const SlotDev* slots, const int* offsets,
+                          const int* counts, const int* records, long long bin_cap, const float* tf_rgba,
+                          const void* moments, const BoundParams& bp, float* rgba, unsigned long long* counters,
+                          hipStream_t s);
+// stage two from the pieces stage one kept (store, pcount per pixel) for tiles [tile_lo, tile_hi)
+hipError_t launch_eval(int mm, const FrameDev& f, int tile_lo, int tile_hi, const PieceStore& store,
+                       const int* pcount, const float* tf_rgba, const void* moments, const BoundParams& bp,
+                       float* rgba, unsigned long long* counters, hipStream_t s);
 // FP16 packing of a global moment image
 hipError_t launch_pack_f16(const float* in, int m1, int64_t pixels, void* out_f16, hipStream_t s);
-hipError_t launch_tile_sums(const int* pcount, int n_tiles, long long* tile_tot, hipStream_t s);
-hipError_t launch_piece_offsets(const int* pcount, const long long* tile_off, int n_tiles, long long* poff,
-                                hipStream_t s);
 hipError_t launch_sum_moments(const float* in, int n_slots, const int* order, int64_t elems, float* out,
                               hipStream_t s);
 hipError_t launch_sum_images(const float* in, int n_slots, const int* order, int64_t pixels, const float* b0,

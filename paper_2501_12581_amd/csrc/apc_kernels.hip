@@ -222,8 +222,15 @@ __device__ __forceinline__ bool enter_face(const Ray& r, int id0, int id1, int i
   return true;
 }
 
+// Per-lane event counts, summed over the wavefront at the end of a kernel.  Events that are rare by design
+// (a walk cut off by its step limit, an exit face chosen by the tie fallback, an entry list or buffer that
+// overflowed) go straight to the device counters instead, so they hold no register in the walk.
 struct LaneCount {
-  unsigned pieces, steps, entries, steplimit, fallback, overflow, nonpd, tabled, tab_fallback, segments;
+  unsigned pieces, steps, entries, nonpd, tabled, tab_fallback, segments;
+  unsigned long long* ctr;
+  __device__ void rare(int which, unsigned n = 1u) {
+    if (n) atomicAdd(ctr + which, (unsigned long long)n);
+  }
 };
 
 // Cut the chord [t0, t1] (scalar s0 -> s1) at the lattice t_near + k*step and
@@ -273,9 +280,78 @@ __device__ __forceinline__ float lerp_nc(float a, float b, float fr) {
   return a * (1.0f - fr) + b * fr;
 }
 
+// Where a walk stands: the face (A, B, C) through which the ray entered the
+// current tet, with its positive side products, and the tet with the local
+// index of the vertex opposite that face.
+struct WalkPos {
+  VS A, B, C;
+  float pAB, pBC, pCA;
+  int tet, apex;
+};
+
+__device__ __forceinline__ WalkPos walk_start(const Entry& e, int tet, int apex) {
+  return WalkPos{e.A, e.B, e.C, e.pAB, e.pBC, e.pCA, tet, apex};
+}
+
+// One step of the walk: the face through which the ray leaves the current
+// tet and the depth and scalar where it does (tout >= tin); the position moves
+// to the tet behind that face.  Returns false when that face lies on the mesh
+// hull or leads out of the subdomain (tet range [t_lo, t_hi)).
+__device__ __forceinline__ bool walk_step(const MeshDev& M, const Ray& r, WalkPos& w, double tin, int t_lo, int t_hi,
+                                          double& tout, float& sout, LaneCount& cnt) {
+  // ids, neighbours and the apex vertex come from one 128-byte record, so
+  // the three loads go out together (no vertex load waiting on the ids)
+  const int4* rec = M.wrec + 8 * size_t(w.tet);
+  const int4 tv = rec[0];
+  const int4 tn = rec[1];
+  const float4 dp = reinterpret_cast<const float4*>(rec)[2 + w.apex];
+  const int did = sel4(tv, w.apex);
+  const VS D = vstate(r, did, dp);
+  const float qA = side(D, w.A), qB = side(D, w.B), qC = side(D, w.C);
+  // exit through the face opposite X where q(next of X) > 0 > q(previous of X)
+  int x;
+  if (qB > 0.0f && qC < 0.0f)
+    x = 0;
+  else if (qC > 0.0f && qA < 0.0f)
+    x = 1;
+  else if (qA > 0.0f && qB < 0.0f)
+    x = 2;
+  else {  // sign pattern no line can have (rounding near a vertex): least-violated face
+    float m0 = fminf(qB, -qC), m1 = fminf(qC, -qA), m2 = fminf(qA, -qB);
+    x = (m0 >= m1 && m0 >= m2) ? 0 : (m1 >= m2 ? 1 : 2);
+    cnt.rare(C_FALLBACK);
+  }
+  const int xid = x == 0 ? w.A.id : (x == 1 ? w.B.id : w.C.id);
+  // The exit face replaces X by D in place: (D, B, C), (A, D, C) and
+  // (A, B, D) are rotations of the exit faces (B, C, D), (C, A, D) and
+  // (A, B, D), so the cyclic order with positive products is kept.
+  const float nAB = x == 0 ? qB : (x == 1 ? -qA : w.pAB);
+  const float nBC = x == 0 ? w.pBC : (x == 1 ? qC : -qB);
+  const float nCA = x == 0 ? -qC : (x == 1 ? w.pCA : qA);
+  if (x == 0) w.A = D;
+  if (x == 1) w.B = D;
+  if (x == 2) w.C = D;
+  w.pAB = nAB;
+  w.pBC = nBC;
+  w.pCA = nCA;
+  face_point(w.A, w.B, w.C, w.pAB, w.pBC, w.pCA, tout, sout);
+  if (!(tout >= tin)) tout = tin;
+  ++cnt.steps;
+  const int xl = tv.x == xid ? 0 : (tv.y == xid ? 1 : (tv.z == xid ? 2 : 3));
+  const int nb = sel4(tn, xl);
+  if (nb < 0) return false;
+  const int t2 = nb >> 2;
+  if (t2 < t_lo || t2 >= t_hi) return false;
+  w.tet = t2;
+  w.apex = nb & 3;
+  return true;
+}
+
 // Walk the ray from an entry through the tets of one subdomain (tet range
 // [t_lo, t_hi)) until it leaves the subdomain, handing every chord to sink.
-// `apex` is the local index of the vertex opposite the entry face.
+// `apex` is the local index of the vertex opposite the entry face.  (The loop
+// body repeats walk_step's, written out: the stage-one kernel keeps fewer
+// registers that way.)
 template <class Sink>
 __device__ void walk(const MeshDev& M, const FrameDev& f, const Ray& r, int tet, int apex, Entry e, int t_lo,
                      int t_hi, Sink& sink, LaneCount& cnt) {
@@ -284,11 +360,9 @@ __device__ void walk(const MeshDev& M, const FrameDev& f, const Ray& r, int tet,
   double tin = e.t;
   for (int step = 0;; ++step) {
     if (step >= f.max_steps) {
-      ++cnt.steplimit;
+      cnt.rare(C_STEPLIMIT);
       return;
     }
-    // ids, neighbours and the apex vertex come from one 128-byte record, so
-    // the three loads go out together (no vertex load waiting on the ids)
     const int4* rec = M.wrec + 8 * size_t(tet);
     const int4 tv = rec[0];
     const int4 tn = rec[1];
@@ -296,7 +370,6 @@ __device__ void walk(const MeshDev& M, const FrameDev& f, const Ray& r, int tet,
     int did = sel4(tv, apex);
     VS D = vstate(r, did, dp);
     float qA = side(D, A), qB = side(D, B), qC = side(D, C);
-    // exit through the face opposite X where q(next of X) > 0 > q(previous of X)
     int x;
     if (qB > 0.0f && qC < 0.0f)
       x = 0;
@@ -304,15 +377,12 @@ __device__ void walk(const MeshDev& M, const FrameDev& f, const Ray& r, int tet,
       x = 1;
     else if (qA > 0.0f && qB < 0.0f)
       x = 2;
-    else {  // sign pattern no line can have (rounding near a vertex): least-violated face
+    else {
       float m0 = fminf(qB, -qC), m1 = fminf(qC, -qA), m2 = fminf(qA, -qB);
       x = (m0 >= m1 && m0 >= m2) ? 0 : (m1 >= m2 ? 1 : 2);
-      ++cnt.fallback;
+      cnt.rare(C_FALLBACK);
     }
     const int xid = x == 0 ? A.id : (x == 1 ? B.id : C.id);
-    // The exit face replaces X by D in place: (D, B, C), (A, D, C) and
-    // (A, B, D) are rotations of the exit faces (B, C, D), (C, A, D) and
-    // (A, B, D), so the cyclic order with positive products is kept.
     const float nAB = x == 0 ? qB : (x == 1 ? -qA : pAB);
     const float nBC = x == 0 ? pBC : (x == 1 ? qC : -qB);
     const float nCA = x == 0 ? -qC : (x == 1 ? pCA : qA);
@@ -372,10 +442,69 @@ __device__ __forceinline__ void stage_faces(const MeshDev& M, const int* rec, in
   }
 }
 
+// LDS writes of a wavefront visible to all its lanes (no workgroup barrier)
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The next (up to EMAX) entries of this lane's ray into one subdomain after
+// the key (last_t, last_c), sorted by (depth, code) into L; returns how many,
+// and sets `more` when there were others beyond them.  Must be called by the
+// whole wavefront (it stages faces cooperatively into the wavefront's own LDS
+// slice, so a workgroup may hold several wavefronts walking different tiles).
+template <int EMAX>
+__device__ int collect_entries(const MeshDev& M, const Ray& r, bool want, const int* rec, int n_rec, FaceL* faces,
+                               EntryList& L, float last_t, int last_c, bool& more) {
+  int n = 0;
+  more = false;
+  for (int c0 = 0; c0 < n_rec; c0 += CHUNK) {
+    int nc = min(CHUNK, n_rec - c0);
+    wave_sync();  // every lane is done with the previous chunk
+    stage_faces(M, rec + c0, nc, faces, L.lane);
+    wave_sync();
+    if (!want) continue;
+    for (int k = 0; k < nc; ++k) {
+      const FaceL& F = faces[k];
+      Entry e;
+      if (!enter_face(r, F.id0, F.id1, F.id2, F.p0, F.p1, F.p2, e)) continue;
+      const float et = float(e.t);  // sort key: the entry depth rounded to FP32
+      if (!key_less(last_t, last_c, et, F.code)) continue;  // walked in an earlier round
+      if (n == EMAX) {
+        more = true;
+        if (!key_less(et, F.code, L.T(n - 1), L.Cd(n - 1))) continue;
+        --n;  // evict the largest
+      }
+      int pos = n;
+      while (pos > 0 && key_less(et, F.code, L.T(pos - 1), L.Cd(pos - 1))) {
+        L.T(pos) = L.T(pos - 1);
+        L.Cd(pos) = L.Cd(pos - 1);
+        --pos;
+      }
+      L.T(pos) = et;
+      L.Cd(pos) = F.code;
+      ++n;
+    }
+  }
+  return n;
+}
+
+// Entry k of the list: the boundary face it crosses, as an entry state.
+__device__ __forceinline__ bool list_entry(const MeshDev& M, const Ray& r, EntryList& L, int k, Entry& e, int& t,
+                                           int& fc) {
+  const int code = L.Cd(k);
+  t = code >> 2;
+  fc = code & 3;
+  const int4 tv = M.tet[2 * t];
+  const int i0 = sel4(tv, kFaceOut[fc][0]), i1 = sel4(tv, kFaceOut[fc][1]), i2 = sel4(tv, kFaceOut[fc][2]);
+  return enter_face(r, i0, i1, i2, M.vert[i0], M.vert[i1], M.vert[i2], e);  // true: it was listed so
+}
+
 // All entries of this lane's ray into one subdomain, walked in (depth, code)
 // order.  Handles more than E_MAX entries by repeated rounds that pick the
 // next E_MAX entries after the last one walked.  Must be called by the whole
-// wavefront (it stages faces cooperatively).
+// wavefront.
 template <class Sink>
 __device__ void walk_subdomain(const MeshDev& M, const FrameDev& f, const Ray& r, bool valid, const int* rec,
                                int n_rec, const SlotDev& sl, FaceL* faces, EntryList& L, Sink& sink,
@@ -386,44 +515,12 @@ __device__ void walk_subdomain(const MeshDev& M, const FrameDev& f, const Ray& r
   while (true) {
     bool want = valid && more;
     if (!__any(want)) break;
-    int n = 0;
-    more = false;
-    for (int c0 = 0; c0 < n_rec; c0 += CHUNK) {
-      int nc = min(CHUNK, n_rec - c0);
-      __syncthreads();
-      stage_faces(M, rec + c0, nc, faces, threadIdx.x);
-      __syncthreads();
-      if (!want) continue;
-      for (int k = 0; k < nc; ++k) {
-        const FaceL& F = faces[k];
-        Entry e;
-        if (!enter_face(r, F.id0, F.id1, F.id2, F.p0, F.p1, F.p2, e)) continue;
-        const float et = float(e.t);  // sort key: the entry depth rounded to FP32
-        if (!key_less(last_t, last_c, et, F.code)) continue;  // walked in an earlier round
-        if (n == E_MAX) {
-          more = true;
-          if (!key_less(et, F.code, L.T(n - 1), L.Cd(n - 1))) continue;
-          --n;  // evict the largest
-        }
-        int pos = n;
-        while (pos > 0 && key_less(et, F.code, L.T(pos - 1), L.Cd(pos - 1))) {
-          L.T(pos) = L.T(pos - 1);
-          L.Cd(pos) = L.Cd(pos - 1);
-          --pos;
-        }
-        L.T(pos) = et;
-        L.Cd(pos) = F.code;
-        ++n;
-      }
-    }
-    if (more) ++cnt.overflow;
+    const int n = collect_entries<E_MAX>(M, r, want, rec, n_rec, faces, L, last_t, last_c, more);
+    if (more) cnt.rare(C_OVERFLOW);
     for (int k = 0; k < n; ++k) {
-      int code = L.Cd(k);
-      int t = code >> 2, fc = code & 3;
-      int4 tv = M.tet[2 * t];
-      int i0 = sel4(tv, kFaceOut[fc][0]), i1 = sel4(tv, kFaceOut[fc][1]), i2 = sel4(tv, kFaceOut[fc][2]);
       Entry e;
-      if (!enter_face(r, i0, i1, i2, M.vert[i0], M.vert[i1], M.vert[i2], e)) continue;  // cannot happen
+      int t, fc;
+      if (!list_entry(M, r, L, k, e, t, fc)) continue;  // cannot happen
       ++cnt.entries;
       const unsigned before = sink.pieces;
       walk(M, f, r, t, fc, e, sl.tet_begin, sl.tet_end, sink, cnt);
@@ -450,9 +547,6 @@ __device__ __forceinline__ void flush_counts(const LaneCount& c, unsigned long l
   flush_one(c.pieces, ctr + C_PIECES);
   flush_one(c.steps, ctr + C_STEPS);
   flush_one(c.entries, ctr + C_ENTRIES);
-  flush_one(c.steplimit, ctr + C_STEPLIMIT);
-  flush_one(c.fallback, ctr + C_FALLBACK);
-  flush_one(c.overflow, ctr + C_OVERFLOW);
   flush_one(c.nonpd, ctr + C_NONPD);
   flush_one(c.tabled, ctr + C_TABLED);
   flush_one(c.tab_fallback, ctr + C_TABFB);
@@ -593,6 +687,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_WALK_W
   const size_t HW = size_t(f.W) * f.H, pix = size_t(py) * f.W + px;
   EntryList L{ent_t, ent_c, lane};
   LaneCount cnt = {};
+  cnt.ctr = ctr;
   int covering = 0;  // subdomains with at least one piece on this ray
   // the global sum's FP64 partials: in registers for m <= 6 (room within the register budget of 3
   // wavefronts per SIMD), else in the per-pixel scratch gacc; the same additions either way
@@ -621,7 +716,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_WALK_W
       const SlotDev sl = slots[k];
       walk_subdomain(M, f, r, valid, records + offsets[bin], n_rec, sl, faces, L, sink, cnt);
     } else if (n_rec > 0) {
-      ++cnt.overflow;  // binned beyond the record capacity (never on an eagerly sized workspace)
+      cnt.rare(C_OVERFLOW);  // binned beyond the record capacity (never on an eagerly sized workspace)
     }
     cnt.pieces += sink.pieces;
     if (gacc) {
@@ -667,111 +762,13 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_WALK_W
   flush_counts(cnt, ctr);
 }
 
-// ------------------------------------------------------------------ stage two
+// ------------------------------------------------------------------ stage two, kept pieces
 //
-// Stage two is split in two kernels so that the per-sample FP64 moment bound
-// never runs inside the divergent tet walk:
-//   k_stage  walks the rays again exactly like stage one and writes every
-//            piece (warped depth z, optical depth a, scalar s) in walk order
-//            to a pixel-ordered buffer in HBM (per-pixel offsets come from the
-//            piece counts of stage one);
-//   k_eval   one wavefront per tile: the 64 lanes evaluate 64 consecutive
-//            pieces of the tile together (whatever pixel they belong to) with
-//            that pixel's Cholesky factor from LDS, then every pixel adds its
-//            own contributions in walk order, so the sum is deterministic.
-
-// counts the pieces each pixel ray generates (same walk, no output)
-struct CountSink {
-  const FrameDev* f;
-  unsigned pieces;
-  __device__ void chord(double t0, double t1, float s0, float s1) {
-    cut_chord(*f, t0, t1, s0, s1, [&](double, float, float) { ++pieces; });
-  }
-};
-
-// writes (z, a, s) of every piece of one pixel ray, in walk order; the walk
-// is the bit-identical repeat of the counting walk, and `cap` (the counted
-// pieces) bounds the writes regardless.  (Gathering pieces in registers to
-// write them in bursts cuts the HBM write bytes from 3.3x to 1.4x the staged
-// bytes but costs more in selects than the writes cost: measured slower.)
-struct StageSink {
-  const FrameDev* f;
-  const float* tfa;  // LDS alpha column
-  float* out;        // this pixel's records: 3 floats each
-  unsigned pieces;
-  unsigned cap;
-  __device__ void chord(double t0, double t1, float s0, float s1) {
-    cut_chord(*f, t0, t1, s0, s1, [&](double tm, float len, float s) {
-      int i0;
-      float fr, a, z;
-      tf_coord(*f, s, i0, fr);
-      float A = lerp_nc(tfa[i0], tfa[i0 + 1], fr);
-      piece_az(*f, tm, len, A, a, z);
-      if (pieces < cap) {
-        float* o = out + 3 * size_t(pieces);
-        o[0] = z;
-        o[1] = a;
-        o[2] = s;
-      }
-      ++pieces;
-    });
-  }
-};
-
-// Walk every pixel ray of a tile through the listed subdomains.  mode 0:
-// count pieces into pcount (tile-major); mode 1: write piece records at
-// poff[pixel] - base into rec.
-__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_WALK_WAVES, 8))) void k_stage(
-    MeshDev M, FrameDev f, const SlotDev* __restrict__ slots,
-                                                const int* __restrict__ offsets, const int* __restrict__ counts,
-                                                const int* __restrict__ records, long long bin_cap,
-                                                const float* __restrict__ tf_rgba,
-                                                int tile_lo, int mode, int* __restrict__ pcount,
-                                                const long long* __restrict__ poff, long long base,
-                                                long long rec_cap, float* __restrict__ rec, unsigned long long* ctr) {
-  extern __shared__ float4 dyn_lds[];
-  float* tfa = reinterpret_cast<float*>(dyn_lds);
-  __shared__ FaceL faces[CHUNK];
-  __shared__ float ent_t[E_MAX * WAVE];
-  __shared__ int ent_c[E_MAX * WAVE];
-  const int lane = threadIdx.x;
-  for (int i = lane; i < f.n_tf; i += WAVE) tfa[i] = tf_rgba[4 * i + 3];
-  const int tile = tile_lo + xcd_tile(blockIdx.x, gridDim.x);
-  const int tx = tile % f.tiles_x, ty = tile / f.tiles_x;
-  const int px = (tx << f.tw_log2) + (lane & ((1 << f.tw_log2) - 1)),
-            py = ty * (WAVE >> f.tw_log2) + (lane >> f.tw_log2);
-  const bool valid = px < f.W && py < f.H;
-  const Ray r = pixel_ray(f, valid ? py : 0, valid ? px : 0);
-  EntryList L{ent_t, ent_c, lane};
-  LaneCount cnt = {};
-  const size_t slot = size_t(tile) * WAVE + lane;
-  __syncthreads();
-  if (mode == 0) {
-    CountSink sink{&f, 0u};
-    for (int k = 0; k < f.n_slots; ++k) {
-      const int bin = tile * f.n_slots + k;
-      const int n_rec = counts[bin];
-      if (n_rec > 0 && offsets[bin] + n_rec <= bin_cap)
-        walk_subdomain(M, f, r, valid, records + offsets[bin], n_rec, slots[k], faces, L, sink, cnt);
-    }
-    pcount[slot] = int(sink.pieces);
-  } else {
-    // staged pieces beyond the buffer's capacity are not written (counted; never on an eagerly sized buffer)
-    const bool fits = poff[slot + 1] - base <= rec_cap;
-    const unsigned cap = fits ? unsigned(poff[slot + 1] - poff[slot]) : 0u;
-    cnt.overflow += fits ? 0u : 1u;
-    StageSink sink{&f, tfa, rec + 3 * (fits ? poff[slot] - base : 0), 0u, cap};
-    for (int k = 0; k < f.n_slots; ++k) {
-      const int bin = tile * f.n_slots + k;
-      const int n_rec = counts[bin];
-      if (n_rec > 0 && offsets[bin] + n_rec <= bin_cap)
-        walk_subdomain(M, f, r, valid, records + offsets[bin], n_rec, slots[k], faces, L, sink, cnt);
-    }
-    cnt.pieces += sink.pieces;
-    if (fits && sink.pieces != cap) ++cnt.overflow;  // a re-walk that disagrees with the count (never expected)
-  }
-  flush_counts(cnt, ctr);
-}
+// When stage one kept its pieces, stage two evaluates them without a walk:
+// one wavefront per tile takes the tile's pixels one at a time, and its 64
+// lanes evaluate 64 consecutive pieces of that pixel with the pixel's factor
+// from LDS; every pixel then adds its own contributions in a fixed order, so
+// the sum is deterministic.
 
 __device__ __forceinline__ float wave_uniform(float v) {
   return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
@@ -799,6 +796,45 @@ __device__ __forceinline__ float wave_sum_f(float v) {
   return v;
 }
 
+// The global moments b_0..b_2N of one pixel (zero for an invalid lane), from
+// the FP32 image [2N+1][H][W] or its packed FP16 form [2N+3][H][W] (ln b0 and
+// the mean, each as two halves, and the central moments); returns b0 in FP32.
+template <int N, class R>
+__device__ __forceinline__ float pixel_moments(const void* moments, int f16, bool valid, size_t pix, size_t HW,
+                                               R* b) {
+  constexpr int M1 = 2 * N + 1;
+  float b0f;
+  if (f16) {
+    const _Float16* hm = static_cast<const _Float16*>(moments);
+    const double lb0 = valid ? double(hm[pix]) + double(hm[HW + pix]) : -HUGE_VAL;
+    b0f = float(exp(lb0));  // exp(-inf) = 0: background
+    double c[M1];
+    c[0] = 1.0;
+    c[1] = 0.0;
+#pragma unroll
+    for (int k = 2; k < M1; ++k) c[k] = valid ? double(hm[size_t(k + 2) * HW + pix]) : 0.0;
+    const double mu = valid ? double(hm[2 * HW + pix]) + double(hm[3 * HW + pix]) : 0.0;
+    b[0] = R(b0f);
+#pragma unroll
+    for (int j = 1; j < M1; ++j) {  // beta_j = E[z^j] = sum_k C(j, k) mu^(j-k) E[(z - mu)^k]
+      double sum = 0.0, binom = 1.0, pw = 1.0;
+#pragma unroll
+      for (int k = j; k >= 0; --k) {  // term k: C(j, k) c_k mu^(j-k)
+        sum += binom * c[k] * pw;
+        pw *= mu;
+        binom = binom * double(k) / double(j - k + 1);
+      }
+      b[j] = R(sum * double(b0f));
+    }
+  } else {
+    const float* fm = static_cast<const float*>(moments);
+#pragma unroll
+    for (int j = 0; j < M1; ++j) b[j] = valid ? R(fm[size_t(j) * HW + pix]) : R(0);
+    b0f = valid ? fm[pix] : 0.0f;
+  }
+  return b0f;
+}
+
 // Moment bound for every staged piece of a tile and the per-pixel colour
 // sums (Alg. 1 second loop, Alg. 3).  The tile's pixels are taken one at a
 // time: the 64 lanes evaluate that pixel's consecutive pieces (so they share
@@ -823,20 +859,9 @@ __device__ __forceinline__ float wave_sum_f(float v) {
 // transfer-function table in LDS (the per-pixel state is per wavefront).
 constexpr int EVAL_WPB = 4;
 
-// LDS writes of a wavefront visible to all its lanes (no workgroup barrier)
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// CHUNKED: the pieces come from the store stage one kept (else from the staging buffer a re-walk filled);
-// fixed per launch, so the choice is a template parameter and the sample loop carries no branch on it
-template <int N, class R, bool CHUNKED>
+template <int N, class R>
 __global__ __launch_bounds__(WAVE * EVAL_WPB) __attribute__((amdgpu_waves_per_eu(N >= 4 ? APC_EVAL_WAVES_N4 : APC_EVAL_WAVES, 8))) void k_eval(
-    FrameDev f, int tile_lo, int tile_hi, const long long* __restrict__ poff,
-                                               long long base, long long rec_cap, const float* __restrict__ rec,
-                                               PieceStore ps, const int* __restrict__ pcount,
+    FrameDev f, int tile_lo, int tile_hi, PieceStore ps, const int* __restrict__ pcount,
                                                const float* __restrict__ tf_rgba, const void* __restrict__ moments,
                                                BoundParams bp, float* __restrict__ rgba,
                                                unsigned long long* ctr) {
@@ -871,12 +896,10 @@ __global__ __launch_bounds__(WAVE * EVAL_WPB) __attribute__((amdgpu_waves_per_eu
   const bool valid = px < f.W && py < f.H;
   const size_t HW = size_t(f.W) * f.H, pix = size_t(py) * f.W + px;
   const size_t slot0 = size_t(tile) * WAVE;
-  constexpr bool chunked = CHUNKED;  // pieces kept by stage one
-  long long tile_base = 0;
-  bool staged = true;
-  if (chunked) {  // per-pixel offsets within the tile: scan of the piece counts
-    // a lane of stage one that could not keep its pieces leaves its chunk table unset: then nothing is read
-    staged = ps.next[1] == 0;
+  // per-pixel offsets within the tile: scan of the piece counts.  A lane of stage one that could not keep
+  // its pieces leaves its chunk table unset: then nothing is read (counted)
+  const bool staged = ps.next[1] == 0;
+  {
     int c = staged ? pcount[slot0 + lane] : 0;
     const int own = c;
     for (int o = 1; o < WAVE; o <<= 1) {
@@ -885,49 +908,17 @@ __global__ __launch_bounds__(WAVE * EVAL_WPB) __attribute__((amdgpu_waves_per_eu
     }
     off_lds[lane] = c - own;
     if (lane == WAVE - 1) off_lds[WAVE] = c;
-  } else {
-    // a tile whose pieces lie beyond the staging buffer was not staged: it is left empty (counted)
-    tile_base = poff[slot0];
-    staged = poff[slot0 + WAVE] - base <= rec_cap;
-    off_lds[lane] = staged ? int(poff[slot0 + lane] - tile_base) : 0;
-    if (lane == 0) off_lds[WAVE] = staged ? int(poff[slot0 + WAVE] - tile_base) : 0;
   }
   LaneCount cnt = {};
-  cnt.overflow += (!staged && lane == 0) ? 1u : 0u;
+  cnt.ctr = ctr;
+  if (!staged && lane == 0) cnt.rare(C_OVERFLOW);
   // per-pixel part of Alg. 3, once per pixel instead of once per sample
   float b0f = 0.0f;
   {
     LdsBound<N, R> bound;
     bound.Li.base = li_lds + lane;
     R b[M1], bias[2 * N], zs[N];
-    if (bp.moments_f16) {  // ln b0 and the mean, each as two halves, and the central moments, in FP16
-      const _Float16* hm = static_cast<const _Float16*>(moments);
-      const double lb0 = valid ? double(hm[pix]) + double(hm[HW + pix]) : -HUGE_VAL;
-      b0f = float(exp(lb0));  // exp(-inf) = 0: background
-      double c[M1];
-      c[0] = 1.0;
-      c[1] = 0.0;
-#pragma unroll
-      for (int k = 2; k < M1; ++k) c[k] = valid ? double(hm[size_t(k + 2) * HW + pix]) : 0.0;
-      const double mu = valid ? double(hm[2 * HW + pix]) + double(hm[3 * HW + pix]) : 0.0;
-      b[0] = R(b0f);
-#pragma unroll
-      for (int j = 1; j < M1; ++j) {  // beta_j = E[z^j] = sum_k C(j, k) mu^(j-k) E[(z - mu)^k]
-        double sum = 0.0, binom = 1.0, pw = 1.0;
-#pragma unroll
-        for (int k = j; k >= 0; --k) {  // term k: C(j, k) c_k mu^(j-k)
-          sum += binom * c[k] * pw;
-          pw *= mu;
-          binom = binom * double(k) / double(j - k + 1);
-        }
-        b[j] = R(sum * double(b0f));
-      }
-    } else {
-      const float* fm = static_cast<const float*>(moments);
-#pragma unroll
-      for (int j = 0; j < M1; ++j) b[j] = valid ? R(fm[size_t(j) * HW + pix]) : R(0);
-      b0f = valid ? fm[pix] : 0.0f;
-    }
+    b0f = pixel_moments<N, R>(moments, bp.moments_f16, valid, pix, HW, b);
 #pragma unroll
     for (int j = 0; j < 2 * N; ++j) bias[j] = R(bp.bias[j]);
     cnt.nonpd += bound.setup(b, R(bp.alpha), bias, zs);
@@ -938,7 +929,6 @@ __global__ __launch_bounds__(WAVE * EVAL_WPB) __attribute__((amdgpu_waves_per_eu
     mode_lds[lane] = valid ? bound.mode : 0;
   }
   wave_sync();
-  const float* trec = chunked ? nullptr : rec + 3 * (tile_base - base);
   const R eta = R(bp.eta);
   float4 mine = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   for (int p = 0; p < WAVE; ++p) {  // uniform loop over the tile's pixels
@@ -970,29 +960,24 @@ __global__ __launch_bounds__(WAVE * EVAL_WPB) __attribute__((amdgpu_waves_per_eu
       }
     }
     float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
-    const int* chunks = chunked ? ps.ptab + (slot0 + p) * size_t(ps.maxc) : nullptr;
+    const int* chunks = ps.ptab + (slot0 + p) * size_t(ps.maxc);
     // the pixel's first 64 chunk ids, one per lane, fetched before the loop
     const int n_ch = (hi - lo + PIECE_CHUNK - 1) / PIECE_CHUNK;
-    const int my_ch = (chunked && lane < n_ch && lane < ps.maxc) ? chunks[lane] : 0;
+    const int my_ch = (lane < n_ch && lane < ps.maxc) ? chunks[lane] : 0;
     // the piece of step ib for this lane (z, a, s), or ok = false past the pixel's end.  Steps start at
     // lo + 64 k and a chunk holds 64 pieces, so a step's pieces are exactly chunk k of the pixel: its id is
     // the same for the whole wavefront (a scalar), and lane l reads the chunk's l-th record
     static_assert(PIECE_CHUNK == WAVE, "one evaluation step reads one chunk");
     auto fetch = [&](int ib, float& z, float& a, float& s, bool& ok) {
       ok = ib + lane < hi;
-      const float* pr;
-      if (chunked) {
-        const int k = (ib - lo) / PIECE_CHUNK;  // uniform
-        const int ch = k < WAVE ? __builtin_amdgcn_readlane(my_ch, k) : __builtin_amdgcn_readfirstlane(chunks[k]);
-        if (unsigned(ch) >= unsigned(ps.n_chunks)) {  // cannot happen when every lane kept its pieces; never read
-          cnt.overflow += ok ? 1u : 0u;
-          ok = false;
-          return;
-        }
-        pr = ps.pool + (size_t(ch) * PIECE_CHUNK + lane) * 3;
-      } else {
-        pr = trec + 3 * size_t(ib + lane);
+      const int k = (ib - lo) / PIECE_CHUNK;  // uniform
+      const int ch = k < WAVE ? __builtin_amdgcn_readlane(my_ch, k) : __builtin_amdgcn_readfirstlane(chunks[k]);
+      if (unsigned(ch) >= unsigned(ps.n_chunks)) {  // cannot happen when every lane kept its pieces; never read
+        if (ok) cnt.rare(C_OVERFLOW);
+        ok = false;
+        return;
       }
+      const float* pr = ps.pool + (size_t(ch) * PIECE_CHUNK + lane) * 3;
       if (!ok) return;
       z = pr[0];
       a = pr[1];
@@ -1039,57 +1024,299 @@ __global__ __launch_bounds__(WAVE * EVAL_WPB) __attribute__((amdgpu_waves_per_eu
   flush_counts(cnt, ctr);
 }
 
-// per-tile totals of the per-pixel piece counts (tile-major)
-__global__ void k_tile_sums(const int* __restrict__ pcount, int n_tiles, long long* __restrict__ tot) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_tiles) return;
-  long long s = 0;
-  for (int l = 0; l < WAVE; ++l) s += pcount[size_t(t) * WAVE + l];
-  tot[t] = s;
+// ------------------------------------------------------------------ stage two, fused re-walk
+//
+// The plain form of stage two (Alg. 1 second loop, Section 4.2): every ray is
+// walked again exactly like stage one (the same pieces with bit for bit the
+// same warped depths and optical depths), and each piece is weighted at once
+// by the transmittance the moment bound gives at its depth.  Per pixel nothing
+// but (m + 1) moments in and 4 colour sums out, whatever the depth
+// complexity; no piece is written to memory (a lane queues at most RQ of its
+// pieces in LDS until the wavefront evaluates them together).  Each lane holds
+// its pixel's inverse Cholesky factor and the zeros of the degree-n
+// orthonormal polynomial in registers, and (n >= 3) starts a sample's root
+// solve from the previous sample's roots (apcm::Bound::frac_before_cont).  The
+// wavefronts of a workgroup walk different tiles and share one copy of the
+// transfer function.
+#ifndef APC_RES_WPB
+#define APC_RES_WPB 4
+#endif
+constexpr int RES_WPB = APC_RES_WPB;
+// Waves per SIMD the fused kernel is compiled for (register budget 512 / n): the walk's FP64 ray frame,
+// the walk position and its pixel's inverse factor stay in registers across the evaluation
+#ifndef APC_RES_WAVES
+#define APC_RES_WAVES 2
+#endif
+#ifndef APC_RES_QUEUE
+#define APC_RES_QUEUE 12
+#endif
+#ifndef APC_RES_EMAX
+#define APC_RES_EMAX 8
+#endif
+constexpr int RQ = APC_RES_QUEUE;         // pieces queued per lane
+constexpr int RES_EMAX = APC_RES_EMAX;    // entries per ray held at once in the re-walk
+// walk steps a lane takes per iteration while its queue has room for another chord's pieces
+#ifndef APC_RES_BURST
+#define APC_RES_BURST 4
+#endif
+// A drain evaluates one queued piece per lane while at least this many lanes have one, or while some
+// lane's queue has no room for another chord's pieces (RQ - RES_ROOM queued: that lane cannot walk on)
+#ifndef APC_RES_DRAIN_MIN
+#define APC_RES_DRAIN_MIN 40
+#endif
+constexpr int RES_ROOM = 3;
+
+// Per-lane state of the fused re-walk: the pixel's moment bound, the colour
+// sums, a ring of queued pieces in LDS (lane-minor: the 64 lanes hit
+// distinct banks) and the chord being cut.  The walk only cuts chords and
+// queues pieces; the evaluation runs where the whole wavefront has
+// reconverged, one queued piece per lane, so the FP64 solve does not run at
+// the lane utilisation of the divergent walk.
+template <int N, class R>
+struct Resolver {
+  const FrameDev* f;
+  const float4* tf;  // LDS RGBA table
+  apcm::Bound<N, R> bound;
+  apcm::RegArray<N, R> zs;
+  typename apcm::Bound<N, R>::Cont cont;
+  R eta;
+  float a0, a1, a2, a3;
+  unsigned pieces, solved, closed_used;  // samples; of those, needing roots; of those, by the closed forms
+  float *qz, *qa, *qs;                   // [RQ][WAVE] each
+  int lane, head, len;
+  // the chord being cut (bit for bit cut_chord's arithmetic, resumable when the queue is full)
+  bool cutting;
+  double cu, ckf, ct0, ct1;
+  float cs0, cslope;
+  int cguard;
+
+  __device__ void start_cut(double t0, double t1, float s0, float s1) {
+#pragma clang fp contract(off)
+    const double len_c = t1 - t0;
+    cutting = len_c > 0.0;
+    if (!cutting) return;
+    cslope = (s1 - s0) / float(len_c);
+    ckf = floor((t0 - f->t_near) * f->inv_step) + 1.0;
+    cu = t0;
+    ct0 = t0;
+    ct1 = t1;
+    cs0 = s0;
+    cguard = 0;
+  }
+  // queue pieces of the chord being cut until it ends or the queue is full
+  __device__ void cut_more() {
+#pragma clang fp contract(off)
+    while (cutting && len < RQ) {
+      if (!(cu < ct1) || cguard >= (1 << 22)) {
+        cutting = false;
+        break;
+      }
+      ++cguard;
+      const double nxt = f->t_near + ckf * f->step;
+      ckf += 1.0;
+      if (nxt <= cu) continue;
+      const double v = fmin(nxt, ct1);
+      const double tm = 0.5 * (cu + v);
+      const float s = cs0 + cslope * float(tm - ct0);
+      int i0;
+      float fr, a, z;
+      tf_coord(*f, s, i0, fr);
+      piece_az(*f, tm, float(v - cu), lerp_nc(tf[i0].w, tf[i0 + 1].w, fr), a, z);  // as stage one
+      int slot = head + len;
+      slot -= slot >= RQ ? RQ : 0;
+      qz[slot * WAVE + lane] = z;
+      qa[slot * WAVE + lane] = a;
+      qs[slot * WAVE + lane] = s;
+      ++len;
+      ++pieces;
+      cu = v;
+    }
+  }
+  // evaluate the oldest queued piece (Alg. 1 second loop with Alg. 3's bound)
+  __device__ void eval_one() {
+    const int slot = head;
+    const float z = qz[slot * WAVE + lane], a = qa[slot * WAVE + lane], s = qs[slot * WAVE + lane];
+    head = head + 1 == RQ ? 0 : head + 1;
+    --len;
+    if (bound.mode == 0) return;  // no absorbance on the ray: every piece has a = 0
+    int i0;
+    float fr;
+    tf_coord(*f, s, i0, fr);
+    const float4 c0 = tf[i0], c1 = tf[i0 + 1];
+    R F;
+    if constexpr (N >= 3) {
+      int how;
+      F = bound.frac_before_cont(R(z), eta, zs, cont, how);
+      solved += how != 0 ? 1u : 0u;
+      closed_used += how == 2 ? 1u : 0u;
+    } else {
+      F = bound.frac_before(R(z), eta);
+    }
+    float T = __expf(-float(bound.b0 * F));
+    T = fminf(fmaxf(T, 0.0f), 1.0f);
+    const float w = T * (-expm1f(-a));
+    a0 += w * lerp_nc(c0.x, c1.x, fr);
+    a1 += w * lerp_nc(c0.y, c1.y, fr);
+    a2 += w * lerp_nc(c0.z, c1.z, fr);
+    a3 += w;
+  }
+  // called by the whole wavefront: one queued piece per lane while enough lanes have one or some lane's
+  // queue is too full to walk on (all: until every queue is empty).  Each round empties one slot of every
+  // non-empty queue, so after it every lane can take its next walk step or chord piece.
+  __device__ void drain(bool all) {
+    while (true) {
+      const unsigned long long ready = __ballot(len > 0);
+      if (!ready) break;
+      if (!all && __popcll(ready) < APC_RES_DRAIN_MIN && !__any(len > RQ - RES_ROOM)) break;
+      if (len > 0) eval_one();
+    }
+  }
+};
+
+// All entries of this lane's ray into one subdomain, walked in (depth, code)
+// order, one walk step (or one entry start, or the rest of a chord) per lane
+// per iteration of a loop the whole wavefront runs, with the queue drained
+// between iterations.  The pieces, their order per ray and every depth are
+// those of walk_subdomain.
+template <int N, class R>
+__device__ void walk_subdomain_queued(const MeshDev& M, const FrameDev& f, const Ray& r, bool valid, const int* rec,
+                                      int n_rec, const SlotDev& sl, FaceL* faces, EntryList& L, Resolver<N, R>& q,
+                                      LaneCount& cnt) {
+  float last_t = -FLT_MAX;
+  int last_c = -1;
+  bool more = true;
+  while (true) {
+    const bool want = valid && more;
+    if (!__any(want)) break;
+    const int n = collect_entries<RES_EMAX>(M, r, want, rec, n_rec, faces, L, last_t, last_c, more);
+    if (more) cnt.rare(C_OVERFLOW);
+    int k = 0, steps = 0;
+    bool walking = false, open = false;  // a walk in progress; an entry whose segment is still counted
+    unsigned seg_start = 0;
+    WalkPos w;
+    double tin = 0.0;
+    float sin_ = 0.0f;
+    while (true) {
+      const bool busy = q.cutting || walking || k < n;
+      if (!__any(busy)) break;
+      if (!q.cutting && !walking && k < n) {  // the next entry
+        Entry e;
+        int t, fc;
+        if (list_entry(M, r, L, k, e, t, fc)) {
+          ++cnt.entries;
+          w = walk_start(e, t, fc);
+          tin = e.t;
+          sin_ = e.s;
+          walking = true;
+          steps = 0;
+          open = true;
+          seg_start = q.pieces;
+        }
+        ++k;
+      }
+      if (q.cutting) q.cut_more();  // the rest of a chord that did not fit the queue
+      // a few walk steps while the queue has room for their pieces
+      for (int burst = 0; !q.cutting && walking && burst < APC_RES_BURST && q.len <= RQ - RES_ROOM; ++burst) {
+        if (steps >= f.max_steps) {
+          cnt.rare(C_STEPLIMIT);
+          walking = false;
+          break;
+        }
+        double tout;
+        float sout;
+        walking = walk_step(M, r, w, tin, sl.tet_begin, sl.tet_end, tout, sout, cnt);
+        ++steps;
+        q.start_cut(tin, tout, sin_, sout);
+        q.cut_more();
+        tin = tout;
+        sin_ = sout;
+      }
+      if (open && !walking && !q.cutting) {  // a maximal ray interval inside the subdomain ended
+        cnt.segments += q.pieces > seg_start ? 1u : 0u;
+        open = false;
+      }
+      q.drain(false);
+    }
+    if (n > 0) {
+      last_t = L.T(n - 1);
+      last_c = L.Cd(n - 1);
+    }
+  }
 }
 
-// exclusive prefix of the tile-major piece counts in 64-bit (one block per
-// tile: lane-level scan inside, tile bases from the scanned tile totals)
-__global__ void k_piece_offsets(const int* __restrict__ pcount, const long long* __restrict__ tile_off,
-                                int n_tiles, long long* __restrict__ poff) {
-  __shared__ long long part[WAVE];
-  const int t = blockIdx.x, lane = threadIdx.x;
-  const long long v = pcount[size_t(t) * WAVE + lane];
-  part[lane] = v;
-  __syncthreads();
-  for (int o = 1; o < WAVE; o <<= 1) {
-    long long add = lane >= o ? part[lane - o] : 0;
-    __syncthreads();
-    part[lane] += add;
-    __syncthreads();
+template <int N, class R>
+__global__ __launch_bounds__(WAVE * RES_WPB) __attribute__((amdgpu_waves_per_eu(APC_RES_WAVES, 8))) void k_resolve(
+    MeshDev M, FrameDev f, const SlotDev* __restrict__ slots, const int* __restrict__ offsets,
+    const int* __restrict__ counts, const int* __restrict__ records, long long bin_cap,
+    const float* __restrict__ tf_rgba, const void* __restrict__ moments, BoundParams bp, float* __restrict__ rgba,
+    unsigned long long* ctr) {
+  extern __shared__ float4 dyn_lds[];
+  float4* tf = dyn_lds;  // [n_tf] RGBA
+  __shared__ FaceL faces_all[RES_WPB][CHUNK];
+  __shared__ float ent_t_all[RES_WPB][RES_EMAX * WAVE];
+  __shared__ int ent_c_all[RES_WPB][RES_EMAX * WAVE];
+  __shared__ float queue_all[RES_WPB][3][RQ * WAVE];
+  for (int i = threadIdx.x; i < f.n_tf; i += WAVE * RES_WPB)
+    tf[i] = make_float4(tf_rgba[4 * i], tf_rgba[4 * i + 1], tf_rgba[4 * i + 2], tf_rgba[4 * i + 3]);
+  __syncthreads();  // the only workgroup barrier: every later wait is within a wavefront
+  const int wv = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x, (XCD_RUN + RES_WPB - 1) / RES_WPB) * RES_WPB + wv;
+  if (tile >= f.n_tiles) return;
+  const int tx = tile % f.tiles_x, ty = tile / f.tiles_x;
+  const int px = (tx << f.tw_log2) + (lane & ((1 << f.tw_log2) - 1)),
+            py = ty * (WAVE >> f.tw_log2) + (lane >> f.tw_log2);
+  const bool valid = px < f.W && py < f.H;
+  const Ray r = pixel_ray(f, valid ? py : 0, valid ? px : 0);
+  const size_t HW = size_t(f.W) * f.H, pix = size_t(py) * f.W + px;
+  LaneCount cnt = {};
+  cnt.ctr = ctr;
+  Resolver<N, R> q;
+  q.f = &f;
+  q.tf = tf;
+  q.eta = R(bp.eta);
+  q.a0 = q.a1 = q.a2 = q.a3 = 0.0f;
+  q.pieces = q.solved = q.closed_used = 0u;
+  q.qz = queue_all[wv][0];
+  q.qa = queue_all[wv][1];
+  q.qs = queue_all[wv][2];
+  q.lane = lane;
+  q.head = q.len = 0;
+  q.cutting = false;
+  q.cont.k = -1;
+#pragma unroll
+  for (int c = 0; c < int(sizeof(q.cont.v) / sizeof(R)); ++c) q.cont.v[c] = R(0);
+  float b0f;
+  {  // per-pixel part of Alg. 3, once per pixel instead of once per sample
+    R b[2 * N + 1], bias[2 * N], zsr[N];
+    b0f = pixel_moments<N, R>(moments, bp.moments_f16, valid, pix, HW, b);
+#pragma unroll
+    for (int j = 0; j < 2 * N; ++j) bias[j] = R(bp.bias[j]);
+    cnt.nonpd += q.bound.setup(b, R(bp.alpha), bias, zsr);
+#pragma unroll
+    for (int i = 0; i < N; ++i) q.zs.v[i] = zsr[i];
+    // no zeros found (never expected for a positive definite factor): no shortcut, every sample solves
+    if (q.bound.mode == 2 && !(zsr[0] < zsr[N - 1])) {
+      q.bound.xlo = -R(HUGE_VAL);
+      q.bound.xhi = R(HUGE_VAL);
+    }
   }
-  poff[size_t(t) * WAVE + lane] = tile_off[t] + part[lane] - v;
-  if (t == n_tiles - 1 && lane == WAVE - 1) poff[size_t(n_tiles) * WAVE] = tile_off[t] + part[lane];
-}
-
-// exclusive scan of the per-tile piece totals on the device (one workgroup;
-// each thread sums a contiguous run), for frames that may not wait on the host
-__global__ __launch_bounds__(1024) void k_tile_offsets(const long long* __restrict__ tot, int n,
-                                                       long long* __restrict__ off) {
-  __shared__ long long part[1024];
-  const int t = threadIdx.x;
-  const int per = (n + 1023) / 1024;
-  const int lo = min(n, t * per), hi = min(n, lo + per);
-  long long s = 0;
-  for (int i = lo; i < hi; ++i) s += tot[i];
-  part[t] = s;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    const long long add = t >= o ? part[t - o] : 0;
-    __syncthreads();
-    part[t] += add;
-    __syncthreads();
+  EntryList L{ent_t_all[wv], ent_c_all[wv], lane};
+  for (int k = 0; k < f.n_slots; ++k) {
+    const int bin = tile * f.n_slots + k;
+    const int n_rec = counts[bin];
+    if (n_rec > 0 && offsets[bin] + n_rec <= bin_cap)
+      walk_subdomain_queued(M, f, r, valid, records + offsets[bin], n_rec, slots[k], faces_all[wv], L, q, cnt);
+    else if (n_rec > 0)
+      cnt.rare(C_OVERFLOW);  // binned beyond the record capacity (never on an eagerly sized workspace)
   }
-  long long run = part[t] - s;
-  for (int i = lo; i < hi; ++i) {
-    off[i] = run;
-    run += tot[i];
-  }
+  q.drain(true);
+  cnt.pieces += q.pieces;
+  cnt.tabled += q.solved;
+  cnt.tab_fallback += q.closed_used;
+  if (valid)
+    reinterpret_cast<float4*>(rgba)[pix] =
+        finalize_px(make_float4(q.a0, q.a1, q.a2, q.a3), b0f, bp.finalize, bp.renormalize);
+  flush_counts(cnt, ctr);
 }
 
 // walk records: [ids][neighbours][v0][v1][v2][v3], 8 x 16 bytes per tet
@@ -1422,40 +1649,39 @@ hipError_t launch_moments(int mm, const MeshDev& m, const FrameDev& f, const Slo
   return hipGetLastError();
 }
 
-hipError_t launch_stage(int mode, const MeshDev& m, const FrameDev& f, const SlotDev* slots, const int* offsets,
-                        const int* counts, const int* records, long long bin_cap, const float* tf_rgba, int tile_lo,
-                        int tile_hi, int* pcount, const long long* poff, long long base, long long rec_cap,
-                        float* rec, unsigned long long* counters, hipStream_t s) {
-  if (tile_hi <= tile_lo) return hipSuccess;
-  const size_t lds = size_t(f.n_tf) * sizeof(float);
-  hipLaunchKernelGGL(k_stage, dim3(tile_hi - tile_lo), dim3(WAVE), lds, s, m, f, slots, offsets, counts, records,
-                     bin_cap, tf_rgba, tile_lo, mode, pcount, poff, base, rec_cap, rec, counters);
-  return hipGetLastError();
-}
-
-hipError_t launch_eval(int mm, const FrameDev& f, int tile_lo, int tile_hi, const long long* poff, long long base,
-                       long long rec_cap, const float* rec, const PieceStore& store, const int* pcount,
-                       const float* tf_rgba, const void* moments, const BoundParams& bp,
+hipError_t launch_eval(int mm, const FrameDev& f, int tile_lo, int tile_hi, const PieceStore& store,
+                       const int* pcount, const float* tf_rgba, const void* moments, const BoundParams& bp,
                        float* rgba, unsigned long long* counters, hipStream_t s) {
   if (tile_hi <= tile_lo) return hipSuccess;
   const size_t lds = size_t(f.n_tf) * sizeof(float4);
   const dim3 grid((tile_hi - tile_lo + EVAL_WPB - 1) / EVAL_WPB), block(WAVE * EVAL_WPB);
-#define APC_LAUNCH_EVAL(N, R)                                                                                  \
-  do {                                                                                                         \
-    if (store.pool)                                                                                            \
-      hipLaunchKernelGGL((k_eval<N, R, true>), grid, block, lds, s, f, tile_lo, tile_hi, poff, base, rec_cap,  \
-                         rec, store, pcount, tf_rgba, moments, bp, rgba, counters);                            \
-    else                                                                                                       \
-      hipLaunchKernelGGL((k_eval<N, R, false>), grid, block, lds, s, f, tile_lo, tile_hi, poff, base, rec_cap, \
-                         rec, store, pcount, tf_rgba, moments, bp, rgba, counters);                            \
-  } while (0)
   if (mm == 4)
-    APC_LAUNCH_EVAL(2, float);
+    hipLaunchKernelGGL((k_eval<2, float>), grid, block, lds, s, f, tile_lo, tile_hi, store, pcount, tf_rgba, moments,
+                       bp, rgba, counters);
   else if (mm == 6)
-    APC_LAUNCH_EVAL(3, double);
+    hipLaunchKernelGGL((k_eval<3, double>), grid, block, lds, s, f, tile_lo, tile_hi, store, pcount, tf_rgba,
+                       moments, bp, rgba, counters);
   else
-    APC_LAUNCH_EVAL(4, double);
-#undef APC_LAUNCH_EVAL
+    hipLaunchKernelGGL((k_eval<4, double>), grid, block, lds, s, f, tile_lo, tile_hi, store, pcount, tf_rgba,
+                       moments, bp, rgba, counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_resolve(int mm, const MeshDev& m, const FrameDev& f, const SlotDev* slots, const int* offsets,
+                          const int* counts, const int* records, long long bin_cap, const float* tf_rgba,
+                          const void* moments, const BoundParams& bp, float* rgba, unsigned long long* counters,
+                          hipStream_t s) {
+  const size_t lds = size_t(f.n_tf) * sizeof(float4);
+  const dim3 grid((f.n_tiles + RES_WPB - 1) / RES_WPB), block(WAVE * RES_WPB);
+  if (mm == 4)
+    hipLaunchKernelGGL((k_resolve<2, float>), grid, block, lds, s, m, f, slots, offsets, counts, records, bin_cap,
+                       tf_rgba, moments, bp, rgba, counters);
+  else if (mm == 6)
+    hipLaunchKernelGGL((k_resolve<3, double>), grid, block, lds, s, m, f, slots, offsets, counts, records, bin_cap,
+                       tf_rgba, moments, bp, rgba, counters);
+  else
+    hipLaunchKernelGGL((k_resolve<4, double>), grid, block, lds, s, m, f, slots, offsets, counts, records, bin_cap,
+                       tf_rgba, moments, bp, rgba, counters);
   return hipGetLastError();
 }
 
@@ -1469,23 +1695,6 @@ hipError_t launch_pack_f16(const float* in, int m1, int64_t pixels, void* out_f1
 hipError_t launch_walk_records(const int4* tet, const float4* vert, int64_t n_tets, int4* wrec, hipStream_t s) {
   if (n_tets <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_walk_records, dim3(grid1(n_tets, 256)), dim3(256), 0, s, tet, vert, n_tets, wrec);
-  return hipGetLastError();
-}
-
-hipError_t launch_tile_offsets(const long long* tile_tot, int n_tiles, long long* tile_off, hipStream_t s) {
-  if (n_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_tile_offsets, dim3(1), dim3(1024), 0, s, tile_tot, n_tiles, tile_off);
-  return hipGetLastError();
-}
-
-hipError_t launch_tile_sums(const int* pcount, int n_tiles, long long* tile_tot, hipStream_t s) {
-  hipLaunchKernelGGL(k_tile_sums, dim3(grid1(n_tiles, 256)), dim3(256), 0, s, pcount, n_tiles, tile_tot);
-  return hipGetLastError();
-}
-
-hipError_t launch_piece_offsets(const int* pcount, const long long* tile_off, int n_tiles, long long* poff,
-                                hipStream_t s) {
-  hipLaunchKernelGGL(k_piece_offsets, dim3(n_tiles), dim3(WAVE), 0, s, pcount, tile_off, n_tiles, poff);
   return hipGetLastError();
 }
 

@@ -320,7 +320,38 @@ APC_HD int poly_roots_body(const R* q, R* x) {
     }
   }
   int nr = 0;
-  if (deg == 1) {
+  if (N >= 3 && deg == N && m_abs(q[N]) < R(1e-4) * cmax) {
+    // A small leading coefficient: one root lies far out (the sample depth is near a zero of the degree-N
+    // orthonormal polynomial).  Made monic, the polynomial's other coefficients would swamp the closed
+    // forms; instead the far root comes from the two leading coefficients, refined by Newton on the full
+    // polynomial, and is divided out from the low end (b_0 = -q_0 / r, b_j = (b_(j-1) - q_j) / r), which is
+    // stable for a large root; the quotient's roots come from the closed forms one degree lower.
+    R r = -q[N - 1] * m_rcp(q[N]);
+#pragma unroll
+    for (int it = 0; it < 3; ++it) {
+      R p = q[N], dp = R(0);
+#pragma unroll
+      for (int j = N - 1; j >= 0; --j) {
+        dp = dp * r + p;
+        p = p * r + q[j];
+      }
+      if (dp != R(0)) {
+        const R rn = r - p * m_rcp(dp);
+        if (m_finite(rn)) r = rn;
+      }
+    }
+    R b[N];
+    const R ir = m_rcp(r);
+    b[0] = -q[0] * ir;
+#pragma unroll
+    for (int j = 1; j < N; ++j) b[j] = (b[j - 1] - q[j]) * ir;
+    if constexpr (N == 4) {
+      nr = roots3(b, x) + 1;
+    } else {
+      nr = roots2(b[0], b[1], b[2], x) + 1;
+    }
+    x[N - 1] = r;
+  } else if (deg == 1) {
     x[0] = -q[0] * m_rcp(q[1]);
     nr = 1;
   } else if (deg == 2) {
@@ -413,6 +444,20 @@ APC_HD R pick_reg(const R* a, int i) {
   for (int t = 0; t < K; ++t) r += R(i == t ? 1 : 0) * a[t];
   return r;
 }
+
+// K values held in registers, read with a run-time index through a chain of
+// selects (never an indexed register or scratch access; a constant index
+// folds to the element itself).
+template <int K, class R>
+struct RegArray {
+  R v[K];
+  APC_HD R operator[](int i) const {
+    R r = v[0];
+#pragma unroll
+    for (int t = 1; t < K; ++t) r = i == t ? v[t] : r;
+    return r;
+  }
+};
 
 // Per-pixel state of the bound.
 template <int N, class R, class Store = ArrayStore<(N + 1) * (N + 2) / 2, R>>
@@ -595,13 +640,14 @@ struct Bound {
 
   // regularised position of root r of gap j, for z in gap (lo, hi) with
   // sz = (z - lo) / (hi - z): finite and smooth in z up to both gap ends
+  // (reciprocal estimates: the value only seeds a later Newton iteration)
   template <class Z>
   APC_HD static R to_table(const Z& zs, int j, R r, R sz) {
     if (j == 0) return (r - zs[0]) * sz;
-    if (j == N) return (r - zs[N - 1]) / sz;
+    if (j == N) return (r - zs[N - 1]) * m_rcp_est(sz);
     const R a = pick<N>(zs, j - 1), b = pick<N>(zs, j);
-    const R fr = (r - a) / (b - a);
-    return fr / ((R(1) - fr) * sz);
+    const R fr = (r - a) * m_rcp_est(b - a);
+    return fr * m_rcp_est((R(1) - fr) * sz);
   }
   template <class Z>
   APC_HD static R from_table(const Z& zs, int j, R v, R sz, R isz) {
@@ -704,16 +750,129 @@ struct Bound {
         const R lam = m_rcp(kernel_diag(x));
         const R ad = m_abs(d);
         // converged: a small last step, or (outer gaps, where K grows away
-        // from the zeros) a weight too small for the step to matter
+        // from the zeros) a weight too small for the step to matter -- from an
+        // iterate that has settled (a step small against its distance to the
+        // gap's edge; one running off to infinity has a tiny weight too)
         const R edge = j == 0 ? bhi : blo;
         const bool conv = ad <= R(1e-7) * m_max(R(1), m_abs(x)) ||
-                          ((j == 0 || j == N) && lam * ad <= R(1e-12) * m_abs(x - edge));
+                          ((j == 0 || j == N) && lam * ad <= R(1e-12) * m_abs(x - edge) &&
+                           ad <= R(1e-3) * m_abs(x - edge));
         ok = ok && x > blo && x < bhi && conv;
         S += lam;
       }
     }
     F = 2 * kk <= N ? eta * lam0 + S : R(1) - (R(1) - eta) * lam0 - S;
     return ok;
+  }
+
+  // ---- continuation along one ray (the fused re-walk of stage two)
+  //
+  // Consecutive samples of a ray lie close in depth, and inside one gap the
+  // roots a sample needs move smoothly with z -- except that the outer roots
+  // run to infinity like 1 / (distance to one gap end).  Cont therefore holds
+  // each root in the table's regularised coordinate (to_table), which stays
+  // smooth up to both gap ends, and the previous sample's value, mapped back
+  // with this sample's gap coordinate, is the Newton start.  Cont also holds
+  // the gap of the last sample whose roots were found (-1: none).  A sample in
+  // another gap (or after a failure) takes its starts from the closed forms.
+  // Either way the roots must converge inside their gaps (the table path's
+  // test), else the sample takes the closed-form bound, so the start changes
+  // the cost of a sample but not its result beyond rounding.
+  static constexpr int CONT_STEPS = 4;  // Newton steps from a continued (or closed-form) start
+  struct Cont {
+    int k;
+    R v[Gaps<N>::NC > 0 ? Gaps<N>::NC : 1];  // regularised roots (to_table) of gap k
+  };
+
+  // Fraction of the absorbance in front of z; `how` says how the roots were
+  // found: 0 none needed, 1 Newton from the previous sample's roots, 2 the
+  // closed forms ran (a new gap, or no convergence).  zs: the sorted zeros.
+  template <class Z>
+  APC_HD R frac_before_cont(R z, R eta, const Z& zs, Cont& c, int& how) const {
+    constexpr int NC = Gaps<N>::NC;
+    bool closed = false;
+    how = 0;
+    if (mode == 1) {
+      if (m_abs(z1 - z) <= Num<R>::same_depth) return eta;
+      return z1 < z ? R(1) : R(0);
+    }
+    R P[N + 1];
+    values(z, P);
+    R K0 = R(0);
+#pragma unroll
+    for (int k = 0; k <= N; ++k) K0 += P[k] * P[k];
+    const R lam0 = m_rcp(K0);
+    if (z < xlo) return eta * lam0;
+    if (z > xhi) return R(1) - (R(1) - eta) * lam0;
+    R q[N + 1];
+    coeffs(P, q);
+    int k = 0;
+#pragma unroll
+    for (int t = 0; t < N; ++t) k += zs[t] < z ? 1 : 0;
+    bool ok = k >= 1 && k <= N - 1;
+    const int kk = ok ? k : 1;
+    const int nn = side_count(kk);
+    const R lo = zs[kk - 1], hi = zs[kk];
+    const R sz = (z - lo) * m_rcp_est(hi - z);  // the gap coordinate only maps Newton starts
+    R x[NC];
+    if (ok && kk == c.k) {
+      const R isz = (hi - z) * m_rcp_est(z - lo);  // the start needs no more
+#pragma unroll
+      for (int cc = 0; cc < NC; ++cc) x[cc] = cc < nn ? from_table(zs, side_gap(kk, cc), c.v[cc], sz, isz) : R(0);
+    } else {  // starts from the closed forms, sorted, on the fewer-node side of the gap
+      closed = true;
+      R r[N];
+#pragma unroll
+      for (int t = 0; t < N; ++t) r[t] = R(0);
+      const int nr = poly_roots<N, R, 1>(q, r);
+      sort_up(r);
+      ok = ok && nr == N;
+#pragma unroll
+      for (int cc = 0; cc < NC; ++cc) {
+        const int j = side_gap(kk, cc);
+        x[cc] = (cc < nn) ? pick_reg<N>(r, j < kk ? j : j - 1) : R(0);
+      }
+    }
+    R S = R(0);
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) {
+      if (cc < nn) {
+        const int j = side_gap(kk, cc);
+        R xi = x[cc], d = R(0);
+#pragma unroll
+        for (int it = 0; it < CONT_STEPS; ++it) {
+          R p = q[N], dp = R(0);
+#pragma unroll
+          for (int t = N - 1; t >= 0; --t) {
+            dp = dp * xi + p;
+            p = p * xi + q[t];
+          }
+          d = p * m_rcp_est(dp);
+          xi -= d;
+        }
+        const R blo = j == 0 ? -R(HUGE_VAL) : pick<N>(zs, j - 1);
+        const R bhi = j == N ? R(HUGE_VAL) : pick<N>(zs, j);
+        const R lam = m_rcp(kernel_diag(xi));
+        const R ad = m_abs(d);
+        const R edge = j == 0 ? bhi : blo;
+        const bool conv = ad <= R(1e-7) * m_max(R(1), m_abs(xi)) ||
+                          ((j == 0 || j == N) && lam * ad <= R(1e-12) * m_abs(xi - edge) &&
+                           ad <= R(1e-3) * m_abs(xi - edge));
+        ok = ok && xi > blo && xi < bhi && conv;
+        x[cc] = xi;
+        S += lam;
+      }
+    }
+    if (!ok) {
+      c.k = -1;
+      how = 2;
+      return closed_tail(z, eta, lam0, q);
+    }
+    how = closed ? 2 : 1;
+    c.k = kk;
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) c.v[cc] = cc < nn ? to_table(zs, side_gap(kk, cc), x[cc], sz) : R(0);
+    return 2 * kk <= N ? eta * lam0 + S : R(1) - (R(1) - eta) * lam0 - S;
   }
 };
 

@@ -1,15 +1,16 @@
 """Render-request serving over the library: a resident mesh, continuous batching, admission by HBM footprint.
 
 A `Server` keeps one mesh resident and runs frames for a stream of requests (image size, camera, number of
-moments, transfer function).  It has `slots`: each slot is a library context (its own workspace, capped by
-`apc_set_workspace_limit`) with its own HIP stream, driven by one worker thread.  In "batched" mode a request
-is admitted as soon as it has arrived, a slot that can hold its size is free and its buffers fit the HBM budget
-beside the requests already in flight, so frames of different requests overlap on the device.  Slots come in
-two sizes: large ones take any request, small ones only requests up to a smaller image size, with a workspace
-sized for those (the kept pieces of a frame grow with its pixels, so HBM holds more small slots).  In "fifo" mode one request runs at
-a time in arrival order (the plain per-request form).  A frame is stage one summing every subdomain itself
-(`APC_MOMENTS_GLOBAL`: the server holds the whole mesh) and the resolve pass.  Every step of a frame runs in
-the library's kernels; this module only schedules, allocates buffers and times.
+moments, transfer function).  It has `slots`: each slot is a library context (its own workspace) with its own
+HIP stream, driven by one worker thread.  In "batched" mode a request is admitted as soon as it has arrived, a
+slot that can hold its size is free and its HBM footprint (its images and the library workspace a frame of its
+size needs, see Server.footprint) fits the budget beside the requests already in flight, so frames of
+different requests overlap on the device; each frame's interval on the device is taken from HIP events on its
+slot's stream.  Slots come in two sizes: large ones take any request, small ones only requests up to a smaller
+image size.  In "fifo" mode one request runs at a time in arrival order.  A frame is stage one summing every
+subdomain itself (`APC_MOMENTS_GLOBAL`: the server holds the whole mesh) and the resolve pass, in the plain
+form (stage two walks again) unless the server keeps pieces.  Every step of a frame runs in the library's
+kernels; this module only schedules, allocates buffers and times.
 """
 from __future__ import annotations
 
@@ -40,15 +41,16 @@ def look_at_view(eye, target, width: int, height: int, fovy_deg: float = 45.0) -
 class Server:
     def __init__(self, mesh, step, tfs, s_range, kappa=4.0, absorbance_max=10.0, alpha=5e-5, eta=0.3,
                  slots=4, workspace_limit=8 << 30, hbm_budget=64 << 30, max_size=2048, max_m=8, device=0,
-                 small_slots=0, small_size=1024, small_workspace_limit=None):
+                 small_slots=0, small_size=1024, small_workspace_limit=None, keep=False):
         """mesh: arrays (xyz, scalar, tets, tet_sub, n_sub); tfs: list of [n][4] float32 tables;
         s_range: (s_min, s_max) of the transfer functions' domain; workspace_limit: bytes per slot for the
-        kept-piece pool + staging; hbm_budget: bytes of the requests' own buffers allowed in flight;
+        kept-piece pool; hbm_budget: bytes of the requests' footprints (see footprint) allowed in flight;
         max_size, max_m: the largest request, for which every slot's buffers are allocated once (no
         allocation while serving: device allocations would synchronise the other slots' work).
         small_slots more slots take only requests up to small_size^2, with small_workspace_limit bytes each
         (default: workspace_limit scaled by the pixel ratio): a slot's workspace must hold the kept pieces
-        of its largest frame, so HBM allows more small slots than large ones."""
+        of its largest frame, so HBM allows more small slots than large ones.  keep: frames keep their pieces
+        in stage one for stage two (APC_KEEP_PIECES) instead of walking twice (the plain form)."""
         import torch
         self.torch = torch
         self.device = device
@@ -56,6 +58,8 @@ class Server:
         self.owner = Context(device)
         xyz, scalar, tets, tet_sub, n_sub = mesh
         self.mesh = self.owner.load_mesh(xyz, scalar, tets, tet_sub, n_sub)
+        self.n_boundary_faces = self.mesh.info()["n_boundary_faces"]
+        self.slot_ws = None  # measured by warm()
         self.n_sub = n_sub
         self.subs = np.arange(n_sub, dtype=np.int32)
         self.step = step
@@ -80,6 +84,11 @@ class Server:
                               torch.empty(4 * px, dtype=torch.float32, device=self.dev)))
         self.workspace_limit = workspace_limit
         self.hbm_budget = hbm_budget
+        self.keep = keep
+        self.events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                       for _ in self.slot_size]
+        self.t_ref = None
+        self.last_device = [None] * len(self.slot_size)
 
     def warm(self, eye=(2.0, 0.9, 0.7), tf=0):
         """One frame of each slot's largest request (its size, max_m) on every slot, one slot at a time: the
@@ -89,13 +98,29 @@ class Server:
             req = {"id": -1, "arrival": 0.0, "size": self.slot_size[k], "eye": eye, "m": self.max_m, "tf": tf}
             for _ in range(2):  # the second frame runs at the grown size
                 self.render(k, req)
+        self.slot_ws = [c.workspace_bytes() for c, _ in self.slots]
 
     def footprint(self, req) -> int:
-        """Bytes of one request's own buffers: global moments and image (the FP64 sums and the kept pieces
-        live in the slot's context, bounded by its workspace and grown by warm())."""
-        px = req["size"] ** 2
-        return px * (4 * (req["m"] + 1) + 16)
-
+        """HBM bytes a request occupies while it runs: its moment image and RGBA image, and the workspace of
+        the slot it runs on.  A library context keeps the buffers its largest frame needed (FP64 moment
+        partials, segment statistics, piece counts, binning state, and the piece pool when frames keep their
+        pieces), so after warm() the workspace of every slot that could take the request is measured with
+        apc_get_workspace_bytes and the largest is counted; before it, an estimate from the request's size
+        (8 (m+1) + 12 bytes per pixel, 12 bytes per (tile, subdomain) pair, 4 per binned face record -- two
+        per boundary face, since a face's conservative pixel box can reach into a neighbouring tile -- with the
+        library's growth slack, plus the pool limit when frames keep their pieces)."""
+        size, m = req["size"], req["m"]
+        px = size * size
+        own = px * (4 * (m + 1) + 16)
+        eligible = [k for k, s in enumerate(self.slot_size) if s >= size]
+        if self.slot_ws is not None and eligible:
+            return own + max(self.slot_ws[k] for k in eligible)
+        tiles = -(-size // 8) ** 2
+        ws = px * (8 * (m + 1) + 12) + tiles * 12 * self.n_sub + 4 * 2 * max(self.n_boundary_faces, 16 * tiles)
+        ws = ws * 5 // 4 + (64 << 10)  # the library's buffers grow with a quarter of slack, 4 KiB at least
+        if self.keep:
+            ws += self.workspace_limit
+        return own + ws
     def _bias(self, m):
         j = np.arange(1, m + 1)
         return np.where(j % 2 == 0, 1.0 / (j + 1.0), 0.0)
@@ -116,9 +141,14 @@ class Server:
         mom = b_mom[: (m + 1) * H * W].view(m + 1, H, W)
         rgba = b_rgba[: 4 * H * W].view(H, W, 4)
         s = stream.cuda_stream
-        ctx.moments_pass(self.mesh, view, tf, m, self.subs, mom, s, global_sum=True)
+        ev0, ev1 = self.events[slot]
+        ev0.record(stream)
+        ctx.moments_pass(self.mesh, view, tf, m, self.subs, mom, s, global_sum=True, keep=self.keep)
         ctx.resolve_pass(self.mesh, view, tf, mb, mom, self.subs, rgba, finalize=True, stream=s)
+        ev1.record(stream)
         stream.synchronize()
+        if self.t_ref is not None:  # the frame's interval on the device, in ms after the run's reference event
+            self.last_device[slot] = (self.t_ref.elapsed_time(ev0), self.t_ref.elapsed_time(ev1))
         return rgba
 
     def run(self, requests, mode="batched", keep_images=False) -> dict:
@@ -128,11 +158,23 @@ class Server:
             raise ValueError(mode)
         n_slots = len(self.slots) if mode == "batched" else 1
 
+        torch = self.torch
+        torch.cuda.synchronize(self.dev)
+        self.t_ref = torch.cuda.Event(enable_timing=True)
+        self.t_ref.record(torch.cuda.current_stream(self.dev))
+        device = {}
+
         def render(slot, req):
             rgba = self.render(slot, req)
+            device[req["id"]] = self.last_device[slot]
             return rgba.cpu() if keep_images else None
 
-        return schedule(requests, n_slots, self.footprint, self.hbm_budget, render, mode, slot_size=self.slot_size)
+        st = schedule(requests, n_slots, self.footprint, self.hbm_budget, render, mode, slot_size=self.slot_size)
+        for rec in st["records"]:
+            rec["device_start_ms"], rec["device_end_ms"] = device[rec["id"]]
+        st["device_overlap_frac"] = device_overlap(st["records"])
+        self.t_ref = None
+        return st
 
     def close(self):
         self.torch.cuda.synchronize(self.dev)
@@ -140,6 +182,20 @@ class Server:
             c.close()
         self.mesh.free()
         self.owner.close()
+
+
+def device_overlap(records) -> float:
+    """Fraction of the requests whose frame ran on the device (HIP event interval) while another request's
+    frame did."""
+    iv = sorted((r["device_start_ms"], r["device_end_ms"]) for r in records)
+    n = len(iv)
+    hit = [False] * n
+    for i in range(n):
+        for j in range(i + 1, n):
+            if iv[j][0] >= iv[i][1]:
+                break
+            hit[i] = hit[j] = True
+    return sum(hit) / max(n, 1)
 
 
 def schedule(requests, n_slots, footprint, hbm_budget, render, mode="batched", slot_size=None) -> dict:

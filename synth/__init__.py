@@ -28,7 +28,7 @@ __all__ = [
     "Mesh", "Scene", "jittered_grid", "kuhn_tets", "morton_order", "partition_chunks",
     "partition_slabs", "gaussian_field", "make_tf", "ortho_view_z", "perspective_view",
     "sphere_eye", "default_bias", "scene_tiny", "scene_medium", "scene_large", "scene",
-    "sandwich_scene", "scene_batching", "scene_amr_small", "scene_slabs",
+    "sandwich_scene", "scene_batching", "scene_amr_small", "scene_slabs", "orbit_view",
 ]
 
 
@@ -291,11 +291,19 @@ def scene_medium(seed: int = 2, size: int = 1024) -> Scene:
     return _scene("medium", mesh, view, n, 6, tf_seed=seed + 11)
 
 
-def scene_large(seed: int = 4, size: int = 2560, camera: int = 0, n: int = 256) -> Scene:
+def orbit_view(seed: int, camera: int, size: int) -> dict:
+    """Camera `camera` of a workload's seeded orbit: a perspective view from a point of the radius-2 sphere
+    around the cube's centre, looking at the centre (the analogue of the paper's camera paths)."""
+    return perspective_view(sphere_eye(seed + 3 + 97 * camera), (0.5, 0.5, 0.5), size, size)
+
+
+LARGE_SEED, BATCHING_SEED = 4, 7
+
+
+def scene_large(seed: int = LARGE_SEED, size: int = 2560, camera: int = 0, n: int = 256) -> Scene:
     """256^3 x 6 = 100,663,296 tets, 72 equal Morton chunks, perspective 2560^2, m = 8."""
     mesh = grid_mesh(n, 72, seed, n_gauss=16, jagged_seed=None)
-    view = perspective_view(sphere_eye(seed + 3 + 97 * camera), (0.5, 0.5, 0.5), size, size)
-    return _scene("large", mesh, view, n, 8, tf_seed=seed + 11)
+    return _scene("large", mesh, orbit_view(seed, camera, size), n, 8, tf_seed=seed + 11)
 
 
 def sandwich_scene(n: int = 24, n_sub: int = 3, slabs_per_sub: int = 2, m: int = 4, seed: int = 5,
@@ -337,7 +345,7 @@ def uneven_weights(n_sub: int, ratio: float, seed: int) -> np.ndarray:
     return np.random.default_rng(seed).permutation(w)
 
 
-def scene_batching(size: int = 2560, m: int = 8, seed: int = 7, camera: int = 0, base: int = 32, levels: int = 3,
+def scene_batching(size: int = 2560, m: int = 8, seed: int = BATCHING_SEED, camera: int = 0, base: int = 32, levels: int = 3,
                    tet_range: tuple = (19_000_000, 21_000_000), n_sub: int = 72) -> Scene:
     """Uneven-subdomain workload on an adaptive mesh: a base^3 grid of cubes refined 0..levels times where
     |grad f| * h exceeds a threshold chosen so that the tet count falls in tet_range, 2:1 balanced and cut
@@ -348,8 +356,7 @@ def scene_batching(size: int = 2560, m: int = 8, seed: int = 7, camera: int = 0,
     from .amr import amr_mesh
     w = uneven_weights(n_sub, 12.0, seed + 5)
     mesh, _, _ = amr_mesh(base, levels, n_sub, seed, tet_range=tet_range, chunk_weights=w)
-    view = perspective_view(sphere_eye(seed + 3 + 97 * camera), (0.5, 0.5, 0.5), size, size)
-    return _scene("batching", mesh, view, base << levels, m, tf_seed=seed + 11)
+    return _scene("batching", mesh, orbit_view(seed, camera, size), base << levels, m, tf_seed=seed + 11)
 
 
 def scene_amr_small(size: int = 256, m: int = 8, seed: int = 8, threshold: float = 0.3, n_sub: int = 8) -> Scene:

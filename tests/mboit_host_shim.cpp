@@ -76,3 +76,57 @@ extern "C" int shim_bound_table(const double* b, int m, double alpha, const doub
   if (m == 8) return run_table<4>(b, alpha, bias, eta, z, n, f_tab, f_closed);
   return -1;
 }
+
+// The continuation path of the fused re-walk for one moment vector: the
+// depths z[0..n) in the order a ray's samples would meet them, each through
+// frac_before_cont with the state the previous sample left, and through the
+// closed forms.  Returns how many samples took the closed forms (a new gap or
+// no convergence), or -1 when the pixel has no zeros.
+template <int N>
+static int run_cont(const double* b, double alpha, const double* bias, double eta, const double* z, int n,
+                    double* f_cont, double* f_closed) {
+  double bb[2 * N + 1], bs[2 * N];
+  for (int j = 0; j <= 2 * N; ++j) bb[j] = b[j];
+  for (int j = 0; j < 2 * N; ++j) bs[j] = bias[j];
+  apcm::Bound<N, double> B;
+  apcm::RegArray<N, double> zs;
+  B.setup(bb, alpha, bs, zs.v);
+  if (B.mode != 2 || !(B.xlo < B.xhi)) return -1;
+  typename apcm::Bound<N, double>::Cont c;
+  c.k = -1;
+  for (auto& v : c.v) v = 0.0;
+  int closed_n = 0;
+  for (int i = 0; i < n; ++i) {
+    int how = 0;
+    f_cont[i] = B.frac_before_cont(z[i], eta, zs, c, how);
+    closed_n += how == 2 ? 1 : 0;
+    f_closed[i] = B.frac_before(z[i], eta);
+  }
+  return closed_n;
+}
+
+extern "C" int shim_bound_cont(const double* b, int m, double alpha, const double* bias, double eta,
+                               const double* z, int n, double* f_cont, double* f_closed) {
+  if (m == 6) return run_cont<3>(b, alpha, bias, eta, z, n, f_cont, f_closed);
+  if (m == 8) return run_cont<4>(b, alpha, bias, eta, z, n, f_cont, f_closed);
+  return -1;
+}
+
+// The zeros of the degree-n orthonormal polynomial of a moment vector (ascending), or 0 when the pixel has
+// none; and the closed-form bound at one depth.
+extern "C" int shim_zeros(const double* b, int m, double alpha, const double* bias, double* zeros) {
+  double bb[9], bs[8];
+  for (int j = 0; j <= m; ++j) bb[j] = b[j];
+  for (int j = 0; j < m; ++j) bs[j] = bias[j];
+  if (m == 6) {
+    apcm::Bound<3, double> B;
+    B.setup(bb, alpha, bs, zeros);
+    return B.mode == 2 && B.xlo < B.xhi ? 3 : 0;
+  }
+  if (m == 8) {
+    apcm::Bound<4, double> B;
+    B.setup(bb, alpha, bs, zeros);
+    return B.mode == 2 && B.xlo < B.xhi ? 4 : 0;
+  }
+  return 0;
+}

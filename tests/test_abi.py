@@ -84,7 +84,8 @@ def test_missing_library_fails_loudly(apc, monkeypatch):
 def test_flag_constants_match_the_header(apc):
     text = open(HEADER).read()
     defs = dict((k, int(v)) for k, v in re.findall(r"#define (APC_[A-Z0-9_]+) (\d+)u\b", text))
-    for name in ("APC_FINALIZE", "APC_MOMENTS_F16", "APC_REWALK", "APC_MOMENTS_GLOBAL"):
+    names = ("APC_FINALIZE", "APC_MOMENTS_F16", "APC_MOMENTS_GLOBAL", "APC_KEEP_PIECES")
+    for name in names:
         assert getattr(apc, name) == defs[name], name
-    flags = [defs[n] for n in ("APC_FINALIZE", "APC_MOMENTS_F16", "APC_REWALK", "APC_MOMENTS_GLOBAL")]
+    flags = [defs[n] for n in names]
     assert all(f & (f - 1) == 0 for f in flags) and len(set(flags)) == len(flags)  # distinct single bits

@@ -274,7 +274,7 @@ def test_resolve_pass_statuses(P, ctx, scene):
     odd = C.c_void_p(sc["out"]["f16"].ctypes.data + 1)
     assert resolve(P, ctx, sc, flags=P.APC_FINALIZE | P.APC_MOMENTS_F16, moments_buf=odd) == 1
     assert resolve(P, ctx, sc, flags=P.APC_MOMENTS_F16, moments_buf=ptr(sc["out"]["f16"])) == 4
-    assert resolve(P, ctx, sc, flags=P.APC_REWALK) == 1 and "unknown flags" in err(P, ctx)
+    assert resolve(P, ctx, sc, flags=P.APC_KEEP_PIECES) == 1 and "unknown flags" in err(P, ctx)
     assert resolve(P, ctx, sc, rgba=C.c_void_p()) == 1 and "NULL" in err(P, ctx)
 
 

@@ -26,6 +26,11 @@ def shim(tmp_path_factory):
                              C.POINTER(C.c_int)]
     L.shim_roots.restype = C.c_int
     L.shim_roots.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p]
+    L.shim_zeros.restype = C.c_int
+    L.shim_zeros.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_void_p, C.c_void_p]
+    L.shim_bound_cont.restype = C.c_int
+    L.shim_bound_cont.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_void_p, C.c_double, C.c_void_p, C.c_int,
+                                  C.c_void_p, C.c_void_p]
     L.shim_bound_table.restype = C.c_int
     L.shim_bound_table.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_void_p, C.c_double, C.c_void_p, C.c_int,
                                    C.c_void_p, C.c_void_p]
@@ -145,3 +150,65 @@ def test_gap_table_on_random_atoms(shim):
                 worst = max(worst, abs(ft[i] - ref))
         assert worst <= tol, (m, worst)
         assert worst_closed <= tol, (m, worst_closed)
+
+
+@pytest.mark.parametrize("m", [6, 8])
+def test_bound_on_and_near_the_zeros(shim, m):
+    """Depths on and next to a zero of the degree-n orthonormal polynomial, where one node of the bound runs
+    off to infinity and the kernel polynomial's leading coefficient vanishes: the closed forms (which divide
+    the far root out instead of making the polynomial monic) match the oracle's companion-matrix roots."""
+    rng = np.random.default_rng(70 + m)
+    bias = np.ascontiguousarray(np.pad(synth.default_bias(m), (0, 8 - m)))
+    fl = C.c_int(0)
+    zs = np.zeros(4)
+    worst, n = 0.0, 0
+    for _ in range(300):
+        b = np.ascontiguousarray(_moments(rng, m, rng.integers(m // 2 + 2, 12)))
+        if shim.shim_zeros(b.ctypes.data, m, 5e-5, bias.ctypes.data, zs.ctypes.data) == 0:
+            continue
+        for t in zs[: m // 2]:
+            for dz in (0.0, 1e-12, -1e-12, 1e-9, -1e-9, 1e-6, -1e-6, 1e-4, -1e-4):
+                zf = float(t + dz)
+                ref = oracle.bound(b, 5e-5, bias[:m], 0.3, zf)[0]
+                got = shim.shim_bound(b.ctypes.data, m, 5e-5, bias.ctypes.data, 0.3, zf, 1, C.byref(fl))
+                worst = max(worst, abs(got - ref))
+                n += 1
+    assert n > 1000
+    assert worst <= 1e-7, worst
+
+
+@pytest.mark.parametrize("m", [6, 8])
+def test_continued_roots_match_oracle(shim, m):
+    """The re-walk's root solve: each sample of a ray starts Newton from the previous sample's roots (in the
+    gap's regularised coordinate), taking the closed forms in a new gap.  On rendered moment vectors, with
+    the samples in runs of increasing depth in a random order (a ray meeting several subdomains), the bound
+    matches the closed forms everywhere and the oracle wherever the two differ by more than rounding."""
+    sc = synth.scene_medium(size=96)
+    sc.m = m
+    sc.bias = synth.default_bias(m)
+    pix = np.random.default_rng(2).choice(96 * 96, 300, replace=False)
+    ref = oracle.render(sc, pixels=pix, pass2=False)
+    bias = np.ascontiguousarray(np.pad(synth.default_bias(m), (0, 8 - m)))
+    rng = np.random.default_rng(4)
+    total = closed = 0
+    worst = 0.0
+    for q in range(len(pix)):
+        b = np.ascontiguousarray(ref["moments"][:, q])
+        if b[0] <= 0:
+            continue
+        segs = np.sort(rng.uniform(-1, 1, (5, 2)), axis=1)
+        z = np.ascontiguousarray(np.concatenate(
+            [np.arange(a, e, rng.uniform(0.001, 0.01)) for a, e in segs[rng.permutation(5)]]))
+        fc, fx = np.zeros(len(z)), np.zeros(len(z))
+        n = shim.shim_bound_cont(b.ctypes.data, m, 5e-5, bias.ctypes.data, 0.3, z.ctypes.data, len(z),
+                                 fc.ctypes.data, fx.ctypes.data)
+        if n < 0:
+            continue
+        total += len(z)
+        closed += n
+        for i in np.where(np.abs(fc - fx) > 1e-10)[0]:
+            worst = max(worst, abs(fc[i] - oracle.bound(b, 5e-5, bias[:m], 0.3, z[i])[0]))
+        worst = max(worst, float(np.max(np.abs(fc - fx))) if np.all(np.abs(fc - fx) <= 1e-10) else 0.0)
+    assert total > 20000
+    assert closed <= 0.05 * total
+    assert worst <= 1e-9, worst

@@ -107,7 +107,7 @@ def test_tiny_moments_and_image_match_oracle(apc, ctx, tiny_ref):
     assert np.abs(d).max() <= 2e-3, np.abs(d).max()
     assert math.sqrt(np.mean(d ** 2)) <= 5e-4
     c = ctx.counters()
-    walks = 1 if ctx.timings()["stage_ms"] == 0 else 2  # stage two walks again unless stage one kept the pieces
+    walks = 2 if ctx.timings()["rewalk_ms"] > 0 else 1  # stage two walks again unless stage one kept the pieces
     print("counters", c, "walks", walks)
     assert c["walk_step_limit"] == 0
     assert abs(c["pieces"] - walks * ref["n_pieces"]) <= 1e-4 * ref["n_pieces"]
@@ -279,25 +279,33 @@ def test_medium_sampled_pixels_match_oracle(apc, ctx):
     assert np.abs(d).max() <= 2e-3 and math.sqrt(np.mean(d ** 2)) <= 5e-4
 
 
-def test_medium_m8_gap_tables(apc, ctx):
-    """m = 8 on the medium mesh at 512^2: enough pieces per pixel for every
-    covered pixel's roots to come from its gap table (Newton from the table,
-    closed forms as fallback); sampled pixels against the oracle."""
+def test_medium_m8_root_starts(apc, ctx):
+    """m = 8 on the medium mesh at 512^2, both forms of stage two.  The plain form (re-walk) starts each
+    sample's root solve from the previous sample's roots; the kept-piece form from its pixel's gap table.
+    Either way the closed forms are the fallback, rare after the start is good: at most 5 % of the samples
+    in the re-walk (every first sample in a new gap of the moment bound takes them) and 0.2 % with tables.
+    Sampled pixels of both against the oracle."""
     sc = synth.scene_medium(size=512)
     sc.m = 8
     sc.bias = synth.default_bias(8)
-    ctx.counters(reset=True)
-    r, rgba = _render(apc, ctx, sc)
-    cnt = ctx.counters()
+    r = apc.Renderer(ctx, sc)
     W, H = sc.view["width"], sc.view["height"]
     pix = np.sort(np.random.default_rng(9).choice(W * H, 4000, replace=False))
     ref = oracle.render(sc, pixels=pix)
-    _check_moments(sc, pix, _flat_moments(r.moments)[:, pix], ref)
-    d = _np(rgba).reshape(-1, 4)[pix] - ref["rgba"]
-    print("medium m=8: max", np.abs(d).max(), "rmse", math.sqrt(np.mean(d ** 2)), cnt)
-    assert cnt["table_samples"] > 0.5 * cnt["pieces"] / 2
-    assert cnt["table_fallback"] <= 2e-3 * cnt["table_samples"]
-    assert np.abs(d).max() <= 2e-3 and math.sqrt(np.mean(d ** 2)) <= 5e-4
+    for keep in (False, True):
+        for _ in range(2 if keep else 1):  # a kept-piece frame sizes its pool first
+            ctx.counters(reset=True)
+            rgba = r.frame(global_sum=True, keep=keep)
+        torch.cuda.synchronize()
+        cnt = ctx.counters()
+        _check_moments(sc, pix, _flat_moments(r.moments)[:, pix], ref)
+        d = _np(rgba).reshape(-1, 4)[pix] - ref["rgba"]
+        solved = cnt["table_samples"]
+        print("medium m=8 keep=%s: max %.3g rmse %.3g, closed forms %.4f of %d" % (
+            keep, np.abs(d).max(), math.sqrt(np.mean(d ** 2)), cnt["table_fallback"] / max(solved, 1), solved))
+        assert cnt["table_samples"] > 0.5 * cnt["pieces"] / 2
+        assert cnt["table_fallback"] <= (2e-3 if keep else 0.05) * solved
+        assert np.abs(d).max() <= 2e-3 and math.sqrt(np.mean(d ** 2)) <= 5e-4
 
 
 @pytest.mark.parametrize("m", [4, 6, 8])
@@ -345,7 +353,7 @@ def test_slab_segments_and_parity(apc, ctx):
     r, rgba = _render(apc, ctx, sc)
     segs = ctx.segment_counts(128, 128).cpu().numpy().reshape(2, -1)
     assert np.all(segs[0] == 16) and np.all(segs[1] == 4)
-    walks = 1 if ctx.timings()["stage_ms"] == 0 else 2
+    walks = 2 if ctx.timings()["rewalk_ms"] > 0 else 1
     assert ctx.counters()["segments"] == walks * 16 * 128 * 128  # every walk counts them
     ref = oracle.render(sc, segments=True)
     assert np.array_equal(segs, ref["segments"])
@@ -416,17 +424,18 @@ def test_tile_shapes_give_identical_results_and_autotuner(apc, ctx):
         ctx.set_tile_shape(8)
 
 
-@pytest.mark.parametrize("fused", [False, True])
-def test_frame_graph_replays_match_eager_frames(apc, ctx, fused):
-    """A frame captured in a HIP graph (with the separate moment sum, or with stage one summing the
-    subdomains itself): every replay (with eager work and synchronisation between replays) gives bitwise
-    the eager frame, and after the transfer-function table is edited in place a replay gives bitwise the
-    eager frame with the new table."""
+@pytest.mark.parametrize("global_sum,keep", [(False, False), (True, False), (True, True)])
+def test_frame_graph_replays_match_eager_frames(apc, ctx, global_sum, keep):
+    """A frame captured in a HIP graph (separate moment sum or stage one summing the subdomains itself; stage
+    two walking again or evaluating kept pieces): every replay (with eager work and synchronisation between
+    replays) gives bitwise the eager frame, and after the transfer-function table is edited in place a
+    replay gives bitwise the eager frame with the new table."""
     sc = synth.scene_medium(size=256)
     r = apc.Renderer(ctx, sc)
-    eager = r.frame(fused=fused).clone()
+    for _ in range(2 if keep else 1):  # a kept-piece frame sizes the pool first
+        eager = r.frame(global_sum=global_sum, keep=keep).clone()
     eager_mom = r.moments.clone()
-    g = apc.FrameGraph(r, fused=fused)
+    g = apc.FrameGraph(r, global_sum=global_sum, keep=keep)
     try:
         torch.cuda.synchronize()
         assert torch.equal(r.rgba, eager)  # the sizing frame
@@ -441,14 +450,14 @@ def test_frame_graph_replays_match_eager_frames(apc, ctx, fused):
             torch.cuda.synchronize()
             del junk
         cnt = g.counters()
-        assert cnt["pieces"] > 0 and cnt["walk_step_limit"] == 0
+        assert cnt["pieces"] > 0 and cnt["walk_step_limit"] == 0 and cnt["entry_overflow"] == 0
         # edit the transfer function in place: the replay follows it
         r.tf_dev[:, :3] = r.tf_dev[:, :3].flip(0).contiguous()
         torch.cuda.synchronize()
         g.launch()
         torch.cuda.synchronize()
         replay = r.rgba.clone()
-        again = r.frame(fused=fused)
+        again = r.frame(global_sum=global_sum, keep=keep)
         torch.cuda.synchronize()
         assert torch.equal(replay, again)
         assert not torch.equal(replay, eager)
@@ -456,27 +465,36 @@ def test_frame_graph_replays_match_eager_frames(apc, ctx, fused):
         g.close()
 
 
-@pytest.mark.parametrize("m", [4, 8])
-def test_kept_pieces_match_rewalk(apc, ctx, m):
-    """Stage two reading the pieces stage one kept gives bitwise the image of
-    stage two walking the rays again (the same pieces in the same order per
-    pixel), including after the piece store had to grow."""
+@pytest.mark.parametrize("m", [4, 6, 8])
+def test_kept_pieces_match_the_plain_form(apc, ctx, m):
+    """Stage two evaluating the pieces stage one kept gives the image of the plain form (stage two walking
+    the rays again and evaluating each piece at once) to rounding: the same pieces, the same bound, other
+    root-solver starts (a per-pixel gap table instead of the previous sample's roots) and another summation
+    order.  Both match the oracle on sampled pixels."""
     sc = synth.scene_medium(size=384)
     sc.m = m
     sc.bias = synth.default_bias(m)
     r = apc.Renderer(ctx, sc)
-    walked = r.frame(rewalk=True).clone()
-    assert ctx.timings()["stage_ms"] > 0
-    r.frame()  # the first kept frame may not fit the store; the store grows after it
-    kept = r.frame().clone()
+    plain = r.frame(global_sum=True).clone()
+    t = ctx.timings()
+    assert t["rewalk_ms"] > 0 and t["eval_ms"] == 0
+    r.frame(global_sum=True, keep=True)  # the first kept frame may not fit the store; the store grows after it
+    kept = r.frame(global_sum=True, keep=True).clone()
     torch.cuda.synchronize()
     t = ctx.timings()
-    assert t["stage_ms"] == 0 and t["eval_ms"] > 0  # no second walk
-    assert torch.equal(kept, walked)
+    assert t["rewalk_ms"] == 0 and t["eval_ms"] > 0  # no second walk
+    diff = (kept - plain).abs().max().item()
+    print("m = %d: kept vs plain max %.3g" % (m, diff))
+    assert diff <= 2e-5
+    pix = np.sort(np.random.default_rng(23).choice(384 * 384, 1500, replace=False))
+    ref = oracle.render(sc, pixels=pix)
+    for img in (plain, kept):
+        d = _np(img).reshape(-1, 4)[pix] - ref["rgba"]
+        assert np.abs(d).max() <= 2e-3 and math.sqrt(np.mean(d ** 2)) <= 5e-4
 
 
 @pytest.mark.parametrize("m", [4, 8])
-def test_fused_global_sum_is_bitwise_the_separate_sum(apc, ctx, m):
+def test_global_sum_in_stage_one_is_bitwise_the_separate_sum(apc, ctx, m):
     """Stage one summing the subdomains itself (APC_MOMENTS_GLOBAL) gives bitwise the global moments of the
     per-subdomain images summed by apc_sum_moments, and the same image; the ids must be ascending."""
     sc = synth.scene_medium(size=256)
@@ -485,33 +503,33 @@ def test_fused_global_sum_is_bitwise_the_separate_sum(apc, ctx, m):
     r = apc.Renderer(ctx, sc)
     sep = r.frame().clone()
     mom_sep = r.moments.clone()
-    for _ in range(2):  # the first fused frame may still re-walk after the store grew; both must match
+    for _ in range(2):
         r.moments.fill_(float("nan"))
-        fused = r.frame(fused=True)
+        glob = r.frame(global_sum=True)
         torch.cuda.synchronize()
         assert torch.equal(r.moments, mom_sep)
-        assert torch.equal(fused, sep)
+        assert torch.equal(glob, sep)
     with pytest.raises(RuntimeError):
         ctx.moments_pass(r.mesh, r.view, r.tf, m, r.subs[::-1].copy(), r.moments, global_sum=True)
 
 
-def test_workspace_limit_stages_in_chunks_with_the_same_image(apc, ctx):
-    """A context whose workspace limit is far below the frame's pieces (48 MB of pool, 16 MB of staging for
-    more than four times that in pieces) re-walks in stage two and stages its tiles in several chunks: the
-    image is bitwise that of an unlimited context, frame after frame."""
+def test_pool_limit_below_the_pieces_walks_again_with_the_plain_image(apc, ctx):
+    """A context whose kept-piece pool is capped far below the frame's pieces (48 MB for more than twice
+    that) cannot keep them: stage two walks again, and the image is bitwise that of the plain form, frame
+    after frame."""
     sc = synth.scene_medium(size=256)
     ref = apc.Renderer(ctx, sc).frame().clone()
     small = apc.Context(0)
     try:
-        small.set_workspace_limit(64 << 20)
+        small.set_workspace_limit(48 << 20)
         r = apc.Renderer(small, sc)
         for _ in range(2):
             small.counters(reset=True)
-            got = r.frame()
+            got = r.frame(keep=True)
             torch.cuda.synchronize()
             t, c = small.timings(), small.counters()
-            assert t["stage_ms"] > 0  # the pieces do not fit the pool: stage two walked again
-            assert c["pieces"] // 2 * 12 > 4 * (16 << 20)  # each of the two walks: pieces for 4+ chunks
+            assert t["rewalk_ms"] > 0  # the pieces do not fit the pool: stage two walked again
+            assert c["pieces"] // 2 * 12 > 2 * (48 << 20)  # each walk's pieces: more than twice the pool
             assert torch.equal(got, ref)
     finally:
         del r
@@ -520,27 +538,32 @@ def test_workspace_limit_stages_in_chunks_with_the_same_image(apc, ctx):
 
 def test_large_full_size_sampled_pixels_match_oracle(apc, ctx):
     """The full-size configuration the benchmark times (256^3 x 6 = 100,663,296 tets, 72 subdomains,
-    2560^2 perspective, m = 8), in its launch configuration (a warm-up frame, then a frame that keeps its
-    pieces): 3,000 seeded pixels against the oracle (moments by the forward or backward-error bar, RGBA
-    by the image bar), and both frames' images equal."""
+    2560^2 perspective, m = 8), in its launch configuration (stage one summing the subdomains, stage two
+    walking again; a warm-up frame, then the timed one): 3,000 seeded pixels against the oracle (moments by
+    the forward bar, RGBA by the image bar), both frames bitwise equal; and the kept-piece variant's image
+    equal to it to rounding."""
     sc = synth.scene_large()
     r = apc.Renderer(ctx, sc)
-    first = r.frame().clone()
+    first = r.frame(global_sum=True).clone()
     ctx.counters(reset=True)
-    rgba = r.frame()
+    rgba = r.frame(global_sum=True).clone()
     torch.cuda.synchronize()
-    assert ctx.timings()["stage_ms"] == 0  # the timed frame evaluates the kept pieces
+    assert ctx.timings()["rewalk_ms"] > 0
     assert torch.equal(rgba, first)
+    assert ctx.counters()["walk_step_limit"] == 0 and ctx.counters()["nonpd_pivots"] == 0
     W, H = sc.view["width"], sc.view["height"]
     pix = np.sort(np.random.default_rng(17).choice(W * H, 3000, replace=False))
     ref = oracle.render(sc, pixels=pix)
-    # ~1,000 tets per ray: more rays graze a face than on the coarser meshes (1.2 % of covered pixels on a
-    # 65,536-pixel sample), every one of them inside the backward-error band
     fwd, n_back = _check_moments(sc, pix, _flat_moments(r.moments)[:, pix], ref)
     d = _np(rgba).reshape(-1, 4)[pix] - ref["rgba"]
     print("large: moments forward %.3g (%d on the backward bar), rgba max %.3g rmse %.3g" % (
         fwd, n_back, np.abs(d).max(), math.sqrt(np.mean(d ** 2))))
     assert np.abs(d).max() <= 2e-3 and math.sqrt(np.mean(d ** 2)) <= 5e-4
+    for _ in range(2):  # the kept-piece variant: the first frame sizes the pool
+        kept = r.frame(global_sum=True, keep=True)
+    torch.cuda.synchronize()
+    assert ctx.timings()["eval_ms"] > 0
+    assert (kept - rgba).abs().max().item() <= 2e-5
     del r
 
 
@@ -553,9 +576,8 @@ def test_adaptive_mesh_full_image_matches_oracle(apc, ctx):
     ctx.counters(reset=True)
     r, rgba = _render(apc, ctx, sc)
     pix = np.arange(200 * 200)
-    # 1.4 % of the covered pixels need the backward bar (all inside the band): low-b0 rays through the
-    # coarsest leaves (edge 1/8) at the volume's silhouette, where FP32 depth rounding across a face grows
-    # with the face's size; on the 1/64 grid of the medium mesh it is 0.1 %
+    # a few silhouette pixels (0.02 %) need the backward bar: low-b0 rays through the coarsest leaves (edge
+    # 1/8), where the FP32 side products' rounding across a face grows with the face's size
     fwd, n_back = _check_moments(sc, pix, _flat_moments(r.moments), ref)
     fwd_s, n_back_s = _check_moments(sc, pix, _flat_moments(r.per_sub), ref, per_sub=True)
     d = _np(rgba).reshape(-1, 4) - ref["rgba"]

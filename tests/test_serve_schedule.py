@@ -6,7 +6,7 @@ import time
 import numpy as np
 import pytest
 
-from paper_2501_12581_amd.serve import schedule
+from paper_2501_12581_amd.serve import device_overlap, schedule
 
 
 def _stub(service_s):
@@ -85,3 +85,9 @@ def test_request_larger_than_every_slot_is_rejected_up_front():
     with pytest.raises(ValueError):
         schedule([{"id": 0, "arrival": 0.0, "size": 4096}], 2, lambda r: 1, 1 << 30, _stub({0: 0.0})[0],
                  slot_size=[2048, 1024])
+
+
+def test_device_overlap_counts_requests_whose_intervals_intersect():
+    recs = [{"device_start_ms": a, "device_end_ms": b} for a, b in ((0, 10), (5, 12), (20, 30), (30, 31), (40, 50))]
+    assert device_overlap(recs) == 2 / 5  # (0,10) and (5,12); touching intervals do not overlap
+    assert device_overlap([]) == 0.0
