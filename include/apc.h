@@ -266,6 +266,27 @@ apc_status apc_resolve_pass(apc_ctx ctx, apc_mesh mesh, const apc_view* view, co
                             const apc_mboit* mboit, const void* moments_global, const int32_t* subdomains,
                             int32_t n_sub, float* rgba_out, uint32_t flags, void* stream);
 
+/* apc_resolve_pass for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the plain form only (stage two walks the rays again; kept
+ * pieces are never used), with the same arguments, flags, validation and
+ * results bit for bit.  Its binning state lives in a static device workspace
+ * of 64 MiB in the library's code object (every GPU the library runs on holds
+ * one, until the process ends) instead of the context's growable buffers, so
+ * the call allocates nothing.  The call reads back the number of binned
+ * (face, tile) records (one stream synchronisation) before it walks.
+ * Limits: the slot table, 3 x 4 bytes per (tile, subdomain) pair and the
+ * binned records must fit the 64 MiB (about 16 subdomains at 2048^2 or all
+ * 72 of a 100M-tet mesh at 1024^2); a frame beyond them returns APC_E_NOMEM
+ * with the sizes in the message and writes nothing to rgba_out.  Every call on
+ * one GPU shares that GPU's workspace: calls that overlap in time on one GPU
+ * (any contexts, any streams) race.  Everything it needs is cleared by its own
+ * kernels on every call. */
+apc_status apc_resolve_pass_noalloc(apc_ctx ctx, apc_mesh mesh, const apc_view* view, const apc_tf* tf,
+                                    const apc_mboit* mboit, const void* moments_global,
+                                    const int32_t* subdomains, int32_t n_sub, float* rgba_out, uint32_t flags,
+                                    void* stream);
+
 /* Final image = sum of partial images (Section 4.2; the paper's
  * MPI_Reduce), in ascending subdomain-id order, then finalised like
  * apc_resolve_pass with APC_FINALIZE.

@@ -31,7 +31,7 @@ EXPORTS = ["apc_create", "apc_destroy", "apc_last_error", "apc_version", "apc_lo
            "apc_resolve_pass", "apc_sum_images", "apc_pack_moments_f16", "apc_segment_counts", "apc_get_counters",
            "apc_get_timings", "apc_set_tile_shape", "apc_get_tile_shape", "apc_autotune_tile_shape",
            "apc_frame_graph_create", "apc_frame_graph_launch", "apc_frame_graph_counters", "apc_frame_graph_destroy",
-           "apc_set_workspace_limit", "apc_get_workspace_bytes"]
+           "apc_set_workspace_limit", "apc_resolve_pass_noalloc", "apc_get_workspace_bytes"]
 
 
 class ApcError(RuntimeError):
@@ -116,6 +116,9 @@ def lib():
                                        C.c_int32, vp, C.c_uint32, vp]
         L.apc_get_workspace_bytes.restype = st
         L.apc_get_workspace_bytes.argtypes = [vp, C.POINTER(C.c_int64)]
+        L.apc_resolve_pass_noalloc.restype = st
+        L.apc_resolve_pass_noalloc.argtypes = [vp, vp, C.POINTER(View), C.POINTER(TF), C.POINTER(Mboit), vp, vp,
+                                               C.c_int32, vp, C.c_uint32, vp]
         L.apc_pack_moments_f16.restype = st
         L.apc_pack_moments_f16.argtypes = [vp, vp, C.c_int32, C.c_int32, C.c_int32, vp, vp]
         L.apc_set_workspace_limit.restype = st
@@ -308,6 +311,20 @@ class Context:
                                                  "moments"), ptr, len(ids),
                                         _dev_ptr(out, torch.float32, (view.height, view.width, 4), "rgba"),
                                         flags, _stream(stream)))
+
+    def resolve_pass_noalloc(self, mesh, view: View, tf: TF, mboit: Mboit, moments, subdomains, out, finalize=True,
+                             stream=None):
+        """apc_resolve_pass_noalloc: the plain-form resolve with its binning state in the library's static
+        device workspace (no device allocation)."""
+        import torch
+        ids, ptr = _ids(subdomains)
+        f16 = moments.dtype == torch.float16
+        flags = (APC_FINALIZE if finalize else 0) | (APC_MOMENTS_F16 if f16 else 0)
+        self._ck(lib().apc_resolve_pass_noalloc(
+            self.handle, mesh.handle, C.byref(view), C.byref(tf), C.byref(mboit),
+            _dev_ptr(moments, torch.float16 if f16 else torch.float32,
+                     (mboit.m + (3 if f16 else 1), view.height, view.width), "moments"), ptr, len(ids),
+            _dev_ptr(out, torch.float32, (view.height, view.width, 4), "rgba"), flags, _stream(stream)))
 
     def workspace_bytes(self) -> int:
         """Device memory the context holds now (apc_get_workspace_bytes)."""

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -84,6 +85,36 @@ struct DevBuf {
   }
 };
 
+}  // namespace
+
+// ---- the static workspace of apc_resolve_pass_noalloc
+//
+// Device memory in the library's own code object: every GPU the library runs
+// on holds one copy of it (allocated when the code object is loaded, held
+// until the process ends).  In host code `scratch` names a host-side stand-in,
+// not a device address: its address on each device comes from
+// hipGetSymbolAddress at context creation (apc_create), with that device
+// current, and only that address is handed to kernels.
+namespace {
+constexpr size_t NOALLOC_BYTES = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+hipError_t g_noalloc_err[NOALLOC_MAX_DEVICES] = {};
+bool g_noalloc_done[NOALLOC_MAX_DEVICES] = {};
+
+// once per device, with `device` current
+void noalloc_setup(int device) {
+  if (device < 0 || device >= NOALLOC_MAX_DEVICES) return;
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (g_noalloc_done[device]) return;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  g_noalloc_err[device] = e;
+  g_noalloc_ptr[device] = e == hipSuccess ? ptr : nullptr;
+  g_noalloc_done[device] = true;
+}
 }  // namespace
 
 struct apc_ctx_s {
@@ -331,7 +362,7 @@ apc_status check_subdomains(const apc_mesh_s* m, const int32_t* subs, int32_t n_
 long long bin_cap(apc_ctx ctx) { return (long long)(ctx->records.bytes / sizeof(int)); }
 
 // Where a frame's binning state lives: the context's growable buffers, or
-// fixed slices of a caller-independent workspace.
+// fixed slices of the static workspace (apc_resolve_pass_noalloc).
 struct BinSpace {
   SlotDev* slots;
   int *counts, *offsets, *cursors, *tmp, *records;
@@ -390,7 +421,7 @@ apc_status bin_faces(apc_ctx ctx, const apc_mesh_s* m, const FrameDev& f, const 
       B.records = ctx->records.as<int>();
       B.rec_cap = bin_cap(ctx);
     } else if (total > B.rec_cap) {
-      return fail(APC_E_NOMEM, "the frame bins %lld (face, tile) records; the workspace holds %lld",
+      return fail(APC_E_NOMEM, "the frame bins %lld (face, tile) records; the static workspace holds %lld",
                   (long long)total, B.rec_cap);
     }
     ctx->bin_records += total;
@@ -544,6 +575,7 @@ apc_status apc_create(int device, apc_ctx* out) {
   apc_ctx c = new (std::nothrow) apc_ctx_s();
   if (!c) return fail(APC_E_NOMEM, "host allocation failed");
   c->device = device;
+  noalloc_setup(device);
   hipError_t e = c->counters.ensure(sizeof(unsigned long long) * apc::C_COUNT);
   if (e == hipSuccess) e = hipMemset(c->counters.p, 0, c->counters.bytes);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->staging_done, hipEventDisableTiming);
@@ -1048,6 +1080,52 @@ static apc_status resolve_frame(apc_ctx ctx, apc_mesh m, const apc_view* view, c
   HIPCHK(ev_mark(ctx, EV_STG, 0, s));
   HIPCHK(apc::launch_resolve(mb->m, md, f, ctx->slots.as<SlotDev>(), ctx->offsets.as<int>(), ctx->counts.as<int>(),
                              ctx->records.as<int>(), bin_cap(ctx), tf->rgba, moments, bp, rgba, ctr, s));
+  HIPCHK(ev_mark(ctx, EV_STG, 1, s));
+  HIPCHK(ev_mark(ctx, EV_RES, 1, s));
+  return APC_OK;
+}
+
+apc_status apc_resolve_pass_noalloc(apc_ctx ctx, apc_mesh m, const apc_view* view, const apc_tf* tf,
+                                    const apc_mboit* mb, const void* moments, const int32_t* subs, int32_t n_sub,
+                                    float* rgba, uint32_t flags, void* stream) {
+  apc::BoundParams bp;
+  FrameDev f;
+  apc_status st =
+      check_resolve(ctx, m, view, tf, mb, moments, subs, n_sub, rgba, flags, bp, f, "apc_resolve_pass_noalloc");
+  if (st != APC_OK) return st;
+  // the binning state's slices of the static workspace: slots, counts, offsets, cursors, scan scratch, then
+  // the (face, tile) records in the rest
+  const int64_t nb = int64_t(f.n_tiles) * n_sub;
+  auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+  const size_t o_counts = up(sizeof(SlotDev) * n_sub);
+  const size_t o_offsets = o_counts + up(sizeof(int) * nb);
+  const size_t o_cursors = o_offsets + up(sizeof(int) * (nb + 1));
+  const size_t o_tmp = o_cursors + up(sizeof(int) * nb);
+  const size_t o_rec = o_tmp + up(sizeof(int) * apc::scan_tmp_elems(nb));
+  if (o_rec + sizeof(int) > NOALLOC_BYTES)
+    return fail(APC_E_NOMEM,
+                "a %d x %d frame of %d subdomains needs %zu bytes of binning state before its records; the static "
+                "workspace holds %zu",
+                view->width, view->height, n_sub, o_rec, NOALLOC_BYTES);
+  const int dev = ctx->device;
+  if (dev >= NOALLOC_MAX_DEVICES || !g_noalloc_ptr[dev])
+    return fail(APC_E_DEVICE, "the static workspace has no address on device %d: %s", dev,
+                dev < NOALLOC_MAX_DEVICES ? hipGetErrorString(g_noalloc_err[dev]) : "device id too large");
+  unsigned char* base = static_cast<unsigned char*>(g_noalloc_ptr[dev]);
+  BinSpace B = {reinterpret_cast<SlotDev*>(base), reinterpret_cast<int*>(base + o_counts),
+                reinterpret_cast<int*>(base + o_offsets), reinterpret_cast<int*>(base + o_cursors),
+                reinterpret_cast<int*>(base + o_tmp), reinterpret_cast<int*>(base + o_rec),
+                (long long)((NOALLOC_BYTES - o_rec) / sizeof(int)), false};
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned long long* ctr = ctx->counters.as<unsigned long long>();
+  ctx->ev_used[EV_STG] = false;
+  ctx->ev_used[EV_EVL] = false;
+  MeshDev md;
+  HIPCHK(ev_mark(ctx, EV_RES, 0, s));
+  if ((st = bin_faces(ctx, m, f, subs, n_sub, B, s, md)) != APC_OK) return st;
+  HIPCHK(ev_mark(ctx, EV_STG, 0, s));
+  HIPCHK(apc::launch_resolve(mb->m, md, f, B.slots, B.offsets, B.counts, B.records, B.rec_cap, tf->rgba, moments, bp,
+                             rgba, ctr, s));
   HIPCHK(ev_mark(ctx, EV_STG, 1, s));
   HIPCHK(ev_mark(ctx, EV_RES, 1, s));
   return APC_OK;

@@ -276,6 +276,15 @@ def test_resolve_pass_statuses(P, ctx, scene):
     assert resolve(P, ctx, sc, flags=P.APC_MOMENTS_F16, moments_buf=ptr(sc["out"]["f16"])) == 4
     assert resolve(P, ctx, sc, flags=P.APC_KEEP_PIECES) == 1 and "unknown flags" in err(P, ctx)
     assert resolve(P, ctx, sc, rgba=C.c_void_p()) == 1 and "NULL" in err(P, ctx)
+    # the allocation-free variant validates the same way
+    L = P.lib()
+    args = (ctx, sc["mesh"], C.byref(sc["view"]), C.byref(sc["tf"]))
+    ok = L.apc_resolve_pass_noalloc(*args, C.byref(sc["mb"]), ptr(sc["out"]["mom"]), ptr(sc["subs"]), 3,
+                                    ptr(sc["out"]["rgba"]), P.APC_FINALIZE, None)
+    assert ok == 4 and "apc_resolve_pass_noalloc" in err(P, ctx) and "nothing was launched" in err(P, ctx)
+    bad = L.apc_resolve_pass_noalloc(*args, C.byref(P.make_mboit(5, 5e-5, np.zeros(5), 0.3)),
+                                     ptr(sc["out"]["mom"]), ptr(sc["subs"]), 3, ptr(sc["out"]["rgba"]), 0, None)
+    assert bad == 1 and "m = 5" in err(P, ctx)
 
 
 def test_sums_pack_and_settings_statuses(P, ctx, scene):
