@@ -283,6 +283,17 @@ __device__ __forceinline__ float lerp_nc(float a, float b, float fr) {
 // Where a walk stands: the face (A, B, C) through which the ray entered the
 // current tet, with its positive side products, and the tet with the local
 // index of the vertex opposite that face.
+// a or b, field by field (value selects: no store through a selected address)
+__device__ __forceinline__ VS pick(bool c, const VS& a, const VS& b) {
+  VS r;
+  r.id = c ? a.id : b.id;
+  r.s = c ? a.s : b.s;
+  r.u = c ? a.u : b.u;
+  r.v = c ? a.v : b.v;
+  r.t = c ? a.t : b.t;
+  return r;
+}
+
 struct WalkPos {
   VS A, B, C;
   float pAB, pBC, pCA;
@@ -328,9 +339,9 @@ __device__ __forceinline__ bool walk_step(const MeshDev& M, const Ray& r, WalkPo
   const float nAB = x == 0 ? qB : (x == 1 ? -qA : w.pAB);
   const float nBC = x == 0 ? w.pBC : (x == 1 ? qC : -qB);
   const float nCA = x == 0 ? -qC : (x == 1 ? w.pCA : qA);
-  if (x == 0) w.A = D;
-  if (x == 1) w.B = D;
-  if (x == 2) w.C = D;
+  w.A = pick(x == 0, D, w.A);
+  w.B = pick(x == 1, D, w.B);
+  w.C = pick(x == 2, D, w.C);
   w.pAB = nAB;
   w.pBC = nBC;
   w.pCA = nCA;
@@ -1074,11 +1085,10 @@ constexpr int RES_ROOM = 3;
 // the lane utilisation of the divergent walk.
 template <int N, class R>
 struct Resolver {
-  const FrameDev* f;
+  using Bd = apcm::Bound<N, R>;
+  using Zs = apcm::RegArray<N, R>;
+  using Ct = typename apcm::Bound<N, R>::Cont;
   const float4* tf;  // LDS RGBA table
-  apcm::Bound<N, R> bound;
-  apcm::RegArray<N, R> zs;
-  typename apcm::Bound<N, R>::Cont cont;
   R eta;
   float a0, a1, a2, a3;
   unsigned pieces, solved, closed_used;  // samples; of those, needing roots; of those, by the closed forms
@@ -1090,13 +1100,13 @@ struct Resolver {
   float cs0, cslope;
   int cguard;
 
-  __device__ void start_cut(double t0, double t1, float s0, float s1) {
+  __device__ __forceinline__ void start_cut(const FrameDev& f, double t0, double t1, float s0, float s1) {
 #pragma clang fp contract(off)
     const double len_c = t1 - t0;
     cutting = len_c > 0.0;
     if (!cutting) return;
     cslope = (s1 - s0) / float(len_c);
-    ckf = floor((t0 - f->t_near) * f->inv_step) + 1.0;
+    ckf = floor((t0 - f.t_near) * f.inv_step) + 1.0;
     cu = t0;
     ct0 = t0;
     ct1 = t1;
@@ -1104,7 +1114,7 @@ struct Resolver {
     cguard = 0;
   }
   // queue pieces of the chord being cut until it ends or the queue is full
-  __device__ void cut_more() {
+  __device__ __forceinline__ void cut_more(const FrameDev& f) {
 #pragma clang fp contract(off)
     while (cutting && len < RQ) {
       if (!(cu < ct1) || cguard >= (1 << 22)) {
@@ -1112,7 +1122,7 @@ struct Resolver {
         break;
       }
       ++cguard;
-      const double nxt = f->t_near + ckf * f->step;
+      const double nxt = f.t_near + ckf * f.step;
       ckf += 1.0;
       if (nxt <= cu) continue;
       const double v = fmin(nxt, ct1);
@@ -1120,8 +1130,8 @@ struct Resolver {
       const float s = cs0 + cslope * float(tm - ct0);
       int i0;
       float fr, a, z;
-      tf_coord(*f, s, i0, fr);
-      piece_az(*f, tm, float(v - cu), lerp_nc(tf[i0].w, tf[i0 + 1].w, fr), a, z);  // as stage one
+      tf_coord(f, s, i0, fr);
+      piece_az(f, tm, float(v - cu), lerp_nc(tf[i0].w, tf[i0 + 1].w, fr), a, z);  // as stage one
       int slot = head + len;
       slot -= slot >= RQ ? RQ : 0;
       qz[slot * WAVE + lane] = z;
@@ -1133,7 +1143,7 @@ struct Resolver {
     }
   }
   // evaluate the oldest queued piece (Alg. 1 second loop with Alg. 3's bound)
-  __device__ void eval_one() {
+  __device__ __forceinline__ void eval_one(const FrameDev& f, const Bd& bound, const Zs& zs, Ct& cont) {
     const int slot = head;
     const float z = qz[slot * WAVE + lane], a = qa[slot * WAVE + lane], s = qs[slot * WAVE + lane];
     head = head + 1 == RQ ? 0 : head + 1;
@@ -1141,7 +1151,7 @@ struct Resolver {
     if (bound.mode == 0) return;  // no absorbance on the ray: every piece has a = 0
     int i0;
     float fr;
-    tf_coord(*f, s, i0, fr);
+    tf_coord(f, s, i0, fr);
     const float4 c0 = tf[i0], c1 = tf[i0 + 1];
     R F;
     if constexpr (N >= 3) {
@@ -1163,12 +1173,12 @@ struct Resolver {
   // called by the whole wavefront: one queued piece per lane while enough lanes have one or some lane's
   // queue is too full to walk on (all: until every queue is empty).  Each round empties one slot of every
   // non-empty queue, so after it every lane can take its next walk step or chord piece.
-  __device__ void drain(bool all) {
+  __device__ __forceinline__ void drain(const FrameDev& f, const Bd& bound, const Zs& zs, Ct& cont, bool all) {
     while (true) {
       const unsigned long long ready = __ballot(len > 0);
       if (!ready) break;
       if (!all && __popcll(ready) < APC_RES_DRAIN_MIN && !__any(len > RQ - RES_ROOM)) break;
-      if (len > 0) eval_one();
+      if (len > 0) eval_one(f, bound, zs, cont);
     }
   }
 };
@@ -1179,9 +1189,10 @@ struct Resolver {
 // between iterations.  The pieces, their order per ray and every depth are
 // those of walk_subdomain.
 template <int N, class R>
-__device__ void walk_subdomain_queued(const MeshDev& M, const FrameDev& f, const Ray& r, bool valid, const int* rec,
+__device__ __forceinline__ void walk_subdomain_queued(const MeshDev& M, const FrameDev& f, const Ray& r, bool valid, const int* rec,
                                       int n_rec, const SlotDev& sl, FaceL* faces, EntryList& L, Resolver<N, R>& q,
-                                      LaneCount& cnt) {
+                                      const apcm::Bound<N, R>& bound, const apcm::RegArray<N, R>& zs,
+                                      typename apcm::Bound<N, R>::Cont& cont, LaneCount& cnt) {
   float last_t = -FLT_MAX;
   int last_c = -1;
   bool more = true;
@@ -1214,7 +1225,7 @@ __device__ void walk_subdomain_queued(const MeshDev& M, const FrameDev& f, const
         }
         ++k;
       }
-      if (q.cutting) q.cut_more();  // the rest of a chord that did not fit the queue
+      if (q.cutting) q.cut_more(f);  // the rest of a chord that did not fit the queue
       // a few walk steps while the queue has room for their pieces
       for (int burst = 0; !q.cutting && walking && burst < APC_RES_BURST && q.len <= RQ - RES_ROOM; ++burst) {
         if (steps >= f.max_steps) {
@@ -1226,8 +1237,8 @@ __device__ void walk_subdomain_queued(const MeshDev& M, const FrameDev& f, const
         float sout;
         walking = walk_step(M, r, w, tin, sl.tet_begin, sl.tet_end, tout, sout, cnt);
         ++steps;
-        q.start_cut(tin, tout, sin_, sout);
-        q.cut_more();
+        q.start_cut(f, tin, tout, sin_, sout);
+        q.cut_more(f);
         tin = tout;
         sin_ = sout;
       }
@@ -1235,7 +1246,7 @@ __device__ void walk_subdomain_queued(const MeshDev& M, const FrameDev& f, const
         cnt.segments += q.pieces > seg_start ? 1u : 0u;
         open = false;
       }
-      q.drain(false);
+      q.drain(f, bound, zs, cont, false);
     }
     if (n > 0) {
       last_t = L.T(n - 1);
@@ -1271,7 +1282,9 @@ __global__ __launch_bounds__(WAVE * RES_WPB) __attribute__((amdgpu_waves_per_eu(
   LaneCount cnt = {};
   cnt.ctr = ctr;
   Resolver<N, R> q;
-  q.f = &f;
+  apcm::Bound<N, R> bound;
+  apcm::RegArray<N, R> zs;
+  typename apcm::Bound<N, R>::Cont cont;
   q.tf = tf;
   q.eta = R(bp.eta);
   q.a0 = q.a1 = q.a2 = q.a3 = 0.0f;
@@ -1282,22 +1295,22 @@ __global__ __launch_bounds__(WAVE * RES_WPB) __attribute__((amdgpu_waves_per_eu(
   q.lane = lane;
   q.head = q.len = 0;
   q.cutting = false;
-  q.cont.k = -1;
+  cont.k = -1;
 #pragma unroll
-  for (int c = 0; c < int(sizeof(q.cont.v) / sizeof(R)); ++c) q.cont.v[c] = R(0);
+  for (int c = 0; c < int(sizeof(cont.v) / sizeof(R)); ++c) cont.v[c] = R(0);
   float b0f;
   {  // per-pixel part of Alg. 3, once per pixel instead of once per sample
     R b[2 * N + 1], bias[2 * N], zsr[N];
     b0f = pixel_moments<N, R>(moments, bp.moments_f16, valid, pix, HW, b);
 #pragma unroll
     for (int j = 0; j < 2 * N; ++j) bias[j] = R(bp.bias[j]);
-    cnt.nonpd += q.bound.setup(b, R(bp.alpha), bias, zsr);
+    cnt.nonpd += bound.setup(b, R(bp.alpha), bias, zsr);
 #pragma unroll
-    for (int i = 0; i < N; ++i) q.zs.v[i] = zsr[i];
+    for (int i = 0; i < N; ++i) zs.v[i] = zsr[i];
     // no zeros found (never expected for a positive definite factor): no shortcut, every sample solves
-    if (q.bound.mode == 2 && !(zsr[0] < zsr[N - 1])) {
-      q.bound.xlo = -R(HUGE_VAL);
-      q.bound.xhi = R(HUGE_VAL);
+    if (bound.mode == 2 && !(zsr[0] < zsr[N - 1])) {
+      bound.xlo = -R(HUGE_VAL);
+      bound.xhi = R(HUGE_VAL);
     }
   }
   EntryList L{ent_t_all[wv], ent_c_all[wv], lane};
@@ -1305,11 +1318,12 @@ __global__ __launch_bounds__(WAVE * RES_WPB) __attribute__((amdgpu_waves_per_eu(
     const int bin = tile * f.n_slots + k;
     const int n_rec = counts[bin];
     if (n_rec > 0 && offsets[bin] + n_rec <= bin_cap)
-      walk_subdomain_queued(M, f, r, valid, records + offsets[bin], n_rec, slots[k], faces_all[wv], L, q, cnt);
+      walk_subdomain_queued(M, f, r, valid, records + offsets[bin], n_rec, slots[k], faces_all[wv], L, q, bound, zs,
+                            cont, cnt);
     else if (n_rec > 0)
       cnt.rare(C_OVERFLOW);  // binned beyond the record capacity (never on an eagerly sized workspace)
   }
-  q.drain(true);
+  q.drain(f, bound, zs, cont, true);
   cnt.pieces += q.pieces;
   cnt.tabled += q.solved;
   cnt.tab_fallback += q.closed_used;

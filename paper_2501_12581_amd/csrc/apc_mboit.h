@@ -55,6 +55,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 #if defined(__HIPCC__)
 #define APC_HD __host__ __device__ inline
 // out of line on the device: called once per pixel or for rare samples, and
@@ -445,17 +447,21 @@ APC_HD R pick_reg(const R* a, int i) {
   return r;
 }
 
-// K values held in registers, read with a run-time index through a chain of
-// selects (never an indexed register or scratch access; a constant index
-// folds to the element itself).
+// K values held in registers, read with a run-time index as an OR of masked
+// bit patterns (never an indexed register or scratch access; a constant index
+// folds to the element itself).  A chain of selects between the elements is
+// not enough: the compiler folds a select of two loads into one load from a
+// selected address, and a run-time address into the array keeps the whole
+// array, and any structure holding it, in scratch memory.
 template <int K, class R>
 struct RegArray {
   R v[K];
   APC_HD R operator[](int i) const {
-    R r = v[0];
+    using U = typename std::conditional<sizeof(R) == 8, unsigned long long, unsigned>::type;
+    U r = 0;
 #pragma unroll
-    for (int t = 1; t < K; ++t) r = i == t ? v[t] : r;
-    return r;
+    for (int t = 0; t < K; ++t) r |= (i == t ? ~U(0) : U(0)) & __builtin_bit_cast(U, v[t]);
+    return __builtin_bit_cast(R, r);
   }
 };
 
