@@ -1042,59 +1042,69 @@ __global__ __launch_bounds__(WAVE * EVAL_WPB) __attribute__((amdgpu_waves_per_eu
 // same warped depths and optical depths), and each piece is weighted at once
 // by the transmittance the moment bound gives at its depth.  Per pixel nothing
 // but (m + 1) moments in and 4 colour sums out, whatever the depth
-// complexity; no piece is written to memory (a lane queues at most RQ of its
-// pieces in LDS until the wavefront evaluates them together).  Each lane holds
-// its pixel's inverse Cholesky factor and the zeros of the degree-n
-// orthonormal polynomial in registers, and (n >= 3) starts a sample's root
-// solve from the previous sample's roots (apcm::Bound::frac_before_cont).  The
-// wavefronts of a workgroup walk different tiles and share one copy of the
-// transfer function.
-#ifndef APC_RES_WPB
-#define APC_RES_WPB 4
-#endif
-constexpr int RES_WPB = APC_RES_WPB;
-// Waves per SIMD the fused kernel is compiled for (register budget 512 / n): the walk's FP64 ray frame,
-// the walk position and its pixel's inverse factor stay in registers across the evaluation
-#ifndef APC_RES_WAVES
-#define APC_RES_WAVES 2
-#endif
-#ifndef APC_RES_QUEUE
-#define APC_RES_QUEUE 12
-#endif
+// complexity; no piece is written to memory.
+//
+// Each tile is one workgroup of two wavefronts, a walker and an evaluator.
+// The walk is bound by its dependent record loads and the evaluation by FP64
+// arithmetic, and the evaluation's per-pixel state (inverse Cholesky factor,
+// zeros of the degree-n orthonormal polynomial, continuation of the roots) is
+// what limits how many wavefronts a SIMD holds.  Split this way neither
+// wavefront holds the other's registers (three workgroups of two per SIMD,
+// where one wavefront doing both fits two), and the evaluator's arithmetic
+// fills the issue slots the walker spends waiting on memory.  The pieces pass
+// through a ring of PQ slots per lane in LDS.  The two wavefronts meet at
+// phase boundaries (workgroup barriers): at each the walker publishes how many
+// pieces each lane has produced and the evaluator how many it has evaluated;
+// between two boundaries the evaluator takes only pieces published at the
+// earlier one and the walker writes only ring slots evaluated before it, so
+// they never touch the same slot.  Per lane the pieces are evaluated in walk
+// order, each with the roots the previous one left
+// (apcm::Bound::frac_before_cont, n >= 3).
 #ifndef APC_RES_EMAX
 #define APC_RES_EMAX 8
 #endif
-constexpr int RQ = APC_RES_QUEUE;         // pieces queued per lane
-constexpr int RES_EMAX = APC_RES_EMAX;    // entries per ray held at once in the re-walk
-// walk steps a lane takes per iteration while its queue has room for another chord's pieces
+constexpr int RES_EMAX = APC_RES_EMAX;  // entries per ray held at once in the re-walk
+// walk steps a lane takes per iteration while its ring has room for another chord's pieces
 #ifndef APC_RES_BURST
 #define APC_RES_BURST 4
 #endif
-// A drain evaluates one queued piece per lane while at least this many lanes have one, or while some
-// lane's queue has no room for another chord's pieces (RQ - RES_ROOM queued: that lane cannot walk on)
-#ifndef APC_RES_DRAIN_MIN
-#define APC_RES_DRAIN_MIN 40
+constexpr int RES_ROOM = 3;  // ring slots a walk step needs free (a chord of one tet rarely has more pieces)
+#ifndef APC_PAIR_QUEUE
+#define APC_PAIR_QUEUE 16
 #endif
-constexpr int RES_ROOM = 3;
+// evaluation rounds per phase at most (one piece per lane per round).  Measured on the large frame (m = 8):
+// 4 rounds 148 ms, 6 130, 7 126, 8 132, 12 156, 16 192: fewer rounds keep the walker waiting for room, more
+// keep it waiting at the boundary
+#ifndef APC_PAIR_ROUNDS
+#define APC_PAIR_ROUNDS 7
+#endif
+// the walker ends its phase once this many 64ths of its lanes that still walk cannot take a step
+#ifndef APC_PAIR_BLOCKED
+#define APC_PAIR_BLOCKED 16
+#endif
+// wavefronts per SIMD the kernel is compiled for (register budget 512 / n)
+#ifndef APC_PAIR_WAVES
+#define APC_PAIR_WAVES 3
+#endif
+constexpr int PQ = APC_PAIR_QUEUE;
+static_assert((PQ & (PQ - 1)) == 0, "the ring size is a power of two");
 
-// Per-lane state of the fused re-walk: the pixel's moment bound, the colour
-// sums, a ring of queued pieces in LDS (lane-minor: the 64 lanes hit
-// distinct banks) and the chord being cut.  The walk only cuts chords and
-// queues pieces; the evaluation runs where the whole wavefront has
-// reconverged, one queued piece per lane, so the FP64 solve does not run at
-// the lane utilisation of the divergent walk.
-template <int N, class R>
-struct Resolver {
-  using Bd = apcm::Bound<N, R>;
-  using Zs = apcm::RegArray<N, R>;
-  using Ct = typename apcm::Bound<N, R>::Cont;
+struct PairLDS {
+  float q[3][PQ * WAVE];  // z, a, s of ring slot j of lane l at j * WAVE + l (the 64 lanes hit distinct banks)
+  int tail[2][WAVE];      // pieces lane l has produced, published at the boundaries of each parity
+  int head[2][WAVE];      // pieces of lane l evaluated
+  int done[2];            // the walker has no more pieces
+};
+
+// The walker's side: the chord being cut (bit for bit cut_chord's arithmetic,
+// resumable when the ring is full) and the ring position.
+struct Producer {
+  PairLDS* sh;
   const float4* tf;  // LDS RGBA table
-  R eta;
-  float a0, a1, a2, a3;
-  unsigned pieces, solved, closed_used;  // samples; of those, needing roots; of those, by the closed forms
-  float *qz, *qa, *qs;                   // [RQ][WAVE] each
-  int lane, head, len;
-  // the chord being cut (bit for bit cut_chord's arithmetic, resumable when the queue is full)
+  int lane, parity;
+  int tail;   // pieces produced
+  int limit;  // ring slots free up to here (evaluated count at the last boundary + PQ)
+  unsigned pieces;
   bool cutting;
   double cu, ckf, ct0, ct1;
   float cs0, cslope;
@@ -1113,10 +1123,10 @@ struct Resolver {
     cs0 = s0;
     cguard = 0;
   }
-  // queue pieces of the chord being cut until it ends or the queue is full
+  // ring the pieces of the chord being cut until it ends or the ring is full
   __device__ __forceinline__ void cut_more(const FrameDev& f) {
 #pragma clang fp contract(off)
-    while (cutting && len < RQ) {
+    while (cutting && tail < limit) {
       if (!(cu < ct1) || cguard >= (1 << 22)) {
         cutting = false;
         break;
@@ -1132,67 +1142,34 @@ struct Resolver {
       float fr, a, z;
       tf_coord(f, s, i0, fr);
       piece_az(f, tm, float(v - cu), lerp_nc(tf[i0].w, tf[i0 + 1].w, fr), a, z);  // as stage one
-      int slot = head + len;
-      slot -= slot >= RQ ? RQ : 0;
-      qz[slot * WAVE + lane] = z;
-      qa[slot * WAVE + lane] = a;
-      qs[slot * WAVE + lane] = s;
-      ++len;
+      const int slot = (tail & (PQ - 1)) * WAVE + lane;
+      sh->q[0][slot] = z;
+      sh->q[1][slot] = a;
+      sh->q[2][slot] = s;
+      ++tail;
       ++pieces;
       cu = v;
     }
   }
-  // evaluate the oldest queued piece (Alg. 1 second loop with Alg. 3's bound)
-  __device__ __forceinline__ void eval_one(const FrameDev& f, const Bd& bound, const Zs& zs, Ct& cont) {
-    const int slot = head;
-    const float z = qz[slot * WAVE + lane], a = qa[slot * WAVE + lane], s = qs[slot * WAVE + lane];
-    head = head + 1 == RQ ? 0 : head + 1;
-    --len;
-    if (bound.mode == 0) return;  // no absorbance on the ray: every piece has a = 0
-    int i0;
-    float fr;
-    tf_coord(f, s, i0, fr);
-    const float4 c0 = tf[i0], c1 = tf[i0 + 1];
-    R F;
-    if constexpr (N >= 3) {
-      int how;
-      F = bound.frac_before_cont(R(z), eta, zs, cont, how);
-      solved += how != 0 ? 1u : 0u;
-      closed_used += how == 2 ? 1u : 0u;
-    } else {
-      F = bound.frac_before(R(z), eta);
-    }
-    float T = __expf(-float(bound.b0 * F));
-    T = fminf(fmaxf(T, 0.0f), 1.0f);
-    const float w = T * (-expm1f(-a));
-    a0 += w * lerp_nc(c0.x, c1.x, fr);
-    a1 += w * lerp_nc(c0.y, c1.y, fr);
-    a2 += w * lerp_nc(c0.z, c1.z, fr);
-    a3 += w;
-  }
-  // called by the whole wavefront: one queued piece per lane while enough lanes have one or some lane's
-  // queue is too full to walk on (all: until every queue is empty).  Each round empties one slot of every
-  // non-empty queue, so after it every lane can take its next walk step or chord piece.
-  __device__ __forceinline__ void drain(const FrameDev& f, const Bd& bound, const Zs& zs, Ct& cont, bool all) {
-    while (true) {
-      const unsigned long long ready = __ballot(len > 0);
-      if (!ready) break;
-      if (!all && __popcll(ready) < APC_RES_DRAIN_MIN && !__any(len > RQ - RES_ROOM)) break;
-      if (len > 0) eval_one(f, bound, zs, cont);
-    }
+  __device__ __forceinline__ bool can_step() const { return tail <= limit - RES_ROOM; }
+  // phase boundary (the whole walker wavefront): publish, meet the evaluator, learn what it evaluated
+  __device__ __forceinline__ void boundary(bool finished) {
+    sh->tail[parity][lane] = tail;
+    if (lane == 0) sh->done[parity] = finished ? 1 : 0;
+    __syncthreads();
+    limit = sh->head[parity][lane] + PQ;
+    parity ^= 1;
   }
 };
 
 // All entries of this lane's ray into one subdomain, walked in (depth, code)
-// order, one walk step (or one entry start, or the rest of a chord) per lane
-// per iteration of a loop the whole wavefront runs, with the queue drained
-// between iterations.  The pieces, their order per ray and every depth are
-// those of walk_subdomain.
-template <int N, class R>
-__device__ __forceinline__ void walk_subdomain_queued(const MeshDev& M, const FrameDev& f, const Ray& r, bool valid, const int* rec,
-                                      int n_rec, const SlotDev& sl, FaceL* faces, EntryList& L, Resolver<N, R>& q,
-                                      const apcm::Bound<N, R>& bound, const apcm::RegArray<N, R>& zs,
-                                      typename apcm::Bound<N, R>::Cont& cont, LaneCount& cnt) {
+// order as in walk_subdomain (same pieces, same order), one entry start, the
+// rest of a chord or a few walk steps per lane per iteration of a loop the
+// whole walker wavefront runs; a lane whose ring has no room waits, and the
+// wavefront ends its phase when enough of its lanes wait.
+__device__ void walk_subdomain_paired(const MeshDev& M, const FrameDev& f, const Ray& r, bool valid, const int* rec,
+                                      int n_rec, const SlotDev& sl, FaceL* faces, EntryList& L, Producer& q,
+                                      LaneCount& cnt) {
   float last_t = -FLT_MAX;
   int last_c = -1;
   bool more = true;
@@ -1209,7 +1186,8 @@ __device__ __forceinline__ void walk_subdomain_queued(const MeshDev& M, const Fr
     float sin_ = 0.0f;
     while (true) {
       const bool busy = q.cutting || walking || k < n;
-      if (!__any(busy)) break;
+      const unsigned long long act = __ballot(busy);
+      if (!act) break;
       if (!q.cutting && !walking && k < n) {  // the next entry
         Entry e;
         int t, fc;
@@ -1225,9 +1203,8 @@ __device__ __forceinline__ void walk_subdomain_queued(const MeshDev& M, const Fr
         }
         ++k;
       }
-      if (q.cutting) q.cut_more(f);  // the rest of a chord that did not fit the queue
-      // a few walk steps while the queue has room for their pieces
-      for (int burst = 0; !q.cutting && walking && burst < APC_RES_BURST && q.len <= RQ - RES_ROOM; ++burst) {
+      if (q.cutting) q.cut_more(f);  // the rest of a chord that did not fit the ring
+      for (int burst = 0; !q.cutting && walking && burst < APC_RES_BURST && q.can_step(); ++burst) {
         if (steps >= f.max_steps) {
           cnt.rare(C_STEPLIMIT);
           walking = false;
@@ -1246,7 +1223,12 @@ __device__ __forceinline__ void walk_subdomain_queued(const MeshDev& M, const Fr
         cnt.segments += q.pieces > seg_start ? 1u : 0u;
         open = false;
       }
-      q.drain(f, bound, zs, cont, false);
+      // lanes that still have work here but no room to go on
+      const bool stuck = (q.cutting || walking || k < n) && !(q.cutting ? q.tail < q.limit : q.can_step());
+      const unsigned long long blocked = __ballot(stuck);
+      const unsigned long long still = __ballot(q.cutting || walking || k < n);
+      if (blocked && (blocked == still || __popcll(blocked) * 64 >= APC_PAIR_BLOCKED * __popcll(still)))
+        q.boundary(false);
     }
     if (n > 0) {
       last_t = L.T(n - 1);
@@ -1256,80 +1238,125 @@ __device__ __forceinline__ void walk_subdomain_queued(const MeshDev& M, const Fr
 }
 
 template <int N, class R>
-__global__ __launch_bounds__(WAVE * RES_WPB) __attribute__((amdgpu_waves_per_eu(APC_RES_WAVES, 8))) void k_resolve(
+__global__ __launch_bounds__(2 * WAVE) __attribute__((amdgpu_waves_per_eu(APC_PAIR_WAVES, 8))) void k_resolve(
     MeshDev M, FrameDev f, const SlotDev* __restrict__ slots, const int* __restrict__ offsets,
     const int* __restrict__ counts, const int* __restrict__ records, long long bin_cap,
     const float* __restrict__ tf_rgba, const void* __restrict__ moments, BoundParams bp, float* __restrict__ rgba,
     unsigned long long* ctr) {
   extern __shared__ float4 dyn_lds[];
   float4* tf = dyn_lds;  // [n_tf] RGBA
-  __shared__ FaceL faces_all[RES_WPB][CHUNK];
-  __shared__ float ent_t_all[RES_WPB][RES_EMAX * WAVE];
-  __shared__ int ent_c_all[RES_WPB][RES_EMAX * WAVE];
-  __shared__ float queue_all[RES_WPB][3][RQ * WAVE];
-  for (int i = threadIdx.x; i < f.n_tf; i += WAVE * RES_WPB)
+  __shared__ FaceL faces[CHUNK];
+  __shared__ float ent_t[RES_EMAX * WAVE];
+  __shared__ int ent_c[RES_EMAX * WAVE];
+  __shared__ PairLDS sh;
+  for (int i = threadIdx.x; i < f.n_tf; i += 2 * WAVE)
     tf[i] = make_float4(tf_rgba[4 * i], tf_rgba[4 * i + 1], tf_rgba[4 * i + 2], tf_rgba[4 * i + 3]);
-  __syncthreads();  // the only workgroup barrier: every later wait is within a wavefront
-  const int wv = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x, (XCD_RUN + RES_WPB - 1) / RES_WPB) * RES_WPB + wv;
-  if (tile >= f.n_tiles) return;
+  __syncthreads();
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  if (tile >= f.n_tiles) return;  // both wavefronts of the workgroup alike
+  const bool walker = threadIdx.x < WAVE;
+  const int lane = threadIdx.x % WAVE;
   const int tx = tile % f.tiles_x, ty = tile / f.tiles_x;
   const int px = (tx << f.tw_log2) + (lane & ((1 << f.tw_log2) - 1)),
             py = ty * (WAVE >> f.tw_log2) + (lane >> f.tw_log2);
   const bool valid = px < f.W && py < f.H;
-  const Ray r = pixel_ray(f, valid ? py : 0, valid ? px : 0);
-  const size_t HW = size_t(f.W) * f.H, pix = size_t(py) * f.W + px;
   LaneCount cnt = {};
   cnt.ctr = ctr;
-  Resolver<N, R> q;
-  apcm::Bound<N, R> bound;
-  apcm::RegArray<N, R> zs;
-  typename apcm::Bound<N, R>::Cont cont;
-  q.tf = tf;
-  q.eta = R(bp.eta);
-  q.a0 = q.a1 = q.a2 = q.a3 = 0.0f;
-  q.pieces = q.solved = q.closed_used = 0u;
-  q.qz = queue_all[wv][0];
-  q.qa = queue_all[wv][1];
-  q.qs = queue_all[wv][2];
-  q.lane = lane;
-  q.head = q.len = 0;
-  q.cutting = false;
-  cont.k = -1;
-#pragma unroll
-  for (int c = 0; c < int(sizeof(cont.v) / sizeof(R)); ++c) cont.v[c] = R(0);
-  float b0f;
-  {  // per-pixel part of Alg. 3, once per pixel instead of once per sample
-    R b[2 * N + 1], bias[2 * N], zsr[N];
-    b0f = pixel_moments<N, R>(moments, bp.moments_f16, valid, pix, HW, b);
-#pragma unroll
-    for (int j = 0; j < 2 * N; ++j) bias[j] = R(bp.bias[j]);
-    cnt.nonpd += bound.setup(b, R(bp.alpha), bias, zsr);
-#pragma unroll
-    for (int i = 0; i < N; ++i) zs.v[i] = zsr[i];
-    // no zeros found (never expected for a positive definite factor): no shortcut, every sample solves
-    if (bound.mode == 2 && !(zsr[0] < zsr[N - 1])) {
-      bound.xlo = -R(HUGE_VAL);
-      bound.xhi = R(HUGE_VAL);
+  if (walker) {
+    const Ray r = pixel_ray(f, valid ? py : 0, valid ? px : 0);
+    Producer q;
+    q.sh = &sh;
+    q.tf = tf;
+    q.lane = lane;
+    q.parity = 0;
+    q.tail = 0;
+    q.limit = PQ;
+    q.pieces = 0u;
+    q.cutting = false;
+    EntryList L{ent_t, ent_c, lane};
+    for (int k = 0; k < f.n_slots; ++k) {
+      const int bin = tile * f.n_slots + k;
+      const int n_rec = counts[bin];
+      if (n_rec > 0 && offsets[bin] + n_rec <= bin_cap)
+        walk_subdomain_paired(M, f, r, valid, records + offsets[bin], n_rec, slots[k], faces, L, q, cnt);
+      else if (n_rec > 0)
+        cnt.rare(C_OVERFLOW);  // binned beyond the record capacity (never on an eagerly sized workspace)
     }
+    q.boundary(true);
+    cnt.pieces += q.pieces;
+  } else {
+    const size_t HW = size_t(f.W) * f.H, pix = size_t(py) * f.W + px;
+    // per-pixel part of Alg. 3, once per pixel instead of once per sample; the bound, its zeros and the
+    // continuation are separate locals (a structure holding a run-time indexed array would live in scratch)
+    apcm::Bound<N, R> bound;
+    apcm::RegArray<N, R> zs;
+    typename apcm::Bound<N, R>::Cont cont;
+    cont.k = -1;
+#pragma unroll
+    for (int c = 0; c < int(sizeof(cont.v) / sizeof(R)); ++c) cont.v[c] = R(0);
+    float b0f;
+    {
+      R b[2 * N + 1], bias[2 * N], zsr[N];
+      b0f = pixel_moments<N, R>(moments, bp.moments_f16, valid, pix, HW, b);
+#pragma unroll
+      for (int j = 0; j < 2 * N; ++j) bias[j] = R(bp.bias[j]);
+      cnt.nonpd += bound.setup(b, R(bp.alpha), bias, zsr);
+#pragma unroll
+      for (int i = 0; i < N; ++i) zs.v[i] = zsr[i];
+      // no zeros found (never expected for a positive definite factor): no shortcut, every sample solves
+      if (bound.mode == 2 && !(zsr[0] < zsr[N - 1])) {
+        bound.xlo = -R(HUGE_VAL);
+        bound.xhi = R(HUGE_VAL);
+      }
+    }
+    const R eta = R(bp.eta);
+    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+    unsigned solved = 0u, closed_used = 0u;  // samples needing roots; of those, by the closed forms
+    int head = 0, avail = 0, parity = 0;
+    auto eval_one = [&]() {  // Alg. 1 second loop with Alg. 3's bound, for the piece at `head`
+      const int slot = (head & (PQ - 1)) * WAVE + lane;
+      const float z = sh.q[0][slot], a = sh.q[1][slot], s = sh.q[2][slot];
+      ++head;
+      if (bound.mode == 0) return;  // no absorbance on the ray: every piece has a = 0
+      int i0;
+      float fr;
+      tf_coord(f, s, i0, fr);
+      const float4 c0 = tf[i0], c1 = tf[i0 + 1];
+      R F;
+      if constexpr (N >= 3) {
+        int how;
+        F = bound.frac_before_cont(R(z), eta, zs, cont, how);
+        solved += how != 0 ? 1u : 0u;
+        closed_used += how == 2 ? 1u : 0u;
+      } else {
+        F = bound.frac_before(R(z), eta);
+      }
+      float T = __expf(-float(bound.b0 * F));
+      T = fminf(fmaxf(T, 0.0f), 1.0f);
+      const float w = T * (-expm1f(-a));
+      a0 += w * lerp_nc(c0.x, c1.x, fr);
+      a1 += w * lerp_nc(c0.y, c1.y, fr);
+      a2 += w * lerp_nc(c0.z, c1.z, fr);
+      a3 += w;
+    };
+    while (true) {  // one phase per iteration, as many as the walker has
+      for (int round = 0; round < APC_PAIR_ROUNDS && __any(head < avail); ++round)
+        if (head < avail) eval_one();
+      sh.head[parity][lane] = head;
+      __syncthreads();
+      avail = sh.tail[parity][lane];
+      const bool fin = sh.done[parity] != 0;
+      parity ^= 1;
+      if (fin) break;
+    }
+    while (__any(head < avail))
+      if (head < avail) eval_one();
+    cnt.tabled += solved;
+    cnt.tab_fallback += closed_used;
+    if (valid)
+      reinterpret_cast<float4*>(rgba)[pix] =
+          finalize_px(make_float4(a0, a1, a2, a3), b0f, bp.finalize, bp.renormalize);
   }
-  EntryList L{ent_t_all[wv], ent_c_all[wv], lane};
-  for (int k = 0; k < f.n_slots; ++k) {
-    const int bin = tile * f.n_slots + k;
-    const int n_rec = counts[bin];
-    if (n_rec > 0 && offsets[bin] + n_rec <= bin_cap)
-      walk_subdomain_queued(M, f, r, valid, records + offsets[bin], n_rec, slots[k], faces_all[wv], L, q, bound, zs,
-                            cont, cnt);
-    else if (n_rec > 0)
-      cnt.rare(C_OVERFLOW);  // binned beyond the record capacity (never on an eagerly sized workspace)
-  }
-  q.drain(f, bound, zs, cont, true);
-  cnt.pieces += q.pieces;
-  cnt.tabled += q.solved;
-  cnt.tab_fallback += q.closed_used;
-  if (valid)
-    reinterpret_cast<float4*>(rgba)[pix] =
-        finalize_px(make_float4(q.a0, q.a1, q.a2, q.a3), b0f, bp.finalize, bp.renormalize);
   flush_counts(cnt, ctr);
 }
 
@@ -1686,7 +1713,7 @@ hipError_t launch_resolve(int mm, const MeshDev& m, const FrameDev& f, const Slo
                           const void* moments, const BoundParams& bp, float* rgba, unsigned long long* counters,
                           hipStream_t s) {
   const size_t lds = size_t(f.n_tf) * sizeof(float4);
-  const dim3 grid((f.n_tiles + RES_WPB - 1) / RES_WPB), block(WAVE * RES_WPB);
+  const dim3 grid(f.n_tiles), block(2 * WAVE);  // one tile per workgroup: its walker and its evaluator
   if (mm == 4)
     hipLaunchKernelGGL((k_resolve<2, float>), grid, block, lds, s, m, f, slots, offsets, counts, records, bin_cap,
                        tf_rgba, moments, bp, rgba, counters);
