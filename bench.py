@@ -409,6 +409,21 @@ def batching_leg(bsc, steps=5):
         out["graph_rgba_bitwise_equal"] = bool(torch.equal(r.rgba, rgba0))
     finally:
         g.close()
+    # the same plain frames from a persistent launch taking tiles from a work queue, against one workgroup
+    # per tile: all 5 cameras, each pass's kernel time
+    grid_kern = out["kernels_ms_mean"]
+    ctx.set_dispatch(apc.APC_DISPATCH_QUEUE)
+    try:
+        fr.frame(0)
+        torch.cuda.synchronize()
+        same = bool(torch.equal(r.rgba, rgba0))
+        qrun = fr.timed(steps)
+        out["work_queue"] = {
+            "median_camera_frame_ms": round(qrun["median_camera_ms"], 3),
+            "kernels_ms_mean": {k: round(float(np.mean(v)), 3) for k, v in qrun["kernels"].items()},
+            "grid_kernels_ms_mean": grid_kern, "rgba_bitwise_equal_camera0": same}
+    finally:
+        ctx.set_dispatch(apc.APC_DISPATCH_GRID)
     del fr, kf, r
     ctx.close()
     torch.cuda.synchronize()

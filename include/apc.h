@@ -352,6 +352,29 @@ apc_status apc_frame_graph_destroy(apc_graph graph);
 apc_status apc_set_tile_shape(apc_ctx ctx, int32_t tile_width);  /* 1, 2, 4, ..., 64; else APC_E_ARG */
 apc_status apc_get_tile_shape(apc_ctx ctx, int32_t* tile_width, int32_t* tile_height);
 
+/* ------------------------------------------------------------------ dispatch */
+
+/* How both passes hand their tiles (tile x subdomain-list work units, the
+ * batching of Section 5.3's uneven partitions) to the GPU; a property of the
+ * context for later passes, frame graphs included.  Results are identical
+ * either way (each tile is computed by the same code in the same order).
+ *   APC_DISPATCH_GRID   one workgroup per tile, handed out by the hardware
+ *                       (default).
+ *   APC_DISPATCH_QUEUE  persistent: as many workgroups as the device holds
+ *                       at once, each taking tile after tile from a work
+ *                       queue of per-XCD counters (the order of
+ *                       APC_DISPATCH_GRID per XCD; an XCD whose tiles are
+ *                       gone takes the next XCD's).  The counters (32 bytes)
+ *                       are allocated by this call, so that no pass
+ *                       allocates them; they are reset on the caller's
+ *                       stream by a kernel before each pass, so two passes
+ *                       of one context must not overlap in time.
+ * Other modes: APC_E_ARG. */
+#define APC_DISPATCH_GRID 0
+#define APC_DISPATCH_QUEUE 1
+apc_status apc_set_dispatch(apc_ctx ctx, int32_t mode);
+apc_status apc_get_dispatch(apc_ctx ctx, int32_t* mode);
+
 /* Autotuner: times whole frames -- stage one summing the subdomains itself
  * (APC_MOMENTS_GLOBAL: `subdomains` ascending, else APC_E_ARG) followed by
  * the finalising resolve, as a frame on one GPU runs them -- for tile widths

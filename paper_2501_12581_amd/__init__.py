@@ -24,6 +24,8 @@ APC_MOMENTS_GLOBAL = 8
 APC_KEEP_PIECES = 16
 APC_DEVICE_NONE = -1   # apc_create: a host-only context (validates, launches nothing)
 APC_MESH_DEVICE = 1    # apc_mesh_desc.flags: the mesh arrays are device memory
+APC_DISPATCH_GRID = 0   # apc_set_dispatch: one workgroup per tile
+APC_DISPATCH_QUEUE = 1  # apc_set_dispatch: persistent workgroups taking tiles from a work queue
 STATUS = {0: "APC_OK", 1: "APC_E_ARG", 2: "APC_E_MESH", 3: "APC_E_NOMEM", 4: "APC_E_DEVICE",
           5: "APC_E_NUMERIC", 6: "APC_E_UNSUPPORTED"}
 EXPORTS = ["apc_create", "apc_destroy", "apc_last_error", "apc_version", "apc_load_mesh", "apc_free_mesh",
@@ -31,7 +33,8 @@ EXPORTS = ["apc_create", "apc_destroy", "apc_last_error", "apc_version", "apc_lo
            "apc_resolve_pass", "apc_sum_images", "apc_pack_moments_f16", "apc_segment_counts", "apc_get_counters",
            "apc_get_timings", "apc_set_tile_shape", "apc_get_tile_shape", "apc_autotune_tile_shape",
            "apc_frame_graph_create", "apc_frame_graph_launch", "apc_frame_graph_counters", "apc_frame_graph_destroy",
-           "apc_set_workspace_limit", "apc_resolve_pass_noalloc", "apc_get_workspace_bytes"]
+           "apc_set_workspace_limit", "apc_resolve_pass_noalloc", "apc_get_workspace_bytes", "apc_set_dispatch",
+           "apc_get_dispatch"]
 
 
 class ApcError(RuntimeError):
@@ -136,6 +139,10 @@ def lib():
         L.apc_set_tile_shape.argtypes = [vp, C.c_int32]
         L.apc_get_tile_shape.restype = st
         L.apc_get_tile_shape.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.apc_set_dispatch.restype = st
+        L.apc_set_dispatch.argtypes = [vp, C.c_int32]
+        L.apc_get_dispatch.restype = st
+        L.apc_get_dispatch.argtypes = [vp, C.POINTER(C.c_int32)]
         L.apc_autotune_tile_shape.restype = st
         L.apc_autotune_tile_shape.argtypes = [vp, vp, C.POINTER(View), C.POINTER(TF), C.POINTER(Mboit), vp,
                                               C.c_int32, vp, vp, C.c_int32, C.POINTER(C.c_int32), vp, vp]
@@ -333,8 +340,17 @@ class Context:
         return b.value
 
     def set_workspace_limit(self, nbytes):
-        """Cap the kept-piece pool at 3/4 and the re-walk staging buffer at 1/4 of nbytes (0: default policy)."""
+        """Cap the kept-piece pool (APC_KEEP_PIECES) at nbytes (0: default policy)."""
         self._ck(lib().apc_set_workspace_limit(self.handle, int(nbytes)))
+
+    def set_dispatch(self, mode):
+        """APC_DISPATCH_GRID (one workgroup per tile) or APC_DISPATCH_QUEUE (persistent work queue)."""
+        self._ck(lib().apc_set_dispatch(self.handle, int(mode)))
+
+    def dispatch(self):
+        v = C.c_int32(0)
+        self._ck(lib().apc_get_dispatch(self.handle, C.byref(v)))
+        return v.value
 
     def set_tile_shape(self, tile_width):
         self._ck(lib().apc_set_tile_shape(self.handle, int(tile_width)))

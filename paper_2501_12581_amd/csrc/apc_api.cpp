@@ -155,6 +155,8 @@ struct apc_ctx_s {
   apc_tf store_tf = {};              // the transfer function they were made with
   bool store_failed_last = false;    // the last resolve found that stage one could not keep every piece
   int64_t ws_limit = 0;              // bytes for the piece pool (0: up to 60 % of free memory)
+  int dispatch = APC_DISPATCH_GRID;  // how both passes spread their tiles (apc_set_dispatch)
+  DevBuf queue;                      // the work queue's per-XCD tile counters (APC_DISPATCH_QUEUE)
 };
 
 struct apc_graph_s {
@@ -359,6 +361,8 @@ apc_status check_subdomains(const apc_mesh_s* m, const int32_t* subs, int32_t n_
 }
 
 // records the bin buffer holds
+// the tile counters of a persistent launch, or null for one workgroup per tile
+int* tile_queue(apc_ctx ctx) { return ctx->dispatch == APC_DISPATCH_QUEUE ? ctx->queue.as<int>() : nullptr; }
 long long bin_cap(apc_ctx ctx) { return (long long)(ctx->records.bytes / sizeof(int)); }
 
 // Where a frame's binning state lives: the context's growable buffers, or
@@ -599,8 +603,8 @@ apc_status apc_destroy(apc_ctx ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   for (DevBuf* b : {&ctx->counts, &ctx->offsets, &ctx->cursors, &ctx->records, &ctx->scan_tmp, &ctx->slots,
-                    &ctx->order, &ctx->counters, &ctx->pcount, &ctx->segs, &ctx->gacc, &ctx->pool, &ctx->ptab,
-                    &ctx->store_next})
+                    &ctx->order, &ctx->counters, &ctx->pcount, &ctx->segs, &ctx->gacc, &ctx->queue, &ctx->pool,
+                    &ctx->ptab, &ctx->store_next})
     b->release();
   if (ctx->staging) (void)hipHostFree(ctx->staging);
   if (ctx->staging_done) (void)hipEventDestroy(ctx->staging_done);
@@ -942,7 +946,7 @@ apc_status apc_moments_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const
   HIPCHK(apc::launch_moments(mm, md, f, ctx->slots.as<SlotDev>(), ctx->offsets.as<int>(), ctx->counts.as<int>(),
                              ctx->records.as<int>(), bin_cap(ctx), tf->rgba, out,
                              global ? ctx->gacc.as<double>() : nullptr, ctx->pcount.as<int>(), ctx->segs.as<int>(), ps,
-                             ctx->counters.as<unsigned long long>(), s));
+                             ctx->counters.as<unsigned long long>(), tile_queue(ctx), s));
   HIPCHK(ev_mark(ctx, EV_MOM, 1, s));
   set_piece_key(ctx, m, view, subs, n_sub);
   ctx->store_ready = ps.pool != nullptr;
@@ -1079,7 +1083,8 @@ static apc_status resolve_frame(apc_ctx ctx, apc_mesh m, const apc_view* view, c
   if ((st = build_bins(ctx, m, f, subs, n_sub, s, md)) != APC_OK) return st;
   HIPCHK(ev_mark(ctx, EV_STG, 0, s));
   HIPCHK(apc::launch_resolve(mb->m, md, f, ctx->slots.as<SlotDev>(), ctx->offsets.as<int>(), ctx->counts.as<int>(),
-                             ctx->records.as<int>(), bin_cap(ctx), tf->rgba, moments, bp, rgba, ctr, s));
+                             ctx->records.as<int>(), bin_cap(ctx), tf->rgba, moments, bp, rgba, ctr, tile_queue(ctx),
+                             s));
   HIPCHK(ev_mark(ctx, EV_STG, 1, s));
   HIPCHK(ev_mark(ctx, EV_RES, 1, s));
   return APC_OK;
@@ -1125,7 +1130,7 @@ apc_status apc_resolve_pass_noalloc(apc_ctx ctx, apc_mesh m, const apc_view* vie
   if ((st = bin_faces(ctx, m, f, subs, n_sub, B, s, md)) != APC_OK) return st;
   HIPCHK(ev_mark(ctx, EV_STG, 0, s));
   HIPCHK(apc::launch_resolve(mb->m, md, f, B.slots, B.offsets, B.counts, B.records, B.rec_cap, tf->rgba, moments, bp,
-                             rgba, ctr, s));
+                             rgba, ctr, tile_queue(ctx), s));
   HIPCHK(ev_mark(ctx, EV_STG, 1, s));
   HIPCHK(ev_mark(ctx, EV_RES, 1, s));
   return APC_OK;
@@ -1165,6 +1170,10 @@ apc_status apc_frame_graph_create(apc_ctx ctx, apc_mesh m, const apc_view* view,
     return st;
   }
   g->own->tw_log2 = ctx->tw_log2;
+  if ((st = apc_set_dispatch(g->own, ctx->dispatch)) != APC_OK) {
+    apc_frame_graph_destroy(g);
+    return st;
+  }
   if (hipStreamCreateWithFlags(&g->cs, hipStreamNonBlocking) != hipSuccess) {
     apc_frame_graph_destroy(g);
     return fail(APC_E_DEVICE, "stream creation failed");
@@ -1251,10 +1260,30 @@ apc_status apc_get_workspace_bytes(apc_ctx ctx, int64_t* bytes) {
   if (!bytes) return fail(APC_E_ARG, "bytes is NULL");
   int64_t total = 0;
   for (const DevBuf* b : {&ctx->counts, &ctx->offsets, &ctx->cursors, &ctx->records, &ctx->scan_tmp, &ctx->slots,
-                          &ctx->order, &ctx->counters, &ctx->pcount, &ctx->segs, &ctx->gacc, &ctx->pool, &ctx->ptab,
-                          &ctx->store_next})
+                          &ctx->order, &ctx->counters, &ctx->pcount, &ctx->segs, &ctx->gacc, &ctx->queue, &ctx->pool,
+                          &ctx->ptab, &ctx->store_next})
     total += int64_t(b->bytes);
   *bytes = total;
+  return APC_OK;
+}
+
+apc_status apc_set_dispatch(apc_ctx ctx, int32_t mode) {
+  apc_status st = check_ctx(ctx);
+  if (st != APC_OK) return st;
+  if (mode != APC_DISPATCH_GRID && mode != APC_DISPATCH_QUEUE) return fail(APC_E_ARG, "unknown dispatch mode %d", mode);
+  if (mode == APC_DISPATCH_QUEUE && !ctx->host_only) {  // the counters now, so that no pass allocates them
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(ctx->queue.ensure(sizeof(int) * apc::QUEUE_INTS));
+  }
+  ctx->dispatch = mode;
+  return APC_OK;
+}
+
+apc_status apc_get_dispatch(apc_ctx ctx, int32_t* mode) {
+  apc_status st = check_ctx(ctx);
+  if (st != APC_OK) return st;
+  if (!mode) return fail(APC_E_ARG, "mode is NULL");
+  *mode = ctx->dispatch;
   return APC_OK;
 }
 

@@ -99,13 +99,16 @@ hipError_t launch_bin_fill(const MeshDev& m, const FrameDev& f, const SlotDev* s
 hipError_t launch_moments(int mm, const MeshDev& m, const FrameDev& f, const SlotDev* slots, const int* offsets,
                           const int* counts, const int* records, long long bin_cap, const float* tf_rgba, float* out,
                           double* gacc, int* pcount, int* segs, const PieceStore& store,
-                          unsigned long long* counters, hipStream_t s);
+                          unsigned long long* counters, int* queue, hipStream_t s);
+// queue (both passes): null for one workgroup per tile; else QUEUE_INTS device ints that the launch
+// resets and a persistent launch (as many workgroups as the device holds) takes the tiles from
+constexpr int QUEUE_INTS = 8;
 // stage two, plain form: the rays are walked again and every piece is evaluated at once (no piece
 // is kept); rgba [H][W][4] receives the listed subdomains' colour sums, finalised with bp.finalize
 hipError_t launch_resolve(int mm, const MeshDev& m, const FrameDev& f, const SlotDev* slots, const int* offsets,
                           const int* counts, const int* records, long long bin_cap, const float* tf_rgba,
                           const void* moments, const BoundParams& bp, float* rgba, unsigned long long* counters,
-                          hipStream_t s);
+                          int* queue, hipStream_t s);
 // stage two from the pieces stage one kept (store, pcount per pixel) for tiles [tile_lo, tile_hi)
 hipError_t launch_eval(int mm, const FrameDev& f, int tile_lo, int tile_hi, const PieceStore& store,
                        const int* pcount, const float* tf_rgba, const void* moments, const BoundParams& bp,

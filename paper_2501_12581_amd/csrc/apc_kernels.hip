@@ -72,6 +72,24 @@ __device__ __forceinline__ int xcd_tile(int b, int nb, int run = XCD_RUN) {
   return whole + x * q + (x < r ? x : r) + i;
 }
 
+// Persistent launches (a work queue): as many workgroups as the device holds
+// at once, each taking tile after tile until none is left.  The tiles are
+// the ones the ordinary launch of nb workgroups would give, per XCD in the
+// same order: XCD x owns the tiles of the workgroups b = 8k + x, handed out
+// by its own counter q[x]; a workgroup whose XCD has none left takes the next
+// one of the following XCDs.  Called by one lane; -1 when all are taken.
+__device__ __forceinline__ int queue_take(int* q, int nb) {
+  const int x = blockIdx.x & 7;
+  for (int d = 0; d < 8; ++d) {
+    const int y = (x + d) & 7;
+    const int own = (nb - y + 7) >> 3;  // workgroups b < nb with b % 8 == y
+    if (__hip_atomic_load(q + y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= own) continue;
+    const int k = atomicAdd(q + y, 1);
+    if (k < own) return xcd_tile(8 * k + y, nb);
+  }
+  return -1;
+}
+
 // A pixel ray in FP64: origin o (moved forward by t_mid), unit direction d,
 // and unit vectors a, b = d x a perpendicular to d, so that (a, b, d) is a
 // right-handed orthonormal frame.
@@ -185,7 +203,7 @@ __device__ __forceinline__ void face_point(const VS& A, const VS& B, const VS& C
     s = s0;
     return;
   }
-  float inv = 1.0f / sum;
+  float inv = __builtin_amdgcn_rcpf(sum);  // 1 ulp; both passes alike
   t = t0 + double((u1 * float(t1 - t0) + u2 * float(t2 - t0)) * inv);
   s = (u0 * s0 + u1 * s1 + u2 * s2) * inv;
 }
@@ -242,7 +260,7 @@ __device__ __forceinline__ void cut_chord(const FrameDev& f, double t0, double t
 #pragma clang fp contract(off)
   const double len = t1 - t0;
   if (!(len > 0.0)) return;
-  const float slope = (s1 - s0) / float(len);
+  const float slope = (s1 - s0) * __builtin_amdgcn_rcpf(float(len));
   double kf = floor((t0 - f.t_near) * f.inv_step) + 1.0;
   double u = t0;
   for (int guard = 0; u < t1 && guard < (1 << 22); ++guard) {
@@ -658,11 +676,12 @@ struct MomentSink {
       tf_coord(*f, s, i0, fr);
       float A = lerp_nc(tfa[i0], tfa[i0 + 1], fr);
       piece_az(*f, tm, len, A, a, z);
-      float term = a;
+      double term = a;  // the powers in FP64 too: one conversion per piece, not one per moment
+      const double zd = z;
 #pragma unroll
       for (int j = 0; j < M1; ++j) {  // Alg. 2: moment j gains absorbance * depth^j
-        b[j] += double(term);
-        term *= z;
+        b[j] += term;
+        term *= zd;
       }
       if constexpr (KEEP) st.put(z, a, s, lane);
       ++pieces;
@@ -675,13 +694,13 @@ struct MomentSink {
 #define APC_WALK_WAVES 3
 #endif
 
-template <int M1, bool KEEP>
+template <int M1, bool KEEP, bool QUEUE>
 __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_WALK_WAVES, 8))) void k_moments(MeshDev M, FrameDev f, const SlotDev* __restrict__ slots,
                                                   const int* __restrict__ offsets, const int* __restrict__ counts,
                                                   const int* __restrict__ records, const float* __restrict__ tf_rgba,
                                                   float* __restrict__ out, double* __restrict__ gacc,
                                                   int* __restrict__ pcount, int* __restrict__ segs, long long bin_cap,
-                                                  PieceStore ps, unsigned long long* ctr) {
+                                                  PieceStore ps, unsigned long long* ctr, int* queue) {
   extern __shared__ float4 dyn_lds[];
   float* tfa = reinterpret_cast<float*>(dyn_lds);  // [n_tf] alpha column
   __shared__ FaceL faces[CHUNK];
@@ -689,7 +708,17 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_WALK_W
   __shared__ int ent_c[E_MAX * WAVE];
   const int lane = threadIdx.x;
   for (int i = lane; i < f.n_tf; i += WAVE) tfa[i] = tf_rgba[4 * i + 3];
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  __shared__ unsigned long long blk_base;
+  __shared__ int blk_used;
+  if (lane == 0) {
+    blk_base = 0;
+    blk_used = STORE_BLOCK;  // no block yet
+  }
+  __syncthreads();
+  int tile = QUEUE ? __builtin_amdgcn_readfirstlane(lane == 0 ? queue_take(queue, f.n_tiles) : 0)
+                   : xcd_tile(blockIdx.x, gridDim.x);
+  for (; tile >= 0;
+       tile = QUEUE ? __builtin_amdgcn_readfirstlane(lane == 0 ? queue_take(queue, f.n_tiles) : 0) : -1) {
   const int tx = tile % f.tiles_x, ty = tile / f.tiles_x;
   const int px = (tx << f.tw_log2) + (lane & ((1 << f.tw_log2) - 1)),
             py = ty * (WAVE >> f.tw_log2) + (lane >> f.tw_log2);
@@ -707,16 +736,9 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_WALK_W
   MomentSink<M1, KEEP> sink;  // one sink for all subdomains: its piece store runs across them
   sink.f = &f;
   sink.tfa = tfa;
-  __shared__ unsigned long long blk_base;
-  __shared__ int blk_used;
-  if (lane == 0) {
-    blk_base = 0;
-    blk_used = STORE_BLOCK;  // no block yet
-  }
   sink.st = LaneStore{ps, size_t(tile) * WAVE + lane, 0u, nullptr, ps.pool != nullptr && valid, (lds_vu64*)&blk_base,
                       (lds_vi32*)&blk_used};
   sink.lane = lane;
-  __syncthreads();
   for (int k = 0; k < f.n_slots; ++k) {
     const int bin = tile * f.n_slots + k;
     const int n_rec = counts[bin];
@@ -771,6 +793,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_WALK_W
     segs[HW + pix] = covering;
   }
   flush_counts(cnt, ctr);
+  }  // tiles
 }
 
 // ------------------------------------------------------------------ stage two, kept pieces
@@ -1115,7 +1138,7 @@ struct Producer {
     const double len_c = t1 - t0;
     cutting = len_c > 0.0;
     if (!cutting) return;
-    cslope = (s1 - s0) / float(len_c);
+    cslope = (s1 - s0) * __builtin_amdgcn_rcpf(float(len_c));  // as cut_chord
     ckf = floor((t0 - f.t_near) * f.inv_step) + 1.0;
     cu = t0;
     ct0 = t0;
@@ -1237,23 +1260,24 @@ __device__ void walk_subdomain_paired(const MeshDev& M, const FrameDev& f, const
   }
 }
 
-template <int N, class R>
+template <int N, class R, bool QUEUE>
 __global__ __launch_bounds__(2 * WAVE) __attribute__((amdgpu_waves_per_eu(APC_PAIR_WAVES, 8))) void k_resolve(
     MeshDev M, FrameDev f, const SlotDev* __restrict__ slots, const int* __restrict__ offsets,
     const int* __restrict__ counts, const int* __restrict__ records, long long bin_cap,
     const float* __restrict__ tf_rgba, const void* __restrict__ moments, BoundParams bp, float* __restrict__ rgba,
-    unsigned long long* ctr) {
+    unsigned long long* ctr, int* queue) {
   extern __shared__ float4 dyn_lds[];
   float4* tf = dyn_lds;  // [n_tf] RGBA
   __shared__ FaceL faces[CHUNK];
   __shared__ float ent_t[RES_EMAX * WAVE];
   __shared__ int ent_c[RES_EMAX * WAVE];
   __shared__ PairLDS sh;
+  __shared__ int next_tile;
   for (int i = threadIdx.x; i < f.n_tf; i += 2 * WAVE)
     tf[i] = make_float4(tf_rgba[4 * i], tf_rgba[4 * i + 1], tf_rgba[4 * i + 2], tf_rgba[4 * i + 3]);
+  if (threadIdx.x == 0) next_tile = QUEUE ? queue_take(queue, f.n_tiles) : xcd_tile(blockIdx.x, gridDim.x);
   __syncthreads();
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  if (tile >= f.n_tiles) return;  // both wavefronts of the workgroup alike
+  for (int tile = next_tile; tile >= 0;) {  // the same tiles for both wavefronts of the workgroup
   const bool walker = threadIdx.x < WAVE;
   const int lane = threadIdx.x % WAVE;
   const int tx = tile % f.tiles_x, ty = tile / f.tiles_x;
@@ -1358,6 +1382,13 @@ __global__ __launch_bounds__(2 * WAVE) __attribute__((amdgpu_waves_per_eu(APC_PA
           finalize_px(make_float4(a0, a1, a2, a3), b0f, bp.finalize, bp.renormalize);
   }
   flush_counts(cnt, ctr);
+  if (!QUEUE) break;
+  // both wavefronts are done with the tile (and with next_tile): take the next one
+  __syncthreads();
+  if (threadIdx.x == 0) next_tile = queue_take(queue, f.n_tiles);
+  __syncthreads();
+  tile = next_tile;
+  }  // tiles
 }
 
 // walk records: [ids][neighbours][v0][v1][v2][v3], 8 x 16 bytes per tet
@@ -1665,20 +1696,50 @@ hipError_t launch_bin_fill(const MeshDev& m, const FrameDev& f, const SlotDev* s
   return hipGetLastError();
 }
 
+// Workgroups of `kernel` the device holds at once (the grid of a persistent launch), at least one.
+template <class K>
+static int resident_blocks(K kernel, int block, size_t lds) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, lds) != hipSuccess)
+    return 1;
+  return cus * per_cu > 0 ? cus * per_cu : 1;
+}
+
+// the 8 per-XCD tile counters of a persistent launch start at zero (a fill kernel, not a memset: the
+// launch may be captured in a graph)
+static hipError_t reset_queue(int* queue, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, s, queue, 0, int64_t(QUEUE_INTS));
+  return hipGetLastError();
+}
+
 hipError_t launch_moments(int mm, const MeshDev& m, const FrameDev& f, const SlotDev* slots, const int* offsets,
                           const int* counts, const int* records, long long bin_cap, const float* tf_rgba, float* out,
                           double* gacc, int* pcount, int* segs, const PieceStore& store,
-                          unsigned long long* counters, hipStream_t s) {
+                          unsigned long long* counters, int* queue, hipStream_t s) {
   const size_t lds = size_t(f.n_tf) * sizeof(float);
-  const dim3 grid(f.n_tiles), block(WAVE);
+  const dim3 block(WAVE);
+  if (queue) {
+    const hipError_t e = reset_queue(queue, s);
+    if (e != hipSuccess) return e;
+  }
+#define APC_LAUNCH_MOMENTS_K(M1, KP)                                                                    \
+  do {                                                                                                  \
+    if (queue)                                                                                          \
+      hipLaunchKernelGGL((k_moments<M1, KP, true>), dim3(resident_blocks(k_moments<M1, KP, true>, WAVE, lds)), \
+                         block, lds, s, m, f, slots, offsets, counts, records, tf_rgba, out, gacc, pcount, \
+                         segs, bin_cap, store, counters, queue);                                        \
+    else                                                                                                \
+      hipLaunchKernelGGL((k_moments<M1, KP, false>), dim3(f.n_tiles), block, lds, s, m, f, slots, offsets, \
+                         counts, records, tf_rgba, out, gacc, pcount, segs, bin_cap, store, counters, queue); \
+  } while (0)
 #define APC_LAUNCH_MOMENTS(M1)                                                                          \
   do {                                                                                                  \
     if (store.pool)                                                                                     \
-      hipLaunchKernelGGL((k_moments<M1, true>), grid, block, lds, s, m, f, slots, offsets, counts, records, \
-                         tf_rgba, out, gacc, pcount, segs, bin_cap, store, counters);                   \
+      APC_LAUNCH_MOMENTS_K(M1, true);                                                                   \
     else                                                                                                \
-      hipLaunchKernelGGL((k_moments<M1, false>), grid, block, lds, s, m, f, slots, offsets, counts,     \
-                         records, tf_rgba, out, gacc, pcount, segs, bin_cap, store, counters);          \
+      APC_LAUNCH_MOMENTS_K(M1, false);                                                                  \
   } while (0)
   if (mm == 4)
     APC_LAUNCH_MOMENTS(5);
@@ -1687,6 +1748,7 @@ hipError_t launch_moments(int mm, const MeshDev& m, const FrameDev& f, const Slo
   else
     APC_LAUNCH_MOMENTS(9);
 #undef APC_LAUNCH_MOMENTS
+#undef APC_LAUNCH_MOMENTS_K
   return hipGetLastError();
 }
 
@@ -1711,18 +1773,30 @@ hipError_t launch_eval(int mm, const FrameDev& f, int tile_lo, int tile_hi, cons
 hipError_t launch_resolve(int mm, const MeshDev& m, const FrameDev& f, const SlotDev* slots, const int* offsets,
                           const int* counts, const int* records, long long bin_cap, const float* tf_rgba,
                           const void* moments, const BoundParams& bp, float* rgba, unsigned long long* counters,
-                          hipStream_t s) {
+                          int* queue, hipStream_t s) {
   const size_t lds = size_t(f.n_tf) * sizeof(float4);
-  const dim3 grid(f.n_tiles), block(2 * WAVE);  // one tile per workgroup: its walker and its evaluator
+  const dim3 block(2 * WAVE);  // a tile per workgroup at a time: its walker and its evaluator
+  if (queue) {
+    const hipError_t e = reset_queue(queue, s);
+    if (e != hipSuccess) return e;
+  }
+#define APC_LAUNCH_RESOLVE(N, R)                                                                               \
+  do {                                                                                                         \
+    if (queue)                                                                                                 \
+      hipLaunchKernelGGL((k_resolve<N, R, true>), dim3(resident_blocks(k_resolve<N, R, true>, 2 * WAVE, lds)), \
+                         block, lds, s, m, f, slots, offsets, counts, records, bin_cap, tf_rgba, moments, bp,  \
+                         rgba, counters, queue);                                                               \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_resolve<N, R, false>), dim3(f.n_tiles), block, lds, s, m, f, slots, offsets,      \
+                         counts, records, bin_cap, tf_rgba, moments, bp, rgba, counters, queue);              \
+  } while (0)
   if (mm == 4)
-    hipLaunchKernelGGL((k_resolve<2, float>), grid, block, lds, s, m, f, slots, offsets, counts, records, bin_cap,
-                       tf_rgba, moments, bp, rgba, counters);
+    APC_LAUNCH_RESOLVE(2, float);
   else if (mm == 6)
-    hipLaunchKernelGGL((k_resolve<3, double>), grid, block, lds, s, m, f, slots, offsets, counts, records, bin_cap,
-                       tf_rgba, moments, bp, rgba, counters);
+    APC_LAUNCH_RESOLVE(3, double);
   else
-    hipLaunchKernelGGL((k_resolve<4, double>), grid, block, lds, s, m, f, slots, offsets, counts, records, bin_cap,
-                       tf_rgba, moments, bp, rgba, counters);
+    APC_LAUNCH_RESOLVE(4, double);
+#undef APC_LAUNCH_RESOLVE
   return hipGetLastError();
 }
 

@@ -310,6 +310,12 @@ def test_sums_pack_and_settings_statuses(P, ctx, scene):
     assert L.apc_get_tile_shape(ctx, C.byref(w), C.byref(h)) == 0 and (w.value, h.value) == (16, 4)
     assert L.apc_set_workspace_limit(ctx, -1) == 1
     assert L.apc_set_workspace_limit(ctx, 1 << 30) == 0
+    mode = C.c_int32(-5)
+    assert L.apc_get_dispatch(ctx, C.byref(mode)) == 0 and mode.value == P.APC_DISPATCH_GRID
+    assert L.apc_set_dispatch(ctx, 2) == 1 and "dispatch mode" in err(P, ctx)
+    assert L.apc_set_dispatch(ctx, P.APC_DISPATCH_QUEUE) == 0  # a host-only context allocates nothing
+    assert L.apc_get_dispatch(ctx, C.byref(mode)) == 0 and mode.value == P.APC_DISPATCH_QUEUE
+    assert L.apc_get_dispatch(ctx, None) == 1
     best = C.c_int32()
     assert L.apc_autotune_tile_shape(ctx, sc["mesh"], C.byref(sc["view"]), C.byref(sc["tf"]), C.byref(sc["mb"]),
                                      ptr(sc["subs"]), 3, mg, rgba, 0, C.byref(best), None, None) == 1

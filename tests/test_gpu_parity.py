@@ -430,6 +430,53 @@ def test_tile_shapes_give_identical_results_and_autotuner(apc, ctx):
         ctx.set_tile_shape(8)
 
 
+def test_work_queue_dispatch_gives_identical_results(apc, ctx):
+    """Persistent workgroups taking tiles from per-XCD counters (APC_DISPATCH_QUEUE) compute each tile with
+    the same code in the same order as one workgroup per tile: per-subdomain and global moments, the kept
+    pieces' and the plain form's images, a partial image and a captured frame are bitwise the grid's, on the
+    uneven batching mesh (ragged image: the last tiles are partly outside) and at m = 4."""
+    sc = synth.scene_batching(size=300)
+    r = apc.Renderer(ctx, sc)
+    try:
+        assert ctx.dispatch() == apc.APC_DISPATCH_GRID
+        grid = {}
+        for mode in (apc.APC_DISPATCH_GRID, apc.APC_DISPATCH_QUEUE):
+            ctx.set_dispatch(mode)
+            out = [r.frame().clone(), r.per_sub.clone(), r.moments.clone(), r.frame(global_sum=True).clone(),
+                   r.moments.clone()]
+            r.frame(global_sum=True, keep=True)
+            out.append(r.frame(global_sum=True, keep=True).clone())
+            part = torch.empty_like(r.rgba)
+            ctx.resolve_pass(r.mesh, r.view, r.tf, r.mboit, r.moments, [5, 40], part, finalize=False)
+            out.append(part)
+            g = apc.FrameGraph(r, global_sum=True)
+            try:
+                g.launch()
+                torch.cuda.synchronize()
+                out.append(r.rgba.clone())
+            finally:
+                g.close()
+            c = ctx.counters(reset=True)
+            assert c["walk_step_limit"] == 0
+            if mode == apc.APC_DISPATCH_GRID:
+                grid = out
+            else:
+                assert ctx.dispatch() == apc.APC_DISPATCH_QUEUE
+                for k, (a, b) in enumerate(zip(grid, out)):
+                    assert torch.equal(a, b), k
+        sc4 = synth.scene_medium(size=200)
+        sc4.m = 4
+        sc4.bias = synth.default_bias(4)
+        r4 = apc.Renderer(ctx, sc4)
+        q4 = r4.frame(global_sum=True).clone()
+        ctx.set_dispatch(apc.APC_DISPATCH_GRID)
+        assert torch.equal(r4.frame(global_sum=True), q4)
+        with pytest.raises(apc.ApcError):
+            ctx.set_dispatch(2)
+    finally:
+        ctx.set_dispatch(apc.APC_DISPATCH_GRID)
+
+
 @pytest.mark.parametrize("global_sum,keep", [(False, False), (True, False), (True, True)])
 def test_frame_graph_replays_match_eager_frames(apc, ctx, global_sum, keep):
     """A frame captured in a HIP graph (separate moment sum or stage one summing the subdomains itself; stage
