@@ -4,8 +4,9 @@ tests and the benchmark's oracle leg).
 Bar: |b_j - b_j_ref| <= tol * max(b0_ref, floor) per pixel and j, and exactly 0
 where b0_ref = 0.  A pixel that misses it passes a backward-error bar instead
 when the tested value lies within the oracle's own spread over cameras moved by
-a few FP32 ulps: the library's rays are FP32, and a grazing ray's moments are
-sensitive to that rounding (a 1e-7 change of the ray moves b0 by ~1e-7 there).
+a few FP32 ulps: the library's vertex positions and the in-plane coordinates of
+its side products are FP32, and a grazing ray's moments are sensitive to that
+rounding (a 1e-7 change of the ray moves b0 by ~1e-7 there).
 """
 from __future__ import annotations
 
