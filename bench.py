@@ -311,9 +311,32 @@ def variants_leg(args, sc, r, ctx, fr, survey, rgba0, mom0):
                            "sum_ms": round(other[-1][2], 3),
                            "global_moments_bitwise_equal": bool(torch.equal(r.moments, mom0)),
                            "rgba_bitwise_equal": bool(torch.equal(r.rgba, rgba0))}
+    dense_bytes = int(r.per_sub.numel() * 4)
+    out["separate_sum"]["per_subdomain_image_bytes"] = dense_bytes
     r._per_sub = None
     torch.cuda.empty_cache()
     log("separate sum %s" % out["separate_sum"])
+    # the same per-subdomain moments as tiles of the (tile, subdomain) pairs with binned faces (camera 0)
+    r.view = fr.views[0]
+    m1 = r.moments.shape[0]
+    n = ctx.moments_pass_tiles(r.mesh, r.view, r.tf, m1 - 1, r.subs)
+    tiles = torch.empty((n, m1, 64), dtype=torch.float32, device=r.moments.device)
+    pair_bin = torch.empty((n,), dtype=torch.int32, device=r.moments.device)
+    glob = torch.empty_like(r.moments)
+    for _ in range(2):
+        f0 = time.perf_counter()
+        ctx.moments_pass_tiles(r.mesh, r.view, r.tf, m1 - 1, r.subs, tiles, pair_bin)
+        ctx.sum_moment_tiles(tiles, pair_bin, n, len(r.subs), m1 - 1, r.view.height, r.view.width, glob)
+        tk = ctx.timings()
+        torch.cuda.synchronize()
+        t_ms = (time.perf_counter() - f0) * 1e3
+    out["moment_tiles"] = {"pairs": int(n), "tile_bytes": int(tiles.numel() * 4 + pair_bin.numel() * 4),
+                           "dense_bytes": dense_bytes, "moments_and_sum_ms": round(t_ms, 2),
+                           "moments_ms": round(tk["moments_ms"], 3), "sum_ms": round(tk["sum_ms"], 3),
+                           "global_moments_bitwise_equal": bool(torch.equal(glob, mom0))}
+    del tiles, pair_bin, glob
+    torch.cuda.empty_cache()
+    log("moment tiles %s" % out["moment_tiles"])
     # FP16 moment images (camera 0); their error against the oracle is added by the oracle leg
     fr.frame(0, moments_f16=True)
     torch.cuda.synchronize()

@@ -287,6 +287,38 @@ apc_status apc_resolve_pass_noalloc(apc_ctx ctx, apc_mesh mesh, const apc_view* 
                                     const int32_t* subdomains, int32_t n_sub, float* rgba_out, uint32_t flags,
                                     void* stream);
 
+/* Stage one in the tiles form: the per-subdomain moments as the message a
+ * rank would send (Section 4.3: only non-empty tiles are exchanged) -- one
+ * tile of 64 pixels x (m+1) moments per (tile, subdomain) pair that has
+ * boundary faces of the subdomain binned to it, instead of dense
+ * [n_sub][m+1][H][W] images that are mostly zero (92 % at 2560^2 over 72
+ * subdomains).  Same pieces and per-pixel sums as apc_moments_pass: a pair's
+ * tile holds exactly the dense image's values of its 64 pixels (0 on pixels
+ * with no piece or outside the image), and every pixel of a tile without a
+ * pair is 0 there.
+ *   subdomains  host [n_sub], ascending ids (else APC_E_ARG)
+ *   tiles       device [max_pairs][m+1][64] FP32: pair p's moment j of
+ *               lane l (the tile's pixel (l mod w, l / w) for the context's
+ *               tile shape w x 64/w) at tiles[(p*(m+1) + j)*64 + l]
+ *   pair_bin    device [max_pairs] int32: pair p's bin, tile*n_sub + slot
+ *               (slot = index into `subdomains`), ascending
+ *   max_pairs   capacity of tiles and pair_bin; with tiles == NULL and
+ *               max_pairs == 0 the call only counts the pairs (a query)
+ *   n_pairs     host out: the frame's pair count (also on APC_E_NOMEM)
+ * More pairs than max_pairs: APC_E_NOMEM, nothing written.  Reads the pair
+ * count back (one stream synchronisation) before it walks. */
+apc_status apc_moments_pass_tiles(apc_ctx ctx, apc_mesh mesh, const apc_view* view, const apc_tf* tf, int32_t m,
+                                  const int32_t* subdomains, int32_t n_sub, float* tiles, int32_t* pair_bin,
+                                  int64_t max_pairs, int64_t* n_pairs, void* stream);
+
+/* The global [m+1][H][W] moments from the tiles form: per pixel the pairs of
+ * its tile summed in FP64 in slot (ascending id) order -- bitwise what
+ * apc_sum_moments gives for the dense images of the same stage one.
+ * tile_width is the tile shape the tiles were made with. */
+apc_status apc_sum_moment_tiles(apc_ctx ctx, const float* tiles, const int32_t* pair_bin, int64_t n_pairs,
+                                int32_t n_sub, int32_t m, int32_t height, int32_t width, int32_t tile_width,
+                                float* moments_global, void* stream);
+
 /* Final image = sum of partial images (Section 4.2; the paper's
  * MPI_Reduce), in ascending subdomain-id order, then finalised like
  * apc_resolve_pass with APC_FINALIZE.

@@ -34,7 +34,7 @@ EXPORTS = ["apc_create", "apc_destroy", "apc_last_error", "apc_version", "apc_lo
            "apc_get_timings", "apc_set_tile_shape", "apc_get_tile_shape", "apc_autotune_tile_shape",
            "apc_frame_graph_create", "apc_frame_graph_launch", "apc_frame_graph_counters", "apc_frame_graph_destroy",
            "apc_set_workspace_limit", "apc_resolve_pass_noalloc", "apc_get_workspace_bytes", "apc_set_dispatch",
-           "apc_get_dispatch"]
+           "apc_get_dispatch", "apc_moments_pass_tiles", "apc_sum_moment_tiles"]
 
 
 class ApcError(RuntimeError):
@@ -114,6 +114,12 @@ def lib():
                                        C.c_uint32, vp]
         L.apc_sum_moments.restype = st
         L.apc_sum_moments.argtypes = [vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp, vp, vp]
+        L.apc_moments_pass_tiles.restype = st
+        L.apc_moments_pass_tiles.argtypes = [vp, vp, C.POINTER(View), C.POINTER(TF), C.c_int32, vp, C.c_int32, vp,
+                                             vp, C.c_int64, C.POINTER(C.c_int64), vp]
+        L.apc_sum_moment_tiles.restype = st
+        L.apc_sum_moment_tiles.argtypes = [vp, vp, vp, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                           C.c_int32, vp, vp]
         L.apc_resolve_pass.restype = st
         L.apc_resolve_pass.argtypes = [vp, vp, C.POINTER(View), C.POINTER(TF), C.POINTER(Mboit), vp, vp,
                                        C.c_int32, vp, C.c_uint32, vp]
@@ -296,6 +302,35 @@ class Context:
                                         len(ids), _dev_ptr(out, torch.float32, shape,
                                                            "moments" if global_sum else "moments_per_sub"),
                                         flags, _stream(stream)))
+
+    def moments_pass_tiles(self, mesh, view: View, tf: TF, m, subdomains, tiles=None, pair_bin=None, stream=None):
+        """Stage one in the tiles form (ascending subdomain ids): tiles [P][m+1][64] FP32 and pair_bin [P] int32
+        for the P (tile, subdomain) pairs with binned faces.  Without buffers only counts the pairs.  Returns
+        the pair count (raises ApcError, status APC_E_NOMEM, when the buffers are too small)."""
+        import torch
+        ids, ptr = _ids(subdomains)
+        n = C.c_int64(0)
+        if tiles is None:
+            tp, bp, cap = None, None, 0
+        else:
+            cap = int(tiles.shape[0])
+            tp = _dev_ptr(tiles, torch.float32, (cap, m + 1, 64), "tiles")
+            bp = _dev_ptr(pair_bin, torch.int32, (cap,), "pair_bin")
+        self._ck(lib().apc_moments_pass_tiles(self.handle, mesh.handle, C.byref(view), C.byref(tf), int(m), ptr,
+                                              len(ids), tp, bp, cap, C.byref(n), _stream(stream)))
+        return n.value
+
+    def sum_moment_tiles(self, tiles, pair_bin, n_pairs, n_sub, m, height, width, out, stream=None):
+        """Global [m+1][H][W] moments from the first n_pairs tiles (tile shape of this context)."""
+        import torch
+        tp = _dev_ptr(tiles, torch.float32, name="tiles") if n_pairs > 0 else None
+        bp = _dev_ptr(pair_bin, torch.int32, name="pair_bin") if n_pairs > 0 else None
+        if n_pairs > 0 and (tiles.numel() < n_pairs * (m + 1) * 64 or pair_bin.numel() < n_pairs):
+            raise ValueError("tiles / pair_bin hold fewer than n_pairs pairs")
+        self._ck(lib().apc_sum_moment_tiles(self.handle, tp, bp, int(n_pairs), int(n_sub), int(m), int(height),
+                                            int(width), self.tile_shape()[0],
+                                            _dev_ptr(out, torch.float32, (m + 1, height, width), "moments"),
+                                            _stream(stream)))
 
     def sum_moments(self, per_sub, m, subdomains, out, stream=None):
         import torch

@@ -157,6 +157,7 @@ struct apc_ctx_s {
   int64_t ws_limit = 0;              // bytes for the piece pool (0: up to 60 % of free memory)
   int dispatch = APC_DISPATCH_GRID;  // how both passes spread their tiles (apc_set_dispatch)
   DevBuf queue;                      // the work queue's per-XCD tile counters (APC_DISPATCH_QUEUE)
+  DevBuf pidx;                       // tiles form: the pair number of each (tile, slot) bin
 };
 
 struct apc_graph_s {
@@ -603,8 +604,8 @@ apc_status apc_destroy(apc_ctx ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   for (DevBuf* b : {&ctx->counts, &ctx->offsets, &ctx->cursors, &ctx->records, &ctx->scan_tmp, &ctx->slots,
-                    &ctx->order, &ctx->counters, &ctx->pcount, &ctx->segs, &ctx->gacc, &ctx->queue, &ctx->pool,
-                    &ctx->ptab, &ctx->store_next})
+                    &ctx->order, &ctx->counters, &ctx->pcount, &ctx->segs, &ctx->gacc, &ctx->queue, &ctx->pidx,
+                    &ctx->pool, &ctx->ptab, &ctx->store_next})
     b->release();
   if (ctx->staging) (void)hipHostFree(ctx->staging);
   if (ctx->staging_done) (void)hipEventDestroy(ctx->staging_done);
@@ -946,11 +947,87 @@ apc_status apc_moments_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const
   HIPCHK(apc::launch_moments(mm, md, f, ctx->slots.as<SlotDev>(), ctx->offsets.as<int>(), ctx->counts.as<int>(),
                              ctx->records.as<int>(), bin_cap(ctx), tf->rgba, out,
                              global ? ctx->gacc.as<double>() : nullptr, ctx->pcount.as<int>(), ctx->segs.as<int>(), ps,
-                             ctx->counters.as<unsigned long long>(), tile_queue(ctx), s));
+                             ctx->counters.as<unsigned long long>(), tile_queue(ctx), nullptr, s));
   HIPCHK(ev_mark(ctx, EV_MOM, 1, s));
   set_piece_key(ctx, m, view, subs, n_sub);
   ctx->store_ready = ps.pool != nullptr;
   ctx->store_tf = *tf;
+  return APC_OK;
+}
+
+apc_status apc_moments_pass_tiles(apc_ctx ctx, apc_mesh m, const apc_view* view, const apc_tf* tf, int32_t mm,
+                                  const int32_t* subs, int32_t n_sub, float* tiles, int32_t* pair_bin,
+                                  int64_t max_pairs, int64_t* n_pairs, void* stream) {
+  apc_status st = check_ctx(ctx);
+  if (st != APC_OK) return st;
+  if ((st = check_mesh(ctx, m)) != APC_OK) return st;
+  if ((st = check_view_tf(view, tf)) != APC_OK) return st;
+  if (mm != 4 && mm != 6 && mm != 8) return fail(APC_E_ARG, "m = %d unsupported (4, 6 or 8)", mm);
+  if ((st = check_subdomains(m, subs, n_sub)) != APC_OK) return st;
+  for (int k = 1; k < n_sub; ++k)
+    if (!(subs[k - 1] < subs[k])) return fail(APC_E_ARG, "the tiles form needs ascending subdomain ids");
+  if (!n_pairs) return fail(APC_E_ARG, "n_pairs is NULL");
+  if (max_pairs < 0) return fail(APC_E_ARG, "max_pairs = %lld", (long long)max_pairs);
+  if (max_pairs > 0 && (!tiles || !pair_bin)) return fail(APC_E_ARG, "tiles or pair_bin is NULL");
+  FrameDev f;
+  if ((st = make_frame(m, view, tf, n_sub, max_tets_of(m, subs, n_sub), ctx->tw_log2, f)) != APC_OK) return st;
+  if (ctx->host_only) return no_device("apc_moments_pass_tiles");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  MeshDev md;
+  if ((st = build_bins(ctx, m, f, subs, n_sub, s, md)) != APC_OK) return st;
+  // number the (tile, slot) bins that have faces: those are the pairs (the binning's cursors are free now)
+  const int64_t nb = int64_t(f.n_tiles) * n_sub;
+  HIPCHK(ctx->pidx.ensure(sizeof(int) * nb));
+  HIPCHK(apc::launch_pair_scan(ctx->counts.as<int>(), nb, ctx->cursors.as<int>(), ctx->pidx.as<int>(),
+                               ctx->scan_tmp.as<int>(), s));
+  int tail[2];
+  HIPCHK(hipMemcpyAsync(&tail[0], ctx->pidx.as<int>() + nb - 1, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&tail[1], ctx->cursors.as<int>() + nb - 1, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const int64_t pairs = int64_t(tail[0]) + tail[1];
+  *n_pairs = pairs;
+  if (max_pairs == 0 && !tiles) return APC_OK;  // a query: the caller sizes its buffers from *n_pairs
+  if (pairs > max_pairs)
+    return fail(APC_E_NOMEM, "the frame has %lld (tile, subdomain) pairs; the buffers hold %lld (nothing written)",
+                (long long)pairs, (long long)max_pairs);
+  HIPCHK(ctx->pcount.ensure(sizeof(int) * size_t(f.n_tiles) * 64));
+  HIPCHK(ctx->segs.ensure(sizeof(int) * 2 * size_t(view->width) * view->height));
+  ctx->seg_h = view->height;
+  ctx->seg_w = view->width;
+  ctx->store_ready = false;
+  HIPCHK(apc::launch_pair_list(ctx->counts.as<int>(), nb, ctx->pidx.as<int>(), pair_bin, s));
+  HIPCHK(ev_mark(ctx, EV_MOM, 0, s));
+  HIPCHK(apc::launch_moments(mm, md, f, ctx->slots.as<SlotDev>(), ctx->offsets.as<int>(), ctx->counts.as<int>(),
+                             ctx->records.as<int>(), bin_cap(ctx), tf->rgba, tiles, nullptr, ctx->pcount.as<int>(),
+                             ctx->segs.as<int>(), apc::PieceStore{}, ctx->counters.as<unsigned long long>(),
+                             tile_queue(ctx), ctx->pidx.as<int>(), s));
+  HIPCHK(ev_mark(ctx, EV_MOM, 1, s));
+  set_piece_key(ctx, m, view, subs, n_sub);
+  return APC_OK;
+}
+
+apc_status apc_sum_moment_tiles(apc_ctx ctx, const float* tiles, const int32_t* pair_bin, int64_t n_pairs,
+                                int32_t n_sub, int32_t mm, int32_t H, int32_t W, int32_t tile_width, float* outg,
+                                void* stream) {
+  apc_status st = check_ctx(ctx);
+  if (st != APC_OK) return st;
+  if (!outg) return fail(APC_E_ARG, "moments_global is NULL");
+  if (n_pairs > 0 && (!tiles || !pair_bin)) return fail(APC_E_ARG, "tiles or pair_bin is NULL");
+  if (mm != 4 && mm != 6 && mm != 8) return fail(APC_E_ARG, "m = %d unsupported", mm);
+  if (n_sub < 1 || H <= 0 || W <= 0 || n_pairs < 0) return fail(APC_E_ARG, "sizes out of range");
+  int lg = -1;
+  for (int k = 0; k <= 6; ++k)
+    if (tile_width == (1 << k)) lg = k;
+  if (lg < 0) return fail(APC_E_ARG, "tile width %d is not a power of two in 1..64", tile_width);
+  const int64_t tiles_x = (int64_t(W) + (1 << lg) - 1) >> lg, tiles_y = (int64_t(H) + (64 >> lg) - 1) / (64 >> lg);
+  if (n_pairs > tiles_x * tiles_y * n_sub)
+    return fail(APC_E_ARG, "%lld pairs exceed the %lld (tile, subdomain) bins of a %d x %d image",
+                (long long)n_pairs, (long long)(tiles_x * tiles_y * n_sub), W, H);
+  if (ctx->host_only) return no_device("apc_sum_moment_tiles");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIPCHK(ev_mark(ctx, EV_SUM, 0, s));
+  HIPCHK(apc::launch_sum_tiles(tiles, pair_bin, n_pairs, n_sub, mm + 1, W, H, lg, outg, s));
+  HIPCHK(ev_mark(ctx, EV_SUM, 1, s));
   return APC_OK;
 }
 
@@ -1260,8 +1337,8 @@ apc_status apc_get_workspace_bytes(apc_ctx ctx, int64_t* bytes) {
   if (!bytes) return fail(APC_E_ARG, "bytes is NULL");
   int64_t total = 0;
   for (const DevBuf* b : {&ctx->counts, &ctx->offsets, &ctx->cursors, &ctx->records, &ctx->scan_tmp, &ctx->slots,
-                          &ctx->order, &ctx->counters, &ctx->pcount, &ctx->segs, &ctx->gacc, &ctx->queue, &ctx->pool,
-                          &ctx->ptab, &ctx->store_next})
+                          &ctx->order, &ctx->counters, &ctx->pcount, &ctx->segs, &ctx->gacc, &ctx->queue, &ctx->pidx,
+                          &ctx->pool, &ctx->ptab, &ctx->store_next})
     total += int64_t(b->bytes);
   *bytes = total;
   return APC_OK;

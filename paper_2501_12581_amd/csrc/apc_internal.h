@@ -99,7 +99,9 @@ hipError_t launch_bin_fill(const MeshDev& m, const FrameDev& f, const SlotDev* s
 hipError_t launch_moments(int mm, const MeshDev& m, const FrameDev& f, const SlotDev* slots, const int* offsets,
                           const int* counts, const int* records, long long bin_cap, const float* tf_rgba, float* out,
                           double* gacc, int* pcount, int* segs, const PieceStore& store,
-                          unsigned long long* counters, int* queue, hipStream_t s);
+                          unsigned long long* counters, int* queue, const int* pair_idx, hipStream_t s);
+// pair_idx (tiles form, gacc null): per bin with faces its pair number; out is then [pairs][m+1][64]
+// (lane-minor), every lane of every pair written
 // queue (both passes): null for one workgroup per tile; else QUEUE_INTS device ints that the launch
 // resets and a persistent launch (as many workgroups as the device holds) takes the tiles from
 constexpr int QUEUE_INTS = 8;
@@ -124,6 +126,13 @@ hipError_t launch_walk_records(const int4* tet, const float4* vert, int64_t n_te
 // exclusive scan of n int32 values; tmp must hold scan_tmp_elems(n) ints
 int64_t scan_tmp_elems(int64_t n);
 hipError_t launch_exclusive_scan(const int* in, int* out, int64_t n, int* tmp, hipStream_t s);
+// tiles form: pidx[b] = pair number of bin b when counts[b] > 0 (bins with faces, numbered in bin order; the
+// pair count is pidx[nb-1] + flags[nb-1]); flags: nb ints; tmp as for the scan.  Then pair_bin[p] = its bin.
+hipError_t launch_pair_scan(const int* counts, int64_t nb, int* flags, int* pidx, int* tmp, hipStream_t s);
+hipError_t launch_pair_list(const int* counts, int64_t nb, const int* pidx, int* pair_bin, hipStream_t s);
+// global [m1][H][W] moments from n_pairs tiles (pair_bin ascending, n_slots slots per tile, ascending ids)
+hipError_t launch_sum_tiles(const float* tiles, const int* pair_bin, int64_t n_pairs, int n_slots, int m1, int W,
+                            int H, int tw_log2, float* out, hipStream_t s);
 hipError_t launch_fill_i32(int* p, int value, int64_t n, hipStream_t s);
 
 // ---- mesh residency kernels

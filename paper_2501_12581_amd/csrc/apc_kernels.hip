@@ -8,12 +8,17 @@
 //                subdomain, walk the ray tet by tet from each entry to where
 //                it leaves the subdomain, cut every chord at the global
 //                sampling lattice and add a*z^j per piece (paper Alg. 2)
-//   k_sum_moments  canonical-order FP64 sum of the per-subdomain images
-//                (the paper's moment Allreduce, Section 4.1)
-//   k_stage      the same walk again, staging every piece (z, a, s) in HBM
-//   k_eval       per pixel the global moments give the moment bound (Alg. 3);
-//                64 staged pieces at a time get T = exp(-b0 F), which weights
-//                the piece's colour (Alg. 1 second loop, Section 4.2)
+//                (with every subdomain on one GPU it also sums them: the
+//                global image; else per-subdomain images, dense or as tiles
+//                of the (tile, subdomain) pairs that have boundary faces)
+//   k_sum_moments / k_sum_tiles  canonical-order FP64 sum of per-subdomain
+//                images or tiles (the paper's moment Allreduce, Section 4.1)
+//   k_resolve    stage two, plain form: per tile a walker wavefront walks the
+//                rays again and hands each piece (z, a, s) through LDS to an
+//                evaluator wavefront, which forms the moment bound of its
+//                pixel (Alg. 3) and weights the piece's colour by
+//                T = exp(-b0 F) (Alg. 1 second loop, Section 4.2)
+//   k_eval       the same evaluation over pieces stage one kept (variant)
 //   k_sum_images canonical-order sum of partial images + renormalisation
 //
 // Geometry.  A ray crosses a face iff its Plücker side products with the
@@ -700,7 +705,8 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_WALK_W
                                                   const int* __restrict__ records, const float* __restrict__ tf_rgba,
                                                   float* __restrict__ out, double* __restrict__ gacc,
                                                   int* __restrict__ pcount, int* __restrict__ segs, long long bin_cap,
-                                                  PieceStore ps, unsigned long long* ctr, int* queue) {
+                                                  PieceStore ps, unsigned long long* ctr, int* queue,
+                                                  const int* __restrict__ pair_idx) {
   extern __shared__ float4 dyn_lds[];
   float* tfa = reinterpret_cast<float*>(dyn_lds);  // [n_tf] alpha column
   __shared__ FaceL faces[CHUNK];
@@ -765,6 +771,13 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_WALK_W
           else
             g[size_t(j) * HW] = covering > 0 ? g[size_t(j) * HW] + v : v;
         }
+      }
+    } else if (pair_idx) {  // tiles form: only pairs with binned faces, every lane (zeros outside the image)
+      if (n_rec > 0) {
+        const int p = pair_idx[bin];
+        float* o = out + size_t(p) * M1 * WAVE + lane;
+#pragma unroll
+        for (int j = 0; j < M1; ++j) o[j * WAVE] = float(sink.b[j]);
       }
     } else if (valid) {
       float* o = out + size_t(k) * M1 * HW + pix;
@@ -1529,6 +1542,50 @@ __global__ void k_sum_moments(const float* __restrict__ in, int n_slots, const i
 // and the rest lo); the central moments E[(z - mu)^k] (mu = hi + lo), k = 2..m.  Central moments keep the
 // spread of a concentrated depth distribution at FP16's relative precision, which raw moments (all near mu^j)
 // lose; the split ln b0 keeps the opacity 1 - exp(-b0) near FP32 precision.
+// The tiles form's pairs: bin b = tile * n_slots + slot with binned faces is pair pidx[b] (exclusive scan of
+// the flags, so in bin order); pair_bin lists the bins of the pairs in that order.
+__global__ void k_pair_flags(const int* __restrict__ counts, int64_t nb, int* __restrict__ flags) {
+  const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (b < nb) flags[b] = counts[b] > 0 ? 1 : 0;
+}
+__global__ void k_pair_list(const int* __restrict__ counts, int64_t nb, const int* __restrict__ pidx,
+                            int* __restrict__ pair_bin) {
+  const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (b < nb && counts[b] > 0) pair_bin[pidx[b]] = int(b);
+}
+
+// Global moments from the tiles form: pixel (tile t, lane l) adds, for the pairs of tile t in slot order
+// (ascending subdomain ids), tile p's value at lane l in FP64 -- the additions of k_sum_moments without the
+// pairs' zeros (adding an exact 0 changes nothing), so the result is bitwise the dense form's.  A tile's
+// pairs are contiguous in pair_bin (ascending): found by binary search.
+__global__ void k_sum_tiles(const float* __restrict__ tiles, const int* __restrict__ pair_bin, int64_t n_pairs,
+                            int n_slots, int m1, int W, int H, int tw_log2, float* __restrict__ out) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t HW = int64_t(W) * H;
+  if (i >= HW) return;
+  const int y = int(i / W), x = int(i - int64_t(y) * W);
+  const int tw = 1 << tw_log2, th = WAVE >> tw_log2;
+  const int tiles_x = (W + tw - 1) / tw;
+  const int tile = (y / th) * tiles_x + (x >> tw_log2);
+  const int lane = (y % th) * tw + (x & (tw - 1));
+  const int64_t first_bin = int64_t(tile) * n_slots;
+  int64_t lo = 0, hi = n_pairs;  // first pair with pair_bin >= first_bin
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (pair_bin[mid] < first_bin)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  double acc[9];
+  for (int j = 0; j < m1; ++j) acc[j] = 0.0;
+  for (int64_t p = lo; p < n_pairs && pair_bin[p] < first_bin + n_slots; ++p) {
+    const float* t = tiles + p * m1 * WAVE + lane;
+    for (int j = 0; j < m1; ++j) acc[j] += double(t[j * WAVE]);
+  }
+  for (int j = 0; j < m1; ++j) out[int64_t(j) * HW + i] = float(acc[j]);
+}
+
 __global__ void k_pack_f16(const float* __restrict__ in, int m1, int64_t pixels, _Float16* __restrict__ out) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= pixels) return;
@@ -1717,7 +1774,7 @@ static hipError_t reset_queue(int* queue, hipStream_t s) {
 hipError_t launch_moments(int mm, const MeshDev& m, const FrameDev& f, const SlotDev* slots, const int* offsets,
                           const int* counts, const int* records, long long bin_cap, const float* tf_rgba, float* out,
                           double* gacc, int* pcount, int* segs, const PieceStore& store,
-                          unsigned long long* counters, int* queue, hipStream_t s) {
+                          unsigned long long* counters, int* queue, const int* pair_idx, hipStream_t s) {
   const size_t lds = size_t(f.n_tf) * sizeof(float);
   const dim3 block(WAVE);
   if (queue) {
@@ -1729,10 +1786,11 @@ hipError_t launch_moments(int mm, const MeshDev& m, const FrameDev& f, const Slo
     if (queue)                                                                                          \
       hipLaunchKernelGGL((k_moments<M1, KP, true>), dim3(resident_blocks(k_moments<M1, KP, true>, WAVE, lds)), \
                          block, lds, s, m, f, slots, offsets, counts, records, tf_rgba, out, gacc, pcount, \
-                         segs, bin_cap, store, counters, queue);                                        \
+                         segs, bin_cap, store, counters, queue, pair_idx);                              \
     else                                                                                                \
       hipLaunchKernelGGL((k_moments<M1, KP, false>), dim3(f.n_tiles), block, lds, s, m, f, slots, offsets, \
-                         counts, records, tf_rgba, out, gacc, pcount, segs, bin_cap, store, counters, queue); \
+                         counts, records, tf_rgba, out, gacc, pcount, segs, bin_cap, store, counters, queue,  \
+                         pair_idx);                                                                     \
   } while (0)
 #define APC_LAUNCH_MOMENTS(M1)                                                                          \
   do {                                                                                                  \
@@ -1817,6 +1875,29 @@ hipError_t launch_sum_moments(const float* in, int n_slots, const int* order, in
                               hipStream_t s) {
   hipLaunchKernelGGL(k_sum_moments, dim3(grid1((elems + 3) / 4, 256)), dim3(256), 0, s, in, n_slots, order, elems,
                      out);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_scan(const int* counts, int64_t nb, int* flags, int* pidx, int* tmp, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pair_flags, dim3(grid1(nb, 256)), dim3(256), 0, s, counts, nb, flags);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_exclusive_scan(flags, pidx, nb, tmp, s);
+}
+
+hipError_t launch_pair_list(const int* counts, int64_t nb, const int* pidx, int* pair_bin, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pair_list, dim3(grid1(nb, 256)), dim3(256), 0, s, counts, nb, pidx, pair_bin);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_tiles(const float* tiles, const int* pair_bin, int64_t n_pairs, int n_slots, int m1, int W,
+                            int H, int tw_log2, float* out, hipStream_t s) {
+  const int64_t HW = int64_t(W) * H;
+  if (HW <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sum_tiles, dim3(grid1(HW, 256)), dim3(256), 0, s, tiles, pair_bin, n_pairs, n_slots, m1, W, H,
+                     tw_log2, out);
   return hipGetLastError();
 }
 

@@ -316,6 +316,23 @@ def test_sums_pack_and_settings_statuses(P, ctx, scene):
     assert L.apc_set_dispatch(ctx, P.APC_DISPATCH_QUEUE) == 0  # a host-only context allocates nothing
     assert L.apc_get_dispatch(ctx, C.byref(mode)) == 0 and mode.value == P.APC_DISPATCH_QUEUE
     assert L.apc_get_dispatch(ctx, None) == 1
+    n = C.c_int64(-1)
+    args = (ctx, sc["mesh"], C.byref(sc["view"]), C.byref(sc["tf"]), 8)
+    assert L.apc_moments_pass_tiles(*args, ptr(np.array([2, 0, 1], np.int32)), 3, None, None, 0, C.byref(n),
+                                    None) == 1 and "ascending" in err(P, ctx)
+    assert L.apc_moments_pass_tiles(*args, ptr(sc["subs"]), 3, None, None, 0, None, None) == 1
+    assert L.apc_moments_pass_tiles(*args, ptr(sc["subs"]), 3, None, None, -1, C.byref(n), None) == 1
+    assert L.apc_moments_pass_tiles(*args, ptr(sc["subs"]), 3, None, None, 5, C.byref(n), None) == 1
+    assert L.apc_moments_pass_tiles(ctx, sc["mesh"], C.byref(sc["view"]), C.byref(sc["tf"]), 5, ptr(sc["subs"]), 3,
+                                    None, None, 0, C.byref(n), None) == 1
+    assert L.apc_moments_pass_tiles(*args, ptr(sc["subs"]), 3, None, None, 0, C.byref(n), None) == 4
+    assert n.value == -1  # nothing written by a call that failed
+    tl, pb = ptr(sc["out"]["mom"]), ptr(np.zeros(4, np.int32))
+    assert L.apc_sum_moment_tiles(ctx, tl, pb, 4, 3, 8, 24, 32, 3, mg, None) == 1 and "power of two" in err(P, ctx)
+    assert L.apc_sum_moment_tiles(ctx, tl, pb, 10 ** 6, 3, 8, 24, 32, 8, mg, None) == 1  # more pairs than bins
+    assert L.apc_sum_moment_tiles(ctx, None, None, 4, 3, 8, 24, 32, 8, mg, None) == 1
+    assert L.apc_sum_moment_tiles(ctx, tl, pb, 4, 3, 8, 24, 32, 8, None, None) == 1
+    assert L.apc_sum_moment_tiles(ctx, tl, pb, 4, 3, 8, 24, 32, 8, mg, None) == 4
     best = C.c_int32()
     assert L.apc_autotune_tile_shape(ctx, sc["mesh"], C.byref(sc["view"]), C.byref(sc["tf"]), C.byref(sc["mb"]),
                                      ptr(sc["subs"]), 3, mg, rgba, 0, C.byref(best), None, None) == 1

@@ -430,6 +430,58 @@ def test_tile_shapes_give_identical_results_and_autotuner(apc, ctx):
         ctx.set_tile_shape(8)
 
 
+@pytest.mark.parametrize("size,m,tw", [(300, 8, 8), (200, 4, 16)])
+def test_moment_tiles_hold_the_dense_images(apc, ctx, size, m, tw):
+    """The tiles form of stage one (one 64-pixel tile per (tile, subdomain) pair with binned faces): every
+    pair's tile is the dense per-subdomain image's values on its pixels (0 outside the image), every pixel of
+    a tile without a pair is 0 in the dense image, pair_bin ascends, and the sum of the tiles is bitwise the
+    dense sum.  A query counts the pairs; buffers one pair short get APC_E_NOMEM and stay untouched.  Ragged
+    image, two tile shapes, m = 8 and 4."""
+    sc = synth.scene_medium(size=size)
+    sc.m = m
+    sc.bias = synth.default_bias(m)
+    try:
+        ctx.set_tile_shape(tw)
+        r = apc.Renderer(ctx, sc)
+        r.frame()  # dense per-subdomain images + apc_sum_moments
+        dense, glob = _np(r.per_sub), r.moments.clone()
+        S, H, W = len(r.subs), size, size
+        n = ctx.moments_pass_tiles(r.mesh, r.view, r.tf, m, r.subs)
+        assert n > 0
+        small = torch.full((n - 1, m + 1, 64), -7.0, dtype=torch.float32, device="cuda")
+        small_b = torch.full((n - 1,), -7, dtype=torch.int32, device="cuda")
+        with pytest.raises(apc.ApcError) as e:
+            ctx.moments_pass_tiles(r.mesh, r.view, r.tf, m, r.subs, small, small_b)
+        assert e.value.status == 3
+        torch.cuda.synchronize()
+        assert bool((small == -7.0).all()) and bool((small_b == -7).all())
+        tiles = torch.full((n, m + 1, 64), -7.0, dtype=torch.float32, device="cuda")
+        pb = torch.full((n,), -7, dtype=torch.int32, device="cuda")
+        assert ctx.moments_pass_tiles(r.mesh, r.view, r.tf, m, r.subs, tiles, pb) == n
+        g = torch.empty_like(glob)
+        ctx.sum_moment_tiles(tiles, pb, n, S, m, H, W, g)
+        torch.cuda.synchronize()
+        assert torch.equal(g, glob)
+        # rebuild the dense images from the tiles on the host
+        t_np, b_np = _np(tiles), pb.cpu().numpy().astype(np.int64)
+        assert np.all(np.diff(b_np) > 0) and b_np[0] >= 0
+        th, tiles_x = 64 // tw, (W + tw - 1) // tw
+        tile, slot = b_np // S, b_np % S
+        lane = np.arange(64)
+        y = (tile // tiles_x)[:, None] * th + lane[None, :] // tw
+        x = (tile % tiles_x)[:, None] * tw + lane[None, :] % tw
+        inside = (y < H) & (x < W)
+        assert np.all(t_np.transpose(0, 2, 1)[~inside] == 0)
+        rebuilt = np.zeros_like(dense)
+        pp, ll = np.nonzero(inside)
+        rebuilt[slot[pp], :, y[pp, ll], x[pp, ll]] = t_np[pp, :, ll]
+        assert np.array_equal(rebuilt, dense)
+        print("size %d m %d tile %dx%d: %d pairs of %d bins, %.1f%% of the dense bytes" % (
+            size, m, tw, th, n, S * tiles_x * ((H + th - 1) // th), 100.0 * n * 64 / (S * H * W)))
+    finally:
+        ctx.set_tile_shape(8)
+
+
 def test_work_queue_dispatch_gives_identical_results(apc, ctx):
     """Persistent workgroups taking tiles from per-XCD counters (APC_DISPATCH_QUEUE) compute each tile with
     the same code in the same order as one workgroup per tile: per-subdomain and global moments, the kept
