@@ -1537,11 +1537,6 @@ __global__ void k_sum_moments(const float* __restrict__ in, int n_slots, const i
   }
 }
 
-// FP16 form of a global moment image: ln b0 (-inf on background) and b_j / b0
-// FP16 moment image, planes [m+3][pixels]: ln b0 and the mean depth mu = beta_1, each as two FP16 halves (hi,
-// and the rest lo); the central moments E[(z - mu)^k] (mu = hi + lo), k = 2..m.  Central moments keep the
-// spread of a concentrated depth distribution at FP16's relative precision, which raw moments (all near mu^j)
-// lose; the split ln b0 keeps the opacity 1 - exp(-b0) near FP32 precision.
 // The tiles form's pairs: bin b = tile * n_slots + slot with binned faces is pair pidx[b] (exclusive scan of
 // the flags, so in bin order); pair_bin lists the bins of the pairs in that order.
 __global__ void k_pair_flags(const int* __restrict__ counts, int64_t nb, int* __restrict__ flags) {
@@ -1586,6 +1581,10 @@ __global__ void k_sum_tiles(const float* __restrict__ tiles, const int* __restri
   for (int j = 0; j < m1; ++j) out[int64_t(j) * HW + i] = float(acc[j]);
 }
 
+// FP16 moment image, planes [m+3][pixels]: ln b0 (-inf on background) and the mean depth mu = beta_1, each as
+// two FP16 halves (hi, and the rest lo); the central moments E[(z - mu)^k] (mu = hi + lo), k = 2..m.  Central
+// moments keep the spread of a concentrated depth distribution at FP16's relative precision, which raw moments
+// (all near mu^j) lose; the split ln b0 keeps the opacity 1 - exp(-b0) near FP32 precision.
 __global__ void k_pack_f16(const float* __restrict__ in, int m1, int64_t pixels, _Float16* __restrict__ out) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= pixels) return;
