@@ -289,13 +289,22 @@ __device__ __forceinline__ void tf_coord(const FrameDev& f, float s, int& i0, fl
   fr = u - float(i0);
 }
 
-// Optical depth of a piece and its warped depth (Alg. 2: absorbance capped,
-// log depth rescaled to [-1, 1]).
-__device__ __forceinline__ void piece_az(const FrameDev& f, double tm, float len, float A, float& a, float& z) {
+// Optical depth of a piece (Alg. 2: absorbance capped) from the transfer
+// function's alpha at its scalar and its length, and its warped depth (log
+// depth rescaled to [-1, 1]) from its mid depth measured from the eye (wt =
+// tm + t_mid, rounded to FP32).
+__device__ __forceinline__ float piece_a(const FrameDev& f, float A, float len) {
 #pragma clang fp contract(off)
-  a = fminf(f.kappa * A * len, f.amax);
-  z = (__log2f(float(tm + f.t_mid)) - f.lg_near) * f.warp_scale - 1.0f;
-  z = fminf(fmaxf(z, -1.0f), 1.0f);
+  return fminf(f.kappa * A * len, f.amax);
+}
+__device__ __forceinline__ float piece_z(const FrameDev& f, float wt) {
+#pragma clang fp contract(off)
+  const float z = (__log2f(wt) - f.lg_near) * f.warp_scale - 1.0f;
+  return fminf(fmaxf(z, -1.0f), 1.0f);
+}
+__device__ __forceinline__ void piece_az(const FrameDev& f, double tm, float len, float A, float& a, float& z) {
+  a = piece_a(f, A, len);
+  z = piece_z(f, float(tm + f.t_mid));
 }
 
 __device__ __forceinline__ float lerp_nc(float a, float b, float fr) {
@@ -1126,17 +1135,19 @@ constexpr int PQ = APC_PAIR_QUEUE;
 static_assert((PQ & (PQ - 1)) == 0, "the ring size is a power of two");
 
 struct PairLDS {
-  float q[3][PQ * WAVE];  // z, a, s of ring slot j of lane l at j * WAVE + l (the 64 lanes hit distinct banks)
+  float q[3][PQ * WAVE];  // wt, len, s of ring slot j of lane l at j * WAVE + l (the 64 lanes hit distinct banks)
   int tail[2][WAVE];      // pieces lane l has produced, published at the boundaries of each parity
   int head[2][WAVE];      // pieces of lane l evaluated
   int done[2];            // the walker has no more pieces
 };
 
 // The walker's side: the chord being cut (bit for bit cut_chord's arithmetic,
-// resumable when the ring is full) and the ring position.
+// resumable when the ring is full) and the ring position.  A piece goes into
+// the ring raw -- depth from the eye, length, scalar -- and the evaluator
+// forms its optical depth and warped depth (piece_a, piece_z, the arithmetic
+// of stage one): the walker's divergent cutting loop stays short.
 struct Producer {
   PairLDS* sh;
-  const float4* tf;  // LDS RGBA table
   int lane, parity;
   int tail;   // pieces produced
   int limit;  // ring slots free up to here (evaluated count at the last boundary + PQ)
@@ -1174,13 +1185,9 @@ struct Producer {
       const double v = fmin(nxt, ct1);
       const double tm = 0.5 * (cu + v);
       const float s = cs0 + cslope * float(tm - ct0);
-      int i0;
-      float fr, a, z;
-      tf_coord(f, s, i0, fr);
-      piece_az(f, tm, float(v - cu), lerp_nc(tf[i0].w, tf[i0 + 1].w, fr), a, z);  // as stage one
       const int slot = (tail & (PQ - 1)) * WAVE + lane;
-      sh->q[0][slot] = z;
-      sh->q[1][slot] = a;
+      sh->q[0][slot] = float(tm + f.t_mid);
+      sh->q[1][slot] = float(v - cu);
       sh->q[2][slot] = s;
       ++tail;
       ++pieces;
@@ -1303,7 +1310,6 @@ __global__ __launch_bounds__(2 * WAVE) __attribute__((amdgpu_waves_per_eu(APC_PA
     const Ray r = pixel_ray(f, valid ? py : 0, valid ? px : 0);
     Producer q;
     q.sh = &sh;
-    q.tf = tf;
     q.lane = lane;
     q.parity = 0;
     q.tail = 0;
@@ -1352,13 +1358,14 @@ __global__ __launch_bounds__(2 * WAVE) __attribute__((amdgpu_waves_per_eu(APC_PA
     int head = 0, avail = 0, parity = 0;
     auto eval_one = [&]() {  // Alg. 1 second loop with Alg. 3's bound, for the piece at `head`
       const int slot = (head & (PQ - 1)) * WAVE + lane;
-      const float z = sh.q[0][slot], a = sh.q[1][slot], s = sh.q[2][slot];
+      const float wt = sh.q[0][slot], len = sh.q[1][slot], s = sh.q[2][slot];
       ++head;
       if (bound.mode == 0) return;  // no absorbance on the ray: every piece has a = 0
       int i0;
       float fr;
       tf_coord(f, s, i0, fr);
       const float4 c0 = tf[i0], c1 = tf[i0 + 1];
+      const float a = piece_a(f, lerp_nc(c0.w, c1.w, fr), len), z = piece_z(f, wt);  // as stage one
       R F;
       if constexpr (N >= 3) {
         int how;
