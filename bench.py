@@ -384,7 +384,8 @@ def batching_leg(bsc, steps=5):
     import synth
     ctx = apc.Context(0)
     r = apc.Renderer(ctx, bsc)
-    best, ms = ctx.autotune_tile_shape(r.mesh, r.view, r.tf, r.mboit, r.subs, r.moments, r.rgba, repeats=1)
+    best, mode, table = ctx.autotune_launch(r.mesh, r.view, r.tf, r.mboit, r.subs, r.moments, r.rgba, repeats=1)
+    ms = {w: v for (d, w), v in table.items() if d == apc.APC_DISPATCH_GRID}
     views = [synth.orbit_view(synth.BATCHING_SEED, c, bsc.view["width"]) for c in range(N_CAMERAS)]
     fr = Frames(r, ctx, views)
     survey = fr.survey()
@@ -393,7 +394,10 @@ def batching_leg(bsc, steps=5):
     out = {"workload": "batching: %d tets (32^3 base refined 0-3 levels, cone decomposition), 72 Morton subdomains "
                        "of tet-count ratio 12, %dx%d perspective views (5 orbit cameras), m=%d" % (
                            bsc.mesh.n_tets, bsc.view["width"], bsc.view["height"], bsc.m),
-           "autotune": {"best_width": best, "frame_ms_by_width": {str(k): round(v, 3) for k, v in ms.items()}},
+           "autotune": {"best_width": best, "best_dispatch": "queue" if mode == apc.APC_DISPATCH_QUEUE else "grid",
+                        "frame_ms_by_width": {str(k): round(v, 3) for k, v in ms.items()},
+                        "queue_frame_ms_by_width": {str(w): round(v, 3) for (d, w), v in table.items()
+                                                    if d == apc.APC_DISPATCH_QUEUE}},
            "steps": steps, "ms_per_step": round(run["elapsed_s"] * 1e3 / steps, 3),
            "median_camera_frame_ms": round(run["median_camera_ms"], 3),
            "frames_per_s": round(1e3 / run["median_camera_ms"], 3),
@@ -432,21 +436,22 @@ def batching_leg(bsc, steps=5):
         out["graph_rgba_bitwise_equal"] = bool(torch.equal(r.rgba, rgba0))
     finally:
         g.close()
-    # the same plain frames from a persistent launch taking tiles from a work queue, against one workgroup
-    # per tile: all 5 cameras, each pass's kernel time
-    grid_kern = out["kernels_ms_mean"]
-    ctx.set_dispatch(apc.APC_DISPATCH_QUEUE)
+    # the same plain frames in the other dispatch mode than the autotuned one (a persistent launch taking
+    # tiles from a work queue, or one workgroup per tile): all 5 cameras, each pass's kernel time
+    other = apc.APC_DISPATCH_GRID if mode == apc.APC_DISPATCH_QUEUE else apc.APC_DISPATCH_QUEUE
+    ctx.set_dispatch(other)
     try:
         fr.frame(0)
         torch.cuda.synchronize()
         same = bool(torch.equal(r.rgba, rgba0))
         qrun = fr.timed(steps)
-        out["work_queue"] = {
+        out["other_dispatch"] = {
+            "dispatch": "queue" if other == apc.APC_DISPATCH_QUEUE else "grid",
             "median_camera_frame_ms": round(qrun["median_camera_ms"], 3),
             "kernels_ms_mean": {k: round(float(np.mean(v)), 3) for k, v in qrun["kernels"].items()},
-            "grid_kernels_ms_mean": grid_kern, "rgba_bitwise_equal_camera0": same}
+            "rgba_bitwise_equal_camera0": same}
     finally:
-        ctx.set_dispatch(apc.APC_DISPATCH_GRID)
+        ctx.set_dispatch(mode)
     del fr, kf, r
     ctx.close()
     torch.cuda.synchronize()
@@ -570,9 +575,10 @@ def main():
     if args.tile_width:
         ctx.set_tile_shape(args.tile_width)
     if args.autotune:
-        best, ms = ctx.autotune_tile_shape(r.mesh, r.view, r.tf, r.mboit, r.subs, r.moments, r.rgba, repeats=1)
-        tuned = {"best_width": best, "frame_ms_by_width": {str(k): round(v, 3) for k, v in ms.items()}}
-        log("autotuned tile: %s" % tuned)
+        best, mode, table = ctx.autotune_launch(r.mesh, r.view, r.tf, r.mboit, r.subs, r.moments, r.rgba, repeats=1)
+        tuned = {"best_width": best, "best_dispatch": "queue" if mode == apc.APC_DISPATCH_QUEUE else "grid",
+                 "frame_ms": {"%s/%d" % ("queue" if d else "grid", w): round(v, 3) for (d, w), v in table.items()}}
+        log("autotuned launch: %s" % tuned)
 
     views = camera_views(args, sc)
     fr = Frames(r, ctx, views, keep=args.keep)

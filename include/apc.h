@@ -424,6 +424,16 @@ apc_status apc_autotune_tile_shape(apc_ctx ctx, apc_mesh mesh, const apc_view* v
                                    float* rgba_out, int32_t repeats, int32_t* best_width, float* ms_per_width,
                                    void* stream);
 
+/* The same search over tile widths 2..32 for both dispatch modes
+ * (APC_DISPATCH_GRID, APC_DISPATCH_QUEUE), setting the fastest width and
+ * mode on the context.  ms_table: host [2][7] or NULL, entry [d][k] = frame
+ * milliseconds for mode d and width 2^k, -1 where not timed.  Allocates the
+ * work queue's counters (as apc_set_dispatch does).  Synchronous. */
+apc_status apc_autotune_launch(apc_ctx ctx, apc_mesh mesh, const apc_view* view, const apc_tf* tf,
+                               const apc_mboit* mboit, const int32_t* subdomains, int32_t n_sub, float* moments,
+                               float* rgba_out, int32_t repeats, int32_t* best_width, int32_t* best_dispatch,
+                               float* ms_table, void* stream);
+
 /* ------------------------------------------------------------------ diagnostics */
 
 /* Per-pixel segment statistics of the last apc_moments_pass on this context

@@ -34,7 +34,7 @@ EXPORTS = ["apc_create", "apc_destroy", "apc_last_error", "apc_version", "apc_lo
            "apc_get_timings", "apc_set_tile_shape", "apc_get_tile_shape", "apc_autotune_tile_shape",
            "apc_frame_graph_create", "apc_frame_graph_launch", "apc_frame_graph_counters", "apc_frame_graph_destroy",
            "apc_set_workspace_limit", "apc_resolve_pass_noalloc", "apc_get_workspace_bytes", "apc_set_dispatch",
-           "apc_get_dispatch", "apc_moments_pass_tiles", "apc_sum_moment_tiles"]
+           "apc_get_dispatch", "apc_moments_pass_tiles", "apc_sum_moment_tiles", "apc_autotune_launch"]
 
 
 class ApcError(RuntimeError):
@@ -152,6 +152,9 @@ def lib():
         L.apc_autotune_tile_shape.restype = st
         L.apc_autotune_tile_shape.argtypes = [vp, vp, C.POINTER(View), C.POINTER(TF), C.POINTER(Mboit), vp,
                                               C.c_int32, vp, vp, C.c_int32, C.POINTER(C.c_int32), vp, vp]
+        L.apc_autotune_launch.restype = st
+        L.apc_autotune_launch.argtypes = [vp, vp, C.POINTER(View), C.POINTER(TF), C.POINTER(Mboit), vp, C.c_int32,
+                                          vp, vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), vp, vp]
         L.apc_segment_counts.restype = st
         L.apc_segment_counts.argtypes = [vp, vp, C.c_int32, C.c_int32, vp]
         L.apc_sum_images.restype = st
@@ -410,6 +413,21 @@ class Context:
                                                _dev_ptr(rgba, torch.float32, name="rgba"), int(repeats),
                                                C.byref(best), C.c_void_p(ms.ctypes.data), _stream(stream)))
         return best.value, {1 << k: float(ms[k]) for k in range(7) if ms[k] >= 0}
+
+    def autotune_launch(self, mesh, view: View, tf: TF, mboit: Mboit, subdomains, moments, rgba, repeats=1,
+                        stream=None):
+        """The tile-width search of autotune_tile_shape for both dispatch modes; sets the fastest width and mode.
+        Returns (width, mode, {(mode, width): frame ms})."""
+        import torch
+        ids, ptr = _ids(subdomains)
+        best, mode = C.c_int32(0), C.c_int32(0)
+        ms = np.full(14, -1.0, dtype=np.float32)
+        self._ck(lib().apc_autotune_launch(self.handle, mesh.handle, C.byref(view), C.byref(tf), C.byref(mboit), ptr,
+                                           len(ids), _dev_ptr(moments, torch.float32, name="moments"),
+                                           _dev_ptr(rgba, torch.float32, name="rgba"), int(repeats), C.byref(best),
+                                           C.byref(mode), C.c_void_p(ms.ctypes.data), _stream(stream)))
+        table = {(d, 1 << k): float(ms[d * 7 + k]) for d in range(2) for k in range(7) if ms[d * 7 + k] >= 0}
+        return best.value, mode.value, table
 
     def segment_counts(self, height, width, stream=None):
         """[2][H][W] int32 of the last stage one: segments per pixel, subdomains met per pixel."""

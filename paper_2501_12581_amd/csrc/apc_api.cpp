@@ -1383,54 +1383,85 @@ apc_status apc_get_tile_shape(apc_ctx ctx, int32_t* tile_width, int32_t* tile_he
   return APC_OK;
 }
 
-apc_status apc_autotune_tile_shape(apc_ctx ctx, apc_mesh m, const apc_view* view, const apc_tf* tf,
-                                   const apc_mboit* mboit, const int32_t* subs, int32_t n_sub, float* moments,
-                                   float* rgba_out, int32_t repeats, int32_t* best_width, float* ms_per_width,
-                                   void* stream) {
+// Whole frames (stage one summing the subdomains itself, then the finalising resolve) timed with HIP events
+// on `stream` for tile widths 2..32 and, with both_modes, both dispatch modes: the best of `repeats` after a
+// warm-up frame per configuration.  Sets the fastest on the context (leaves it as it was on failure).
+static apc_status autotune_frames(apc_ctx ctx, apc_mesh m, const apc_view* view, const apc_tf* tf,
+                                  const apc_mboit* mboit, const int32_t* subs, int32_t n_sub, float* moments,
+                                  float* rgba_out, int32_t repeats, bool both_modes, int32_t* best_width,
+                                  int32_t* best_dispatch, float* ms_table, void* stream, const char* who) {
   apc_status st = check_ctx(ctx);
   if (st != APC_OK) return st;
   if (repeats < 1 || repeats > 100) return fail(APC_E_ARG, "repeats must be in 1..100");
   if (!mboit) return fail(APC_E_ARG, "mboit is NULL");
   if ((st = check_mesh(ctx, m)) != APC_OK) return st;
-  if (ctx->host_only) return no_device("apc_autotune_tile_shape");
+  if (ctx->host_only) return no_device(who);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  const int old_lg = ctx->tw_log2, old_mode = ctx->dispatch;
+  const int n_modes = both_modes ? 2 : 1;
+  for (int k = 0; k < 7 * n_modes; ++k)
+    if (ms_table) ms_table[k] = -1.0f;
+  if (both_modes && (st = apc_set_dispatch(ctx, APC_DISPATCH_QUEUE)) != APC_OK) return st;  // its counters, once
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
-  const int old = ctx->tw_log2;
-  int best = old;
-  float best_ms = 0.0f;
-  for (int k = 0; k <= 6; ++k)
-    if (ms_per_width) ms_per_width[k] = -1.0f;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(APC_E_DEVICE, "event creation failed");
+  }
+  int best_lg = old_lg, best_mode = old_mode;
+  float best_ms = -1.0f;
   apc_status res = APC_OK;
-  for (int lg = 1; lg <= 5 && res == APC_OK; ++lg) {  // 2x32 .. 32x2
-    ctx->tw_log2 = lg;
-    float t_min = 0.0f;
-    for (int rep = 0; rep <= repeats && res == APC_OK; ++rep) {  // the first run is a warm-up
-      if (hipEventRecord(e0, s) != hipSuccess) res = fail(APC_E_DEVICE, "event record failed");
-      if (res == APC_OK)
-        res = apc_moments_pass(ctx, m, view, tf, mboit->m, subs, n_sub, moments, APC_MOMENTS_GLOBAL, stream);
-      if (res == APC_OK)
-        res = apc_resolve_pass(ctx, m, view, tf, mboit, moments, subs, n_sub, rgba_out, APC_FINALIZE, stream);
-      if (res == APC_OK && hipEventRecord(e1, s) != hipSuccess) res = fail(APC_E_DEVICE, "event record failed");
-      float ms = 0.0f;
-      if (res == APC_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-        res = fail(APC_E_DEVICE, "event timing failed");
-      if (res == APC_OK && rep > 0) t_min = (rep == 1) ? ms : std::min(t_min, ms);
-    }
-    if (res != APC_OK) break;
-    if (ms_per_width) ms_per_width[lg] = t_min;
-    if (lg == 1 || t_min < best_ms) {
-      best_ms = t_min;
-      best = lg;
+  for (int mi = 0; mi < n_modes && res == APC_OK; ++mi) {
+    ctx->dispatch = both_modes ? (mi == 0 ? APC_DISPATCH_GRID : APC_DISPATCH_QUEUE) : old_mode;
+    for (int lg = 1; lg <= 5 && res == APC_OK; ++lg) {  // 2x32 .. 32x2
+      ctx->tw_log2 = lg;
+      float t_min = 0.0f;
+      for (int rep = 0; rep <= repeats && res == APC_OK; ++rep) {  // the first run is a warm-up
+        if (hipEventRecord(e0, s) != hipSuccess) res = fail(APC_E_DEVICE, "event record failed");
+        if (res == APC_OK)
+          res = apc_moments_pass(ctx, m, view, tf, mboit->m, subs, n_sub, moments, APC_MOMENTS_GLOBAL, stream);
+        if (res == APC_OK)
+          res = apc_resolve_pass(ctx, m, view, tf, mboit, moments, subs, n_sub, rgba_out, APC_FINALIZE, stream);
+        if (res == APC_OK && hipEventRecord(e1, s) != hipSuccess) res = fail(APC_E_DEVICE, "event record failed");
+        float ms = 0.0f;
+        if (res == APC_OK &&
+            (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+          res = fail(APC_E_DEVICE, "event timing failed");
+        if (res == APC_OK && rep > 0) t_min = (rep == 1) ? ms : std::min(t_min, ms);
+      }
+      if (res != APC_OK) break;
+      if (ms_table) ms_table[mi * 7 + lg] = t_min;
+      if (best_ms < 0.0f || t_min < best_ms) {
+        best_ms = t_min;
+        best_lg = lg;
+        best_mode = ctx->dispatch;
+      }
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  ctx->tw_log2 = res == APC_OK ? best : old;
+  ctx->tw_log2 = res == APC_OK ? best_lg : old_lg;
+  ctx->dispatch = res == APC_OK ? best_mode : old_mode;
   ctx->pc_valid = false;  // the piece counts of the last run belong to another tile shape
-  if (res == APC_OK && best_width) *best_width = 1 << best;
+  if (res == APC_OK && best_width) *best_width = 1 << best_lg;
+  if (res == APC_OK && best_dispatch) *best_dispatch = best_mode;
   return res;
+}
+
+apc_status apc_autotune_tile_shape(apc_ctx ctx, apc_mesh m, const apc_view* view, const apc_tf* tf,
+                                   const apc_mboit* mboit, const int32_t* subs, int32_t n_sub, float* moments,
+                                   float* rgba_out, int32_t repeats, int32_t* best_width, float* ms_per_width,
+                                   void* stream) {
+  return autotune_frames(ctx, m, view, tf, mboit, subs, n_sub, moments, rgba_out, repeats, false, best_width,
+                         nullptr, ms_per_width, stream, "apc_autotune_tile_shape");
+}
+
+apc_status apc_autotune_launch(apc_ctx ctx, apc_mesh m, const apc_view* view, const apc_tf* tf,
+                               const apc_mboit* mboit, const int32_t* subs, int32_t n_sub, float* moments,
+                               float* rgba_out, int32_t repeats, int32_t* best_width, int32_t* best_dispatch,
+                               float* ms_table, void* stream) {
+  return autotune_frames(ctx, m, view, tf, mboit, subs, n_sub, moments, rgba_out, repeats, true, best_width,
+                         best_dispatch, ms_table, stream, "apc_autotune_launch");
 }
 
 apc_status apc_segment_counts(apc_ctx ctx, int32_t* out, int32_t H, int32_t W, void* stream) {

@@ -338,6 +338,13 @@ def test_sums_pack_and_settings_statuses(P, ctx, scene):
                                      ptr(sc["subs"]), 3, mg, rgba, 0, C.byref(best), None, None) == 1
     assert L.apc_autotune_tile_shape(ctx, sc["mesh"], C.byref(sc["view"]), C.byref(sc["tf"]), C.byref(sc["mb"]),
                                      ptr(sc["subs"]), 3, mg, rgba, 1, C.byref(best), None, None) == 4
+    mode = C.c_int32()
+    assert L.apc_autotune_launch(ctx, sc["mesh"], C.byref(sc["view"]), C.byref(sc["tf"]), C.byref(sc["mb"]),
+                                 ptr(sc["subs"]), 3, mg, rgba, 0, C.byref(best), C.byref(mode), None, None) == 1
+    assert L.apc_autotune_launch(ctx, sc["mesh"], C.byref(sc["view"]), C.byref(sc["tf"]), None,
+                                 ptr(sc["subs"]), 3, mg, rgba, 1, C.byref(best), C.byref(mode), None, None) == 1
+    assert L.apc_autotune_launch(ctx, sc["mesh"], C.byref(sc["view"]), C.byref(sc["tf"]), C.byref(sc["mb"]),
+                                 ptr(sc["subs"]), 3, mg, rgba, 1, C.byref(best), C.byref(mode), None, None) == 4
     cnt = P.Counters()
     assert L.apc_get_counters(ctx, C.byref(cnt), 0) == 4
     g = C.c_void_p()

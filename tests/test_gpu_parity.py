@@ -426,8 +426,16 @@ def test_tile_shapes_give_identical_results_and_autotuner(apc, ctx):
         assert torch.equal(r.frame(), outs[8][1])
         with pytest.raises(apc.ApcError):
             ctx.set_tile_shape(3)
+        # widths and both dispatch modes: the fastest is set, the frame is unchanged
+        best, mode, table = ctx.autotune_launch(r.mesh, r.view, r.tf, r.mboit, r.subs, r.moments, r.rgba)
+        print("autotuned launch", best, mode, table)
+        assert sorted(table) == [(d, w) for d in (0, 1) for w in (2, 4, 8, 16, 32)]
+        assert table[(mode, best)] == min(table.values())
+        assert ctx.tile_shape()[0] == best and ctx.dispatch() == mode
+        assert torch.equal(r.frame(), outs[8][1])
     finally:
         ctx.set_tile_shape(8)
+        ctx.set_dispatch(apc.APC_DISPATCH_GRID)
 
 
 @pytest.mark.parametrize("size,m,tw", [(300, 8, 8), (200, 4, 16)])
