@@ -795,6 +795,7 @@ struct Bound {
   // closed forms ran (a new gap, or no convergence).  zs: the sorted zeros.
   template <class Z>
   APC_HD R frac_before_cont(R z, R eta, const Z& zs, Cont& c, int& how) const {
+    static_assert(N == 3 || N == 4, "the continuation serves m = 6 and m = 8");
     constexpr int NC = Gaps<N>::NC;
     bool closed = false;
     how = 0;
@@ -817,15 +818,30 @@ struct Bound {
     for (int t = 0; t < N; ++t) k += zs[t] < z ? 1 : 0;
     bool ok = k >= 1 && k <= N - 1;
     const int kk = ok ? k : 1;
-    const int nn = side_count(kk);
-    const R lo = zs[kk - 1], hi = zs[kk];
+    // For N <= 4 the nodes on the fewer side of gap kk (side_gap) are the one
+    // of gap 0 (left: 2 kk <= N) or of gap N (right), and for N = 4, kk = 2
+    // also the one of gap 1 = (zs[0], zs[1]).  So root slot 0 always lies in
+    // an outer gap and slot 1 in gap 1, and every zero is read at a constant
+    // index (a run-time index costs a select over all N of them).
+    const bool left = 2 * kk <= N;
+    const bool two = N == 4 && kk == 2;  // slot 1 in use
+    R lo = zs[0], hi = zs[1];            // the gap of z: (zs[kk - 1], zs[kk])
+#pragma unroll
+    for (int t = 2; t < N; ++t) {
+      lo = kk == t ? zs[t - 1] : lo;
+      hi = kk == t ? zs[t] : hi;
+    }
+    const R base = left ? zs[0] : zs[N - 1];  // slot 0: the finite end of its gap
     const R sz = (z - lo) * m_rcp_est(hi - z);  // the gap coordinate only maps Newton starts
     R x[NC];
-    if (ok && kk == c.k) {
+    if (ok && kk == c.k) {  // from_table of each slot's root
       const R isz = (hi - z) * m_rcp_est(z - lo);  // the start needs no more
-#pragma unroll
-      for (int cc = 0; cc < NC; ++cc) x[cc] = cc < nn ? from_table(zs, side_gap(kk, cc), c.v[cc], sz, isz) : R(0);
-    } else {  // starts from the closed forms, sorted, on the fewer-node side of the gap
+      x[0] = base + c.v[0] * (left ? isz : sz);
+      if constexpr (NC > 1) {
+        const R e = c.v[1] * sz;
+        x[1] = two ? zs[0] + (zs[1] - zs[0]) * e * m_rcp_est(R(1) + e) : R(0);
+      }
+    } else {  // starts from the closed forms, sorted: gap j's root is r[j] below kk, r[j - 1] above
       closed = true;
       R r[N];
 #pragma unroll
@@ -833,17 +849,13 @@ struct Bound {
       const int nr = poly_roots<N, R, 1>(q, r);
       sort_up(r);
       ok = ok && nr == N;
-#pragma unroll
-      for (int cc = 0; cc < NC; ++cc) {
-        const int j = side_gap(kk, cc);
-        x[cc] = (cc < nn) ? pick_reg<N>(r, j < kk ? j : j - 1) : R(0);
-      }
+      x[0] = left ? r[0] : r[N - 1];
+      if constexpr (NC > 1) x[1] = two ? r[1] : R(0);
     }
     R S = R(0);
 #pragma unroll
     for (int cc = 0; cc < NC; ++cc) {
-      if (cc < nn) {
-        const int j = side_gap(kk, cc);
+      if (cc == 0 || two) {
         R xi = x[cc], d = R(0);
 #pragma unroll
         for (int it = 0; it < CONT_STEPS; ++it) {
@@ -856,14 +868,16 @@ struct Bound {
           d = p * m_rcp_est(dp);
           xi -= d;
         }
-        const R blo = j == 0 ? -R(HUGE_VAL) : pick<N>(zs, j - 1);
-        const R bhi = j == N ? R(HUGE_VAL) : pick<N>(zs, j);
+        const R blo = cc == 0 ? (left ? -R(HUGE_VAL) : zs[N - 1]) : zs[0];
+        const R bhi = cc == 0 ? (left ? zs[0] : R(HUGE_VAL)) : zs[1];
         const R lam = m_rcp(kernel_diag(xi));
         const R ad = m_abs(d);
-        const R edge = j == 0 ? bhi : blo;
+        // converged: a small last step, or (outer gaps, where K grows away
+        // from the zeros) a weight too small for the step to matter -- from an
+        // iterate that has settled against its distance to the gap's end
         const bool conv = ad <= R(1e-7) * m_max(R(1), m_abs(xi)) ||
-                          ((j == 0 || j == N) && lam * ad <= R(1e-12) * m_abs(xi - edge) &&
-                           ad <= R(1e-3) * m_abs(xi - edge));
+                          (cc == 0 && lam * ad <= R(1e-12) * m_abs(xi - base) &&
+                           ad <= R(1e-3) * m_abs(xi - base));
         ok = ok && xi > blo && xi < bhi && conv;
         x[cc] = xi;
         S += lam;
@@ -876,10 +890,14 @@ struct Bound {
     }
     how = closed ? 2 : 1;
     c.k = kk;
-#pragma unroll
-    for (int cc = 0; cc < NC; ++cc) c.v[cc] = cc < nn ? to_table(zs, side_gap(kk, cc), x[cc], sz) : R(0);
-    return 2 * kk <= N ? eta * lam0 + S : R(1) - (R(1) - eta) * lam0 - S;
+    c.v[0] = (x[0] - base) * (left ? sz : m_rcp_est(sz));  // to_table of slot 0
+    if constexpr (NC > 1) {
+      const R fr = (x[1] - zs[0]) * m_rcp_est(zs[1] - zs[0]);
+      c.v[1] = two ? fr * m_rcp_est((R(1) - fr) * sz) : R(0);
+    }
+    return left ? eta * lam0 + S : R(1) - (R(1) - eta) * lam0 - S;
   }
+
 };
 
 }  // namespace apcm
