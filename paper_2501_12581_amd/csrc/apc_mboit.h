@@ -119,6 +119,16 @@ APC_HD double m_rcp(double b) {
 #endif
 }
 
+// 1/b for finite b != 0 with one Newton-Raphson refinement of the estimate
+APC_HD double m_rcp1(double b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r = __builtin_amdgcn_rcp(b);
+  return fma(fma(-b, r, 1.0), r, r);
+#else
+  return 1.0 / b;
+#endif
+}
+
 // 1/b to about half precision (hardware estimate on the device): enough for
 // the steps of an iteration whose final step is checked
 APC_HD double m_rcp_est(double b) {
@@ -784,7 +794,7 @@ struct Bound {
   // Either way the roots must converge inside their gaps (the table path's
   // test), else the sample takes the closed-form bound, so the start changes
   // the cost of a sample but not its result beyond rounding.
-  static constexpr int CONT_STEPS = 4;  // Newton steps from a continued (or closed-form) start
+  static constexpr int CONT_STEPS = 4;  // steps from a continued (or closed-form) start: 3 Newton, 1 chord
   struct Cont {
     int k;
     R v[Gaps<N>::NC > 0 ? Gaps<N>::NC : 1];  // regularised roots (to_table) of gap k
@@ -808,7 +818,7 @@ struct Bound {
     R K0 = R(0);
 #pragma unroll
     for (int k = 0; k <= N; ++k) K0 += P[k] * P[k];
-    const R lam0 = m_rcp(K0);
+    const R lam0 = m_rcp1(K0);
     if (z < xlo) return eta * lam0;
     if (z > xhi) return R(1) - (R(1) - eta) * lam0;
     R q[N + 1];
@@ -856,21 +866,27 @@ struct Bound {
 #pragma unroll
     for (int cc = 0; cc < NC; ++cc) {
       if (cc == 0 || two) {
-        R xi = x[cc], d = R(0);
+        R xi = x[cc], d = R(0), rd = R(0);
 #pragma unroll
         for (int it = 0; it < CONT_STEPS; ++it) {
           R p = q[N], dp = R(0);
+          if (it < CONT_STEPS - 1) {  // Newton steps
 #pragma unroll
-          for (int t = N - 1; t >= 0; --t) {
-            dp = dp * xi + p;
-            p = p * xi + q[t];
+            for (int t = N - 1; t >= 0; --t) {
+              dp = dp * xi + p;
+              p = p * xi + q[t];
+            }
+            rd = m_rcp_est(dp);
+          } else {  // the last step keeps the previous slope
+#pragma unroll
+            for (int t = N - 1; t >= 0; --t) p = p * xi + q[t];
           }
-          d = p * m_rcp_est(dp);
+          d = p * rd;
           xi -= d;
         }
         const R blo = cc == 0 ? (left ? -R(HUGE_VAL) : zs[N - 1]) : zs[0];
         const R bhi = cc == 0 ? (left ? zs[0] : R(HUGE_VAL)) : zs[1];
-        const R lam = m_rcp(kernel_diag(xi));
+        const R lam = m_rcp1(kernel_diag(xi));
         const R ad = m_abs(d);
         // converged: a small last step, or (outer gaps, where K grows away
         // from the zeros) a weight too small for the step to matter -- from an
