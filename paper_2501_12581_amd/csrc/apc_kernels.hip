@@ -51,6 +51,11 @@ __device__ __constant__ int kFaceOut[4][3] = {{1, 2, 3}, {0, 3, 2}, {0, 1, 3}, {
 __device__ __forceinline__ int sel4(const int4& v, int i) {
   return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
 }
+// The same as an OR of masked components: every component is read (the four
+// come from one load), and no branch or indexed access is left.
+__device__ __forceinline__ int sel4m(const int4& v, int i) {
+  return (v.x & -int(i == 0)) | (v.y & -int(i == 1)) | (v.z & -int(i == 2)) | (v.w & -int(i == 3));
+}
 
 // Blocks are dispatched round-robin over the 8 XCDs (block b runs on XCD
 // b % 8).  The tiles are handed out in runs of XCD_RUN consecutive tiles, run
@@ -362,7 +367,7 @@ __device__ __forceinline__ bool walk_step(const MeshDev& M, const Ray& r, WalkPo
   const int4 tv = rec[0];
   const int4 tn = rec[1];
   const float4 dp = reinterpret_cast<const float4*>(rec)[2 + w.apex];
-  const int did = sel4(tv, w.apex);
+  const int did = sel4m(tv, w.apex);
   const VS D = vstate(r, did, dp);
   const float qA = side(D, w.A), qB = side(D, w.B), qC = side(D, w.C);
   // exit through the face opposite X where q(next of X) > 0 > q(previous of X)
@@ -395,7 +400,7 @@ __device__ __forceinline__ bool walk_step(const MeshDev& M, const Ray& r, WalkPo
   if (!(tout >= tin)) tout = tin;
   ++cnt.steps;
   const int xl = tv.x == xid ? 0 : (tv.y == xid ? 1 : (tv.z == xid ? 2 : 3));
-  const int nb = sel4(tn, xl);
+  const int nb = sel4m(tn, xl);
   if (nb < 0) return false;
   const int t2 = nb >> 2;
   if (t2 < t_lo || t2 >= t_hi) return false;
@@ -456,7 +461,7 @@ __device__ void walk(const MeshDev& M, const FrameDev& f, const Ray& r, int tet,
     ++cnt.steps;
     sink.chord(tin, tout, sin_, sout);
     int xl = tv.x == xid ? 0 : (tv.y == xid ? 1 : (tv.z == xid ? 2 : 3));
-    int nb = sel4(tn, xl);
+    int nb = sel4m(tn, xl);
     if (nb < 0) return;
     int t2 = nb >> 2;
     if (t2 < t_lo || t2 >= t_hi) return;
