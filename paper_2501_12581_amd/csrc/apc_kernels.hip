@@ -1266,20 +1266,24 @@ __device__ void walk_subdomain_paired(const MeshDev& M, const FrameDev& f, const
         ++k;
       }
       if (q.cutting) q.cut_more(f);  // the rest of a chord that did not fit the ring
-      for (int burst = 0; !q.cutting && walking && burst < APC_RES_BURST && q.can_step(); ++burst) {
-        if (steps >= f.max_steps) {
-          cnt.rare(C_STEPLIMIT);
-          walking = false;
-          break;
+      for (int burst = 0; burst < APC_RES_BURST; ++burst) {  // a uniform loop: lanes that stop just idle
+        const bool act = !q.cutting && walking && q.can_step();
+        if (!__any(act)) break;
+        if (act) {
+          if (steps >= f.max_steps) {
+            cnt.rare(C_STEPLIMIT);
+            walking = false;
+          } else {
+            double tout;
+            float sout;
+            walking = walk_step(M, r, w, tin, sl.tet_begin, sl.tet_end, tout, sout, cnt);
+            ++steps;
+            q.start_cut(f, tin, tout, sin_, sout);
+            q.cut_more(f);
+            tin = tout;
+            sin_ = sout;
+          }
         }
-        double tout;
-        float sout;
-        walking = walk_step(M, r, w, tin, sl.tet_begin, sl.tet_end, tout, sout, cnt);
-        ++steps;
-        q.start_cut(f, tin, tout, sin_, sout);
-        q.cut_more(f);
-        tin = tout;
-        sin_ = sout;
       }
       if (open && !walking && !q.cutting) {  // a maximal ray interval inside the subdomain ended
         cnt.segments += q.pieces > seg_start ? 1u : 0u;
