@@ -191,9 +191,10 @@ __device__ __forceinline__ float side(const VS& a, const VS& b) {
 
 // Crossing point of the ray with the face (A, B, C) whose oriented products
 // pAB, pBC, pCA are all positive: barycentric weights (pBC, pCA, pAB).  The
-// sums start at the vertex with the smallest id, so the walk that leaves a
-// tet through a face and the entry test of the tet behind it (which list the
-// face's vertices in different rotations) get the same depth bit for bit.
+// sums start at the vertex with the smallest id, so a walk that leaves its
+// subdomain (or the mesh) through a face and the entry test of the tet behind
+// it (which list the face's vertices in different rotations) get the same
+// depth bit for bit.
 // The depth is that vertex's FP64 depth plus the weighted depth differences
 // across the face (at most a cell's extent, so FP32 keeps them to ~1e-7 of a
 // cell, the precision of the weights themselves).
@@ -216,6 +217,25 @@ __device__ __forceinline__ void face_point(const VS& A, const VS& B, const VS& C
   float inv = __builtin_amdgcn_rcpf(sum);  // 1 ulp; both passes alike
   t = t0 + double((u1 * float(t1 - t0) + u2 * float(t2 - t0)) * inv);
   s = (u0 * s0 + u1 * s1 + u2 * s2) * inv;
+}
+
+// The same crossing with A as the base vertex: the depth and scalar a walk
+// hands from one tet to the next inside a subdomain, where only this walk
+// meets the face.  Where the walk leaves the subdomain (the neighbouring
+// subdomain's entry test meets the face too) face_point's ordering is used.
+__device__ __forceinline__ void face_point_a(const VS& A, const VS& B, const VS& C, float pAB, float pBC, float pCA,
+                                             double& t, float& s) {
+#pragma clang fp contract(off)
+  const float uA = fmaxf(pBC, 0.0f), uB = fmaxf(pCA, 0.0f), uC = fmaxf(pAB, 0.0f);
+  const float sum = uA + uB + uC;
+  if (!(sum > 0.0f)) {
+    t = A.t;
+    s = A.s;
+    return;
+  }
+  const float inv = __builtin_amdgcn_rcpf(sum);
+  t = A.t + double((uB * float(B.t - A.t) + uC * float(C.t - A.t)) * inv);
+  s = (uA * A.s + uB * B.s + uC * C.s) * inv;
 }
 
 // A boundary face staged in LDS, vertices in outward order of its tet.
@@ -396,14 +416,17 @@ __device__ __forceinline__ bool walk_step(const MeshDev& M, const Ray& r, WalkPo
   w.pAB = nAB;
   w.pBC = nBC;
   w.pCA = nCA;
-  face_point(w.A, w.B, w.C, w.pAB, w.pBC, w.pCA, tout, sout);
-  if (!(tout >= tin)) tout = tin;
   ++cnt.steps;
   const int xl = tv.x == xid ? 0 : (tv.y == xid ? 1 : (tv.z == xid ? 2 : 3));
   const int nb = sel4m(tn, xl);
-  if (nb < 0) return false;
   const int t2 = nb >> 2;
-  if (t2 < t_lo || t2 >= t_hi) return false;
+  const bool stays = nb >= 0 && t2 >= t_lo && t2 < t_hi;
+  if (stays)
+    face_point_a(w.A, w.B, w.C, w.pAB, w.pBC, w.pCA, tout, sout);
+  else
+    face_point(w.A, w.B, w.C, w.pAB, w.pBC, w.pCA, tout, sout);
+  if (!(tout >= tin)) tout = tin;
+  if (!stays) return false;
   w.tet = t2;
   w.apex = nb & 3;
   return true;
@@ -456,15 +479,18 @@ __device__ void walk(const MeshDev& M, const FrameDev& f, const Ray& r, int tet,
     pCA = nCA;
     double tout;
     float sout;
-    face_point(A, B, C, pAB, pBC, pCA, tout, sout);
+    int xl = tv.x == xid ? 0 : (tv.y == xid ? 1 : (tv.z == xid ? 2 : 3));
+    int nb = sel4m(tn, xl);
+    int t2 = nb >> 2;
+    const bool stays = nb >= 0 && t2 >= t_lo && t2 < t_hi;
+    if (stays)
+      face_point_a(A, B, C, pAB, pBC, pCA, tout, sout);
+    else
+      face_point(A, B, C, pAB, pBC, pCA, tout, sout);
     if (!(tout >= tin)) tout = tin;
     ++cnt.steps;
     sink.chord(tin, tout, sin_, sout);
-    int xl = tv.x == xid ? 0 : (tv.y == xid ? 1 : (tv.z == xid ? 2 : 3));
-    int nb = sel4m(tn, xl);
-    if (nb < 0) return;
-    int t2 = nb >> 2;
-    if (t2 < t_lo || t2 >= t_hi) return;
+    if (!stays) return;
     tet = t2;
     apex = nb & 3;
     tin = tout;
