@@ -14,10 +14,11 @@
 //   k_sum_moments / k_sum_tiles  canonical-order FP64 sum of per-subdomain
 //                images or tiles (the paper's moment Allreduce, Section 4.1)
 //   k_resolve    stage two, plain form: per tile a walker wavefront walks the
-//                rays again and hands each piece (z, a, s) through LDS to an
-//                evaluator wavefront, which forms the moment bound of its
-//                pixel (Alg. 3) and weights the piece's colour by
-//                T = exp(-b0 F) (Alg. 1 second loop, Section 4.2)
+//                rays again and hands each piece (depth, length, scalar)
+//                through LDS to an evaluator wavefront, which forms the piece's
+//                optical and warped depths as stage one did, evaluates the
+//                moment bound of its pixel (Alg. 3) and weights the piece's
+//                colour by T = exp(-b0 F) (Alg. 1 second loop, Section 4.2)
 //   k_eval       the same evaluation over pieces stage one kept (variant)
 //   k_sum_images canonical-order sum of partial images + renormalisation
 //
