@@ -292,12 +292,13 @@ __device__ __forceinline__ void cut_chord(const FrameDev& f, double t0, double t
   const double len = t1 - t0;
   if (!(len > 0.0)) return;
   const float slope = (s1 - s0) * __builtin_amdgcn_rcpf(float(len));
+  // the first lattice point after t0 (the rounded floor can fall one short)
   double kf = floor((t0 - f.t_near) * f.inv_step) + 1.0;
+  if (!(f.t_near + kf * f.step > t0)) kf += 1.0;
   double u = t0;
   for (int guard = 0; u < t1 && guard < (1 << 22); ++guard) {
     const double nxt = f.t_near + kf * f.step;
     kf += 1.0;
-    if (nxt <= u) continue;
     const double v = fmin(nxt, t1);
     const double tm = 0.5 * (u + v);
     const float s = s0 + slope * float(tm - t0);
@@ -1210,6 +1211,7 @@ struct Producer {
     if (!cutting) return;
     cslope = (s1 - s0) * __builtin_amdgcn_rcpf(float(len_c));  // as cut_chord
     ckf = floor((t0 - f.t_near) * f.inv_step) + 1.0;
+    if (!(f.t_near + ckf * f.step > t0)) ckf += 1.0;
     cu = t0;
     ct0 = t0;
     ct1 = t1;
@@ -1227,7 +1229,6 @@ struct Producer {
       ++cguard;
       const double nxt = f.t_near + ckf * f.step;
       ckf += 1.0;
-      if (nxt <= cu) continue;
       const double v = fmin(nxt, ct1);
       const double tm = 0.5 * (cu + v);
       const float s = cs0 + cslope * float(tm - ct0);
