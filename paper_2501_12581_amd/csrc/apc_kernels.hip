@@ -311,7 +311,7 @@ __device__ __forceinline__ void cut_chord(const FrameDev& f, double t0, double t
 __device__ __forceinline__ void tf_coord(const FrameDev& f, float s, int& i0, float& fr) {
 #pragma clang fp contract(off)
   float u = (s - f.s_min) * f.tf_scale;
-  u = fminf(fmaxf(u, 0.0f), float(f.n_tf - 1));
+  u = __builtin_amdgcn_fmed3f(u, 0.0f, float(f.n_tf - 1));  // clamp to [0, n_tf - 1] in one instruction
   i0 = min(int(u), f.n_tf - 2);
   fr = u - float(i0);
 }
@@ -322,7 +322,7 @@ __device__ __forceinline__ void tf_coord(const FrameDev& f, float s, int& i0, fl
 // tm + t_mid, rounded to FP32).
 __device__ __forceinline__ float piece_a(const FrameDev& f, float A, float len) {
 #pragma clang fp contract(off)
-  return fminf(f.kappa * A * len, f.amax);
+  return __builtin_amdgcn_fmed3f(f.kappa * A * len, 0.0f, f.amax);  // min with the cap (the product is >= 0)
 }
 __device__ __forceinline__ float piece_z(const FrameDev& f, float wt) {
 #pragma clang fp contract(off)
