@@ -473,9 +473,9 @@ __device__ void walk(const MeshDev& M, const FrameDev& f, const Ray& r, int tet,
     const float nAB = x == 0 ? qB : (x == 1 ? -qA : pAB);
     const float nBC = x == 0 ? pBC : (x == 1 ? qC : -qB);
     const float nCA = x == 0 ? -qC : (x == 1 ? pCA : qA);
-    if (x == 0) A = D;
-    if (x == 1) B = D;
-    if (x == 2) C = D;
+    A = pick(x == 0, D, A);
+    B = pick(x == 1, D, B);
+    C = pick(x == 2, D, C);
     pAB = nAB;
     pBC = nBC;
     pCA = nCA;
