@@ -33,8 +33,8 @@
 // polished by Newton steps on the kernel polynomial.  A vanishing leading
 // coefficient means one node has gone to infinity with zero weight; the
 // degree is lowered instead of dividing by it.  Reciprocals use the hardware
-// estimate plus Newton-Raphson steps in FP64 on the device (two; one for the
-// weights of the continuation below, whose image that leaves unchanged).
+// estimate plus Newton-Raphson steps in FP64 on the device: two, or one for
+// the weights in the continuation below (one already gives full precision).
 //
 // Gap tables (n >= 3, FP64).  Written t for the zeros of the degree-n
 // orthonormal polynomial, the node sets vary smoothly with z inside each gap
