@@ -34,7 +34,7 @@
 // coefficient means one node has gone to infinity with zero weight; the
 // degree is lowered instead of dividing by it.  Reciprocals use the hardware
 // estimate plus Newton-Raphson steps in FP64 on the device: two, or one for
-// the weights in the continuation below (one already gives full precision).
+// the weights in the continuation below (measured: the same FP32 image).
 //
 // Gap tables (n >= 3, FP64).  Written t for the zeros of the degree-n
 // orthonormal polynomial, the node sets vary smoothly with z inside each gap
