@@ -578,6 +578,30 @@ def test_frame_graph_replays_match_eager_frames(apc, ctx, global_sum, keep):
         g.close()
 
 
+@pytest.mark.parametrize("name", ["tiny", "medium", "adaptive"])
+def test_rewalk_meets_the_pieces_of_stage_one(apc, ctx, name):
+    """Stage two walks every ray again (Alg. 1, second loop) in a walker wavefront that hands the pieces to the
+    evaluator through an LDS ring in phases: it must meet exactly the pieces, tet steps, entries and ray
+    segments stage one met, whatever the phases did (a dropped or doubled piece, or a chord cut differently,
+    shows up here before it shows in the image)."""
+    sc = {"tiny": synth.scene_tiny, "medium": lambda: synth.scene_medium(size=512),
+          "adaptive": lambda: synth.scene_amr_small(size=200)}[name]()
+    r = apc.Renderer(ctx, sc)
+    r.frame(global_sum=True)  # sizes the context's buffers
+    torch.cuda.synchronize()
+    ctx.counters(reset=True)
+    ctx.moments_pass(r.mesh, r.view, r.tf, sc.m, r.subs, r.moments, None, global_sum=True)
+    torch.cuda.synchronize()
+    one = ctx.counters(reset=True)
+    ctx.resolve_pass(r.mesh, r.view, r.tf, r.mboit, r.moments, r.subs, r.rgba, finalize=True)
+    torch.cuda.synchronize()
+    two = ctx.counters()
+    print(name, {k: (one[k], two[k]) for k in ("pieces", "tet_steps", "entries", "segments")})
+    assert one["pieces"] > 0 and one["walk_step_limit"] == 0 and two["walk_step_limit"] == 0
+    for k in ("pieces", "tet_steps", "entries", "segments"):
+        assert two[k] == one[k], (k, one[k], two[k])
+
+
 @pytest.mark.parametrize("m", [4, 6, 8])
 def test_kept_pieces_match_the_plain_form(apc, ctx, m):
     """Stage two evaluating the pieces stage one kept gives the image of the plain form (stage two walking
