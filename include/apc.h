@@ -311,6 +311,19 @@ apc_status apc_moments_pass_tiles(apc_ctx ctx, apc_mesh mesh, const apc_view* vi
                                   const int32_t* subdomains, int32_t n_sub, float* tiles, int32_t* pair_bin,
                                   int64_t max_pairs, int64_t* n_pairs, void* stream);
 
+/* The tiles form walked pair by pair: the same arguments, results and
+ * errors as apc_moments_pass_tiles (bitwise the same tiles), but one
+ * workgroup walks one (tile, subdomain) pair instead of all the pairs of
+ * its tile in turn.  A small image has few tiles, each a long chain of
+ * dependent walk steps through every subdomain on its rays; by pair the
+ * chains are short and many.  (Section 4.1's per-rank stage one, every
+ * subdomain a rank.)  Keeps no per-pixel segment counts
+ * (apc_segment_counts then fails with APC_E_ARG); ignores the work-queue
+ * dispatch setting. */
+apc_status apc_moments_pass_pairs(apc_ctx ctx, apc_mesh mesh, const apc_view* view, const apc_tf* tf, int32_t m,
+                                  const int32_t* subdomains, int32_t n_sub, float* tiles, int32_t* pair_bin,
+                                  int64_t max_pairs, int64_t* n_pairs, void* stream);
+
 /* The global [m+1][H][W] moments from the tiles form: per pixel the pairs of
  * its tile summed in FP64 in slot (ascending id) order -- bitwise what
  * apc_sum_moments gives for the dense images of the same stage one.

@@ -34,7 +34,8 @@ EXPORTS = ["apc_create", "apc_destroy", "apc_last_error", "apc_version", "apc_lo
            "apc_get_timings", "apc_set_tile_shape", "apc_get_tile_shape", "apc_autotune_tile_shape",
            "apc_frame_graph_create", "apc_frame_graph_launch", "apc_frame_graph_counters", "apc_frame_graph_destroy",
            "apc_set_workspace_limit", "apc_resolve_pass_noalloc", "apc_get_workspace_bytes", "apc_set_dispatch",
-           "apc_get_dispatch", "apc_moments_pass_tiles", "apc_sum_moment_tiles", "apc_autotune_launch"]
+           "apc_get_dispatch", "apc_moments_pass_tiles", "apc_sum_moment_tiles", "apc_autotune_launch",
+           "apc_moments_pass_pairs"]
 
 
 class ApcError(RuntimeError):
@@ -114,9 +115,10 @@ def lib():
                                        C.c_uint32, vp]
         L.apc_sum_moments.restype = st
         L.apc_sum_moments.argtypes = [vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp, vp, vp]
-        L.apc_moments_pass_tiles.restype = st
-        L.apc_moments_pass_tiles.argtypes = [vp, vp, C.POINTER(View), C.POINTER(TF), C.c_int32, vp, C.c_int32, vp,
-                                             vp, C.c_int64, C.POINTER(C.c_int64), vp]
+        for name in ("apc_moments_pass_tiles", "apc_moments_pass_pairs"):
+            getattr(L, name).restype = st
+            getattr(L, name).argtypes = [vp, vp, C.POINTER(View), C.POINTER(TF), C.c_int32, vp, C.c_int32, vp, vp,
+                                         C.c_int64, C.POINTER(C.c_int64), vp]
         L.apc_sum_moment_tiles.restype = st
         L.apc_sum_moment_tiles.argtypes = [vp, vp, vp, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                            C.c_int32, vp, vp]
@@ -306,10 +308,12 @@ class Context:
                                                            "moments" if global_sum else "moments_per_sub"),
                                         flags, _stream(stream)))
 
-    def moments_pass_tiles(self, mesh, view: View, tf: TF, m, subdomains, tiles=None, pair_bin=None, stream=None):
+    def moments_pass_tiles(self, mesh, view: View, tf: TF, m, subdomains, tiles=None, pair_bin=None, stream=None,
+                           by_pair=False):
         """Stage one in the tiles form (ascending subdomain ids): tiles [P][m+1][64] FP32 and pair_bin [P] int32
         for the P (tile, subdomain) pairs with binned faces.  Without buffers only counts the pairs.  Returns
-        the pair count (raises ApcError, status APC_E_NOMEM, when the buffers are too small)."""
+        the pair count (raises ApcError, status APC_E_NOMEM, when the buffers are too small).  by_pair: a
+        workgroup per pair (apc_moments_pass_pairs) instead of one per tile; the same tiles."""
         import torch
         ids, ptr = _ids(subdomains)
         n = C.c_int64(0)
@@ -319,8 +323,9 @@ class Context:
             cap = int(tiles.shape[0])
             tp = _dev_ptr(tiles, torch.float32, (cap, m + 1, 64), "tiles")
             bp = _dev_ptr(pair_bin, torch.int32, (cap,), "pair_bin")
-        self._ck(lib().apc_moments_pass_tiles(self.handle, mesh.handle, C.byref(view), C.byref(tf), int(m), ptr,
-                                              len(ids), tp, bp, cap, C.byref(n), _stream(stream)))
+        fn = lib().apc_moments_pass_pairs if by_pair else lib().apc_moments_pass_tiles
+        self._ck(fn(self.handle, mesh.handle, C.byref(view), C.byref(tf), int(m), ptr, len(ids), tp, bp, cap,
+                    C.byref(n), _stream(stream)))
         return n.value
 
     def sum_moment_tiles(self, tiles, pair_bin, n_pairs, n_sub, m, height, width, out, stream=None):
@@ -530,6 +535,7 @@ class Renderer:
         self._device = device
         self.moments = torch.empty((m + 1, H, W), dtype=torch.float32, device=device)
         self.rgba = torch.empty((H, W, 4), dtype=torch.float32, device=device)
+        self._tiles = self._pair_bin = None  # the tiles form's buffers (stage one by pairs), grown on demand
 
     @property
     def per_sub(self):
@@ -540,13 +546,44 @@ class Renderer:
             self._per_sub = torch.empty((len(self.subs), m1, H, W), dtype=torch.float32, device=self._device)
         return self._per_sub
 
-    def frame(self, subdomains=None, finalize=True, stream=None, moments_f16=False, keep=False, global_sum=False):
+    def moments_by_pair(self, subs, stream=None):
+        """Stage one by (tile, subdomain) pairs into the tiles form, then their ordered FP64 sum into
+        self.moments: bitwise the global moments of the other forms (ascending subdomain ids)."""
+        import torch
+        m = self.scene.m
+        while True:
+            if self._tiles is not None:
+                try:
+                    n = self.ctx.moments_pass_tiles(self.mesh, self.view, self.tf, m, subs, self._tiles,
+                                                    self._pair_bin, stream, by_pair=True)
+                    break
+                except ApcError as e:
+                    if e.status != 3:  # APC_E_NOMEM: grow the buffers below
+                        raise
+            n = self.ctx.moments_pass_tiles(self.mesh, self.view, self.tf, m, subs, stream=stream)
+            cap = max(64, n + n // 4)
+            dev = self.moments.device
+            self._tiles = self._pair_bin = None
+            self._tiles = torch.empty((cap, m + 1, 64), dtype=torch.float32, device=dev)
+            self._pair_bin = torch.empty((cap,), dtype=torch.int32, device=dev)
+        H, W = self.moments.shape[1:]
+        self.ctx.sum_moment_tiles(self._tiles, self._pair_bin, n, len(subs), m, H, W, self.moments, stream)
+        return n
+
+    def frame(self, subdomains=None, finalize=True, stream=None, moments_f16=False, keep=False, global_sum=False,
+              by_pair=False):
         """One frame.  moments_f16: the resolve reads the FP16-packed moment image (self.moments_h); keep:
         stage one keeps its pieces and stage two evaluates them (else stage two walks the rays again, the
         plain form); global_sum (all subdomains, ascending): stage one writes the global moments itself and
-        self.per_sub is not written."""
+        self.per_sub is not written; by_pair (ascending subdomains, no keep): stage one walks the (tile,
+        subdomain) pairs in parallel into the tiles form and their ordered sum gives the global moments
+        (the same bits)."""
         subs = self.subs if subdomains is None else np.asarray(subdomains, np.int32)
-        if global_sum:
+        if by_pair:
+            if keep:
+                raise ValueError("stage one by pairs keeps no pieces")
+            self.moments_by_pair(subs, stream)
+        elif global_sum:
             self.ctx.moments_pass(self.mesh, self.view, self.tf, self.scene.m, subs, self.moments, stream,
                                   keep=keep, global_sum=True)
         else:

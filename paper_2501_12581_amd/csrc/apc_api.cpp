@@ -947,7 +947,7 @@ apc_status apc_moments_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const
   HIPCHK(apc::launch_moments(mm, md, f, ctx->slots.as<SlotDev>(), ctx->offsets.as<int>(), ctx->counts.as<int>(),
                              ctx->records.as<int>(), bin_cap(ctx), tf->rgba, out,
                              global ? ctx->gacc.as<double>() : nullptr, ctx->pcount.as<int>(), ctx->segs.as<int>(), ps,
-                             ctx->counters.as<unsigned long long>(), tile_queue(ctx), nullptr, s));
+                             ctx->counters.as<unsigned long long>(), tile_queue(ctx), nullptr, nullptr, 0, s));
   HIPCHK(ev_mark(ctx, EV_MOM, 1, s));
   set_piece_key(ctx, m, view, subs, n_sub);
   ctx->store_ready = ps.pool != nullptr;
@@ -955,9 +955,11 @@ apc_status apc_moments_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const
   return APC_OK;
 }
 
-apc_status apc_moments_pass_tiles(apc_ctx ctx, apc_mesh m, const apc_view* view, const apc_tf* tf, int32_t mm,
-                                  const int32_t* subs, int32_t n_sub, float* tiles, int32_t* pair_bin,
-                                  int64_t max_pairs, int64_t* n_pairs, void* stream) {
+namespace {
+// the tiles form; by_pair: a workgroup per (tile, subdomain) pair instead of one per tile
+apc_status moments_tiles(apc_ctx ctx, apc_mesh m, const apc_view* view, const apc_tf* tf, int32_t mm,
+                         const int32_t* subs, int32_t n_sub, float* tiles, int32_t* pair_bin, int64_t max_pairs,
+                         int64_t* n_pairs, void* stream, bool by_pair, const char* name) {
   apc_status st = check_ctx(ctx);
   if (st != APC_OK) return st;
   if ((st = check_mesh(ctx, m)) != APC_OK) return st;
@@ -971,7 +973,7 @@ apc_status apc_moments_pass_tiles(apc_ctx ctx, apc_mesh m, const apc_view* view,
   if (max_pairs > 0 && (!tiles || !pair_bin)) return fail(APC_E_ARG, "tiles or pair_bin is NULL");
   FrameDev f;
   if ((st = make_frame(m, view, tf, n_sub, max_tets_of(m, subs, n_sub), ctx->tw_log2, f)) != APC_OK) return st;
-  if (ctx->host_only) return no_device("apc_moments_pass_tiles");
+  if (ctx->host_only) return no_device(name);
   hipStream_t s = static_cast<hipStream_t>(stream);
   MeshDev md;
   if ((st = build_bins(ctx, m, f, subs, n_sub, s, md)) != APC_OK) return st;
@@ -990,20 +992,41 @@ apc_status apc_moments_pass_tiles(apc_ctx ctx, apc_mesh m, const apc_view* view,
   if (pairs > max_pairs)
     return fail(APC_E_NOMEM, "the frame has %lld (tile, subdomain) pairs; the buffers hold %lld (nothing written)",
                 (long long)pairs, (long long)max_pairs);
-  HIPCHK(ctx->pcount.ensure(sizeof(int) * size_t(f.n_tiles) * 64));
-  HIPCHK(ctx->segs.ensure(sizeof(int) * 2 * size_t(view->width) * view->height));
-  ctx->seg_h = view->height;
-  ctx->seg_w = view->width;
   ctx->store_ready = false;
+  if (by_pair) {  // several workgroups per tile: no per-pixel piece or segment counts
+    ctx->seg_h = ctx->seg_w = 0;
+  } else {
+    HIPCHK(ctx->pcount.ensure(sizeof(int) * size_t(f.n_tiles) * 64));
+    HIPCHK(ctx->segs.ensure(sizeof(int) * 2 * size_t(view->width) * view->height));
+    ctx->seg_h = view->height;
+    ctx->seg_w = view->width;
+  }
   HIPCHK(apc::launch_pair_list(ctx->counts.as<int>(), nb, ctx->pidx.as<int>(), pair_bin, s));
   HIPCHK(ev_mark(ctx, EV_MOM, 0, s));
   HIPCHK(apc::launch_moments(mm, md, f, ctx->slots.as<SlotDev>(), ctx->offsets.as<int>(), ctx->counts.as<int>(),
-                             ctx->records.as<int>(), bin_cap(ctx), tf->rgba, tiles, nullptr, ctx->pcount.as<int>(),
-                             ctx->segs.as<int>(), apc::PieceStore{}, ctx->counters.as<unsigned long long>(),
-                             tile_queue(ctx), ctx->pidx.as<int>(), s));
+                             ctx->records.as<int>(), bin_cap(ctx), tf->rgba, tiles, nullptr,
+                             by_pair ? nullptr : ctx->pcount.as<int>(), by_pair ? nullptr : ctx->segs.as<int>(),
+                             apc::PieceStore{}, ctx->counters.as<unsigned long long>(),
+                             by_pair ? nullptr : tile_queue(ctx), ctx->pidx.as<int>(), by_pair ? pair_bin : nullptr,
+                             pairs, s));
   HIPCHK(ev_mark(ctx, EV_MOM, 1, s));
   set_piece_key(ctx, m, view, subs, n_sub);
   return APC_OK;
+}
+}  // namespace
+
+apc_status apc_moments_pass_tiles(apc_ctx ctx, apc_mesh m, const apc_view* view, const apc_tf* tf, int32_t mm,
+                                  const int32_t* subs, int32_t n_sub, float* tiles, int32_t* pair_bin,
+                                  int64_t max_pairs, int64_t* n_pairs, void* stream) {
+  return moments_tiles(ctx, m, view, tf, mm, subs, n_sub, tiles, pair_bin, max_pairs, n_pairs, stream, false,
+                       "apc_moments_pass_tiles");
+}
+
+apc_status apc_moments_pass_pairs(apc_ctx ctx, apc_mesh m, const apc_view* view, const apc_tf* tf, int32_t mm,
+                                  const int32_t* subs, int32_t n_sub, float* tiles, int32_t* pair_bin,
+                                  int64_t max_pairs, int64_t* n_pairs, void* stream) {
+  return moments_tiles(ctx, m, view, tf, mm, subs, n_sub, tiles, pair_bin, max_pairs, n_pairs, stream, true,
+                       "apc_moments_pass_pairs");
 }
 
 apc_status apc_sum_moment_tiles(apc_ctx ctx, const float* tiles, const int32_t* pair_bin, int64_t n_pairs,
@@ -1468,7 +1491,7 @@ apc_status apc_segment_counts(apc_ctx ctx, int32_t* out, int32_t H, int32_t W, v
   apc_status st = check_ctx(ctx);
   if (st != APC_OK) return st;
   if (!out) return fail(APC_E_ARG, "out is NULL");
-  if (ctx->seg_h == 0) return fail(APC_E_ARG, "no stage one has run on this context");
+  if (ctx->seg_h == 0) return fail(APC_E_ARG, "no segment counts: no stage one has run on this context, or the last ran by pairs");
   if (H != ctx->seg_h || W != ctx->seg_w)
     return fail(APC_E_ARG, "image is %dx%d, the last stage one was %dx%d", W, H, ctx->seg_w, ctx->seg_h);
   if (ctx->host_only) return no_device("apc_segment_counts");

@@ -99,9 +99,11 @@ hipError_t launch_bin_fill(const MeshDev& m, const FrameDev& f, const SlotDev* s
 hipError_t launch_moments(int mm, const MeshDev& m, const FrameDev& f, const SlotDev* slots, const int* offsets,
                           const int* counts, const int* records, long long bin_cap, const float* tf_rgba, float* out,
                           double* gacc, int* pcount, int* segs, const PieceStore& store,
-                          unsigned long long* counters, int* queue, const int* pair_idx, hipStream_t s);
+                          unsigned long long* counters, int* queue, const int* pair_idx, const int* pair_list,
+                          int64_t n_pairs, hipStream_t s);
 // pair_idx (tiles form, gacc null): per bin with faces its pair number; out is then [pairs][m+1][64]
-// (lane-minor), every lane of every pair written
+// (lane-minor), every lane of every pair written.  pair_list (tiles form, may be null): the bin of each of
+// the n_pairs pairs; a workgroup per pair then walks that pair alone (pcount and segs must be null)
 // queue (both passes): null for one workgroup per tile; else QUEUE_INTS device ints that the launch
 // resets and a persistent launch (as many workgroups as the device holds) takes the tiles from
 constexpr int QUEUE_INTS = 8;

@@ -762,7 +762,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_WALK_W
                                                   float* __restrict__ out, double* __restrict__ gacc,
                                                   int* __restrict__ pcount, int* __restrict__ segs, long long bin_cap,
                                                   PieceStore ps, unsigned long long* ctr, int* queue,
-                                                  const int* __restrict__ pair_idx) {
+                                                  const int* __restrict__ pair_idx, const int* __restrict__ pair_list) {
   extern __shared__ float4 dyn_lds[];
   float* tfa = reinterpret_cast<float*>(dyn_lds);  // [n_tf] alpha column
   __shared__ FaceL faces[CHUNK];
@@ -777,8 +777,17 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_WALK_W
     blk_used = STORE_BLOCK;  // no block yet
   }
   __syncthreads();
+  // a pair list (tiles form): this workgroup walks the one (tile, subdomain) pair blockIdx.x names;
+  // else every subdomain of its tile
+  int k_first = 0, k_end = f.n_slots;
   int tile = QUEUE ? __builtin_amdgcn_readfirstlane(lane == 0 ? queue_take(queue, f.n_tiles) : 0)
                    : xcd_tile(blockIdx.x, gridDim.x);
+  if (!QUEUE && pair_list) {
+    const int bin = pair_list[blockIdx.x];
+    tile = bin / f.n_slots;
+    k_first = bin - tile * f.n_slots;
+    k_end = k_first + 1;
+  }
   for (; tile >= 0;
        tile = QUEUE ? __builtin_amdgcn_readfirstlane(lane == 0 ? queue_take(queue, f.n_tiles) : 0) : -1) {
   const int tx = tile % f.tiles_x, ty = tile / f.tiles_x;
@@ -801,7 +810,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(APC_WALK_W
   sink.st = LaneStore{ps, size_t(tile) * WAVE + lane, 0u, nullptr, ps.pool != nullptr && valid, (lds_vu64*)&blk_base,
                       (lds_vi32*)&blk_used};
   sink.lane = lane;
-  for (int k = 0; k < f.n_slots; ++k) {
+  for (int k = k_first; k < k_end; ++k) {
     const int bin = tile * f.n_slots + k;
     const int n_rec = counts[bin];
     sink.pieces = 0;
@@ -1831,9 +1840,15 @@ static hipError_t reset_queue(int* queue, hipStream_t s) {
 hipError_t launch_moments(int mm, const MeshDev& m, const FrameDev& f, const SlotDev* slots, const int* offsets,
                           const int* counts, const int* records, long long bin_cap, const float* tf_rgba, float* out,
                           double* gacc, int* pcount, int* segs, const PieceStore& store,
-                          unsigned long long* counters, int* queue, const int* pair_idx, hipStream_t s) {
+                          unsigned long long* counters, int* queue, const int* pair_idx, const int* pair_list,
+                          int64_t n_pairs, hipStream_t s) {
   const size_t lds = size_t(f.n_tf) * sizeof(float);
   const dim3 block(WAVE);
+  if (pair_list) {
+    queue = nullptr;  // a workgroup per pair
+    if (n_pairs <= 0) return hipSuccess;
+  }
+  const dim3 grid(pair_list ? unsigned(n_pairs) : unsigned(f.n_tiles));
   if (queue) {
     const hipError_t e = reset_queue(queue, s);
     if (e != hipSuccess) return e;
@@ -1843,11 +1858,11 @@ hipError_t launch_moments(int mm, const MeshDev& m, const FrameDev& f, const Slo
     if (queue)                                                                                          \
       hipLaunchKernelGGL((k_moments<M1, KP, true>), dim3(resident_blocks(k_moments<M1, KP, true>, WAVE, lds)), \
                          block, lds, s, m, f, slots, offsets, counts, records, tf_rgba, out, gacc, pcount, \
-                         segs, bin_cap, store, counters, queue, pair_idx);                              \
+                         segs, bin_cap, store, counters, queue, pair_idx, nullptr);                     \
     else                                                                                                \
-      hipLaunchKernelGGL((k_moments<M1, KP, false>), dim3(f.n_tiles), block, lds, s, m, f, slots, offsets, \
-                         counts, records, tf_rgba, out, gacc, pcount, segs, bin_cap, store, counters, queue,  \
-                         pair_idx);                                                                     \
+      hipLaunchKernelGGL((k_moments<M1, KP, false>), grid, block, lds, s, m, f, slots, offsets, counts,   \
+                         records, tf_rgba, out, gacc, pcount, segs, bin_cap, store, counters, queue, pair_idx, \
+                         pair_list);                                                                    \
   } while (0)
 #define APC_LAUNCH_MOMENTS(M1)                                                                          \
   do {                                                                                                  \

@@ -327,6 +327,11 @@ def test_sums_pack_and_settings_statuses(P, ctx, scene):
                                     None, None, 0, C.byref(n), None) == 1
     assert L.apc_moments_pass_tiles(*args, ptr(sc["subs"]), 3, None, None, 0, C.byref(n), None) == 4
     assert n.value == -1  # nothing written by a call that failed
+    assert L.apc_moments_pass_pairs(*args, ptr(np.array([2, 0, 1], np.int32)), 3, None, None, 0, C.byref(n),
+                                    None) == 1 and "ascending" in err(P, ctx)
+    assert L.apc_moments_pass_pairs(*args, ptr(sc["subs"]), 3, None, None, 5, C.byref(n), None) == 1
+    assert L.apc_moments_pass_pairs(*args, ptr(sc["subs"]), 3, None, None, 0, C.byref(n), None) == 4
+    assert "apc_moments_pass_pairs" in err(P, ctx) and n.value == -1
     tl, pb = ptr(sc["out"]["mom"]), ptr(np.zeros(4, np.int32))
     assert L.apc_sum_moment_tiles(ctx, tl, pb, 4, 3, 8, 24, 32, 3, mg, None) == 1 and "power of two" in err(P, ctx)
     assert L.apc_sum_moment_tiles(ctx, tl, pb, 10 ** 6, 3, 8, 24, 32, 8, mg, None) == 1  # more pairs than bins

@@ -443,8 +443,9 @@ def test_moment_tiles_hold_the_dense_images(apc, ctx, size, m, tw):
     """The tiles form of stage one (one 64-pixel tile per (tile, subdomain) pair with binned faces): every
     pair's tile is the dense per-subdomain image's values on its pixels (0 outside the image), every pixel of
     a tile without a pair is 0 in the dense image, pair_bin ascends, and the sum of the tiles is bitwise the
-    dense sum.  A query counts the pairs; buffers one pair short get APC_E_NOMEM and stay untouched.  Ragged
-    image, two tile shapes, m = 8 and 4."""
+    dense sum.  A query counts the pairs; buffers one pair short get APC_E_NOMEM and stay untouched.  Walked
+    pair by pair (a workgroup per pair) the tiles are bitwise the same.  Ragged image, two tile shapes, m = 8
+    and 4."""
     sc = synth.scene_medium(size=size)
     sc.m = m
     sc.bias = synth.default_bias(m)
@@ -484,6 +485,14 @@ def test_moment_tiles_hold_the_dense_images(apc, ctx, size, m, tw):
         pp, ll = np.nonzero(inside)
         rebuilt[slot[pp], :, y[pp, ll], x[pp, ll]] = t_np[pp, :, ll]
         assert np.array_equal(rebuilt, dense)
+        # walked pair by pair (a workgroup per pair): bitwise the same tiles and pair list
+        tiles2 = torch.full((n, m + 1, 64), -7.0, dtype=torch.float32, device="cuda")
+        pb2 = torch.full((n,), -7, dtype=torch.int32, device="cuda")
+        assert ctx.moments_pass_tiles(r.mesh, r.view, r.tf, m, r.subs, tiles2, pb2, by_pair=True) == n
+        torch.cuda.synchronize()
+        assert torch.equal(tiles2, tiles) and torch.equal(pb2, pb)
+        with pytest.raises(apc.ApcError):  # no per-pixel segment counts after a stage one by pairs
+            ctx.segment_counts(H, W)
         print("size %d m %d tile %dx%d: %d pairs of %d bins, %.1f%% of the dense bytes" % (
             size, m, tw, th, n, S * tiles_x * ((H + th - 1) // th), 100.0 * n * 64 / (S * H * W)))
     finally:
@@ -600,6 +609,43 @@ def test_rewalk_meets_the_pieces_of_stage_one(apc, ctx, name):
     assert one["pieces"] > 0 and one["walk_step_limit"] == 0 and two["walk_step_limit"] == 0
     for k in ("pieces", "tet_steps", "entries", "segments"):
         assert two[k] == one[k], (k, one[k], two[k])
+
+
+@pytest.mark.parametrize("name", ["tiny", "medium", "adaptive"])
+def test_frame_by_pair_is_the_frame_by_tile(apc, ctx, name):
+    """Stage one by (tile, subdomain) pairs (a workgroup per pair into the tiles form, then the ordered FP64
+    sum of the pairs) gives the global moments and the image bit for bit: each pair is the same walk as in
+    the per-tile launch and the sum takes the slots in the same order.  The walk counters agree too.  For a
+    subset of the subdomains it equals the separate sum of their per-subdomain images."""
+    sc = {"tiny": synth.scene_tiny, "medium": lambda: synth.scene_medium(size=300),
+          "adaptive": lambda: synth.scene_amr_small(size=200)}[name]()
+    r = apc.Renderer(ctx, sc)
+    r.frame(global_sum=True)  # sizes the context's buffers
+    torch.cuda.synchronize()
+    ctx.counters(reset=True)
+    r.frame(global_sum=True)
+    torch.cuda.synchronize()
+    by_tile = ctx.counters(reset=True)
+    rgba, mom = r.rgba.clone(), r.moments.clone()
+    r.rgba.fill_(-1.0)
+    r.moments.fill_(-1.0)
+    r.frame(by_pair=True)
+    torch.cuda.synchronize()
+    by_pair = ctx.counters(reset=True)
+    assert torch.equal(r.moments, mom) and torch.equal(r.rgba, rgba)
+    for k in ("pieces", "tet_steps", "entries", "segments", "walk_step_limit"):
+        assert by_pair[k] == by_tile[k], (k, by_tile[k], by_pair[k])
+    with pytest.raises(ValueError):
+        r.frame(by_pair=True, keep=True)
+    subset = np.asarray(r.subs[1::2], np.int32)
+    r.frame(subdomains=subset)
+    torch.cuda.synchronize()
+    rgba_s, mom_s = r.rgba.clone(), r.moments.clone()
+    r.frame(subdomains=subset, by_pair=True)
+    torch.cuda.synchronize()
+    assert torch.equal(r.moments, mom_s) and torch.equal(r.rgba, rgba_s)
+    assert not torch.equal(mom_s, mom)
+    print(name, "pieces", by_tile["pieces"], "subset", len(subset), "of", len(r.subs))
 
 
 @pytest.mark.parametrize("m", [4, 6, 8])
