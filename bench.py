@@ -100,17 +100,22 @@ def camera_views(args, sc):
 
 
 class Frames:
-    """Frames of one renderer over a list of cameras, in the plain form unless `keep`."""
+    """Frames of one renderer over a list of cameras, in the plain form unless `keep`.  by_pair: stage one
+    walks the (tile, subdomain) pairs in parallel into the tiles form and sums them in order (the same global
+    moments, bit for bit); else one workgroup per tile walks all its subdomains and sums them itself."""
 
-    def __init__(self, r, ctx, views, global_sum=True, keep=False):
+    def __init__(self, r, ctx, views, global_sum=True, keep=False, by_pair=False):
         """views: camera dicts, or the apc_view structures of another Frames."""
         import paper_2501_12581_amd as apc
         self.r, self.ctx, self.global_sum, self.keep = r, ctx, global_sum, keep
+        self.by_pair = by_pair and global_sum and not keep
         self.views = [apc.make_view(v, r.scene.step) if isinstance(v, dict) else v for v in views]
 
-    def frame(self, c, **kw):
+    def frame(self, c, by_tile=False, **kw):
+        """by_tile: this frame's stage one one workgroup per tile whatever self.by_pair says (it keeps the
+        per-pixel segment statistics the pair form does not)."""
         self.r.view = self.views[c]
-        return self.r.frame(global_sum=self.global_sum, keep=self.keep, **kw)
+        return self.r.frame(global_sum=self.global_sum, keep=self.keep, by_pair=self.by_pair and not by_tile, **kw)
 
     def survey(self):
         """One untimed frame per camera (sizes the library's buffers): pieces, segment statistics and
@@ -119,7 +124,7 @@ class Frames:
         out = []
         for c in range(len(self.views)):
             self.ctx.counters(reset=True)
-            self.frame(c)
+            self.frame(c, by_tile=True)
             torch.cuda.synchronize()
             cnt = self.ctx.counters()
             walks = 2 if self.ctx.timings()["rewalk_ms"] > 0 else 1
@@ -166,14 +171,16 @@ class Frames:
                 "camera_mean_ms": cam_mean, "median_camera_ms": float(np.median(list(cam_mean.values())))}
 
 
-def roofline_figures(mesh, m, H, W, survey, run):
+def roofline_figures(mesh, m, H, W, survey, run, by_pair=False):
     """Per-kernel rooflines from the method's own work (algorithmic bytes and flops): stage one
-    reads each touched tet and vertex once and writes each (pixel, subdomain) pair's m+1 moments into the
-    sum plus the global image; stage two reads the mesh again and the global image and writes the colour;
-    its dominant cost is the moment bound, ~250 FP64 flops per piece at m = 8."""
+    reads each touched tet and vertex once and writes each (pixel, subdomain) pair's m+1 moments (by_pair:
+    into the tiles, which the ordered sum reads back into the global image; else into the sum plus the
+    global image); stage two reads the mesh again and the global image and writes the colour; its dominant
+    cost is the moment bound, ~250 FP64 flops per piece at m = 8."""
     mesh_bytes = mesh.n_tets * TET_BYTES + mesh.n_vertices * VERT_BYTES
     cams, kern = run["cameras"], run["kernels"]
-    mom_bytes = sum(mesh_bytes + (survey[c]["pairs"] + H * W) * (m + 1) * 4.0 for c in cams)
+    img = 0 if by_pair else H * W
+    mom_bytes = sum(mesh_bytes + (survey[c]["pairs"] + img) * (m + 1) * 4.0 for c in cams)
     res_bytes = sum(mesh_bytes + H * W * ((m + 1) * 4.0 + 16.0) for c in cams)
     flops = sum(FP64_FLOPS_PER_PIECE_M8 * survey[c]["pieces"] for c in cams) if m == 8 else None
     t_mom = sum(kern["moments_ms"]) / 1e3
@@ -182,9 +189,18 @@ def roofline_figures(mesh, m, H, W, survey, run):
     out = {
         "k_moments": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS, "kernel_ms": 1e3 * t_mom / n,
                       "achieved": mom_bytes / t_mom / 1e9,
-                      "work_per_launch": "mesh %.3g B (each tet 32 B + each vertex 16 B) + (pairs + pixels) x "
-                                         "(m+1) x 4 B moments, %.3g B on average" % (mesh_bytes, mom_bytes / n)},
+                      "work_per_launch": "mesh %%.3g B (each tet 32 B + each vertex 16 B) + %s x "
+                                         "(m+1) x 4 B moments, %%.3g B on average" % (
+                                             "(pixel, subdomain) pairs" if by_pair else "(pairs + pixels)") % (
+                                             mesh_bytes, mom_bytes / n)},
     }
+    t_sum = sum(kern["sum_ms"]) / 1e3
+    if by_pair and t_sum > 0:
+        sum_bytes = sum((survey[c]["pairs"] + H * W) * (m + 1) * 4.0 for c in cams)
+        out["k_sum_tiles"] = {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS, "kernel_ms": 1e3 * t_sum / n,
+                              "achieved": sum_bytes / t_sum / 1e9,
+                              "work_per_launch": "(pixel, subdomain) pairs read + pixels written, x (m+1) x 4 B, "
+                                                 "%.3g B on average" % (sum_bytes / n)}
     if t_res > 0 and flops is not None:
         out["k_resolve"] = {"bound": "alu", "unit": "TFLOP/s", "peak": FP64_PEAK_TFLOPS, "kernel_ms": 1e3 * t_res / n,
                             "achieved": flops / t_res / 1e12,
@@ -316,7 +332,29 @@ def variants_leg(args, sc, r, ctx, fr, survey, rgba0, mom0):
     r._per_sub = None
     torch.cuda.empty_cache()
     log("separate sum %s" % out["separate_sum"])
-    # the same per-subdomain moments as tiles of the (tile, subdomain) pairs with binned faces (camera 0)
+    # the other form of stage one over every camera: one workgroup per tile (all its subdomains, the sum
+    # folded in), or by (tile, subdomain) pairs then the ordered sum
+    of = Frames(r, ctx, fr.views, by_pair=not fr.by_pair)
+    of_ms, of_mom, of_sum = [], [], []
+    for c in range(n_cam):
+        of.frame(c)
+        torch.cuda.synchronize()
+        f0 = time.perf_counter()
+        of.frame(c)
+        tk = ctx.timings()
+        torch.cuda.synchronize()
+        of_ms.append((time.perf_counter() - f0) * 1e3)
+        of_mom.append(tk["moments_ms"])
+        of_sum.append(tk["sum_ms"])
+        if c == 0:
+            same_mom, same_rgba = bool(torch.equal(r.moments, mom0)), bool(torch.equal(r.rgba, rgba0))
+    key = "stage_one_by_pair" if of.by_pair else "stage_one_by_tile"
+    out[key] = {"frame_ms_by_camera": [round(x, 2) for x in of_ms], "median_frame_ms": round(float(np.median(of_ms)), 3),
+                "moments_ms_mean": round(float(np.mean(of_mom)), 3), "sum_ms_mean": round(float(np.mean(of_sum)), 3),
+                "global_moments_bitwise_equal_camera0": same_mom, "rgba_bitwise_equal_camera0": same_rgba}
+    log("%s %s" % (key, out[key]))
+    # the same per-subdomain moments as tiles of the (tile, subdomain) pairs with binned faces, one
+    # workgroup per tile walking all its subdomains (camera 0)
     r.view = fr.views[0]
     m1 = r.moments.shape[0]
     n = ctx.moments_pass_tiles(r.mesh, r.view, r.tf, m1 - 1, r.subs)
@@ -373,6 +411,49 @@ def variants_leg(args, sc, r, ctx, fr, survey, rgba0, mom0):
     out["with_rgba_d2h"] = {"frame_ms": round(float(np.median(d2h)), 3), "rgba_bytes": int(r.rgba.numel() * 4)}
     log("variants %s" % {k: out[k] for k in ("fp16_moments", "graph_replay", "with_rgba_d2h")})
     return out, kept0, rgba16
+
+
+def stage_one_by_size(ctx, r, seed, sizes=(256, 512, 1024, 2048, 2560)):
+    """Stage one of orbit camera 0 at several image sizes on the renderer's mesh: one workgroup per tile
+    (the sum folded in) against one per (tile, subdomain) pair plus the ordered sum of the pairs, each the
+    best of 3 by the library's HIP events, the global moments compared bit for bit; and the re-walk's time
+    at that size."""
+    import torch
+    import paper_2501_12581_amd as apc
+    import synth
+    m, S, out = r.scene.m, len(r.subs), {}
+    dev = r.moments.device
+    for size in sizes:
+        v = apc.make_view(synth.orbit_view(seed, 0, size), r.scene.step)
+        mom = torch.empty((m + 1, size, size), dtype=torch.float32, device=dev)
+        glob = torch.empty_like(mom)
+        rgba = torch.empty((size, size, 4), dtype=torch.float32, device=dev)
+        n = ctx.moments_pass_tiles(r.mesh, v, r.tf, m, r.subs)
+        tiles = torch.empty((max(n, 1), m + 1, 64), dtype=torch.float32, device=dev)
+        pb = torch.empty((max(n, 1),), dtype=torch.int32, device=dev)
+        res = {"pairs": int(n), "tiles": -(-size // ctx.tile_shape()[0]) * -(-size // ctx.tile_shape()[1])}
+        for form in ("by_tile", "by_pair"):
+            best = None
+            for _ in range(3):
+                if form == "by_tile":
+                    ctx.moments_pass(r.mesh, v, r.tf, m, r.subs, mom, None, global_sum=True)
+                else:
+                    ctx.moments_pass_tiles(r.mesh, v, r.tf, m, r.subs, tiles, pb, by_pair=True)
+                    ctx.sum_moment_tiles(tiles, pb, n, S, m, size, size, glob)
+                tk = ctx.timings()
+                torch.cuda.synchronize()
+                t = tk["moments_ms"] + (tk["sum_ms"] if form == "by_pair" else 0.0)
+                best = t if best is None else min(best, t)
+            res[form + "_ms"] = round(best, 3)
+        res["global_moments_bitwise_equal"] = bool(torch.equal(glob, mom))
+        ctx.resolve_pass(r.mesh, v, r.tf, r.mboit, mom, r.subs, rgba, finalize=True)
+        res["rewalk_ms"] = round(ctx.timings()["rewalk_ms"], 3)
+        torch.cuda.synchronize()
+        out[str(size)] = res
+        log("stage one at %d^2: %s" % (size, res))
+        del mom, glob, rgba, tiles, pb
+    torch.cuda.empty_cache()
+    return out
 
 
 def batching_leg(bsc, steps=5):
@@ -452,6 +533,7 @@ def batching_leg(bsc, steps=5):
             "rgba_bitwise_equal_camera0": same}
     finally:
         ctx.set_dispatch(mode)
+    out["stage_one_by_size_camera0"] = stage_one_by_size(ctx, r, synth.BATCHING_SEED)
     del fr, kf, r
     ctx.close()
     torch.cuda.synchronize()
@@ -462,14 +544,15 @@ def batching_leg(bsc, steps=5):
 
 def serve_leg(n_requests, n_requests_30, sc):
     """p50/p99 frame latency of a served request stream on the batching configuration's mesh: batched
-    (continuous batching over slots) against one request at a time, both in the plain form."""
+    (continuous batching over slots) against one request at a time, both in the plain form with stage one by
+    (tile, subdomain) pairs; at 30 requests/s also with stage one by tiles."""
     import synth
     from paper_2501_12581_amd.serve import Server
     t0 = time.time()
     m = sc.mesh
     tfs = [synth.make_tf(s) for s in (21, 22, 23)]
     srv = Server((m.xyz, m.scalar, m.tets, m.tet_sub, m.n_sub), sc.step, tfs, (sc.s_min, sc.s_max), slots=4,
-                 hbm_budget=16 << 30)
+                 hbm_budget=16 << 30, by_pair=True)
     srv.warm()
     log("serving: %d tets, resident and warm in %.1fs" % (m.n_tets, time.time() - t0))
     warm = synth.request_stream(8, rate=1000.0, seed=99)
@@ -485,13 +568,24 @@ def serve_leg(n_requests, n_requests_30, sc):
             st.pop("records")
             res["%s_%g" % (mode, rate)] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
             log("serving %g/s %s: %s" % (rate, mode, res["%s_%g" % (mode, rate)]))
+    if n_requests_30 > 0:
+        srv.by_pair = False
+        reqs = synth.request_stream(n_requests_30, rate=30.0, seed=12)
+        for mode in ("batched", "fifo"):
+            st = srv.run(reqs, mode)
+            st.pop("records")
+            res["%s_by_tile_30" % mode] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
+            log("serving 30/s %s, stage one by tiles: %s" % (mode, res["%s_by_tile_30" % mode]))
     srv.close()
     out = {"workload": "batching mesh: %d tets, 72 Morton subdomains of tet-count ratio 12; Poisson arrivals, sizes "
                        "{256,512,1024,2048}^2, m in {4,6,8}, 3 transfer functions, cameras on the radius-2 sphere; "
-                       "plain form (stage two walks again)" % m.n_tets}
+                       "plain form (stage two walks again), stage one by (tile, subdomain) pairs" % m.n_tets}
     for rate in (50, 30):
         if "batched_%d" % rate in res:
             out["rate_%d_per_s" % rate] = {"batched": res["batched_%d" % rate], "one_at_a_time": res["fifo_%d" % rate]}
+    if "batched_by_tile_30" in res:
+        out["rate_30_per_s_stage_one_by_tiles"] = {"batched": res["batched_by_tile_30"],
+                                                   "one_at_a_time": res["fifo_by_tile_30"]}
     return out
 
 
@@ -507,6 +601,9 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="pick the tile shape with the autotuner first")
     ap.add_argument("--size", type=int, default=None, help="override the image size (square)")
     ap.add_argument("--grid", type=int, default=None, help="override cubes per axis (large workload)")
+    ap.add_argument("--by-pair", action="store_true",
+                    help="stage one by (tile, subdomain) pairs into the tiles form, then their ordered sum "
+                         "(default: one workgroup per tile walks all its subdomains, the sum folded in)")
     ap.add_argument("--keep", action="store_true",
                     help="time the kept-piece variant (stage one keeps every piece for stage two) instead of the "
                          "plain form")
@@ -581,7 +678,8 @@ def main():
         log("autotuned launch: %s" % tuned)
 
     views = camera_views(args, sc)
-    fr = Frames(r, ctx, views, keep=args.keep)
+    fr = Frames(r, ctx, views, keep=args.keep, by_pair=args.by_pair)
+    by_pair = fr.by_pair
     survey = fr.survey()  # one untimed frame per camera
     rgba0, mom0 = None, None
     for k in range(args.warmup):
@@ -602,7 +700,7 @@ def main():
             run["kernels"]["eval_ms"][k]))
     kern_mean = {k: round(float(np.mean(v)), 3) for k, v in run["kernels"].items()}
 
-    rooflines = roofline_figures(mesh, m, H, W, survey, run)
+    rooflines = roofline_figures(mesh, m, H, W, survey, run, by_pair=by_pair)
     timed = {k: v["kernel_ms"] for k, v in rooflines.items()}
     dom = max(timed, key=timed.get)
     rf = rooflines[dom]
@@ -671,7 +769,8 @@ def main():
                 args.workload, "Morton"),
             W, H, "perspective" if sc.view["projection"] else "orthographic",
             "s (%d orbit cameras)" % len(views) if len(views) > 1 else "", m,
-            "kept-piece variant" if args.keep else "plain form: stage two walks the rays again"),
+            "kept-piece variant" if args.keep else "plain form: stage two walks the rays again" + (
+                ", stage one by (tile, subdomain) pairs" if by_pair else ", stage one by tiles")),
             "global_batch": 1, "seq_len": None, "parallelism": "single GPU, all subdomains on device"},
         "frames_per_s": round(1e3 / run["median_camera_ms"], 4),
         "frames_per_s_definition": "1 / median over the cameras of their mean frame time (RGBA stays on the device)",

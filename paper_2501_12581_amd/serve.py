@@ -9,7 +9,10 @@ different requests overlap on the device; each frame's interval on the device is
 slot's stream.  Slots come in two sizes: large ones take any request, small ones only requests up to a smaller
 image size.  In "fifo" mode one request runs at a time in arrival order.  A frame is stage one summing every
 subdomain itself (`APC_MOMENTS_GLOBAL`: the server holds the whole mesh) and the resolve pass, in the plain
-form (stage two walks again) unless the server keeps pieces.  Every step of a frame runs in the library's
+form (stage two walks again) unless the server keeps pieces.  With by_pair, stage one walks the (tile,
+subdomain) pairs in parallel into buffers the slot sized when it was warmed, and their ordered sum gives the
+same global moments (a small frame has too few tiles to fill the device one workgroup per tile); a frame
+with more pairs than the buffers hold takes the per-tile form instead (counted, never an allocation).  Every step of a frame runs in the library's
 kernels; this module only schedules, allocates buffers and times.
 """
 from __future__ import annotations
@@ -41,7 +44,8 @@ def look_at_view(eye, target, width: int, height: int, fovy_deg: float = 45.0) -
 class Server:
     def __init__(self, mesh, step, tfs, s_range, kappa=4.0, absorbance_max=10.0, alpha=5e-5, eta=0.3,
                  slots=4, workspace_limit=8 << 30, hbm_budget=64 << 30, max_size=2048, max_m=8, device=0,
-                 small_slots=0, small_size=1024, small_workspace_limit=None, keep=False):
+                 small_slots=0, small_size=1024, small_workspace_limit=None, keep=False, by_pair=False,
+                 pair_slack=2.0):
         """mesh: arrays (xyz, scalar, tets, tet_sub, n_sub); tfs: list of [n][4] float32 tables;
         s_range: (s_min, s_max) of the transfer functions' domain; workspace_limit: bytes per slot for the
         kept-piece pool; hbm_budget: bytes of the requests' footprints (see footprint) allowed in flight;
@@ -50,7 +54,11 @@ class Server:
         small_slots more slots take only requests up to small_size^2, with small_workspace_limit bytes each
         (default: workspace_limit scaled by the pixel ratio): a slot's workspace must hold the kept pieces
         of its largest frame, so HBM allows more small slots than large ones.  keep: frames keep their pieces
-        in stage one for stage two (APC_KEEP_PIECES) instead of walking twice (the plain form)."""
+        in stage one for stage two (APC_KEEP_PIECES) instead of walking twice (the plain form).  by_pair
+        (plain form only): stage one by (tile, subdomain) pairs, into per-slot buffers of pair_slack times the
+        pairs of the slot's warm-up frame (allocated by warm())."""
+        if by_pair and keep:
+            raise ValueError("stage one by pairs keeps no pieces")
         import torch
         self.torch = torch
         self.device = device
@@ -85,6 +93,10 @@ class Server:
         self.workspace_limit = workspace_limit
         self.hbm_budget = hbm_budget
         self.keep = keep
+        self.by_pair, self.pair_slack = by_pair, pair_slack
+        self.pair_bufs = [None] * len(self.slot_size)  # (flat FP32 tiles, int32 pair bins) per slot
+        # per slot (each has one worker thread): frames with more pairs than the slot's buffers, run per tile
+        self.pair_overflow = [0] * len(self.slot_size)
         self.events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                        for _ in self.slot_size]
         self.t_ref = None
@@ -94,15 +106,26 @@ class Server:
         """One frame of each slot's largest request (its size, max_m) on every slot, one slot at a time: the
         library grows a context's buffers (bins, piece pool, staging) to what a frame needs, and a device
         allocation or release while other slots' frames run waits for all of them."""
+        torch = self.torch
         for k in range(len(self.slots)):
             req = {"id": -1, "arrival": 0.0, "size": self.slot_size[k], "eye": eye, "m": self.max_m, "tf": tf}
+            if self.by_pair and self.pair_bufs[k] is None:
+                ctx, stream = self.slots[k]
+                view, tfd, _ = self._frame_args(req)
+                n = ctx.moments_pass_tiles(self.mesh, view, tfd, self.max_m, self.subs, stream=stream.cuda_stream)
+                cap = max(256, int(math.ceil(n * self.pair_slack)))
+                self.pair_bufs[k] = (
+                    torch.empty(cap * (self.max_m + 1) * 64, dtype=torch.float32, device=self.dev),
+                    # as many bins as the FP32 buffer holds tiles of the smallest m (4)
+                    torch.empty(cap * (self.max_m + 1) // 5, dtype=torch.int32, device=self.dev))
             for _ in range(2):  # the second frame runs at the grown size
                 self.render(k, req)
-        self.slot_ws = [c.workspace_bytes() for c, _ in self.slots]
+        self.slot_ws = [c.workspace_bytes() + (0 if b is None else b[0].numel() * 4 + b[1].numel() * 4)
+                        for (c, _), b in zip(self.slots, self.pair_bufs)]
 
     def footprint(self, req) -> int:
         """HBM bytes a request occupies while it runs: its moment image and RGBA image, and the workspace of
-        the slot it runs on.  A library context keeps the buffers its largest frame needed (FP64 moment
+        the slot it runs on (with its stage-one pair buffers).  A library context keeps the buffers its largest frame needed (FP64 moment
         partials, segment statistics, piece counts, binning state, and the piece pool when frames keep their
         pieces), so after warm() the workspace of every slot that could take the request is measured with
         apc_get_workspace_bytes and the largest is counted; before it, an estimate from the request's size
@@ -125,6 +148,30 @@ class Server:
         j = np.arange(1, m + 1)
         return np.where(j % 2 == 0, 1.0 / (j + 1.0), 0.0)
 
+    def _frame_args(self, req):
+        W = H = req["size"]
+        m = req["m"]
+        view = make_view(look_at_view(req["eye"], (0.5, 0.5, 0.5), W, H), self.step)
+        tf = make_tf(self.tf_dev[req["tf"]], self.s_range[0], self.s_range[1], self.kappa, self.absorbance_max)
+        return view, tf, make_mboit(m, self.alpha, self._bias(m), self.eta, 1)
+
+    def _moments_by_pair(self, slot, view, tf, m, mom, s) -> bool:
+        """Stage one by pairs into the slot's buffers and their ordered sum into mom; False (nothing written)
+        when the frame has more pairs than the buffers hold."""
+        from . import ApcError
+        ctx, _ = self.slots[slot]
+        flat, bins = self.pair_bufs[slot]
+        cap = min(flat.numel() // ((m + 1) * 64), bins.numel())
+        tiles = flat[: cap * (m + 1) * 64].view(cap, m + 1, 64)
+        try:
+            n = ctx.moments_pass_tiles(self.mesh, view, tf, m, self.subs, tiles, bins[:cap], s, by_pair=True)
+        except ApcError as e:
+            if e.status != 3:  # APC_E_NOMEM: the buffers stay untouched
+                raise
+            return False
+        ctx.sum_moment_tiles(tiles, bins, n, len(self.subs), m, view.height, view.width, mom, s)
+        return True
+
     def render(self, slot: int, req) -> "object":
         """One frame for `req` on slot `slot` (stage one, moment sum, resolve); returns the RGBA image (a view
         of the slot's buffer, valid until the slot's next request) after the slot's stream has finished it."""
@@ -132,9 +179,7 @@ class Server:
         ctx, stream = self.slots[slot]
         W = H = req["size"]
         m = req["m"]
-        view = make_view(look_at_view(req["eye"], (0.5, 0.5, 0.5), W, H), self.step)
-        tf = make_tf(self.tf_dev[req["tf"]], self.s_range[0], self.s_range[1], self.kappa, self.absorbance_max)
-        mb = make_mboit(m, self.alpha, self._bias(m), self.eta, 1)
+        view, tf, mb = self._frame_args(req)
         if W > self.slot_size[slot] or m > self.max_m:
             raise ValueError("request larger than slot %d (%d^2, m=%d)" % (slot, self.slot_size[slot], self.max_m))
         b_mom, b_rgba = self.bufs[slot]
@@ -143,7 +188,11 @@ class Server:
         s = stream.cuda_stream
         ev0, ev1 = self.events[slot]
         ev0.record(stream)
-        ctx.moments_pass(self.mesh, view, tf, m, self.subs, mom, s, global_sum=True, keep=self.keep)
+        by_pair = self.by_pair and self.pair_bufs[slot] is not None
+        if not (by_pair and self._moments_by_pair(slot, view, tf, m, mom, s)):
+            if by_pair:
+                self.pair_overflow[slot] += 1
+            ctx.moments_pass(self.mesh, view, tf, m, self.subs, mom, s, global_sum=True, keep=self.keep)
         ctx.resolve_pass(self.mesh, view, tf, mb, mom, self.subs, rgba, finalize=True, stream=s)
         ev1.record(stream)
         stream.synchronize()
@@ -162,6 +211,7 @@ class Server:
         torch.cuda.synchronize(self.dev)
         self.t_ref = torch.cuda.Event(enable_timing=True)
         self.t_ref.record(torch.cuda.current_stream(self.dev))
+        self.pair_overflow = [0] * len(self.slot_size)
         device = {}
 
         def render(slot, req):
@@ -173,6 +223,9 @@ class Server:
         for rec in st["records"]:
             rec["device_start_ms"], rec["device_end_ms"] = device[rec["id"]]
         st["device_overlap_frac"] = device_overlap(st["records"])
+        st["stage_one"] = "by (tile, subdomain) pairs" if self.by_pair else "by tiles"
+        if self.by_pair:
+            st["pair_buffer_overflows"] = int(sum(self.pair_overflow))
         self.t_ref = None
         return st
 

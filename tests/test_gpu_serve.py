@@ -89,6 +89,41 @@ def test_served_frames_keep_their_pieces():
         plain.close()
 
 
+def test_stage_one_by_pair_serves_the_same_images():
+    """Slots that walk stage one by (tile, subdomain) pairs, into buffers sized when they were warmed, give
+    every request bitwise the image of the per-tile form, batched or one at a time; a frame with more pairs
+    than its slot's buffers hold (a tiny pair_slack) takes the per-tile form, with the same image, and is
+    counted."""
+    from paper_2501_12581_amd.serve import Server
+    sc = synth.scene_medium(size=128)
+    m = sc.mesh
+    tfs = [synth.make_tf(s) for s in (13, 14)]
+    args = ((m.xyz, m.scalar, m.tets, m.tet_sub, m.n_sub), sc.step, tfs, (sc.s_min, sc.s_max))
+    kw = dict(workspace_limit=1 << 30, hbm_budget=1 << 30, max_size=192)
+    ref = Server(*args, slots=1, **kw)
+    pair = Server(*args, slots=2, by_pair=True, **kw)
+    tight = Server(*args, slots=1, by_pair=True, pair_slack=1e-3, **kw)
+    try:
+        with pytest.raises(ValueError):
+            Server(*args, slots=1, by_pair=True, keep=True, **kw)
+        for s in (ref, pair, tight):
+            s.warm()
+        reqs = synth.request_stream(12, rate=400.0, seed=7, sizes=(96, 128, 192), ms=(4, 6, 8), n_tf=2)
+        want = ref.run(reqs, "fifo", keep_images=True)
+        got = pair.run(reqs, "batched", keep_images=True)
+        low = tight.run(reqs, "fifo", keep_images=True)
+        for a, b, c in zip(want["records"], got["records"], low["records"]):
+            assert a["id"] == b["id"] == c["id"]
+            assert torch.equal(a["rgba"], b["rgba"]) and torch.equal(a["rgba"], c["rgba"]), a["id"]
+        print("overflows: slack 2 %d, slack 1e-3 %d of %d" % (got["pair_buffer_overflows"],
+                                                             low["pair_buffer_overflows"], len(reqs)))
+        assert want["stage_one"] == "by tiles" and got["stage_one"] == "by (tile, subdomain) pairs"
+        assert got["pair_buffer_overflows"] < len(reqs) and low["pair_buffer_overflows"] > 0
+    finally:
+        for s in (ref, pair, tight):
+            s.close()
+
+
 def test_small_slots_take_small_requests_with_the_same_results():
     """Slots of two sizes: 2 that take any request and 2 that take requests up to 128^2 (with a smaller
     workspace).  Every request runs on a slot that holds it, the small slots are used, and each image is
