@@ -222,6 +222,7 @@ apc_status apc_sum_moments(apc_ctx ctx, const float* moments_per_sub, int32_t n_
 #define APC_MOMENTS_F16 2u
 #define APC_MOMENTS_GLOBAL 8u
 #define APC_KEEP_PIECES 16u
+#define APC_BY_PAIR 32u
 
 /* Pack a global moment image for FP16 storage, m + 3 planes each rounded to
  * the nearest FP16 value: planes 0 and 1 hold ln(b0) as two halves (hi, then
@@ -261,7 +262,16 @@ apc_status apc_pack_moments_f16(apc_ctx ctx, const float* moments_global, int32_
  * The per-pixel Hankel/Cholesky set-up and the per-piece solve run in FP64
  * when m = 6 or 8 and in FP32 when m = 4; everything else runs in FP32, the
  * walk's ray geometry in FP64.
- * flags: APC_FINALIZE, APC_MOMENTS_F16. */
+ * APC_BY_PAIR (plain form; ignored when kept pieces are evaluated): one
+ * workgroup walks one (tile, subdomain) pair with binned faces and writes
+ * its unfinalised colour sums to a context buffer, then each pixel's pairs
+ * are summed in FP64 in slot order and finalised.  For frames of few tiles
+ * (one chain of dependent steps per tile through every subdomain otherwise);
+ * the same pieces, the image equal to the per-tile form's to FP32 rounding
+ * (another grouping of the colour sums, and each pair's root solver starts
+ * afresh).  Reads the pair count back (one stream synchronisation); not with
+ * APC_MOMENTS_F16 or in a captured frame (APC_E_ARG).
+ * flags: APC_FINALIZE, APC_MOMENTS_F16, APC_BY_PAIR. */
 apc_status apc_resolve_pass(apc_ctx ctx, apc_mesh mesh, const apc_view* view, const apc_tf* tf,
                             const apc_mboit* mboit, const void* moments_global, const int32_t* subdomains,
                             int32_t n_sub, float* rgba_out, uint32_t flags, void* stream);

@@ -22,6 +22,7 @@ APC_FINALIZE = 1
 APC_MOMENTS_F16 = 2
 APC_MOMENTS_GLOBAL = 8
 APC_KEEP_PIECES = 16
+APC_BY_PAIR = 32  # apc_resolve_pass: a workgroup per (tile, subdomain) pair, then the ordered colour sum
 APC_DEVICE_NONE = -1   # apc_create: a host-only context (validates, launches nothing)
 APC_MESH_DEVICE = 1    # apc_mesh_desc.flags: the mesh arrays are device memory
 APC_DISPATCH_GRID = 0   # apc_set_dispatch: one workgroup per tile
@@ -349,12 +350,13 @@ class Context:
                                        _stream(stream)))
 
     def resolve_pass(self, mesh, view: View, tf: TF, mboit: Mboit, moments, subdomains, out, finalize=True,
-                     stream=None):
-        """`moments`: the FP32 global image, or (torch.float16) the packed image of pack_moments_f16."""
+                     stream=None, by_pair=False):
+        """`moments`: the FP32 global image, or (torch.float16) the packed image of pack_moments_f16.
+        by_pair: APC_BY_PAIR (plain form, FP32 moments)."""
         import torch
         ids, ptr = _ids(subdomains)
         f16 = moments.dtype == torch.float16
-        flags = (APC_FINALIZE if finalize else 0) | (APC_MOMENTS_F16 if f16 else 0)
+        flags = (APC_FINALIZE if finalize else 0) | (APC_MOMENTS_F16 if f16 else 0) | (APC_BY_PAIR if by_pair else 0)
         self._ck(lib().apc_resolve_pass(self.handle, mesh.handle, C.byref(view), C.byref(tf), C.byref(mboit),
                                         _dev_ptr(moments, torch.float16 if f16 else torch.float32,
                                                  (mboit.m + (3 if f16 else 1), view.height, view.width),
@@ -571,13 +573,14 @@ class Renderer:
         return n
 
     def frame(self, subdomains=None, finalize=True, stream=None, moments_f16=False, keep=False, global_sum=False,
-              by_pair=False):
+              by_pair=False, resolve_by_pair=False):
         """One frame.  moments_f16: the resolve reads the FP16-packed moment image (self.moments_h); keep:
         stage one keeps its pieces and stage two evaluates them (else stage two walks the rays again, the
         plain form); global_sum (all subdomains, ascending): stage one writes the global moments itself and
         self.per_sub is not written; by_pair (ascending subdomains, no keep): stage one walks the (tile,
         subdomain) pairs in parallel into the tiles form and their ordered sum gives the global moments
-        (the same bits)."""
+        (the same bits); resolve_by_pair (plain form, FP32 moments): stage two walks the pairs in parallel
+        too and sums their colours in order (the image to FP32 rounding)."""
         subs = self.subs if subdomains is None else np.asarray(subdomains, np.int32)
         if by_pair:
             if keep:
@@ -599,5 +602,5 @@ class Renderer:
             self.ctx.pack_moments_f16(self.moments, self.scene.m, self.moments_h, stream)
             mom = self.moments_h
         self.ctx.resolve_pass(self.mesh, self.view, self.tf, self.mboit, mom, subs, self.rgba,
-                              finalize=finalize, stream=stream)
+                              finalize=finalize, stream=stream, by_pair=resolve_by_pair)
         return self.rgba

@@ -158,6 +158,7 @@ struct apc_ctx_s {
   int dispatch = APC_DISPATCH_GRID;  // how both passes spread their tiles (apc_set_dispatch)
   DevBuf queue;                      // the work queue's per-XCD tile counters (APC_DISPATCH_QUEUE)
   DevBuf pidx;                       // tiles form: the pair number of each (tile, slot) bin
+  DevBuf rpair, rpart;               // stage two by pairs: the pairs' bins, their colour sums [pairs][4][64]
 };
 
 struct apc_graph_s {
@@ -605,7 +606,7 @@ apc_status apc_destroy(apc_ctx ctx) {
   (void)hipDeviceSynchronize();
   for (DevBuf* b : {&ctx->counts, &ctx->offsets, &ctx->cursors, &ctx->records, &ctx->scan_tmp, &ctx->slots,
                     &ctx->order, &ctx->counters, &ctx->pcount, &ctx->segs, &ctx->gacc, &ctx->queue, &ctx->pidx,
-                    &ctx->pool, &ctx->ptab, &ctx->store_next})
+                    &ctx->rpair, &ctx->rpart, &ctx->pool, &ctx->ptab, &ctx->store_next})
     b->release();
   if (ctx->staging) (void)hipHostFree(ctx->staging);
   if (ctx->staging_done) (void)hipEventDestroy(ctx->staging_done);
@@ -1113,7 +1114,7 @@ apc_status apc_resolve_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const
 static apc_status check_resolve(apc_ctx ctx, apc_mesh m, const apc_view* view, const apc_tf* tf,
                                 const apc_mboit* mb, const void* moments, const int32_t* subs, int32_t n_sub,
                                 const float* rgba, uint32_t flags, apc::BoundParams& bp, FrameDev& f,
-                                const char* call) {
+                                const char* call, uint32_t allowed = APC_FINALIZE | APC_MOMENTS_F16) {
   apc_status st = check_ctx(ctx);
   if (st != APC_OK) return st;
   if ((st = check_mesh(ctx, m)) != APC_OK) return st;
@@ -1122,7 +1123,9 @@ static apc_status check_resolve(apc_ctx ctx, apc_mesh m, const apc_view* view, c
   if ((st = check_subdomains(m, subs, n_sub)) != APC_OK) return st;
   if (!moments || !rgba) return fail(APC_E_ARG, "buffer is NULL");
   if (reinterpret_cast<uintptr_t>(rgba) & 15) return fail(APC_E_ARG, "rgba_out must be 16-byte aligned");
-  if (flags & ~(APC_FINALIZE | APC_MOMENTS_F16)) return fail(APC_E_ARG, "unknown flags 0x%x", flags);
+  if (flags & ~allowed) return fail(APC_E_ARG, "unknown flags 0x%x for %s", flags, call);
+  if ((flags & APC_BY_PAIR) && (flags & APC_MOMENTS_F16))
+    return fail(APC_E_ARG, "stage two by pairs reads FP32 moments (APC_BY_PAIR with APC_MOMENTS_F16)");
   bp.moments_f16 = (flags & APC_MOMENTS_F16) ? 1 : 0;
   if (bp.moments_f16 && (reinterpret_cast<uintptr_t>(moments) & 1))
     return fail(APC_E_ARG, "packed FP16 moments must be 2-byte aligned");
@@ -1136,8 +1139,11 @@ static apc_status resolve_frame(apc_ctx ctx, apc_mesh m, const apc_view* view, c
                                 float* rgba, uint32_t flags, void* stream) {
   apc::BoundParams bp;
   FrameDev f;
-  apc_status st = check_resolve(ctx, m, view, tf, mb, moments, subs, n_sub, rgba, flags, bp, f, "apc_resolve_pass");
+  apc_status st = check_resolve(ctx, m, view, tf, mb, moments, subs, n_sub, rgba, flags, bp, f, "apc_resolve_pass",
+                                APC_FINALIZE | APC_MOMENTS_F16 | APC_BY_PAIR);
   if (st != APC_OK) return st;
+  if ((flags & APC_BY_PAIR) && ctx->capturing)
+    return fail(APC_E_ARG, "stage two by pairs reads its pair count back: not in a captured frame");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int nt = f.n_tiles;
   unsigned long long* ctr = ctx->counters.as<unsigned long long>();
@@ -1181,10 +1187,35 @@ static apc_status resolve_frame(apc_ctx ctx, apc_mesh m, const apc_view* view, c
   // the plain form: walk the rays again and evaluate every piece at once
   MeshDev md;
   if ((st = build_bins(ctx, m, f, subs, n_sub, s, md)) != APC_OK) return st;
+  if (flags & APC_BY_PAIR) {
+    // number the (tile, slot) bins with faces (the binning's cursors are free now), list them, walk each
+    // pair in a workgroup of its own, then sum each pixel's pairs in slot order and finalise
+    const int64_t nb = int64_t(f.n_tiles) * n_sub;
+    HIPCHK(ctx->pidx.ensure(sizeof(int) * nb));
+    HIPCHK(apc::launch_pair_scan(ctx->counts.as<int>(), nb, ctx->cursors.as<int>(), ctx->pidx.as<int>(),
+                                 ctx->scan_tmp.as<int>(), s));
+    int tail[2];
+    HIPCHK(hipMemcpyAsync(&tail[0], ctx->pidx.as<int>() + nb - 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&tail[1], ctx->cursors.as<int>() + nb - 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const int64_t pairs = int64_t(tail[0]) + tail[1];
+    HIPCHK(ctx->rpair.ensure(sizeof(int) * size_t(std::max<int64_t>(pairs, 1))));
+    HIPCHK(ctx->rpart.ensure(sizeof(float) * 4 * 64 * size_t(std::max<int64_t>(pairs, 1))));
+    HIPCHK(apc::launch_pair_list(ctx->counts.as<int>(), nb, ctx->pidx.as<int>(), ctx->rpair.as<int>(), s));
+    HIPCHK(ev_mark(ctx, EV_STG, 0, s));
+    HIPCHK(apc::launch_resolve(mb->m, md, f, ctx->slots.as<SlotDev>(), ctx->offsets.as<int>(),
+                               ctx->counts.as<int>(), ctx->records.as<int>(), bin_cap(ctx), tf->rgba, moments, bp,
+                               rgba, ctr, nullptr, ctx->rpair.as<int>(), ctx->rpart.as<float>(), pairs, s));
+    HIPCHK(apc::launch_sum_color_tiles(ctx->rpart.as<float>(), ctx->rpair.as<int>(), pairs, n_sub, f.W, f.H,
+                                       ctx->tw_log2, static_cast<const float*>(moments), bp, rgba, s));
+    HIPCHK(ev_mark(ctx, EV_STG, 1, s));
+    HIPCHK(ev_mark(ctx, EV_RES, 1, s));
+    return APC_OK;
+  }
   HIPCHK(ev_mark(ctx, EV_STG, 0, s));
   HIPCHK(apc::launch_resolve(mb->m, md, f, ctx->slots.as<SlotDev>(), ctx->offsets.as<int>(), ctx->counts.as<int>(),
                              ctx->records.as<int>(), bin_cap(ctx), tf->rgba, moments, bp, rgba, ctr, tile_queue(ctx),
-                             s));
+                             nullptr, nullptr, 0, s));
   HIPCHK(ev_mark(ctx, EV_STG, 1, s));
   HIPCHK(ev_mark(ctx, EV_RES, 1, s));
   return APC_OK;
@@ -1230,7 +1261,7 @@ apc_status apc_resolve_pass_noalloc(apc_ctx ctx, apc_mesh m, const apc_view* vie
   if ((st = bin_faces(ctx, m, f, subs, n_sub, B, s, md)) != APC_OK) return st;
   HIPCHK(ev_mark(ctx, EV_STG, 0, s));
   HIPCHK(apc::launch_resolve(mb->m, md, f, B.slots, B.offsets, B.counts, B.records, B.rec_cap, tf->rgba, moments, bp,
-                             rgba, ctr, tile_queue(ctx), s));
+                             rgba, ctr, tile_queue(ctx), nullptr, nullptr, 0, s));
   HIPCHK(ev_mark(ctx, EV_STG, 1, s));
   HIPCHK(ev_mark(ctx, EV_RES, 1, s));
   return APC_OK;
@@ -1361,7 +1392,7 @@ apc_status apc_get_workspace_bytes(apc_ctx ctx, int64_t* bytes) {
   int64_t total = 0;
   for (const DevBuf* b : {&ctx->counts, &ctx->offsets, &ctx->cursors, &ctx->records, &ctx->scan_tmp, &ctx->slots,
                           &ctx->order, &ctx->counters, &ctx->pcount, &ctx->segs, &ctx->gacc, &ctx->queue, &ctx->pidx,
-                          &ctx->pool, &ctx->ptab, &ctx->store_next})
+                          &ctx->rpair, &ctx->rpart, &ctx->pool, &ctx->ptab, &ctx->store_next})
     total += int64_t(b->bytes);
   *bytes = total;
   return APC_OK;

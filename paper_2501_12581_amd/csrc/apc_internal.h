@@ -108,11 +108,17 @@ hipError_t launch_moments(int mm, const MeshDev& m, const FrameDev& f, const Slo
 // resets and a persistent launch (as many workgroups as the device holds) takes the tiles from
 constexpr int QUEUE_INTS = 8;
 // stage two, plain form: the rays are walked again and every piece is evaluated at once (no piece
-// is kept); rgba [H][W][4] receives the listed subdomains' colour sums, finalised with bp.finalize
+// is kept); rgba [H][W][4] receives the listed subdomains' colour sums, finalised with bp.finalize.
+// pair_list (may be null): the bins of n_pairs (tile, subdomain) pairs, ascending; a workgroup per pair then
+// writes that pair's unfinalised colour sums to part [n_pairs][4][64] instead of rgba (queue ignored)
 hipError_t launch_resolve(int mm, const MeshDev& m, const FrameDev& f, const SlotDev* slots, const int* offsets,
                           const int* counts, const int* records, long long bin_cap, const float* tf_rgba,
                           const void* moments, const BoundParams& bp, float* rgba, unsigned long long* counters,
-                          int* queue, hipStream_t s);
+                          int* queue, const int* pair_list, float* part, int64_t n_pairs, hipStream_t s);
+// the image from stage two's pair colour sums: per pixel its tile's pairs summed in FP64 in slot order, then
+// finalised with bp.finalize and b0 [H][W] (plane 0 of the FP32 moment image)
+hipError_t launch_sum_color_tiles(const float* part, const int* pair_bin, int64_t n_pairs, int n_slots, int W, int H,
+                                 int tw_log2, const float* b0, const BoundParams& bp, float* out, hipStream_t s);
 // stage two from the pieces stage one kept (store, pcount per pixel) for tiles [tile_lo, tile_hi)
 hipError_t launch_eval(int mm, const FrameDev& f, int tile_lo, int tile_hi, const PieceStore& store,
                        const int* pcount, const float* tf_rgba, const void* moments, const BoundParams& bp,

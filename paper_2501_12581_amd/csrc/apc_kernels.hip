@@ -1340,12 +1340,12 @@ __device__ void walk_subdomain_paired(const MeshDev& M, const FrameDev& f, const
   }
 }
 
-template <int N, class R, bool QUEUE>
+template <int N, class R, bool QUEUE, bool PAIRS>
 __global__ __launch_bounds__(2 * WAVE) __attribute__((amdgpu_waves_per_eu(APC_PAIR_WAVES, 8))) void k_resolve(
     MeshDev M, FrameDev f, const SlotDev* __restrict__ slots, const int* __restrict__ offsets,
     const int* __restrict__ counts, const int* __restrict__ records, long long bin_cap,
     const float* __restrict__ tf_rgba, const void* __restrict__ moments, BoundParams bp, float* __restrict__ rgba,
-    unsigned long long* ctr, int* queue) {
+    unsigned long long* ctr, int* queue, const int* __restrict__ pair_list, float* __restrict__ part) {
   extern __shared__ float4 dyn_lds[];
   float4* tf = dyn_lds;  // [n_tf] RGBA
   __shared__ FaceL faces[CHUNK];
@@ -1355,7 +1355,17 @@ __global__ __launch_bounds__(2 * WAVE) __attribute__((amdgpu_waves_per_eu(APC_PA
   __shared__ int next_tile;
   for (int i = threadIdx.x; i < f.n_tf; i += 2 * WAVE)
     tf[i] = make_float4(tf_rgba[4 * i], tf_rgba[4 * i + 1], tf_rgba[4 * i + 2], tf_rgba[4 * i + 3]);
-  if (threadIdx.x == 0) next_tile = QUEUE ? queue_take(queue, f.n_tiles) : xcd_tile(blockIdx.x, gridDim.x);
+  // PAIRS (a launch over pair_list): this workgroup walks the one (tile, subdomain) pair `pair` and writes
+  // its colour sums, unfinalised, to part[pair]; else every subdomain of its tile, into the image
+  int pair = 0, k_first = 0, k_end = f.n_slots;
+  if constexpr (PAIRS) {
+    pair = xcd_tile(blockIdx.x, gridDim.x);
+    k_first = pair_list[pair] % f.n_slots;
+    k_end = k_first + 1;
+  }
+  if (threadIdx.x == 0)
+    next_tile = QUEUE ? queue_take(queue, f.n_tiles)
+                      : PAIRS ? pair_list[pair] / f.n_slots : xcd_tile(blockIdx.x, gridDim.x);
   __syncthreads();
   for (int tile = next_tile; tile >= 0;) {  // the same tiles for both wavefronts of the workgroup
   const bool walker = threadIdx.x < WAVE;
@@ -1377,7 +1387,7 @@ __global__ __launch_bounds__(2 * WAVE) __attribute__((amdgpu_waves_per_eu(APC_PA
     q.pieces = 0u;
     q.cutting = false;
     EntryList L{ent_t, ent_c, lane};
-    for (int k = 0; k < f.n_slots; ++k) {
+    for (int k = k_first; k < k_end; ++k) {
       const int bin = tile * f.n_slots + k;
       const int n_rec = counts[bin];
       if (n_rec > 0 && offsets[bin] + n_rec <= bin_cap)
@@ -1457,9 +1467,16 @@ __global__ __launch_bounds__(2 * WAVE) __attribute__((amdgpu_waves_per_eu(APC_PA
       if (head < avail) eval_one();
     cnt.tabled += solved;
     cnt.tab_fallback += closed_used;
-    if (valid)
+    if constexpr (PAIRS) {  // [pairs][4][64], every lane
+      float* o = part + size_t(pair) * 4 * WAVE + lane;
+      o[0] = a0;
+      o[WAVE] = a1;
+      o[2 * WAVE] = a2;
+      o[3 * WAVE] = a3;
+    } else if (valid) {
       reinterpret_cast<float4*>(rgba)[pix] =
           finalize_px(make_float4(a0, a1, a2, a3), b0f, bp.finalize, bp.renormalize);
+    }
   }
   flush_counts(cnt, ctr);
   if (!QUEUE) break;
@@ -1680,6 +1697,41 @@ __global__ void k_pack_f16(const float* __restrict__ in, int m1, int64_t pixels,
     }
     out[int64_t(k + 2) * pixels + i] = bg ? _Float16(0.0f) : _Float16(c);
   }
+}
+
+// Stage two by pairs: pixel (tile t, lane l) adds the colour sums of tile t's pairs at lane l in slot order
+// (ascending subdomain ids) in FP64, then finalises with its b0 (FP32 moment image plane 0) -- the
+// per-subdomain partial images' canonical sum, taken over the pairs only (a subdomain without a pair on
+// the tile has no piece there).
+__global__ void k_sum_color_tiles(const float* __restrict__ part, const int* __restrict__ pair_bin, int64_t n_pairs,
+                                  int n_slots, int W, int H, int tw_log2, const float* __restrict__ b0,
+                                  BoundParams bp, float4* __restrict__ out) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t HW = int64_t(W) * H;
+  if (i >= HW) return;
+  const int y = int(i / W), x = int(i - int64_t(y) * W);
+  const int tw = 1 << tw_log2, th = WAVE >> tw_log2;
+  const int tiles_x = (W + tw - 1) / tw;
+  const int tile = (y / th) * tiles_x + (x >> tw_log2);
+  const int lane = (y % th) * tw + (x & (tw - 1));
+  const int64_t first_bin = int64_t(tile) * n_slots;
+  int64_t lo = 0, hi = n_pairs;  // first pair with pair_bin >= first_bin
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (pair_bin[mid] < first_bin)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  for (int64_t p = lo; p < n_pairs && pair_bin[p] < first_bin + n_slots; ++p) {
+    const float* t = part + p * 4 * WAVE + lane;
+    s0 += t[0];
+    s1 += t[WAVE];
+    s2 += t[2 * WAVE];
+    s3 += t[3 * WAVE];
+  }
+  out[i] = finalize_px(make_float4(float(s0), float(s1), float(s2), float(s3)), b0[i], bp.finalize, bp.renormalize);
 }
 
 __global__ void k_sum_images(const float4* __restrict__ in, int n_slots, const int* __restrict__ order,
@@ -1903,22 +1955,31 @@ hipError_t launch_eval(int mm, const FrameDev& f, int tile_lo, int tile_hi, cons
 hipError_t launch_resolve(int mm, const MeshDev& m, const FrameDev& f, const SlotDev* slots, const int* offsets,
                           const int* counts, const int* records, long long bin_cap, const float* tf_rgba,
                           const void* moments, const BoundParams& bp, float* rgba, unsigned long long* counters,
-                          int* queue, hipStream_t s) {
+                          int* queue, const int* pair_list, float* part, int64_t n_pairs, hipStream_t s) {
   const size_t lds = size_t(f.n_tf) * sizeof(float4);
-  const dim3 block(2 * WAVE);  // a tile per workgroup at a time: its walker and its evaluator
+  const dim3 block(2 * WAVE);  // a tile (or a pair) per workgroup at a time: its walker and its evaluator
+  if (pair_list) {
+    queue = nullptr;
+    if (n_pairs <= 0) return hipSuccess;
+  }
+  const dim3 grid(pair_list ? unsigned(n_pairs) : unsigned(f.n_tiles));
   if (queue) {
     const hipError_t e = reset_queue(queue, s);
     if (e != hipSuccess) return e;
   }
 #define APC_LAUNCH_RESOLVE(N, R)                                                                               \
   do {                                                                                                         \
-    if (queue)                                                                                                 \
-      hipLaunchKernelGGL((k_resolve<N, R, true>), dim3(resident_blocks(k_resolve<N, R, true>, 2 * WAVE, lds)), \
-                         block, lds, s, m, f, slots, offsets, counts, records, bin_cap, tf_rgba, moments, bp,  \
-                         rgba, counters, queue);                                                               \
+    if (pair_list)                                                                                             \
+      hipLaunchKernelGGL((k_resolve<N, R, false, true>), grid, block, lds, s, m, f, slots, offsets, counts,   \
+                         records, bin_cap, tf_rgba, moments, bp, rgba, counters, nullptr, pair_list, part);   \
+    else if (queue)                                                                                            \
+      hipLaunchKernelGGL((k_resolve<N, R, true, false>),                                                      \
+                         dim3(resident_blocks(k_resolve<N, R, true, false>, 2 * WAVE, lds)), block, lds, s, m, \
+                         f, slots, offsets, counts, records, bin_cap, tf_rgba, moments, bp, rgba, counters,    \
+                         queue, nullptr, nullptr);                                                             \
     else                                                                                                       \
-      hipLaunchKernelGGL((k_resolve<N, R, false>), dim3(f.n_tiles), block, lds, s, m, f, slots, offsets,      \
-                         counts, records, bin_cap, tf_rgba, moments, bp, rgba, counters, queue);              \
+      hipLaunchKernelGGL((k_resolve<N, R, false, false>), grid, block, lds, s, m, f, slots, offsets, counts,  \
+                         records, bin_cap, tf_rgba, moments, bp, rgba, counters, nullptr, nullptr, nullptr);  \
   } while (0)
   if (mm == 4)
     APC_LAUNCH_RESOLVE(2, float);
@@ -1970,6 +2031,15 @@ hipError_t launch_sum_tiles(const float* tiles, const int* pair_bin, int64_t n_p
   if (HW <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_sum_tiles, dim3(grid1(HW, 256)), dim3(256), 0, s, tiles, pair_bin, n_pairs, n_slots, m1, W, H,
                      tw_log2, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_color_tiles(const float* part, const int* pair_bin, int64_t n_pairs, int n_slots, int W, int H,
+                                 int tw_log2, const float* b0, const BoundParams& bp, float* out, hipStream_t s) {
+  const int64_t HW = int64_t(W) * H;
+  if (HW <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sum_color_tiles, dim3(grid1(HW, 256)), dim3(256), 0, s, part, pair_bin, n_pairs, n_slots, W,
+                     H, tw_log2, b0, bp, reinterpret_cast<float4*>(out));
   return hipGetLastError();
 }
 

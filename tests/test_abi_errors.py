@@ -285,6 +285,13 @@ def test_resolve_pass_statuses(P, ctx, scene):
     bad = L.apc_resolve_pass_noalloc(*args, C.byref(P.make_mboit(5, 5e-5, np.zeros(5), 0.3)),
                                      ptr(sc["out"]["mom"]), ptr(sc["subs"]), 3, ptr(sc["out"]["rgba"]), 0, None)
     assert bad == 1 and "m = 5" in err(P, ctx)
+    # stage two by pairs: a valid call reaches the device check; not with the FP16 moments; not allocation-free
+    assert resolve(P, ctx, sc, flags=P.APC_FINALIZE | P.APC_BY_PAIR) == 4 and "nothing was launched" in err(P, ctx)
+    assert resolve(P, ctx, sc, flags=P.APC_BY_PAIR | P.APC_MOMENTS_F16, moments_buf=ptr(sc["out"]["f16"])) == 1
+    assert "FP32 moments" in err(P, ctx)
+    by_pair = L.apc_resolve_pass_noalloc(*args, C.byref(sc["mb"]), ptr(sc["out"]["mom"]), ptr(sc["subs"]), 3,
+                                         ptr(sc["out"]["rgba"]), P.APC_FINALIZE | P.APC_BY_PAIR, None)
+    assert by_pair == 1 and "unknown flags" in err(P, ctx) and "apc_resolve_pass_noalloc" in err(P, ctx)
 
 
 def test_sums_pack_and_settings_statuses(P, ctx, scene):

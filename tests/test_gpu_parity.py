@@ -648,6 +648,53 @@ def test_frame_by_pair_is_the_frame_by_tile(apc, ctx, name):
     print(name, "pieces", by_tile["pieces"], "subset", len(subset), "of", len(r.subs))
 
 
+@pytest.mark.parametrize("name", ["tiny", "medium", "adaptive"])
+def test_rewalk_by_pair_matches_the_rewalk_by_tile(apc, ctx, name):
+    """Stage two by (tile, subdomain) pairs (APC_BY_PAIR: a workgroup per pair writes its unfinalised colour
+    sums, then each pixel's pairs are summed in slot order and finalised) meets exactly the pieces, tet steps,
+    entries and segments of the per-tile re-walk and gives its image to FP32 rounding: the colour sums are
+    grouped by subdomain and each pair's root solver starts afresh, the differences the kept-piece form has
+    too (its bar, 2e-5).  Pixels without pieces are bitwise equal.  Also the unfinalised partial image of a
+    subset, the whole frame with both stages by pairs, and (tiny) the oracle's bars."""
+    sc = {"tiny": synth.scene_tiny, "medium": lambda: synth.scene_medium(size=300),
+          "adaptive": lambda: synth.scene_amr_small(size=200)}[name]()
+    r = apc.Renderer(ctx, sc)
+    r.frame(global_sum=True)
+    ctx.resolve_pass(r.mesh, r.view, r.tf, r.mboit, r.moments, r.subs, r.rgba, finalize=True, by_pair=True)
+    torch.cuda.synchronize()  # both forms' buffers sized
+    ctx.counters(reset=True)
+    ctx.resolve_pass(r.mesh, r.view, r.tf, r.mboit, r.moments, r.subs, r.rgba, finalize=True)
+    torch.cuda.synchronize()
+    by_tile, want = ctx.counters(reset=True), r.rgba.clone()
+    got = torch.full_like(want, -1.0)
+    ctx.resolve_pass(r.mesh, r.view, r.tf, r.mboit, r.moments, r.subs, got, finalize=True, by_pair=True)
+    torch.cuda.synchronize()
+    by_pair = ctx.counters(reset=True)
+    assert by_tile["pieces"] > 0
+    for k in ("pieces", "tet_steps", "entries", "segments", "walk_step_limit"):
+        assert by_pair[k] == by_tile[k], (k, by_tile[k], by_pair[k])
+    diff = (got - want).abs().max().item()
+    assert diff <= 2e-5, diff
+    empty = r.moments[0] == 0
+    assert torch.equal(got[empty], want[empty])
+    subset = np.asarray(r.subs[1::2], np.int32)
+    part_t, part_p = torch.empty_like(want), torch.full_like(want, -1.0)
+    ctx.resolve_pass(r.mesh, r.view, r.tf, r.mboit, r.moments, subset, part_t, finalize=False)
+    ctx.resolve_pass(r.mesh, r.view, r.tf, r.mboit, r.moments, subset, part_p, finalize=False, by_pair=True)
+    torch.cuda.synchronize()
+    assert (part_p - part_t).abs().max().item() <= 2e-5
+    assert not torch.equal(part_t, want)
+    r.rgba.fill_(-1.0)
+    r.frame(by_pair=True, resolve_by_pair=True)
+    torch.cuda.synchronize()
+    assert (r.rgba - want).abs().max().item() <= 2e-5
+    if name == "tiny":
+        ref = oracle.render(sc)
+        d = _np(got).reshape(-1, 4) - ref["rgba"]
+        assert np.abs(d).max() <= 2e-3 and math.sqrt(np.mean(d ** 2)) <= 5e-4
+    print(name, "pieces", by_tile["pieces"], "max |by pair - by tile|", diff)
+
+
 @pytest.mark.parametrize("m", [4, 6, 8])
 def test_kept_pieces_match_the_plain_form(apc, ctx, m):
     """Stage two evaluating the pieces stage one kept gives the image of the plain form (stage two walking

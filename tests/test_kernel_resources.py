@@ -48,11 +48,12 @@ def test_stage_one_uses_no_scratch(usage, pattern):
     assert u["ScratchSize"] == 0 and u["VGPRs Spill"] == 0, u
 
 
-@pytest.mark.parametrize("pattern", [r"k_resolveILi4EdLb0E", r"k_resolveILi3EdLb0E", r"k_resolveILi2EfLb0E"])
+@pytest.mark.parametrize("pattern", [r"k_resolveILi4EdLb0ELb0E", r"k_resolveILi3EdLb0ELb0E", r"k_resolveILi2EfLb0ELb0E",
+                                     r"k_resolveILi4EdLb0ELb1E", r"k_resolveILi3EdLb0ELb1E", r"k_resolveILi2EfLb0ELb1E"])
 def test_fused_rewalk_fits_three_workgroups_per_simd(usage, pattern):
-    """The walker/evaluator pair (one workgroup per tile) is compiled for three workgroups of two wavefronts
-    per SIMD (168 VGPRs): a few registers of the walk may spill there, not the per-lane state (which took 848
-    bytes per lane)."""
+    """The walker/evaluator pair (one workgroup per tile, or per (tile, subdomain) pair) is compiled for three
+    workgroups of two wavefronts per SIMD (168 VGPRs): a few registers of the walk may spill there, not the
+    per-lane state (which took 848 bytes per lane)."""
     u = _find(usage, pattern)
     assert u["Occupancy"] >= 3 and u["ScratchSize"] <= 64 and u["VGPRs Spill"] <= 16, u
     assert u["LDS Size"] * 6 <= 160 * 1024 - 6 * 256 * 16, u  # six workgroups per CU with a 256-entry table
