@@ -100,9 +100,10 @@ def camera_views(args, sc):
 
 
 class Frames:
-    """Frames of one renderer over a list of cameras, in the plain form unless `keep`.  by_pair: stage one
-    walks the (tile, subdomain) pairs in parallel into the tiles form and sums them in order (the same global
-    moments, bit for bit); else one workgroup per tile walks all its subdomains and sums them itself."""
+    """Frames of one renderer over a list of cameras, in the plain form unless `keep`.  by_pair: both passes
+    walk the (tile, subdomain) pairs in parallel -- stage one into the tiles form, summed in order (the same
+    global moments, bit for bit), stage two into per-pair colour sums, summed in order and finalised (the
+    image to FP32 rounding); else one workgroup per tile walks all its subdomains in each pass."""
 
     def __init__(self, r, ctx, views, global_sum=True, keep=False, by_pair=False):
         """views: camera dicts, or the apc_view structures of another Frames."""
@@ -115,7 +116,8 @@ class Frames:
         """by_tile: this frame's stage one one workgroup per tile whatever self.by_pair says (it keeps the
         per-pixel segment statistics the pair form does not)."""
         self.r.view = self.views[c]
-        return self.r.frame(global_sum=self.global_sum, keep=self.keep, by_pair=self.by_pair and not by_tile, **kw)
+        bp = self.by_pair and not by_tile
+        return self.r.frame(global_sum=self.global_sum, keep=self.keep, by_pair=bp, resolve_by_pair=bp, **kw)
 
     def survey(self):
         """One untimed frame per camera (sizes the library's buffers): pieces, segment statistics and
@@ -332,10 +334,10 @@ def variants_leg(args, sc, r, ctx, fr, survey, rgba0, mom0):
     r._per_sub = None
     torch.cuda.empty_cache()
     log("separate sum %s" % out["separate_sum"])
-    # the other form of stage one over every camera: one workgroup per tile (all its subdomains, the sum
-    # folded in), or by (tile, subdomain) pairs then the ordered sum
+    # the frames in the other form over every camera: one workgroup per tile (all its subdomains, stage
+    # one's sum folded in), or by (tile, subdomain) pairs and ordered sums in both passes
     of = Frames(r, ctx, fr.views, by_pair=not fr.by_pair)
-    of_ms, of_mom, of_sum = [], [], []
+    of_ms, of_mom, of_sum, of_rw = [], [], [], []
     for c in range(n_cam):
         of.frame(c)
         torch.cuda.synchronize()
@@ -346,12 +348,15 @@ def variants_leg(args, sc, r, ctx, fr, survey, rgba0, mom0):
         of_ms.append((time.perf_counter() - f0) * 1e3)
         of_mom.append(tk["moments_ms"])
         of_sum.append(tk["sum_ms"])
+        of_rw.append(tk["rewalk_ms"])
         if c == 0:
-            same_mom, same_rgba = bool(torch.equal(r.moments, mom0)), bool(torch.equal(r.rgba, rgba0))
-    key = "stage_one_by_pair" if of.by_pair else "stage_one_by_tile"
+            same_mom = bool(torch.equal(r.moments, mom0))
+            rgba_diff = float((r.rgba - rgba0).abs().max().item())
+    key = "frames_by_pair" if of.by_pair else "frames_by_tile"
     out[key] = {"frame_ms_by_camera": [round(x, 2) for x in of_ms], "median_frame_ms": round(float(np.median(of_ms)), 3),
                 "moments_ms_mean": round(float(np.mean(of_mom)), 3), "sum_ms_mean": round(float(np.mean(of_sum)), 3),
-                "global_moments_bitwise_equal_camera0": same_mom, "rgba_bitwise_equal_camera0": same_rgba}
+                "rewalk_ms_mean": round(float(np.mean(of_rw)), 3),
+                "global_moments_bitwise_equal_camera0": same_mom, "rgba_max_abs_diff_camera0": rgba_diff}
     log("%s %s" % (key, out[key]))
     # the same per-subdomain moments as tiles of the (tile, subdomain) pairs with binned faces, one
     # workgroup per tile walking all its subdomains (camera 0)
@@ -413,11 +418,11 @@ def variants_leg(args, sc, r, ctx, fr, survey, rgba0, mom0):
     return out, kept0, rgba16
 
 
-def stage_one_by_size(ctx, r, seed, sizes=(256, 512, 1024, 2048, 2560)):
-    """Stage one of orbit camera 0 at several image sizes on the renderer's mesh: one workgroup per tile
-    (the sum folded in) against one per (tile, subdomain) pair plus the ordered sum of the pairs, each the
-    best of 3 by the library's HIP events, the global moments compared bit for bit; and the re-walk's time
-    at that size."""
+def passes_by_size(ctx, r, seed, sizes=(256, 512, 1024, 2048, 2560)):
+    """Both passes of orbit camera 0 at several image sizes on the renderer's mesh: one workgroup per tile
+    against one per (tile, subdomain) pair plus the ordered sum of the pairs, each the best of 3 by the
+    library's HIP events; stage one's global moments compared bit for bit, stage two's images by their
+    largest difference."""
     import torch
     import paper_2501_12581_amd as apc
     import synth
@@ -446,12 +451,20 @@ def stage_one_by_size(ctx, r, seed, sizes=(256, 512, 1024, 2048, 2560)):
                 best = t if best is None else min(best, t)
             res[form + "_ms"] = round(best, 3)
         res["global_moments_bitwise_equal"] = bool(torch.equal(glob, mom))
-        ctx.resolve_pass(r.mesh, v, r.tf, r.mboit, mom, r.subs, rgba, finalize=True)
-        res["rewalk_ms"] = round(ctx.timings()["rewalk_ms"], 3)
-        torch.cuda.synchronize()
+        rgba2 = torch.empty_like(rgba)
+        for form in ("by_tile", "by_pair"):
+            best = None
+            for _ in range(3):
+                ctx.resolve_pass(r.mesh, v, r.tf, r.mboit, mom, r.subs, rgba2 if form == "by_pair" else rgba,
+                                 finalize=True, by_pair=form == "by_pair")
+                t = ctx.timings()["rewalk_ms"]
+                torch.cuda.synchronize()
+                best = t if best is None else min(best, t)
+            res["rewalk_" + form + "_ms"] = round(best, 3)
+        res["rgba_max_abs_diff"] = float((rgba2 - rgba).abs().max().item())
         out[str(size)] = res
-        log("stage one at %d^2: %s" % (size, res))
-        del mom, glob, rgba, tiles, pb
+        log("both passes at %d^2: %s" % (size, res))
+        del mom, glob, rgba, rgba2, tiles, pb
     torch.cuda.empty_cache()
     return out
 
@@ -533,7 +546,7 @@ def batching_leg(bsc, steps=5):
             "rgba_bitwise_equal_camera0": same}
     finally:
         ctx.set_dispatch(mode)
-    out["stage_one_by_size_camera0"] = stage_one_by_size(ctx, r, synth.BATCHING_SEED)
+    out["passes_by_size_camera0"] = passes_by_size(ctx, r, synth.BATCHING_SEED)
     del fr, kf, r
     ctx.close()
     torch.cuda.synchronize()
@@ -544,8 +557,8 @@ def batching_leg(bsc, steps=5):
 
 def serve_leg(n_requests, n_requests_30, sc):
     """p50/p99 frame latency of a served request stream on the batching configuration's mesh: batched
-    (continuous batching over slots) against one request at a time, both in the plain form with stage one by
-    (tile, subdomain) pairs; at 30 requests/s also with stage one by tiles."""
+    (continuous batching over slots) against one request at a time, both in the plain form with both passes by
+    (tile, subdomain) pairs; at 30 requests/s also with both passes by tiles."""
     import synth
     from paper_2501_12581_amd.serve import Server
     t0 = time.time()
@@ -575,16 +588,16 @@ def serve_leg(n_requests, n_requests_30, sc):
             st = srv.run(reqs, mode)
             st.pop("records")
             res["%s_by_tile_30" % mode] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
-            log("serving 30/s %s, stage one by tiles: %s" % (mode, res["%s_by_tile_30" % mode]))
+            log("serving 30/s %s, by tiles: %s" % (mode, res["%s_by_tile_30" % mode]))
     srv.close()
     out = {"workload": "batching mesh: %d tets, 72 Morton subdomains of tet-count ratio 12; Poisson arrivals, sizes "
                        "{256,512,1024,2048}^2, m in {4,6,8}, 3 transfer functions, cameras on the radius-2 sphere; "
-                       "plain form (stage two walks again), stage one by (tile, subdomain) pairs" % m.n_tets}
+                       "plain form (stage two walks again), both passes by (tile, subdomain) pairs" % m.n_tets}
     for rate in (50, 30):
         if "batched_%d" % rate in res:
             out["rate_%d_per_s" % rate] = {"batched": res["batched_%d" % rate], "one_at_a_time": res["fifo_%d" % rate]}
     if "batched_by_tile_30" in res:
-        out["rate_30_per_s_stage_one_by_tiles"] = {"batched": res["batched_by_tile_30"],
+        out["rate_30_per_s_by_tiles"] = {"batched": res["batched_by_tile_30"],
                                                    "one_at_a_time": res["fifo_by_tile_30"]}
     return out
 
@@ -602,8 +615,8 @@ def main():
     ap.add_argument("--size", type=int, default=None, help="override the image size (square)")
     ap.add_argument("--grid", type=int, default=None, help="override cubes per axis (large workload)")
     ap.add_argument("--by-pair", action="store_true",
-                    help="stage one by (tile, subdomain) pairs into the tiles form, then their ordered sum "
-                         "(default: one workgroup per tile walks all its subdomains, the sum folded in)")
+                    help="both passes by (tile, subdomain) pairs, each followed by the pairs' ordered sum "
+                         "(default: one workgroup per tile walks all its subdomains)")
     ap.add_argument("--keep", action="store_true",
                     help="time the kept-piece variant (stage one keeps every piece for stage two) instead of the "
                          "plain form")
@@ -770,7 +783,7 @@ def main():
             W, H, "perspective" if sc.view["projection"] else "orthographic",
             "s (%d orbit cameras)" % len(views) if len(views) > 1 else "", m,
             "kept-piece variant" if args.keep else "plain form: stage two walks the rays again" + (
-                ", stage one by (tile, subdomain) pairs" if by_pair else ", stage one by tiles")),
+                ", both passes by (tile, subdomain) pairs" if by_pair else ", both passes by tiles")),
             "global_batch": 1, "seq_len": None, "parallelism": "single GPU, all subdomains on device"},
         "frames_per_s": round(1e3 / run["median_camera_ms"], 4),
         "frames_per_s_definition": "1 / median over the cameras of their mean frame time (RGBA stays on the device)",

@@ -9,10 +9,11 @@ different requests overlap on the device; each frame's interval on the device is
 slot's stream.  Slots come in two sizes: large ones take any request, small ones only requests up to a smaller
 image size.  In "fifo" mode one request runs at a time in arrival order.  A frame is stage one summing every
 subdomain itself (`APC_MOMENTS_GLOBAL`: the server holds the whole mesh) and the resolve pass, in the plain
-form (stage two walks again) unless the server keeps pieces.  With by_pair, stage one walks the (tile,
-subdomain) pairs in parallel into buffers the slot sized when it was warmed, and their ordered sum gives the
-same global moments (a small frame has too few tiles to fill the device one workgroup per tile); a frame
-with more pairs than the buffers hold takes the per-tile form instead (counted, never an allocation).  Every step of a frame runs in the library's
+form (stage two walks again) unless the server keeps pieces.  With by_pair, both passes walk the (tile,
+subdomain) pairs in parallel (a small frame has too few tiles to fill the device one workgroup per tile):
+stage one into buffers the slot sized when it was warmed, whose ordered sum gives the same global moments
+(a frame with more pairs than the buffers hold takes the per-tile form instead, counted, never an
+allocation), and stage two (APC_BY_PAIR) into the library's pair buffers, the image to FP32 rounding.  Every step of a frame runs in the library's
 kernels; this module only schedules, allocates buffers and times.
 """
 from __future__ import annotations
@@ -55,8 +56,8 @@ class Server:
         (default: workspace_limit scaled by the pixel ratio): a slot's workspace must hold the kept pieces
         of its largest frame, so HBM allows more small slots than large ones.  keep: frames keep their pieces
         in stage one for stage two (APC_KEEP_PIECES) instead of walking twice (the plain form).  by_pair
-        (plain form only): stage one by (tile, subdomain) pairs, into per-slot buffers of pair_slack times the
-        pairs of the slot's warm-up frame (allocated by warm())."""
+        (plain form only): both passes by (tile, subdomain) pairs, stage one into per-slot buffers of
+        pair_slack times the pairs of the slot's warm-up frame (allocated by warm())."""
         if by_pair and keep:
             raise ValueError("stage one by pairs keeps no pieces")
         import torch
@@ -193,7 +194,8 @@ class Server:
             if by_pair:
                 self.pair_overflow[slot] += 1
             ctx.moments_pass(self.mesh, view, tf, m, self.subs, mom, s, global_sum=True, keep=self.keep)
-        ctx.resolve_pass(self.mesh, view, tf, mb, mom, self.subs, rgba, finalize=True, stream=s)
+        ctx.resolve_pass(self.mesh, view, tf, mb, mom, self.subs, rgba, finalize=True, stream=s,
+                         by_pair=self.by_pair and not self.keep)
         ev1.record(stream)
         stream.synchronize()
         if self.t_ref is not None:  # the frame's interval on the device, in ms after the run's reference event
@@ -223,7 +225,7 @@ class Server:
         for rec in st["records"]:
             rec["device_start_ms"], rec["device_end_ms"] = device[rec["id"]]
         st["device_overlap_frac"] = device_overlap(st["records"])
-        st["stage_one"] = "by (tile, subdomain) pairs" if self.by_pair else "by tiles"
+        st["passes"] = "by (tile, subdomain) pairs" if self.by_pair else "by tiles"
         if self.by_pair:
             st["pair_buffer_overflows"] = int(sum(self.pair_overflow))
         self.t_ref = None

@@ -89,11 +89,12 @@ def test_served_frames_keep_their_pieces():
         plain.close()
 
 
-def test_stage_one_by_pair_serves_the_same_images():
-    """Slots that walk stage one by (tile, subdomain) pairs, into buffers sized when they were warmed, give
-    every request bitwise the image of the per-tile form, batched or one at a time; a frame with more pairs
-    than its slot's buffers hold (a tiny pair_slack) takes the per-tile form, with the same image, and is
-    counted."""
+def test_serving_by_pair_gives_the_same_images():
+    """Slots that walk both passes by (tile, subdomain) pairs (stage one into buffers sized when they were
+    warmed) give every request the image of the per-tile form to FP32 rounding (stage two's colour sums are
+    grouped by subdomain: the bar of the kept-piece form, 2e-5), batched or one at a time; a frame with more
+    pairs than its slot's buffers hold (a tiny pair_slack) takes the per-tile stage one, with bitwise the
+    same image (the same moments), and is counted."""
     from paper_2501_12581_amd.serve import Server
     sc = synth.scene_medium(size=128)
     m = sc.mesh
@@ -114,10 +115,11 @@ def test_stage_one_by_pair_serves_the_same_images():
         low = tight.run(reqs, "fifo", keep_images=True)
         for a, b, c in zip(want["records"], got["records"], low["records"]):
             assert a["id"] == b["id"] == c["id"]
-            assert torch.equal(a["rgba"], b["rgba"]) and torch.equal(a["rgba"], c["rgba"]), a["id"]
+            assert torch.equal(b["rgba"], c["rgba"]), a["id"]
+            assert (a["rgba"] - b["rgba"]).abs().max().item() <= 2e-5, a["id"]
         print("overflows: slack 2 %d, slack 1e-3 %d of %d" % (got["pair_buffer_overflows"],
                                                              low["pair_buffer_overflows"], len(reqs)))
-        assert want["stage_one"] == "by tiles" and got["stage_one"] == "by (tile, subdomain) pairs"
+        assert want["passes"] == "by tiles" and got["passes"] == "by (tile, subdomain) pairs"
         assert got["pair_buffer_overflows"] < len(reqs) and low["pair_buffer_overflows"] > 0
     finally:
         for s in (ref, pair, tight):
