@@ -59,12 +59,15 @@ __device__ __forceinline__ int sel4m(const int4& v, int i) {
 }
 
 // Blocks are dispatched round-robin over the 8 XCDs (block b runs on XCD
-// b % 8).  The tiles are handed out in runs of XCD_RUN consecutive tiles, run
-// c to XCD c % 8, so neighbouring tiles (which read the same tets) share one
-// XCD's L2 while every XCD gets runs from all over the image: the work of a
-// view is concentrated where the volume projects, and one contiguous band of
-// the image per XCD gave the busiest XCD twice the mean work.  The blocks
-// beyond the last whole round of 8 runs take the remaining tiles in bands.
+// b % 8).  The tiles are handed out in runs of XCD_RUN consecutive tiles, so
+// neighbouring tiles (which read the same tets) share one XCD's L2, and
+// every XCD gets runs from all over the image: the work of a view is
+// concentrated where the volume projects, and one contiguous band of the
+// image per XCD gave the busiest XCD twice the mean work.  Round k of 8 runs
+// (runs 8k .. 8k+7) goes to the XCDs rotated by k: with run c on XCD c % 8,
+// an image row of 4 runs (2048 pixels of 8-wide tiles) put the same quarter
+// of every row on one XCD.  The blocks beyond the last whole round take the
+// remaining tiles in bands.
 #ifndef APC_XCD_RUN
 #define APC_XCD_RUN 64
 #endif
@@ -74,7 +77,7 @@ __device__ __forceinline__ int xcd_tile(int b, int nb, int run = XCD_RUN) {
   if (b < whole) {
     const int x = b & 7, i = b >> 3;
     const int k = i / run;
-    return (k * 8 + x) * run + (i - k * run);
+    return (k * 8 + ((x + k) & 7)) * run + (i - k * run);
   }
   b -= whole;
   nb -= whole;
