@@ -143,7 +143,11 @@ apc_status apc_mesh_subdomain_info(apc_mesh mesh, int32_t subdomain, int64_t* n_
  * must start outside the mesh (the walk enters each subdomain through its
  * boundary faces): a perspective eye outside the mesh's bounding box, an
  * orthographic image plane with the whole box in front of it; APC_E_ARG
- * otherwise.  Depths outside [t_near, t_far] warp outside [-1, 1]. */
+ * otherwise.  A perspective view must also have the whole box in front of
+ * the eye (every corner at a positive coefficient of dir when written in
+ * (dir, right, down)): a ray is the half-line from the eye, and no line may
+ * cross the mesh behind it; APC_E_ARG otherwise.  Depths outside
+ * [t_near, t_far] warp outside [-1, 1]. */
 typedef struct apc_view {
   int32_t width, height;
   int32_t projection;   /* APC_ORTHOGRAPHIC or APC_PERSPECTIVE */

@@ -305,6 +305,15 @@ apc_status make_frame(const apc_mesh_s* m, const apc_view* v, const apc_tf* tf, 
     bool inside = true;
     for (int k = 0; k < 3; ++k) inside = inside && v->eye[k] >= m->lo[k] && v->eye[k] <= m->hi[k];
     if (inside) return fail(APC_E_ARG, "camera inside the mesh's bounding box");
+    // a ray is the half-line from the eye, but the walk's entry test (which side of each face edge the ray
+    // passes) sees the whole line: the box must lie in front of the eye, every corner at a positive
+    // coefficient of dir in (dir, right, down), so that no line crosses the mesh behind the eye (the
+    // coefficient is linear in the point and the box convex)
+    for (int c = 0; c < 8; ++c) {
+      double l = 0.0;
+      for (int k = 0; k < 3; ++k) l += minv[k] * (((c >> k) & 1 ? m->hi[k] : m->lo[k]) - v->eye[k]);
+      if (!(l > 0.0)) return fail(APC_E_ARG, "the mesh's bounding box is not entirely in front of the camera");
+    }
   } else {
     for (int c = 0; c < 8; ++c) {  // dir is normalised here
       double d = 0.0;

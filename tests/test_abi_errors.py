@@ -225,6 +225,25 @@ def test_moments_pass_statuses(P, ctx, scene):
                                     ptr(sc["out"]["mom"]), 0, None) == 1
 
 
+def test_perspective_views_need_the_mesh_in_front_of_the_eye(P, ctx, scene):
+    """The walk's entry test sees the whole line of a ray, so a perspective view must have the mesh's
+    bounding box in front of the eye: a camera outside the box looking away from it, or looking sideways
+    past it with part of the box behind, is an argument error; looking at it is valid (a host-only context
+    then reports that nothing was launched)."""
+    sc = scene
+    eye = np.asarray(synth.sphere_eye(4))
+    c = np.array([0.5, 0.5, 0.5])
+    side = np.cross(c - eye, [0.0, 0.0, 1.0])
+    for target, status in ((tuple(c), 4), (tuple(eye + (eye - c)), 1), (tuple(eye + side), 1)):
+        v = P.make_view(synth.perspective_view(tuple(eye), target, 32, 24), 1.0 / 16)
+        assert moments(P, ctx, sc, view=v) == status, (target, err(P, ctx))
+        if status == 1:
+            assert "in front of the camera" in err(P, ctx)
+    # a camera beside the box, looking along it, outside the box but with its corners on both sides
+    v = P.make_view(synth.perspective_view((0.5, -0.2, 0.5), (0.5, 1.5, 1.2), 32, 24), 1.0 / 16)
+    assert moments(P, ctx, sc, view=v) == 1
+
+
 def test_view_and_transfer_function_statuses(P, ctx, scene):
     sc = scene
     def copy_struct(x):
