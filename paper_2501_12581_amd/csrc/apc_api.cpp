@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <atomic>
 #include <cstring>
 #include <string>
 #include <mutex>
@@ -159,6 +160,13 @@ struct apc_ctx_s {
   DevBuf queue;                      // the work queue's per-XCD tile counters (APC_DISPATCH_QUEUE)
   DevBuf pidx;                       // tiles form: the pair number of each (tile, slot) bin
   DevBuf rpair, rpart;               // stage two by pairs: the pairs' bins, their colour sums [pairs][4][64]
+  // the (tile, slot) bins in counts / offsets / records / slots were made for this mesh, view, tile shape
+  // and subdomain list (stage two of a frame reuses stage one's)
+  bool bins_valid = false;
+  uint64_t bin_mesh = 0;
+  apc_view bin_view = {};
+  int bin_tw = -1;
+  std::vector<int> bin_subs;
 };
 
 struct apc_graph_s {
@@ -189,6 +197,7 @@ struct apc_mesh_s {
   double lo[3], hi[3];
   int64_t device_bytes = 0;
   bool host_only = false;  // loaded by a host-only context: no device arrays
+  uint64_t uid = 0;        // unique per load in the process (a freed mesh's address may be reused)
 };
 
 namespace {
@@ -447,9 +456,21 @@ apc_status bin_faces(apc_ctx ctx, const apc_mesh_s* m, const FrameDev& f, const 
   return APC_OK;
 }
 
-// bin_faces into the context's growable buffers
-apc_status build_bins(apc_ctx ctx, const apc_mesh_s* m, const FrameDev& f, const int32_t* subs, int32_t n_sub,
-                      hipStream_t s, MeshDev& md) {
+// bin_faces into the context's growable buffers, unless they already hold the bins of this mesh, view, tile
+// shape and subdomain list (stage two after stage one of the same frame); a captured frame always bins
+apc_status build_bins(apc_ctx ctx, const apc_mesh_s* m, const apc_view* v, const FrameDev& f, const int32_t* subs,
+                      int32_t n_sub, hipStream_t s, MeshDev& md) {
+  if (!ctx->capturing && ctx->bins_valid && ctx->bin_mesh == m->uid && ctx->bin_tw == ctx->tw_log2 &&
+      std::memcmp(&ctx->bin_view, v, sizeof(apc_view)) == 0 && ctx->bin_subs.size() == size_t(n_sub) &&
+      std::equal(subs, subs + n_sub, ctx->bin_subs.begin())) {
+    md.vert = m->vert;
+    md.tet = m->tet;
+    md.wrec = m->wrec;
+    md.n_vertices = m->V;
+    md.n_tets = m->T;
+    return APC_OK;
+  }
+  ctx->bins_valid = false;
   const int64_t nb = int64_t(f.n_tiles) * n_sub;
   HIPCHK(ctx->slots.ensure(sizeof(SlotDev) * n_sub));
   HIPCHK(ctx->counts.ensure(sizeof(int) * nb));
@@ -458,7 +479,15 @@ apc_status build_bins(apc_ctx ctx, const apc_mesh_s* m, const FrameDev& f, const
   HIPCHK(ctx->scan_tmp.ensure(sizeof(int) * apc::scan_tmp_elems(nb)));
   BinSpace B = {ctx->slots.as<SlotDev>(), ctx->counts.as<int>(), ctx->offsets.as<int>(), ctx->cursors.as<int>(),
                 ctx->scan_tmp.as<int>(), ctx->records.as<int>(), bin_cap(ctx), true};
-  return bin_faces(ctx, m, f, subs, n_sub, B, s, md);
+  const apc_status st = bin_faces(ctx, m, f, subs, n_sub, B, s, md);
+  if (st == APC_OK && !ctx->capturing) {
+    ctx->bins_valid = true;
+    ctx->bin_mesh = m->uid;
+    ctx->bin_view = *v;
+    ctx->bin_tw = ctx->tw_log2;
+    ctx->bin_subs.assign(subs, subs + n_sub);
+  }
+  return st;
 }
 
 void set_piece_key(apc_ctx ctx, const apc_mesh_s* m, const apc_view* v, const int32_t* subs, int32_t n_sub) {
@@ -708,8 +737,10 @@ apc_status apc_load_mesh(apc_ctx ctx, const apc_mesh_desc* d, apc_mesh* out, voi
       return fail(APC_E_MESH, "tet %lld: %s", (long long)bad[k], msg[why[k]]);
     }
   // ---- group tets by subdomain, keeping input order inside each (stable counting sort)
+  static std::atomic<uint64_t> next_uid{1};
   apc_mesh_s* m = new (std::nothrow) apc_mesh_s();
   if (!m) return fail(APC_E_NOMEM, "host allocation failed");
+  m->uid = next_uid.fetch_add(1);
   m->ctx = ctx;
   m->V = V;
   m->T = T;
@@ -926,7 +957,7 @@ apc_status apc_moments_pass(apc_ctx ctx, apc_mesh m, const apc_view* view, const
   if (ctx->host_only) return no_device("apc_moments_pass");
   hipStream_t s = static_cast<hipStream_t>(stream);
   MeshDev md;
-  if ((st = build_bins(ctx, m, f, subs, n_sub, s, md)) != APC_OK) return st;
+  if ((st = build_bins(ctx, m, view, f, subs, n_sub, s, md)) != APC_OK) return st;
   HIPCHK(ctx->pcount.ensure(sizeof(int) * size_t(f.n_tiles) * 64));
   // keep the pieces for stage two unless asked not to (or the pool cannot be had)
   apc::PieceStore ps = {};
@@ -986,7 +1017,7 @@ apc_status moments_tiles(apc_ctx ctx, apc_mesh m, const apc_view* view, const ap
   if (ctx->host_only) return no_device(name);
   hipStream_t s = static_cast<hipStream_t>(stream);
   MeshDev md;
-  if ((st = build_bins(ctx, m, f, subs, n_sub, s, md)) != APC_OK) return st;
+  if ((st = build_bins(ctx, m, view, f, subs, n_sub, s, md)) != APC_OK) return st;
   // number the (tile, slot) bins that have faces: those are the pairs (the binning's cursors are free now)
   const int64_t nb = int64_t(f.n_tiles) * n_sub;
   HIPCHK(ctx->pidx.ensure(sizeof(int) * nb));
@@ -1195,7 +1226,7 @@ static apc_status resolve_frame(apc_ctx ctx, apc_mesh m, const apc_view* view, c
   }
   // the plain form: walk the rays again and evaluate every piece at once
   MeshDev md;
-  if ((st = build_bins(ctx, m, f, subs, n_sub, s, md)) != APC_OK) return st;
+  if ((st = build_bins(ctx, m, view, f, subs, n_sub, s, md)) != APC_OK) return st;
   if (flags & APC_BY_PAIR) {
     // number the (tile, slot) bins with faces (the binning's cursors are free now), list them, walk each
     // pair in a workgroup of its own, then sum each pixel's pairs in slot order and finalise

@@ -695,6 +695,76 @@ def test_rewalk_by_pair_matches_the_rewalk_by_tile(apc, ctx, name):
     print(name, "pieces", by_tile["pieces"], "max |by pair - by tile|", diff)
 
 
+def test_stage_two_reuses_the_bins_of_stage_one_only_for_the_same_frame(apc, ctx):
+    """Both passes skip binning when the context's bins were made for the same mesh, view, tile shape and
+    subdomain list (stage two after stage one of the same frame, or the same frame again): a frame bins once,
+    as much as a fresh context's stage one, and its repetition not at all.  After a stage one of another
+    view, another subdomain list, another tile shape or another mesh load it bins again, and every image
+    is bitwise the one of a context that binned for it afresh."""
+    sc = synth.scene_tiny()
+    r = apc.Renderer(ctx, sc)
+    view_a = r.view
+    view_b = apc.make_view(synth.perspective_view(synth.sphere_eye(9), (0.5, 0.5, 0.5), 128, 128), sc.step)
+    fresh = apc.Context(0)
+    fresh_mesh = None
+    try:
+        fresh_mesh = fresh.load_mesh(sc.mesh.xyz, sc.mesh.scalar, sc.mesh.tets, sc.mesh.tet_sub, sc.mesh.n_sub)
+        # the whole frame on view A: stage one bins, stage two reuses them
+        ctx.counters(reset=True)
+        r.view = view_a
+        r.frame(global_sum=True)
+        torch.cuda.synchronize()
+        c = ctx.counters(reset=True)
+        mom_a, rgba_a = r.moments.clone(), r.rgba.clone()
+        fresh.counters(reset=True)
+        fresh.moments_pass(fresh_mesh, view_a, r.tf, sc.m, r.subs, torch.empty_like(mom_a), None, global_sum=True)
+        torch.cuda.synchronize()
+        assert fresh.counters(reset=True)["bin_records"] == c["bin_records"] > 0  # one binning per frame
+        ctx.moments_pass(r.mesh, view_a, r.tf, sc.m, r.subs, r.moments, None, global_sum=True)
+        torch.cuda.synchronize()
+        assert ctx.counters(reset=True)["bin_records"] == 0  # the same frame again: nothing to bin
+        assert torch.equal(r.moments, mom_a)
+        # stage one of view B, then stage two of view A with A's moments: bins again, the same image
+        ctx.moments_pass(r.mesh, view_b, r.tf, sc.m, r.subs, r.moments, None, global_sum=True)
+        out = torch.full_like(rgba_a, -1.0)
+        ctx.resolve_pass(r.mesh, view_a, r.tf, r.mboit, mom_a, r.subs, out, finalize=True)
+        torch.cuda.synchronize()
+        assert torch.equal(out, rgba_a)
+        # a subset after stage one of all subdomains: its partial image as a fresh context makes it
+        subset = np.asarray(r.subs[1::2], np.int32)
+        ctx.moments_pass(r.mesh, view_a, r.tf, sc.m, r.subs, r.moments, None, global_sum=True)
+        part = torch.full_like(rgba_a, -1.0)
+        ctx.resolve_pass(r.mesh, view_a, r.tf, r.mboit, mom_a, subset, part, finalize=False)
+        want = torch.full_like(rgba_a, -2.0)
+        fresh.resolve_pass(fresh_mesh, view_a, r.tf, r.mboit, mom_a, subset, want, finalize=False)
+        torch.cuda.synchronize()
+        assert torch.equal(part, want)
+        # another tile shape between the passes
+        ctx.moments_pass(r.mesh, view_a, r.tf, sc.m, r.subs, r.moments, None, global_sum=True)
+        ctx.set_tile_shape(16)
+        out.fill_(-1.0)
+        ctx.resolve_pass(r.mesh, view_a, r.tf, r.mboit, mom_a, r.subs, out, finalize=True)
+        fresh.set_tile_shape(16)
+        want.fill_(-2.0)
+        fresh.resolve_pass(fresh_mesh, view_a, r.tf, r.mboit, mom_a, r.subs, want, finalize=True)
+        torch.cuda.synchronize()
+        assert torch.equal(out, want)
+        ctx.set_tile_shape(8)
+        # another load of the mesh (same arrays): bins again, the same image
+        ctx.moments_pass(r.mesh, view_a, r.tf, sc.m, r.subs, r.moments, None, global_sum=True)
+        other = ctx.load_mesh(sc.mesh.xyz, sc.mesh.scalar, sc.mesh.tets, sc.mesh.tet_sub, sc.mesh.n_sub)
+        out.fill_(-1.0)
+        ctx.resolve_pass(other, view_a, r.tf, r.mboit, mom_a, r.subs, out, finalize=True)
+        torch.cuda.synchronize()
+        assert torch.equal(out, rgba_a)
+        other.free()
+    finally:
+        ctx.set_tile_shape(8)
+        if fresh_mesh is not None:
+            fresh_mesh.free()
+        fresh.close()
+
+
 @pytest.mark.parametrize("m", [4, 6, 8])
 def test_kept_pieces_match_the_plain_form(apc, ctx, m):
     """Stage two evaluating the pieces stage one kept gives the image of the plain form (stage two walking
