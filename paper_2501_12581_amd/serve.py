@@ -9,9 +9,10 @@ different requests overlap on the device; each frame's interval on the device is
 slot's stream.  Slots come in two sizes: large ones take any request, small ones only requests up to a smaller
 image size.  In "fifo" mode one request runs at a time in arrival order.  A frame is stage one summing every
 subdomain itself (`APC_MOMENTS_GLOBAL`: the server holds the whole mesh) and the resolve pass, in the plain
-form (stage two walks again) unless the server keeps pieces.  With by_pair, both passes of a frame of at
-most pair_max_tiles tiles walk the (tile, subdomain) pairs in parallel (such a frame has too few tiles to
-fill the device one workgroup per tile; a larger one is faster per tile):
+form (stage two walks again) unless the server keeps pieces.  With by_pair, stage one of a frame of at most
+moments_pair_max_tiles tiles and stage two of one of at most pair_max_tiles tiles walk the (tile, subdomain)
+pairs in parallel (such a frame has too few tiles to fill the device one workgroup per tile; a larger one
+is faster per tile):
 stage one into buffers the slot sized when it was warmed, whose ordered sum gives the same global moments
 (a frame with more pairs than the buffers hold takes the per-tile form instead, counted, never an
 allocation), and stage two (APC_BY_PAIR) into the library's pair buffers, the image to FP32 rounding.  Every step of a frame runs in the library's
@@ -47,7 +48,7 @@ class Server:
     def __init__(self, mesh, step, tfs, s_range, kappa=4.0, absorbance_max=10.0, alpha=5e-5, eta=0.3,
                  slots=4, workspace_limit=8 << 30, hbm_budget=64 << 30, max_size=2048, max_m=8, device=0,
                  small_slots=0, small_size=1024, small_workspace_limit=None, keep=False, by_pair=False,
-                 pair_slack=2.0, pair_max_tiles=4096):
+                 pair_slack=2.0, pair_max_tiles=4096, moments_pair_max_tiles=16384):
         """mesh: arrays (xyz, scalar, tets, tet_sub, n_sub); tfs: list of [n][4] float32 tables;
         s_range: (s_min, s_max) of the transfer functions' domain; workspace_limit: bytes per slot for the
         kept-piece pool; hbm_budget: bytes of the requests' footprints (see footprint) allowed in flight;
@@ -57,9 +58,10 @@ class Server:
         (default: workspace_limit scaled by the pixel ratio): a slot's workspace must hold the kept pieces
         of its largest frame, so HBM allows more small slots than large ones.  keep: frames keep their pieces
         in stage one for stage two (APC_KEEP_PIECES) instead of walking twice (the plain form).  by_pair
-        (plain form only): both passes by (tile, subdomain) pairs for frames of at most pair_max_tiles tiles
-        (4096: 512^2 in 8 x 8 tiles; measured on the batching mesh, both passes are faster by pairs up to
-        512^2 and per tile from 1024^2), stage one into per-slot buffers of pair_slack times the pairs of the
+        (plain form only): stage one by (tile, subdomain) pairs for frames of at most moments_pair_max_tiles
+        tiles (16384: 1024^2 in 8 x 8 tiles), stage two for frames of at most pair_max_tiles (4096: 512^2);
+        measured on the batching mesh, stage one is faster by pairs up to 1024^2 and stage two up to 512^2,
+        both per tile beyond.  Stage one writes into per-slot buffers of pair_slack times the pairs of the
         slot's largest such frame at warm-up (allocated by warm())."""
         if by_pair and keep:
             raise ValueError("stage one by pairs keeps no pieces")
@@ -98,6 +100,7 @@ class Server:
         self.hbm_budget = hbm_budget
         self.keep = keep
         self.by_pair, self.pair_slack, self.pair_max_tiles = by_pair, pair_slack, pair_max_tiles
+        self.moments_pair_max_tiles = moments_pair_max_tiles
         self.pair_bufs = [None] * len(self.slot_size)  # (flat FP32 tiles, int32 pair bins) per slot
         # per slot (each has one worker thread): frames with more pairs than the slot's buffers, run per tile
         self.pair_overflow = [0] * len(self.slot_size)
@@ -113,7 +116,7 @@ class Server:
         torch = self.torch
         for k in range(len(self.slots)):
             req = {"id": -1, "arrival": 0.0, "size": self.slot_size[k], "eye": eye, "m": self.max_m, "tf": tf}
-            ps = self._pair_size(k)
+            ps = self._pair_size(k, self.moments_pair_max_tiles)
             if self.by_pair and ps > 0 and self.pair_bufs[k] is None:
                 ctx, stream = self.slots[k]
                 view, tfd, _ = self._frame_args({**req, "size": ps})
@@ -123,10 +126,11 @@ class Server:
                     torch.empty(cap * (self.max_m + 1) * 64, dtype=torch.float32, device=self.dev),
                     # as many bins as the FP32 buffer holds tiles of the smallest m (4)
                     torch.empty(cap * (self.max_m + 1) // 5, dtype=torch.int32, device=self.dev))
+            sizes = sorted({ps, self._pair_size(k, self.pair_max_tiles)} - {0, req["size"]}) if self.by_pair else []
             for _ in range(2):  # the second frame runs at the grown size
                 self.render(k, req)
-                if self.by_pair and 0 < ps < req["size"]:  # the largest frame by pairs sizes their buffers
-                    self.render(k, {**req, "size": ps})
+                for size in sizes:  # the largest frames by pairs of each pass size their buffers
+                    self.render(k, {**req, "size": size})
         self.slot_ws = [c.workspace_bytes() + (0 if b is None else b[0].numel() * 4 + b[1].numel() * 4)
                         for (c, _), b in zip(self.slots, self.pair_bufs)]
 
@@ -159,10 +163,10 @@ class Server:
         tw, th = self.slots[slot][0].tile_shape()
         return -(-size // tw) * -(-size // th)
 
-    def _pair_size(self, slot) -> int:
-        """The largest square frame of the slot walked by pairs (0: none)."""
+    def _pair_size(self, slot, max_tiles) -> int:
+        """The largest square frame of the slot with at most max_tiles tiles (0: none)."""
         size = self.slot_size[slot]
-        while size > 0 and self._pair_tiles(slot, size) > self.pair_max_tiles:
+        while size > 0 and self._pair_tiles(slot, size) > max_tiles:
             size -= 1
         return size
 
@@ -206,13 +210,15 @@ class Server:
         s = stream.cuda_stream
         ev0, ev1 = self.events[slot]
         ev0.record(stream)
-        by_pair = (self.by_pair and not self.keep and self.pair_bufs[slot] is not None
-                   and self._pair_tiles(slot, W) <= self.pair_max_tiles)
-        if not (by_pair and self._moments_by_pair(slot, view, tf, m, mom, s)):
-            if by_pair:
+        tiles = self._pair_tiles(slot, W)
+        pairs = self.by_pair and not self.keep
+        one_by_pair = pairs and self.pair_bufs[slot] is not None and tiles <= self.moments_pair_max_tiles
+        if not (one_by_pair and self._moments_by_pair(slot, view, tf, m, mom, s)):
+            if one_by_pair:
                 self.pair_overflow[slot] += 1
             ctx.moments_pass(self.mesh, view, tf, m, self.subs, mom, s, global_sum=True, keep=self.keep)
-        ctx.resolve_pass(self.mesh, view, tf, mb, mom, self.subs, rgba, finalize=True, stream=s, by_pair=by_pair)
+        ctx.resolve_pass(self.mesh, view, tf, mb, mom, self.subs, rgba, finalize=True, stream=s,
+                         by_pair=pairs and tiles <= self.pair_max_tiles)
         ev1.record(stream)
         stream.synchronize()
         if self.t_ref is not None:  # the frame's interval on the device, in ms after the run's reference event
@@ -242,8 +248,8 @@ class Server:
         for rec in st["records"]:
             rec["device_start_ms"], rec["device_end_ms"] = device[rec["id"]]
         st["device_overlap_frac"] = device_overlap(st["records"])
-        st["passes"] = ("by (tile, subdomain) pairs up to %d tiles per frame, else by tiles" % self.pair_max_tiles
-                        if self.by_pair else "by tiles")
+        st["passes"] = ("by (tile, subdomain) pairs up to %d (stage one) and %d (stage two) tiles per frame, else "
+                        "by tiles" % (self.moments_pair_max_tiles, self.pair_max_tiles) if self.by_pair else "by tiles")
         if self.by_pair:
             st["pair_buffer_overflows"] = int(sum(self.pair_overflow))
         self.t_ref = None

@@ -95,7 +95,9 @@ def test_serving_by_pair_gives_the_same_images():
     grouped by subdomain: the bar of the kept-piece form, 2e-5), batched or one at a time; a frame with more
     pairs than its slot's buffers hold (a tiny pair_slack) takes the per-tile stage one, with bitwise the
     same image (the same moments), and is counted.  With pair_max_tiles = 256 the 192^2 frames (576 tiles)
-    run per tile, bitwise the per-tile image, and the smaller ones by pairs."""
+    run stage two per tile, bitwise the per-tile image (stage one by pairs gives the same moments), and the
+    smaller ones both passes by pairs; with moments_pair_max_tiles = 256 as well, stage one of the 192^2
+    frames runs per tile too, the same image."""
     from paper_2501_12581_amd.serve import Server
     sc = synth.scene_medium(size=128)
     m = sc.mesh
@@ -106,19 +108,22 @@ def test_serving_by_pair_gives_the_same_images():
     pair = Server(*args, slots=2, by_pair=True, **kw)
     tight = Server(*args, slots=1, by_pair=True, pair_slack=1e-3, **kw)
     mixed = Server(*args, slots=1, by_pair=True, pair_max_tiles=256, **kw)
+    mixed1 = Server(*args, slots=1, by_pair=True, pair_max_tiles=256, moments_pair_max_tiles=256, **kw)
     try:
         with pytest.raises(ValueError):
             Server(*args, slots=1, by_pair=True, keep=True, **kw)
-        for s in (ref, pair, tight, mixed):
+        for s in (ref, pair, tight, mixed, mixed1):
             s.warm()
         reqs = synth.request_stream(12, rate=400.0, seed=7, sizes=(96, 128, 192), ms=(4, 6, 8), n_tf=2)
         want = ref.run(reqs, "fifo", keep_images=True)
         got = pair.run(reqs, "batched", keep_images=True)
         low = tight.run(reqs, "fifo", keep_images=True)
         mix = mixed.run(reqs, "fifo", keep_images=True)
-        for a, b, c, d in zip(want["records"], got["records"], low["records"], mix["records"]):
-            assert a["id"] == b["id"] == c["id"] == d["id"]
+        mix1 = mixed1.run(reqs, "fifo", keep_images=True)
+        for a, b, c, d, e in zip(want["records"], got["records"], low["records"], mix["records"], mix1["records"]):
+            assert a["id"] == b["id"] == c["id"] == d["id"] == e["id"]
             assert torch.equal(d["rgba"], a["rgba"] if a["size"] == 192 else b["rgba"]), a["id"]
+            assert torch.equal(e["rgba"], d["rgba"]), a["id"]
             assert torch.equal(b["rgba"], c["rgba"]), a["id"]
             assert (a["rgba"] - b["rgba"]).abs().max().item() <= 2e-5, a["id"]
         print("overflows: slack 2 %d, slack 1e-3 %d of %d" % (got["pair_buffer_overflows"],
@@ -126,7 +131,7 @@ def test_serving_by_pair_gives_the_same_images():
         assert want["passes"] == "by tiles" and got["passes"].startswith("by (tile, subdomain) pairs")
         assert got["pair_buffer_overflows"] < len(reqs) and low["pair_buffer_overflows"] > 0
     finally:
-        for s in (ref, pair, tight, mixed):
+        for s in (ref, pair, tight, mixed, mixed1):
             s.close()
 
 
